@@ -1,0 +1,390 @@
+/*
+ * hvpic_oracle.c -- plain FP64 CPU oracle of the Hybrid-VPIC step
+ * (Le et al., arXiv 2305.05600).  TEST INFRASTRUCTURE ONLY: the GPU library
+ * never calls this file and shares nothing with it.
+ *
+ * Each function follows one passage of the paper; readings of points the
+ * paper leaves open are stated where they are used:
+ *   gather ..... App. B, eq:quadFI and eq:quadF (QS); Sec. II.B (NGP)
+ *   boris ...... Sec. II.B, eq:vadv and the Boris description after it
+ *   move ....... Sec. II.B, position update and the (I, dx,dy,dz) store
+ *   deposit .... Sec. II.B eq:ngp (NGP); App. B eq:quad (QS)
+ *   ohm ........ Sec. II.A eq:ohm, density floor, Ampere, EOS
+ *   faraday .... Sec. II.A Faraday + subcycling; Sec. II.B extrapolation
+ *   gradients .. Sec. II.B centred differences on the cell-centred grid
+ *   smoothing .. Sec. II.B (binomial passes; the cited method is not in the
+ *                paper, the (1,2,1)/4 reading is documented)
+ *   sort ....... not in the paper: a stable counting sort by cell index
+ */
+#include "hvpic_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ---------------------------------------------------------------- grid -- */
+
+static int64_t ncell_of(const orc_params* p) {
+  return (int64_t)p->nx * p->ny * p->nz;
+}
+
+static int wrap(int i, int n) {
+  int r = i % n;
+  return r < 0 ? r + n : r;
+}
+
+/* I <-> (i,j,k), row-major with i fastest (Sec. II.B). */
+static int64_t cell_of(const orc_params* p, int i, int j, int k) {
+  return (int64_t)wrap(i, p->nx) +
+         (int64_t)p->nx * ((int64_t)wrap(j, p->ny) + (int64_t)p->ny * wrap(k, p->nz));
+}
+
+static void ijk_of(const orc_params* p, int64_t c, int* i, int* j, int* k) {
+  *i = (int)(c % p->nx);
+  *j = (int)((c / p->nx) % p->ny);
+  *k = (int)(c / ((int64_t)p->nx * p->ny));
+}
+
+static double cell_volume(const orc_params* p) { return p->dx * p->dy * p->dz; }
+
+/* Centred difference of scalar Q along axis a at (i,j,k):
+   (Q_{+1} - Q_{-1}) / (2 Delta_a)  (Sec. II.B gradient formula). */
+static double dcentred(const orc_params* p, const double* Q, int a, int i, int j, int k) {
+  int di = a == 0, dj = a == 1, dk = a == 2;
+  double h = a == 0 ? p->dx : (a == 1 ? p->dy : p->dz);
+  return (Q[cell_of(p, i + di, j + dj, k + dk)] - Q[cell_of(p, i - di, j - dj, k - dk)]) /
+         (2.0 * h);
+}
+
+/* ---------------------------------------------------------- gather ----- */
+
+/* QS interpolation (App. B).  The interpolants of eq:quadFI are built for the
+   particle's cell and combined with eq:quadF:
+     F = F0 + dx (Fx + dx Fxx) + dy (Fy + dy Fyy) + dz (Fz + dz Fzz).
+   In 2D nz = 1, so k+1 and k-1 are cell k itself; Fz and Fzz then vanish. */
+static double qs_interp(const orc_params* p, const double* Fc, int i, int j, int k,
+                        double dx, double dy, double dz) {
+  double F = Fc[cell_of(p, i, j, k)];
+  double Fip = Fc[cell_of(p, i + 1, j, k)], Fim = Fc[cell_of(p, i - 1, j, k)];
+  double Fjp = Fc[cell_of(p, i, j + 1, k)], Fjm = Fc[cell_of(p, i, j - 1, k)];
+  double Fkp = Fc[cell_of(p, i, j, k + 1)], Fkm = Fc[cell_of(p, i, j, k - 1)];
+  double F0 = (1.0 / 12.0) * (6.0 * F + Fip + Fjp + Fkp + Fim + Fjm + Fkm);
+  double Fx = (1.0 / 6.0) * (Fip - Fim);
+  double Fy = (1.0 / 6.0) * (Fjp - Fjm);
+  double Fz = (1.0 / 6.0) * (Fkp - Fkm);
+  double Fxx = (1.0 / 12.0) * (Fip + Fim - 2.0 * F);
+  double Fyy = (1.0 / 12.0) * (Fjp + Fjm - 2.0 * F);
+  double Fzz = (1.0 / 12.0) * (Fkp + Fkm - 2.0 * F);
+  return F0 + dx * (Fx + dx * Fxx) + dy * (Fy + dy * Fyy) + dz * (Fz + dz * Fzz);
+}
+
+void orc_gather(const orc_params* p, const double* F, int32_t cell, double ox,
+                double oy, double oz, double out[3]) {
+  int64_t nc = ncell_of(p);
+  int i, j, k;
+  ijk_of(p, cell, &i, &j, &k);
+  if (p->ndim == 2) oz = 0.0;
+  for (int comp = 0; comp < 3; ++comp) {
+    const double* Fc = F + comp * nc;
+    if (p->shape == ORC_SHAPE_NGP)
+      out[comp] = Fc[cell]; /* NGP: the local cell value (Sec. II.B) */
+    else
+      out[comp] = qs_interp(p, Fc, i, j, k, ox, oy, oz);
+  }
+}
+
+/* ----------------------------------------------------------- Boris ----- */
+
+/* v^{n+1/2} = v^{n-1/2} + (q/m)(E + vbar x B) dt with vbar the mean of the two
+   half-step velocities (eq:vadv), solved by the standard Boris split: half
+   electric kick, rotation about B, half electric kick.  a = (q/m) dt / 2;
+   t = a B, s = 2 t / (1 + t.t). */
+void orc_boris(double a, const double E[3], const double B[3], double v[3]) {
+  double vm[3], vp[3], vprime[3], t[3], s[3];
+  for (int c = 0; c < 3; ++c) vm[c] = v[c] + a * E[c];
+  for (int c = 0; c < 3; ++c) t[c] = a * B[c];
+  double tt = t[0] * t[0] + t[1] * t[1] + t[2] * t[2];
+  for (int c = 0; c < 3; ++c) s[c] = 2.0 * t[c] / (1.0 + tt);
+  vprime[0] = vm[0] + (vm[1] * t[2] - vm[2] * t[1]);
+  vprime[1] = vm[1] + (vm[2] * t[0] - vm[0] * t[2]);
+  vprime[2] = vm[2] + (vm[0] * t[1] - vm[1] * t[0]);
+  vp[0] = vm[0] + (vprime[1] * s[2] - vprime[2] * s[1]);
+  vp[1] = vm[1] + (vprime[2] * s[0] - vprime[0] * s[2]);
+  vp[2] = vm[2] + (vprime[0] * s[1] - vprime[1] * s[0]);
+  for (int c = 0; c < 3; ++c) v[c] = vp[c] + a * E[c];
+}
+
+/* ------------------------------------------------------------ move ----- */
+
+/* Offsets live in [-1,1) in half-cell units.  After xi' = xi + displacement,
+   the shift s is the unique integer with xi' - 2 s in [-1,1): a particle that
+   lands exactly on the right face (+1) belongs to the next cell at -1.
+   Returns s and updates *xi.  A non-finite or runaway xi' (|xi'| >= 1e6) keeps
+   the particle where it was and counts it in *bad. */
+static int reindex(double* xi, double disp, int64_t* gt1, int64_t* bad) {
+  double x = *xi + disp;
+  if (!(fabs(x) < 1.0e6)) {
+    if (bad) ++*bad;
+    return 0;
+  }
+  int s;
+  if (x >= 1.0) {
+    s = x < 3.0 ? 1 : (int)floor((x + 1.0) * 0.5);
+  } else if (x < -1.0) {
+    s = x >= -3.0 ? -1 : (int)floor((x + 1.0) * 0.5);
+  } else {
+    s = 0;
+  }
+  x -= 2.0 * s;
+  while (x >= 1.0) { x -= 2.0; ++s; }
+  while (x < -1.0) { x += 2.0; --s; }
+  if ((s > 1 || s < -1) && gt1) ++*gt1;
+  *xi = x;
+  return s;
+}
+
+void orc_push(const orc_params* p, int64_t np, int32_t* cell, double* ox, double* oy,
+              double* oz, double* ux, double* uy, double* uz, const double* w,
+              const double* E, const double* B, double diag[4], orc_status* st) {
+  double a = 0.5 * (p->qs / p->ms) * p->dt;
+  double K = 0.0, P[3] = {0.0, 0.0, 0.0};
+  int64_t gt1 = 0, bad = 0;
+  for (int64_t n = 0; n < np; ++n) {
+    double zoff = (p->ndim == 3) ? oz[n] : 0.0;
+    double Ep[3], Bp[3];
+    orc_gather(p, E, cell[n], ox[n], oy[n], zoff, Ep);
+    orc_gather(p, B, cell[n], ox[n], oy[n], zoff, Bp);
+    double vold[3] = {ux[n], uy[n], uz[n]};
+    double v[3] = {ux[n], uy[n], uz[n]};
+    orc_boris(a, Ep, Bp, v);
+    K += 0.5 * p->ms * w[n] * (vold[0] * v[0] + vold[1] * v[1] + vold[2] * v[2]);
+    for (int c = 0; c < 3; ++c) P[c] += p->ms * w[n] * 0.5 * (vold[c] + v[c]);
+    ux[n] = v[0];
+    uy[n] = v[1];
+    uz[n] = v[2];
+    /* x^{n+1} = x^n + v^{n+1/2} dt; in half-cell units the displacement
+       along an axis of width h is 2 v dt / h. */
+    int i, j, k;
+    ijk_of(p, cell[n], &i, &j, &k);
+    int64_t far = 0;
+    int si = reindex(&ox[n], 2.0 * v[0] * p->dt / p->dx, &far, &bad);
+    int sj = reindex(&oy[n], 2.0 * v[1] * p->dt / p->dy, &far, &bad);
+    int sk = 0;
+    if (p->ndim == 3) sk = reindex(&oz[n], 2.0 * v[2] * p->dt / p->dz, &far, &bad);
+    if (far) ++gt1; /* counted once per particle */
+    cell[n] = (int32_t)cell_of(p, i + si, j + sj, k + sk);
+  }
+  if (diag) {
+    diag[0] = K;
+    diag[1] = P[0];
+    diag[2] = P[1];
+    diag[3] = P[2];
+  }
+  if (st) {
+    st->moved_gt1 += gt1;
+    st->nonfinite += bad;
+  }
+}
+
+/* ------------------------------------------------------------ sort ----- */
+
+/* Counting sort: histogram of keys, exclusive prefix sum, then a scatter in
+   input order so equal keys keep their input order (stable). */
+void orc_sort(const orc_params* p, int64_t np, const int32_t* key, int64_t* perm,
+              int32_t* cell_start) {
+  int64_t nc = ncell_of(p);
+  int64_t* count = (int64_t*)calloc((size_t)nc + 1, sizeof(int64_t));
+  for (int64_t n = 0; n < np; ++n) count[key[n]] += 1;
+  int64_t run = 0;
+  for (int64_t c = 0; c < nc; ++c) {
+    int64_t here = count[c];
+    cell_start[c] = (int32_t)run;
+    count[c] = run; /* becomes the write cursor of cell c */
+    run += here;
+  }
+  cell_start[nc] = (int32_t)run;
+  for (int64_t n = 0; n < np; ++n) perm[count[key[n]]++] = n;
+  free(count);
+}
+
+/* --------------------------------------------------------- deposit ----- */
+
+/* Adds weight W of a particle of charge weight qw and velocity u to cell c. */
+static void accumulate(int64_t nc, double* n, double* J, int64_t c, double qwV, double W,
+                       const double u[3]) {
+  n[c] += qwV * W;
+  J[c] += qwV * W * u[0];
+  J[c + nc] += qwV * W * u[1];
+  J[c + 2 * nc] += qwV * W * u[2];
+}
+
+/* Moments at x - half_dt_back v.  NGP (eq:ngp): n = q w / V_c in the cell,
+   J = q w u / V_c.  QS (eq:quad, 7 cells):
+     centre (3 - dx^2 - dy^2 - dz^2)/6, i+-1: (1 +- dx)^2/12, likewise j, k,
+   each times q w / V_c for n and additionally times u for J (the current
+   carries the density weight times the particle velocity).  In 2D the k+-1
+   cells are the centre cell (nz = 1) and dz = 0. */
+void orc_deposit(const orc_params* p, int64_t np, const int32_t* cell, const double* ox,
+                 const double* oy, const double* oz, const double* ux, const double* uy,
+                 const double* uz, const double* w, double half_dt_back, double* n,
+                 double* J) {
+  int64_t nc = ncell_of(p);
+  memset(n, 0, sizeof(double) * (size_t)nc);
+  memset(J, 0, sizeof(double) * 3 * (size_t)nc);
+  double V = cell_volume(p);
+  for (int64_t q = 0; q < np; ++q) {
+    double u[3] = {ux[q], uy[q], uz[q]};
+    int i, j, k;
+    ijk_of(p, cell[q], &i, &j, &k);
+    double dx = ox[q], dy = oy[q], dz = (p->ndim == 3) ? oz[q] : 0.0;
+    /* x^{n+1/2} = x^{n+1} - (dt/2) v^{n+1/2}, re-indexed like a move. */
+    i += reindex(&dx, -2.0 * half_dt_back * u[0] / p->dx, NULL, NULL);
+    j += reindex(&dy, -2.0 * half_dt_back * u[1] / p->dy, NULL, NULL);
+    if (p->ndim == 3) k += reindex(&dz, -2.0 * half_dt_back * u[2] / p->dz, NULL, NULL);
+    double qwV = p->qs * w[q] / V;
+    if (p->shape == ORC_SHAPE_NGP) {
+      accumulate(nc, n, J, cell_of(p, i, j, k), qwV, 1.0, u);
+      continue;
+    }
+    accumulate(nc, n, J, cell_of(p, i, j, k), qwV, (3.0 - dx * dx - dy * dy - dz * dz) / 6.0, u);
+    accumulate(nc, n, J, cell_of(p, i + 1, j, k), qwV, (1.0 + dx) * (1.0 + dx) / 12.0, u);
+    accumulate(nc, n, J, cell_of(p, i, j + 1, k), qwV, (1.0 + dy) * (1.0 + dy) / 12.0, u);
+    accumulate(nc, n, J, cell_of(p, i, j, k + 1), qwV, (1.0 + dz) * (1.0 + dz) / 12.0, u);
+    accumulate(nc, n, J, cell_of(p, i - 1, j, k), qwV, (1.0 - dx) * (1.0 - dx) / 12.0, u);
+    accumulate(nc, n, J, cell_of(p, i, j - 1, k), qwV, (1.0 - dy) * (1.0 - dy) / 12.0, u);
+    accumulate(nc, n, J, cell_of(p, i, j, k - 1), qwV, (1.0 - dz) * (1.0 - dz) / 12.0, u);
+  }
+}
+
+/* ------------------------------------------------------- smoothing ----- */
+
+/* One pass = the (1,2,1)/4 binomial filter along x, then y, then z (an axis of
+   one cell is left unchanged, since its neighbours are the cell itself). */
+void orc_smooth(const orc_params* p, double* F, int32_t ncomp, int32_t npasses) {
+  int64_t nc = ncell_of(p);
+  double* tmp = (double*)malloc(sizeof(double) * (size_t)nc);
+  for (int pass = 0; pass < npasses; ++pass)
+    for (int comp = 0; comp < ncomp; ++comp) {
+      double* Q = F + comp * nc;
+      for (int a = 0; a < 3; ++a) {
+        int di = a == 0, dj = a == 1, dk = a == 2;
+        for (int64_t c = 0; c < nc; ++c) {
+          int i, j, k;
+          ijk_of(p, c, &i, &j, &k);
+          tmp[c] = 0.25 * (Q[cell_of(p, i - di, j - dj, k - dk)] + 2.0 * Q[c] +
+                           Q[cell_of(p, i + di, j + dj, k + dk)]);
+        }
+        memcpy(Q, tmp, sizeof(double) * (size_t)nc);
+      }
+    }
+  free(tmp);
+}
+
+/* ------------------------------------------------------------ fields --- */
+
+void orc_curl(const orc_params* p, const double* A, double* C) {
+  int64_t nc = ncell_of(p);
+  const double *Ax = A, *Ay = A + nc, *Az = A + 2 * nc;
+  for (int64_t c = 0; c < nc; ++c) {
+    int i, j, k;
+    ijk_of(p, c, &i, &j, &k);
+    C[c] = dcentred(p, Az, 1, i, j, k) - dcentred(p, Ay, 2, i, j, k);
+    C[c + nc] = dcentred(p, Ax, 2, i, j, k) - dcentred(p, Az, 0, i, j, k);
+    C[c + 2 * nc] = dcentred(p, Ay, 0, i, j, k) - dcentred(p, Ax, 1, i, j, k);
+  }
+}
+
+/* Ohm's law (eq:ohm) with mu0 J = curl B (low-frequency Ampere), the density
+   floor n_e <- max(n_e, n_f) applied to every use of the density, the EOS
+   p_e = n0 te (n_e/n0)^gamma and R_ei = eta J:
+     E = -grad(p_e)/n_e - u_i x B + (J x B)/n_e + eta J,  u_i = J_i / n_e. */
+void orc_ohm(const orc_params* p, const double* B, const double* n, const double* Ji,
+             double* E) {
+  int64_t nc = ncell_of(p);
+  double* pe = (double*)malloc(sizeof(double) * (size_t)nc);
+  double* J = (double*)malloc(sizeof(double) * 3 * (size_t)nc);
+  for (int64_t c = 0; c < nc; ++c) {
+    double ne = n[c] > p->n_floor ? n[c] : p->n_floor;
+    pe[c] = p->n0 * p->te * pow(ne / p->n0, p->gamma_e);
+  }
+  orc_curl(p, B, J);
+  for (int64_t c = 0; c < nc; ++c) {
+    int i, j, k;
+    ijk_of(p, c, &i, &j, &k);
+    double ne = n[c] > p->n_floor ? n[c] : p->n_floor;
+    double b[3] = {B[c], B[c + nc], B[c + 2 * nc]};
+    double jt[3] = {J[c], J[c + nc], J[c + 2 * nc]};
+    double ui[3] = {Ji[c] / ne, Ji[c + nc] / ne, Ji[c + 2 * nc] / ne};
+    double gp[3] = {dcentred(p, pe, 0, i, j, k), dcentred(p, pe, 1, i, j, k),
+                    dcentred(p, pe, 2, i, j, k)};
+    double uxb[3] = {ui[1] * b[2] - ui[2] * b[1], ui[2] * b[0] - ui[0] * b[2],
+                     ui[0] * b[1] - ui[1] * b[0]};
+    double jxb[3] = {jt[1] * b[2] - jt[2] * b[1], jt[2] * b[0] - jt[0] * b[2],
+                     jt[0] * b[1] - jt[1] * b[0]};
+    for (int a = 0; a < 3; ++a)
+      E[c + a * nc] = -gp[a] / ne - uxb[a] + jxb[a] / ne + p->eta * jt[a];
+  }
+  free(pe);
+  free(J);
+}
+
+static void field_energy(const orc_params* p, const double* B, double diag[2]) {
+  int64_t nc = ncell_of(p);
+  double V = cell_volume(p);
+  double mean[3] = {0, 0, 0}, wb = 0.0, wdb = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    for (int64_t c = 0; c < nc; ++c) mean[a] += B[c + a * nc];
+    mean[a] /= (double)nc;
+  }
+  for (int a = 0; a < 3; ++a)
+    for (int64_t c = 0; c < nc; ++c) {
+      double b = B[c + a * nc];
+      wb += 0.5 * b * b * V;
+      wdb += 0.5 * (b - mean[a]) * (b - mean[a]) * V;
+    }
+  diag[0] = wb;
+  diag[1] = wdb;
+}
+
+/* Faraday dB/dt = -curl E, subcycled nsub times per particle step (Sec. II.A).
+   Each substep of length h = dt/nsub is the explicit midpoint rule with the
+   moments held at their n+1/2 values:
+     Ea = Ohm(B),  B* = B - (h/2) curl Ea,  Eb = Ohm(B*),  B <- B - h curl Eb.
+   After the subcycle J_i is extrapolated (Sec. II.B)
+     J^{n+1} = 3/2 J^{n+1/2} - 1/2 J^{n-1/2}
+   and n the same way, and E^{n+1} = Ohm(B^{n+1}, n^{n+1}, J^{n+1}). */
+void orc_field_advance(const orc_params* p, double* B, const double* n_half,
+                       const double* J_half, const double* n_prev, const double* J_prev,
+                       double* E_out, int32_t mode, double diag[2], orc_status* st) {
+  int64_t nc = ncell_of(p);
+  if (st)
+    for (int64_t c = 0; c < nc; ++c)
+      if (n_half[c] < p->n_floor) st->floor_hits += 1;
+  if (mode == 1) {
+    orc_ohm(p, B, n_half, J_half, E_out);
+    if (diag) field_energy(p, B, diag);
+    return;
+  }
+  size_t v3 = sizeof(double) * 3 * (size_t)nc;
+  double* Ea = (double*)malloc(v3);
+  double* C = (double*)malloc(v3);
+  double* Bs = (double*)malloc(v3);
+  double h = p->dt / p->nsub;
+  for (int m = 0; m < p->nsub; ++m) {
+    orc_ohm(p, B, n_half, J_half, Ea);
+    orc_curl(p, Ea, C);
+    for (int64_t c = 0; c < 3 * nc; ++c) Bs[c] = B[c] - 0.5 * h * C[c];
+    orc_ohm(p, Bs, n_half, J_half, Ea);
+    orc_curl(p, Ea, C);
+    for (int64_t c = 0; c < 3 * nc; ++c) B[c] = B[c] - h * C[c];
+  }
+  double* n1 = (double*)malloc(sizeof(double) * (size_t)nc);
+  for (int64_t c = 0; c < nc; ++c) n1[c] = 1.5 * n_half[c] - 0.5 * n_prev[c];
+  for (int64_t c = 0; c < 3 * nc; ++c) Bs[c] = 1.5 * J_half[c] - 0.5 * J_prev[c];
+  orc_ohm(p, B, n1, Bs, E_out);
+  if (diag) field_energy(p, B, diag);
+  free(n1);
+  free(Ea);
+  free(C);
+  free(Bs);
+}

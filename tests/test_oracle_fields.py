@@ -1,0 +1,186 @@
+"""Pins of the oracle's field solver (Sec. II.A eq:ohm, Ampere, Faraday with
+subcycling; Sec. II.B centred differences and J_i extrapolation) and of the
+binomial smoothing, against closed forms derived by hand.
+
+Single circularly polarised mode.  With dB = A (0, cos kx, p sin kx) on the
+grid, the centred curl gives D x dB = -p k_e dB with k_e = sin(k dx)/dx, and
+dB x xhat is the same mode shifted a quarter wave.  Writing
+dB = alpha a + beta b (a the mode, b = a x xhat) and z = alpha + i beta, the
+hybrid equations with n = 1, uniform ion flow U xhat, resistivity eta reduce to
+the linear ODE dz/dt = lambda z with
+    lambda = -k_e^2 (eta + i) + i p U k_e,
+so one explicit-midpoint substep multiplies z by 1 + h lambda + (h lambda)^2/2.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2305_05600_amd import workloads as W
+
+
+def _cfg(nx=32, ny=1, nz=1, ndim=2, **kw):
+    base = dict(name="f", ndim=ndim, nx=nx, ny=ny, nz=nz, dx=0.5, dy=0.4, dz=1.0,
+                dt=0.05, nsub=4, te=0.3, n_floor=0.05, eta=0.0)
+    base.update(kw)
+    return W.Config(**base)
+
+
+def _mode(cfg, m, p, amp, axis="x"):
+    x, y, _ = W.cell_centres(cfg)
+    if axis == "x":
+        k = 2 * math.pi * m / (cfg.nx * cfg.dx)
+        a = np.stack([np.zeros(cfg.ncell), np.cos(k * x), p * np.sin(k * x)]) * amp
+        ke = math.sin(k * cfg.dx) / cfg.dx
+    return a, ke
+
+
+@pytest.mark.parametrize("p", [1, -1])
+@pytest.mark.parametrize("eta,U", [(0.0, 0.0), (0.05, 0.0), (0.0, 0.7), (0.02, -0.4)])
+def test_faraday_subcycle_single_mode(p, eta, U):
+    cfg = _cfg(eta=eta, nsub=5, dt=0.05)
+    a, ke = _mode(cfg, 2, p, 0.3)
+    b = np.stack([a[0], a[2], -a[1]])  # a x xhat
+    B = a.copy()
+    B[0] += 1.0
+    n = np.ones(cfg.ncell)
+    Ji = np.zeros((3, cfg.ncell))
+    Ji[0] = U
+    B1, E1, diag, _ = O.field_advance(cfg, B, n, Ji, n, Ji, mode=0)
+    h = cfg.dt / cfg.nsub
+    lam = -ke * ke * (eta + 1j) + 1j * p * U * ke
+    G = (1 + h * lam + (h * lam) ** 2 / 2) ** cfg.nsub
+    expect = G.real * a + G.imag * b
+    expect[0] += 1.0
+    assert np.allclose(B1, expect, rtol=0, atol=1e-13)
+    # E^{n+1} for this state: E = dJ x xhat... compare against the closed form
+    # E = -U xhat x B + (J x B) + eta J, J = -p k_e dB (n = 1)
+    dB = B1 - np.array([[1.0], [0.0], [0.0]])
+    J = -p * ke * dB
+    Bt = B1
+    Ecf = -np.cross(np.array([U, 0, 0])[None, :], Bt.T).T + np.cross(J.T, Bt.T).T + eta * J
+    assert np.allclose(E1, Ecf, atol=1e-13)
+    assert diag[0] == pytest.approx(0.5 * (B1**2).sum() * cfg.dx * cfg.dy * cfg.dz, rel=1e-14)
+
+
+def test_divergence_of_b_is_kept():
+    """D.B is unchanged by the subcycle: centred differences commute, D.(D x E) = 0."""
+    cfg = _cfg(nx=9, ny=7, nz=5, ndim=3, dz=0.6, eta=0.01, nsub=3)
+    B = W.random_field(3, cfg, 0.3, (1.0, 0.2, -0.1)).astype(float)
+    n = W.random_density(4, cfg).astype(float)
+    Ji = W.random_field(5, cfg, 0.2).astype(float)
+
+    def div(F):
+        i = np.arange(cfg.ncell) % cfg.nx
+        j = (np.arange(cfg.ncell) // cfg.nx) % cfg.ny
+        k = np.arange(cfg.ncell) // (cfg.nx * cfg.ny)
+
+        def at(di, dj, dk):
+            return ((i + di) % cfg.nx) + cfg.nx * (((j + dj) % cfg.ny) + cfg.ny * ((k + dk) % cfg.nz))
+
+        return ((F[0][at(1, 0, 0)] - F[0][at(-1, 0, 0)]) / (2 * cfg.dx)
+                + (F[1][at(0, 1, 0)] - F[1][at(0, -1, 0)]) / (2 * cfg.dy)
+                + (F[2][at(0, 0, 1)] - F[2][at(0, 0, -1)]) / (2 * cfg.dz))
+
+    B1, _, _, _ = O.field_advance(cfg, B, n, Ji, n, Ji, mode=0)
+    assert np.abs(div(B1) - div(B)).max() < 1e-12
+    assert np.abs(B1 - B).max() > 1e-4  # the field did change
+
+
+def test_ohm_uniform_plasma_at_rest():
+    cfg = _cfg(nx=6, ny=5, eta=0.1)
+    B = np.zeros((3, cfg.ncell))
+    B[0], B[1], B[2] = 1.0, -0.3, 0.2
+    E = O.ohm(cfg, B, np.full(cfg.ncell, 0.8), np.zeros((3, cfg.ncell)))
+    assert np.abs(E).max() == 0.0
+
+
+@pytest.mark.parametrize("gamma", [1.0, 5.0 / 3.0])
+def test_ohm_density_ripple(gamma):
+    """n = 1 + eps cos kx, uniform B, no flow: E_x = -D p_e / n with
+    p_e = te n^gamma, D cos kx = -k_e sin kx exactly on the grid for gamma = 1."""
+    cfg = _cfg(nx=24, gamma_e=gamma, te=0.4)
+    x, _, _ = W.cell_centres(cfg)
+    k = 2 * math.pi * 3 / (cfg.nx * cfg.dx)
+    n = 1 + 0.2 * np.cos(k * x)
+    B = np.zeros((3, cfg.ncell))
+    B[0] = 1.0
+    E = O.ohm(cfg, B, n, np.zeros((3, cfg.ncell)))
+    pe = cfg.te * n**gamma
+    if gamma == 1.0:
+        ke = math.sin(k * cfg.dx) / cfg.dx
+        Dp = cfg.te * 0.2 * (-ke) * np.sin(k * x)
+    else:
+        Dp = (np.roll(pe, -1) - np.roll(pe, 1)) / (2 * cfg.dx)
+    assert np.allclose(E[0], -Dp / n, atol=1e-14)
+    assert np.abs(E[1:]).max() == 0.0
+
+
+def test_ohm_floor_and_flow():
+    """Below the floor the density used is n_f, also inside u_i = J_i/n."""
+    cfg = _cfg(nx=8, ny=3, n_floor=0.05, te=0.0)
+    B = np.zeros((3, cfg.ncell))
+    B[2] = 2.0
+    n = np.full(cfg.ncell, 0.01)
+    Ji = np.zeros((3, cfg.ncell))
+    Ji[0] = 0.003
+    E = O.ohm(cfg, B, n, Ji)
+    # E = -u x B with u = (0.003/0.05) xhat, B = 2 zhat -> E_y = +0.06 * 2
+    assert np.allclose(E[1], 0.003 / 0.05 * 2.0, rtol=1e-14)
+    assert np.abs(E[0]).max() == 0 and np.abs(E[2]).max() == 0
+
+
+def test_hall_force_sums_to_minus_b_divb():
+    """Summation by parts: sum_c (D x B) x B = -sum_c B (D.B) on a periodic grid."""
+    cfg = _cfg(nx=7, ny=6, nz=5, ndim=3, dz=0.9, te=0.0, eta=0.0)
+    B = W.random_field(12, cfg, 1.0).astype(float)
+    n = np.ones(cfg.ncell)
+    E = O.ohm(cfg, B, n, np.zeros((3, cfg.ncell)))  # E = (D x B) x B here
+    i = np.arange(cfg.ncell) % cfg.nx
+    j = (np.arange(cfg.ncell) // cfg.nx) % cfg.ny
+    k = np.arange(cfg.ncell) // (cfg.nx * cfg.ny)
+
+    def at(di, dj, dk):
+        return ((i + di) % cfg.nx) + cfg.nx * (((j + dj) % cfg.ny) + cfg.ny * ((k + dk) % cfg.nz))
+
+    divB = ((B[0][at(1, 0, 0)] - B[0][at(-1, 0, 0)]) / (2 * cfg.dx)
+            + (B[1][at(0, 1, 0)] - B[1][at(0, -1, 0)]) / (2 * cfg.dy)
+            + (B[2][at(0, 0, 1)] - B[2][at(0, 0, -1)]) / (2 * cfg.dz))
+    assert np.allclose(E.sum(axis=1), -(B * divB).sum(axis=1), atol=1e-11)
+
+
+def test_extrapolation_to_full_step():
+    """E^{n+1} uses n, J_i extrapolated as 3/2 (n+1/2) - 1/2 (n-1/2): with no
+    subcycles B is unchanged and E equals the closed form for the extrapolated
+    state (uniform flow U across uniform B: E = -U x B)."""
+    cfg = _cfg(nx=5, ny=4, nsub=0, te=0.0)
+    B = np.zeros((3, cfg.ncell))
+    B[2] = 1.5
+    n_half = np.full(cfg.ncell, 1.2)
+    n_prev = np.full(cfg.ncell, 1.6)  # -> n^{n+1} = 1.0
+    J_half = np.zeros((3, cfg.ncell))
+    J_prev = np.zeros((3, cfg.ncell))
+    J_half[0], J_prev[0] = 0.5, 0.9   # -> J^{n+1} = 0.3
+    B1, E, _, _ = O.field_advance(cfg, B, n_half, J_half, n_prev, J_prev, mode=0)
+    assert np.array_equal(B1, B)
+    assert np.allclose(E[1], 0.3 / 1.0 * 1.5, rtol=1e-14)
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_smoothing_transfer_function(ndim):
+    """One (1,2,1)/4 pass multiplies a Fourier mode by (1 + cos(k h))/2 per axis;
+    the mean is kept."""
+    cfg = _cfg(nx=16, ny=12, nz=(8 if ndim == 3 else 1), ndim=ndim)
+    x, y, z = W.cell_centres(cfg)
+    kx = 2 * math.pi * 3 / (cfg.nx * cfg.dx)
+    ky = 2 * math.pi * 2 / (cfg.ny * cfg.dy)
+    kz = 2 * math.pi * 1 / (cfg.nz * cfg.dz)
+    F = 0.7 + np.cos(kx * x + ky * y + (kz * z if ndim == 3 else 0))
+    for npass in (1, 3):
+        S = O.smooth(cfg, F, npass)
+        g = ((1 + math.cos(kx * cfg.dx)) / 2 * (1 + math.cos(ky * cfg.dy)) / 2) ** npass
+        if ndim == 3:
+            g *= ((1 + math.cos(kz * cfg.dz)) / 2) ** npass
+        assert np.allclose(S, 0.7 + g * (F - 0.7), atol=1e-14)
+        assert S.mean() == pytest.approx(F.mean(), rel=1e-14)
