@@ -1,0 +1,189 @@
+/*
+ * hvpic.h -- C-ABI of the MI355X (gfx950) hybrid-PIC step library libhvpic.so.
+ *
+ * The library advances kinetic ions coupled to a massless electron fluid by
+ * explicit time stepping, after Le et al., "Hybrid-VPIC: an open-source
+ * kinetic/fluid hybrid particle-in-cell code" (arXiv 2305.05600):
+ *   - ion push: leapfrog with the non-relativistic Boris method (Sec. II.B,
+ *     eq:vadv and the position update that follows it);
+ *   - particle shapes NGP (Sec. II.B, eq:ngp) and QS (App. B, eq:quad for the
+ *     deposit, eq:quadFI + eq:quadF for the gather);
+ *   - Ohm's law for massless electrons (Sec. II.A, eq:ohm) with the density
+ *     floor, low-frequency Ampere, an isothermal/polytropic EOS and
+ *     R_ei = eta J; Faraday's law subcycled inside the particle step;
+ *     J_i extrapolated to the full step (Sec. II.B);
+ *   - a stable counting sort of the particle store by cell (the store keeps a
+ *     cell index plus in-cell offsets, Sec. II.B).
+ *
+ * Units: hybrid units with n0 = B0 = m_i = e = mu0 = 1 (lengths in d_i, time
+ * in 1/Omega_i, speed in v_A).
+ *
+ * Data layout (all arrays are DEVICE memory owned by the caller):
+ *   - cell index I = i + nx*(j + ny*k), 0 <= I < ncell = nx*ny*nz;
+ *   - particles are structure-of-arrays: int32 cell[n]; float ox, oy[, oz][n]
+ *     in-cell offsets in [-1, 1) in half-cell units about the cell centre
+ *     (-1 is the left face; a particle on the right face belongs to the next
+ *     cell); float ux, uy, uz[n] velocity; float w[n] weight.  2D runs use
+ *     nz = 1 and pass oz = NULL;
+ *   - grid fields are float [3][ncell] component-major (x block, y block,
+ *     z block); densities are float [ncell];
+ *   - cell_start is int32 [ncell+1]: particles of cell c occupy
+ *     [cell_start[c], cell_start[c+1]) of a sorted store.
+ *
+ * Execution: every call validates its arguments on the host, then enqueues
+ * kernels on the HIP stream given to hvpic_init and returns without waiting.
+ * Only hvpic_sync_status blocks.  A context is not thread-safe; use one
+ * context per stream.  The library allocates no device memory: every scratch
+ * buffer lives in the caller-provided workspace.
+ *
+ * Errors: functions return HVPIC_OK (0) or a negative code.  Argument errors
+ * return HVPIC_EINVAL and launch nothing.  Conditions found by kernels are
+ * sticky status bits read (and cleared) by hvpic_sync_status.
+ */
+#ifndef HVPIC_H
+#define HVPIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  HVPIC_OK = 0,
+  HVPIC_EINVAL = -1, /* bad argument; nothing was launched            */
+  HVPIC_ENOMEM = -2, /* workspace too small for the request           */
+  HVPIC_EHIP = -3,   /* a HIP runtime call or kernel launch failed    */
+  HVPIC_ESTATE = -4  /* context used before init or after finalize    */
+};
+
+enum { HVPIC_SHAPE_NGP = 0, HVPIC_SHAPE_QS = 1 };
+
+/* Sticky status bits (hvpic_sync_status). */
+enum {
+  HVPIC_FLAG_MOVE_GT1 = 1,   /* a particle crossed more than one cell face in a
+                                step; the neighbour-move sort fell back to the
+                                full sort                                      */
+  HVPIC_FLAG_FLOOR_HIT = 2,  /* n^{n+1/2} fell below n_floor in some cell      */
+  HVPIC_FLAG_NONFINITE = 4,  /* non-finite or runaway displacement; the
+                                particle was left in place                     */
+  HVPIC_FLAG_BAD_INPUT = 8   /* a cell index outside [0, ncell) or an
+                                inconsistent cell_start was met; the offending
+                                entries were skipped                           */
+};
+
+typedef struct {
+  int32_t ndim;              /* 2 or 3                                          */
+  int32_t nx, ny, nz;        /* cells per axis; nz = 1 when ndim = 2            */
+  double dx, dy, dz;         /* cell sizes (d_i); the cell volume is dx*dy*dz   */
+  double dt;                 /* particle time step (1/Omega_i)                  */
+  int32_t nsub;              /* Faraday substeps per particle step (Sec. II.A)  */
+  int32_t shape;             /* HVPIC_SHAPE_NGP or HVPIC_SHAPE_QS               */
+  int32_t nsmooth;           /* binomial passes applied by hvpic_smooth users   */
+  double qs, ms;             /* ion species charge (Z e) and mass               */
+  double te, gamma_e, n0;    /* EOS p_e = n0 te (n/n0)^gamma_e (Sec. II.A)      */
+  double n_floor;            /* density floor n_f of the field solver           */
+  double eta;                /* resistivity: R_ei = eta J                       */
+  double eta_h;              /* hyper-resistivity; must be 0 in this version    */
+  int64_t np_capacity;       /* largest particle count any call will pass       */
+} hvpic_params;
+
+typedef struct {
+  int64_t n;                 /* particle count, 0 <= n <= np_capacity            */
+  int32_t* cell;
+  float *ox, *oy, *oz;       /* oz NULL in 2D                                   */
+  float *ux, *uy, *uz;
+  float* w;
+} hvpic_particles;
+
+typedef struct hvpic_ctx hvpic_ctx;
+
+/* Bytes of device workspace hvpic_init needs for these parameters.  Pure host
+   computation; returns HVPIC_EINVAL for invalid parameters. */
+int hvpic_workspace_bytes(const hvpic_params* params, size_t* bytes);
+
+/* Creates a context bound to `hip_stream` (a hipStream_t; NULL = the null
+   stream) and to `workspace` (device memory of at least
+   hvpic_workspace_bytes, 256-byte aligned, owned by the caller and kept alive
+   until hvpic_finalize).  Enqueues the clearing of the workspace's counters
+   on the stream.  The context copies *params. */
+int hvpic_init(const hvpic_params* params, void* hip_stream, void* workspace,
+               hvpic_ctx** out);
+
+/* Frees the host-side context only (never the caller's memory). */
+int hvpic_finalize(hvpic_ctx* ctx);
+
+/* Gather + push (Sec. II.B eq:vadv, App. B eq:quadF): for each particle, E^n
+   and B^n are interpolated at x^n with the context's shape, the velocity is
+   advanced v^{n-1/2} -> v^{n+1/2} by the Boris method with
+   a = (qs/ms) dt / 2 (half electric kick, rotation by t = a B,
+   s = 2t/(1+t.t), half electric kick), and the particle moves
+   x^{n+1} = x^n + v^{n+1/2} dt with its cell index and offsets renormalised
+   into [-1, 1).  Updates p->cell, offsets and velocities in place.
+   E, B: [3][ncell].  When n_mid and J_mid are both non-NULL, the moments at
+   x^{n+1/2} = x^n + (dt/2) v^{n+1/2} are also deposited in the same pass
+   (overwriting n_mid [ncell] and J_mid [3][ncell]; identical in value to
+   hvpic_deposit with half_dt_back = dt/2 after the push), which saves one
+   read of the particle store.  The fused deposit is fastest on a store sorted
+   by cell.  diag_out (device, may be NULL) receives 4 doubles:
+   K = sum 1/2 ms w v^{n-1/2}.v^{n+1/2} and P = sum ms w (v^{n-1/2}+v^{n+1/2})/2. */
+int hvpic_gather_push(hvpic_ctx* ctx, hvpic_particles* p, const float* E,
+                      const float* B, float* n_mid, float* J_mid, double* diag_out);
+
+/* Stable counting sort by cell index: out receives the particles of `in` in
+   order of cell, equal cells in input order; cell_start [ncell+1] is written.
+   `in` and `out` must not overlap and out->n is set to in->n (out's arrays
+   must hold in->n entries; out->oz may be NULL in 2D).
+   If full == 0 and cell_start_prev (the cell_start of `in` before its last
+   push) is given, the neighbour-move path is used: it relies on every
+   particle having moved at most one cell per axis since the store was sorted;
+   particles that moved further are detected on the device and the call then
+   completes with the general sort instead (HVPIC_FLAG_MOVE_GT1 is raised).
+   full != 0 or cell_start_prev == NULL always runs the general sort (an
+   LSD radix sort on the cell key).  Both paths give identical, bit-exact
+   results. */
+int hvpic_sort(hvpic_ctx* ctx, const hvpic_particles* in, hvpic_particles* out,
+               const int32_t* cell_start_prev, int32_t* cell_start, int full);
+
+/* Moments of the ion species (Sec. II.A n_e, J_i; eq:ngp / eq:quad) at
+   x - half_dt_back * v (half_dt_back = dt/2 after a push gives
+   x^{n+1/2}; 0 deposits at x).  Contributions per particle: n += qs w W/V_c,
+   J += qs w W u/V_c with W the shape weight of each cell.  Overwrites
+   n [ncell] and J [3][ncell].  cell_start may be NULL; when given (the store
+   is sorted) it is only used as a locality hint. */
+int hvpic_deposit(hvpic_ctx* ctx, const hvpic_particles* p, const int32_t* cell_start,
+                  float half_dt_back, float* n, float* J);
+
+/* Field advance (Sec. II.A eq:ohm + Faraday with subcycling, Sec. II.B
+   extrapolation).  mode 0 (full step): with nbar = max(n_half, n_floor) and
+   J_half held fixed, nsub explicit-midpoint substeps of h = dt/nsub
+       Ea = Ohm(B), B* = B - (h/2) curl Ea, Eb = Ohm(B*), B <- B - h curl Eb,
+   then n^{n+1} = 3/2 n_half - 1/2 n_prev, J^{n+1} likewise, and
+   E_out = Ohm(B^{n+1}, n^{n+1}, J^{n+1}).  mode 1 (E only): E_out =
+   Ohm(B, n_half, J_half); B, n_prev, J_prev are not touched (may be NULL).
+   Ohm(B, n, J_i) = -u_i x B + (J x B)/n_f - grad(p_e)/n_f + eta J with
+   J = curl B (centred differences), n_f = max(n, n_floor), u_i = J_i/n_f,
+   p_e = n0 te (n_f/n0)^gamma_e; 1/n_f is formed in double precision.
+   diag_out (device, may be NULL): 2 doubles {W_B, W_dB} =
+   {1/2 sum |B|^2 V_c, 1/2 sum |B - <B>|^2 V_c} of the B left behind. */
+int hvpic_field_advance(hvpic_ctx* ctx, float* B, const float* n_half,
+                        const float* J_half, const float* n_prev, const float* J_prev,
+                        float* E_out, int mode, double* diag_out);
+
+/* npasses of the binomial (1,2,1)/4 filter along every axis (Sec. II.B
+   smoothing), in place on ncomp component-major grid arrays F. */
+int hvpic_smooth(hvpic_ctx* ctx, float* F, int ncomp, int npasses);
+
+/* Waits for the context's stream, returns the sticky status bits in *flags
+   and, if counts is non-NULL, counts[0..2] = {particles moved more than one
+   cell, non-finite/runaway particles, floor hits}; then clears them. */
+int hvpic_sync_status(hvpic_ctx* ctx, uint32_t* flags, int64_t* counts);
+
+/* Static description of an error code. */
+const char* hvpic_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,237 @@
+// C-ABI entry points of libhvpic.so: argument validation, the context and the
+// workspace layout.  Every compute step runs in the kernels of particles.hip,
+// sort.hip and fields.hip on the context's stream.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+
+#include "hvpic_internal.hpp"
+
+namespace hvpic {
+namespace {
+
+bool finite_pos(double x) { return isfinite(x) && x > 0.0; }
+
+bool params_ok(const hvpic_params* p) {
+  if (!p) return false;
+  if (p->ndim != 2 && p->ndim != 3) return false;
+  if (p->nx < 1 || p->ny < 1 || p->nz < 1) return false;
+  if (p->ndim == 2 && p->nz != 1) return false;
+  const int64_t nc = (int64_t)p->nx * p->ny * p->nz;
+  if (nc >= (1ll << 31) - 1) return false;
+  if (!finite_pos(p->dx) || !finite_pos(p->dy) || !finite_pos(p->dz) || !finite_pos(p->dt))
+    return false;
+  if (p->nsub < 0 || p->nsmooth < 0) return false;
+  if (p->shape != HVPIC_SHAPE_NGP && p->shape != HVPIC_SHAPE_QS) return false;
+  if (!isfinite(p->qs) || !finite_pos(p->ms)) return false;
+  if (!isfinite(p->te) || p->te < 0.0 || !finite_pos(p->gamma_e) || !finite_pos(p->n0) ||
+      !finite_pos(p->n_floor))
+    return false;
+  if (!isfinite(p->eta) || p->eta < 0.0) return false;
+  if (p->eta_h != 0.0) return false;  // hyper-resistivity is not implemented
+  if (p->np_capacity < 0 || p->np_capacity >= (1ll << 31) - 1) return false;
+  return true;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+bool parts_ok(const hvpic_ctx* c, const hvpic_particles* q, bool need_w) {
+  if (!q || q->n < 0 || q->n > c->p.np_capacity) return false;
+  if (q->n == 0) return true;
+  if (!q->cell || !q->ox || !q->oy || !q->ux || !q->uy || !q->uz) return false;
+  if (need_w && !q->w) return false;
+  if (c->p.ndim == 3 && !q->oz) return false;
+  return true;
+}
+
+bool ctx_ok(const hvpic_ctx* c) { return c && c->magic == kMagic; }
+
+__global__ void k_init_ws(Status* st, double* a, double* b, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) {
+    st->flags = 0;
+    st->moved_gt1 = st->nonfinite = st->floor_hits = st->bad_input = 0;
+    st->sort_fallback = 0;
+    st->done_push = st->done_field = 0;
+  }
+  if (i < n) {
+    a[i] = 0.0;
+    b[i] = 0.0;
+  }
+}
+
+__global__ void k_clear_status(Status* st) {
+  if (threadIdx.x == 0) {
+    st->flags = 0;
+    st->moved_gt1 = st->nonfinite = st->floor_hits = st->bad_input = 0;
+  }
+}
+
+}  // namespace
+
+Layout workspace_layout(const hvpic_params* p) {
+  Layout L;
+  const int64_t nc = (int64_t)p->nx * p->ny * p->nz;
+  const int64_t cap = std::max<int64_t>(p->np_capacity, 1);
+  const int ndir = p->ndim == 2 ? 9 : 27;
+  const int64_t ntiles = ceil_div(cap, kRadixTile);
+  const int64_t nblk = std::max(ceil_div(nc, kScanTile), ceil_div(kRadixBins * ntiles, kScanTile)) + 1;
+  size_t off = 0;
+  L.status = off;    off += align256(sizeof(Status));
+  L.diag_acc = off;  off += align256(sizeof(double) * 4 * kDiagSlots);
+  L.field_acc = off; off += align256(sizeof(double) * 4 * kDiagSlots);
+  L.sort_cnt = off;  off += align256(sizeof(uint32_t) * ndir * nc);
+  L.sort_blk = off;  off += align256(sizeof(uint32_t) * nblk);
+  L.rkey0 = off;     off += align256(sizeof(uint32_t) * cap);
+  L.rkey1 = off;     off += align256(sizeof(uint32_t) * cap);
+  L.rval0 = off;     off += align256(sizeof(uint32_t) * cap);
+  L.rval1 = off;     off += align256(sizeof(uint32_t) * cap);
+  L.rhist = off;     off += align256(sizeof(uint32_t) * kRadixBins * ntiles);
+  L.fscratch = off;  off += align256(sizeof(float) * 16 * nc);
+  L.total = off;
+  return L;
+}
+
+}  // namespace hvpic
+
+using namespace hvpic;
+
+extern "C" {
+
+int hvpic_workspace_bytes(const hvpic_params* params, size_t* bytes) {
+  if (!params_ok(params) || !bytes) return HVPIC_EINVAL;
+  *bytes = workspace_layout(params).total;
+  return HVPIC_OK;
+}
+
+int hvpic_init(const hvpic_params* params, void* hip_stream, void* workspace, hvpic_ctx** out) {
+  if (!params_ok(params) || !workspace || !out) return HVPIC_EINVAL;
+  if (((uintptr_t)workspace & 255) != 0) return HVPIC_EINVAL;
+  hvpic_ctx* c = new (std::nothrow) hvpic_ctx;
+  if (!c) return HVPIC_ENOMEM;
+  memset(c, 0, sizeof(*c));
+  c->p = *params;
+  c->stream = (hipStream_t)hip_stream;
+  c->ws = (char*)workspace;
+  const Layout L = workspace_layout(params);
+  c->ws_bytes = L.total;
+  c->ncell = params->nx * params->ny * params->nz;
+  c->magic = kMagic;
+  c->sort_gen = 0;
+  const double qm = params->qs / params->ms;
+  c->a = (float)(0.5 * qm * params->dt);
+  c->kx = (float)(2.0 * params->dt / params->dx);
+  c->ky = (float)(2.0 * params->dt / params->dy);
+  c->kz = (float)(2.0 * params->dt / params->dz);
+  c->qV = (float)(params->qs / (params->dx * params->dy * params->dz));
+  c->fnx = make_fastdiv((uint32_t)params->nx);
+  c->fny = make_fastdiv((uint32_t)params->ny);
+  c->status = (Status*)(c->ws + L.status);
+  c->diag_acc = (double*)(c->ws + L.diag_acc);
+  c->field_acc = (double*)(c->ws + L.field_acc);
+  c->sort_cnt = (uint32_t*)(c->ws + L.sort_cnt);
+  c->sort_blk = (int32_t*)(c->ws + L.sort_blk);
+  c->rkey[0] = (uint32_t*)(c->ws + L.rkey0);
+  c->rkey[1] = (uint32_t*)(c->ws + L.rkey1);
+  c->rval[0] = (uint32_t*)(c->ws + L.rval0);
+  c->rval[1] = (uint32_t*)(c->ws + L.rval1);
+  c->rhist = (uint32_t*)(c->ws + L.rhist);
+  c->fscratch = (float*)(c->ws + L.fscratch);
+  const int n = 4 * kDiagSlots;
+  hipLaunchKernelGGL(k_init_ws, dim3((n + 255) / 256), dim3(256), 0, c->stream, c->status,
+                     c->diag_acc, c->field_acc, n);
+  if (hipGetLastError() != hipSuccess) {
+    delete c;
+    return HVPIC_EHIP;
+  }
+  *out = c;
+  return HVPIC_OK;
+}
+
+int hvpic_finalize(hvpic_ctx* ctx) {
+  if (!ctx_ok(ctx)) return HVPIC_ESTATE;
+  ctx->magic = 0;
+  delete ctx;
+  return HVPIC_OK;
+}
+
+int hvpic_gather_push(hvpic_ctx* ctx, hvpic_particles* p, const float* E, const float* B,
+                      float* n_mid, float* J_mid, double* diag_out) {
+  if (!ctx_ok(ctx)) return HVPIC_ESTATE;
+  const bool need_w = (n_mid && J_mid) || diag_out;
+  if (!parts_ok(ctx, p, need_w) || !E || !B) return HVPIC_EINVAL;
+  if ((n_mid == nullptr) != (J_mid == nullptr)) return HVPIC_EINVAL;
+  return launch_gather_push(ctx, p, E, B, n_mid, J_mid, diag_out);
+}
+
+int hvpic_sort(hvpic_ctx* ctx, const hvpic_particles* in, hvpic_particles* out,
+               const int32_t* cell_start_prev, int32_t* cell_start, int full) {
+  if (!ctx_ok(ctx)) return HVPIC_ESTATE;
+  if (!parts_ok(ctx, in, true) || !out || !cell_start) return HVPIC_EINVAL;
+  if (in->n > 0) {
+    if (!out->cell || !out->ox || !out->oy || !out->ux || !out->uy || !out->uz || !out->w)
+      return HVPIC_EINVAL;
+    if (ctx->p.ndim == 3 && !out->oz) return HVPIC_EINVAL;
+    if (out->cell == in->cell || out->ox == in->ox || out->ux == in->ux || out->w == in->w)
+      return HVPIC_EINVAL;
+  }
+  return launch_sort(ctx, in, out, cell_start_prev, cell_start, full);
+}
+
+int hvpic_deposit(hvpic_ctx* ctx, const hvpic_particles* p, const int32_t* cell_start,
+                  float half_dt_back, float* n, float* J) {
+  (void)cell_start;
+  if (!ctx_ok(ctx)) return HVPIC_ESTATE;
+  if (!parts_ok(ctx, p, true) || !n || !J || !isfinite(half_dt_back)) return HVPIC_EINVAL;
+  return launch_deposit(ctx, p, half_dt_back, n, J);
+}
+
+int hvpic_field_advance(hvpic_ctx* ctx, float* B, const float* n_half, const float* J_half,
+                        const float* n_prev, const float* J_prev, float* E_out, int mode,
+                        double* diag_out) {
+  if (!ctx_ok(ctx)) return HVPIC_ESTATE;
+  if (!B || !n_half || !J_half || !E_out) return HVPIC_EINVAL;
+  if (mode != 0 && mode != 1) return HVPIC_EINVAL;
+  if (mode == 0 && (!n_prev || !J_prev)) return HVPIC_EINVAL;
+  return launch_field_advance(ctx, B, n_half, J_half, n_prev, J_prev, E_out, mode, diag_out);
+}
+
+int hvpic_smooth(hvpic_ctx* ctx, float* F, int ncomp, int npasses) {
+  if (!ctx_ok(ctx)) return HVPIC_ESTATE;
+  if (!F || ncomp < 1 || ncomp > 3 || npasses < 0) return HVPIC_EINVAL;
+  return launch_smooth(ctx, F, ncomp, npasses);
+}
+
+int hvpic_sync_status(hvpic_ctx* ctx, uint32_t* flags, int64_t* counts) {
+  if (!ctx_ok(ctx)) return HVPIC_ESTATE;
+  if (!flags) return HVPIC_EINVAL;
+  if (hipStreamSynchronize(ctx->stream) != hipSuccess) return HVPIC_EHIP;
+  Status h;
+  if (hipMemcpy(&h, ctx->status, sizeof(Status), hipMemcpyDeviceToHost) != hipSuccess)
+    return HVPIC_EHIP;
+  *flags = h.flags;
+  if (counts) {
+    counts[0] = (int64_t)h.moved_gt1;
+    counts[1] = (int64_t)h.nonfinite;
+    counts[2] = (int64_t)h.floor_hits;
+  }
+  hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(64), 0, ctx->stream, ctx->status);
+  if (hipGetLastError() != hipSuccess) return HVPIC_EHIP;
+  if (hipStreamSynchronize(ctx->stream) != hipSuccess) return HVPIC_EHIP;
+  return HVPIC_OK;
+}
+
+const char* hvpic_strerror(int code) {
+  switch (code) {
+    case HVPIC_OK: return "ok";
+    case HVPIC_EINVAL: return "invalid argument";
+    case HVPIC_ENOMEM: return "out of memory or workspace too small";
+    case HVPIC_EHIP: return "HIP runtime error";
+    case HVPIC_ESTATE: return "context not initialised";
+    default: return "unknown error";
+  }
+}
+
+}  // extern "C"

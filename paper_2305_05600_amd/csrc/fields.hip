@@ -1,0 +1,372 @@
+// Field solver kernels of libhvpic.so (gfx950).
+//
+// Method (arXiv 2305.05600, Sec. II.A and II.B):
+//   Ohm's law (eq:ohm) for massless electrons, with mu0 J = curl B, the
+//   density floor n_f = max(n, n_floor) used everywhere the density enters,
+//   p_e = n0 te (n_f/n0)^gamma and R_ei = eta J:
+//       E = -u_i x B + (J x B)/n_f - grad(p_e)/n_f + eta J,   u_i = J_i/n_f;
+//   Faraday dB/dt = -curl E, subcycled: nsub explicit-midpoint substeps with
+//   the moments held at their n+1/2 values; J_i (and n) extrapolated to the
+//   full step as 3/2 (n+1/2) - 1/2 (n-1/2); gradients are centred differences
+//   on the cell-centred grid.
+//
+// The moments are frozen during the subcycle, so one prep kernel forms
+// 1/n_f (in FP64), u_i and -grad(p_e)/n_f once per step.  Each RK2 stage is
+// then one kernel that evaluates Ohm's law at the 2*ndim neighbours of a cell
+// and takes the curl; E is never stored.  All grids are small enough to live in
+// the MI355X L2/MALL during the subcycle, so the stages are latency-bound and
+// each lane keeps its work independent.
+#include "hvpic_internal.hpp"
+
+namespace hvpic {
+namespace {
+
+struct FGeo {
+  int nx, ny, nz, ncell, nxny;
+  float idx2, idy2, idz2;  // 1 / (2 dx) etc.
+  FastDiv fnx, fny;
+};
+
+struct Aux {
+  float* inv;  // 1/n_f
+  float* u;    // [3][ncell] u_i
+  float* gp;   // [3][ncell] -grad(p_e)/n_f
+};
+
+__device__ __forceinline__ void fijk(int c, const FGeo& g, int& i, int& j, int& k) {
+  const uint32_t q = fdiv((uint32_t)c, g.fnx);
+  i = c - (int)q * g.nx;
+  const uint32_t q2 = fdiv(q, g.fny);
+  j = (int)q - (int)q2 * g.ny;
+  k = (int)q2;
+}
+
+// Linear indices of the +-x, +-y, +-z neighbours (periodic).
+struct Nbr {
+  int xm, xp, ym, yp, zm, zp;
+};
+
+__device__ __forceinline__ Nbr neighbours(int c, int i, int j, int k, const FGeo& g) {
+  Nbr n;
+  n.xm = i == 0 ? c + g.nx - 1 : c - 1;
+  n.xp = i == g.nx - 1 ? c - g.nx + 1 : c + 1;
+  n.ym = j == 0 ? c + g.nxny - g.nx : c - g.nx;
+  n.yp = j == g.ny - 1 ? c - g.nxny + g.nx : c + g.nx;
+  n.zm = k == 0 ? c + g.ncell - g.nxny : c - g.nxny;
+  n.zp = k == g.nz - 1 ? c - g.ncell + g.nxny : c + g.nxny;
+  return n;
+}
+
+template <int NDIM>
+__device__ __forceinline__ void curl_at(const float* __restrict__ A, int c, const FGeo& g,
+                                        float out[3]) {
+  int i, j, k;
+  fijk(c, g, i, j, k);
+  const Nbr n = neighbours(c, i, j, k, g);
+  const int nc = g.ncell;
+  const float* Ax = A;
+  const float* Ay = A + nc;
+  const float* Az = A + 2 * nc;
+  const float dyAz = (Az[n.yp] - Az[n.ym]) * g.idy2;
+  const float dxAz = (Az[n.xp] - Az[n.xm]) * g.idx2;
+  const float dxAy = (Ay[n.xp] - Ay[n.xm]) * g.idx2;
+  const float dyAx = (Ax[n.yp] - Ax[n.ym]) * g.idy2;
+  float dzAy = 0.f, dzAx = 0.f;
+  if (NDIM == 3) {
+    dzAy = (Ay[n.zp] - Ay[n.zm]) * g.idz2;
+    dzAx = (Ax[n.zp] - Ax[n.zm]) * g.idz2;
+  }
+  out[0] = dyAz - dzAy;
+  out[1] = dzAx - dxAz;
+  out[2] = dxAy - dyAx;
+}
+
+// Ohm's law at cell c with the frozen-moment terms precomputed in aux.
+template <int NDIM>
+__device__ __forceinline__ void ohm_at(const float* __restrict__ B, const Aux& aux, float eta, int c,
+                                       const FGeo& g, float E[3]) {
+  const int nc = g.ncell;
+  float J[3];
+  curl_at<NDIM>(B, c, g, J);
+  const float b0 = B[c], b1 = B[nc + c], b2 = B[2 * nc + c];
+  const float inv = aux.inv[c];
+  const float u0 = aux.u[c], u1 = aux.u[nc + c], u2 = aux.u[2 * nc + c];
+  // (J - J_i) x B / n_f is -u_i x B + J x B / n_f
+  const float w0 = J[0] * inv - u0, w1 = J[1] * inv - u1, w2 = J[2] * inv - u2;
+  E[0] = (w1 * b2 - w2 * b1) + aux.gp[c] + eta * J[0];
+  E[1] = (w2 * b0 - w0 * b2) + aux.gp[nc + c] + eta * J[1];
+  E[2] = (w0 * b1 - w1 * b0) + aux.gp[2 * nc + c] + eta * J[2];
+}
+
+__device__ __forceinline__ float pressure(float n, float nfloor, float te_n0, float n0, float gam,
+                                          bool iso) {
+  const float nf = fmaxf(n, nfloor);
+  return iso ? te_n0 / n0 * nf : te_n0 * powf(nf / n0, gam);
+}
+
+// Per-step frozen terms from n_eff = ca*na + cb*nb, J_eff = ca*Ja + cb*Jb.
+template <int NDIM>
+__global__ __launch_bounds__(kBlock) void k_field_prep(const float* __restrict__ na,
+                                                       const float* __restrict__ nb,
+                                                       const float* __restrict__ Ja,
+                                                       const float* __restrict__ Jb, float ca,
+                                                       float cb, FGeo g, float nfloor, float te_n0,
+                                                       float n0, float gam, int iso, Aux aux,
+                                                       Status* st, int count_floor) {
+  const int c = blockIdx.x * kBlock + threadIdx.x;
+  const bool live = c < g.ncell;
+  bool below = false;
+  if (live) {
+    const int nc = g.ncell;
+    int i, j, k;
+    fijk(c, g, i, j, k);
+    const Nbr nn = neighbours(c, i, j, k, g);
+    auto dens = [&](int q) { return nb ? ca * na[q] + cb * nb[q] : na[q]; };
+    const float n = dens(c);
+    below = n < nfloor;
+    const float nf = fmaxf(n, nfloor);
+    const float inv = (float)(1.0 / (double)nf);
+    aux.inv[c] = inv;
+    for (int a = 0; a < 3; ++a) {
+      const float J = Jb ? ca * Ja[a * nc + c] + cb * Jb[a * nc + c] : Ja[a * nc + c];
+      aux.u[a * nc + c] = J * inv;
+    }
+    const float pxp = pressure(dens(nn.xp), nfloor, te_n0, n0, gam, iso);
+    const float pxm = pressure(dens(nn.xm), nfloor, te_n0, n0, gam, iso);
+    const float pyp = pressure(dens(nn.yp), nfloor, te_n0, n0, gam, iso);
+    const float pym = pressure(dens(nn.ym), nfloor, te_n0, n0, gam, iso);
+    aux.gp[c] = -(pxp - pxm) * g.idx2 * inv;
+    aux.gp[nc + c] = -(pyp - pym) * g.idy2 * inv;
+    float gz = 0.f;
+    if (NDIM == 3) {
+      const float pzp = pressure(dens(nn.zp), nfloor, te_n0, n0, gam, iso);
+      const float pzm = pressure(dens(nn.zm), nfloor, te_n0, n0, gam, iso);
+      gz = -(pzp - pzm) * g.idz2 * inv;
+    }
+    aux.gp[2 * nc + c] = gz;
+  }
+  if (count_floor) {
+    const uint64_t m = __ballot(live && below);
+    if ((threadIdx.x & 63) == 0 && m) {
+      atomicOr(&st->flags, (uint32_t)HVPIC_FLAG_FLOOR_HIT);
+      atomicAdd(&st->floor_hits, (unsigned long long)__builtin_popcountll(m));
+    }
+  }
+}
+
+// One RK2 stage: Bdst = Bbase - coef * curl(Ohm(Bsrc)).  Bdst may alias Bbase.
+template <int NDIM>
+__global__ __launch_bounds__(kBlock) void k_field_stage(const float* __restrict__ Bsrc,
+                                                        const float* Bbase, float* Bdst, float coef,
+                                                        float eta, FGeo g, Aux aux) {
+  const int c = blockIdx.x * kBlock + threadIdx.x;
+  if (c >= g.ncell) return;
+  const int nc = g.ncell;
+  int i, j, k;
+  fijk(c, g, i, j, k);
+  const Nbr n = neighbours(c, i, j, k, g);
+  float Exp[3], Exm[3], Eyp[3], Eym[3];
+  ohm_at<NDIM>(Bsrc, aux, eta, n.xp, g, Exp);
+  ohm_at<NDIM>(Bsrc, aux, eta, n.xm, g, Exm);
+  ohm_at<NDIM>(Bsrc, aux, eta, n.yp, g, Eyp);
+  ohm_at<NDIM>(Bsrc, aux, eta, n.ym, g, Eym);
+  float cx = (Eyp[2] - Eym[2]) * g.idy2;
+  float cy = -(Exp[2] - Exm[2]) * g.idx2;
+  float cz = (Exp[1] - Exm[1]) * g.idx2 - (Eyp[0] - Eym[0]) * g.idy2;
+  if (NDIM == 3) {
+    float Ezp[3], Ezm[3];
+    ohm_at<NDIM>(Bsrc, aux, eta, n.zp, g, Ezp);
+    ohm_at<NDIM>(Bsrc, aux, eta, n.zm, g, Ezm);
+    cx -= (Ezp[1] - Ezm[1]) * g.idz2;
+    cy += (Ezp[0] - Ezm[0]) * g.idz2;
+  }
+  const float b0 = Bbase[c], b1 = Bbase[nc + c], b2 = Bbase[2 * nc + c];
+  Bdst[c] = b0 - coef * cx;
+  Bdst[nc + c] = b1 - coef * cy;
+  Bdst[2 * nc + c] = b2 - coef * cz;
+}
+
+// E = Ohm(B) written out, plus the FP64 magnetic diagnostics of B.
+template <int NDIM>
+__global__ __launch_bounds__(kBlock) void k_field_ohm_out(const float* __restrict__ B, float eta,
+                                                          FGeo g, Aux aux, float* __restrict__ E,
+                                                          double* diag_out, double* acc,
+                                                          Status* st) {
+  __shared__ double s_red[kBlock / 64][4];
+  __shared__ bool s_last;
+  const int c = blockIdx.x * kBlock + threadIdx.x;
+  const int nc = g.ncell;
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  if (c < nc) {
+    float e[3];
+    ohm_at<NDIM>(B, aux, eta, c, g, e);
+    E[c] = e[0];
+    E[nc + c] = e[1];
+    E[2 * nc + c] = e[2];
+    const double b0 = B[c], b1 = B[nc + c], b2 = B[2 * nc + c];
+    v[0] = b0 * b0 + b1 * b1 + b2 * b2;
+    v[1] = b0;
+    v[2] = b1;
+    v[3] = b2;
+  }
+  if (!diag_out) return;
+  for (int q = 0; q < 4; ++q)
+    for (int o = 32; o > 0; o >>= 1) v[q] += __shfl_xor(v[q], o);
+  const int wid = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0)
+    for (int q = 0; q < 4; ++q) s_red[wid][q] = v[q];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int slot = blockIdx.x % kDiagSlots;
+    for (int q = 0; q < 4; ++q) {
+      double t = 0.0;
+      for (int w = 0; w < kBlock / 64; ++w) t += s_red[w][q];
+      unsafeAtomicAdd(acc + slot * 4 + q, t);
+    }
+    __threadfence();
+    s_last = atomicAdd(&st->done_field, 1u) == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  double t[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int s = threadIdx.x; s < kDiagSlots; s += kBlock)
+    for (int q = 0; q < 4; ++q) {
+      t[q] += __hip_atomic_load(acc + s * 4 + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(acc + s * 4 + q, 0.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  for (int q = 0; q < 4; ++q)
+    for (int o = 32; o > 0; o >>= 1) t[q] += __shfl_xor(t[q], o);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0)
+    for (int q = 0; q < 4; ++q) s_red[wid][q] = t[q];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r[4];
+    for (int q = 0; q < 4; ++q) {
+      r[q] = 0.0;
+      for (int w = 0; w < kBlock / 64; ++w) r[q] += s_red[w][q];
+    }
+    diag_out[0] = r[0];
+    diag_out[1] = r[1] * r[1] + r[2] * r[2] + r[3] * r[3];
+    __hip_atomic_store(&st->done_field, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// Turns {sum |B|^2, |sum B|^2} into {W_B, W_dB}.
+__global__ void k_field_diag_scale(double* d, double half_vol, double inv_ncell) {
+  if (threadIdx.x == 0) {
+    const double s2 = d[0], m2 = d[1];
+    d[0] = half_vol * s2;
+    d[1] = half_vol * (s2 - m2 * inv_ncell);
+  }
+}
+
+// One binomial (1,2,1)/4 pass along `axis` for ncomp component arrays.
+__global__ __launch_bounds__(kBlock) void k_smooth_axis(const float* __restrict__ in,
+                                                        float* __restrict__ out, int ncomp, int axis,
+                                                        FGeo g) {
+  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (t >= (int64_t)ncomp * g.ncell) return;
+  const int comp = (int)(t / g.ncell);
+  const int c = (int)(t - (int64_t)comp * g.ncell);
+  int i, j, k;
+  fijk(c, g, i, j, k);
+  const Nbr n = neighbours(c, i, j, k, g);
+  const int m = axis == 0 ? n.xm : (axis == 1 ? n.ym : n.zm);
+  const int p = axis == 0 ? n.xp : (axis == 1 ? n.yp : n.zp);
+  const float* f = in + (int64_t)comp * g.ncell;
+  out[(int64_t)comp * g.ncell + c] = 0.25f * (f[m] + 2.0f * f[c] + f[p]);
+}
+
+__global__ void k_copy(const float* __restrict__ in, float* __restrict__ out, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) out[i] = in[i];
+}
+
+FGeo fgeo(const hvpic_ctx* c) {
+  FGeo g;
+  g.nx = c->p.nx;
+  g.ny = c->p.ny;
+  g.nz = c->p.nz;
+  g.ncell = c->ncell;
+  g.nxny = c->p.nx * c->p.ny;
+  g.idx2 = (float)(0.5 / c->p.dx);
+  g.idy2 = (float)(0.5 / c->p.dy);
+  g.idz2 = (float)(0.5 / c->p.dz);
+  g.fnx = c->fnx;
+  g.fny = c->fny;
+  return g;
+}
+
+template <int NDIM>
+int field_impl(hvpic_ctx* c, float* B, const float* n_half, const float* J_half,
+               const float* n_prev, const float* J_prev, float* E_out, int mode,
+               double* diag_out) {
+  const FGeo g = fgeo(c);
+  const int nc = c->ncell;
+  const dim3 grid((unsigned)ceil_div(nc, kBlock)), blk(kBlock);
+  hipStream_t s = c->stream;
+  Aux aux;
+  aux.inv = c->fscratch;
+  aux.u = c->fscratch + nc;
+  aux.gp = c->fscratch + 4ll * nc;
+  float* Bs = c->fscratch + 7ll * nc;
+  const float nfloor = (float)c->p.n_floor, n0 = (float)c->p.n0;
+  const float te_n0 = (float)(c->p.te * c->p.n0), gam = (float)c->p.gamma_e;
+  const int iso = c->p.gamma_e == 1.0;
+  const float eta = (float)c->p.eta;
+  // frozen moments for the subcycle (mode 0) or the E-only evaluation (mode 1)
+  hipLaunchKernelGGL((k_field_prep<NDIM>), grid, blk, 0, s, n_half, (const float*)nullptr, J_half,
+                     (const float*)nullptr, 1.0f, 0.0f, g, nfloor, te_n0, n0, gam, iso, aux,
+                     c->status, 1);
+  if (mode == 0) {
+    const float h = (float)(c->p.dt / c->p.nsub);
+    for (int m = 0; m < c->p.nsub; ++m) {
+      hipLaunchKernelGGL((k_field_stage<NDIM>), grid, blk, 0, s, (const float*)B, (const float*)B,
+                         Bs, 0.5f * h, eta, g, aux);
+      hipLaunchKernelGGL((k_field_stage<NDIM>), grid, blk, 0, s, (const float*)Bs, (const float*)B,
+                         B, h, eta, g, aux);
+    }
+    // extrapolated moments for E^{n+1}
+    hipLaunchKernelGGL((k_field_prep<NDIM>), grid, blk, 0, s, n_half, n_prev, J_half, J_prev, 1.5f,
+                       -0.5f, g, nfloor, te_n0, n0, gam, iso, aux, c->status, 0);
+  }
+  hipLaunchKernelGGL((k_field_ohm_out<NDIM>), grid, blk, 0, s, (const float*)B, eta, g, aux, E_out,
+                     diag_out, c->field_acc, c->status);
+  if (diag_out) {
+    const double V = c->p.dx * c->p.dy * c->p.dz;
+    hipLaunchKernelGGL(k_field_diag_scale, dim3(1), dim3(64), 0, s, diag_out, 0.5 * V,
+                       1.0 / (double)nc);
+  }
+  return hipGetLastError() == hipSuccess ? HVPIC_OK : HVPIC_EHIP;
+}
+
+}  // namespace
+
+int launch_field_advance(hvpic_ctx* c, float* B, const float* n_half, const float* J_half,
+                         const float* n_prev, const float* J_prev, float* E_out, int mode,
+                         double* diag_out) {
+  if (c->p.ndim == 2)
+    return field_impl<2>(c, B, n_half, J_half, n_prev, J_prev, E_out, mode, diag_out);
+  return field_impl<3>(c, B, n_half, J_half, n_prev, J_prev, E_out, mode, diag_out);
+}
+
+int launch_smooth(hvpic_ctx* c, float* F, int ncomp, int npasses) {
+  const FGeo g = fgeo(c);
+  const int64_t total = (int64_t)ncomp * c->ncell;
+  if (total == 0 || npasses == 0) return HVPIC_OK;
+  const dim3 grid((unsigned)ceil_div(total, kBlock)), blk(kBlock);
+  float* T = c->fscratch;
+  for (int pass = 0; pass < npasses; ++pass) {
+    hipLaunchKernelGGL(k_smooth_axis, grid, blk, 0, c->stream, (const float*)F, T, ncomp, 0, g);
+    hipLaunchKernelGGL(k_smooth_axis, grid, blk, 0, c->stream, (const float*)T, F, ncomp, 1, g);
+    if (c->p.ndim == 3) {
+      hipLaunchKernelGGL(k_smooth_axis, grid, blk, 0, c->stream, (const float*)F, T, ncomp, 2, g);
+      hipLaunchKernelGGL(k_copy, dim3(1024), blk, 0, c->stream, (const float*)T, F, total);
+    }
+  }
+  return hipGetLastError() == hipSuccess ? HVPIC_OK : HVPIC_EHIP;
+}
+
+}  // namespace hvpic

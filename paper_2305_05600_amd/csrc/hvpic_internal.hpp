@@ -1,0 +1,113 @@
+// Internal declarations of libhvpic.so (gfx950).  Not part of the C-ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hvpic.h"
+
+namespace hvpic {
+
+constexpr int kBlock = 256;      // threads per block for particle kernels
+constexpr int kDiagSlots = 1024; // FP64 reduction slots (spread the atomics)
+
+// Unsigned division by a runtime constant: q = mulhi(n, m) is floor(n/d) or
+// one less, fixed by one compare.  Valid for n < 2^32.
+struct FastDiv {
+  uint32_t d, m;
+};
+
+inline FastDiv make_fastdiv(uint32_t d) {
+  FastDiv f;
+  f.d = d;
+  f.m = d == 1 ? 0xFFFFFFFFu : (uint32_t)((1ull << 32) / d);
+  return f;
+}
+
+__device__ __forceinline__ uint32_t fdiv(uint32_t n, FastDiv f) {
+  uint32_t q = __umulhi(n, f.m);
+  if (n - q * f.d >= f.d) ++q;
+  return q;
+}
+
+// Device-side status block (first bytes of the workspace).
+struct Status {
+  uint32_t flags;
+  uint32_t pad;
+  unsigned long long moved_gt1;
+  unsigned long long nonfinite;
+  unsigned long long floor_hits;
+  unsigned long long bad_input;
+  uint32_t sort_fallback;   // set by the neighbour-move sort when a far mover is seen
+  uint32_t done_push;       // last-block counters of the FP64 reductions
+  uint32_t done_field;
+  uint32_t pad2;
+};
+
+__device__ __forceinline__ void raise_flag(Status* st, uint32_t bit, unsigned long long* counter) {
+  atomicOr(&st->flags, bit);
+  if (counter) atomicAdd(counter, 1ull);
+}
+
+}  // namespace hvpic
+
+// The context (opaque to C callers).
+struct hvpic_ctx {
+  hvpic_params p;
+  hipStream_t stream;
+  char* ws;
+  size_t ws_bytes;
+  int32_t ncell;
+  int32_t magic;
+  uint32_t sort_gen;   // generation tag of the last hvpic_sort call
+  // derived constants (FP32 as the kernels use them)
+  float a;           // (qs/ms) dt / 2
+  float kx, ky, kz;  // 2 dt / (dx, dy, dz): half-cells per unit speed per step
+  float qV;          // qs / V_c
+  hvpic::FastDiv fnx, fny;
+  // workspace carve-out
+  hvpic::Status* status;
+  double* diag_acc;      // [kDiagSlots][4]
+  double* field_acc;     // [kDiagSlots][4]
+  uint32_t* sort_cnt;    // [ncell][3^ndim]
+  int32_t* sort_blk;     // scan block sums
+  uint32_t* rkey[2];     // radix keys   [np_capacity]
+  uint32_t* rval[2];     // radix values [np_capacity]
+  uint32_t* rhist;       // radix per-block digit counts
+  float* fscratch;       // field scratch [16][ncell]
+};
+
+namespace hvpic {
+
+constexpr int32_t kMagic = 0x68767063;
+
+// Launch wrappers, one per kernel family (implemented next to the kernels).
+int launch_gather_push(hvpic_ctx* c, hvpic_particles* p, const float* E, const float* B,
+                       float* n_mid, float* J_mid, double* diag_out);
+int launch_deposit(hvpic_ctx* c, const hvpic_particles* p, float half_dt_back, float* n,
+                   float* J);
+int launch_sort(hvpic_ctx* c, const hvpic_particles* in, hvpic_particles* out,
+                const int32_t* cs_prev, int32_t* cs, int full);
+int launch_field_advance(hvpic_ctx* c, float* B, const float* n_half, const float* J_half,
+                         const float* n_prev, const float* J_prev, float* E_out, int mode,
+                         double* diag_out);
+int launch_smooth(hvpic_ctx* c, float* F, int ncomp, int npasses);
+int launch_zero(hvpic_ctx* c, float* p, int64_t count);
+int launch_init_workspace(hvpic_ctx* c);
+
+// Workspace layout (bytes from the start; each region 256-byte aligned).
+struct Layout {
+  size_t status, diag_acc, field_acc, sort_cnt, sort_blk, rkey0, rkey1, rval0, rval1, rhist,
+      fscratch, total;
+};
+Layout workspace_layout(const hvpic_params* p);
+
+constexpr int kRadixBits = 8;
+constexpr int kRadixBins = 1 << kRadixBits;
+constexpr int kRadixItems = 8;  // keys per thread per radix tile
+constexpr int kRadixTile = kBlock * kRadixItems;
+constexpr int kScanTile = 2048;  // elements per block of the prefix scans
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+}  // namespace hvpic

@@ -1,0 +1,706 @@
+// Particle kernels of libhvpic.so for gfx950: gather + Boris push + move
+// (optionally with the moment deposit fused in) and the stand-alone deposit.
+//
+// Method (arXiv 2305.05600):
+//   gather   App. B eq:quadFI/eq:quadF (QS) -- evaluated here in the equivalent
+//            weight form: F(x_p) = sum_c W_c(dx,dy,dz) F_c with the eq:quad
+//            weights, which the paper's consistency (no self-force) statement
+//            makes identical to the interpolant form; Sec. II.B for NGP.
+//   push     Sec. II.B eq:vadv, non-relativistic Boris split.
+//   move     Sec. II.B position update; offsets renormalised into [-1,1).
+//   deposit  Sec. II.B eq:ngp, App. B eq:quad, at x^{n+1/2}.
+//
+// Data path.  Particles are structure-of-arrays; a block owns one contiguous
+// chunk of kChunk particles and each lane handles every kBlock-th particle of
+// it, so every global load/store of the store is fully coalesced.  E and B are
+// read through the L1/L2 caches (the grid is small and the chunk's particles
+// share a handful of cells).  The deposit accumulates into an LDS window that
+// covers the chunk's cell range in "bands": the window holds, for each band
+// offset (by[, bz]) in -3..3, the linear cells [c0 + by*nx (+ bz*nx*ny) - 2,
+// c1 + ... + 2] (modulo ncell), which contains every cell a QS stencil at the
+// mid-point can touch -- x-wraps shift the band by one row, y-wraps (3D) by one
+// plane.  Within a wavefront, lanes whose mid-point cell coincides (the store
+// is cell-sorted, so most do) are summed with DPP row reductions before the LDS
+// atomics, which removes the 64-way same-address serialisation.  Each block
+// flushes its window with one global atomic per non-zero entry.
+#include "hvpic_internal.hpp"
+
+namespace hvpic {
+namespace {
+
+constexpr int kPPT = 8;                   // particles per thread per chunk
+constexpr int kChunk = kBlock * kPPT;     // particles per block
+constexpr int kBands = 7;                 // band offsets -3..3
+constexpr int kWmax2 = 160;               // widest window (cells per band), 2D
+constexpr int kWmax3 = 40;                // 3D
+constexpr int kWin2 = kBands * kWmax2 * 4;
+constexpr int kWin3 = kBands * kBands * kWmax3 * 4;
+constexpr int kGroupMin = 6;              // smallest lane group worth a reduction
+
+struct Geo {
+  int nx, ny, nz, ncell, nxny;
+  FastDiv fnx, fny;
+};
+
+struct PushArgs {
+  int64_t n;
+  int32_t* __restrict__ cell;
+  float* __restrict__ ox;
+  float* __restrict__ oy;
+  float* __restrict__ oz;
+  float* __restrict__ ux;
+  float* __restrict__ uy;
+  float* __restrict__ uz;
+  const float* __restrict__ w;
+  const float* __restrict__ E;
+  const float* __restrict__ B;
+  float* __restrict__ dn;   // fused deposit: n at x^{n+1/2}
+  float* __restrict__ dJ;   // fused deposit: J at x^{n+1/2}
+  Geo g;
+  float a;                  // (q/m) dt / 2
+  float kx, ky, kz;         // full-step displacement per unit speed (half-cells)
+  float qV;                 // q / V_c
+  double ms;
+  double* diag_out;
+  double* diag_acc;
+  Status* st;
+};
+
+struct DepArgs {
+  int64_t n;
+  const int32_t* __restrict__ cell;
+  const float* __restrict__ ox;
+  const float* __restrict__ oy;
+  const float* __restrict__ oz;
+  const float* __restrict__ ux;
+  const float* __restrict__ uy;
+  const float* __restrict__ uz;
+  const float* __restrict__ w;
+  float* __restrict__ dn;
+  float* __restrict__ dJ;
+  Geo g;
+  float bx, by, bz;         // displacement of the deposit point per unit speed
+  float qV;
+  Status* st;
+};
+
+__device__ __forceinline__ void decompose(int a, const Geo& g, int& i, int& j, int& k) {
+  uint32_t q = fdiv((uint32_t)a, g.fnx);
+  i = a - (int)q * g.nx;
+  uint32_t q2 = fdiv(q, g.fny);
+  j = (int)q - (int)q2 * g.ny;
+  k = (int)q2;
+}
+
+__device__ __forceinline__ int wrapi(int i, int n) {
+  int r = i % n;
+  return r < 0 ? r + n : r;
+}
+
+// Shift s with x - 2s in [-1,1).  Exact compares for the common |s| <= 1 case
+// (x - 2 is exact for x in [1,3) by Sterbenz); general floor beyond.  Returns
+// false for a non-finite / runaway value (the caller keeps the particle).
+__device__ __forceinline__ bool renorm(float& x, int& s) {
+  if (!(fabsf(x) < 1.0e6f)) return false;
+  s = 0;
+  if (x >= 1.0f) {
+    s = 1;
+    if (x >= 3.0f) s = (int)floorf((x + 1.0f) * 0.5f);
+  } else if (x < -1.0f) {
+    s = -1;
+    if (x < -3.0f) s = (int)floorf((x + 1.0f) * 0.5f);
+  }
+  x -= 2.0f * (float)s;
+  while (x >= 1.0f) { x -= 2.0f; ++s; }
+  while (x < -1.0f) { x += 2.0f; --s; }
+  return true;
+}
+
+// ---------------------------------------------------------------- gather --
+
+template <int NDIM, int SHAPE>
+__device__ __forceinline__ void gather_eb(const float* __restrict__ E, const float* __restrict__ B,
+                                          int a, int i, int j, int k, float x, float y, float z,
+                                          const Geo& g, float Ep[3], float Bp[3]) {
+  const int nc = g.ncell;
+  if (SHAPE == HVPIC_SHAPE_NGP) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      Ep[c] = __ldg(E + c * nc + a);
+      Bp[c] = __ldg(B + c * nc + a);
+    }
+    return;
+  }
+  const int im = i == 0 ? a + g.nx - 1 : a - 1;
+  const int ip = i == g.nx - 1 ? a - g.nx + 1 : a + 1;
+  const int jm = j == 0 ? a + g.nxny - g.nx : a - g.nx;
+  const int jp = j == g.ny - 1 ? a - g.nxny + g.nx : a + g.nx;
+  const float c6 = 1.0f / 6.0f, c12 = 1.0f / 12.0f;
+  const float xp = 1.0f + x, xm = 1.0f - x, yp = 1.0f + y, ym = 1.0f - y;
+  const float wxp = xp * xp * c12, wxm = xm * xm * c12, wyp = yp * yp * c12, wym = ym * ym * c12;
+  if (NDIM == 2) {
+    const float w0 = (4.0f - x * x - y * y) * c6;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const float* e = E + c * nc;
+      const float* b = B + c * nc;
+      Ep[c] = w0 * __ldg(e + a) + wxp * __ldg(e + ip) + wxm * __ldg(e + im) + wyp * __ldg(e + jp) +
+              wym * __ldg(e + jm);
+      Bp[c] = w0 * __ldg(b + a) + wxp * __ldg(b + ip) + wxm * __ldg(b + im) + wyp * __ldg(b + jp) +
+              wym * __ldg(b + jm);
+    }
+  } else {
+    const int km = k == 0 ? a + nc - g.nxny : a - g.nxny;
+    const int kp = k == g.nz - 1 ? a - nc + g.nxny : a + g.nxny;
+    const float zp = 1.0f + z, zm = 1.0f - z;
+    const float wzp = zp * zp * c12, wzm = zm * zm * c12;
+    const float w0 = (3.0f - x * x - y * y - z * z) * c6;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const float* e = E + c * nc;
+      const float* b = B + c * nc;
+      Ep[c] = w0 * __ldg(e + a) + wxp * __ldg(e + ip) + wxm * __ldg(e + im) + wyp * __ldg(e + jp) +
+              wym * __ldg(e + jm) + wzp * __ldg(e + kp) + wzm * __ldg(e + km);
+      Bp[c] = w0 * __ldg(b + a) + wxp * __ldg(b + ip) + wxm * __ldg(b + im) + wyp * __ldg(b + jp) +
+              wym * __ldg(b + jm) + wzp * __ldg(b + kp) + wzm * __ldg(b + km);
+    }
+  }
+}
+
+// ---------------------------------------------------------------- deposit --
+
+template <int NDIM, int SHAPE>
+struct Stencil {
+  static constexpr int T = SHAPE == HVPIC_SHAPE_NGP ? 1 : (NDIM == 2 ? 5 : 7);
+};
+
+// Offsets (relative to the mid-point cell) and weights of the stencil cells.
+template <int NDIM, int SHAPE>
+__device__ __forceinline__ void stencil_weights(float x, float y, float z, float* wt, int* sx,
+                                                int* sy, int* sz) {
+  if (SHAPE == HVPIC_SHAPE_NGP) {
+    wt[0] = 1.0f;
+    sx[0] = sy[0] = sz[0] = 0;
+    return;
+  }
+  const float c6 = 1.0f / 6.0f, c12 = 1.0f / 12.0f;
+  const float xp = 1.0f + x, xm = 1.0f - x, yp = 1.0f + y, ym = 1.0f - y;
+  wt[0] = (NDIM == 2 ? (4.0f - x * x - y * y) : (3.0f - x * x - y * y - z * z)) * c6;
+  wt[1] = xp * xp * c12;
+  wt[2] = xm * xm * c12;
+  wt[3] = yp * yp * c12;
+  wt[4] = ym * ym * c12;
+  sx[0] = 0; sy[0] = 0; sz[0] = 0;
+  sx[1] = 1; sy[1] = 0; sz[1] = 0;
+  sx[2] = -1; sy[2] = 0; sz[2] = 0;
+  sx[3] = 0; sy[3] = 1; sz[3] = 0;
+  sx[4] = 0; sy[4] = -1; sz[4] = 0;
+  if (NDIM == 3) {
+    const float zp = 1.0f + z, zm = 1.0f - z;
+    wt[5] = zp * zp * c12;
+    wt[6] = zm * zm * c12;
+    sx[5] = 0; sy[5] = 0; sz[5] = 1;
+    sx[6] = 0; sy[6] = 0; sz[6] = -1;
+  }
+}
+
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+  return __builtin_bit_cast(
+      float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+
+// Sum over the 16 lanes of each DPP row; every lane of the row gets the sum.
+__device__ __forceinline__ float row_sum(float v) {
+  v += dpp<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp<0x141>(v);  // row_half_mirror
+  v += dpp<0x140>(v);  // row_mirror
+  return v;
+}
+
+// Deposits one particle per lane.  Must be called by every lane of the wave
+// (uniform control flow): `live` lanes carry a particle, `inwin` lanes use the
+// LDS window, the other live lanes add straight to global memory.
+template <int NDIM, int SHAPE>
+__device__ __forceinline__ void deposit_lane(bool live, bool inwin, int rel, int i, int j, int k,
+                                             int mx, int my, int mz, float x, float y, float z,
+                                             float q, float vx, float vy, float vz, float* win,
+                                             int W, const Geo& g, float* __restrict__ dn,
+                                             float* __restrict__ dJ) {
+  constexpr int T = Stencil<NDIM, SHAPE>::T;
+  float wt[T];
+  int sx[T], sy[T], sz[T];
+  stencil_weights<NDIM, SHAPE>(x, y, z, wt, sx, sy, sz);
+  int slot[T];
+#pragma unroll
+  for (int t = 0; t < T; ++t) {
+    const int dxt = mx + sx[t], dyt = my + sy[t], dzt = mz + sz[t];
+    const int it = i + dxt;
+    const int wx = it < 0 ? 1 : (it >= g.nx ? -1 : 0);
+    int band = dyt + wx + 3;
+    if (NDIM == 3) {
+      const int jt = j + dyt;
+      const int wy = jt < 0 ? 1 : (jt >= g.ny ? -1 : 0);
+      band += kBands * (dzt + wy + 3);
+    }
+    slot[t] = (band * W + rel + dxt + 2) * 4;
+  }
+  const int lane = threadIdx.x & 63;
+  const int key = (live && inwin) ? slot[0] : -1;
+  uint64_t pend = __ballot(key >= 0);
+#pragma unroll 1
+  for (int grp = 0; grp < 2 && pend != 0; ++grp) {
+    const int leader = __builtin_ctzll(pend);
+    const int lkey = __builtin_amdgcn_readlane(key, leader);
+    const uint64_t members = __ballot(key == lkey) & pend;
+    if (__builtin_popcountll(members) < kGroupMin) break;
+    const bool in = (members >> lane) & 1ull;
+    const uint32_t rowbits = (uint32_t)(members >> (lane & 48)) & 0xFFFFu;
+    const bool adder = in && (lane & 15) == __builtin_ctz(rowbits | 0x10000u);
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      const float nq = in ? q * wt[t] : 0.0f;
+      const float s0 = row_sum(nq);
+      const float s1 = row_sum(nq * vx);
+      const float s2 = row_sum(nq * vy);
+      const float s3 = row_sum(nq * vz);
+      if (adder) {
+        atomicAdd(win + slot[t] + 0, s0);
+        atomicAdd(win + slot[t] + 1, s1);
+        atomicAdd(win + slot[t] + 2, s2);
+        atomicAdd(win + slot[t] + 3, s3);
+      }
+    }
+    pend &= ~members;
+  }
+  if ((pend >> lane) & 1ull) {
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      const float nq = q * wt[t];
+      atomicAdd(win + slot[t] + 0, nq);
+      atomicAdd(win + slot[t] + 1, nq * vx);
+      atomicAdd(win + slot[t] + 2, nq * vy);
+      atomicAdd(win + slot[t] + 3, nq * vz);
+    }
+  }
+  if (live && !inwin) {
+    const int nc = g.ncell;
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      const int c = wrapi(i + mx + sx[t], g.nx) +
+                    g.nx * (wrapi(j + my + sy[t], g.ny) + g.ny * wrapi(k + mz + sz[t], g.nz));
+      const float nq = q * wt[t];
+      unsafeAtomicAdd(dn + c, nq);
+      unsafeAtomicAdd(dJ + c, nq * vx);
+      unsafeAtomicAdd(dJ + nc + c, nq * vy);
+      unsafeAtomicAdd(dJ + 2 * nc + c, nq * vz);
+    }
+  }
+}
+
+// Window geometry for a chunk whose first and last particles sit in c0, c1.
+template <int NDIM>
+__device__ __forceinline__ bool window_ok(int c0, int c1, const Geo& g, int& W) {
+  W = c1 - c0 + 5;
+  const int wmax = NDIM == 2 ? kWmax2 : kWmax3;
+  return c0 >= 0 && c1 < g.ncell && c1 >= c0 && W <= wmax && g.nx >= 4 &&
+         (NDIM == 2 || g.ny >= 4);
+}
+
+template <int NDIM>
+__device__ __forceinline__ int window_len(int W) {
+  return (NDIM == 2 ? kBands : kBands * kBands) * W * 4;
+}
+
+template <int NDIM>
+__device__ void window_flush(const float* win, int W, int c0, const Geo& g, float* __restrict__ dn,
+                             float* __restrict__ dJ) {
+  const int len = window_len<NDIM>(W);
+  for (int s = threadIdx.x; s < len; s += kBlock) {
+    const float v = win[s];
+    if (v == 0.0f) continue;
+    const int ch = s & 3;
+    const int cellslot = s >> 2;
+    const int band = cellslot / W;
+    const int off = cellslot - band * W;
+    const int by = band % kBands - 3;
+    const int bz = band / kBands - 3;
+    int64_t c = (int64_t)c0 - 2 + off + (int64_t)by * g.nx + (int64_t)bz * g.nxny;
+    c %= g.ncell;
+    if (c < 0) c += g.ncell;
+    float* dst = ch == 0 ? dn + c : dJ + (int64_t)(ch - 1) * g.ncell + c;
+    unsafeAtomicAdd(dst, v);
+  }
+}
+
+// FP64 block reduction of NV partial sums and the last-block finalisation.
+template <int NV>
+__device__ void reduce_finalize(double* v, double* acc, uint32_t* done, double* out) {
+  __shared__ double s_red[kBlock / 64][NV];
+  __shared__ bool s_last;
+#pragma unroll
+  for (int k = 0; k < NV; ++k)
+    for (int o = 32; o > 0; o >>= 1) v[k] += __shfl_xor(v[k], o);
+  const int wid = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0)
+    for (int k = 0; k < NV; ++k) s_red[wid][k] = v[k];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int slot = blockIdx.x % kDiagSlots;
+    for (int k = 0; k < NV; ++k) {
+      double t = 0.0;
+      for (int w = 0; w < kBlock / 64; ++w) t += s_red[w][k];
+      unsafeAtomicAdd(acc + slot * 4 + k, t);
+    }
+    __threadfence();
+    const uint32_t prev = atomicAdd(done, 1u);
+    s_last = prev == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  double t[NV];
+  for (int k = 0; k < NV; ++k) t[k] = 0.0;
+  for (int s = threadIdx.x; s < kDiagSlots; s += kBlock)
+    for (int k = 0; k < NV; ++k) {
+      t[k] += __hip_atomic_load(acc + s * 4 + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(acc + s * 4 + k, 0.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  __syncthreads();
+  for (int k = 0; k < NV; ++k)
+    for (int o = 32; o > 0; o >>= 1) t[k] += __shfl_xor(t[k], o);
+  if ((threadIdx.x & 63) == 0)
+    for (int k = 0; k < NV; ++k) s_red[wid][k] = t[k];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < NV; ++k) {
+      double r = 0.0;
+      for (int w = 0; w < kBlock / 64; ++w) r += s_red[w][k];
+      out[k] = r;
+    }
+    __hip_atomic_store(done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// ---------------------------------------------------------------- kernels --
+
+template <int NDIM, int SHAPE, bool DEP>
+__global__ __launch_bounds__(kBlock) void k_gather_push(PushArgs A) {
+  __shared__ float win[DEP ? (NDIM == 2 ? kWin2 : kWin3) : 1];
+  __shared__ int s_c[2];
+  const Geo& g = A.g;
+  const int64_t base = (int64_t)blockIdx.x * kChunk;
+  const int64_t end = min(base + (int64_t)kChunk, A.n);
+
+  int W = 0, c0 = 0;
+  bool wok = false;
+  if (DEP) {
+    if (threadIdx.x == 0) {
+      s_c[0] = A.cell[base];
+      s_c[1] = A.cell[end - 1];
+    }
+    __syncthreads();
+    c0 = s_c[0];
+    wok = window_ok<NDIM>(c0, s_c[1], g, W);
+    if (wok)
+      for (int s = threadIdx.x; s < window_len<NDIM>(W); s += kBlock) win[s] = 0.0f;
+    __syncthreads();
+  }
+
+  const bool want_diag = A.diag_out != nullptr;
+  double dK = 0.0, dP[3] = {0.0, 0.0, 0.0};
+  for (int it = 0; it < kPPT; ++it) {
+    const int64_t idx = base + (int64_t)it * kBlock + threadIdx.x;
+    bool live = idx < end;
+    int a = 0;
+    float x = 0.f, y = 0.f, z = 0.f, vx = 0.f, vy = 0.f, vz = 0.f, wq = 0.f;
+    if (live) {
+      a = A.cell[idx];
+      x = A.ox[idx];
+      y = A.oy[idx];
+      if (NDIM == 3) z = A.oz[idx];
+      vx = A.ux[idx];
+      vy = A.uy[idx];
+      vz = A.uz[idx];
+      if (DEP || want_diag) wq = A.w[idx];
+      if ((unsigned)a >= (unsigned)g.ncell) {
+        raise_flag(A.st, HVPIC_FLAG_BAD_INPUT, &A.st->bad_input);
+        live = false;
+      }
+    }
+    int i = 0, j = 0, k = 0, mx = 0, my = 0, mz = 0;
+    float xm = 0.f, ym = 0.f, zm = 0.f;
+    if (live) {
+      decompose(a, g, i, j, k);
+      float Ep[3], Bp[3];
+      gather_eb<NDIM, SHAPE>(A.E, A.B, a, i, j, k, x, y, z, g, Ep, Bp);
+      // Boris: half kick, rotation, half kick.
+      const float h = A.a;
+      const float vmx = fmaf(h, Ep[0], vx), vmy = fmaf(h, Ep[1], vy), vmz = fmaf(h, Ep[2], vz);
+      const float tx = h * Bp[0], ty = h * Bp[1], tz = h * Bp[2];
+      const float f = 2.0f / (1.0f + (tx * tx + ty * ty + tz * tz));
+      const float sx = f * tx, sy = f * ty, sz = f * tz;
+      const float px = vmx + (vmy * tz - vmz * ty);
+      const float py = vmy + (vmz * tx - vmx * tz);
+      const float pz = vmz + (vmx * ty - vmy * tx);
+      const float nvx = fmaf(h, Ep[0], vmx + (py * sz - pz * sy));
+      const float nvy = fmaf(h, Ep[1], vmy + (pz * sx - px * sz));
+      const float nvz = fmaf(h, Ep[2], vmz + (px * sy - py * sx));
+      if (want_diag) {
+        const double mw = A.ms * (double)wq;
+        dK += 0.5 * mw *
+              ((double)vx * nvx + (double)vy * nvy + (double)vz * nvz);
+        dP[0] += 0.5 * mw * ((double)vx + nvx);
+        dP[1] += 0.5 * mw * ((double)vy + nvy);
+        dP[2] += 0.5 * mw * ((double)vz + nvz);
+      }
+      // Move: x^{n+1} = x^n + v^{n+1/2} dt, renormalised offsets.
+      float nx_ = fmaf(nvx, A.kx, x), ny_ = fmaf(nvy, A.ky, y), nz_ = z;
+      int si = 0, sj = 0, sk = 0;
+      bool ok = renorm(nx_, si) && renorm(ny_, sj);
+      if (NDIM == 3) {
+        nz_ = fmaf(nvz, A.kz, z);
+        ok = ok && renorm(nz_, sk);
+      }
+      if (!ok) {
+        raise_flag(A.st, HVPIC_FLAG_NONFINITE, &A.st->nonfinite);
+        si = sj = sk = 0;
+        nx_ = x;
+        ny_ = y;
+        nz_ = z;
+      } else if (si > 1 || si < -1 || sj > 1 || sj < -1 || sk > 1 || sk < -1) {
+        raise_flag(A.st, HVPIC_FLAG_MOVE_GT1, &A.st->moved_gt1);
+      }
+      int ni = i + si, nj = j + sj, nk = k + sk;
+      if ((unsigned)ni >= (unsigned)g.nx) ni = wrapi(ni, g.nx);
+      if ((unsigned)nj >= (unsigned)g.ny) nj = wrapi(nj, g.ny);
+      if (NDIM == 3 && (unsigned)nk >= (unsigned)g.nz) nk = wrapi(nk, g.nz);
+      A.cell[idx] = ni + g.nx * (nj + g.ny * nk);
+      A.ox[idx] = nx_;
+      A.oy[idx] = ny_;
+      if (NDIM == 3) A.oz[idx] = nz_;
+      A.ux[idx] = nvx;
+      A.uy[idx] = nvy;
+      A.uz[idx] = nvz;
+      if (DEP) {
+        // Mid-point x^{n+1/2} = x^n + (dt/2) v^{n+1/2}.
+        xm = fmaf(nvx, 0.5f * A.kx, x);
+        ym = fmaf(nvy, 0.5f * A.ky, y);
+        zm = NDIM == 3 ? fmaf(nvz, 0.5f * A.kz, z) : 0.0f;
+        if (!ok || !renorm(xm, mx) || !renorm(ym, my) || (NDIM == 3 && !renorm(zm, mz))) {
+          xm = x; ym = y; zm = z; mx = my = mz = 0;
+        }
+        vx = nvx;
+        vy = nvy;
+        vz = nvz;
+      }
+    }
+    if (DEP) {
+      const int rel = a - c0;
+      const bool inwin = wok && rel >= 0 && rel + 5 <= W && mx >= -1 && mx <= 1 && my >= -1 &&
+                         my <= 1 && mz >= -1 && mz <= 1;
+      deposit_lane<NDIM, SHAPE>(live, inwin, rel, i, j, k, mx, my, mz, xm, ym, zm, A.qV * wq, vx,
+                                vy, vz, win, W, g, A.dn, A.dJ);
+    }
+  }
+  if (want_diag) {
+    double v[4] = {dK, dP[0], dP[1], dP[2]};
+    reduce_finalize<4>(v, A.diag_acc, &A.st->done_push, A.diag_out);
+  }
+  if (DEP && wok) {
+    __syncthreads();
+    window_flush<NDIM>(win, W, c0, g, A.dn, A.dJ);
+  }
+}
+
+template <int NDIM, int SHAPE>
+__global__ __launch_bounds__(kBlock) void k_deposit(DepArgs A) {
+  __shared__ float win[NDIM == 2 ? kWin2 : kWin3];
+  __shared__ int s_c[2];
+  const Geo& g = A.g;
+  const int64_t base = (int64_t)blockIdx.x * kChunk;
+  const int64_t end = min(base + (int64_t)kChunk, A.n);
+  if (threadIdx.x == 0) {
+    s_c[0] = A.cell[base];
+    s_c[1] = A.cell[end - 1];
+  }
+  __syncthreads();
+  const int c0 = s_c[0];
+  int W = 0;
+  const bool wok = window_ok<NDIM>(c0, s_c[1], g, W);
+  if (wok)
+    for (int s = threadIdx.x; s < window_len<NDIM>(W); s += kBlock) win[s] = 0.0f;
+  __syncthreads();
+  for (int it = 0; it < kPPT; ++it) {
+    const int64_t idx = base + (int64_t)it * kBlock + threadIdx.x;
+    bool live = idx < end;
+    int a = 0, i = 0, j = 0, k = 0, mx = 0, my = 0, mz = 0;
+    float x = 0.f, y = 0.f, z = 0.f, vx = 0.f, vy = 0.f, vz = 0.f, q = 0.f;
+    if (live) {
+      a = A.cell[idx];
+      x = A.ox[idx];
+      y = A.oy[idx];
+      if (NDIM == 3) z = A.oz[idx];
+      vx = A.ux[idx];
+      vy = A.uy[idx];
+      vz = A.uz[idx];
+      q = A.qV * A.w[idx];
+      if ((unsigned)a >= (unsigned)g.ncell) {
+        raise_flag(A.st, HVPIC_FLAG_BAD_INPUT, &A.st->bad_input);
+        live = false;
+        a = 0;
+      }
+    }
+    if (live) {
+      decompose(a, g, i, j, k);
+      float xm = fmaf(vx, A.bx, x), ym = fmaf(vy, A.by, y), zm = NDIM == 3 ? fmaf(vz, A.bz, z) : 0.f;
+      if (renorm(xm, mx) && renorm(ym, my) && (NDIM == 2 || renorm(zm, mz))) {
+        x = xm;
+        y = ym;
+        z = zm;
+      } else {
+        mx = my = mz = 0;
+      }
+    }
+    const int rel = a - c0;
+    const bool inwin = wok && rel >= 0 && rel + 5 <= W && mx >= -1 && mx <= 1 && my >= -1 &&
+                       my <= 1 && mz >= -1 && mz <= 1;
+    deposit_lane<NDIM, SHAPE>(live, inwin, rel, i, j, k, mx, my, mz, x, y, z, q, vx, vy, vz, win,
+                              W, g, A.dn, A.dJ);
+  }
+  if (wok) {
+    __syncthreads();
+    window_flush<NDIM>(win, W, c0, g, A.dn, A.dJ);
+  }
+}
+
+__global__ void k_zero(float* __restrict__ a, int64_t na, float* __restrict__ b, int64_t nb) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < na + nb; i += stride) {
+    if (i < na)
+      a[i] = 0.0f;
+    else
+      b[i - na] = 0.0f;
+  }
+}
+
+__global__ void k_write_zero_diag(double* out, int nv) {
+  if (threadIdx.x < nv) out[threadIdx.x] = 0.0;
+}
+
+Geo make_geo(const hvpic_ctx* c) {
+  Geo g;
+  g.nx = c->p.nx;
+  g.ny = c->p.ny;
+  g.nz = c->p.nz;
+  g.ncell = c->ncell;
+  g.nxny = c->p.nx * c->p.ny;
+  g.fnx = c->fnx;
+  g.fny = c->fny;
+  return g;
+}
+
+template <int NDIM, int SHAPE>
+void push_dispatch(bool dep, dim3 grid, hipStream_t s, const PushArgs& A) {
+  if (dep)
+    hipLaunchKernelGGL((k_gather_push<NDIM, SHAPE, true>), grid, dim3(kBlock), 0, s, A);
+  else
+    hipLaunchKernelGGL((k_gather_push<NDIM, SHAPE, false>), grid, dim3(kBlock), 0, s, A);
+}
+
+int zero2(hvpic_ctx* c, float* a, int64_t na, float* b, int64_t nb) {
+  const int64_t total = na + nb;
+  if (total <= 0) return HVPIC_OK;
+  const int blocks = (int)std::min<int64_t>(ceil_div(total, kBlock), 4096);
+  hipLaunchKernelGGL(k_zero, dim3(blocks), dim3(kBlock), 0, c->stream, a, na, b, nb);
+  return hipGetLastError() == hipSuccess ? HVPIC_OK : HVPIC_EHIP;
+}
+
+}  // namespace
+
+int launch_zero(hvpic_ctx* c, float* p, int64_t count) { return zero2(c, p, count, nullptr, 0); }
+
+int launch_gather_push(hvpic_ctx* c, hvpic_particles* p, const float* E, const float* B,
+                       float* n_mid, float* J_mid, double* diag_out) {
+  const bool dep = n_mid != nullptr && J_mid != nullptr;
+  if (dep) {
+    int rc = zero2(c, n_mid, c->ncell, J_mid, 3ll * c->ncell);
+    if (rc) return rc;
+  }
+  if (p->n == 0) {
+    if (diag_out) hipLaunchKernelGGL(k_write_zero_diag, dim3(1), dim3(64), 0, c->stream, diag_out, 4);
+    return hipGetLastError() == hipSuccess ? HVPIC_OK : HVPIC_EHIP;
+  }
+  PushArgs A;
+  A.n = p->n;
+  A.cell = p->cell;
+  A.ox = p->ox;
+  A.oy = p->oy;
+  A.oz = p->oz;
+  A.ux = p->ux;
+  A.uy = p->uy;
+  A.uz = p->uz;
+  A.w = p->w;
+  A.E = E;
+  A.B = B;
+  A.dn = n_mid;
+  A.dJ = J_mid;
+  A.g = make_geo(c);
+  A.a = c->a;
+  A.kx = c->kx;
+  A.ky = c->ky;
+  A.kz = c->kz;
+  A.qV = c->qV;
+  A.ms = c->p.ms;
+  A.diag_out = diag_out;
+  A.diag_acc = c->diag_acc;
+  A.st = c->status;
+  const dim3 grid((unsigned)ceil_div(p->n, kChunk));
+  const bool qs = c->p.shape == HVPIC_SHAPE_QS;
+  if (c->p.ndim == 2) {
+    if (qs) push_dispatch<2, HVPIC_SHAPE_QS>(dep, grid, c->stream, A);
+    else push_dispatch<2, HVPIC_SHAPE_NGP>(dep, grid, c->stream, A);
+  } else {
+    if (qs) push_dispatch<3, HVPIC_SHAPE_QS>(dep, grid, c->stream, A);
+    else push_dispatch<3, HVPIC_SHAPE_NGP>(dep, grid, c->stream, A);
+  }
+  return hipGetLastError() == hipSuccess ? HVPIC_OK : HVPIC_EHIP;
+}
+
+int launch_deposit(hvpic_ctx* c, const hvpic_particles* p, float half_dt_back, float* n,
+                   float* J) {
+  int rc = zero2(c, n, c->ncell, J, 3ll * c->ncell);
+  if (rc || p->n == 0) return rc;
+  DepArgs A;
+  A.n = p->n;
+  A.cell = p->cell;
+  A.ox = p->ox;
+  A.oy = p->oy;
+  A.oz = p->oz;
+  A.ux = p->ux;
+  A.uy = p->uy;
+  A.uz = p->uz;
+  A.w = p->w;
+  A.dn = n;
+  A.dJ = J;
+  A.g = make_geo(c);
+  // x - half_dt_back v in half-cell units: offset change -2 half_dt_back v / h.
+  A.bx = (float)(-2.0 * (double)half_dt_back / c->p.dx);
+  A.by = (float)(-2.0 * (double)half_dt_back / c->p.dy);
+  A.bz = (float)(-2.0 * (double)half_dt_back / c->p.dz);
+  A.qV = c->qV;
+  A.st = c->status;
+  const dim3 grid((unsigned)ceil_div(p->n, kChunk));
+  const bool qs = c->p.shape == HVPIC_SHAPE_QS;
+  if (c->p.ndim == 2) {
+    if (qs) hipLaunchKernelGGL((k_deposit<2, HVPIC_SHAPE_QS>), grid, dim3(kBlock), 0, c->stream, A);
+    else hipLaunchKernelGGL((k_deposit<2, HVPIC_SHAPE_NGP>), grid, dim3(kBlock), 0, c->stream, A);
+  } else {
+    if (qs) hipLaunchKernelGGL((k_deposit<3, HVPIC_SHAPE_QS>), grid, dim3(kBlock), 0, c->stream, A);
+    else hipLaunchKernelGGL((k_deposit<3, HVPIC_SHAPE_NGP>), grid, dim3(kBlock), 0, c->stream, A);
+  }
+  return hipGetLastError() == hipSuccess ? HVPIC_OK : HVPIC_EHIP;
+}
+
+}  // namespace hvpic

@@ -1,0 +1,616 @@
+// Stable counting sort of the particle store by cell index (gfx950).
+//
+// The paper keeps each particle as a cell index plus in-cell offsets (Sec.
+// II.B); keeping the store ordered by cell is what makes the deposit's LDS
+// windows and the gather's cache reuse work.  The result is the one stable
+// order: by cell, equal cells in input order, plus cell_start[ncell+1].
+//
+// Neighbour-move path.  The input was sorted by the cells the particles held
+// before the last push, and a push moves a particle by at most one cell per
+// axis.  For an old cell a and a move direction d (3^ndim of them) let
+// cnt[a][d] be the number of its particles that moved by d.  The particles
+// landing in a new cell c come from the 3^ndim cells c - d; in the stable
+// order they appear grouped by old cell index (the input order), and inside a
+// group in input order.  So with cell_start[c] from the prefix sum of the
+// per-new-cell totals, the first slot of group (a, d) is cell_start[c] plus the
+// counts of the groups of c whose old cell index is smaller, and a particle's
+// slot adds its rank among the earlier particles of its own group, found with
+// wavefront ballots.  Kernels: count (one wavefront per old cell), tile totals
+// of the new counts, scan of tile totals, per-cell prefix + group bases,
+// scatter (one wavefront per old cell).  A particle that moved further is
+// detected by the count kernel; the general sort then runs instead (its
+// kernels are always enqueued and return at once unless that happened).
+//
+// General path.  LSD radix sort of (cell, index) pairs with 8-bit digits;
+// each pass is a per-tile digit histogram, a scan of the digit-major
+// histogram, and a stable scatter whose in-tile ranks come from per-wavefront
+// match masks.  The permutation then gathers the particle fields.
+#include "hvpic_internal.hpp"
+
+namespace hvpic {
+namespace {
+
+constexpr int kWaves = kBlock / 64;
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  const int lane = threadIdx.x & 63;
+  return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+struct SortGeo {
+  int nx, ny, nz, ncell;
+  FastDiv fnx, fny;
+};
+
+__device__ __forceinline__ void ijk(int c, const SortGeo& g, int& i, int& j, int& k) {
+  const uint32_t q = fdiv((uint32_t)c, g.fnx);
+  i = c - (int)q * g.nx;
+  const uint32_t q2 = fdiv(q, g.fny);
+  j = (int)q - (int)q2 * g.ny;
+  k = (int)q2;
+}
+
+// Canonical move in {-1,0,1} along an axis of n cells, or 2 for a longer move.
+__device__ __forceinline__ int canon(int delta, int n) {
+  int r = delta < 0 ? delta + n : delta;
+  if (r == 0) return 0;
+  if (r == 1) return 1;
+  if (r == n - 1) return -1;
+  return 2;
+}
+
+template <int NDIM>
+struct Dirs {
+  static constexpr int N = NDIM == 2 ? 9 : 27;
+  static constexpr int BITS = NDIM == 2 ? 4 : 5;
+};
+
+// Direction code of a particle of old cell (i,j,k) now in cell key; -1 when it
+// moved more than one cell along some axis (or the key is invalid).
+template <int NDIM>
+__device__ __forceinline__ int direction(int key, int i, int j, int k, const SortGeo& g) {
+  if ((unsigned)key >= (unsigned)g.ncell) return -1;
+  int i2, j2, k2;
+  ijk(key, g, i2, j2, k2);
+  const int di = canon(i2 - i, g.nx), dj = canon(j2 - j, g.ny);
+  const int dk = NDIM == 3 ? canon(k2 - k, g.nz) : 0;
+  if (di == 2 || dj == 2 || dk == 2) return -1;
+  return (di + 1) + 3 * (dj + 1) + (NDIM == 3 ? 9 * (dk + 1) : 0);
+}
+
+// New cell reached from old cell a by direction d (wrapped).
+template <int NDIM>
+__device__ __forceinline__ int step_cell(int i, int j, int k, int d, const SortGeo& g) {
+  const int di = d % 3 - 1, dj = (d / 3) % 3 - 1, dk = NDIM == 3 ? d / 9 - 1 : 0;
+  int i2 = i + di, j2 = j + dj, k2 = k + dk;
+  if (i2 < 0) i2 += g.nx; else if (i2 >= g.nx) i2 -= g.nx;
+  if (j2 < 0) j2 += g.ny; else if (j2 >= g.ny) j2 -= g.ny;
+  if (NDIM == 3) { if (k2 < 0) k2 += g.nz; else if (k2 >= g.nz) k2 -= g.nz; }
+  return i2 + g.nx * (j2 + g.ny * k2);
+}
+
+// Mask of the lanes of `valid` whose code equals this lane's `code`, computed
+// from one ballot per code bit.
+template <int BITS>
+__device__ __forceinline__ uint64_t match_code(int code, uint64_t valid, const uint64_t* bal) {
+  uint64_t m = valid;
+#pragma unroll
+  for (int b = 0; b < BITS; ++b) m &= ((code >> b) & 1) ? bal[b] : ~bal[b];
+  return m;
+}
+
+// ------------------------------------------------------- neighbour path --
+
+template <int NDIM>
+__global__ __launch_bounds__(kBlock) void k_nb_count(const int32_t* __restrict__ key,
+                                                     const int32_t* __restrict__ cs_prev, int64_t n,
+                                                     SortGeo g, uint32_t* __restrict__ cnt,
+                                                     Status* st, uint32_t gen) {
+  constexpr int ND = Dirs<NDIM>::N, NB = Dirs<NDIM>::BITS;
+  const int a = blockIdx.x * kWaves + (threadIdx.x >> 6);
+  if (a >= g.ncell) return;
+  const int lane = threadIdx.x & 63;
+  int64_t s0 = cs_prev[a], s1 = cs_prev[a + 1];
+  if (s0 < 0 || s1 > n || s1 < s0) {
+    if (lane == 0) {
+      raise_flag(st, HVPIC_FLAG_BAD_INPUT, &st->bad_input);
+      __hip_atomic_store(&st->sort_fallback, gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    s0 = s1 = 0;
+  }
+  int i, j, k;
+  ijk(a, g, i, j, k);
+  uint32_t count = 0;  // lane L < ND counts direction L
+  bool far = false;
+  for (int64_t base = s0; base < s1; base += 64) {
+    const int64_t p = base + lane;
+    const bool valid = p < s1;
+    int d = 0;
+    if (valid) {
+      d = direction<NDIM>(key[p], i, j, k, g);
+      far |= d < 0;
+    }
+    uint64_t bal[NB];
+    const uint64_t vmask = __ballot(valid && d >= 0);
+#pragma unroll
+    for (int b = 0; b < NB; ++b) bal[b] = __ballot(valid && d >= 0 && ((d >> b) & 1));
+    if (lane < ND) count += (uint32_t)__builtin_popcountll(match_code<NB>(lane, vmask, bal));
+  }
+  if (__ballot(far) && lane == 0)
+    __hip_atomic_store(&st->sort_fallback, gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (lane < ND) cnt[(int64_t)a * ND + lane] = count;
+}
+
+// Block-level exclusive scan of kScanTile values held in LDS `s`; returns the
+// tile total.  Thread t owns elements [t*8, t*8+8).
+__device__ uint32_t tile_exclusive_scan(uint32_t* s) {
+  __shared__ uint32_t wsum[kWaves];
+  const int t = threadIdx.x;
+  uint32_t v[8], acc = 0;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    v[q] = s[t * 8 + q];
+    acc += v[q];
+  }
+  // inclusive scan of acc over the block
+  uint32_t x = acc;
+  const int lane = t & 63;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(x, o);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) wsum[t >> 6] = x;
+  __syncthreads();
+  uint32_t woff = 0, total = 0;
+#pragma unroll
+  for (int w = 0; w < kWaves; ++w) {
+    if (w < (t >> 6)) woff += wsum[w];
+    total += wsum[w];
+  }
+  uint32_t run = woff + x - acc;  // exclusive prefix of this thread
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    s[t * 8 + q] = run;
+    run += v[q];
+  }
+  __syncthreads();
+  return total;
+}
+
+// Per-new-cell totals, written to cs[c], and their per-tile sums.
+template <int NDIM>
+__global__ __launch_bounds__(kBlock) void k_nb_newcount(const uint32_t* __restrict__ cnt, SortGeo g,
+                                                        int32_t* __restrict__ cs,
+                                                        uint32_t* __restrict__ blk) {
+  constexpr int ND = Dirs<NDIM>::N;
+  __shared__ uint32_t wsum[kWaves];
+  const int64_t t0 = (int64_t)blockIdx.x * kScanTile;
+  uint32_t local = 0;
+  for (int q = 0; q < kScanTile / kBlock; ++q) {
+    const int64_t c = t0 + q * kBlock + threadIdx.x;
+    if (c >= g.ncell) break;
+    int i, j, k;
+    ijk((int)c, g, i, j, k);
+    uint32_t s = 0;
+    for (int d = 0; d < ND; ++d) {
+      const int src = step_cell<NDIM>(i, j, k, ND - 1 - d, g);  // c - d == c + (ND-1-d)
+      s += cnt[(int64_t)src * ND + d];
+    }
+    cs[c] = (int32_t)s;
+    local += s;
+  }
+  for (int o = 32; o > 0; o >>= 1) local += __shfl_xor(local, o);
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = local;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t s = 0;
+    for (int w = 0; w < kWaves; ++w) s += wsum[w];
+    blk[blockIdx.x] = s;
+  }
+}
+
+// Exclusive scan of m tile totals in one block (in place); blk[m] = total.
+__global__ __launch_bounds__(1024) void k_scan_tiles(uint32_t* blk, int m) {
+  __shared__ uint32_t wsum[16];
+  __shared__ uint32_t carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int base = 0; base < m; base += 1024) {
+    const int idx = base + threadIdx.x;
+    const uint32_t v = idx < m ? blk[idx] : 0u;
+    uint32_t x = v;
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(x, o);
+      if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[wid] = x;
+    __syncthreads();
+    uint32_t woff = 0, tot = 0;
+    for (int w = 0; w < 16; ++w) {
+      if (w < wid) woff += wsum[w];
+      tot += wsum[w];
+    }
+    const uint32_t c0 = carry;
+    if (idx < m) blk[idx] = c0 + woff + x - v;
+    __syncthreads();
+    if (threadIdx.x == 0) carry = c0 + tot;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) blk[m] = carry;
+}
+
+// cell_start from the per-cell totals, and the first slot of every group
+// (source cell, direction) of each new cell, written over cnt.
+template <int NDIM>
+__global__ __launch_bounds__(kBlock) void k_nb_bases(uint32_t* __restrict__ cnt, SortGeo g,
+                                                     int32_t* __restrict__ cs,
+                                                     const uint32_t* __restrict__ blk) {
+  constexpr int ND = Dirs<NDIM>::N;
+  __shared__ uint32_t s[kScanTile];
+  const int64_t t0 = (int64_t)blockIdx.x * kScanTile;
+  for (int q = 0; q < kScanTile / kBlock; ++q) {
+    const int64_t c = t0 + q * kBlock + threadIdx.x;
+    s[q * kBlock + threadIdx.x] = c < g.ncell ? (uint32_t)cs[c] : 0u;
+  }
+  __syncthreads();
+  tile_exclusive_scan(s);
+  const uint32_t off = blk[blockIdx.x];
+  for (int q = 0; q < kScanTile / kBlock; ++q) {
+    const int64_t c = t0 + q * kBlock + threadIdx.x;
+    if (c >= g.ncell) break;
+    const uint32_t start = off + s[q * kBlock + threadIdx.x];
+    cs[c] = (int32_t)start;
+    if (c == g.ncell - 1) cs[g.ncell] = (int32_t)blk[gridDim.x];
+    int i, j, k;
+    ijk((int)c, g, i, j, k);
+    int src[ND];
+    uint32_t n[ND];
+    for (int d = 0; d < ND; ++d) {
+      src[d] = step_cell<NDIM>(i, j, k, ND - 1 - d, g);
+      n[d] = cnt[(int64_t)src[d] * ND + d];
+    }
+    // groups in increasing old-cell index (ties only between empty groups)
+    for (int d = 0; d < ND; ++d) {
+      uint32_t before = 0;
+      for (int e = 0; e < ND; ++e)
+        if (src[e] < src[d] || (src[e] == src[d] && e < d)) before += n[e];
+      cnt[(int64_t)src[d] * ND + d] = start + before;
+    }
+  }
+}
+
+struct Fields {
+  int32_t* cell;
+  float* f[7];  // ox, oy, oz, ux, uy, uz, w (oz may be null)
+};
+
+template <int NDIM>
+__global__ __launch_bounds__(kBlock) void k_nb_scatter(const int32_t* __restrict__ cs_prev, int64_t n,
+                                                       SortGeo g, const uint32_t* __restrict__ bases,
+                                                       Fields in, Fields out, const Status* st,
+                                                       uint32_t gen) {
+  constexpr int ND = Dirs<NDIM>::N, NB = Dirs<NDIM>::BITS;
+  if (__hip_atomic_load(&st->sort_fallback, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen)
+    return;
+  const int a = blockIdx.x * kWaves + (threadIdx.x >> 6);
+  if (a >= g.ncell) return;
+  const int lane = threadIdx.x & 63;
+  const int64_t s0 = cs_prev[a], s1 = cs_prev[a + 1];
+  if (s0 < 0 || s1 > n || s1 < s0) return;
+  int i, j, k;
+  ijk(a, g, i, j, k);
+  const uint32_t mybase = lane < ND ? bases[(int64_t)a * ND + lane] : 0u;
+  uint32_t running = 0;
+  for (int64_t base = s0; base < s1; base += 64) {
+    const int64_t p = base + lane;
+    const bool valid = p < s1;
+    int d = 0, key = 0;
+    if (valid) {
+      key = in.cell[p];
+      d = direction<NDIM>(key, i, j, k, g);
+    }
+    const bool ok = valid && d >= 0;
+    uint64_t bal[NB];
+    const uint64_t vmask = __ballot(ok);
+#pragma unroll
+    for (int b = 0; b < NB; ++b) bal[b] = __ballot(ok && ((d >> b) & 1));
+    const uint64_t mine = match_code<NB>(d, vmask, bal);
+    const uint32_t grp_base = __shfl(mybase + running, ok ? d : 0);
+    if (lane < ND) running += (uint32_t)__builtin_popcountll(match_code<NB>(lane, vmask, bal));
+    if (ok) {
+      const int64_t dst = (int64_t)grp_base + __builtin_popcountll(mine & lanemask_lt());
+      if (dst < n) {
+        out.cell[dst] = key;
+#pragma unroll
+        for (int f = 0; f < 7; ++f)
+          if (in.f[f]) out.f[f][dst] = in.f[f][p];
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------- radix path --
+
+__device__ __forceinline__ bool gate_closed(const Status* st, uint32_t gen, int forced) {
+  return !forced &&
+         __hip_atomic_load(&st->sort_fallback, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != gen;
+}
+
+// Per-tile histogram of one digit; hist is digit-major [bin][tile].
+__global__ __launch_bounds__(kBlock) void k_radix_hist(const uint32_t* __restrict__ keys,
+                                                       const int32_t* __restrict__ cells, int64_t n,
+                                                       int shift, uint32_t* __restrict__ hist,
+                                                       int ntiles, const Status* st, uint32_t gen,
+                                                       int forced, int ncell) {
+  if (gate_closed(st, gen, forced)) return;
+  __shared__ uint32_t h[kRadixBins];
+  for (int b = threadIdx.x; b < kRadixBins; b += kBlock) h[b] = 0;
+  __syncthreads();
+  const int64_t t0 = (int64_t)blockIdx.x * kRadixTile;
+  for (int q = 0; q < kRadixItems; ++q) {
+    const int64_t idx = t0 + q * kBlock + threadIdx.x;
+    if (idx < n) {
+      uint32_t key = keys ? keys[idx] : (uint32_t)cells[idx];
+      if (key >= (uint32_t)ncell) key = (uint32_t)ncell - 1;  // guarded upstream
+      atomicAdd(&h[(key >> shift) & (kRadixBins - 1)], 1u);
+    }
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < kRadixBins; b += kBlock) hist[(int64_t)b * ntiles + blockIdx.x] = h[b];
+}
+
+// Generic 3-kernel exclusive scan of a uint32 array (tile sums / tile scans).
+__global__ __launch_bounds__(kBlock) void k_scan_reduce(const uint32_t* __restrict__ v, int64_t m,
+                                                        uint32_t* __restrict__ blk, const Status* st,
+                                                        uint32_t gen, int forced) {
+  if (gate_closed(st, gen, forced)) return;
+  __shared__ uint32_t wsum[kWaves];
+  const int64_t t0 = (int64_t)blockIdx.x * kScanTile;
+  uint32_t local = 0;
+  for (int q = 0; q < kScanTile / kBlock; ++q) {
+    const int64_t i = t0 + q * kBlock + threadIdx.x;
+    if (i < m) local += v[i];
+  }
+  for (int o = 32; o > 0; o >>= 1) local += __shfl_xor(local, o);
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = local;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t s = 0;
+    for (int w = 0; w < kWaves; ++w) s += wsum[w];
+    blk[blockIdx.x] = s;
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_scan_tiles_gated(uint32_t* blk, int m, const Status* st,
+                                                           uint32_t gen, int forced) {
+  if (gate_closed(st, gen, forced)) return;
+  __shared__ uint32_t wsum[16];
+  __shared__ uint32_t carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int base = 0; base < m; base += 1024) {
+    const int idx = base + threadIdx.x;
+    const uint32_t val = idx < m ? blk[idx] : 0u;
+    uint32_t x = val;
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(x, o);
+      if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[wid] = x;
+    __syncthreads();
+    uint32_t woff = 0, tot = 0;
+    for (int w = 0; w < 16; ++w) {
+      if (w < wid) woff += wsum[w];
+      tot += wsum[w];
+    }
+    const uint32_t c0 = carry;
+    if (idx < m) blk[idx] = c0 + woff + x - val;
+    __syncthreads();
+    if (threadIdx.x == 0) carry = c0 + tot;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) blk[m] = carry;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_apply(uint32_t* __restrict__ v, int64_t m,
+                                                       const uint32_t* __restrict__ blk,
+                                                       const Status* st, uint32_t gen, int forced) {
+  if (gate_closed(st, gen, forced)) return;
+  __shared__ uint32_t s[kScanTile];
+  const int64_t t0 = (int64_t)blockIdx.x * kScanTile;
+  for (int q = 0; q < kScanTile / kBlock; ++q) {
+    const int64_t i = t0 + q * kBlock + threadIdx.x;
+    s[q * kBlock + threadIdx.x] = i < m ? v[i] : 0u;
+  }
+  __syncthreads();
+  tile_exclusive_scan(s);
+  const uint32_t off = blk[blockIdx.x];
+  for (int q = 0; q < kScanTile / kBlock; ++q) {
+    const int64_t i = t0 + q * kBlock + threadIdx.x;
+    if (i < m) v[i] = off + s[q * kBlock + threadIdx.x];
+  }
+}
+
+// Stable scatter of one digit.  Within a tile the order is item-major:
+// element (q, t) is tile[q*kBlock + t], matching the global index order.
+__global__ __launch_bounds__(kBlock) void k_radix_scatter(
+    const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
+    const int32_t* __restrict__ cells, int64_t n, int shift, const uint32_t* __restrict__ offs,
+    int ntiles, uint32_t* __restrict__ kout, uint32_t* __restrict__ vout, const Status* st,
+    uint32_t gen, int forced, int ncell) {
+  if (gate_closed(st, gen, forced)) return;
+  __shared__ uint32_t wcnt[kWaves][kRadixBins];
+  __shared__ uint32_t run[kRadixBins];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int b = threadIdx.x; b < kRadixBins; b += kBlock)
+    run[b] = offs[(int64_t)b * ntiles + blockIdx.x];
+  const int64_t t0 = (int64_t)blockIdx.x * kRadixTile;
+  for (int q = 0; q < kRadixItems; ++q) {
+    for (int b = threadIdx.x; b < kWaves * kRadixBins; b += kBlock) (&wcnt[0][0])[b] = 0;
+    __syncthreads();
+    const int64_t idx = t0 + q * kBlock + threadIdx.x;
+    const bool valid = idx < n;
+    uint32_t key = 0, val = 0;
+    if (valid) {
+      key = kin ? kin[idx] : (uint32_t)cells[idx];
+      if (key >= (uint32_t)ncell) key = (uint32_t)ncell - 1;
+      val = vin ? vin[idx] : (uint32_t)idx;
+    }
+    const int digit = (key >> shift) & (kRadixBins - 1);
+    uint64_t bal[kRadixBits];
+    const uint64_t vmask = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < kRadixBits; ++b) bal[b] = __ballot(valid && ((digit >> b) & 1));
+    const uint64_t mine = match_code<kRadixBits>(digit, vmask, bal);
+    const uint32_t rank_in_wave = __builtin_popcountll(mine & lanemask_lt());
+    // the lowest lane of each digit group publishes the group size
+    if (valid && rank_in_wave == 0) wcnt[wid][digit] = __builtin_popcountll(mine);
+    __syncthreads();
+    if (valid) {
+      uint32_t before = run[digit];
+      for (int w = 0; w < wid; ++w) before += wcnt[w][digit];
+      const uint32_t dst = before + rank_in_wave;
+      kout[dst] = key;
+      vout[dst] = val;
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < kRadixBins; b += kBlock) {
+      uint32_t s = 0;
+      for (int w = 0; w < kWaves; ++w) s += wcnt[w][b];
+      run[b] += s;
+    }
+    __syncthreads();
+  }
+}
+
+// Gathers the particle fields in sorted order and builds cell_start from the
+// sorted keys (every cell boundary between neighbours r-1 and r fills the
+// starts of the cells in (key[r-1], key[r]]).
+__global__ __launch_bounds__(kBlock) void k_radix_final(const uint32_t* __restrict__ keys,
+                                                        const uint32_t* __restrict__ perm, int64_t n,
+                                                        Fields in, Fields out, int32_t* cs,
+                                                        int ncell, const Status* st, uint32_t gen,
+                                                        int forced) {
+  if (gate_closed(st, gen, forced)) return;
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x; r <= n; r += stride) {
+    const int kprev = r == 0 ? -1 : (int)(keys ? keys[r - 1] : 0u);
+    const int knext = r == n ? ncell : (int)(keys ? keys[r] : 0u);
+    for (int c = kprev + 1; c <= knext && c <= ncell; ++c) cs[c] = (int32_t)r;
+    if (r < n) {
+      const uint32_t src = perm ? perm[r] : (uint32_t)r;
+      out.cell[r] = in.cell[src];
+#pragma unroll
+      for (int f = 0; f < 7; ++f)
+        if (in.f[f]) out.f[f][r] = in.f[f][src];
+    }
+  }
+}
+
+Fields fields_of(const hvpic_particles* p) {
+  Fields f;
+  f.cell = p->cell;
+  f.f[0] = p->ox;
+  f.f[1] = p->oy;
+  f.f[2] = p->oz;
+  f.f[3] = p->ux;
+  f.f[4] = p->uy;
+  f.f[5] = p->uz;
+  f.f[6] = p->w;
+  return f;
+}
+
+SortGeo sort_geo(const hvpic_ctx* c) {
+  SortGeo g;
+  g.nx = c->p.nx;
+  g.ny = c->p.ny;
+  g.nz = c->p.nz;
+  g.ncell = c->ncell;
+  g.fnx = c->fnx;
+  g.fny = c->fny;
+  return g;
+}
+
+int radix_bits(int ncell) {
+  int b = 0;
+  while (b < 31 && (1ll << b) < ncell) ++b;
+  return b;
+}
+
+// The general sort; `forced` = run unconditionally, else only when the
+// neighbour path raised the fallback generation `gen`.
+void enqueue_radix(hvpic_ctx* c, const hvpic_particles* in, hvpic_particles* out, int32_t* cs,
+                   uint32_t gen, int forced) {
+  hipStream_t s = c->stream;
+  const int64_t n = in->n;
+  const int ncell = c->ncell;
+  const int ntiles = (int)ceil_div(std::max<int64_t>(n, 1), kRadixTile);
+  const int passes = (radix_bits(ncell) + kRadixBits - 1) / kRadixBits;
+  const uint32_t* kin = nullptr;
+  const uint32_t* vin = nullptr;
+  int cur = 0;
+  const int64_t m = (int64_t)kRadixBins * ntiles;
+  const int mtiles = (int)ceil_div(m, kScanTile);
+  for (int pass = 0; pass < passes && n > 0; ++pass) {
+    const int shift = pass * kRadixBits;
+    hipLaunchKernelGGL(k_radix_hist, dim3(ntiles), dim3(kBlock), 0, s, kin, in->cell, n, shift,
+                       c->rhist, ntiles, c->status, gen, forced, ncell);
+    hipLaunchKernelGGL(k_scan_reduce, dim3(mtiles), dim3(kBlock), 0, s, c->rhist, m,
+                       (uint32_t*)c->sort_blk, c->status, gen, forced);
+    hipLaunchKernelGGL(k_scan_tiles_gated, dim3(1), dim3(1024), 0, s, (uint32_t*)c->sort_blk,
+                       mtiles, c->status, gen, forced);
+    hipLaunchKernelGGL(k_scan_apply, dim3(mtiles), dim3(kBlock), 0, s, c->rhist, m,
+                       (const uint32_t*)c->sort_blk, c->status, gen, forced);
+    hipLaunchKernelGGL(k_radix_scatter, dim3(ntiles), dim3(kBlock), 0, s, kin, vin, in->cell, n,
+                       shift, c->rhist, ntiles, c->rkey[cur], c->rval[cur], c->status, gen, forced,
+                       ncell);
+    kin = c->rkey[cur];
+    vin = c->rval[cur];
+    cur ^= 1;
+  }
+  const int fblocks = (int)std::min<int64_t>(ceil_div(n + 1, kBlock), 65536);
+  hipLaunchKernelGGL(k_radix_final, dim3(fblocks), dim3(kBlock), 0, s, kin, vin, n, fields_of(in),
+                     fields_of(out), cs, ncell, c->status, gen, forced);
+}
+
+template <int NDIM>
+void enqueue_neighbour(hvpic_ctx* c, const hvpic_particles* in, hvpic_particles* out,
+                       const int32_t* cs_prev, int32_t* cs, uint32_t gen) {
+  hipStream_t s = c->stream;
+  const SortGeo g = sort_geo(c);
+  const int cblocks = (int)ceil_div(c->ncell, kWaves);
+  const int tiles = (int)ceil_div(c->ncell, kScanTile);
+  uint32_t* blk = (uint32_t*)c->sort_blk;
+  hipLaunchKernelGGL((k_nb_count<NDIM>), dim3(cblocks), dim3(kBlock), 0, s, in->cell, cs_prev,
+                     in->n, g, c->sort_cnt, c->status, gen);
+  hipLaunchKernelGGL((k_nb_newcount<NDIM>), dim3(tiles), dim3(kBlock), 0, s,
+                     (const uint32_t*)c->sort_cnt, g, cs, blk);
+  hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, s, blk, tiles);
+  hipLaunchKernelGGL((k_nb_bases<NDIM>), dim3(tiles), dim3(kBlock), 0, s, c->sort_cnt, g, cs,
+                     (const uint32_t*)blk);
+  hipLaunchKernelGGL((k_nb_scatter<NDIM>), dim3(cblocks), dim3(kBlock), 0, s, cs_prev, in->n, g,
+                     (const uint32_t*)c->sort_cnt, fields_of(in), fields_of(out), c->status, gen);
+  enqueue_radix(c, in, out, cs, gen, /*forced=*/0);
+}
+
+}  // namespace
+
+int launch_sort(hvpic_ctx* c, const hvpic_particles* in, hvpic_particles* out,
+                const int32_t* cs_prev, int32_t* cs, int full) {
+  out->n = in->n;
+  c->sort_gen = c->sort_gen + 1 == 0 ? 1 : c->sort_gen + 1;
+  const uint32_t gen = c->sort_gen;
+  if (full || cs_prev == nullptr) {
+    enqueue_radix(c, in, out, cs, gen, /*forced=*/1);
+  } else if (c->p.ndim == 2) {
+    enqueue_neighbour<2>(c, in, out, cs_prev, cs, gen);
+  } else {
+    enqueue_neighbour<3>(c, in, out, cs_prev, cs, gen);
+  }
+  return hipGetLastError() == hipSuccess ? HVPIC_OK : HVPIC_EHIP;
+}
+
+}  // namespace hvpic

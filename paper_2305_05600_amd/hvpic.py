@@ -1,0 +1,261 @@
+"""ctypes binding of libhvpic.so (include/hvpic.h).
+
+Argument marshalling only: every function takes torch tensors that live on
+the GPU, checks dtype/shape/contiguity, and passes raw device pointers to the
+C function of the same name.  No computation happens here.  If the library is
+not built the first call raises -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import pathlib
+
+import torch
+
+_PKG = pathlib.Path(__file__).resolve().parent
+LIB_PATH = _PKG / "libhvpic.so"
+_LIB = None
+_NCELL = {}  # context handle -> ncell, for host-side size checks
+
+HVPIC_OK, HVPIC_EINVAL, HVPIC_ENOMEM, HVPIC_EHIP, HVPIC_ESTATE = 0, -1, -2, -3, -4
+HVPIC_SHAPE_NGP, HVPIC_SHAPE_QS = 0, 1
+FLAG_MOVE_GT1, FLAG_FLOOR_HIT, FLAG_NONFINITE, FLAG_BAD_INPUT = 1, 2, 4, 8
+
+EXPORTS = ("hvpic_workspace_bytes", "hvpic_init", "hvpic_finalize", "hvpic_gather_push",
+           "hvpic_sort", "hvpic_deposit", "hvpic_field_advance", "hvpic_smooth",
+           "hvpic_sync_status", "hvpic_strerror")
+
+
+class HvpicParams(ctypes.Structure):
+    _fields_ = [
+        ("ndim", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+        ("nz", ctypes.c_int32),
+        ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dz", ctypes.c_double),
+        ("dt", ctypes.c_double),
+        ("nsub", ctypes.c_int32), ("shape", ctypes.c_int32), ("nsmooth", ctypes.c_int32),
+        ("qs", ctypes.c_double), ("ms", ctypes.c_double),
+        ("te", ctypes.c_double), ("gamma_e", ctypes.c_double), ("n0", ctypes.c_double),
+        ("n_floor", ctypes.c_double),
+        ("eta", ctypes.c_double), ("eta_h", ctypes.c_double),
+        ("np_capacity", ctypes.c_int64),
+    ]
+
+
+class HvpicParticles(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("cell", ctypes.c_void_p),
+                ("ox", ctypes.c_void_p), ("oy", ctypes.c_void_p), ("oz", ctypes.c_void_p),
+                ("ux", ctypes.c_void_p), ("uy", ctypes.c_void_p), ("uz", ctypes.c_void_p),
+                ("w", ctypes.c_void_p)]
+
+
+class HvpicError(RuntimeError):
+    pass
+
+
+def lib():
+    """Loads libhvpic.so (raises if it has not been built)."""
+    global _LIB
+    if _LIB is None:
+        if not LIB_PATH.exists():
+            raise HvpicError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = ctypes.CDLL(str(LIB_PATH))
+        vp, i32, P = ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER
+        L.hvpic_workspace_bytes.argtypes = [P(HvpicParams), P(ctypes.c_size_t)]
+        L.hvpic_init.argtypes = [P(HvpicParams), vp, vp, P(vp)]
+        L.hvpic_finalize.argtypes = [vp]
+        L.hvpic_gather_push.argtypes = [vp, P(HvpicParticles), vp, vp, vp, vp, vp]
+        L.hvpic_sort.argtypes = [vp, P(HvpicParticles), P(HvpicParticles), vp, vp, i32]
+        L.hvpic_deposit.argtypes = [vp, P(HvpicParticles), vp, ctypes.c_float, vp, vp]
+        L.hvpic_field_advance.argtypes = [vp, vp, vp, vp, vp, vp, vp, i32, vp]
+        L.hvpic_smooth.argtypes = [vp, vp, i32, i32]
+        L.hvpic_sync_status.argtypes = [vp, P(ctypes.c_uint32), P(ctypes.c_int64)]
+        L.hvpic_strerror.argtypes = [ctypes.c_int]
+        L.hvpic_strerror.restype = ctypes.c_char_p
+        for f in EXPORTS[:-1]:
+            getattr(L, f).restype = ctypes.c_int
+        _LIB = L
+    return _LIB
+
+
+def _check(rc: int, what: str):
+    if rc != HVPIC_OK:
+        raise HvpicError(f"{what}: {lib().hvpic_strerror(rc).decode()} ({rc})")
+
+
+def _ptr(t, dtype=None, numel=None):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise HvpicError("expected a CUDA (HIP) tensor")
+    if not t.is_contiguous():
+        raise HvpicError("expected a contiguous tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise HvpicError(f"expected {dtype}, got {t.dtype}")
+    if numel is not None and t.numel() < numel:
+        raise HvpicError(f"tensor holds {t.numel()} elements, needs {numel}")
+    return t.data_ptr()
+
+
+def params_from(cfg, np_capacity: int) -> HvpicParams:
+    return HvpicParams(cfg.ndim, cfg.nx, cfg.ny, cfg.nz, cfg.dx, cfg.dy, cfg.dz, cfg.dt,
+                       cfg.nsub, cfg.shape, cfg.nsmooth, cfg.qs, cfg.ms, cfg.te, cfg.gamma_e,
+                       cfg.n0, cfg.n_floor, cfg.eta, cfg.eta_h, int(np_capacity))
+
+
+class Particles:
+    """Structure-of-arrays particle store in device memory."""
+
+    FIELDS = ("cell", "ox", "oy", "oz", "ux", "uy", "uz", "w")
+
+    def __init__(self, ndim: int, capacity: int, device="cuda"):
+        self.ndim = ndim
+        self.capacity = capacity
+        self.n = 0
+        self.cell = torch.empty(capacity, dtype=torch.int32, device=device)
+        f = lambda: torch.empty(capacity, dtype=torch.float32, device=device)
+        self.ox, self.oy = f(), f()
+        self.oz = f() if ndim == 3 else None
+        self.ux, self.uy, self.uz, self.w = f(), f(), f(), f()
+
+    @classmethod
+    def from_numpy(cls, parts: dict, ndim: int, capacity: int | None = None, device="cuda"):
+        n = int(parts["cell"].size)
+        p = cls(ndim, max(capacity or n, 1), device)
+        p.load(parts)
+        return p
+
+    def load(self, parts: dict):
+        n = int(parts["cell"].size)
+        if n > self.capacity:
+            raise HvpicError("more particles than capacity")
+        self.n = n
+        for k in self.FIELDS:
+            t = getattr(self, k)
+            if t is None:
+                continue
+            t[:n].copy_(torch.from_numpy(parts[k]))
+
+    def to_numpy(self) -> dict:
+        out = {}
+        for k in self.FIELDS:
+            t = getattr(self, k)
+            if t is not None:
+                out[k] = t[: self.n].cpu().numpy()
+        return out
+
+    def c(self) -> HvpicParticles:
+        g = lambda t: None if t is None else t.data_ptr()
+        return HvpicParticles(self.n, g(self.cell), g(self.ox), g(self.oy), g(self.oz),
+                              g(self.ux), g(self.uy), g(self.uz), g(self.w))
+
+
+# ---------------------------------------------------------------------------
+# One Python function per C entry point (same names).
+# ---------------------------------------------------------------------------
+
+def hvpic_workspace_bytes(params: HvpicParams) -> int:
+    n = ctypes.c_size_t(0)
+    _check(lib().hvpic_workspace_bytes(ctypes.byref(params), ctypes.byref(n)),
+           "hvpic_workspace_bytes")
+    return n.value
+
+
+def hvpic_init(params: HvpicParams, stream, workspace: torch.Tensor):
+    ctx = ctypes.c_void_p()
+    s = None if stream is None else ctypes.c_void_p(stream)
+    need = hvpic_workspace_bytes(params)
+    _check(lib().hvpic_init(ctypes.byref(params), s, _ptr(workspace, torch.uint8, need),
+                            ctypes.byref(ctx)), "hvpic_init")
+    _NCELL[ctx.value] = params.nx * params.ny * params.nz
+    return ctx
+
+
+def hvpic_finalize(ctx):
+    _check(lib().hvpic_finalize(ctx), "hvpic_finalize")
+    _NCELL.pop(ctx.value, None)
+
+
+def _nc(ctx, k=1):
+    return k * _NCELL[ctx.value] if ctx.value in _NCELL else None
+
+
+def hvpic_gather_push(ctx, p: Particles, E, B, n_mid=None, J_mid=None, diag_out=None):
+    cp = p.c()
+    _check(lib().hvpic_gather_push(ctx, ctypes.byref(cp), _ptr(E, torch.float32, _nc(ctx, 3)),
+                                   _ptr(B, torch.float32, _nc(ctx, 3)),
+                                   _ptr(n_mid, torch.float32, _nc(ctx)),
+                                   _ptr(J_mid, torch.float32, _nc(ctx, 3)),
+                                   _ptr(diag_out, torch.float64, 4)),
+           "hvpic_gather_push")
+
+
+def hvpic_sort(ctx, pin: Particles, pout: Particles, cell_start_prev, cell_start, full=False):
+    ci, co = pin.c(), pout.c()
+    if pout.capacity < pin.n:
+        raise HvpicError("output store too small")
+    ncs = None if _nc(ctx) is None else _nc(ctx) + 1
+    _check(lib().hvpic_sort(ctx, ctypes.byref(ci), ctypes.byref(co),
+                            _ptr(cell_start_prev, torch.int32, ncs),
+                            _ptr(cell_start, torch.int32, ncs),
+                            1 if full else 0), "hvpic_sort")
+    pout.n = co.n
+
+
+def hvpic_deposit(ctx, p: Particles, cell_start, half_dt_back: float, n, J):
+    cp = p.c()
+    _check(lib().hvpic_deposit(ctx, ctypes.byref(cp), _ptr(cell_start, torch.int32),
+                               ctypes.c_float(half_dt_back), _ptr(n, torch.float32, _nc(ctx)),
+                               _ptr(J, torch.float32, _nc(ctx, 3))), "hvpic_deposit")
+
+
+def hvpic_field_advance(ctx, B, n_half, J_half, n_prev, J_prev, E_out, mode=0, diag_out=None):
+    v1, v3 = _nc(ctx), _nc(ctx, 3)
+    _check(lib().hvpic_field_advance(ctx, _ptr(B, torch.float32, v3),
+                                     _ptr(n_half, torch.float32, v1),
+                                     _ptr(J_half, torch.float32, v3),
+                                     _ptr(n_prev, torch.float32, v1),
+                                     _ptr(J_prev, torch.float32, v3),
+                                     _ptr(E_out, torch.float32, v3),
+                                     int(mode), _ptr(diag_out, torch.float64, 2)),
+           "hvpic_field_advance")
+
+
+def hvpic_smooth(ctx, F, npasses: int):
+    ncomp = 1 if F.dim() == 1 else F.shape[0]
+    _check(lib().hvpic_smooth(ctx, _ptr(F, torch.float32, _nc(ctx, ncomp)), int(ncomp),
+                              int(npasses)),
+           "hvpic_smooth")
+
+
+def hvpic_sync_status(ctx):
+    flags = ctypes.c_uint32(0)
+    counts = (ctypes.c_int64 * 3)()
+    _check(lib().hvpic_sync_status(ctx, ctypes.byref(flags), counts), "hvpic_sync_status")
+    return flags.value, tuple(counts)
+
+
+def hvpic_strerror(code: int) -> str:
+    return lib().hvpic_strerror(code).decode()
+
+
+class Context:
+    """Owns a context, its workspace and the stream it is bound to."""
+
+    def __init__(self, cfg, np_capacity: int, device="cuda", stream=None):
+        self.cfg = cfg
+        self.params = params_from(cfg, np_capacity)
+        nbytes = hvpic_workspace_bytes(self.params)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        self.ctx = hvpic_init(self.params, self.stream.cuda_stream, self.workspace)
+
+    def close(self):
+        if self.ctx is not None:
+            hvpic_finalize(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

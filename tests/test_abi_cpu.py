@@ -1,0 +1,72 @@
+"""Host-side checks of libhvpic.so that need no GPU: the library loads, exports
+every function include/hvpic.h declares, and rejects bad arguments before any
+device work (parameter validation is pure host code)."""
+import ctypes
+import pathlib
+import re
+
+import pytest
+
+from paper_2305_05600_amd import workloads as W
+
+ROOT = pathlib.Path(__file__).resolve().parents[1]
+
+
+@pytest.fixture(scope="module")
+def H():
+    from paper_2305_05600_amd import hvpic
+
+    if not hvpic.LIB_PATH.exists():
+        from paper_2305_05600_amd import build
+
+        build.build()
+    hvpic.lib()
+    return hvpic
+
+
+def _declared():
+    text = (ROOT / "include" / "hvpic.h").read_text()
+    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(hvpic_\w+)\s*\(", text, re.M)))
+
+
+def test_exports_every_declared_symbol(H):
+    names = _declared()
+    assert len(names) >= 10, names
+    for n in names:
+        assert hasattr(H.lib(), n), n
+    assert set(names) == set(H.EXPORTS)
+
+
+def test_struct_layout_matches_header(H):
+    # hvpic_params: 4 int32, 4 double, 3 int32 (+pad), 8 double, int64
+    assert ctypes.sizeof(H.HvpicParams) == 16 + 32 + 16 + 64 + 8
+    assert ctypes.sizeof(H.HvpicParticles) == 8 * 9
+
+
+def test_workspace_bytes_and_validation(H):
+    cfg, _, _ = W.periodic_alfven()
+    p = H.params_from(cfg, 65536)
+    nb = H.hvpic_workspace_bytes(p)
+    assert nb > 65536 * 16
+    bad = [dict(ndim=4), dict(nz=2), dict(dx=0.0), dict(dt=float("nan")), dict(shape=7),
+           dict(n_floor=0.0), dict(eta_h=1e-3), dict(np_capacity=-1), dict(nsub=-1)]
+    for b in bad:
+        q = H.params_from(cfg, 65536)
+        for k, v in b.items():
+            setattr(q, k, v)
+        n = ctypes.c_size_t(0)
+        assert H.lib().hvpic_workspace_bytes(ctypes.byref(q), ctypes.byref(n)) == H.HVPIC_EINVAL, b
+
+
+def test_init_rejects_bad_arguments_without_device_work(H):
+    cfg, _, _ = W.periodic_alfven()
+    p = H.params_from(cfg, 10)
+    ctx = ctypes.c_void_p()
+    L = H.lib()
+    assert L.hvpic_init(ctypes.byref(p), None, None, ctypes.byref(ctx)) == H.HVPIC_EINVAL
+    assert L.hvpic_init(ctypes.byref(p), None, ctypes.c_void_p(0x1001), ctypes.byref(ctx)) \
+        == H.HVPIC_EINVAL  # misaligned workspace
+    assert L.hvpic_gather_push(None, None, None, None, None, None, None) == H.HVPIC_ESTATE
+    assert L.hvpic_sort(None, None, None, None, None, 0) == H.HVPIC_ESTATE
+    assert L.hvpic_finalize(None) == H.HVPIC_ESTATE
+    assert H.hvpic_strerror(H.HVPIC_EINVAL) == "invalid argument"

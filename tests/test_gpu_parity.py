@@ -1,0 +1,281 @@
+"""GPU parity: every entry point of libhvpic.so against the FP64 oracle.
+
+Tolerances: sort order, cell_start and cell indices bit-exact (cell indices
+outside the 1e-5 face band); moments and fields within 1e-5 relative L2 after
+one step; FP64 diagnostics within 1e-5.  All inputs are seeded synthetic
+workloads from paper_2305_05600_amd.workloads.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2305_05600_amd import workloads as W
+from tests.helpers import announce, compare_particles, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def H():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2305_05600_amd import hvpic
+
+    hvpic.lib()
+    return hvpic
+
+
+def cfg2(nx=37, ny=23, shape=W.SHAPE_QS, **kw):
+    base = dict(name="p2", ndim=2, nx=nx, ny=ny, nz=1, dx=0.5, dy=0.3, dz=1.0, dt=0.05,
+                nsub=3, shape=shape, te=0.2, eta=1e-3)
+    base.update(kw)
+    return W.Config(**base)
+
+
+def cfg3(nx=13, ny=11, nz=9, shape=W.SHAPE_QS, **kw):
+    base = dict(name="p3", ndim=3, nx=nx, ny=ny, nz=nz, dx=0.5, dy=0.4, dz=0.7, dt=0.05,
+                nsub=3, shape=shape, te=0.2, eta=1e-3)
+    base.update(kw)
+    return W.Config(**base)
+
+
+def dev(a, dtype=None):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=dtype)).cuda()
+
+
+CASES = [("2d-qs", cfg2()), ("2d-ngp", cfg2(shape=W.SHAPE_NGP)), ("3d-qs", cfg3()),
+         ("3d-ngp", cfg3(shape=W.SHAPE_NGP))]
+
+
+def _sorted(cfg, parts):
+    perm, cs = O.sort(cfg, parts["cell"])
+    return {k: np.ascontiguousarray(v[perm]) for k, v in parts.items()}, cs
+
+
+@pytest.mark.parametrize("name,cfg", CASES)
+@pytest.mark.parametrize("ppc", [3.7, 40.2])
+def test_gather_push(H, name, cfg, ppc):
+    announce("gather_push", name, ppc)
+    _, parts, B = W.random_box(21, cfg, ppc)
+    parts, _ = _sorted(cfg, parts)
+    E = W.random_field(22, cfg, 0.3)
+    ctx = H.Context(cfg, parts["cell"].size)
+    p = H.Particles.from_numpy(parts, cfg.ndim)
+    diag = torch.zeros(4, dtype=torch.float64, device="cuda")
+    H.hvpic_gather_push(ctx.ctx, p, dev(E), dev(B), None, None, diag)
+    flags, counts = H.hvpic_sync_status(ctx.ctx)
+    got = p.to_numpy()
+    ref = O.particles64(parts)
+    rd, st = O.push(cfg, ref, E, B)
+    compare_particles(cfg, got, ref)
+    assert np.allclose(diag.cpu().numpy(), rd, rtol=1e-5, atol=1e-6 * abs(rd[0]))
+    assert counts[0] == st.moved_gt1 and counts[1] == st.nonfinite
+
+
+@pytest.mark.parametrize("name,cfg", CASES)
+@pytest.mark.parametrize("ppc,sorted_", [(0.9, True), (37.0, True), (12.0, False)])
+@pytest.mark.parametrize("back", [0.0, 0.025])
+def test_deposit(H, name, cfg, ppc, sorted_, back):
+    announce("deposit", name, ppc, sorted_, back)
+    _, parts, _ = W.random_box(31, cfg, ppc)
+    if sorted_:
+        parts, _ = _sorted(cfg, parts)
+    ctx = H.Context(cfg, parts["cell"].size)
+    p = H.Particles.from_numpy(parts, cfg.ndim)
+    n = torch.full((cfg.ncell,), 7.0, device="cuda")   # overwritten
+    J = torch.full((3, cfg.ncell), 7.0, device="cuda")
+    H.hvpic_deposit(ctx.ctx, p, None, back, n, J)
+    rn, rJ = O.deposit(cfg, O.particles64(parts), back)
+    assert rel_l2(n.cpu().numpy(), rn) < 1e-5
+    assert rel_l2(J.cpu().numpy(), rJ) < 1e-5
+
+
+@pytest.mark.parametrize("name,cfg", CASES)
+def test_fused_push_deposit(H, name, cfg):
+    """Push with the mid-point deposit fused in == oracle push, then deposit at
+    x^{n+1} - (dt/2) v^{n+1/2}."""
+    announce("fused", name)
+    _, parts, B = W.random_box(41, cfg, 33.3)
+    parts, _ = _sorted(cfg, parts)
+    E = W.random_field(42, cfg, 0.3)
+    ctx = H.Context(cfg, parts["cell"].size)
+    p = H.Particles.from_numpy(parts, cfg.ndim)
+    n = torch.zeros(cfg.ncell, device="cuda")
+    J = torch.zeros((3, cfg.ncell), device="cuda")
+    H.hvpic_gather_push(ctx.ctx, p, dev(E), dev(B), n, J, None)
+    ref = O.particles64(parts)
+    O.push(cfg, ref, E, B)
+    rn, rJ = O.deposit(cfg, ref, 0.5 * cfg.dt)
+    compare_particles(cfg, p.to_numpy(), ref)
+    assert rel_l2(n.cpu().numpy(), rn) < 1e-5
+    assert rel_l2(J.cpu().numpy(), rJ) < 1e-5
+
+
+def _check_sorted(cfg, src: dict, out: dict, cs):
+    perm, rcs = O.sort(cfg, src["cell"])
+    assert np.array_equal(cs, rcs)
+    for k in src:
+        assert np.array_equal(out[k], src[k][perm]), k
+
+
+@pytest.mark.parametrize("name,cfg", CASES)
+@pytest.mark.parametrize("ppc", [0.3, 5.0, 70.0])
+def test_full_sort(H, name, cfg, ppc):
+    announce("full_sort", name, ppc)
+    _, parts, _ = W.random_box(51, cfg, ppc)
+    n = parts["cell"].size
+    ctx = H.Context(cfg, n)
+    p = H.Particles.from_numpy(parts, cfg.ndim)
+    q = H.Particles(cfg.ndim, max(n, 1))
+    cs = torch.zeros(cfg.ncell + 1, dtype=torch.int32, device="cuda")
+    H.hvpic_sort(ctx.ctx, p, q, None, cs, full=True)
+    _check_sorted(cfg, parts, q.to_numpy(), cs.cpu().numpy())
+
+
+@pytest.mark.parametrize("name,cfg", CASES)
+@pytest.mark.parametrize("far", [False, True])
+def test_neighbour_sort_after_push(H, name, cfg, far):
+    """Sorted store -> push -> neighbour-move sort gives the stable order; with
+    a particle moved two cells the call falls back to the general sort."""
+    announce("nb_sort", name, far)
+    _, parts, B = W.random_box(61, cfg, 20.0, vmax_cells=0.95)
+    parts, cs0 = _sorted(cfg, parts)
+    if far:
+        parts["ux"][len(parts["ux"]) // 2] = np.float32(2.5 * cfg.dx / cfg.dt)
+    E = W.random_field(62, cfg, 0.01)
+    n = parts["cell"].size
+    ctx = H.Context(cfg, n)
+    p = H.Particles.from_numpy(parts, cfg.ndim)
+    q = H.Particles(cfg.ndim, n)
+    cs_prev = dev(cs0, np.int32)
+    cs = torch.zeros(cfg.ncell + 1, dtype=torch.int32, device="cuda")
+    H.hvpic_gather_push(ctx.ctx, p, dev(E), dev(B))
+    pushed = p.to_numpy()
+    H.hvpic_sort(ctx.ctx, p, q, cs_prev, cs, full=False)
+    flags, counts = H.hvpic_sync_status(ctx.ctx)
+    _check_sorted(cfg, pushed, q.to_numpy(), cs.cpu().numpy())
+    assert bool(flags & H.FLAG_MOVE_GT1) == far
+    # repeated call with a new generation tag behaves the same
+    H.hvpic_sort(ctx.ctx, p, q, cs_prev, cs, full=False)
+    _check_sorted(cfg, pushed, q.to_numpy(), cs.cpu().numpy())
+
+
+@pytest.mark.parametrize("name,cfg", [CASES[0], CASES[2]])
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("gamma", [1.0, 5.0 / 3.0])
+def test_field_advance(H, name, cfg, mode, gamma):
+    announce("field", name, mode, gamma)
+    cfg = cfg.replace(gamma_e=gamma)
+    B = W.random_field(71, cfg, 0.2, (1.0, 0.3, -0.2))
+    nh = W.random_density(72, cfg, 0.02, 1.5)  # some cells below the floor
+    npv = W.random_density(73, cfg, 0.5, 1.5)
+    Jh = W.random_field(74, cfg, 0.2)
+    Jp = W.random_field(75, cfg, 0.2)
+    ctx = H.Context(cfg, 1)
+    Bd = dev(B)
+    Ed = torch.zeros((3, cfg.ncell), device="cuda")
+    diag = torch.zeros(2, dtype=torch.float64, device="cuda")
+    H.hvpic_field_advance(ctx.ctx, Bd, dev(nh), dev(Jh), dev(npv), dev(Jp), Ed, mode, diag)
+    flags, counts = H.hvpic_sync_status(ctx.ctx)
+    rB, rE, rd, st = O.field_advance(cfg, B, nh, Jh, npv, Jp, mode=mode)
+    assert rel_l2(Bd.cpu().numpy(), rB) < 1e-5
+    assert rel_l2(Ed.cpu().numpy(), rE) < 1e-5
+    assert np.allclose(diag.cpu().numpy(), rd, rtol=1e-5)
+    assert counts[2] == st.floor_hits and bool(flags & H.FLAG_FLOOR_HIT) == (st.floor_hits > 0)
+
+
+@pytest.mark.parametrize("name,cfg", [CASES[0], CASES[2]])
+def test_smooth(H, name, cfg):
+    announce("smooth", name)
+    F = W.random_field(81, cfg, 1.0)
+    ctx = H.Context(cfg, 1)
+    Fd = dev(F)
+    H.hvpic_smooth(ctx.ctx, Fd, 3)
+    assert rel_l2(Fd.cpu().numpy(), O.smooth(cfg, F, 3)) < 1e-6
+
+
+def test_empty_and_single(H):
+    cfg = cfg2()
+    announce("empty")
+    empty = {k: np.zeros(0, np.int32 if k == "cell" else np.float32)
+             for k in ("cell", "ox", "oy", "ux", "uy", "uz", "w")}
+    ctx = H.Context(cfg, 4)
+    p = H.Particles.from_numpy(empty, 2, capacity=4)
+    q = H.Particles(2, 4)
+    cs = torch.full((cfg.ncell + 1,), -1, dtype=torch.int32, device="cuda")
+    diag = torch.full((4,), 9.0, dtype=torch.float64, device="cuda")
+    E = torch.zeros((3, cfg.ncell), device="cuda")
+    n = torch.ones(cfg.ncell, device="cuda")
+    J = torch.ones((3, cfg.ncell), device="cuda")
+    H.hvpic_gather_push(ctx.ctx, p, E, E, n, J, diag)
+    H.hvpic_sort(ctx.ctx, p, q, None, cs, full=True)
+    assert np.all(diag.cpu().numpy() == 0) and np.all(cs.cpu().numpy() == 0)
+    assert float(n.abs().sum()) == 0 and float(J.abs().sum()) == 0
+    announce("single")
+    one = {k: v[:1] for k, v in W.random_box(3, cfg, 1.0)[1].items()}
+    p = H.Particles.from_numpy(one, 2, capacity=4)
+    H.hvpic_sort(ctx.ctx, p, q, None, cs, full=True)
+    got = cs.cpu().numpy()
+    assert got[0] == 0 and got[-1] == 1 and np.all(np.diff(got) >= 0)
+
+
+@pytest.mark.parametrize("nx,ny", [(1, 5), (2, 3), (3, 1)])
+def test_tiny_grids(H, nx, ny):
+    """Degenerate grids (periodic axes of 1-3 cells): push, sort, deposit."""
+    cfg = cfg2(nx=nx, ny=ny)
+    announce("tiny", nx, ny)
+    _, parts, B = W.random_box(91, cfg, 50.0, vmax_cells=0.9)
+    parts, cs0 = _sorted(cfg, parts)
+    E = W.random_field(92, cfg, 0.1)
+    n = parts["cell"].size
+    ctx = H.Context(cfg, n)
+    p = H.Particles.from_numpy(parts, 2)
+    q = H.Particles(2, n)
+    nd = torch.zeros(cfg.ncell, device="cuda")
+    Jd = torch.zeros((3, cfg.ncell), device="cuda")
+    H.hvpic_gather_push(ctx.ctx, p, dev(E), dev(B), nd, Jd)
+    pushed = p.to_numpy()
+    cs = torch.zeros(cfg.ncell + 1, dtype=torch.int32, device="cuda")
+    H.hvpic_sort(ctx.ctx, p, q, dev(cs0, np.int32), cs, full=False)
+    ref = O.particles64(parts)
+    O.push(cfg, ref, E, B)
+    compare_particles(cfg, pushed, ref)
+    _check_sorted(cfg, pushed, q.to_numpy(), cs.cpu().numpy())
+    rn, rJ = O.deposit(cfg, ref, 0.5 * cfg.dt)
+    assert rel_l2(nd.cpu().numpy(), rn) < 1e-5 and rel_l2(Jd.cpu().numpy(), rJ) < 1e-5
+
+
+def test_dense_single_cell(H):
+    """All particles in one cell: the neighbour sort's one-wavefront-per-cell
+    loop and the deposit window see one long segment."""
+    cfg = cfg2(nx=9, ny=8)
+    announce("dense")
+    rng = np.random.Generator(np.random.PCG64(5))
+    n = 20000
+    parts = {"cell": np.full(n, 40, np.int32),
+             "ox": W._offsets(rng.uniform(-1, 1, n)),
+             "oy": W._offsets(rng.uniform(-1, 1, n)),
+             "ux": rng.uniform(-4, 4, n).astype(np.float32),
+             "uy": rng.uniform(-2, 2, n).astype(np.float32),
+             "uz": rng.uniform(-1, 1, n).astype(np.float32),
+             "w": np.full(n, 1e-3, np.float32)}
+    _, _, B = W.random_box(6, cfg, 1.0)
+    E = W.random_field(7, cfg, 0.1)
+    cs0 = np.zeros(cfg.ncell + 1, np.int32)
+    cs0[41:] = n
+    ctx = H.Context(cfg, n)
+    p = H.Particles.from_numpy(parts, 2)
+    q = H.Particles(2, n)
+    nd = torch.zeros(cfg.ncell, device="cuda")
+    Jd = torch.zeros((3, cfg.ncell), device="cuda")
+    H.hvpic_gather_push(ctx.ctx, p, dev(E), dev(B), nd, Jd)
+    pushed = p.to_numpy()
+    cs = torch.zeros(cfg.ncell + 1, dtype=torch.int32, device="cuda")
+    H.hvpic_sort(ctx.ctx, p, q, dev(cs0), cs, full=False)
+    _check_sorted(cfg, pushed, q.to_numpy(), cs.cpu().numpy())
+    ref = O.particles64(parts)
+    O.push(cfg, ref, E, B)
+    rn, rJ = O.deposit(cfg, ref, 0.5 * cfg.dt)
+    assert rel_l2(nd.cpu().numpy(), rn) < 1e-5 and rel_l2(Jd.cpu().numpy(), rJ) < 1e-5
