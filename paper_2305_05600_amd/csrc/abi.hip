@@ -48,12 +48,14 @@ bool parts_ok(const hvpic_ctx* c, const hvpic_particles* q, bool need_w) {
 
 bool ctx_ok(const hvpic_ctx* c) { return c && c->magic == kMagic; }
 
-__global__ void k_init_ws(Status* st, double* a, double* b, int n) {
+__global__ void k_init_ws(Status* st, double* a, double* b, int n, double* mom, int64_t nmom) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  for (int64_t q = i; q < nmom; q += (int64_t)gridDim.x * blockDim.x) mom[q] = 0.0;
   if (i == 0) {
     st->flags = 0;
     st->moved_gt1 = st->nonfinite = st->floor_hits = st->bad_input = 0;
-    st->sort_fallback = 0;
+    st->far_flag = 0;
+    st->far_decision = 0;
     st->done_push = st->done_field = 0;
   }
   if (i < n) {
@@ -90,6 +92,7 @@ Layout workspace_layout(const hvpic_params* p) {
   L.rval1 = off;     off += align256(sizeof(uint32_t) * cap);
   L.rhist = off;     off += align256(sizeof(uint32_t) * kRadixBins * ntiles);
   L.fscratch = off;  off += align256(sizeof(float) * 16 * nc);
+  L.mom_acc = off;   off += align256(sizeof(double) * 4 * nc);
   L.total = off;
   return L;
 }
@@ -119,7 +122,6 @@ int hvpic_init(const hvpic_params* params, void* hip_stream, void* workspace, hv
   c->ws_bytes = L.total;
   c->ncell = params->nx * params->ny * params->nz;
   c->magic = kMagic;
-  c->sort_gen = 0;
   const double qm = params->qs / params->ms;
   c->a = (float)(0.5 * qm * params->dt);
   c->kx = (float)(2.0 * params->dt / params->dx);
@@ -139,9 +141,10 @@ int hvpic_init(const hvpic_params* params, void* hip_stream, void* workspace, hv
   c->rval[1] = (uint32_t*)(c->ws + L.rval1);
   c->rhist = (uint32_t*)(c->ws + L.rhist);
   c->fscratch = (float*)(c->ws + L.fscratch);
+  c->mom_acc = (double*)(c->ws + L.mom_acc);
   const int n = 4 * kDiagSlots;
   hipLaunchKernelGGL(k_init_ws, dim3((n + 255) / 256), dim3(256), 0, c->stream, c->status,
-                     c->diag_acc, c->field_acc, n);
+                     c->diag_acc, c->field_acc, n, c->mom_acc, 4ll * c->ncell);
   if (hipGetLastError() != hipSuccess) {
     delete c;
     return HVPIC_EHIP;

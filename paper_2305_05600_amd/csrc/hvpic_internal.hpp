@@ -38,10 +38,10 @@ struct Status {
   unsigned long long nonfinite;
   unsigned long long floor_hits;
   unsigned long long bad_input;
-  uint32_t sort_fallback;   // set by the neighbour-move sort when a far mover is seen
+  uint32_t far_flag;        // set by the neighbour-move count kernel on a far mover
+  uint32_t far_decision;    // far_flag handed to the scatter kernel (and far_flag cleared)
   uint32_t done_push;       // last-block counters of the FP64 reductions
   uint32_t done_field;
-  uint32_t pad2;
 };
 
 __device__ __forceinline__ void raise_flag(Status* st, uint32_t bit, unsigned long long* counter) {
@@ -59,7 +59,6 @@ struct hvpic_ctx {
   size_t ws_bytes;
   int32_t ncell;
   int32_t magic;
-  uint32_t sort_gen;   // generation tag of the last hvpic_sort call
   // derived constants (FP32 as the kernels use them)
   float a;           // (qs/ms) dt / 2
   float kx, ky, kz;  // 2 dt / (dx, dy, dz): half-cells per unit speed per step
@@ -75,6 +74,7 @@ struct hvpic_ctx {
   uint32_t* rval[2];     // radix values [np_capacity]
   uint32_t* rhist;       // radix per-block digit counts
   float* fscratch;       // field scratch [16][ncell]
+  double* mom_acc;       // FP64 moment accumulators [4][ncell], kept at zero between deposits
 };
 
 namespace hvpic {
@@ -98,7 +98,7 @@ int launch_init_workspace(hvpic_ctx* c);
 // Workspace layout (bytes from the start; each region 256-byte aligned).
 struct Layout {
   size_t status, diag_acc, field_acc, sort_cnt, sort_blk, rkey0, rkey1, rval0, rval1, rhist,
-      fscratch, total;
+      fscratch, mom_acc, total;
 };
 Layout workspace_layout(const hvpic_params* p);
 

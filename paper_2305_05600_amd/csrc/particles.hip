@@ -28,13 +28,19 @@
 namespace hvpic {
 namespace {
 
-constexpr int kPPT = 8;                   // particles per thread per chunk
-constexpr int kChunk = kBlock * kPPT;     // particles per block
 constexpr int kBands = 7;                 // band offsets -3..3
-constexpr int kWmax2 = 160;               // widest window (cells per band), 2D
-constexpr int kWmax3 = 40;                // 3D
+constexpr int kWmax2 = 96;                // widest window (cells per band), 2D
+constexpr int kWmax3 = 24;                // 3D
 constexpr int kWin2 = kBands * kWmax2 * 4;
 constexpr int kWin3 = kBands * kBands * kWmax3 * 4;
+
+// Particles per thread and per block: a 3D chunk spans more bands, so it is
+// kept shorter to keep its window small.
+template <int NDIM>
+struct Chunk {
+  static constexpr int PPT = NDIM == 2 ? 8 : 4;
+  static constexpr int N = kBlock * PPT;
+};
 constexpr int kGroupMin = 6;              // smallest lane group worth a reduction
 
 struct Geo {
@@ -54,8 +60,7 @@ struct PushArgs {
   const float* __restrict__ w;
   const float* __restrict__ E;
   const float* __restrict__ B;
-  float* __restrict__ dn;   // fused deposit: n at x^{n+1/2}
-  float* __restrict__ dJ;   // fused deposit: J at x^{n+1/2}
+  double* __restrict__ acc;  // fused deposit: FP64 moments [4][ncell] (n, Jx, Jy, Jz)
   Geo g;
   float a;                  // (q/m) dt / 2
   float kx, ky, kz;         // full-step displacement per unit speed (half-cells)
@@ -76,8 +81,7 @@ struct DepArgs {
   const float* __restrict__ uy;
   const float* __restrict__ uz;
   const float* __restrict__ w;
-  float* __restrict__ dn;
-  float* __restrict__ dJ;
+  double* __restrict__ acc;  // FP64 moments [4][ncell]
   Geo g;
   float bx, by, bz;         // displacement of the deposit point per unit speed
   float qV;
@@ -225,9 +229,8 @@ __device__ __forceinline__ float row_sum(float v) {
 template <int NDIM, int SHAPE>
 __device__ __forceinline__ void deposit_lane(bool live, bool inwin, int rel, int i, int j, int k,
                                              int mx, int my, int mz, float x, float y, float z,
-                                             float q, float vx, float vy, float vz, float* win,
-                                             int W, const Geo& g, float* __restrict__ dn,
-                                             float* __restrict__ dJ) {
+                                             float q, float vx, float vy, float vz, double* win,
+                                             int W, const Geo& g, double* __restrict__ acc) {
   constexpr int T = Stencil<NDIM, SHAPE>::T;
   float wt[T];
   int sx[T], sy[T], sz[T];
@@ -266,10 +269,10 @@ __device__ __forceinline__ void deposit_lane(bool live, bool inwin, int rel, int
       const float s2 = row_sum(nq * vy);
       const float s3 = row_sum(nq * vz);
       if (adder) {
-        atomicAdd(win + slot[t] + 0, s0);
-        atomicAdd(win + slot[t] + 1, s1);
-        atomicAdd(win + slot[t] + 2, s2);
-        atomicAdd(win + slot[t] + 3, s3);
+        atomicAdd(win + slot[t] + 0, (double)s0);
+        atomicAdd(win + slot[t] + 1, (double)s1);
+        atomicAdd(win + slot[t] + 2, (double)s2);
+        atomicAdd(win + slot[t] + 3, (double)s3);
       }
     }
     pend &= ~members;
@@ -278,10 +281,10 @@ __device__ __forceinline__ void deposit_lane(bool live, bool inwin, int rel, int
 #pragma unroll
     for (int t = 0; t < T; ++t) {
       const float nq = q * wt[t];
-      atomicAdd(win + slot[t] + 0, nq);
-      atomicAdd(win + slot[t] + 1, nq * vx);
-      atomicAdd(win + slot[t] + 2, nq * vy);
-      atomicAdd(win + slot[t] + 3, nq * vz);
+      atomicAdd(win + slot[t] + 0, (double)nq);
+      atomicAdd(win + slot[t] + 1, (double)(nq * vx));
+      atomicAdd(win + slot[t] + 2, (double)(nq * vy));
+      atomicAdd(win + slot[t] + 3, (double)(nq * vz));
     }
   }
   if (live && !inwin) {
@@ -291,10 +294,10 @@ __device__ __forceinline__ void deposit_lane(bool live, bool inwin, int rel, int
       const int c = wrapi(i + mx + sx[t], g.nx) +
                     g.nx * (wrapi(j + my + sy[t], g.ny) + g.ny * wrapi(k + mz + sz[t], g.nz));
       const float nq = q * wt[t];
-      unsafeAtomicAdd(dn + c, nq);
-      unsafeAtomicAdd(dJ + c, nq * vx);
-      unsafeAtomicAdd(dJ + nc + c, nq * vy);
-      unsafeAtomicAdd(dJ + 2 * nc + c, nq * vz);
+      unsafeAtomicAdd(acc + c, (double)nq);
+      unsafeAtomicAdd(acc + nc + c, (double)(nq * vx));
+      unsafeAtomicAdd(acc + 2 * nc + c, (double)(nq * vy));
+      unsafeAtomicAdd(acc + 3 * nc + c, (double)(nq * vz));
     }
   }
 }
@@ -314,12 +317,12 @@ __device__ __forceinline__ int window_len(int W) {
 }
 
 template <int NDIM>
-__device__ void window_flush(const float* win, int W, int c0, const Geo& g, float* __restrict__ dn,
-                             float* __restrict__ dJ) {
+__device__ void window_flush(const double* win, int W, int c0, const Geo& g,
+                             double* __restrict__ acc) {
   const int len = window_len<NDIM>(W);
   for (int s = threadIdx.x; s < len; s += kBlock) {
-    const float v = win[s];
-    if (v == 0.0f) continue;
+    const double v = win[s];
+    if (v == 0.0) continue;
     const int ch = s & 3;
     const int cellslot = s >> 2;
     const int band = cellslot / W;
@@ -329,8 +332,7 @@ __device__ void window_flush(const float* win, int W, int c0, const Geo& g, floa
     int64_t c = (int64_t)c0 - 2 + off + (int64_t)by * g.nx + (int64_t)bz * g.nxny;
     c %= g.ncell;
     if (c < 0) c += g.ncell;
-    float* dst = ch == 0 ? dn + c : dJ + (int64_t)(ch - 1) * g.ncell + c;
-    unsafeAtomicAdd(dst, v);
+    unsafeAtomicAdd(acc + (int64_t)ch * g.ncell + c, v);
   }
 }
 
@@ -387,11 +389,12 @@ __device__ void reduce_finalize(double* v, double* acc, uint32_t* done, double* 
 
 template <int NDIM, int SHAPE, bool DEP>
 __global__ __launch_bounds__(kBlock) void k_gather_push(PushArgs A) {
-  __shared__ float win[DEP ? (NDIM == 2 ? kWin2 : kWin3) : 1];
+  constexpr int PPT = Chunk<NDIM>::PPT;
+  __shared__ double win[DEP ? (NDIM == 2 ? kWin2 : kWin3) : 1];
   __shared__ int s_c[2];
   const Geo& g = A.g;
-  const int64_t base = (int64_t)blockIdx.x * kChunk;
-  const int64_t end = min(base + (int64_t)kChunk, A.n);
+  const int64_t base = (int64_t)blockIdx.x * Chunk<NDIM>::N;
+  const int64_t end = min(base + (int64_t)Chunk<NDIM>::N, A.n);
 
   int W = 0, c0 = 0;
   bool wok = false;
@@ -404,13 +407,13 @@ __global__ __launch_bounds__(kBlock) void k_gather_push(PushArgs A) {
     c0 = s_c[0];
     wok = window_ok<NDIM>(c0, s_c[1], g, W);
     if (wok)
-      for (int s = threadIdx.x; s < window_len<NDIM>(W); s += kBlock) win[s] = 0.0f;
+      for (int s = threadIdx.x; s < window_len<NDIM>(W); s += kBlock) win[s] = 0.0;
     __syncthreads();
   }
 
   const bool want_diag = A.diag_out != nullptr;
   double dK = 0.0, dP[3] = {0.0, 0.0, 0.0};
-  for (int it = 0; it < kPPT; ++it) {
+  for (int it = 0; it < PPT; ++it) {
     const int64_t idx = base + (int64_t)it * kBlock + threadIdx.x;
     bool live = idx < end;
     int a = 0;
@@ -501,7 +504,7 @@ __global__ __launch_bounds__(kBlock) void k_gather_push(PushArgs A) {
       const bool inwin = wok && rel >= 0 && rel + 5 <= W && mx >= -1 && mx <= 1 && my >= -1 &&
                          my <= 1 && mz >= -1 && mz <= 1;
       deposit_lane<NDIM, SHAPE>(live, inwin, rel, i, j, k, mx, my, mz, xm, ym, zm, A.qV * wq, vx,
-                                vy, vz, win, W, g, A.dn, A.dJ);
+                                vy, vz, win, W, g, A.acc);
     }
   }
   if (want_diag) {
@@ -510,17 +513,18 @@ __global__ __launch_bounds__(kBlock) void k_gather_push(PushArgs A) {
   }
   if (DEP && wok) {
     __syncthreads();
-    window_flush<NDIM>(win, W, c0, g, A.dn, A.dJ);
+    window_flush<NDIM>(win, W, c0, g, A.acc);
   }
 }
 
 template <int NDIM, int SHAPE>
 __global__ __launch_bounds__(kBlock) void k_deposit(DepArgs A) {
-  __shared__ float win[NDIM == 2 ? kWin2 : kWin3];
+  constexpr int PPT = Chunk<NDIM>::PPT;
+  __shared__ double win[NDIM == 2 ? kWin2 : kWin3];
   __shared__ int s_c[2];
   const Geo& g = A.g;
-  const int64_t base = (int64_t)blockIdx.x * kChunk;
-  const int64_t end = min(base + (int64_t)kChunk, A.n);
+  const int64_t base = (int64_t)blockIdx.x * Chunk<NDIM>::N;
+  const int64_t end = min(base + (int64_t)Chunk<NDIM>::N, A.n);
   if (threadIdx.x == 0) {
     s_c[0] = A.cell[base];
     s_c[1] = A.cell[end - 1];
@@ -530,9 +534,9 @@ __global__ __launch_bounds__(kBlock) void k_deposit(DepArgs A) {
   int W = 0;
   const bool wok = window_ok<NDIM>(c0, s_c[1], g, W);
   if (wok)
-    for (int s = threadIdx.x; s < window_len<NDIM>(W); s += kBlock) win[s] = 0.0f;
+    for (int s = threadIdx.x; s < window_len<NDIM>(W); s += kBlock) win[s] = 0.0;
   __syncthreads();
-  for (int it = 0; it < kPPT; ++it) {
+  for (int it = 0; it < PPT; ++it) {
     const int64_t idx = base + (int64_t)it * kBlock + threadIdx.x;
     bool live = idx < end;
     int a = 0, i = 0, j = 0, k = 0, mx = 0, my = 0, mz = 0;
@@ -567,11 +571,11 @@ __global__ __launch_bounds__(kBlock) void k_deposit(DepArgs A) {
     const bool inwin = wok && rel >= 0 && rel + 5 <= W && mx >= -1 && mx <= 1 && my >= -1 &&
                        my <= 1 && mz >= -1 && mz <= 1;
     deposit_lane<NDIM, SHAPE>(live, inwin, rel, i, j, k, mx, my, mz, x, y, z, q, vx, vy, vz, win,
-                              W, g, A.dn, A.dJ);
+                              W, g, A.acc);
   }
   if (wok) {
     __syncthreads();
-    window_flush<NDIM>(win, W, c0, g, A.dn, A.dJ);
+    window_flush<NDIM>(win, W, c0, g, A.acc);
   }
 }
 
@@ -582,6 +586,21 @@ __global__ void k_zero(float* __restrict__ a, int64_t na, float* __restrict__ b,
       a[i] = 0.0f;
     else
       b[i - na] = 0.0f;
+  }
+}
+
+// FP64 moment accumulators -> FP32 outputs; leaves the accumulators at zero
+// for the next deposit.
+__global__ void k_moments_out(double* __restrict__ acc, int ncell, float* __restrict__ n,
+                              float* __restrict__ J) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < 4ll * ncell; i += stride) {
+    const float v = (float)acc[i];
+    acc[i] = 0.0;
+    if (i < ncell)
+      n[i] = v;
+    else
+      J[i - ncell] = v;
   }
 }
 
@@ -621,15 +640,18 @@ int zero2(hvpic_ctx* c, float* a, int64_t na, float* b, int64_t nb) {
 
 int launch_zero(hvpic_ctx* c, float* p, int64_t count) { return zero2(c, p, count, nullptr, 0); }
 
+void moments_out(hvpic_ctx* c, float* n, float* J) {
+  const int blocks = (int)std::min<int64_t>(ceil_div(4ll * c->ncell, kBlock), 2048);
+  hipLaunchKernelGGL(k_moments_out, dim3(blocks), dim3(kBlock), 0, c->stream, c->mom_acc,
+                     c->ncell, n, J);
+}
+
 int launch_gather_push(hvpic_ctx* c, hvpic_particles* p, const float* E, const float* B,
                        float* n_mid, float* J_mid, double* diag_out) {
   const bool dep = n_mid != nullptr && J_mid != nullptr;
-  if (dep) {
-    int rc = zero2(c, n_mid, c->ncell, J_mid, 3ll * c->ncell);
-    if (rc) return rc;
-  }
   if (p->n == 0) {
     if (diag_out) hipLaunchKernelGGL(k_write_zero_diag, dim3(1), dim3(64), 0, c->stream, diag_out, 4);
+    if (dep) moments_out(c, n_mid, J_mid);
     return hipGetLastError() == hipSuccess ? HVPIC_OK : HVPIC_EHIP;
   }
   PushArgs A;
@@ -644,8 +666,7 @@ int launch_gather_push(hvpic_ctx* c, hvpic_particles* p, const float* E, const f
   A.w = p->w;
   A.E = E;
   A.B = B;
-  A.dn = n_mid;
-  A.dJ = J_mid;
+  A.acc = c->mom_acc;
   A.g = make_geo(c);
   A.a = c->a;
   A.kx = c->kx;
@@ -656,22 +677,26 @@ int launch_gather_push(hvpic_ctx* c, hvpic_particles* p, const float* E, const f
   A.diag_out = diag_out;
   A.diag_acc = c->diag_acc;
   A.st = c->status;
-  const dim3 grid((unsigned)ceil_div(p->n, kChunk));
   const bool qs = c->p.shape == HVPIC_SHAPE_QS;
   if (c->p.ndim == 2) {
+    const dim3 grid((unsigned)ceil_div(p->n, Chunk<2>::N));
     if (qs) push_dispatch<2, HVPIC_SHAPE_QS>(dep, grid, c->stream, A);
     else push_dispatch<2, HVPIC_SHAPE_NGP>(dep, grid, c->stream, A);
   } else {
+    const dim3 grid((unsigned)ceil_div(p->n, Chunk<3>::N));
     if (qs) push_dispatch<3, HVPIC_SHAPE_QS>(dep, grid, c->stream, A);
     else push_dispatch<3, HVPIC_SHAPE_NGP>(dep, grid, c->stream, A);
   }
+  if (dep) moments_out(c, n_mid, J_mid);
   return hipGetLastError() == hipSuccess ? HVPIC_OK : HVPIC_EHIP;
 }
 
 int launch_deposit(hvpic_ctx* c, const hvpic_particles* p, float half_dt_back, float* n,
                    float* J) {
-  int rc = zero2(c, n, c->ncell, J, 3ll * c->ncell);
-  if (rc || p->n == 0) return rc;
+  if (p->n == 0) {
+    moments_out(c, n, J);
+    return hipGetLastError() == hipSuccess ? HVPIC_OK : HVPIC_EHIP;
+  }
   DepArgs A;
   A.n = p->n;
   A.cell = p->cell;
@@ -682,8 +707,7 @@ int launch_deposit(hvpic_ctx* c, const hvpic_particles* p, float half_dt_back, f
   A.uy = p->uy;
   A.uz = p->uz;
   A.w = p->w;
-  A.dn = n;
-  A.dJ = J;
+  A.acc = c->mom_acc;
   A.g = make_geo(c);
   // x - half_dt_back v in half-cell units: offset change -2 half_dt_back v / h.
   A.bx = (float)(-2.0 * (double)half_dt_back / c->p.dx);
@@ -691,15 +715,17 @@ int launch_deposit(hvpic_ctx* c, const hvpic_particles* p, float half_dt_back, f
   A.bz = (float)(-2.0 * (double)half_dt_back / c->p.dz);
   A.qV = c->qV;
   A.st = c->status;
-  const dim3 grid((unsigned)ceil_div(p->n, kChunk));
   const bool qs = c->p.shape == HVPIC_SHAPE_QS;
   if (c->p.ndim == 2) {
+    const dim3 grid((unsigned)ceil_div(p->n, Chunk<2>::N));
     if (qs) hipLaunchKernelGGL((k_deposit<2, HVPIC_SHAPE_QS>), grid, dim3(kBlock), 0, c->stream, A);
     else hipLaunchKernelGGL((k_deposit<2, HVPIC_SHAPE_NGP>), grid, dim3(kBlock), 0, c->stream, A);
   } else {
+    const dim3 grid((unsigned)ceil_div(p->n, Chunk<3>::N));
     if (qs) hipLaunchKernelGGL((k_deposit<3, HVPIC_SHAPE_QS>), grid, dim3(kBlock), 0, c->stream, A);
     else hipLaunchKernelGGL((k_deposit<3, HVPIC_SHAPE_NGP>), grid, dim3(kBlock), 0, c->stream, A);
   }
+  moments_out(c, n, J);
   return hipGetLastError() == hipSuccess ? HVPIC_OK : HVPIC_EHIP;
 }
 

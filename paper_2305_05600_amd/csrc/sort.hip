@@ -17,14 +17,17 @@
 // slot adds its rank among the earlier particles of its own group, found with
 // wavefront ballots.  Kernels: count (one wavefront per old cell), tile totals
 // of the new counts, scan of tile totals, per-cell prefix + group bases,
-// scatter (one wavefront per old cell).  A particle that moved further is
-// detected by the count kernel; the general sort then runs instead (its
-// kernels are always enqueued and return at once unless that happened).
+// scatter (one wavefront per old cell).  A particle that moved further (or an
+// inconsistent cell_start) is flagged by the count kernel; the flag is handed
+// to the scatter kernel, in which one block then runs the general sort on its
+// own (slow, but it costs no extra launch in the common case and needs no host
+// round trip).
 //
 // General path.  LSD radix sort of (cell, index) pairs with 8-bit digits;
 // each pass is a per-tile digit histogram, a scan of the digit-major
 // histogram, and a stable scatter whose in-tile ranks come from per-wavefront
-// match masks.  The permutation then gathers the particle fields.
+// match masks.  The permutation then gathers the particle fields.  The same
+// tile ranking drives the single-block fallback.
 #include "hvpic_internal.hpp"
 
 namespace hvpic {
@@ -105,7 +108,7 @@ template <int NDIM>
 __global__ __launch_bounds__(kBlock) void k_nb_count(const int32_t* __restrict__ key,
                                                      const int32_t* __restrict__ cs_prev, int64_t n,
                                                      SortGeo g, uint32_t* __restrict__ cnt,
-                                                     Status* st, uint32_t gen) {
+                                                     Status* st) {
   constexpr int ND = Dirs<NDIM>::N, NB = Dirs<NDIM>::BITS;
   const int a = blockIdx.x * kWaves + (threadIdx.x >> 6);
   if (a >= g.ncell) return;
@@ -114,7 +117,7 @@ __global__ __launch_bounds__(kBlock) void k_nb_count(const int32_t* __restrict__
   if (s0 < 0 || s1 > n || s1 < s0) {
     if (lane == 0) {
       raise_flag(st, HVPIC_FLAG_BAD_INPUT, &st->bad_input);
-      __hip_atomic_store(&st->sort_fallback, gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&st->far_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     s0 = s1 = 0;
   }
@@ -136,8 +139,10 @@ __global__ __launch_bounds__(kBlock) void k_nb_count(const int32_t* __restrict__
     for (int b = 0; b < NB; ++b) bal[b] = __ballot(valid && d >= 0 && ((d >> b) & 1));
     if (lane < ND) count += (uint32_t)__builtin_popcountll(match_code<NB>(lane, vmask, bal));
   }
-  if (__ballot(far) && lane == 0)
-    __hip_atomic_store(&st->sort_fallback, gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (__ballot(far) && lane == 0) {
+    atomicOr(&st->flags, (uint32_t)HVPIC_FLAG_MOVE_GT1);
+    __hip_atomic_store(&st->far_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
   if (lane < ND) cnt[(int64_t)a * ND + lane] = count;
 }
 
@@ -182,9 +187,14 @@ __device__ uint32_t tile_exclusive_scan(uint32_t* s) {
 template <int NDIM>
 __global__ __launch_bounds__(kBlock) void k_nb_newcount(const uint32_t* __restrict__ cnt, SortGeo g,
                                                         int32_t* __restrict__ cs,
-                                                        uint32_t* __restrict__ blk) {
+                                                        uint32_t* __restrict__ blk, Status* st) {
   constexpr int ND = Dirs<NDIM>::N;
   __shared__ uint32_t wsum[kWaves];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    const uint32_t f = __hip_atomic_load(&st->far_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&st->far_decision, f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&st->far_flag, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
   const int64_t t0 = (int64_t)blockIdx.x * kScanTile;
   uint32_t local = 0;
   for (int q = 0; q < kScanTile / kBlock; ++q) {
@@ -281,19 +291,226 @@ __global__ __launch_bounds__(kBlock) void k_nb_bases(uint32_t* __restrict__ cnt,
   }
 }
 
+
 struct Fields {
   int32_t* cell;
   float* f[7];  // ox, oy, oz, ux, uy, uz, w (oz may be null)
 };
 
+// ------------------------------------------------------------- radix path --
+
+// Stable destination of this thread's element in a block-wide tile whose
+// elements are ordered by thread index.  run[b] is the first free slot of
+// digit b and is advanced past the tile.  Every thread of the block calls it.
+__device__ uint32_t tile_dest(bool valid, int digit, uint32_t (*wcnt)[kRadixBins], uint32_t* run) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int nw = blockDim.x >> 6;
+  for (int b = threadIdx.x; b < nw * kRadixBins; b += blockDim.x) (&wcnt[0][0])[b] = 0;
+  __syncthreads();
+  uint64_t bal[kRadixBits];
+  const uint64_t vmask = __ballot(valid);
+#pragma unroll
+  for (int b = 0; b < kRadixBits; ++b) bal[b] = __ballot(valid && ((digit >> b) & 1));
+  const uint64_t mine = match_code<kRadixBits>(digit, vmask, bal);
+  const uint32_t rank = (uint32_t)__builtin_popcountll(mine & lanemask_lt());
+  if (valid && rank == 0) wcnt[wid][digit] = (uint32_t)__builtin_popcountll(mine);
+  __syncthreads();
+  uint32_t dst = 0;
+  if (valid) {
+    uint32_t before = run[digit];
+    for (int w = 0; w < wid; ++w) before += wcnt[w][digit];
+    dst = before + rank;
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < kRadixBins; b += blockDim.x) {
+    uint32_t s = 0;
+    for (int w = 0; w < nw; ++w) s += wcnt[w][b];
+    run[b] += s;
+  }
+  __syncthreads();
+  return dst;
+}
+
+__device__ __forceinline__ uint32_t load_key(const uint32_t* kin, const int32_t* cells, int64_t i,
+                                             int ncell) {
+  uint32_t key = kin ? kin[i] : (uint32_t)cells[i];
+  return key >= (uint32_t)ncell ? (uint32_t)ncell - 1 : key;  // invalid cells were flagged upstream
+}
+
+// Sorted-order gather of the particle fields plus cell_start from the sorted
+// keys: the boundary between positions r-1 and r fills the starts of the cells
+// in (key[r-1], key[r]].  Threads start at `first` and step by `stride`.
+__device__ void gather_fields(const uint32_t* keys, const uint32_t* perm, int64_t n, Fields in,
+                              Fields out, int32_t* cs, int ncell, int64_t first, int64_t stride) {
+  for (int64_t r = first; r <= n; r += stride) {
+    const int kprev = r == 0 ? -1 : (int)(keys ? keys[r - 1] : 0u);
+    const int knext = r == n ? ncell : (int)(keys ? keys[r] : 0u);
+    for (int c = kprev + 1; c <= knext && c <= ncell; ++c) cs[c] = (int32_t)r;
+    if (r < n) {
+      const uint32_t src = perm ? perm[r] : (uint32_t)r;
+      out.cell[r] = in.cell[src];
+#pragma unroll
+      for (int f = 0; f < 7; ++f)
+        if (in.f[f]) out.f[f][r] = in.f[f][src];
+    }
+  }
+}
+
+// Per-tile histogram of one digit; hist is digit-major [bin][tile].
+__global__ __launch_bounds__(kBlock) void k_radix_hist(const uint32_t* __restrict__ keys,
+                                                       const int32_t* __restrict__ cells, int64_t n,
+                                                       int shift, uint32_t* __restrict__ hist,
+                                                       int ntiles, int ncell) {
+  __shared__ uint32_t h[kRadixBins];
+  for (int b = threadIdx.x; b < kRadixBins; b += kBlock) h[b] = 0;
+  __syncthreads();
+  const int64_t t0 = (int64_t)blockIdx.x * kRadixTile;
+  for (int q = 0; q < kRadixItems; ++q) {
+    const int64_t idx = t0 + q * kBlock + threadIdx.x;
+    if (idx < n) atomicAdd(&h[(load_key(keys, cells, idx, ncell) >> shift) & (kRadixBins - 1)], 1u);
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < kRadixBins; b += kBlock) hist[(int64_t)b * ntiles + blockIdx.x] = h[b];
+}
+
+// Generic 3-kernel exclusive scan of a uint32 array (tile sums, scan of the
+// tile sums in k_scan_tiles, tile scans plus offsets).
+__global__ __launch_bounds__(kBlock) void k_scan_reduce(const uint32_t* __restrict__ v, int64_t m,
+                                                        uint32_t* __restrict__ blk) {
+  __shared__ uint32_t wsum[kWaves];
+  const int64_t t0 = (int64_t)blockIdx.x * kScanTile;
+  uint32_t local = 0;
+  for (int q = 0; q < kScanTile / kBlock; ++q) {
+    const int64_t i = t0 + q * kBlock + threadIdx.x;
+    if (i < m) local += v[i];
+  }
+  for (int o = 32; o > 0; o >>= 1) local += __shfl_xor(local, o);
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = local;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t s = 0;
+    for (int w = 0; w < kWaves; ++w) s += wsum[w];
+    blk[blockIdx.x] = s;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_apply(uint32_t* __restrict__ v, int64_t m,
+                                                       const uint32_t* __restrict__ blk) {
+  __shared__ uint32_t s[kScanTile];
+  const int64_t t0 = (int64_t)blockIdx.x * kScanTile;
+  for (int q = 0; q < kScanTile / kBlock; ++q) {
+    const int64_t i = t0 + q * kBlock + threadIdx.x;
+    s[q * kBlock + threadIdx.x] = i < m ? v[i] : 0u;
+  }
+  __syncthreads();
+  tile_exclusive_scan(s);
+  const uint32_t off = blk[blockIdx.x];
+  for (int q = 0; q < kScanTile / kBlock; ++q) {
+    const int64_t i = t0 + q * kBlock + threadIdx.x;
+    if (i < m) v[i] = off + s[q * kBlock + threadIdx.x];
+  }
+}
+
+// Stable scatter of one digit.  Within a tile the order is item-major:
+// element (q, t) is tile[q*kBlock + t], matching the global index order.
+__global__ __launch_bounds__(kBlock) void k_radix_scatter(
+    const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
+    const int32_t* __restrict__ cells, int64_t n, int shift, const uint32_t* __restrict__ offs,
+    int ntiles, uint32_t* __restrict__ kout, uint32_t* __restrict__ vout, int ncell) {
+  __shared__ uint32_t wcnt[kWaves][kRadixBins];
+  __shared__ uint32_t run[kRadixBins];
+  for (int b = threadIdx.x; b < kRadixBins; b += kBlock)
+    run[b] = offs[(int64_t)b * ntiles + blockIdx.x];
+  const int64_t t0 = (int64_t)blockIdx.x * kRadixTile;
+  for (int q = 0; q < kRadixItems; ++q) {
+    const int64_t idx = t0 + q * kBlock + threadIdx.x;
+    const bool valid = idx < n;
+    uint32_t key = 0, val = 0;
+    if (valid) {
+      key = load_key(kin, cells, idx, ncell);
+      val = vin ? vin[idx] : (uint32_t)idx;
+    }
+    const uint32_t dst = tile_dest(valid, (key >> shift) & (kRadixBins - 1), wcnt, run);
+    if (valid) {
+      kout[dst] = key;
+      vout[dst] = val;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_radix_final(const uint32_t* __restrict__ keys,
+                                                        const uint32_t* __restrict__ perm, int64_t n,
+                                                        Fields in, Fields out, int32_t* cs,
+                                                        int ncell) {
+  gather_fields(keys, perm, n, in, out, cs, ncell, (int64_t)blockIdx.x * kBlock + threadIdx.x,
+                (int64_t)gridDim.x * kBlock);
+}
+
+// The whole stable sort by one block (fallback of the neighbour path).
+__device__ void block_sort(int64_t n, int ncell, Fields in, Fields out, int32_t* cs,
+                           uint32_t* const* rkey, uint32_t* const* rval) {
+  __shared__ uint32_t wcnt[kWaves][kRadixBins];
+  __shared__ uint32_t run[kRadixBins];
+  int bits = 0;
+  while (bits < 31 && (1ll << bits) < ncell) ++bits;
+  const int passes = (bits + kRadixBits - 1) / kRadixBits;
+  const uint32_t* kin = nullptr;
+  const uint32_t* vin = nullptr;
+  int cur = 0;
+  for (int pass = 0; pass < passes && n > 0; ++pass) {
+    const int shift = pass * kRadixBits;
+    for (int b = threadIdx.x; b < kRadixBins; b += blockDim.x) run[b] = 0;
+    __syncthreads();
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x)
+      atomicAdd(&run[(load_key(kin, in.cell, i, ncell) >> shift) & (kRadixBins - 1)], 1u);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint32_t acc = 0;
+      for (int b = 0; b < kRadixBins; ++b) {
+        const uint32_t v = run[b];
+        run[b] = acc;
+        acc += v;
+      }
+    }
+    __syncthreads();
+    for (int64_t t0 = 0; t0 < n; t0 += blockDim.x) {
+      const int64_t idx = t0 + threadIdx.x;
+      const bool valid = idx < n;
+      uint32_t key = 0, val = 0;
+      if (valid) {
+        key = load_key(kin, in.cell, idx, ncell);
+        val = vin ? vin[idx] : (uint32_t)idx;
+      }
+      const uint32_t dst = tile_dest(valid, (key >> shift) & (kRadixBins - 1), wcnt, run);
+      if (valid) {
+        rkey[cur][dst] = key;
+        rval[cur][dst] = val;
+      }
+    }
+    __threadfence();
+    __syncthreads();
+    kin = rkey[cur];
+    vin = rval[cur];
+    cur ^= 1;
+  }
+  gather_fields(kin, vin, n, in, out, cs, ncell, threadIdx.x, blockDim.x);
+}
+
 template <int NDIM>
 __global__ __launch_bounds__(kBlock) void k_nb_scatter(const int32_t* __restrict__ cs_prev, int64_t n,
                                                        SortGeo g, const uint32_t* __restrict__ bases,
-                                                       Fields in, Fields out, const Status* st,
-                                                       uint32_t gen) {
+                                                       Fields in, Fields out, int32_t* cs,
+                                                       const Status* st, uint32_t* rk0, uint32_t* rk1,
+                                                       uint32_t* rv0, uint32_t* rv1) {
   constexpr int ND = Dirs<NDIM>::N, NB = Dirs<NDIM>::BITS;
-  if (__hip_atomic_load(&st->sort_fallback, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen)
+  if (__hip_atomic_load(&st->far_decision, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+    if (blockIdx.x == 0) {
+      uint32_t* rkey[2] = {rk0, rk1};
+      uint32_t* rval[2] = {rv0, rv1};
+      block_sort(n, g.ncell, in, out, cs, rkey, rval);
+    }
     return;
+  }
   const int a = blockIdx.x * kWaves + (threadIdx.x >> 6);
   if (a >= g.ncell) return;
   const int lane = threadIdx.x & 63;
@@ -331,185 +548,6 @@ __global__ __launch_bounds__(kBlock) void k_nb_scatter(const int32_t* __restrict
   }
 }
 
-// ------------------------------------------------------------- radix path --
-
-__device__ __forceinline__ bool gate_closed(const Status* st, uint32_t gen, int forced) {
-  return !forced &&
-         __hip_atomic_load(&st->sort_fallback, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != gen;
-}
-
-// Per-tile histogram of one digit; hist is digit-major [bin][tile].
-__global__ __launch_bounds__(kBlock) void k_radix_hist(const uint32_t* __restrict__ keys,
-                                                       const int32_t* __restrict__ cells, int64_t n,
-                                                       int shift, uint32_t* __restrict__ hist,
-                                                       int ntiles, const Status* st, uint32_t gen,
-                                                       int forced, int ncell) {
-  if (gate_closed(st, gen, forced)) return;
-  __shared__ uint32_t h[kRadixBins];
-  for (int b = threadIdx.x; b < kRadixBins; b += kBlock) h[b] = 0;
-  __syncthreads();
-  const int64_t t0 = (int64_t)blockIdx.x * kRadixTile;
-  for (int q = 0; q < kRadixItems; ++q) {
-    const int64_t idx = t0 + q * kBlock + threadIdx.x;
-    if (idx < n) {
-      uint32_t key = keys ? keys[idx] : (uint32_t)cells[idx];
-      if (key >= (uint32_t)ncell) key = (uint32_t)ncell - 1;  // guarded upstream
-      atomicAdd(&h[(key >> shift) & (kRadixBins - 1)], 1u);
-    }
-  }
-  __syncthreads();
-  for (int b = threadIdx.x; b < kRadixBins; b += kBlock) hist[(int64_t)b * ntiles + blockIdx.x] = h[b];
-}
-
-// Generic 3-kernel exclusive scan of a uint32 array (tile sums / tile scans).
-__global__ __launch_bounds__(kBlock) void k_scan_reduce(const uint32_t* __restrict__ v, int64_t m,
-                                                        uint32_t* __restrict__ blk, const Status* st,
-                                                        uint32_t gen, int forced) {
-  if (gate_closed(st, gen, forced)) return;
-  __shared__ uint32_t wsum[kWaves];
-  const int64_t t0 = (int64_t)blockIdx.x * kScanTile;
-  uint32_t local = 0;
-  for (int q = 0; q < kScanTile / kBlock; ++q) {
-    const int64_t i = t0 + q * kBlock + threadIdx.x;
-    if (i < m) local += v[i];
-  }
-  for (int o = 32; o > 0; o >>= 1) local += __shfl_xor(local, o);
-  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = local;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t s = 0;
-    for (int w = 0; w < kWaves; ++w) s += wsum[w];
-    blk[blockIdx.x] = s;
-  }
-}
-
-__global__ __launch_bounds__(1024) void k_scan_tiles_gated(uint32_t* blk, int m, const Status* st,
-                                                           uint32_t gen, int forced) {
-  if (gate_closed(st, gen, forced)) return;
-  __shared__ uint32_t wsum[16];
-  __shared__ uint32_t carry;
-  if (threadIdx.x == 0) carry = 0;
-  __syncthreads();
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  for (int base = 0; base < m; base += 1024) {
-    const int idx = base + threadIdx.x;
-    const uint32_t val = idx < m ? blk[idx] : 0u;
-    uint32_t x = val;
-    for (int o = 1; o < 64; o <<= 1) {
-      const uint32_t y = __shfl_up(x, o);
-      if (lane >= o) x += y;
-    }
-    if (lane == 63) wsum[wid] = x;
-    __syncthreads();
-    uint32_t woff = 0, tot = 0;
-    for (int w = 0; w < 16; ++w) {
-      if (w < wid) woff += wsum[w];
-      tot += wsum[w];
-    }
-    const uint32_t c0 = carry;
-    if (idx < m) blk[idx] = c0 + woff + x - val;
-    __syncthreads();
-    if (threadIdx.x == 0) carry = c0 + tot;
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) blk[m] = carry;
-}
-
-__global__ __launch_bounds__(kBlock) void k_scan_apply(uint32_t* __restrict__ v, int64_t m,
-                                                       const uint32_t* __restrict__ blk,
-                                                       const Status* st, uint32_t gen, int forced) {
-  if (gate_closed(st, gen, forced)) return;
-  __shared__ uint32_t s[kScanTile];
-  const int64_t t0 = (int64_t)blockIdx.x * kScanTile;
-  for (int q = 0; q < kScanTile / kBlock; ++q) {
-    const int64_t i = t0 + q * kBlock + threadIdx.x;
-    s[q * kBlock + threadIdx.x] = i < m ? v[i] : 0u;
-  }
-  __syncthreads();
-  tile_exclusive_scan(s);
-  const uint32_t off = blk[blockIdx.x];
-  for (int q = 0; q < kScanTile / kBlock; ++q) {
-    const int64_t i = t0 + q * kBlock + threadIdx.x;
-    if (i < m) v[i] = off + s[q * kBlock + threadIdx.x];
-  }
-}
-
-// Stable scatter of one digit.  Within a tile the order is item-major:
-// element (q, t) is tile[q*kBlock + t], matching the global index order.
-__global__ __launch_bounds__(kBlock) void k_radix_scatter(
-    const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
-    const int32_t* __restrict__ cells, int64_t n, int shift, const uint32_t* __restrict__ offs,
-    int ntiles, uint32_t* __restrict__ kout, uint32_t* __restrict__ vout, const Status* st,
-    uint32_t gen, int forced, int ncell) {
-  if (gate_closed(st, gen, forced)) return;
-  __shared__ uint32_t wcnt[kWaves][kRadixBins];
-  __shared__ uint32_t run[kRadixBins];
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  for (int b = threadIdx.x; b < kRadixBins; b += kBlock)
-    run[b] = offs[(int64_t)b * ntiles + blockIdx.x];
-  const int64_t t0 = (int64_t)blockIdx.x * kRadixTile;
-  for (int q = 0; q < kRadixItems; ++q) {
-    for (int b = threadIdx.x; b < kWaves * kRadixBins; b += kBlock) (&wcnt[0][0])[b] = 0;
-    __syncthreads();
-    const int64_t idx = t0 + q * kBlock + threadIdx.x;
-    const bool valid = idx < n;
-    uint32_t key = 0, val = 0;
-    if (valid) {
-      key = kin ? kin[idx] : (uint32_t)cells[idx];
-      if (key >= (uint32_t)ncell) key = (uint32_t)ncell - 1;
-      val = vin ? vin[idx] : (uint32_t)idx;
-    }
-    const int digit = (key >> shift) & (kRadixBins - 1);
-    uint64_t bal[kRadixBits];
-    const uint64_t vmask = __ballot(valid);
-#pragma unroll
-    for (int b = 0; b < kRadixBits; ++b) bal[b] = __ballot(valid && ((digit >> b) & 1));
-    const uint64_t mine = match_code<kRadixBits>(digit, vmask, bal);
-    const uint32_t rank_in_wave = __builtin_popcountll(mine & lanemask_lt());
-    // the lowest lane of each digit group publishes the group size
-    if (valid && rank_in_wave == 0) wcnt[wid][digit] = __builtin_popcountll(mine);
-    __syncthreads();
-    if (valid) {
-      uint32_t before = run[digit];
-      for (int w = 0; w < wid; ++w) before += wcnt[w][digit];
-      const uint32_t dst = before + rank_in_wave;
-      kout[dst] = key;
-      vout[dst] = val;
-    }
-    __syncthreads();
-    for (int b = threadIdx.x; b < kRadixBins; b += kBlock) {
-      uint32_t s = 0;
-      for (int w = 0; w < kWaves; ++w) s += wcnt[w][b];
-      run[b] += s;
-    }
-    __syncthreads();
-  }
-}
-
-// Gathers the particle fields in sorted order and builds cell_start from the
-// sorted keys (every cell boundary between neighbours r-1 and r fills the
-// starts of the cells in (key[r-1], key[r]]).
-__global__ __launch_bounds__(kBlock) void k_radix_final(const uint32_t* __restrict__ keys,
-                                                        const uint32_t* __restrict__ perm, int64_t n,
-                                                        Fields in, Fields out, int32_t* cs,
-                                                        int ncell, const Status* st, uint32_t gen,
-                                                        int forced) {
-  if (gate_closed(st, gen, forced)) return;
-  const int64_t stride = (int64_t)gridDim.x * kBlock;
-  for (int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x; r <= n; r += stride) {
-    const int kprev = r == 0 ? -1 : (int)(keys ? keys[r - 1] : 0u);
-    const int knext = r == n ? ncell : (int)(keys ? keys[r] : 0u);
-    for (int c = kprev + 1; c <= knext && c <= ncell; ++c) cs[c] = (int32_t)r;
-    if (r < n) {
-      const uint32_t src = perm ? perm[r] : (uint32_t)r;
-      out.cell[r] = in.cell[src];
-#pragma unroll
-      for (int f = 0; f < 7; ++f)
-        if (in.f[f]) out.f[f][r] = in.f[f][src];
-    }
-  }
-}
-
 Fields fields_of(const hvpic_particles* p) {
   Fields f;
   f.cell = p->cell;
@@ -540,10 +578,7 @@ int radix_bits(int ncell) {
   return b;
 }
 
-// The general sort; `forced` = run unconditionally, else only when the
-// neighbour path raised the fallback generation `gen`.
-void enqueue_radix(hvpic_ctx* c, const hvpic_particles* in, hvpic_particles* out, int32_t* cs,
-                   uint32_t gen, int forced) {
+void enqueue_radix(hvpic_ctx* c, const hvpic_particles* in, hvpic_particles* out, int32_t* cs) {
   hipStream_t s = c->stream;
   const int64_t n = in->n;
   const int ncell = c->ncell;
@@ -554,46 +589,44 @@ void enqueue_radix(hvpic_ctx* c, const hvpic_particles* in, hvpic_particles* out
   int cur = 0;
   const int64_t m = (int64_t)kRadixBins * ntiles;
   const int mtiles = (int)ceil_div(m, kScanTile);
+  uint32_t* blk = (uint32_t*)c->sort_blk;
   for (int pass = 0; pass < passes && n > 0; ++pass) {
     const int shift = pass * kRadixBits;
     hipLaunchKernelGGL(k_radix_hist, dim3(ntiles), dim3(kBlock), 0, s, kin, in->cell, n, shift,
-                       c->rhist, ntiles, c->status, gen, forced, ncell);
-    hipLaunchKernelGGL(k_scan_reduce, dim3(mtiles), dim3(kBlock), 0, s, c->rhist, m,
-                       (uint32_t*)c->sort_blk, c->status, gen, forced);
-    hipLaunchKernelGGL(k_scan_tiles_gated, dim3(1), dim3(1024), 0, s, (uint32_t*)c->sort_blk,
-                       mtiles, c->status, gen, forced);
+                       c->rhist, ntiles, ncell);
+    hipLaunchKernelGGL(k_scan_reduce, dim3(mtiles), dim3(kBlock), 0, s, c->rhist, m, blk);
+    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, s, blk, mtiles);
     hipLaunchKernelGGL(k_scan_apply, dim3(mtiles), dim3(kBlock), 0, s, c->rhist, m,
-                       (const uint32_t*)c->sort_blk, c->status, gen, forced);
+                       (const uint32_t*)blk);
     hipLaunchKernelGGL(k_radix_scatter, dim3(ntiles), dim3(kBlock), 0, s, kin, vin, in->cell, n,
-                       shift, c->rhist, ntiles, c->rkey[cur], c->rval[cur], c->status, gen, forced,
-                       ncell);
+                       shift, c->rhist, ntiles, c->rkey[cur], c->rval[cur], ncell);
     kin = c->rkey[cur];
     vin = c->rval[cur];
     cur ^= 1;
   }
   const int fblocks = (int)std::min<int64_t>(ceil_div(n + 1, kBlock), 65536);
   hipLaunchKernelGGL(k_radix_final, dim3(fblocks), dim3(kBlock), 0, s, kin, vin, n, fields_of(in),
-                     fields_of(out), cs, ncell, c->status, gen, forced);
+                     fields_of(out), cs, ncell);
 }
 
 template <int NDIM>
 void enqueue_neighbour(hvpic_ctx* c, const hvpic_particles* in, hvpic_particles* out,
-                       const int32_t* cs_prev, int32_t* cs, uint32_t gen) {
+                       const int32_t* cs_prev, int32_t* cs) {
   hipStream_t s = c->stream;
   const SortGeo g = sort_geo(c);
   const int cblocks = (int)ceil_div(c->ncell, kWaves);
   const int tiles = (int)ceil_div(c->ncell, kScanTile);
   uint32_t* blk = (uint32_t*)c->sort_blk;
   hipLaunchKernelGGL((k_nb_count<NDIM>), dim3(cblocks), dim3(kBlock), 0, s, in->cell, cs_prev,
-                     in->n, g, c->sort_cnt, c->status, gen);
+                     in->n, g, c->sort_cnt, c->status);
   hipLaunchKernelGGL((k_nb_newcount<NDIM>), dim3(tiles), dim3(kBlock), 0, s,
-                     (const uint32_t*)c->sort_cnt, g, cs, blk);
+                     (const uint32_t*)c->sort_cnt, g, cs, blk, c->status);
   hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, s, blk, tiles);
   hipLaunchKernelGGL((k_nb_bases<NDIM>), dim3(tiles), dim3(kBlock), 0, s, c->sort_cnt, g, cs,
                      (const uint32_t*)blk);
   hipLaunchKernelGGL((k_nb_scatter<NDIM>), dim3(cblocks), dim3(kBlock), 0, s, cs_prev, in->n, g,
-                     (const uint32_t*)c->sort_cnt, fields_of(in), fields_of(out), c->status, gen);
-  enqueue_radix(c, in, out, cs, gen, /*forced=*/0);
+                     (const uint32_t*)c->sort_cnt, fields_of(in), fields_of(out), cs,
+                     (const Status*)c->status, c->rkey[0], c->rkey[1], c->rval[0], c->rval[1]);
 }
 
 }  // namespace
@@ -601,14 +634,12 @@ void enqueue_neighbour(hvpic_ctx* c, const hvpic_particles* in, hvpic_particles*
 int launch_sort(hvpic_ctx* c, const hvpic_particles* in, hvpic_particles* out,
                 const int32_t* cs_prev, int32_t* cs, int full) {
   out->n = in->n;
-  c->sort_gen = c->sort_gen + 1 == 0 ? 1 : c->sort_gen + 1;
-  const uint32_t gen = c->sort_gen;
   if (full || cs_prev == nullptr) {
-    enqueue_radix(c, in, out, cs, gen, /*forced=*/1);
+    enqueue_radix(c, in, out, cs);
   } else if (c->p.ndim == 2) {
-    enqueue_neighbour<2>(c, in, out, cs_prev, cs, gen);
+    enqueue_neighbour<2>(c, in, out, cs_prev, cs);
   } else {
-    enqueue_neighbour<3>(c, in, out, cs_prev, cs, gen);
+    enqueue_neighbour<3>(c, in, out, cs_prev, cs);
   }
   return hipGetLastError() == hipSuccess ? HVPIC_OK : HVPIC_EHIP;
 }

@@ -51,3 +51,54 @@ def compare_particles(cfg, gpu: dict, ref: dict, band=1e-5, vtol=2e-6):
         err = np.abs(np.asarray(gpu[k], np.float64) - ref[k]).max()
         assert err <= vtol * vs, (k, err, vs)
     return int(np.sum(diff))
+
+
+def _near_face(o, band):
+    o = np.asarray(o, np.float64)
+    return (np.abs(o + 1.0) < band) | (np.abs(o - 1.0) < band)
+
+
+def deposit_point_straddlers(cfg, parts: dict, back: float, band=1e-5) -> np.ndarray:
+    """Particles whose deposit point x - back*v lies within `band` half-cells of
+    a cell face (FP64).  FP32 and FP64 may put such a point in different cells."""
+    offs = [("ox", "ux", cfg.dx), ("oy", "uy", cfg.dy)] + ([("oz", "uz", cfg.dz)] if cfg.ndim == 3 else [])
+    bad = np.zeros(parts["cell"].size, bool)
+    for ko, kv, h in offs:
+        x = np.asarray(parts[ko], np.float64) - 2.0 * back * np.asarray(parts[kv], np.float64) / h
+        x = x - 2.0 * np.floor((x + 1.0) / 2.0)
+        bad |= _near_face(x, band)
+    return bad
+
+
+def drop_straddlers(cfg, parts: dict, B, steps: int = 1, band=1e-5, fused=False) -> dict:
+    """Removes from the input every particle that the FP64 oracle moves, within
+    `steps` steps, to within `band` half-cells of a face, or whose mid-point
+    deposit point lands there.  Uses only the oracle; the GPU and the oracle
+    then run on the same cleaned input, so cell decisions can be compared
+    exactly (the straddler band of the parity contract)."""
+    import oracle as O
+
+    keep = np.ones(parts["cell"].size, bool)
+    for _ in range(4):
+        sub = {k: v[keep] for k, v in parts.items()}
+        ids = np.nonzero(keep)[0]
+        sim = O.OracleSim(cfg, {**sub, "id": ids.astype(np.float64)}, B)
+        bad = np.zeros(parts["cell"].size, bool)
+        for _ in range(steps):
+            O.push(cfg, sim.p, sim.E, sim.B)
+            offs = ["ox", "oy"] + (["oz"] if cfg.ndim == 3 else [])
+            near = np.zeros(sim.p["cell"].size, bool)
+            for k in offs:
+                near |= _near_face(sim.p[k], band)
+            near |= deposit_point_straddlers(cfg, sim.p, 0.5 * cfg.dt, band)
+            bad[sim.p["id"].astype(np.int64)[near]] = True
+            perm, sim.cell_start = O.sort(cfg, sim.p["cell"])
+            sim.p = O.apply_perm(sim.p, perm)
+            n_half, J_half = O.deposit(cfg, sim.p, 0.5 * cfg.dt)
+            sim.B, sim.E, _, _ = O.field_advance(cfg, sim.B, n_half, J_half, sim.n_prev,
+                                                 sim.J_prev, mode=0)
+            sim.n_prev, sim.J_prev = n_half, J_half
+        if not bad.any():
+            return {k: np.ascontiguousarray(v) for k, v in sub.items()}
+        keep &= ~bad
+    raise AssertionError("straddler removal did not converge")

@@ -10,7 +10,8 @@ import pytest
 
 import oracle as O
 from paper_2305_05600_amd import workloads as W
-from tests.helpers import announce, compare_particles, rel_l2
+from tests.helpers import (announce, compare_particles, deposit_point_straddlers,
+                           rel_l2)
 
 pytestmark = pytest.mark.gpu
 
@@ -80,6 +81,10 @@ def test_gather_push(H, name, cfg, ppc):
 def test_deposit(H, name, cfg, ppc, sorted_, back):
     announce("deposit", name, ppc, sorted_, back)
     _, parts, _ = W.random_box(31, cfg, ppc)
+    # FP32 and FP64 may disagree on the cell of a deposit point within rounding
+    # of a face; such points are kept out of the input
+    keep = ~deposit_point_straddlers(cfg, parts, back)
+    parts = {k: v[keep] for k, v in parts.items()}
     if sorted_:
         parts, _ = _sorted(cfg, parts)
     ctx = H.Context(cfg, parts["cell"].size)
@@ -98,8 +103,15 @@ def test_fused_push_deposit(H, name, cfg):
     x^{n+1} - (dt/2) v^{n+1/2}."""
     announce("fused", name)
     _, parts, B = W.random_box(41, cfg, 33.3)
-    parts, _ = _sorted(cfg, parts)
     E = W.random_field(42, cfg, 0.3)
+    ref = O.particles64(parts)
+    O.push(cfg, ref, E, B)
+    offs = ["ox", "oy"] + (["oz"] if cfg.ndim == 3 else [])
+    near = deposit_point_straddlers(cfg, ref, 0.5 * cfg.dt)
+    for k in offs:
+        near |= (np.abs(ref[k] + 1) < 1e-5) | (np.abs(ref[k] - 1) < 1e-5)
+    parts = {k: v[~near] for k, v in parts.items()}
+    parts, _ = _sorted(cfg, parts)
     ctx = H.Context(cfg, parts["cell"].size)
     p = H.Particles.from_numpy(parts, cfg.ndim)
     n = torch.zeros(cfg.ncell, device="cuda")
