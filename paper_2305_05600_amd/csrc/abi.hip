@@ -48,7 +48,7 @@ bool parts_ok(const hvpic_ctx* c, const hvpic_particles* q, bool need_w) {
 
 bool ctx_ok(const hvpic_ctx* c) { return c && c->magic == kMagic; }
 
-__global__ void k_init_ws(Status* st, double* a, double* b, int n, double* mom, int64_t nmom) {
+__global__ void k_init_ws(Status* st, double* mom, int64_t nmom) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   for (int64_t q = i; q < nmom; q += (int64_t)gridDim.x * blockDim.x) mom[q] = 0.0;
   if (i == 0) {
@@ -56,11 +56,6 @@ __global__ void k_init_ws(Status* st, double* a, double* b, int n, double* mom, 
     st->moved_gt1 = st->nonfinite = st->floor_hits = st->bad_input = 0;
     st->far_flag = 0;
     st->far_decision = 0;
-    st->done_push = st->done_field = 0;
-  }
-  if (i < n) {
-    a[i] = 0.0;
-    b[i] = 0.0;
   }
 }
 
@@ -82,8 +77,8 @@ Layout workspace_layout(const hvpic_params* p) {
   const int64_t nblk = std::max(ceil_div(nc, kScanTile), ceil_div(kRadixBins * ntiles, kScanTile)) + 1;
   size_t off = 0;
   L.status = off;    off += align256(sizeof(Status));
-  L.diag_acc = off;  off += align256(sizeof(double) * 4 * kDiagSlots);
-  L.field_acc = off; off += align256(sizeof(double) * 4 * kDiagSlots);
+  L.push_part = off; off += align256(sizeof(double) * 4 * ceil_div(cap, 1024));
+  L.field_part = off; off += align256(sizeof(double) * 4 * ceil_div(nc, kBlock));
   L.sort_cnt = off;  off += align256(sizeof(uint32_t) * ndir * nc);
   L.sort_blk = off;  off += align256(sizeof(uint32_t) * nblk);
   L.rkey0 = off;     off += align256(sizeof(uint32_t) * cap);
@@ -131,8 +126,8 @@ int hvpic_init(const hvpic_params* params, void* hip_stream, void* workspace, hv
   c->fnx = make_fastdiv((uint32_t)params->nx);
   c->fny = make_fastdiv((uint32_t)params->ny);
   c->status = (Status*)(c->ws + L.status);
-  c->diag_acc = (double*)(c->ws + L.diag_acc);
-  c->field_acc = (double*)(c->ws + L.field_acc);
+  c->push_part = (double*)(c->ws + L.push_part);
+  c->field_part = (double*)(c->ws + L.field_part);
   c->sort_cnt = (uint32_t*)(c->ws + L.sort_cnt);
   c->sort_blk = (int32_t*)(c->ws + L.sort_blk);
   c->rkey[0] = (uint32_t*)(c->ws + L.rkey0);
@@ -142,9 +137,8 @@ int hvpic_init(const hvpic_params* params, void* hip_stream, void* workspace, hv
   c->rhist = (uint32_t*)(c->ws + L.rhist);
   c->fscratch = (float*)(c->ws + L.fscratch);
   c->mom_acc = (double*)(c->ws + L.mom_acc);
-  const int n = 4 * kDiagSlots;
-  hipLaunchKernelGGL(k_init_ws, dim3((n + 255) / 256), dim3(256), 0, c->stream, c->status,
-                     c->diag_acc, c->field_acc, n, c->mom_acc, 4ll * c->ncell);
+  hipLaunchKernelGGL(k_init_ws, dim3(256), dim3(256), 0, c->stream, c->status, c->mom_acc,
+                     4ll * c->ncell);
   if (hipGetLastError() != hipSuccess) {
     delete c;
     return HVPIC_EHIP;

@@ -186,14 +186,125 @@ __global__ __launch_bounds__(kBlock) void k_field_stage(const float* __restrict_
   Bdst[2 * nc + c] = b2 - coef * cz;
 }
 
-// E = Ohm(B) written out, plus the FP64 magnetic diagnostics of B.
+
+// One whole RK2 substep for a 2D tile of TX x TY cells with all intermediate
+// fields in LDS: B (halo 4) -> Ea (halo 3) -> B* (halo 2) -> Eb (halo 1) ->
+// B_new on the tile.  Reads Bin, writes Bout (distinct buffers: neighbouring
+// tiles read the halo of Bin while this one writes).
+constexpr int kTX = 32, kTY = 16;
+constexpr int kBW = kTX + 8, kBH = kTY + 8;   // B with halo 4
+constexpr int kAW = kTX + 6, kAH = kTY + 6;   // aux and Ea with halo 3
+constexpr int kSW = kTX + 4, kSH = kTY + 4;   // B* with halo 2
+constexpr int kFW = kTX + 2, kFH = kTY + 2;   // Eb with halo 1
+
+__global__ __launch_bounds__(kBlock) void k_field_substep2d(const float* __restrict__ Bin,
+                                                            float* __restrict__ Bout, float h,
+                                                            float eta, FGeo g, Aux aux) {
+  __shared__ float sB[3][kBH * kBW];
+  __shared__ float sA[7][kAH * kAW];
+  __shared__ float sE[3][kAH * kAW];
+  __shared__ float sS[3][kSH * kSW];
+  const int nc = g.ncell;
+  const int tx0 = blockIdx.x * kTX, ty0 = blockIdx.y * kTY;
+  auto gidx = [&](int lx, int ly) {
+    int x = tx0 + lx, y = ty0 + ly;
+    x %= g.nx; if (x < 0) x += g.nx;
+    y %= g.ny; if (y < 0) y += g.ny;
+    return x + g.nx * y;
+  };
+  for (int t = threadIdx.x; t < kBH * kBW; t += kBlock) {
+    const int ly = t / kBW - 4, lx = t % kBW - 4;
+    const int c = gidx(lx, ly);
+    sB[0][t] = Bin[c];
+    sB[1][t] = Bin[nc + c];
+    sB[2][t] = Bin[2 * nc + c];
+  }
+  for (int t = threadIdx.x; t < kAH * kAW; t += kBlock) {
+    const int ly = t / kAW - 3, lx = t % kAW - 3;
+    const int c = gidx(lx, ly);
+    sA[0][t] = aux.inv[c];
+    sA[1][t] = aux.u[c];
+    sA[2][t] = aux.u[nc + c];
+    sA[3][t] = aux.u[2 * nc + c];
+    sA[4][t] = aux.gp[c];
+    sA[5][t] = aux.gp[nc + c];
+    sA[6][t] = aux.gp[2 * nc + c];
+  }
+  __syncthreads();
+  // Ohm's law at a cell given B there, curl B there and the aux slot.
+  auto ohm = [&](float b0, float b1, float b2, float j0, float j1, float j2, int a, float* e) {
+    const float inv = sA[0][a];
+    const float w0 = j0 * inv - sA[1][a], w1 = j1 * inv - sA[2][a], w2 = j2 * inv - sA[3][a];
+    e[0] = (w1 * b2 - w2 * b1) + sA[4][a] + eta * j0;
+    e[1] = (w2 * b0 - w0 * b2) + sA[5][a] + eta * j1;
+    e[2] = (w0 * b1 - w1 * b0) + sA[6][a] + eta * j2;
+  };
+  // Ea on the tile with halo 3 (from B with halo 4)
+  for (int t = threadIdx.x; t < kAH * kAW; t += kBlock) {
+    const int ly = t / kAW, lx = t % kAW;      // B index = (ly+1, lx+1)
+    const int b = (ly + 1) * kBW + lx + 1;
+    const float j0 = (sB[2][b + kBW] - sB[2][b - kBW]) * g.idy2;
+    const float j1 = -(sB[2][b + 1] - sB[2][b - 1]) * g.idx2;
+    const float j2 = (sB[1][b + 1] - sB[1][b - 1]) * g.idx2 - (sB[0][b + kBW] - sB[0][b - kBW]) * g.idy2;
+    float e[3];
+    ohm(sB[0][b], sB[1][b], sB[2][b], j0, j1, j2, t, e);
+    sE[0][t] = e[0];
+    sE[1][t] = e[1];
+    sE[2][t] = e[2];
+  }
+  __syncthreads();
+  // B* = B - (h/2) curl Ea on the tile with halo 2
+  const float hh = 0.5f * h;
+  for (int t = threadIdx.x; t < kSH * kSW; t += kBlock) {
+    const int ly = t / kSW, lx = t % kSW;
+    const int e = (ly + 1) * kAW + lx + 1;     // Ea index
+    const int b = (ly + 2) * kBW + lx + 2;     // B index
+    const float c0 = (sE[2][e + kAW] - sE[2][e - kAW]) * g.idy2;
+    const float c1 = -(sE[2][e + 1] - sE[2][e - 1]) * g.idx2;
+    const float c2 = (sE[1][e + 1] - sE[1][e - 1]) * g.idx2 - (sE[0][e + kAW] - sE[0][e - kAW]) * g.idy2;
+    sS[0][t] = sB[0][b] - hh * c0;
+    sS[1][t] = sB[1][b] - hh * c1;
+    sS[2][t] = sB[2][b] - hh * c2;
+  }
+  __syncthreads();
+  // Eb on the tile with halo 1 (stored in sE with the Eb row width)
+  for (int t = threadIdx.x; t < kFH * kFW; t += kBlock) {
+    const int ly = t / kFW, lx = t % kFW;
+    const int s = (ly + 1) * kSW + lx + 1;     // B* index
+    const int a = (ly + 2) * kAW + lx + 2;     // aux index
+    const float j0 = (sS[2][s + kSW] - sS[2][s - kSW]) * g.idy2;
+    const float j1 = -(sS[2][s + 1] - sS[2][s - 1]) * g.idx2;
+    const float j2 = (sS[1][s + 1] - sS[1][s - 1]) * g.idx2 - (sS[0][s + kSW] - sS[0][s - kSW]) * g.idy2;
+    float e[3];
+    ohm(sS[0][s], sS[1][s], sS[2][s], j0, j1, j2, a, e);
+    // sE is free again (Ea was consumed before the last barrier)
+    sE[0][t] = e[0];
+    sE[1][t] = e[1];
+    sE[2][t] = e[2];
+  }
+  __syncthreads();
+  // B_new = B - h curl Eb on the tile
+  for (int t = threadIdx.x; t < kTY * kTX; t += kBlock) {
+    const int ly = t / kTX, lx = t % kTX;
+    const int x = tx0 + lx, y = ty0 + ly;
+    if (x >= g.nx || y >= g.ny) continue;
+    const int e = (ly + 1) * kFW + lx + 1;
+    const int b = (ly + 4) * kBW + lx + 4;
+    const float c0 = (sE[2][e + kFW] - sE[2][e - kFW]) * g.idy2;
+    const float c1 = -(sE[2][e + 1] - sE[2][e - 1]) * g.idx2;
+    const float c2 = (sE[1][e + 1] - sE[1][e - 1]) * g.idx2 - (sE[0][e + kFW] - sE[0][e - kFW]) * g.idy2;
+    const int c = x + g.nx * y;
+    Bout[c] = sB[0][b] - h * c0;
+    Bout[nc + c] = sB[1][b] - h * c1;
+    Bout[2 * nc + c] = sB[2][b] - h * c2;
+  }
+}
+
+// E = Ohm(B) written out, plus per-block FP64 partials {sum |B|^2, sum B}.
 template <int NDIM>
 __global__ __launch_bounds__(kBlock) void k_field_ohm_out(const float* __restrict__ B, float eta,
                                                           FGeo g, Aux aux, float* __restrict__ E,
-                                                          double* diag_out, double* acc,
-                                                          Status* st) {
-  __shared__ double s_red[kBlock / 64][4];
-  __shared__ bool s_last;
+                                                          double* part) {
   const int c = blockIdx.x * kBlock + threadIdx.x;
   const int nc = g.ncell;
   double v[4] = {0.0, 0.0, 0.0, 0.0};
@@ -209,56 +320,19 @@ __global__ __launch_bounds__(kBlock) void k_field_ohm_out(const float* __restric
     v[2] = b1;
     v[3] = b2;
   }
-  if (!diag_out) return;
-  for (int q = 0; q < 4; ++q)
-    for (int o = 32; o > 0; o >>= 1) v[q] += __shfl_xor(v[q], o);
-  const int wid = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0)
-    for (int q = 0; q < 4; ++q) s_red[wid][q] = v[q];
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const int slot = blockIdx.x % kDiagSlots;
-    for (int q = 0; q < 4; ++q) {
-      double t = 0.0;
-      for (int w = 0; w < kBlock / 64; ++w) t += s_red[w][q];
-      unsafeAtomicAdd(acc + slot * 4 + q, t);
-    }
-    __threadfence();
-    s_last = atomicAdd(&st->done_field, 1u) == gridDim.x - 1;
-  }
-  __syncthreads();
-  if (!s_last) return;
-  __threadfence();
-  double t[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int s = threadIdx.x; s < kDiagSlots; s += kBlock)
-    for (int q = 0; q < 4; ++q) {
-      t[q] += __hip_atomic_load(acc + s * 4 + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(acc + s * 4 + q, 0.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-  for (int q = 0; q < 4; ++q)
-    for (int o = 32; o > 0; o >>= 1) t[q] += __shfl_xor(t[q], o);
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0)
-    for (int q = 0; q < 4; ++q) s_red[wid][q] = t[q];
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double r[4];
-    for (int q = 0; q < 4; ++q) {
-      r[q] = 0.0;
-      for (int w = 0; w < kBlock / 64; ++w) r[q] += s_red[w][q];
-    }
-    diag_out[0] = r[0];
-    diag_out[1] = r[1] * r[1] + r[2] * r[2] + r[3] * r[3];
-    __hip_atomic_store(&st->done_field, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
+  if (part) block_partial<4>(v, part);
 }
 
-// Turns {sum |B|^2, |sum B|^2} into {W_B, W_dB}.
-__global__ void k_field_diag_scale(double* d, double half_vol, double inv_ncell) {
+// {W_B, W_dB} = {1/2 V sum |B|^2, 1/2 V (sum |B|^2 - |sum B|^2 / ncell)}.
+__global__ __launch_bounds__(kBlock) void k_field_diag_final(const double* part, int nblocks,
+                                                             double* out, double half_vol,
+                                                             double inv_ncell) {
+  double r[4];
+  sum_partials<4>(part, nblocks, r);
   if (threadIdx.x == 0) {
-    const double s2 = d[0], m2 = d[1];
-    d[0] = half_vol * s2;
-    d[1] = half_vol * (s2 - m2 * inv_ncell);
+    const double m2 = r[1] * r[1] + r[2] * r[2] + r[3] * r[3];
+    out[0] = half_vol * r[0];
+    out[1] = half_vol * (r[0] - m2 * inv_ncell);
   }
 }
 
@@ -322,22 +396,39 @@ int field_impl(hvpic_ctx* c, float* B, const float* n_half, const float* J_half,
                      c->status, 1);
   if (mode == 0) {
     const float h = (float)(c->p.dt / c->p.nsub);
-    for (int m = 0; m < c->p.nsub; ++m) {
-      hipLaunchKernelGGL((k_field_stage<NDIM>), grid, blk, 0, s, (const float*)B, (const float*)B,
-                         Bs, 0.5f * h, eta, g, aux);
-      hipLaunchKernelGGL((k_field_stage<NDIM>), grid, blk, 0, s, (const float*)Bs, (const float*)B,
-                         B, h, eta, g, aux);
+    if (NDIM == 2) {
+      // fused substeps, B ping-ponged between the caller's array and scratch
+      const dim3 tiles((unsigned)ceil_div(c->p.nx, kTX), (unsigned)ceil_div(c->p.ny, kTY));
+      float* src = B;
+      float* dst = Bs;
+      for (int m = 0; m < c->p.nsub; ++m) {
+        hipLaunchKernelGGL(k_field_substep2d, tiles, blk, 0, s, (const float*)src, dst, h, eta, g,
+                           aux);
+        float* t = src;
+        src = dst;
+        dst = t;
+      }
+      if (src != B)
+        hipLaunchKernelGGL(k_copy, dim3(std::min<int64_t>(ceil_div(3ll * nc, kBlock), 1024)), blk,
+                           0, s, (const float*)src, B, 3ll * nc);
+    } else {
+      for (int m = 0; m < c->p.nsub; ++m) {
+        hipLaunchKernelGGL((k_field_stage<NDIM>), grid, blk, 0, s, (const float*)B,
+                           (const float*)B, Bs, 0.5f * h, eta, g, aux);
+        hipLaunchKernelGGL((k_field_stage<NDIM>), grid, blk, 0, s, (const float*)Bs,
+                           (const float*)B, B, h, eta, g, aux);
+      }
     }
     // extrapolated moments for E^{n+1}
     hipLaunchKernelGGL((k_field_prep<NDIM>), grid, blk, 0, s, n_half, n_prev, J_half, J_prev, 1.5f,
                        -0.5f, g, nfloor, te_n0, n0, gam, iso, aux, c->status, 0);
   }
   hipLaunchKernelGGL((k_field_ohm_out<NDIM>), grid, blk, 0, s, (const float*)B, eta, g, aux, E_out,
-                     diag_out, c->field_acc, c->status);
+                     diag_out ? c->field_part : nullptr);
   if (diag_out) {
     const double V = c->p.dx * c->p.dy * c->p.dz;
-    hipLaunchKernelGGL(k_field_diag_scale, dim3(1), dim3(64), 0, s, diag_out, 0.5 * V,
-                       1.0 / (double)nc);
+    hipLaunchKernelGGL(k_field_diag_final, dim3(1), blk, 0, s, (const double*)c->field_part,
+                       (int)grid.x, diag_out, 0.5 * V, 1.0 / (double)nc);
   }
   return hipGetLastError() == hipSuccess ? HVPIC_OK : HVPIC_EHIP;
 }

@@ -9,7 +9,6 @@
 namespace hvpic {
 
 constexpr int kBlock = 256;      // threads per block for particle kernels
-constexpr int kDiagSlots = 1024; // FP64 reduction slots (spread the atomics)
 
 // Unsigned division by a runtime constant: q = mulhi(n, m) is floor(n/d) or
 // one less, fixed by one compare.  Valid for n < 2^32.
@@ -40,9 +39,50 @@ struct Status {
   unsigned long long bad_input;
   uint32_t far_flag;        // set by the neighbour-move count kernel on a far mover
   uint32_t far_decision;    // far_flag handed to the scatter kernel (and far_flag cleared)
-  uint32_t done_push;       // last-block counters of the FP64 reductions
-  uint32_t done_field;
 };
+
+// FP64 partial sums of NV values over a block, written by thread 0 to
+// part[blockIdx.x * 4 + k].  Fixed reduction order (deterministic).
+template <int NV>
+__device__ void block_partial(double* v, double* part) {
+  __shared__ double s_red[16][NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k)
+    for (int o = 32; o > 0; o >>= 1) v[k] += __shfl_xor(v[k], o);
+  const int wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if ((threadIdx.x & 63) == 0)
+    for (int k = 0; k < NV; ++k) s_red[wid][k] = v[k];
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int k = 0; k < NV; ++k) {
+      double t = 0.0;
+      for (int w = 0; w < nw; ++w) t += s_red[w][k];
+      part[(int64_t)blockIdx.x * 4 + k] = t;
+    }
+}
+
+// Sum of nblocks partials (as written by block_partial) by one block, in a
+// fixed order; thread 0 returns the totals in res.
+template <int NV>
+__device__ void sum_partials(const double* part, int nblocks, double* res) {
+  __shared__ double s_red[16][NV];
+  double t[NV];
+  for (int k = 0; k < NV; ++k) t[k] = 0.0;
+  for (int b = threadIdx.x; b < nblocks; b += blockDim.x)
+    for (int k = 0; k < NV; ++k) t[k] += part[(int64_t)b * 4 + k];
+  for (int k = 0; k < NV; ++k)
+    for (int o = 32; o > 0; o >>= 1) t[k] += __shfl_xor(t[k], o);
+  const int wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if ((threadIdx.x & 63) == 0)
+    for (int k = 0; k < NV; ++k) s_red[wid][k] = t[k];
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int k = 0; k < NV; ++k) {
+      double r = 0.0;
+      for (int w = 0; w < nw; ++w) r += s_red[w][k];
+      res[k] = r;
+    }
+}
 
 __device__ __forceinline__ void raise_flag(Status* st, uint32_t bit, unsigned long long* counter) {
   atomicOr(&st->flags, bit);
@@ -66,8 +106,8 @@ struct hvpic_ctx {
   hvpic::FastDiv fnx, fny;
   // workspace carve-out
   hvpic::Status* status;
-  double* diag_acc;      // [kDiagSlots][4]
-  double* field_acc;     // [kDiagSlots][4]
+  double* push_part;     // per-block FP64 partials of the push diagnostics [blocks][4]
+  double* field_part;    // per-block FP64 partials of the field diagnostics [blocks][4]
   uint32_t* sort_cnt;    // [ncell][3^ndim]
   int32_t* sort_blk;     // scan block sums
   uint32_t* rkey[2];     // radix keys   [np_capacity]
@@ -97,7 +137,7 @@ int launch_init_workspace(hvpic_ctx* c);
 
 // Workspace layout (bytes from the start; each region 256-byte aligned).
 struct Layout {
-  size_t status, diag_acc, field_acc, sort_cnt, sort_blk, rkey0, rkey1, rval0, rval1, rhist,
+  size_t status, push_part, field_part, sort_cnt, sort_blk, rkey0, rkey1, rval0, rval1, rhist,
       fscratch, mom_acc, total;
 };
 Layout workspace_layout(const hvpic_params* p);

@@ -66,8 +66,7 @@ struct PushArgs {
   float kx, ky, kz;         // full-step displacement per unit speed (half-cells)
   float qV;                 // q / V_c
   double ms;
-  double* diag_out;
-  double* diag_acc;
+  double* diag_part;        // per-block partials of {K, Px, Py, Pz}, or null
   Status* st;
 };
 
@@ -336,55 +335,6 @@ __device__ void window_flush(const double* win, int W, int c0, const Geo& g,
   }
 }
 
-// FP64 block reduction of NV partial sums and the last-block finalisation.
-template <int NV>
-__device__ void reduce_finalize(double* v, double* acc, uint32_t* done, double* out) {
-  __shared__ double s_red[kBlock / 64][NV];
-  __shared__ bool s_last;
-#pragma unroll
-  for (int k = 0; k < NV; ++k)
-    for (int o = 32; o > 0; o >>= 1) v[k] += __shfl_xor(v[k], o);
-  const int wid = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0)
-    for (int k = 0; k < NV; ++k) s_red[wid][k] = v[k];
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const int slot = blockIdx.x % kDiagSlots;
-    for (int k = 0; k < NV; ++k) {
-      double t = 0.0;
-      for (int w = 0; w < kBlock / 64; ++w) t += s_red[w][k];
-      unsafeAtomicAdd(acc + slot * 4 + k, t);
-    }
-    __threadfence();
-    const uint32_t prev = atomicAdd(done, 1u);
-    s_last = prev == gridDim.x - 1;
-  }
-  __syncthreads();
-  if (!s_last) return;
-  __threadfence();
-  double t[NV];
-  for (int k = 0; k < NV; ++k) t[k] = 0.0;
-  for (int s = threadIdx.x; s < kDiagSlots; s += kBlock)
-    for (int k = 0; k < NV; ++k) {
-      t[k] += __hip_atomic_load(acc + s * 4 + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(acc + s * 4 + k, 0.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-  __syncthreads();
-  for (int k = 0; k < NV; ++k)
-    for (int o = 32; o > 0; o >>= 1) t[k] += __shfl_xor(t[k], o);
-  if ((threadIdx.x & 63) == 0)
-    for (int k = 0; k < NV; ++k) s_red[wid][k] = t[k];
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int k = 0; k < NV; ++k) {
-      double r = 0.0;
-      for (int w = 0; w < kBlock / 64; ++w) r += s_red[w][k];
-      out[k] = r;
-    }
-    __hip_atomic_store(done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-}
-
 // ---------------------------------------------------------------- kernels --
 
 template <int NDIM, int SHAPE, bool DEP>
@@ -411,7 +361,7 @@ __global__ __launch_bounds__(kBlock) void k_gather_push(PushArgs A) {
     __syncthreads();
   }
 
-  const bool want_diag = A.diag_out != nullptr;
+  const bool want_diag = A.diag_part != nullptr;
   double dK = 0.0, dP[3] = {0.0, 0.0, 0.0};
   for (int it = 0; it < PPT; ++it) {
     const int64_t idx = base + (int64_t)it * kBlock + threadIdx.x;
@@ -509,7 +459,7 @@ __global__ __launch_bounds__(kBlock) void k_gather_push(PushArgs A) {
   }
   if (want_diag) {
     double v[4] = {dK, dP[0], dP[1], dP[2]};
-    reduce_finalize<4>(v, A.diag_acc, &A.st->done_push, A.diag_out);
+    block_partial<4>(v, A.diag_part);
   }
   if (DEP && wok) {
     __syncthreads();
@@ -608,6 +558,14 @@ __global__ void k_write_zero_diag(double* out, int nv) {
   if (threadIdx.x < nv) out[threadIdx.x] = 0.0;
 }
 
+__global__ __launch_bounds__(kBlock) void k_push_diag_final(const double* part, int nblocks,
+                                                            double* out) {
+  double r[4];
+  sum_partials<4>(part, nblocks, r);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 4; ++k) out[k] = r[k];
+}
+
 Geo make_geo(const hvpic_ctx* c) {
   Geo g;
   g.nx = c->p.nx;
@@ -674,20 +632,23 @@ int launch_gather_push(hvpic_ctx* c, hvpic_particles* p, const float* E, const f
   A.kz = c->kz;
   A.qV = c->qV;
   A.ms = c->p.ms;
-  A.diag_out = diag_out;
-  A.diag_acc = c->diag_acc;
+  A.diag_part = diag_out ? c->push_part : nullptr;
   A.st = c->status;
   const bool qs = c->p.shape == HVPIC_SHAPE_QS;
+  int nblocks = 0;
   if (c->p.ndim == 2) {
-    const dim3 grid((unsigned)ceil_div(p->n, Chunk<2>::N));
-    if (qs) push_dispatch<2, HVPIC_SHAPE_QS>(dep, grid, c->stream, A);
-    else push_dispatch<2, HVPIC_SHAPE_NGP>(dep, grid, c->stream, A);
+    nblocks = (int)ceil_div(p->n, Chunk<2>::N);
+    if (qs) push_dispatch<2, HVPIC_SHAPE_QS>(dep, dim3(nblocks), c->stream, A);
+    else push_dispatch<2, HVPIC_SHAPE_NGP>(dep, dim3(nblocks), c->stream, A);
   } else {
-    const dim3 grid((unsigned)ceil_div(p->n, Chunk<3>::N));
-    if (qs) push_dispatch<3, HVPIC_SHAPE_QS>(dep, grid, c->stream, A);
-    else push_dispatch<3, HVPIC_SHAPE_NGP>(dep, grid, c->stream, A);
+    nblocks = (int)ceil_div(p->n, Chunk<3>::N);
+    if (qs) push_dispatch<3, HVPIC_SHAPE_QS>(dep, dim3(nblocks), c->stream, A);
+    else push_dispatch<3, HVPIC_SHAPE_NGP>(dep, dim3(nblocks), c->stream, A);
   }
   if (dep) moments_out(c, n_mid, J_mid);
+  if (diag_out)
+    hipLaunchKernelGGL(k_push_diag_final, dim3(1), dim3(kBlock), 0, c->stream,
+                       (const double*)c->push_part, nblocks, diag_out);
   return hipGetLastError() == hipSuccess ? HVPIC_OK : HVPIC_EHIP;
 }
 
