@@ -86,7 +86,7 @@ Layout workspace_layout(const hvpic_params* p) {
   L.rval0 = off;     off += align256(sizeof(uint32_t) * cap);
   L.rval1 = off;     off += align256(sizeof(uint32_t) * cap);
   L.rhist = off;     off += align256(sizeof(uint32_t) * kRadixBins * ntiles);
-  L.fscratch = off;  off += align256(sizeof(float) * 16 * nc);
+  L.fscratch = off;  off += align256(sizeof(float) * 20 * nc);
   L.mom_acc = off;   off += align256(sizeof(double) * 4 * nc);
   L.total = off;
   return L;

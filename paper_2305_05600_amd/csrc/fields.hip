@@ -57,24 +57,28 @@ __device__ __forceinline__ Nbr neighbours(int c, int i, int j, int k, const FGeo
   return n;
 }
 
+// B held as an unevaluated sum hi + lo (lo may be null): the compensation
+// term carries the low bits that the subcycle's small updates would round away.
+struct BPair {
+  const float* hi;
+  const float* lo;
+  __device__ __forceinline__ float operator()(int q) const { return lo ? hi[q] + lo[q] : hi[q]; }
+};
+
 template <int NDIM>
-__device__ __forceinline__ void curl_at(const float* __restrict__ A, int c, const FGeo& g,
-                                        float out[3]) {
+__device__ __forceinline__ void curl_at(BPair A, int c, const FGeo& g, float out[3]) {
   int i, j, k;
   fijk(c, g, i, j, k);
   const Nbr n = neighbours(c, i, j, k, g);
   const int nc = g.ncell;
-  const float* Ax = A;
-  const float* Ay = A + nc;
-  const float* Az = A + 2 * nc;
-  const float dyAz = (Az[n.yp] - Az[n.ym]) * g.idy2;
-  const float dxAz = (Az[n.xp] - Az[n.xm]) * g.idx2;
-  const float dxAy = (Ay[n.xp] - Ay[n.xm]) * g.idx2;
-  const float dyAx = (Ax[n.yp] - Ax[n.ym]) * g.idy2;
+  const float dyAz = (A(2 * nc + n.yp) - A(2 * nc + n.ym)) * g.idy2;
+  const float dxAz = (A(2 * nc + n.xp) - A(2 * nc + n.xm)) * g.idx2;
+  const float dxAy = (A(nc + n.xp) - A(nc + n.xm)) * g.idx2;
+  const float dyAx = (A(n.yp) - A(n.ym)) * g.idy2;
   float dzAy = 0.f, dzAx = 0.f;
   if (NDIM == 3) {
-    dzAy = (Ay[n.zp] - Ay[n.zm]) * g.idz2;
-    dzAx = (Ax[n.zp] - Ax[n.zm]) * g.idz2;
+    dzAy = (A(nc + n.zp) - A(nc + n.zm)) * g.idz2;
+    dzAx = (A(n.zp) - A(n.zm)) * g.idz2;
   }
   out[0] = dyAz - dzAy;
   out[1] = dzAx - dxAz;
@@ -83,12 +87,12 @@ __device__ __forceinline__ void curl_at(const float* __restrict__ A, int c, cons
 
 // Ohm's law at cell c with the frozen-moment terms precomputed in aux.
 template <int NDIM>
-__device__ __forceinline__ void ohm_at(const float* __restrict__ B, const Aux& aux, float eta, int c,
-                                       const FGeo& g, float E[3]) {
+__device__ __forceinline__ void ohm_at(BPair B, const Aux& aux, float eta, int c, const FGeo& g,
+                                       float E[3]) {
   const int nc = g.ncell;
   float J[3];
   curl_at<NDIM>(B, c, g, J);
-  const float b0 = B[c], b1 = B[nc + c], b2 = B[2 * nc + c];
+  const float b0 = B(c), b1 = B(nc + c), b2 = B(2 * nc + c);
   const float inv = aux.inv[c];
   const float u0 = aux.u[c], u1 = aux.u[nc + c], u2 = aux.u[2 * nc + c];
   // (J - J_i) x B / n_f is -u_i x B + J x B / n_f
@@ -154,11 +158,15 @@ __global__ __launch_bounds__(kBlock) void k_field_prep(const float* __restrict__
   }
 }
 
-// One RK2 stage: Bdst = Bbase - coef * curl(Ohm(Bsrc)).  Bdst may alias Bbase.
+// One RK2 stage: B_dst = B_base - coef * curl(Ohm(B_src)).  With lo non-null
+// the update is compensated in place: (hi, lo) <- (hi, lo) - coef * curl E
+// (Fast2Sum on the small increment); otherwise Bdst = hi - coef * curl E.
+// Ohm's law is evaluated on B_src only, never on the array being written.
 template <int NDIM>
 __global__ __launch_bounds__(kBlock) void k_field_stage(const float* __restrict__ Bsrc,
-                                                        const float* Bbase, float* Bdst, float coef,
-                                                        float eta, FGeo g, Aux aux) {
+                                                        const float* Bbase, float* Bdst,
+                                                        float* lo, float coef, float eta,
+                                                        FGeo g, Aux aux) {
   const int c = blockIdx.x * kBlock + threadIdx.x;
   if (c >= g.ncell) return;
   const int nc = g.ncell;
@@ -166,24 +174,35 @@ __global__ __launch_bounds__(kBlock) void k_field_stage(const float* __restrict_
   fijk(c, g, i, j, k);
   const Nbr n = neighbours(c, i, j, k, g);
   float Exp[3], Exm[3], Eyp[3], Eym[3];
-  ohm_at<NDIM>(Bsrc, aux, eta, n.xp, g, Exp);
-  ohm_at<NDIM>(Bsrc, aux, eta, n.xm, g, Exm);
-  ohm_at<NDIM>(Bsrc, aux, eta, n.yp, g, Eyp);
-  ohm_at<NDIM>(Bsrc, aux, eta, n.ym, g, Eym);
+  const BPair Bp{Bsrc, nullptr};
+  ohm_at<NDIM>(Bp, aux, eta, n.xp, g, Exp);
+  ohm_at<NDIM>(Bp, aux, eta, n.xm, g, Exm);
+  ohm_at<NDIM>(Bp, aux, eta, n.yp, g, Eyp);
+  ohm_at<NDIM>(Bp, aux, eta, n.ym, g, Eym);
   float cx = (Eyp[2] - Eym[2]) * g.idy2;
   float cy = -(Exp[2] - Exm[2]) * g.idx2;
   float cz = (Exp[1] - Exm[1]) * g.idx2 - (Eyp[0] - Eym[0]) * g.idy2;
   if (NDIM == 3) {
     float Ezp[3], Ezm[3];
-    ohm_at<NDIM>(Bsrc, aux, eta, n.zp, g, Ezp);
-    ohm_at<NDIM>(Bsrc, aux, eta, n.zm, g, Ezm);
+    ohm_at<NDIM>(Bp, aux, eta, n.zp, g, Ezp);
+    ohm_at<NDIM>(Bp, aux, eta, n.zm, g, Ezm);
     cx -= (Ezp[1] - Ezm[1]) * g.idz2;
     cy += (Ezp[0] - Ezm[0]) * g.idz2;
   }
-  const float b0 = Bbase[c], b1 = Bbase[nc + c], b2 = Bbase[2 * nc + c];
-  Bdst[c] = b0 - coef * cx;
-  Bdst[nc + c] = b1 - coef * cy;
-  Bdst[2 * nc + c] = b2 - coef * cz;
+  const float d[3] = {-coef * cx, -coef * cy, -coef * cz};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const int q = a * nc + c;
+    const float hi = Bbase[q];
+    if (lo) {
+      const float y = lo[q] + d[a];
+      const float t = hi + y;
+      lo[q] = y - (t - hi);
+      Bdst[q] = t;
+    } else {
+      Bdst[q] = hi + d[a];
+    }
+  }
 }
 
 
@@ -198,7 +217,9 @@ constexpr int kSW = kTX + 4, kSH = kTY + 4;   // B* with halo 2
 constexpr int kFW = kTX + 2, kFH = kTY + 2;   // Eb with halo 1
 
 __global__ __launch_bounds__(kBlock) void k_field_substep2d(const float* __restrict__ Bin,
-                                                            float* __restrict__ Bout, float h,
+                                                            const float* __restrict__ Lin,
+                                                            float* __restrict__ Bout,
+                                                            float* __restrict__ Lout, float h,
                                                             float eta, FGeo g, Aux aux) {
   __shared__ float sB[3][kBH * kBW];
   __shared__ float sA[7][kAH * kAW];
@@ -294,27 +315,45 @@ __global__ __launch_bounds__(kBlock) void k_field_substep2d(const float* __restr
     const float c1 = -(sE[2][e + 1] - sE[2][e - 1]) * g.idx2;
     const float c2 = (sE[1][e + 1] - sE[1][e - 1]) * g.idx2 - (sE[0][e + kFW] - sE[0][e - kFW]) * g.idy2;
     const int c = x + g.nx * y;
-    Bout[c] = sB[0][b] - h * c0;
-    Bout[nc + c] = sB[1][b] - h * c1;
-    Bout[2 * nc + c] = sB[2][b] - h * c2;
+    // compensated update (hi, lo) - h curl Eb; the increment is tiny next to B
+    const float d[3] = {-h * c0, -h * c1, -h * c2};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const float hi = sB[a][b];
+      const float yv = (Lin ? Lin[a * nc + c] : 0.0f) + d[a];
+      const float tv = hi + yv;
+      Lout[a * nc + c] = yv - (tv - hi);
+      Bout[a * nc + c] = tv;
+    }
   }
 }
 
 // E = Ohm(B) written out, plus per-block FP64 partials {sum |B|^2, sum B}.
+// With Bout non-null the final B = hi + lo is also written there (Bout is
+// never one of the arrays read).
 template <int NDIM>
-__global__ __launch_bounds__(kBlock) void k_field_ohm_out(const float* __restrict__ B, float eta,
+__global__ __launch_bounds__(kBlock) void k_field_ohm_out(const float* __restrict__ Bh,
+                                                          const float* __restrict__ Bl,
+                                                          float* __restrict__ Bout, float eta,
                                                           FGeo g, Aux aux, float* __restrict__ E,
                                                           double* part) {
   const int c = blockIdx.x * kBlock + threadIdx.x;
   const int nc = g.ncell;
   double v[4] = {0.0, 0.0, 0.0, 0.0};
   if (c < nc) {
+    const BPair B{Bh, Bl};
     float e[3];
     ohm_at<NDIM>(B, aux, eta, c, g, e);
     E[c] = e[0];
     E[nc + c] = e[1];
     E[2 * nc + c] = e[2];
-    const double b0 = B[c], b1 = B[nc + c], b2 = B[2 * nc + c];
+    const float f0 = B(c), f1 = B(nc + c), f2 = B(2 * nc + c);
+    if (Bout) {
+      Bout[c] = f0;
+      Bout[nc + c] = f1;
+      Bout[2 * nc + c] = f2;
+    }
+    const double b0 = f0, b1 = f1, b2 = f2;
     v[0] = b0 * b0 + b1 * b1 + b2 * b2;
     v[1] = b0;
     v[2] = b1;
@@ -358,6 +397,11 @@ __global__ void k_copy(const float* __restrict__ in, float* __restrict__ out, in
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) out[i] = in[i];
 }
 
+__global__ void k_fill(float* __restrict__ out, int64_t n, float v) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) out[i] = v;
+}
+
 FGeo fgeo(const hvpic_ctx* c) {
   FGeo g;
   g.nx = c->p.nx;
@@ -385,7 +429,11 @@ int field_impl(hvpic_ctx* c, float* B, const float* n_half, const float* J_half,
   aux.inv = c->fscratch;
   aux.u = c->fscratch + nc;
   aux.gp = c->fscratch + 4ll * nc;
-  float* Bs = c->fscratch + 7ll * nc;
+  // B pairs (hi, lo) for the compensated subcycle, ping-ponged in scratch
+  float* Xh = c->fscratch + 7ll * nc;
+  float* Xl = c->fscratch + 10ll * nc;
+  float* Yh = c->fscratch + 13ll * nc;
+  float* Yl = c->fscratch + 16ll * nc;
   const float nfloor = (float)c->p.n_floor, n0 = (float)c->p.n0;
   const float te_n0 = (float)(c->p.te * c->p.n0), gam = (float)c->p.gamma_e;
   const int iso = c->p.gamma_e == 1.0;
@@ -394,37 +442,47 @@ int field_impl(hvpic_ctx* c, float* B, const float* n_half, const float* J_half,
   hipLaunchKernelGGL((k_field_prep<NDIM>), grid, blk, 0, s, n_half, (const float*)nullptr, J_half,
                      (const float*)nullptr, 1.0f, 0.0f, g, nfloor, te_n0, n0, gam, iso, aux,
                      c->status, 1);
-  if (mode == 0) {
+  const float* fh = B;        // final B = fh + fl
+  const float* fl = nullptr;
+  if (mode == 0 && c->p.nsub > 0) {
     const float h = (float)(c->p.dt / c->p.nsub);
+    const int cblocks = (int)std::min<int64_t>(ceil_div(3ll * nc, kBlock), 1024);
     if (NDIM == 2) {
-      // fused substeps, B ping-ponged between the caller's array and scratch
+      // fused substeps; the caller's B is only read (first substep)
       const dim3 tiles((unsigned)ceil_div(c->p.nx, kTX), (unsigned)ceil_div(c->p.ny, kTY));
-      float* src = B;
-      float* dst = Bs;
+      const float* sh = B;
+      const float* sl = nullptr;
+      float* dh = Xh;
+      float* dl = Xl;
       for (int m = 0; m < c->p.nsub; ++m) {
-        hipLaunchKernelGGL(k_field_substep2d, tiles, blk, 0, s, (const float*)src, dst, h, eta, g,
-                           aux);
-        float* t = src;
-        src = dst;
-        dst = t;
+        hipLaunchKernelGGL(k_field_substep2d, tiles, blk, 0, s, sh, sl, dh, dl, h, eta, g, aux);
+        sh = dh;
+        sl = dl;
+        dh = dh == Xh ? Yh : Xh;
+        dl = dl == Xl ? Yl : Xl;
       }
-      if (src != B)
-        hipLaunchKernelGGL(k_copy, dim3(std::min<int64_t>(ceil_div(3ll * nc, kBlock), 1024)), blk,
-                           0, s, (const float*)src, B, 3ll * nc);
+      fh = sh;
+      fl = sl;
     } else {
+      hipLaunchKernelGGL(k_copy, dim3(cblocks), blk, 0, s, (const float*)B, Xh, 3ll * nc);
+      hipLaunchKernelGGL(k_fill, dim3(cblocks), blk, 0, s, Xl, 3ll * nc, 0.0f);
       for (int m = 0; m < c->p.nsub; ++m) {
-        hipLaunchKernelGGL((k_field_stage<NDIM>), grid, blk, 0, s, (const float*)B,
-                           (const float*)B, Bs, 0.5f * h, eta, g, aux);
-        hipLaunchKernelGGL((k_field_stage<NDIM>), grid, blk, 0, s, (const float*)Bs,
-                           (const float*)B, B, h, eta, g, aux);
+        hipLaunchKernelGGL((k_field_stage<NDIM>), grid, blk, 0, s, (const float*)Xh,
+                           (const float*)Xh, Yh, (float*)nullptr, 0.5f * h, eta, g, aux);
+        hipLaunchKernelGGL((k_field_stage<NDIM>), grid, blk, 0, s, (const float*)Yh,
+                           (const float*)Xh, Xh, Xl, h, eta, g, aux);
       }
+      fh = Xh;
+      fl = Xl;
     }
+  }
+  if (mode == 0) {
     // extrapolated moments for E^{n+1}
     hipLaunchKernelGGL((k_field_prep<NDIM>), grid, blk, 0, s, n_half, n_prev, J_half, J_prev, 1.5f,
                        -0.5f, g, nfloor, te_n0, n0, gam, iso, aux, c->status, 0);
   }
-  hipLaunchKernelGGL((k_field_ohm_out<NDIM>), grid, blk, 0, s, (const float*)B, eta, g, aux, E_out,
-                     diag_out ? c->field_part : nullptr);
+  hipLaunchKernelGGL((k_field_ohm_out<NDIM>), grid, blk, 0, s, fh, fl, fh == B ? nullptr : B, eta,
+                     g, aux, E_out, diag_out ? c->field_part : nullptr);
   if (diag_out) {
     const double V = c->p.dx * c->p.dy * c->p.dz;
     hipLaunchKernelGGL(k_field_diag_final, dim3(1), blk, 0, s, (const double*)c->field_part,

@@ -113,7 +113,7 @@ struct hvpic_ctx {
   uint32_t* rkey[2];     // radix keys   [np_capacity]
   uint32_t* rval[2];     // radix values [np_capacity]
   uint32_t* rhist;       // radix per-block digit counts
-  float* fscratch;       // field scratch [16][ncell]
+  float* fscratch;       // field scratch [20][ncell]
   double* mom_acc;       // FP64 moment accumulators [4][ncell], kept at zero between deposits
 };
 

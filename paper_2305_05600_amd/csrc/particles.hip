@@ -2,46 +2,56 @@
 // (optionally with the moment deposit fused in) and the stand-alone deposit.
 //
 // Method (arXiv 2305.05600):
-//   gather   App. B eq:quadFI/eq:quadF (QS) -- evaluated here in the equivalent
-//            weight form: F(x_p) = sum_c W_c(dx,dy,dz) F_c with the eq:quad
+//   gather   App. B eq:quadFI/eq:quadF (QS) -- evaluated in the equivalent
+//            weight form F(x_p) = sum_c W_c(dx,dy,dz) F_c with the eq:quad
 //            weights, which the paper's consistency (no self-force) statement
 //            makes identical to the interpolant form; Sec. II.B for NGP.
 //   push     Sec. II.B eq:vadv, non-relativistic Boris split.
 //   move     Sec. II.B position update; offsets renormalised into [-1,1).
 //   deposit  Sec. II.B eq:ngp, App. B eq:quad, at x^{n+1/2}.
 //
-// Data path.  Particles are structure-of-arrays; a block owns one contiguous
-// chunk of kChunk particles and each lane handles every kBlock-th particle of
-// it, so every global load/store of the store is fully coalesced.  E and B are
-// read through the L1/L2 caches (the grid is small and the chunk's particles
-// share a handful of cells).  The deposit accumulates into an LDS window that
-// covers the chunk's cell range in "bands": the window holds, for each band
-// offset (by[, bz]) in -3..3, the linear cells [c0 + by*nx (+ bz*nx*ny) - 2,
-// c1 + ... + 2] (modulo ncell), which contains every cell a QS stencil at the
-// mid-point can touch -- x-wraps shift the band by one row, y-wraps (3D) by one
-// plane.  Within a wavefront, lanes whose mid-point cell coincides (the store
-// is cell-sorted, so most do) are summed with DPP row reductions before the LDS
-// atomics, which removes the 64-way same-address serialisation.  Each block
-// flushes its window with one global atomic per non-zero entry.
+// Data path.  Particles are structure-of-arrays and sorted by cell.  A block
+// owns a contiguous chunk of particles; each of its wavefronts walks a
+// contiguous sub-range 64 particles at a time, so every load and store of the
+// store is coalesced and consecutive iterations of a wavefront mostly stay in
+// the same cell.  The chunk's cells [c0, c1] are covered by LDS windows laid
+// out in "bands": band (by[, bz]) holds the linear cells
+// [c0 + by*nx (+ bz*nx*ny) - m, c1 + ... + m] modulo ncell.  A stencil point
+// that wraps around the x boundary lands one band over (and a y wrap in 3D one
+// plane band over), so band index and offset follow from the particle's own
+// cell with no division.
+//   * gather window: bands -1..1, margin 1, E and B interleaved as two float4
+//     per cell, so a stencil point costs two LDS reads;
+//   * deposit window: bands -3..3, margin 2, FP64 (n, Jx, Jy, Jz) per cell.
+// Deposit: each lane keeps running FP32 sums of its particles that belong to
+// the wavefront's current mid-point cell; when the wavefront moves on to the
+// next cell the sums are reduced over each 16-lane DPP row and added to the
+// window in FP64.  Particles whose mid-point sits in another cell (movers) add
+// straight into the window.  Each block flushes its window to FP64 global
+// accumulators; one pass converts them to the FP32 outputs.  Particles outside
+// the windows (unsorted or sparse input) use global loads / FP64 global atomics.
 #include "hvpic_internal.hpp"
 
 namespace hvpic {
 namespace {
 
-constexpr int kBands = 7;                 // band offsets -3..3
-constexpr int kWmax2 = 96;                // widest window (cells per band), 2D
-constexpr int kWmax3 = 24;                // 3D
-constexpr int kWin2 = kBands * kWmax2 * 4;
-constexpr int kWin3 = kBands * kBands * kWmax3 * 4;
+constexpr int kBands = 7;                 // deposit band offsets -3..3
+constexpr int kGBands = 3;                // gather band offsets -1..1
+constexpr int kGroupMin = 6;              // smallest lane group worth a DPP reduction
 
-// Particles per thread and per block: a 3D chunk spans more bands, so it is
-// kept shorter to keep its window small.
+// Particles per thread and per block, and the window limits.  A 3D chunk
+// spans more bands, so it is kept shorter to keep its windows small.
 template <int NDIM>
 struct Chunk {
   static constexpr int PPT = NDIM == 2 ? 8 : 4;
   static constexpr int N = kBlock * PPT;
+  static constexpr int WMAX = NDIM == 2 ? 64 : 20;                 // deposit window width
+  static constexpr int DB = NDIM == 2 ? kBands : kBands * kBands;  // deposit bands
+  static constexpr int GB = NDIM == 2 ? kGBands : kGBands * kGBands;
+  static constexpr int DEP_LEN = DB * WMAX * 4;                    // doubles
+  static constexpr int G_LEN = GB * (WMAX - 2) * 2;                // float4
 };
-constexpr int kGroupMin = 6;              // smallest lane group worth a reduction
+
 
 struct Geo {
   int nx, ny, nz, ncell, nxny;
@@ -222,19 +232,14 @@ __device__ __forceinline__ float row_sum(float v) {
   return v;
 }
 
-// Deposits one particle per lane.  Must be called by every lane of the wave
-// (uniform control flow): `live` lanes carry a particle, `inwin` lanes use the
-// LDS window, the other live lanes add straight to global memory.
+// Deposit slot (index of the (n, Jx, Jy, Jz) quadruple in the window) of each
+// stencil cell of a particle of old cell (i,j,k) = c0 + rel whose mid-point
+// sits (mx,my,mz) cells away.
 template <int NDIM, int SHAPE>
-__device__ __forceinline__ void deposit_lane(bool live, bool inwin, int rel, int i, int j, int k,
-                                             int mx, int my, int mz, float x, float y, float z,
-                                             float q, float vx, float vy, float vz, double* win,
-                                             int W, const Geo& g, double* __restrict__ acc) {
+__device__ __forceinline__ void deposit_slots(int rel, int i, int j, int mx, int my, int mz,
+                                              const int* sx, const int* sy, const int* sz, int W,
+                                              const Geo& g, int* slot) {
   constexpr int T = Stencil<NDIM, SHAPE>::T;
-  float wt[T];
-  int sx[T], sy[T], sz[T];
-  stencil_weights<NDIM, SHAPE>(x, y, z, wt, sx, sy, sz);
-  int slot[T];
 #pragma unroll
   for (int t = 0; t < T; ++t) {
     const int dxt = mx + sx[t], dyt = my + sy[t], dzt = mz + sz[t];
@@ -248,42 +253,99 @@ __device__ __forceinline__ void deposit_lane(bool live, bool inwin, int rel, int
     }
     slot[t] = (band * W + rel + dxt + 2) * 4;
   }
+}
+
+// Running per-lane moment sums of a wavefront for its current mid-point cell.
+template <int T>
+struct DepState {
+  float acc[T][4];
+  int cur;       // wavefront-uniform: deposit slot of the current cell's centre, -1 if none
+  int cslot[T];  // wavefront-uniform: slots of the current cell's stencil
+};
+
+template <int T>
+__device__ __forceinline__ void dep_init(DepState<T>& D) {
+  D.cur = -1;
+#pragma unroll
+  for (int t = 0; t < T; ++t) {
+    D.cslot[t] = 0;
+    D.acc[t][0] = D.acc[t][1] = D.acc[t][2] = D.acc[t][3] = 0.0f;
+  }
+}
+
+template <int T>
+__device__ __forceinline__ void dep_accumulate(DepState<T>& D, bool on, float q, const float* wt,
+                                               float vx, float vy, float vz) {
+  const float qm = on ? q : 0.0f;
+#pragma unroll
+  for (int t = 0; t < T; ++t) {
+    const float a = qm * wt[t];
+    D.acc[t][0] += a;
+    D.acc[t][1] = fmaf(a, vx, D.acc[t][1]);
+    D.acc[t][2] = fmaf(a, vy, D.acc[t][2]);
+    D.acc[t][3] = fmaf(a, vz, D.acc[t][3]);
+  }
+}
+
+// Adds the wavefront's sums for the current cell to the window (one FP64 LDS
+// atomic per value from the first lane of each DPP row).  Uniform call.
+template <int T>
+__device__ __forceinline__ void dep_flush(DepState<T>& D, double* win) {
+  if (D.cur < 0) return;
+  const bool adder = (threadIdx.x & 15) == 0;
+#pragma unroll
+  for (int t = 0; t < T; ++t) {
+#pragma unroll
+    for (int ch = 0; ch < 4; ++ch) {
+      const float s = row_sum(D.acc[t][ch]);
+      if (adder) atomicAdd(win + D.cslot[t] + ch, (double)s);
+      D.acc[t][ch] = 0.0f;
+    }
+  }
+  D.cur = -1;
+}
+
+// One particle per lane; every lane of the wavefront calls it (uniform
+// control flow).  Lanes whose mid-point cell is the wavefront's current cell
+// only add to their running sums; when enough lanes have moved on to another
+// cell, the current sums are flushed and that cell becomes current; the
+// remaining in-window lanes add directly into the window, and lanes outside
+// the window add to the FP64 global accumulators.
+template <int NDIM, int SHAPE>
+__device__ __forceinline__ void dep_step(DepState<Stencil<NDIM, SHAPE>::T>& D, bool live,
+                                         bool inwin, bool mover, const int* slot, const float* wt,
+                                         float q, float vx, float vy, float vz, double* win,
+                                         int i, int j, int k, int mx, int my, int mz,
+                                         const int* sx, const int* sy, const int* sz,
+                                         const Geo& g, double* __restrict__ acc) {
+  constexpr int T = Stencil<NDIM, SHAPE>::T;
   const int lane = threadIdx.x & 63;
   const int key = (live && inwin) ? slot[0] : -1;
-  uint64_t pend = __ballot(key >= 0);
-#pragma unroll 1
-  for (int grp = 0; grp < 2 && pend != 0; ++grp) {
-    const int leader = __builtin_ctzll(pend);
-    const int lkey = __builtin_amdgcn_readlane(key, leader);
-    const uint64_t members = __ballot(key == lkey) & pend;
-    if (__builtin_popcountll(members) < kGroupMin) break;
-    const bool in = (members >> lane) & 1ull;
-    const uint32_t rowbits = (uint32_t)(members >> (lane & 48)) & 0xFFFFu;
-    const bool adder = in && (lane & 15) == __builtin_ctz(rowbits | 0x10000u);
+  const bool mine = key >= 0 && key == D.cur;
+  dep_accumulate<T>(D, mine, q, wt, vx, vy, vz);
+  uint64_t pend = __ballot(key >= 0 && !mine);
+  if (pend) {
+    const uint64_t settled = __ballot(key >= 0 && !mine && !mover);
+    const int src = 63 - __builtin_clzll(settled ? settled : pend);
+    const int nkey = __builtin_amdgcn_readlane(key, src);
+    const uint64_t grp = __ballot(key == nkey) & pend;
+    if (__builtin_popcountll(grp) >= kGroupMin) {
+      dep_flush<T>(D, win);
+      D.cur = nkey;
 #pragma unroll
-    for (int t = 0; t < T; ++t) {
-      const float nq = in ? q * wt[t] : 0.0f;
-      const float s0 = row_sum(nq);
-      const float s1 = row_sum(nq * vx);
-      const float s2 = row_sum(nq * vy);
-      const float s3 = row_sum(nq * vz);
-      if (adder) {
-        atomicAdd(win + slot[t] + 0, (double)s0);
-        atomicAdd(win + slot[t] + 1, (double)s1);
-        atomicAdd(win + slot[t] + 2, (double)s2);
-        atomicAdd(win + slot[t] + 3, (double)s3);
-      }
+      for (int t = 0; t < T; ++t) D.cslot[t] = __builtin_amdgcn_readlane(slot[t], src);
+      dep_accumulate<T>(D, (grp >> lane) & 1ull, q, wt, vx, vy, vz);
+      pend &= ~grp;
     }
-    pend &= ~members;
-  }
-  if ((pend >> lane) & 1ull) {
+    if ((pend >> lane) & 1ull) {
 #pragma unroll
-    for (int t = 0; t < T; ++t) {
-      const float nq = q * wt[t];
-      atomicAdd(win + slot[t] + 0, (double)nq);
-      atomicAdd(win + slot[t] + 1, (double)(nq * vx));
-      atomicAdd(win + slot[t] + 2, (double)(nq * vy));
-      atomicAdd(win + slot[t] + 3, (double)(nq * vz));
+      for (int t = 0; t < T; ++t) {
+        const float nq = q * wt[t];
+        atomicAdd(win + slot[t] + 0, (double)nq);
+        atomicAdd(win + slot[t] + 1, (double)(nq * vx));
+        atomicAdd(win + slot[t] + 2, (double)(nq * vy));
+        atomicAdd(win + slot[t] + 3, (double)(nq * vz));
+      }
     }
   }
   if (live && !inwin) {
@@ -301,24 +363,72 @@ __device__ __forceinline__ void deposit_lane(bool live, bool inwin, int rel, int
   }
 }
 
-// Window geometry for a chunk whose first and last particles sit in c0, c1.
+// Window geometry for a chunk whose first and last particles sit in c0, c1:
+// deposit window width W = span + 4, gather window width W - 2.
 template <int NDIM>
 __device__ __forceinline__ bool window_ok(int c0, int c1, const Geo& g, int& W) {
   W = c1 - c0 + 5;
-  const int wmax = NDIM == 2 ? kWmax2 : kWmax3;
-  return c0 >= 0 && c1 < g.ncell && c1 >= c0 && W <= wmax && g.nx >= 4 &&
+  return c0 >= 0 && c1 < g.ncell && c1 >= c0 && W <= Chunk<NDIM>::WMAX && g.nx >= 4 &&
          (NDIM == 2 || g.ny >= 4);
 }
 
+__device__ __forceinline__ int64_t window_cell(int c0, int margin, int off, int by, int bz,
+                                               const Geo& g) {
+  int64_t c = (int64_t)c0 - margin + off + (int64_t)by * g.nx + (int64_t)bz * g.nxny;
+  c %= g.ncell;
+  return c < 0 ? c + g.ncell : c;
+}
+
+// E and B of the gather window, two float4 per cell: (Ex,Ey,Ez,0),(Bx,By,Bz,0).
 template <int NDIM>
-__device__ __forceinline__ int window_len(int W) {
-  return (NDIM == 2 ? kBands : kBands * kBands) * W * 4;
+__device__ void gather_window_fill(float4* geb, int WG, int c0, const Geo& g,
+                                   const float* __restrict__ E, const float* __restrict__ B) {
+  const int len = Chunk<NDIM>::GB * WG;
+  const int nc = g.ncell;
+  for (int s = threadIdx.x; s < len; s += kBlock) {
+    const int band = s / WG, off = s - band * WG;
+    const int by = band % kGBands - 1, bz = band / kGBands - 1;
+    const int64_t c = window_cell(c0, 1, off, by, bz, g);
+    geb[2 * s] = make_float4(__ldg(E + c), __ldg(E + nc + c), __ldg(E + 2 * nc + c), 0.0f);
+    geb[2 * s + 1] = make_float4(__ldg(B + c), __ldg(B + nc + c), __ldg(B + 2 * nc + c), 0.0f);
+  }
+}
+
+// Gather from the window for a particle of cell c0 + rel.
+template <int NDIM, int SHAPE>
+__device__ __forceinline__ void gather_window(const float4* geb, int WG, int rel, int i, int j,
+                                              float x, float y, float z, const Geo& g,
+                                              float Ep[3], float Bp[3]) {
+  constexpr int T = Stencil<NDIM, SHAPE>::T;
+  float wt[T];
+  int sx[T], sy[T], sz[T];
+  stencil_weights<NDIM, SHAPE>(x, y, z, wt, sx, sy, sz);
+  Ep[0] = Ep[1] = Ep[2] = Bp[0] = Bp[1] = Bp[2] = 0.0f;
+#pragma unroll
+  for (int t = 0; t < T; ++t) {
+    const int it = i + sx[t];
+    const int wx = it < 0 ? 1 : (it >= g.nx ? -1 : 0);
+    int band = sy[t] + wx + 1;
+    if (NDIM == 3) {
+      const int jt = j + sy[t];
+      const int wy = jt < 0 ? 1 : (jt >= g.ny ? -1 : 0);
+      band += kGBands * (sz[t] + wy + 1);
+    }
+    const int s = band * WG + rel + sx[t] + 1;
+    const float4 e = geb[2 * s], b = geb[2 * s + 1];
+    Ep[0] = fmaf(wt[t], e.x, Ep[0]);
+    Ep[1] = fmaf(wt[t], e.y, Ep[1]);
+    Ep[2] = fmaf(wt[t], e.z, Ep[2]);
+    Bp[0] = fmaf(wt[t], b.x, Bp[0]);
+    Bp[1] = fmaf(wt[t], b.y, Bp[1]);
+    Bp[2] = fmaf(wt[t], b.z, Bp[2]);
+  }
 }
 
 template <int NDIM>
 __device__ void window_flush(const double* win, int W, int c0, const Geo& g,
                              double* __restrict__ acc) {
-  const int len = window_len<NDIM>(W);
+  const int len = Chunk<NDIM>::DB * W * 4;
   for (int s = threadIdx.x; s < len; s += kBlock) {
     const double v = win[s];
     if (v == 0.0) continue;
@@ -326,11 +436,7 @@ __device__ void window_flush(const double* win, int W, int c0, const Geo& g,
     const int cellslot = s >> 2;
     const int band = cellslot / W;
     const int off = cellslot - band * W;
-    const int by = band % kBands - 3;
-    const int bz = band / kBands - 3;
-    int64_t c = (int64_t)c0 - 2 + off + (int64_t)by * g.nx + (int64_t)bz * g.nxny;
-    c %= g.ncell;
-    if (c < 0) c += g.ncell;
+    const int64_t c = window_cell(c0, 2, off, band % kBands - 3, band / kBands - 3, g);
     unsafeAtomicAdd(acc + (int64_t)ch * g.ncell + c, v);
   }
 }
@@ -340,31 +446,36 @@ __device__ void window_flush(const double* win, int W, int c0, const Geo& g,
 template <int NDIM, int SHAPE, bool DEP>
 __global__ __launch_bounds__(kBlock) void k_gather_push(PushArgs A) {
   constexpr int PPT = Chunk<NDIM>::PPT;
-  __shared__ double win[DEP ? (NDIM == 2 ? kWin2 : kWin3) : 1];
+  constexpr int T = Stencil<NDIM, SHAPE>::T;
+  __shared__ float4 geb[Chunk<NDIM>::G_LEN];
+  __shared__ double win[DEP ? Chunk<NDIM>::DEP_LEN : 1];
   __shared__ int s_c[2];
   const Geo& g = A.g;
   const int64_t base = (int64_t)blockIdx.x * Chunk<NDIM>::N;
   const int64_t end = min(base + (int64_t)Chunk<NDIM>::N, A.n);
-
-  int W = 0, c0 = 0;
-  bool wok = false;
-  if (DEP) {
-    if (threadIdx.x == 0) {
-      s_c[0] = A.cell[base];
-      s_c[1] = A.cell[end - 1];
-    }
-    __syncthreads();
-    c0 = s_c[0];
-    wok = window_ok<NDIM>(c0, s_c[1], g, W);
-    if (wok)
-      for (int s = threadIdx.x; s < window_len<NDIM>(W); s += kBlock) win[s] = 0.0;
-    __syncthreads();
+  if (threadIdx.x == 0) {
+    s_c[0] = A.cell[base];
+    s_c[1] = A.cell[end - 1];
   }
+  __syncthreads();
+  const int c0 = s_c[0], span = s_c[1] - s_c[0];
+  int W = 0;
+  const bool wok = window_ok<NDIM>(c0, s_c[1], g, W);
+  if (wok) {
+    gather_window_fill<NDIM>(geb, W - 2, c0, g, A.E, A.B);
+    if (DEP)
+      for (int s = threadIdx.x; s < Chunk<NDIM>::DB * W * 4; s += kBlock) win[s] = 0.0;
+  }
+  __syncthreads();
 
+  const int lane = threadIdx.x & 63;
+  const int64_t wbase = base + (int64_t)(threadIdx.x >> 6) * 64 * PPT;
   const bool want_diag = A.diag_part != nullptr;
-  double dK = 0.0, dP[3] = {0.0, 0.0, 0.0};
+  float dK = 0.f, dP0 = 0.f, dP1 = 0.f, dP2 = 0.f;
+  DepState<T> D;
+  if (DEP) dep_init<T>(D);
   for (int it = 0; it < PPT; ++it) {
-    const int64_t idx = base + (int64_t)it * kBlock + threadIdx.x;
+    const int64_t idx = wbase + it * 64 + lane;
     bool live = idx < end;
     int a = 0;
     float x = 0.f, y = 0.f, z = 0.f, vx = 0.f, vy = 0.f, vz = 0.f, wq = 0.f;
@@ -382,12 +493,17 @@ __global__ __launch_bounds__(kBlock) void k_gather_push(PushArgs A) {
         live = false;
       }
     }
+    const int rel = a - c0;
+    const bool in_window = wok && rel >= 0 && rel <= span;
     int i = 0, j = 0, k = 0, mx = 0, my = 0, mz = 0;
     float xm = 0.f, ym = 0.f, zm = 0.f;
     if (live) {
       decompose(a, g, i, j, k);
       float Ep[3], Bp[3];
-      gather_eb<NDIM, SHAPE>(A.E, A.B, a, i, j, k, x, y, z, g, Ep, Bp);
+      if (in_window)
+        gather_window<NDIM, SHAPE>(geb, W - 2, rel, i, j, x, y, z, g, Ep, Bp);
+      else
+        gather_eb<NDIM, SHAPE>(A.E, A.B, a, i, j, k, x, y, z, g, Ep, Bp);
       // Boris: half kick, rotation, half kick.
       const float h = A.a;
       const float vmx = fmaf(h, Ep[0], vx), vmy = fmaf(h, Ep[1], vy), vmz = fmaf(h, Ep[2], vz);
@@ -401,12 +517,10 @@ __global__ __launch_bounds__(kBlock) void k_gather_push(PushArgs A) {
       const float nvy = fmaf(h, Ep[1], vmy + (pz * sx - px * sz));
       const float nvz = fmaf(h, Ep[2], vmz + (px * sy - py * sx));
       if (want_diag) {
-        const double mw = A.ms * (double)wq;
-        dK += 0.5 * mw *
-              ((double)vx * nvx + (double)vy * nvy + (double)vz * nvz);
-        dP[0] += 0.5 * mw * ((double)vx + nvx);
-        dP[1] += 0.5 * mw * ((double)vy + nvy);
-        dP[2] += 0.5 * mw * ((double)vz + nvz);
+        dK = fmaf(wq, vx * nvx + vy * nvy + vz * nvz, dK);
+        dP0 = fmaf(wq, vx + nvx, dP0);
+        dP1 = fmaf(wq, vy + nvy, dP1);
+        dP2 = fmaf(wq, vz + nvz, dP2);
       }
       // Move: x^{n+1} = x^n + v^{n+1/2} dt, renormalised offsets.
       float nx_ = fmaf(nvx, A.kx, x), ny_ = fmaf(nvy, A.ky, y), nz_ = z;
@@ -450,15 +564,20 @@ __global__ __launch_bounds__(kBlock) void k_gather_push(PushArgs A) {
       }
     }
     if (DEP) {
-      const int rel = a - c0;
-      const bool inwin = wok && rel >= 0 && rel + 5 <= W && mx >= -1 && mx <= 1 && my >= -1 &&
-                         my <= 1 && mz >= -1 && mz <= 1;
-      deposit_lane<NDIM, SHAPE>(live, inwin, rel, i, j, k, mx, my, mz, xm, ym, zm, A.qV * wq, vx,
-                                vy, vz, win, W, g, A.acc);
+      float wt[T];
+      int sxs[T], sys[T], szs[T], slot[T];
+      stencil_weights<NDIM, SHAPE>(xm, ym, zm, wt, sxs, sys, szs);
+      const bool inwin = in_window && mx >= -1 && mx <= 1 && my >= -1 && my <= 1 && mz >= -1 &&
+                         mz <= 1;
+      deposit_slots<NDIM, SHAPE>(rel, i, j, mx, my, mz, sxs, sys, szs, W, g, slot);
+      dep_step<NDIM, SHAPE>(D, live, inwin, (mx | my | mz) != 0, slot, wt, A.qV * wq, vx, vy, vz,
+                            win, i, j, k, mx, my, mz, sxs, sys, szs, g, A.acc);
     }
   }
+  if (DEP) dep_flush<T>(D, win);
   if (want_diag) {
-    double v[4] = {dK, dP[0], dP[1], dP[2]};
+    const double hm = 0.5 * A.ms;
+    double v[4] = {hm * dK, hm * dP0, hm * dP1, hm * dP2};
     block_partial<4>(v, A.diag_part);
   }
   if (DEP && wok) {
@@ -470,7 +589,8 @@ __global__ __launch_bounds__(kBlock) void k_gather_push(PushArgs A) {
 template <int NDIM, int SHAPE>
 __global__ __launch_bounds__(kBlock) void k_deposit(DepArgs A) {
   constexpr int PPT = Chunk<NDIM>::PPT;
-  __shared__ double win[NDIM == 2 ? kWin2 : kWin3];
+  constexpr int T = Stencil<NDIM, SHAPE>::T;
+  __shared__ double win[Chunk<NDIM>::DEP_LEN];
   __shared__ int s_c[2];
   const Geo& g = A.g;
   const int64_t base = (int64_t)blockIdx.x * Chunk<NDIM>::N;
@@ -480,14 +600,18 @@ __global__ __launch_bounds__(kBlock) void k_deposit(DepArgs A) {
     s_c[1] = A.cell[end - 1];
   }
   __syncthreads();
-  const int c0 = s_c[0];
+  const int c0 = s_c[0], span = s_c[1] - s_c[0];
   int W = 0;
   const bool wok = window_ok<NDIM>(c0, s_c[1], g, W);
   if (wok)
-    for (int s = threadIdx.x; s < window_len<NDIM>(W); s += kBlock) win[s] = 0.0;
+    for (int s = threadIdx.x; s < Chunk<NDIM>::DB * W * 4; s += kBlock) win[s] = 0.0;
   __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int64_t wbase = base + (int64_t)(threadIdx.x >> 6) * 64 * PPT;
+  DepState<T> D;
+  dep_init<T>(D);
   for (int it = 0; it < PPT; ++it) {
-    const int64_t idx = base + (int64_t)it * kBlock + threadIdx.x;
+    const int64_t idx = wbase + it * 64 + lane;
     bool live = idx < end;
     int a = 0, i = 0, j = 0, k = 0, mx = 0, my = 0, mz = 0;
     float x = 0.f, y = 0.f, z = 0.f, vx = 0.f, vy = 0.f, vz = 0.f, q = 0.f;
@@ -518,11 +642,16 @@ __global__ __launch_bounds__(kBlock) void k_deposit(DepArgs A) {
       }
     }
     const int rel = a - c0;
-    const bool inwin = wok && rel >= 0 && rel + 5 <= W && mx >= -1 && mx <= 1 && my >= -1 &&
+    const bool inwin = wok && rel >= 0 && rel <= span && mx >= -1 && mx <= 1 && my >= -1 &&
                        my <= 1 && mz >= -1 && mz <= 1;
-    deposit_lane<NDIM, SHAPE>(live, inwin, rel, i, j, k, mx, my, mz, x, y, z, q, vx, vy, vz, win,
-                              W, g, A.acc);
+    float wt[T];
+    int sxs[T], sys[T], szs[T], slot[T];
+    stencil_weights<NDIM, SHAPE>(x, y, z, wt, sxs, sys, szs);
+    deposit_slots<NDIM, SHAPE>(rel, i, j, mx, my, mz, sxs, sys, szs, W, g, slot);
+    dep_step<NDIM, SHAPE>(D, live, inwin, (mx | my | mz) != 0, slot, wt, q, vx, vy, vz, win, i, j,
+                          k, mx, my, mz, sxs, sys, szs, g, A.acc);
   }
+  dep_flush<T>(D, win);
   if (wok) {
     __syncthreads();
     window_flush<NDIM>(win, W, c0, g, A.acc);
