@@ -104,46 +104,95 @@ __device__ __forceinline__ uint64_t match_code(int code, uint64_t valid, const u
 
 // ------------------------------------------------------- neighbour path --
 
+// Each wavefront handles kCellsPerWave consecutive old cells and streams
+// their particles in full 64-lane batches (a batch may straddle cells).
+constexpr int kCellsPerWave = 2;
+constexpr int kCellBits = 1;
+constexpr int kCountBatches = 4;    // 64-particle batches whose keys are loaded together
+constexpr int kScatterBatches = 4;  // batches whose fields are loaded together
+
+// Boundaries of the wavefront's cells: b(m) = cs_prev[a0 + m], m = 0..na,
+// held by lane m.  Returns false if they are not a monotone partition of
+// [0, n] (then nothing of the wavefront is trusted).
+__device__ __forceinline__ bool wave_bounds(const int32_t* cs_prev, int a0, int na, int64_t n,
+                                            int lane, int& bnd) {
+  bnd = lane <= na ? cs_prev[a0 + lane] : 0;
+  const int prev = __shfl_up(bnd, 1);
+  const bool bad = lane <= na && (bnd < 0 || bnd > n || (lane > 0 && bnd < prev));
+  return __ballot(bad) == 0;
+}
+
+// Cell index m (0..na-1) within the wavefront of particle p, from the
+// boundaries b(1..na-1) read from lanes 1..na-1 (all lanes must call it).
+__device__ __forceinline__ int cell_in_wave(int64_t p, int bnd, int na) {
+  int m = 0;
+  for (int q = 1; q < na; ++q) m += p >= (int64_t)__builtin_amdgcn_readlane(bnd, q) ? 1 : 0;
+  return m;
+}
+
 template <int NDIM>
 __global__ __launch_bounds__(kBlock) void k_nb_count(const int32_t* __restrict__ key,
                                                      const int32_t* __restrict__ cs_prev, int64_t n,
                                                      SortGeo g, uint32_t* __restrict__ cnt,
                                                      Status* st) {
   constexpr int ND = Dirs<NDIM>::N, NB = Dirs<NDIM>::BITS;
-  const int a = blockIdx.x * kWaves + (threadIdx.x >> 6);
-  if (a >= g.ncell) return;
-  const int lane = threadIdx.x & 63;
-  int64_t s0 = cs_prev[a], s1 = cs_prev[a + 1];
-  if (s0 < 0 || s1 > n || s1 < s0) {
+  constexpr int CODE_BITS = NB + kCellBits;
+  __shared__ uint32_t s_cnt[kWaves][kCellsPerWave * ND];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int a0 = (blockIdx.x * kWaves + wid) * kCellsPerWave;
+  const int na = a0 < g.ncell ? min(kCellsPerWave, g.ncell - a0) : 0;
+  for (int q = lane; q < kCellsPerWave * ND; q += 64) s_cnt[wid][q] = 0;
+  __syncthreads();
+  if (na == 0) return;
+  int bnd;
+  if (!wave_bounds(cs_prev, a0, na, n, lane, bnd)) {
     if (lane == 0) {
       raise_flag(st, HVPIC_FLAG_BAD_INPUT, &st->bad_input);
       __hip_atomic_store(&st->far_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    s0 = s1 = 0;
+    return;
   }
-  int i, j, k;
-  ijk(a, g, i, j, k);
-  uint32_t count = 0;  // lane L < ND counts direction L
+  const int64_t pb = __builtin_amdgcn_readlane(bnd, 0), pe = __builtin_amdgcn_readlane(bnd, na);
   bool far = false;
-  for (int64_t base = s0; base < s1; base += 64) {
-    const int64_t p = base + lane;
-    const bool valid = p < s1;
-    int d = 0;
-    if (valid) {
-      d = direction<NDIM>(key[p], i, j, k, g);
-      far |= d < 0;
-    }
-    uint64_t bal[NB];
-    const uint64_t vmask = __ballot(valid && d >= 0);
+  for (int64_t q0 = pb; q0 < pe; q0 += 64 * kCountBatches) {
+   int keys[kCountBatches];
 #pragma unroll
-    for (int b = 0; b < NB; ++b) bal[b] = __ballot(valid && d >= 0 && ((d >> b) & 1));
-    if (lane < ND) count += (uint32_t)__builtin_popcountll(match_code<NB>(lane, vmask, bal));
+   for (int b = 0; b < kCountBatches; ++b) {
+     const int64_t p = q0 + b * 64 + lane;
+     keys[b] = p < pe ? key[p] : 0;
+   }
+#pragma unroll
+   for (int b = 0; b < kCountBatches; ++b) {
+    const int64_t p = q0 + b * 64 + lane;
+    const bool valid = p < pe;
+    int code = 0;
+    bool ok = false;
+    const int m = cell_in_wave(p, bnd, na);
+    if (valid) {
+      int i, j, k;
+      ijk(a0 + m, g, i, j, k);
+      const int d = direction<NDIM>(keys[b], i, j, k, g);
+      far |= d < 0;
+      ok = d >= 0;
+      code = (m << NB) | (ok ? d : 0);
+    }
+    uint64_t bal[CODE_BITS];
+    const uint64_t vmask = __ballot(ok);
+#pragma unroll
+    for (int b = 0; b < CODE_BITS; ++b) bal[b] = __ballot(ok && ((code >> b) & 1));
+    const uint64_t mine = match_code<CODE_BITS>(code, vmask, bal);
+    if (ok && (mine & lanemask_lt()) == 0) {
+      const int mm = code >> NB, d = code & ((1 << NB) - 1);
+      s_cnt[wid][mm * ND + d] += (uint32_t)__builtin_popcountll(mine);
+    }
+    __builtin_amdgcn_wave_barrier();
+   }
   }
   if (__ballot(far) && lane == 0) {
     atomicOr(&st->flags, (uint32_t)HVPIC_FLAG_MOVE_GT1);
     __hip_atomic_store(&st->far_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
-  if (lane < ND) cnt[(int64_t)a * ND + lane] = count;
+  for (int q = lane; q < na * ND; q += 64) cnt[(int64_t)a0 * ND + q] = s_cnt[wid][q];
 }
 
 // Block-level exclusive scan of kScanTile values held in LDS `s`; returns the
@@ -503,6 +552,7 @@ __global__ __launch_bounds__(kBlock) void k_nb_scatter(const int32_t* __restrict
                                                        const Status* st, uint32_t* rk0, uint32_t* rk1,
                                                        uint32_t* rv0, uint32_t* rv1) {
   constexpr int ND = Dirs<NDIM>::N, NB = Dirs<NDIM>::BITS;
+  constexpr int CODE_BITS = NB + kCellBits;
   if (__hip_atomic_load(&st->far_decision, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
     if (blockIdx.x == 0) {
       uint32_t* rkey[2] = {rk0, rk1};
@@ -511,40 +561,61 @@ __global__ __launch_bounds__(kBlock) void k_nb_scatter(const int32_t* __restrict
     }
     return;
   }
-  const int a = blockIdx.x * kWaves + (threadIdx.x >> 6);
-  if (a >= g.ncell) return;
-  const int lane = threadIdx.x & 63;
-  const int64_t s0 = cs_prev[a], s1 = cs_prev[a + 1];
-  if (s0 < 0 || s1 > n || s1 < s0) return;
-  int i, j, k;
-  ijk(a, g, i, j, k);
-  const uint32_t mybase = lane < ND ? bases[(int64_t)a * ND + lane] : 0u;
-  uint32_t running = 0;
-  for (int64_t base = s0; base < s1; base += 64) {
-    const int64_t p = base + lane;
-    const bool valid = p < s1;
-    int d = 0, key = 0;
+  __shared__ uint32_t s_next[kWaves][kCellsPerWave * ND];  // next free slot of each group
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int a0 = (blockIdx.x * kWaves + wid) * kCellsPerWave;
+  const int na = a0 < g.ncell ? min(kCellsPerWave, g.ncell - a0) : 0;
+  for (int q = lane; q < na * ND; q += 64) s_next[wid][q] = bases[(int64_t)a0 * ND + q];
+  __syncthreads();
+  if (na == 0) return;
+  int bnd;
+  if (!wave_bounds(cs_prev, a0, na, n, lane, bnd)) return;
+  const int64_t pb = __builtin_amdgcn_readlane(bnd, 0), pe = __builtin_amdgcn_readlane(bnd, na);
+  for (int64_t q0 = pb; q0 < pe; q0 += 64 * kScatterBatches) {
+   int keys[kScatterBatches];
+   float vals[kScatterBatches][7];
+#pragma unroll
+   for (int b = 0; b < kScatterBatches; ++b) {
+     const int64_t p = q0 + b * 64 + lane;
+     const bool v = p < pe;
+     keys[b] = v ? in.cell[p] : 0;
+#pragma unroll
+     for (int f = 0; f < 7; ++f) vals[b][f] = (v && in.f[f]) ? in.f[f][p] : 0.0f;
+   }
+#pragma unroll
+   for (int b = 0; b < kScatterBatches; ++b) {
+    const int64_t p = q0 + b * 64 + lane;
+    const bool valid = p < pe;
+    int code = 0;
+    const int key = keys[b];
+    bool ok = false;
+    const int m = cell_in_wave(p, bnd, na);
     if (valid) {
-      key = in.cell[p];
-      d = direction<NDIM>(key, i, j, k, g);
+      int i, j, k;
+      ijk(a0 + m, g, i, j, k);
+      const int d = direction<NDIM>(key, i, j, k, g);
+      ok = d >= 0;
+      code = (m << NB) | (ok ? d : 0);
     }
-    const bool ok = valid && d >= 0;
-    uint64_t bal[NB];
+    uint64_t bal[CODE_BITS];
     const uint64_t vmask = __ballot(ok);
 #pragma unroll
-    for (int b = 0; b < NB; ++b) bal[b] = __ballot(ok && ((d >> b) & 1));
-    const uint64_t mine = match_code<NB>(d, vmask, bal);
-    const uint32_t grp_base = __shfl(mybase + running, ok ? d : 0);
-    if (lane < ND) running += (uint32_t)__builtin_popcountll(match_code<NB>(lane, vmask, bal));
-    if (ok) {
-      const int64_t dst = (int64_t)grp_base + __builtin_popcountll(mine & lanemask_lt());
-      if (dst < n) {
-        out.cell[dst] = key;
+    for (int b = 0; b < CODE_BITS; ++b) bal[b] = __ballot(ok && ((code >> b) & 1));
+    const uint64_t mine = match_code<CODE_BITS>(code, vmask, bal);
+    const uint64_t before = mine & lanemask_lt();
+    const int slot = (code >> NB) * ND + (code & ((1 << NB) - 1));
+    uint32_t dst = 0;
+    if (ok) dst = s_next[wid][slot] + (uint32_t)__builtin_popcountll(before);
+    __builtin_amdgcn_wave_barrier();
+    if (ok && before == 0) s_next[wid][slot] += (uint32_t)__builtin_popcountll(mine);
+    __builtin_amdgcn_wave_barrier();
+    if (ok && dst < n) {
+      out.cell[dst] = key;
 #pragma unroll
-        for (int f = 0; f < 7; ++f)
-          if (in.f[f]) out.f[f][dst] = in.f[f][p];
-      }
+      for (int f = 0; f < 7; ++f)
+        if (in.f[f]) out.f[f][dst] = vals[b][f];
     }
+   }
   }
 }
 
@@ -614,7 +685,7 @@ void enqueue_neighbour(hvpic_ctx* c, const hvpic_particles* in, hvpic_particles*
                        const int32_t* cs_prev, int32_t* cs) {
   hipStream_t s = c->stream;
   const SortGeo g = sort_geo(c);
-  const int cblocks = (int)ceil_div(c->ncell, kWaves);
+  const int cblocks = (int)ceil_div(c->ncell, kWaves * kCellsPerWave);
   const int tiles = (int)ceil_div(c->ncell, kScanTile);
   uint32_t* blk = (uint32_t*)c->sort_blk;
   hipLaunchKernelGGL((k_nb_count<NDIM>), dim3(cblocks), dim3(kBlock), 0, s, in->cell, cs_prev,
