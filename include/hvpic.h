@@ -180,6 +180,26 @@ int hvpic_smooth(hvpic_ctx* ctx, float* F, int ncomp, int npasses);
    cell, non-finite/runaway particles, floor hits}; then clears them. */
 int hvpic_sync_status(hvpic_ctx* ctx, uint32_t* flags, int64_t* counts);
 
+/* Kernel timing on the context's stream (a measurement aid, not part of the
+   method).  hvpic_timing_enable(ctx, max_launches) creates HIP event pairs
+   for up to max_launches launches of each timed kernel (max_launches = 0
+   switches timing off and frees the events; at most 65536).  While enabled,
+   every launch of a timed kernel is bracketed by events recorded on the
+   context's stream, directly around that one kernel.  hvpic_timing_read
+   waits for the stream and returns, for kernel id `kernel`, the summed
+   duration in milliseconds and the number of timed launches, then restarts
+   the count.  Launches beyond max_launches are not timed.  Returns
+   HVPIC_EINVAL for an unknown id or max_launches out of range, HVPIC_EHIP if
+   an event call fails. */
+enum {
+  HVPIC_KERNEL_GATHER_PUSH = 0,  /* fused gather + Boris push (+ deposit) */
+  HVPIC_KERNEL_DEPOSIT = 1,      /* stand-alone moment deposit */
+  HVPIC_KERNEL_SORT_SCATTER = 2, /* neighbour-move sort scatter */
+  HVPIC_KERNEL_COUNT = 3
+};
+int hvpic_timing_enable(hvpic_ctx* ctx, int max_launches);
+int hvpic_timing_read(hvpic_ctx* ctx, int kernel, double* total_ms, int64_t* launches);
+
 /* Static description of an error code. */
 const char* hvpic_strerror(int code);
 

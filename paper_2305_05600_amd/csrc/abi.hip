@@ -149,6 +149,7 @@ int hvpic_init(const hvpic_params* params, void* hip_stream, void* workspace, hv
 
 int hvpic_finalize(hvpic_ctx* ctx) {
   if (!ctx_ok(ctx)) return HVPIC_ESTATE;
+  hvpic_timing_enable(ctx, 0);
   ctx->magic = 0;
   delete ctx;
   return HVPIC_OK;
@@ -217,6 +218,56 @@ int hvpic_sync_status(hvpic_ctx* ctx, uint32_t* flags, int64_t* counts) {
   hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(64), 0, ctx->stream, ctx->status);
   if (hipGetLastError() != hipSuccess) return HVPIC_EHIP;
   if (hipStreamSynchronize(ctx->stream) != hipSuccess) return HVPIC_EHIP;
+  return HVPIC_OK;
+}
+
+int hvpic_timing_enable(hvpic_ctx* ctx, int max_launches) {
+  if (!ctx_ok(ctx)) return HVPIC_ESTATE;
+  if (max_launches < 0 || max_launches > 65536) return HVPIC_EINVAL;
+  int rc = HVPIC_OK;
+  if (ctx->tev) {
+    if (hipStreamSynchronize(ctx->stream) != hipSuccess) rc = HVPIC_EHIP;
+    const int64_t ne = (int64_t)HVPIC_KERNEL_COUNT * ctx->tmax * 2;
+    for (int64_t i = 0; i < ne; ++i)
+      if (ctx->tev[i]) (void)hipEventDestroy(ctx->tev[i]);
+    delete[] ctx->tev;
+    ctx->tev = nullptr;
+  }
+  ctx->tmax = 0;
+  for (int k = 0; k < HVPIC_KERNEL_COUNT; ++k) ctx->tcount[k] = 0;
+  if (max_launches == 0 || rc != HVPIC_OK) return rc;
+  const int64_t ne = (int64_t)HVPIC_KERNEL_COUNT * max_launches * 2;
+  hipEvent_t* ev = new (std::nothrow) hipEvent_t[ne];
+  if (!ev) return HVPIC_ENOMEM;
+  for (int64_t i = 0; i < ne; ++i) ev[i] = nullptr;
+  for (int64_t i = 0; i < ne; ++i)
+    if (hipEventCreate(&ev[i]) != hipSuccess) {
+      for (int64_t j = 0; j < i; ++j) (void)hipEventDestroy(ev[j]);
+      delete[] ev;
+      return HVPIC_EHIP;
+    }
+  ctx->tev = ev;
+  ctx->tmax = max_launches;
+  return HVPIC_OK;
+}
+
+int hvpic_timing_read(hvpic_ctx* ctx, int kernel, double* total_ms, int64_t* launches) {
+  if (!ctx_ok(ctx)) return HVPIC_ESTATE;
+  if (kernel < 0 || kernel >= HVPIC_KERNEL_COUNT || !total_ms || !launches) return HVPIC_EINVAL;
+  *total_ms = 0.0;
+  *launches = 0;
+  if (!ctx->tev) return HVPIC_OK;
+  if (hipStreamSynchronize(ctx->stream) != hipSuccess) return HVPIC_EHIP;
+  double t = 0.0;
+  for (int i = 0; i < ctx->tcount[kernel]; ++i) {
+    float ms = 0.f;
+    const int64_t e = ((int64_t)kernel * ctx->tmax + i) * 2;
+    if (hipEventElapsedTime(&ms, ctx->tev[e], ctx->tev[e + 1]) != hipSuccess) return HVPIC_EHIP;
+    t += ms;
+  }
+  *total_ms = t;
+  *launches = ctx->tcount[kernel];
+  ctx->tcount[kernel] = 0;
   return HVPIC_OK;
 }
 

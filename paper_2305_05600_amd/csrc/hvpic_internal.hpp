@@ -68,8 +68,19 @@ __device__ void sum_partials(const double* part, int nblocks, double* res) {
   __shared__ double s_red[16][NV];
   double t[NV];
   for (int k = 0; k < NV; ++k) t[k] = 0.0;
-  for (int b = threadIdx.x; b < nblocks; b += blockDim.x)
-    for (int k = 0; k < NV; ++k) t[k] += part[(int64_t)b * 4 + k];
+  // eight independent loads in flight per thread and step
+  const int stride = blockDim.x;
+  for (int b0 = threadIdx.x; b0 < nblocks; b0 += 8 * stride) {
+    double v[8][NV];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int b = b0 + u * stride;
+      for (int k = 0; k < NV; ++k) v[u][k] = b < nblocks ? part[(int64_t)b * 4 + k] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      for (int k = 0; k < NV; ++k) t[k] += v[u][k];
+  }
   for (int k = 0; k < NV; ++k)
     for (int o = 32; o > 0; o >>= 1) t[k] += __shfl_xor(t[k], o);
   const int wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
@@ -115,6 +126,10 @@ struct hvpic_ctx {
   uint32_t* rhist;       // radix per-block digit counts
   float* fscratch;       // field scratch [20][ncell]
   double* mom_acc;       // FP64 moment accumulators [4][ncell], kept at zero between deposits
+  // optional per-kernel timing: event pairs [kernel][slot][2]
+  hipEvent_t* tev;
+  int tmax;
+  int tcount[HVPIC_KERNEL_COUNT];
 };
 
 namespace hvpic {
@@ -133,6 +148,18 @@ int launch_field_advance(hvpic_ctx* c, float* B, const float* n_half, const floa
                          double* diag_out);
 int launch_smooth(hvpic_ctx* c, float* F, int ncomp, int npasses);
 int launch_zero(hvpic_ctx* c, float* p, int64_t count);
+
+// Event bracket around one launch of kernel id k (no-op unless timing is on).
+inline void timing_begin(hvpic_ctx* c, int k) {
+  if (c->tev && c->tcount[k] < c->tmax)
+    (void)hipEventRecord(c->tev[((int64_t)k * c->tmax + c->tcount[k]) * 2], c->stream);
+}
+inline void timing_end(hvpic_ctx* c, int k) {
+  if (c->tev && c->tcount[k] < c->tmax) {
+    (void)hipEventRecord(c->tev[((int64_t)k * c->tmax + c->tcount[k]) * 2 + 1], c->stream);
+    ++c->tcount[k];
+  }
+}
 int launch_init_workspace(hvpic_ctx* c);
 
 // Workspace layout (bytes from the start; each region 256-byte aligned).

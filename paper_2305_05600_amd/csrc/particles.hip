@@ -765,6 +765,7 @@ int launch_gather_push(hvpic_ctx* c, hvpic_particles* p, const float* E, const f
   A.st = c->status;
   const bool qs = c->p.shape == HVPIC_SHAPE_QS;
   int nblocks = 0;
+  timing_begin(c, HVPIC_KERNEL_GATHER_PUSH);
   if (c->p.ndim == 2) {
     nblocks = (int)ceil_div(p->n, Chunk<2>::N);
     if (qs) push_dispatch<2, HVPIC_SHAPE_QS>(dep, dim3(nblocks), c->stream, A);
@@ -774,6 +775,7 @@ int launch_gather_push(hvpic_ctx* c, hvpic_particles* p, const float* E, const f
     if (qs) push_dispatch<3, HVPIC_SHAPE_QS>(dep, dim3(nblocks), c->stream, A);
     else push_dispatch<3, HVPIC_SHAPE_NGP>(dep, dim3(nblocks), c->stream, A);
   }
+  timing_end(c, HVPIC_KERNEL_GATHER_PUSH);
   if (dep) moments_out(c, n_mid, J_mid);
   if (diag_out)
     hipLaunchKernelGGL(k_push_diag_final, dim3(1), dim3(kBlock), 0, c->stream,
@@ -806,6 +808,7 @@ int launch_deposit(hvpic_ctx* c, const hvpic_particles* p, float half_dt_back, f
   A.qV = c->qV;
   A.st = c->status;
   const bool qs = c->p.shape == HVPIC_SHAPE_QS;
+  timing_begin(c, HVPIC_KERNEL_DEPOSIT);
   if (c->p.ndim == 2) {
     const dim3 grid((unsigned)ceil_div(p->n, Chunk<2>::N));
     if (qs) hipLaunchKernelGGL((k_deposit<2, HVPIC_SHAPE_QS>), grid, dim3(kBlock), 0, c->stream, A);
@@ -815,6 +818,7 @@ int launch_deposit(hvpic_ctx* c, const hvpic_particles* p, float half_dt_back, f
     if (qs) hipLaunchKernelGGL((k_deposit<3, HVPIC_SHAPE_QS>), grid, dim3(kBlock), 0, c->stream, A);
     else hipLaunchKernelGGL((k_deposit<3, HVPIC_SHAPE_NGP>), grid, dim3(kBlock), 0, c->stream, A);
   }
+  timing_end(c, HVPIC_KERNEL_DEPOSIT);
   moments_out(c, n, J);
   return hipGetLastError() == hipSuccess ? HVPIC_OK : HVPIC_EHIP;
 }

@@ -695,9 +695,11 @@ void enqueue_neighbour(hvpic_ctx* c, const hvpic_particles* in, hvpic_particles*
   hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, s, blk, tiles);
   hipLaunchKernelGGL((k_nb_bases<NDIM>), dim3(tiles), dim3(kBlock), 0, s, c->sort_cnt, g, cs,
                      (const uint32_t*)blk);
+  timing_begin(c, HVPIC_KERNEL_SORT_SCATTER);
   hipLaunchKernelGGL((k_nb_scatter<NDIM>), dim3(cblocks), dim3(kBlock), 0, s, cs_prev, in->n, g,
                      (const uint32_t*)c->sort_cnt, fields_of(in), fields_of(out), cs,
                      (const Status*)c->status, c->rkey[0], c->rkey[1], c->rval[0], c->rval[1]);
+  timing_end(c, HVPIC_KERNEL_SORT_SCATTER);
 }
 
 }  // namespace

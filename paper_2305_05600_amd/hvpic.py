@@ -23,7 +23,8 @@ FLAG_MOVE_GT1, FLAG_FLOOR_HIT, FLAG_NONFINITE, FLAG_BAD_INPUT = 1, 2, 4, 8
 
 EXPORTS = ("hvpic_workspace_bytes", "hvpic_init", "hvpic_finalize", "hvpic_gather_push",
            "hvpic_sort", "hvpic_deposit", "hvpic_field_advance", "hvpic_smooth",
-           "hvpic_sync_status", "hvpic_strerror")
+           "hvpic_sync_status", "hvpic_timing_enable", "hvpic_timing_read", "hvpic_strerror")
+KERNEL_GATHER_PUSH, KERNEL_DEPOSIT, KERNEL_SORT_SCATTER = 0, 1, 2
 
 
 class HvpicParams(ctypes.Structure):
@@ -69,6 +70,8 @@ def lib():
         L.hvpic_field_advance.argtypes = [vp, vp, vp, vp, vp, vp, vp, i32, vp]
         L.hvpic_smooth.argtypes = [vp, vp, i32, i32]
         L.hvpic_sync_status.argtypes = [vp, P(ctypes.c_uint32), P(ctypes.c_int64)]
+        L.hvpic_timing_enable.argtypes = [vp, i32]
+        L.hvpic_timing_read.argtypes = [vp, i32, P(ctypes.c_double), P(ctypes.c_int64)]
         L.hvpic_strerror.argtypes = [ctypes.c_int]
         L.hvpic_strerror.restype = ctypes.c_char_p
         for f in EXPORTS[:-1]:
@@ -232,6 +235,19 @@ def hvpic_sync_status(ctx):
     counts = (ctypes.c_int64 * 3)()
     _check(lib().hvpic_sync_status(ctx, ctypes.byref(flags), counts), "hvpic_sync_status")
     return flags.value, tuple(counts)
+
+
+def hvpic_timing_enable(ctx, max_launches: int):
+    _check(lib().hvpic_timing_enable(ctx, max_launches), "hvpic_timing_enable")
+
+
+def hvpic_timing_read(ctx, kernel: int):
+    """(summed milliseconds, number of timed launches) of kernel id `kernel`."""
+    ms = ctypes.c_double(0.0)
+    n = ctypes.c_int64(0)
+    _check(lib().hvpic_timing_read(ctx, kernel, ctypes.byref(ms), ctypes.byref(n)),
+           "hvpic_timing_read")
+    return ms.value, n.value
 
 
 def hvpic_strerror(code: int) -> str:

@@ -124,3 +124,27 @@ def test_harris_full_size_one_step(mods):
     assert rel_l2(g.B.cpu().numpy(), rB) < 1e-5
     assert rel_l2(g.E.cpu().numpy(), rE) < 1e-5
     assert np.allclose(g.push_diag.cpu().numpy(), o.push_diag, rtol=1e-5)
+
+
+def test_kernel_timing_counts_launches(mods):
+    H, S = mods
+    announce("kernel_timing")
+    cfg, parts, B = W.periodic_alfven()
+    g = S.GpuSim(cfg, parts, B, fused=True)
+    c = g.ctx.ctx
+    H.hvpic_timing_enable(c, 3)
+    for _ in range(5):
+        g.step()
+    ms, n = H.hvpic_timing_read(c, H.KERNEL_GATHER_PUSH)
+    assert n == 3 and ms > 0.0
+    ms, n = H.hvpic_timing_read(c, H.KERNEL_SORT_SCATTER)
+    assert n == 3 and ms > 0.0
+    assert H.hvpic_timing_read(c, H.KERNEL_DEPOSIT) == (0.0, 0)
+    assert H.hvpic_timing_read(c, H.KERNEL_GATHER_PUSH) == (0.0, 0)  # count restarted
+    with pytest.raises(H.HvpicError):
+        H.hvpic_timing_read(c, 7)
+    with pytest.raises(H.HvpicError):
+        H.hvpic_timing_enable(c, -1)
+    H.hvpic_timing_enable(c, 0)
+    g.step()
+    assert H.hvpic_timing_read(c, H.KERNEL_GATHER_PUSH) == (0.0, 0)
