@@ -121,9 +121,9 @@ def main() -> int:
         e = ev[s]
         e[0].record()
         if g.fused:
-            H.hvpic_gather_push(c, g.p, g.E, g.B, g.n_half, g.J_half, pd)
+            H.hvpic_gather_push(c, g.p, g.cs, g.E, g.B, g.n_half, g.J_half, pd)
         else:
-            H.hvpic_gather_push(c, g.p, g.E, g.B, None, None, pd)
+            H.hvpic_gather_push(c, g.p, g.cs, g.E, g.B, None, None, pd)
         e[1].record()
         H.hvpic_sort(c, g.p, g.q, g.cs, g.cs_alt, full=False)
         g.p, g.q = g.q, g.p

@@ -125,11 +125,23 @@ int hvpic_finalize(hvpic_ctx* ctx);
    x^{n+1/2} = x^n + (dt/2) v^{n+1/2} are also deposited in the same pass
    (overwriting n_mid [ncell] and J_mid [3][ncell]; identical in value to
    hvpic_deposit with half_dt_back = dt/2 after the push), which saves one
-   read of the particle store.  The fused deposit is fastest on a store sorted
-   by cell.  diag_out (device, may be NULL) receives 4 doubles:
-   K = sum 1/2 ms w v^{n-1/2}.v^{n+1/2} and P = sum ms w (v^{n-1/2}+v^{n+1/2})/2. */
-int hvpic_gather_push(hvpic_ctx* ctx, hvpic_particles* p, const float* E,
-                      const float* B, float* n_mid, float* J_mid, double* diag_out);
+   read of the particle store.  diag_out (device, may be NULL) receives 4
+   doubles: K = sum 1/2 ms w v^{n-1/2}.v^{n+1/2} and
+   P = sum ms w (v^{n-1/2}+v^{n+1/2})/2.
+   cell_start (device int32 [ncell+1], may be NULL): when given, p must be
+   sorted by cell with exactly this cell_start (as hvpic_sort writes it).
+   The call then also counts, for every cell, its particles moving in each
+   of the 3^ndim directions: the first pass of the neighbour-move sort, which
+   the next hvpic_sort of the same store with cell_start_prev = cell_start
+   uses instead of counting again (another push or sort in between discards
+   the counts).  A particle whose place disagrees with cell_start, or a
+   cell_start that is not a monotone partition of [0, n], raises
+   HVPIC_FLAG_BAD_INPUT and sends that sort down the general path; the push
+   itself is unaffected (every particle is pushed from its own cell).  With
+   cell_start == NULL any order is accepted; a sorted order is the fast case. */
+int hvpic_gather_push(hvpic_ctx* ctx, hvpic_particles* p, const int32_t* cell_start,
+                      const float* E, const float* B, float* n_mid, float* J_mid,
+                      double* diag_out);
 
 /* Stable counting sort by cell index: out receives the particles of `in` in
    order of cell, equal cells in input order; cell_start [ncell+1] is written.
@@ -150,8 +162,8 @@ int hvpic_sort(hvpic_ctx* ctx, const hvpic_particles* in, hvpic_particles* out,
    x - half_dt_back * v (half_dt_back = dt/2 after a push gives
    x^{n+1/2}; 0 deposits at x).  Contributions per particle: n += qs w W/V_c,
    J += qs w W u/V_c with W the shape weight of each cell.  Overwrites
-   n [ncell] and J [3][ncell].  cell_start may be NULL; when given (the store
-   is sorted) it is only used as a locality hint. */
+   n [ncell] and J [3][ncell].  Any particle order is accepted; a store
+   sorted by cell is the fast case.  cell_start is not read (may be NULL). */
 int hvpic_deposit(hvpic_ctx* ctx, const hvpic_particles* p, const int32_t* cell_start,
                   float half_dt_back, float* n, float* J);
 

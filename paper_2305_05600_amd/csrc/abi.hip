@@ -48,9 +48,10 @@ bool parts_ok(const hvpic_ctx* c, const hvpic_particles* q, bool need_w) {
 
 bool ctx_ok(const hvpic_ctx* c) { return c && c->magic == kMagic; }
 
-__global__ void k_init_ws(Status* st, double* mom, int64_t nmom) {
+__global__ void k_init_ws(Status* st, double* mom, int64_t nmom, uint32_t* cnt, int64_t ncnt) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   for (int64_t q = i; q < nmom; q += (int64_t)gridDim.x * blockDim.x) mom[q] = 0.0;
+  for (int64_t q = i; q < ncnt; q += (int64_t)gridDim.x * blockDim.x) cnt[q] = 0u;
   if (i == 0) {
     st->flags = 0;
     st->moved_gt1 = st->nonfinite = st->floor_hits = st->bad_input = 0;
@@ -77,7 +78,10 @@ Layout workspace_layout(const hvpic_params* p) {
   const int64_t nblk = std::max(ceil_div(nc, kScanTile), ceil_div(kRadixBins * ntiles, kScanTile)) + 1;
   size_t off = 0;
   L.status = off;    off += align256(sizeof(Status));
-  L.push_part = off; off += align256(sizeof(double) * 4 * ceil_div(cap, 1024));
+  // per-block partials: particle-chunk blocks (>= 1024 particles each) or
+  // cell-row blocks (>= 16 cells each)
+  L.push_part = off;
+  off += align256(sizeof(double) * 4 * std::max(ceil_div(cap, 1024), ceil_div(nc, 16)));
   L.field_part = off; off += align256(sizeof(double) * 4 * ceil_div(nc, kBlock));
   L.sort_cnt = off;  off += align256(sizeof(uint32_t) * ndir * nc);
   L.sort_blk = off;  off += align256(sizeof(uint32_t) * nblk);
@@ -138,7 +142,9 @@ int hvpic_init(const hvpic_params* params, void* hip_stream, void* workspace, hv
   c->fscratch = (float*)(c->ws + L.fscratch);
   c->mom_acc = (double*)(c->ws + L.mom_acc);
   hipLaunchKernelGGL(k_init_ws, dim3(256), dim3(256), 0, c->stream, c->status, c->mom_acc,
-                     4ll * c->ncell);
+                     4ll * c->ncell, c->sort_cnt,
+                     (int64_t)c->ncell * (params->ndim == 2 ? 9 : 27));
+  c->cnt_clean = true;
   if (hipGetLastError() != hipSuccess) {
     delete c;
     return HVPIC_EHIP;
@@ -155,13 +161,14 @@ int hvpic_finalize(hvpic_ctx* ctx) {
   return HVPIC_OK;
 }
 
-int hvpic_gather_push(hvpic_ctx* ctx, hvpic_particles* p, const float* E, const float* B,
-                      float* n_mid, float* J_mid, double* diag_out) {
+int hvpic_gather_push(hvpic_ctx* ctx, hvpic_particles* p, const int32_t* cell_start,
+                      const float* E, const float* B, float* n_mid, float* J_mid,
+                      double* diag_out) {
   if (!ctx_ok(ctx)) return HVPIC_ESTATE;
   const bool need_w = (n_mid && J_mid) || diag_out;
   if (!parts_ok(ctx, p, need_w) || !E || !B) return HVPIC_EINVAL;
   if ((n_mid == nullptr) != (J_mid == nullptr)) return HVPIC_EINVAL;
-  return launch_gather_push(ctx, p, E, B, n_mid, J_mid, diag_out);
+  return launch_gather_push(ctx, p, cell_start, E, B, n_mid, J_mid, diag_out);
 }
 
 int hvpic_sort(hvpic_ctx* ctx, const hvpic_particles* in, hvpic_particles* out,
@@ -180,10 +187,9 @@ int hvpic_sort(hvpic_ctx* ctx, const hvpic_particles* in, hvpic_particles* out,
 
 int hvpic_deposit(hvpic_ctx* ctx, const hvpic_particles* p, const int32_t* cell_start,
                   float half_dt_back, float* n, float* J) {
-  (void)cell_start;
   if (!ctx_ok(ctx)) return HVPIC_ESTATE;
   if (!parts_ok(ctx, p, true) || !n || !J || !isfinite(half_dt_back)) return HVPIC_EINVAL;
-  return launch_deposit(ctx, p, half_dt_back, n, J);
+  return launch_deposit(ctx, p, cell_start, half_dt_back, n, J);
 }
 
 int hvpic_field_advance(hvpic_ctx* ctx, float* B, const float* n_half, const float* J_half,

@@ -95,6 +95,17 @@ __device__ void sum_partials(const double* part, int nblocks, double* res) {
     }
 }
 
+// Canonical move in {-1, 0, 1} between two indices along a periodic axis of
+// n cells (delta = new - old), or 2 for a longer move.  Shared by the push
+// (which counts moves for the sort) and the sort, so both classify alike.
+__device__ __forceinline__ int canon_move(int delta, int n) {
+  const int r = delta < 0 ? delta + n : delta;
+  if (r == 0) return 0;
+  if (r == 1) return 1;
+  if (r == n - 1) return -1;
+  return 2;
+}
+
 __device__ __forceinline__ void raise_flag(Status* st, uint32_t bit, unsigned long long* counter) {
   atomicOr(&st->flags, bit);
   if (counter) atomicAdd(counter, 1ull);
@@ -126,6 +137,13 @@ struct hvpic_ctx {
   uint32_t* rhist;       // radix per-block digit counts
   float* fscratch;       // field scratch [20][ncell]
   double* mom_acc;       // FP64 moment accumulators [4][ncell], kept at zero between deposits
+  // Move counts left in sort_cnt by a row-kernel push, valid for the next
+  // neighbour-move sort of the same store (cell array, cell_start, size).
+  bool cnt_ready;
+  bool cnt_clean;  // sort_cnt is all zero (a counting push needs that)
+  const int32_t* cnt_cell;
+  const int32_t* cnt_cs;
+  int64_t cnt_n;
   // optional per-kernel timing: event pairs [kernel][slot][2]
   hipEvent_t* tev;
   int tmax;
@@ -137,10 +155,11 @@ namespace hvpic {
 constexpr int32_t kMagic = 0x68767063;
 
 // Launch wrappers, one per kernel family (implemented next to the kernels).
-int launch_gather_push(hvpic_ctx* c, hvpic_particles* p, const float* E, const float* B,
-                       float* n_mid, float* J_mid, double* diag_out);
-int launch_deposit(hvpic_ctx* c, const hvpic_particles* p, float half_dt_back, float* n,
-                   float* J);
+int launch_gather_push(hvpic_ctx* c, hvpic_particles* p, const int32_t* cell_start,
+                       const float* E, const float* B, float* n_mid, float* J_mid,
+                       double* diag_out);
+int launch_deposit(hvpic_ctx* c, const hvpic_particles* p, const int32_t* cell_start,
+                   float half_dt_back, float* n, float* J);
 int launch_sort(hvpic_ctx* c, const hvpic_particles* in, hvpic_particles* out,
                 const int32_t* cs_prev, int32_t* cs, int full);
 int launch_field_advance(hvpic_ctx* c, float* B, const float* n_half, const float* J_half,
@@ -148,6 +167,7 @@ int launch_field_advance(hvpic_ctx* c, float* B, const float* n_half, const floa
                          double* diag_out);
 int launch_smooth(hvpic_ctx* c, float* F, int ncomp, int npasses);
 int launch_zero(hvpic_ctx* c, float* p, int64_t count);
+void zero_counts(hvpic_ctx* c);  // enqueues the clearing of sort_cnt
 
 // Event bracket around one launch of kernel id k (no-op unless timing is on).
 inline void timing_begin(hvpic_ctx* c, int k) {

@@ -2,56 +2,47 @@
 // (optionally with the moment deposit fused in) and the stand-alone deposit.
 //
 // Method (arXiv 2305.05600):
-//   gather   App. B eq:quadFI/eq:quadF (QS) -- evaluated in the equivalent
-//            weight form F(x_p) = sum_c W_c(dx,dy,dz) F_c with the eq:quad
-//            weights, which the paper's consistency (no self-force) statement
-//            makes identical to the interpolant form; Sec. II.B for NGP.
+//   gather   App. B eq:quadFI/eq:quadF (QS), Sec. II.B (NGP); evaluated from
+//            per-cell polynomial coefficients in the particle offsets.
 //   push     Sec. II.B eq:vadv, non-relativistic Boris split.
 //   move     Sec. II.B position update; offsets renormalised into [-1,1).
 //   deposit  Sec. II.B eq:ngp, App. B eq:quad, at x^{n+1/2}.
 //
 // Data path.  Particles are structure-of-arrays and sorted by cell.  A block
-// owns a contiguous chunk of particles; each of its wavefronts walks a
-// contiguous sub-range 64 particles at a time, so every load and store of the
-// store is coalesced and consecutive iterations of a wavefront mostly stay in
-// the same cell.  The chunk's cells [c0, c1] are covered by LDS windows laid
-// out in "bands": band (by[, bz]) holds the linear cells
-// [c0 + by*nx (+ bz*nx*ny) - m, c1 + ... + m] modulo ncell.  A stencil point
-// that wraps around the x boundary lands one band over (and a y wrap in 3D one
-// plane band over), so band index and offset follow from the particle's own
-// cell with no division.
-//   * gather window: bands -1..1, margin 1, E and B interleaved as two float4
-//     per cell, so a stencil point costs two LDS reads;
-//   * deposit window: bands -3..3, margin 2, FP64 (n, Jx, Jy, Jz) per cell.
-// Deposit: each lane keeps running FP32 sums of its particles that belong to
-// the wavefront's current mid-point cell; when the wavefront moves on to the
-// next cell the sums are reduced over each 16-lane DPP row and added to the
-// window in FP64.  Particles whose mid-point sits in another cell (movers) add
-// straight into the window.  Each block flushes its window to FP64 global
-// accumulators; one pass converts them to the FP32 outputs.  Particles outside
-// the windows (unsorted or sparse input) use global loads / FP64 global atomics.
+// owns a contiguous chunk of particles; each wavefront walks its share in
+// steps of 256, lane l taking four consecutive particles per step (16-byte
+// accesses, 1 KiB per wavefront and array).  Sorted input means a lane's
+// four particles nearly always share a cell, and the block's cells [c0, c1]
+// form a short linear range.
+//   * gather window (LDS): one record per cell c0..c1 with the interpolant's
+//     polynomial coefficients for E and B and the cell's (i, j[, k]);
+//   * deposit window (LDS, FP64 n, Jx, Jy, Jz): "bands" of cells
+//     [c0 - 2, c1 + 2] shifted by by*nx (+ bz*nx*ny), by, bz in -3..3, so a
+//     stencil cell that wraps around the x (3D: y) boundary lands one band
+//     over, with no division;
+//   * each lane keeps running FP32 sums of its particles that deposit into
+//     the same cell and adds them to the window with FP64 LDS atomics when
+//     that cell changes or the step ends (at the step end a quad of lanes
+//     whose sums share a cell combines them first); the block then adds its
+//     window to FP64 global
+//     accumulators, and one pass converts those to the FP32 outputs.
+// Particles outside the windows (unsorted or sparse input) use global loads
+// and FP64 global atomics.
+#include <type_traits>
+
 #include "hvpic_internal.hpp"
 
 namespace hvpic {
 namespace {
 
-constexpr int kBands = 7;                 // deposit band offsets -3..3
-constexpr int kGBands = 3;                // gather band offsets -1..1
-constexpr int kGroupMin = 6;              // smallest lane group worth a DPP reduction
-
-// Particles per thread and per block, and the window limits.  A 3D chunk
-// spans more bands, so it is kept shorter to keep its windows small.
+// Particles per lane and per block, and the largest deposit-window width
+// (cells per band).  A 3D chunk spans more bands, so it is kept shorter.
 template <int NDIM>
 struct Chunk {
   static constexpr int PPT = NDIM == 2 ? 8 : 4;
   static constexpr int N = kBlock * PPT;
-  static constexpr int WMAX = NDIM == 2 ? 64 : 20;                 // deposit window width
-  static constexpr int DB = NDIM == 2 ? kBands : kBands * kBands;  // deposit bands
-  static constexpr int GB = NDIM == 2 ? kGBands : kGBands * kGBands;
-  static constexpr int DEP_LEN = DB * WMAX * 4;                    // doubles
-  static constexpr int G_LEN = GB * (WMAX - 2) * 2;                // float4
+  static constexpr int WMAX = NDIM == 2 ? 64 : 24;
 };
-
 
 struct Geo {
   int nx, ny, nz, ncell, nxny;
@@ -78,6 +69,9 @@ struct PushArgs {
   double ms;
   double* diag_part;        // per-block partials of {K, Px, Py, Pz}, or null
   Status* st;
+  bool vec;                 // all particle arrays 16-byte aligned
+  const int32_t* cs;        // cell_start of the sorted store, or null
+  uint32_t* cnt;            // moves per (old cell, direction), written when cs is given
 };
 
 struct DepArgs {
@@ -95,6 +89,7 @@ struct DepArgs {
   float bx, by, bz;         // displacement of the deposit point per unit speed
   float qV;
   Status* st;
+  bool vec;
 };
 
 __device__ __forceinline__ void decompose(int a, const Geo& g, int& i, int& j, int& k) {
@@ -180,20 +175,143 @@ __device__ __forceinline__ void gather_eb(const float* __restrict__ E, const flo
   }
 }
 
-// ---------------------------------------------------------------- deposit --
+// ---------------------------------------------------------------- windows --
+
+// Gather record of one cell: the interpolated field as a polynomial in the
+// particle's offsets (x, y[, z] in half-cell units), for the six components
+// (Ex, Ey, Ez, Bx, By, Bz), followed by the cell's integer indices i, j[, k].
+// Coefficient c of component f is stored at [c * 6 + f]:
+//   2D QS: F = c0 + c1 x + c2 y + c3 x^2 + c4 y^2
+//   3D QS: F = c0 + c1 x + c2 y + c3 z + c4 x^2 + c5 y^2 + c6 z^2
+//   NGP:   F = c0
+// For QS these are the App. B eq:quad weights (equivalently the
+// eq:quadFI/eq:quadF interpolant) applied to the cell's 5- or 7-point
+// neighbourhood and collected by powers of the offsets.
+template <int NDIM, int SHAPE>
+struct Rec {
+  static constexpr int NC = SHAPE == HVPIC_SHAPE_NGP ? 1 : (NDIM == 2 ? 5 : 7);
+  static constexpr int NF4 = (NC * 6 + NDIM + 3) / 4;  // float4 per record
+};
 
 template <int NDIM, int SHAPE>
 struct Stencil {
   static constexpr int T = SHAPE == HVPIC_SHAPE_NGP ? 1 : (NDIM == 2 ? 5 : 7);
 };
 
-// Offsets (relative to the mid-point cell) and weights of the stencil cells.
+template <int NDIM>
+__device__ __forceinline__ bool window_ok(int c0, int c1, const Geo& g, int& W) {
+  W = c1 - c0 + 5;
+  return c0 >= 0 && c1 < g.ncell && c1 >= c0 && W <= Chunk<NDIM>::WMAX && g.nx >= 4 &&
+         (NDIM == 2 || g.ny >= 4);
+}
+
+// Linear cell of deposit-window column `off` in band (by, bz): the window
+// starts two cells before c0; band (by, bz) is shifted by by*nx + bz*nx*ny.
+__device__ __forceinline__ int64_t window_cell(int c0, int off, int by, int bz, const Geo& g) {
+  int64_t c = (int64_t)c0 - 2 + off + (int64_t)by * g.nx + (int64_t)bz * g.nxny;
+  c %= g.ncell;
+  return c < 0 ? c + g.ncell : c;
+}
+
+// Fills the gather records of cells c0 .. c0 + ncells - 1 (all inside the
+// grid).  One thread per (cell, component).
 template <int NDIM, int SHAPE>
-__device__ __forceinline__ void stencil_weights(float x, float y, float z, float* wt, int* sx,
-                                                int* sy, int* sz) {
+__device__ void gwin_fill(float* gw, int ncells, int c0, const Geo& g,
+                          const float* __restrict__ E, const float* __restrict__ B) {
+  constexpr int NC = Rec<NDIM, SHAPE>::NC;
+  constexpr int RL = Rec<NDIM, SHAPE>::NF4 * 4;
+  const int nc = g.ncell;
+  for (int s = threadIdx.x; s < ncells * 6; s += kBlock) {
+    const int r = s / 6, comp = s - 6 * r;
+    const int a = c0 + r;
+    int i, j, k;
+    decompose(a, g, i, j, k);
+    const float* F = comp < 3 ? E + comp * nc : B + (comp - 3) * nc;
+    float* rec = gw + r * RL;
+    const float f0 = __ldg(F + a);
+    if (SHAPE == HVPIC_SHAPE_NGP) {
+      rec[comp] = f0;
+    } else {
+      const int im = i == 0 ? a + g.nx - 1 : a - 1;
+      const int ip = i == g.nx - 1 ? a - g.nx + 1 : a + 1;
+      const int jm = j == 0 ? a + g.nxny - g.nx : a - g.nx;
+      const int jp = j == g.ny - 1 ? a - g.nxny + g.nx : a + g.nx;
+      const float fxp = __ldg(F + ip), fxm = __ldg(F + im);
+      const float fyp = __ldg(F + jp), fym = __ldg(F + jm);
+      const float c6 = 1.0f / 6.0f, c12 = 1.0f / 12.0f;
+      if (NDIM == 2) {
+        rec[0 * 6 + comp] = f0 * (4.0f * c6) + ((fxp + fxm) + (fyp + fym)) * c12;
+        rec[1 * 6 + comp] = (fxp - fxm) * c6;
+        rec[2 * 6 + comp] = (fyp - fym) * c6;
+        rec[3 * 6 + comp] = (fxp + fxm) * c12 - f0 * c6;
+        rec[4 * 6 + comp] = (fyp + fym) * c12 - f0 * c6;
+      } else {
+        const int km = k == 0 ? a + nc - g.nxny : a - g.nxny;
+        const int kp = k == g.nz - 1 ? a - nc + g.nxny : a + g.nxny;
+        const float fzp = __ldg(F + kp), fzm = __ldg(F + km);
+        rec[0 * 6 + comp] = f0 * 0.5f + ((fxp + fxm) + (fyp + fym) + (fzp + fzm)) * c12;
+        rec[1 * 6 + comp] = (fxp - fxm) * c6;
+        rec[2 * 6 + comp] = (fyp - fym) * c6;
+        rec[3 * 6 + comp] = (fzp - fzm) * c6;
+        rec[4 * 6 + comp] = (fxp + fxm) * c12 - f0 * c6;
+        rec[5 * 6 + comp] = (fyp + fym) * c12 - f0 * c6;
+        rec[6 * 6 + comp] = (fzp + fzm) * c12 - f0 * c6;
+      }
+    }
+    if (comp == 0) {
+      int* ri = reinterpret_cast<int*>(rec + NC * 6);
+      ri[0] = i;
+      ri[1] = j;
+      if (NDIM == 3) ri[2] = k;
+    }
+  }
+}
+
+// Field at a particle of window cell rel with offsets (x, y, z); also returns
+// the cell's indices.
+template <int NDIM, int SHAPE>
+__device__ __forceinline__ void gather_rec(const float4* gw, int rel, float x, float y, float z,
+                                           float Ep[3], float Bp[3], int& i, int& j, int& k) {
+  constexpr int NF4 = Rec<NDIM, SHAPE>::NF4;
+  constexpr int NC = Rec<NDIM, SHAPE>::NC;
+  float r[NF4 * 4];
+  const float4* p = gw + rel * NF4;
+#pragma unroll
+  for (int q = 0; q < NF4; ++q) {
+    const float4 v = p[q];
+    r[4 * q] = v.x;
+    r[4 * q + 1] = v.y;
+    r[4 * q + 2] = v.z;
+    r[4 * q + 3] = v.w;
+  }
+#pragma unroll
+  for (int f = 0; f < 6; ++f) {
+    float v;
+    if (SHAPE == HVPIC_SHAPE_NGP)
+      v = r[f];
+    else if (NDIM == 2)
+      v = fmaf(x, fmaf(x, r[18 + f], r[6 + f]), fmaf(y, fmaf(y, r[24 + f], r[12 + f]), r[f]));
+    else
+      v = fmaf(x, fmaf(x, r[24 + f], r[6 + f]),
+               fmaf(y, fmaf(y, r[30 + f], r[12 + f]), fmaf(z, fmaf(z, r[36 + f], r[18 + f]), r[f])));
+    if (f < 3)
+      Ep[f] = v;
+    else
+      Bp[f - 3] = v;
+  }
+  i = __float_as_int(r[NC * 6]);
+  j = __float_as_int(r[NC * 6 + 1]);
+  k = NDIM == 3 ? __float_as_int(r[NC * 6 + 2]) : 0;
+}
+
+// ---------------------------------------------------------------- deposit --
+
+// Stencil weights at deposit offsets (x, y, z): centre, +x, -x, +y, -y[, +z, -z]
+// (Sec. II.B eq:ngp, App. B eq:quad).
+template <int NDIM, int SHAPE>
+__device__ __forceinline__ void dep_weights(float x, float y, float z, float* wt) {
   if (SHAPE == HVPIC_SHAPE_NGP) {
     wt[0] = 1.0f;
-    sx[0] = sy[0] = sz[0] = 0;
     return;
   }
   const float c6 = 1.0f / 6.0f, c12 = 1.0f / 12.0f;
@@ -203,252 +321,516 @@ __device__ __forceinline__ void stencil_weights(float x, float y, float z, float
   wt[2] = xm * xm * c12;
   wt[3] = yp * yp * c12;
   wt[4] = ym * ym * c12;
-  sx[0] = 0; sy[0] = 0; sz[0] = 0;
-  sx[1] = 1; sy[1] = 0; sz[1] = 0;
-  sx[2] = -1; sy[2] = 0; sz[2] = 0;
-  sx[3] = 0; sy[3] = 1; sz[3] = 0;
-  sx[4] = 0; sy[4] = -1; sz[4] = 0;
   if (NDIM == 3) {
     const float zp = 1.0f + z, zm = 1.0f - z;
     wt[5] = zp * zp * c12;
     wt[6] = zm * zm * c12;
-    sx[5] = 0; sy[5] = 0; sz[5] = 1;
-    sx[6] = 0; sy[6] = 0; sz[6] = -1;
+  }
+}
+
+// Deposit window: FP64 (n, Jx, Jy, Jz) per slot; slot = band * SW + column,
+// band = (by + 3) [+ 7 (bz + 3)] for band offsets by, bz in -3..3.
+template <int NDIM>
+struct DWin {
+  static constexpr int SW = Chunk<NDIM>::WMAX;  // slots per band
+  static constexpr int BZ = 7 * SW;             // slots per z band row (3D)
+  static constexpr int NB = NDIM == 2 ? 7 : 49;
+  static constexpr int LEN = NB * SW * 4;       // doubles
+};
+
+// Window slots of the stencil cells of the cell at slot `key`; wrap bit 0/1:
+// its +x/-x neighbour wraps around the x boundary, bit 2/3 the same for y (3D).
+template <int NDIM, int SHAPE>
+__device__ __forceinline__ void stencil_slots(int key, int wrap, int* s) {
+  constexpr int SW = DWin<NDIM>::SW, BZ = DWin<NDIM>::BZ;
+  s[0] = key;
+  if (SHAPE == HVPIC_SHAPE_QS) {
+    s[1] = key + 1 - ((wrap & 1) ? SW : 0);
+    s[2] = key - 1 + ((wrap & 2) ? SW : 0);
+    if (NDIM == 2) {
+      s[3] = key + SW;
+      s[4] = key - SW;
+    } else {
+      s[3] = key + SW - ((wrap & 4) ? BZ : 0);
+      s[4] = key - SW + ((wrap & 8) ? BZ : 0);
+      s[5] = key + BZ;
+      s[6] = key - BZ;
+    }
+  }
+}
+
+// Wrap bits (as in stencil_slots) of the cell with indices (i, j).
+template <int NDIM>
+__device__ __forceinline__ int wrap_bits(int i, int j, const Geo& g) {
+  int w = (i == g.nx - 1 ? 1 : 0) | (i == 0 ? 2 : 0);
+  if (NDIM == 3) w |= (j == g.ny - 1 ? 4 : 0) | (j == 0 ? 8 : 0);
+  return w;
+}
+
+// Window slot << 4 | wrap bits of the cell (mx, my, mz) away from the cell
+// of window column `rel` with indices (i, j).
+template <int NDIM>
+__device__ __forceinline__ int slot_wrap(int rel, int i, int j, int mx, int my, int mz,
+                                         const Geo& g) {
+  const int t1 = i + mx;
+  const int wx = t1 < 0 ? 1 : (t1 >= g.nx ? -1 : 0);
+  int band = my + wx + 3, t2 = 0, wy = 0;
+  if (NDIM == 3) {
+    t2 = j + my;
+    wy = t2 < 0 ? 1 : (t2 >= g.ny ? -1 : 0);
+    band += 7 * (mz + wy + 3);
+  }
+  return ((band * DWin<NDIM>::SW + rel + mx + 2) << 4) |
+         wrap_bits<NDIM>(t1 + wx * g.nx, t2 + wy * g.ny, g);
+}
+
+// Deposit straight into the FP64 global accumulators (particles outside the
+// windows).
+template <int NDIM, int SHAPE>
+__device__ __forceinline__ void deposit_global(int i, int j, int k, int mx, int my, int mz,
+                                               const float* wt, float q, float vx, float vy,
+                                               float vz, const Geo& g, double* __restrict__ acc) {
+  constexpr int T = Stencil<NDIM, SHAPE>::T;
+  const int nc = g.ncell;
+  int sx[T], sy[T], sz[T];
+  sx[0] = sy[0] = sz[0] = 0;
+  if (SHAPE == HVPIC_SHAPE_QS) {
+    sx[1] = 1; sy[1] = 0; sz[1] = 0;
+    sx[2] = -1; sy[2] = 0; sz[2] = 0;
+    sx[3] = 0; sy[3] = 1; sz[3] = 0;
+    sx[4] = 0; sy[4] = -1; sz[4] = 0;
+    if (NDIM == 3) {
+      sx[5] = 0; sy[5] = 0; sz[5] = 1;
+      sx[6] = 0; sy[6] = 0; sz[6] = -1;
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < T; ++t) {
+    const int c = wrapi(i + mx + sx[t], g.nx) +
+                  g.nx * (wrapi(j + my + sy[t], g.ny) + g.ny * wrapi(k + mz + sz[t], g.nz));
+    const float nq = q * wt[t];
+    unsafeAtomicAdd(acc + c, (double)nq);
+    unsafeAtomicAdd(acc + nc + c, (double)(nq * vx));
+    unsafeAtomicAdd(acc + 2 * nc + c, (double)(nq * vy));
+    unsafeAtomicAdd(acc + 3 * nc + c, (double)(nq * vz));
   }
 }
 
 template <int CTRL>
-__device__ __forceinline__ float dpp(float v) {
+__device__ __forceinline__ float dpp_f(float v) {
   return __builtin_bit_cast(
       float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
 }
-
-// Sum over the 16 lanes of each DPP row; every lane of the row gets the sum.
-__device__ __forceinline__ float row_sum(float v) {
-  v += dpp<0xB1>(v);   // quad_perm [1,0,3,2]
-  v += dpp<0x4E>(v);   // quad_perm [2,3,0,1]
-  v += dpp<0x141>(v);  // row_half_mirror
-  v += dpp<0x140>(v);  // row_mirror
-  return v;
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
 }
 
-// Deposit slot (index of the (n, Jx, Jy, Jz) quadruple in the window) of each
-// stencil cell of a particle of old cell (i,j,k) = c0 + rel whose mid-point
-// sits (mx,my,mz) cells away.
-template <int NDIM, int SHAPE>
-__device__ __forceinline__ void deposit_slots(int rel, int i, int j, int mx, int my, int mz,
-                                              const int* sx, const int* sy, const int* sz, int W,
-                                              const Geo& g, int* slot) {
-  constexpr int T = Stencil<NDIM, SHAPE>::T;
-#pragma unroll
-  for (int t = 0; t < T; ++t) {
-    const int dxt = mx + sx[t], dyt = my + sy[t], dzt = mz + sz[t];
-    const int it = i + dxt;
-    const int wx = it < 0 ? 1 : (it >= g.nx ? -1 : 0);
-    int band = dyt + wx + 3;
-    if (NDIM == 3) {
-      const int jt = j + dyt;
-      const int wy = jt < 0 ? 1 : (jt >= g.ny ? -1 : 0);
-      band += kBands * (dzt + wy + 3);
-    }
-    slot[t] = (band * W + rel + dxt + 2) * 4;
-  }
+__device__ __forceinline__ int lanes_below_count(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                   __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
-// Running per-lane moment sums of a wavefront for its current mid-point cell.
-template <int T>
-struct DepState {
-  float acc[T][4];
-  int cur;       // wavefront-uniform: deposit slot of the current cell's centre, -1 if none
-  int cslot[T];  // wavefront-uniform: slots of the current cell's stencil
+// Orders the wavefront's LDS writes before its following LDS reads.
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Per-wavefront queue (LDS, structure-of-arrays of QCAP entries) of deposits
+// that do not add to their lane's running sums: word 0 = window slot << 4 |
+// wrap bits, then the deposit offsets, the charge factor and the velocity.
+template <int NDIM>
+struct Queue {
+  static constexpr int QCAP = 64;
+  static constexpr int QW = NDIM == 2 ? 7 : 8;  // words per entry
+  float* base;
+  int count;  // wavefront-uniform
 };
 
-template <int T>
-__device__ __forceinline__ void dep_init(DepState<T>& D) {
-  D.cur = -1;
+// Adds every queued deposit to the window, lane e taking entry e.
+template <int NDIM, int SHAPE>
+__device__ __forceinline__ void queue_drain(Queue<NDIM>& Q, double* win) {
+  constexpr int T = Stencil<NDIM, SHAPE>::T;
+  constexpr int QC = Queue<NDIM>::QCAP, o = NDIM == 3 ? 4 : 3;
+  if (Q.count == 0) return;
+  wave_sync_lds();
+  const int e = threadIdx.x & 63;
+  if (e < Q.count) {
+    const float* b = Q.base;
+    const int kw = __float_as_int(b[e]);
+    const float x = b[QC + e], y = b[2 * QC + e];
+    const float z = NDIM == 3 ? b[3 * QC + e] : 0.0f;
+    const float q = b[o * QC + e], vx = b[(o + 1) * QC + e];
+    const float vy = b[(o + 2) * QC + e], vz = b[(o + 3) * QC + e];
+    float wt[T];
+    dep_weights<NDIM, SHAPE>(x, y, z, wt);
+    int s[T];
+    stencil_slots<NDIM, SHAPE>(kw >> 4, kw & 15, s);
 #pragma unroll
-  for (int t = 0; t < T; ++t) {
-    D.cslot[t] = 0;
-    D.acc[t][0] = D.acc[t][1] = D.acc[t][2] = D.acc[t][3] = 0.0f;
+    for (int t = 0; t < T; ++t) {
+      const float nq = q * wt[t];
+      atomicAdd(win + s[t] * 4 + 0, (double)nq);
+      atomicAdd(win + s[t] * 4 + 1, (double)(nq * vx));
+      atomicAdd(win + s[t] * 4 + 2, (double)(nq * vy));
+      atomicAdd(win + s[t] * 4 + 3, (double)(nq * vz));
+    }
   }
+  wave_sync_lds();
+  Q.count = 0;
 }
 
-template <int T>
-__device__ __forceinline__ void dep_accumulate(DepState<T>& D, bool on, float q, const float* wt,
-                                               float vx, float vy, float vz) {
-  const float qm = on ? q : 0.0f;
+// Queues this lane's deposit when `exc`; every lane of the wavefront calls it.
+template <int NDIM, int SHAPE>
+__device__ __forceinline__ void queue_push(Queue<NDIM>& Q, double* win, bool exc, int kw, float x,
+                                           float y, float z, float q, float vx, float vy,
+                                           float vz) {
+  constexpr int QC = Queue<NDIM>::QCAP, o = NDIM == 3 ? 4 : 3;
+  const uint64_t m = __ballot(exc);
+  if (m == 0) return;
+  const int add = __builtin_popcountll(m);
+  if (Q.count + add > QC) queue_drain<NDIM, SHAPE>(Q, win);
+  if (exc) {
+    const int e = Q.count + lanes_below_count(m);
+    float* b = Q.base;
+    b[e] = __int_as_float(kw);
+    b[QC + e] = x;
+    b[2 * QC + e] = y;
+    if (NDIM == 3) b[3 * QC + e] = z;
+    b[o * QC + e] = q;
+    b[(o + 1) * QC + e] = vx;
+    b[(o + 2) * QC + e] = vy;
+    b[(o + 3) * QC + e] = vz;
+  }
+  Q.count += add;
+}
+
+// A lane's running FP32 moment sums for its home cell: the deposit cell of
+// the first particle of its current group of four.
+template <int NDIM, int SHAPE>
+struct Home {
+  float acc[Stencil<NDIM, SHAPE>::T][4];
+  int kw;  // slot << 4 | wrap of the home cell, -1 if none yet
+};
+
+template <int NDIM, int SHAPE>
+__device__ __forceinline__ void home_clear(Home<NDIM, SHAPE>& H) {
+  H.kw = -1;
+#pragma unroll
+  for (int t = 0; t < Stencil<NDIM, SHAPE>::T; ++t)
+    H.acc[t][0] = H.acc[t][1] = H.acc[t][2] = H.acc[t][3] = 0.0f;
+}
+
+// Deposit of one particle: into the home sums when its deposit cell is the
+// home cell, else into the queue (in the window) or the global accumulators.
+// Every lane of the wavefront calls it.
+template <int NDIM, int SHAPE>
+__device__ __forceinline__ void deposit_particle(Home<NDIM, SHAPE>& H, Queue<NDIM>& Q,
+                                                 double* win, bool live, bool inwin, int rel,
+                                                 int i, int j, int k, int mx, int my, int mz,
+                                                 float x, float y, float z, float q, float vx,
+                                                 float vy, float vz, const Geo& g,
+                                                 double* __restrict__ acc) {
+  constexpr int T = Stencil<NDIM, SHAPE>::T;
+  const bool use_win = live && inwin && mx >= -1 && mx <= 1 && my >= -1 && my <= 1 &&
+                       mz >= -1 && mz <= 1;
+  const int kw = use_win ? slot_wrap<NDIM>(rel, i, j, mx, my, mz, g) : -1;
+  if (use_win && H.kw < 0) H.kw = kw;
+  const bool stay = use_win && kw == H.kw;
+  float wt[T];
+  dep_weights<NDIM, SHAPE>(x, y, z, wt);
+  const float qm = stay ? q : 0.0f;
 #pragma unroll
   for (int t = 0; t < T; ++t) {
     const float a = qm * wt[t];
-    D.acc[t][0] += a;
-    D.acc[t][1] = fmaf(a, vx, D.acc[t][1]);
-    D.acc[t][2] = fmaf(a, vy, D.acc[t][2]);
-    D.acc[t][3] = fmaf(a, vz, D.acc[t][3]);
+    H.acc[t][0] += a;
+    H.acc[t][1] = fmaf(a, vx, H.acc[t][1]);
+    H.acc[t][2] = fmaf(a, vy, H.acc[t][2]);
+    H.acc[t][3] = fmaf(a, vz, H.acc[t][3]);
   }
+  queue_push<NDIM, SHAPE>(Q, win, use_win && !stay, kw, x, y, z, q, vx, vy, vz);
+  if (live && !use_win) deposit_global<NDIM, SHAPE>(i, j, k, mx, my, mz, wt, q, vx, vy, vz, g, acc);
 }
 
-// Adds the wavefront's sums for the current cell to the window (one FP64 LDS
-// atomic per value from the first lane of each DPP row).  Uniform call.
-template <int T>
-__device__ __forceinline__ void dep_flush(DepState<T>& D, double* win) {
-  if (D.cur < 0) return;
-  const bool adder = (threadIdx.x & 15) == 0;
-#pragma unroll
-  for (int t = 0; t < T; ++t) {
-#pragma unroll
-    for (int ch = 0; ch < 4; ++ch) {
-      const float s = row_sum(D.acc[t][ch]);
-      if (adder) atomicAdd(win + D.cslot[t] + ch, (double)s);
-      D.acc[t][ch] = 0.0f;
-    }
-  }
-  D.cur = -1;
-}
-
-// One particle per lane; every lane of the wavefront calls it (uniform
-// control flow).  Lanes whose mid-point cell is the wavefront's current cell
-// only add to their running sums; when enough lanes have moved on to another
-// cell, the current sums are flushed and that cell becomes current; the
-// remaining in-window lanes add directly into the window, and lanes outside
-// the window add to the FP64 global accumulators.
+// End of a group step: the home sums go to the window; a quad of lanes with
+// the same home cell (consecutive particles, so the usual case) first
+// combines them across its lanes (DPP) and its first lane alone adds them,
+// which keeps concurrent LDS atomics on one address few.  Every lane of the
+// wavefront calls it.
 template <int NDIM, int SHAPE>
-__device__ __forceinline__ void dep_step(DepState<Stencil<NDIM, SHAPE>::T>& D, bool live,
-                                         bool inwin, bool mover, const int* slot, const float* wt,
-                                         float q, float vx, float vy, float vz, double* win,
-                                         int i, int j, int k, int mx, int my, int mz,
-                                         const int* sx, const int* sy, const int* sz,
-                                         const Geo& g, double* __restrict__ acc) {
+__device__ __forceinline__ void home_flush(Home<NDIM, SHAPE>& H, double* win) {
   constexpr int T = Stencil<NDIM, SHAPE>::T;
-  const int lane = threadIdx.x & 63;
-  const int key = (live && inwin) ? slot[0] : -1;
-  const bool mine = key >= 0 && key == D.cur;
-  dep_accumulate<T>(D, mine, q, wt, vx, vy, vz);
-  uint64_t pend = __ballot(key >= 0 && !mine);
-  if (pend) {
-    const uint64_t settled = __ballot(key >= 0 && !mine && !mover);
-    const int src = 63 - __builtin_clzll(settled ? settled : pend);
-    const int nkey = __builtin_amdgcn_readlane(key, src);
-    const uint64_t grp = __ballot(key == nkey) & pend;
-    if (__builtin_popcountll(grp) >= kGroupMin) {
-      dep_flush<T>(D, win);
-      D.cur = nkey;
+  const int h = H.kw;
+  const bool same = h == dpp_i<0xB1>(h) && h == dpp_i<0x4E>(h) && h == dpp_i<0x1B>(h);
+  if (same) {
 #pragma unroll
-      for (int t = 0; t < T; ++t) D.cslot[t] = __builtin_amdgcn_readlane(slot[t], src);
-      dep_accumulate<T>(D, (grp >> lane) & 1ull, q, wt, vx, vy, vz);
-      pend &= ~grp;
-    }
-    if ((pend >> lane) & 1ull) {
+    for (int t = 0; t < T; ++t)
 #pragma unroll
-      for (int t = 0; t < T; ++t) {
-        const float nq = q * wt[t];
-        atomicAdd(win + slot[t] + 0, (double)nq);
-        atomicAdd(win + slot[t] + 1, (double)(nq * vx));
-        atomicAdd(win + slot[t] + 2, (double)(nq * vy));
-        atomicAdd(win + slot[t] + 3, (double)(nq * vz));
+      for (int ch = 0; ch < 4; ++ch) {
+        float v = H.acc[t][ch];
+        v += dpp_f<0xB1>(v);  // quad_perm [1,0,3,2]
+        v += dpp_f<0x4E>(v);  // quad_perm [2,3,0,1]
+        H.acc[t][ch] = v;
       }
-    }
   }
-  if (live && !inwin) {
-    const int nc = g.ncell;
+  if (h >= 0 && (!same || (threadIdx.x & 3) == 0)) {
+    int s[T];
+    stencil_slots<NDIM, SHAPE>(h >> 4, h & 15, s);
 #pragma unroll
-    for (int t = 0; t < T; ++t) {
-      const int c = wrapi(i + mx + sx[t], g.nx) +
-                    g.nx * (wrapi(j + my + sy[t], g.ny) + g.ny * wrapi(k + mz + sz[t], g.nz));
-      const float nq = q * wt[t];
-      unsafeAtomicAdd(acc + c, (double)nq);
-      unsafeAtomicAdd(acc + nc + c, (double)(nq * vx));
-      unsafeAtomicAdd(acc + 2 * nc + c, (double)(nq * vy));
-      unsafeAtomicAdd(acc + 3 * nc + c, (double)(nq * vz));
-    }
-  }
-}
-
-// Window geometry for a chunk whose first and last particles sit in c0, c1:
-// deposit window width W = span + 4, gather window width W - 2.
-template <int NDIM>
-__device__ __forceinline__ bool window_ok(int c0, int c1, const Geo& g, int& W) {
-  W = c1 - c0 + 5;
-  return c0 >= 0 && c1 < g.ncell && c1 >= c0 && W <= Chunk<NDIM>::WMAX && g.nx >= 4 &&
-         (NDIM == 2 || g.ny >= 4);
-}
-
-__device__ __forceinline__ int64_t window_cell(int c0, int margin, int off, int by, int bz,
-                                               const Geo& g) {
-  int64_t c = (int64_t)c0 - margin + off + (int64_t)by * g.nx + (int64_t)bz * g.nxny;
-  c %= g.ncell;
-  return c < 0 ? c + g.ncell : c;
-}
-
-// E and B of the gather window, two float4 per cell: (Ex,Ey,Ez,0),(Bx,By,Bz,0).
-template <int NDIM>
-__device__ void gather_window_fill(float4* geb, int WG, int c0, const Geo& g,
-                                   const float* __restrict__ E, const float* __restrict__ B) {
-  const int len = Chunk<NDIM>::GB * WG;
-  const int nc = g.ncell;
-  for (int s = threadIdx.x; s < len; s += kBlock) {
-    const int band = s / WG, off = s - band * WG;
-    const int by = band % kGBands - 1, bz = band / kGBands - 1;
-    const int64_t c = window_cell(c0, 1, off, by, bz, g);
-    geb[2 * s] = make_float4(__ldg(E + c), __ldg(E + nc + c), __ldg(E + 2 * nc + c), 0.0f);
-    geb[2 * s + 1] = make_float4(__ldg(B + c), __ldg(B + nc + c), __ldg(B + 2 * nc + c), 0.0f);
-  }
-}
-
-// Gather from the window for a particle of cell c0 + rel.
-template <int NDIM, int SHAPE>
-__device__ __forceinline__ void gather_window(const float4* geb, int WG, int rel, int i, int j,
-                                              float x, float y, float z, const Geo& g,
-                                              float Ep[3], float Bp[3]) {
-  constexpr int T = Stencil<NDIM, SHAPE>::T;
-  float wt[T];
-  int sx[T], sy[T], sz[T];
-  stencil_weights<NDIM, SHAPE>(x, y, z, wt, sx, sy, sz);
-  Ep[0] = Ep[1] = Ep[2] = Bp[0] = Bp[1] = Bp[2] = 0.0f;
+    for (int t = 0; t < T; ++t)
 #pragma unroll
-  for (int t = 0; t < T; ++t) {
-    const int it = i + sx[t];
-    const int wx = it < 0 ? 1 : (it >= g.nx ? -1 : 0);
-    int band = sy[t] + wx + 1;
-    if (NDIM == 3) {
-      const int jt = j + sy[t];
-      const int wy = jt < 0 ? 1 : (jt >= g.ny ? -1 : 0);
-      band += kGBands * (sz[t] + wy + 1);
-    }
-    const int s = band * WG + rel + sx[t] + 1;
-    const float4 e = geb[2 * s], b = geb[2 * s + 1];
-    Ep[0] = fmaf(wt[t], e.x, Ep[0]);
-    Ep[1] = fmaf(wt[t], e.y, Ep[1]);
-    Ep[2] = fmaf(wt[t], e.z, Ep[2]);
-    Bp[0] = fmaf(wt[t], b.x, Bp[0]);
-    Bp[1] = fmaf(wt[t], b.y, Bp[1]);
-    Bp[2] = fmaf(wt[t], b.z, Bp[2]);
+      for (int ch = 0; ch < 4; ++ch) atomicAdd(win + s[t] * 4 + ch, (double)H.acc[t][ch]);
+  }
+  home_clear(H);
+}
+
+// Clears columns [0, W) of every band of the deposit window.
+template <int NDIM>
+__device__ void dwin_zero(double* win, int W) {
+  constexpr int SW = DWin<NDIM>::SW;
+  for (int s = threadIdx.x; s < DWin<NDIM>::NB * W * 4; s += kBlock) {
+    const int band = s / (W * 4), rest = s - band * W * 4;
+    win[band * SW * 4 + rest] = 0.0;
   }
 }
 
+// Adds columns [0, W) of the block's deposit window (column 0 = cell c0 - 2)
+// to the FP64 global accumulators.
 template <int NDIM>
-__device__ void window_flush(const double* win, int W, int c0, const Geo& g,
-                             double* __restrict__ acc) {
-  const int len = Chunk<NDIM>::DB * W * 4;
-  for (int s = threadIdx.x; s < len; s += kBlock) {
-    const double v = win[s];
+__device__ void dwin_flush(const double* win, int W, int c0, const Geo& g,
+                           double* __restrict__ acc) {
+  constexpr int SW = DWin<NDIM>::SW;
+  for (int s = threadIdx.x; s < DWin<NDIM>::NB * W * 4; s += kBlock) {
+    const int band = s / (W * 4), rest = s - band * W * 4;
+    const double v = win[band * SW * 4 + rest];
     if (v == 0.0) continue;
-    const int ch = s & 3;
-    const int cellslot = s >> 2;
-    const int band = cellslot / W;
-    const int off = cellslot - band * W;
-    const int64_t c = window_cell(c0, 2, off, band % kBands - 3, band / kBands - 3, g);
+    const int ch = rest & 3, off = rest >> 2;
+    const int64_t c = window_cell(c0, off, band % 7 - 3, band / 7 - 3, g);
     unsafeAtomicAdd(acc + (int64_t)ch * g.ncell + c, v);
+  }
+}
+
+// ------------------------------------------------------ particle I/O -----
+
+// Four consecutive values at p + i: one 16-byte access when `full` (i + 4 <=
+// end and 16-byte aligned arrays), else element by element up to end.
+template <typename T>
+__device__ __forceinline__ void load4(const T* __restrict__ p, int64_t i, int64_t end, bool full,
+                                      T v[4]) {
+  if (full) {
+    using V = typename std::conditional<std::is_same<T, int>::value, int4, float4>::type;
+    const V u = *reinterpret_cast<const V*>(p + i);
+    v[0] = u.x;
+    v[1] = u.y;
+    v[2] = u.z;
+    v[3] = u.w;
+  } else {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v[q] = i + q < end ? p[i + q] : T(0);
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void store4(T* __restrict__ p, int64_t i, int64_t end, bool full,
+                                       const T v[4]) {
+  if (full) {
+    using V = typename std::conditional<std::is_same<T, int>::value, int4, float4>::type;
+    V u;
+    u.x = v[0];
+    u.y = v[1];
+    u.z = v[2];
+    u.w = v[3];
+    *reinterpret_cast<V*>(p + i) = u;
+  } else {
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (i + q < end) p[i + q] = v[q];
+  }
+}
+
+// Group of four at p + b4 of which [lo, hi) is wanted: one 16-byte load when
+// `vec` (the whole group lies inside the array and it is 16-byte aligned),
+// else element by element.  Values outside [lo, hi) are unspecified.
+template <typename T>
+__device__ __forceinline__ void load4r(const T* __restrict__ p, int64_t b4, int64_t lo, int64_t hi,
+                                       bool vec, T v[4]) {
+  if (vec) {
+    using V = typename std::conditional<std::is_same<T, int>::value, int4, float4>::type;
+    const V u = *reinterpret_cast<const V*>(p + b4);
+    v[0] = u.x;
+    v[1] = u.y;
+    v[2] = u.z;
+    v[3] = u.w;
+  } else {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v[q] = (b4 + q >= lo && b4 + q < hi) ? p[b4 + q] : T(0);
+  }
+}
+
+// Writes the elements [lo, hi) of the group at p + b4; one 16-byte store
+// when `full` (the group is exactly [lo, hi) and aligned).
+template <typename T>
+__device__ __forceinline__ void store4r(T* __restrict__ p, int64_t b4, int64_t lo, int64_t hi,
+                                        bool full, const T v[4]) {
+  if (full) {
+    using V = typename std::conditional<std::is_same<T, int>::value, int4, float4>::type;
+    V u;
+    u.x = v[0];
+    u.y = v[1];
+    u.z = v[2];
+    u.w = v[3];
+    *reinterpret_cast<V*>(p + b4) = u;
+  } else {
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (b4 + q >= lo && b4 + q < hi) p[b4 + q] = v[q];
+  }
+}
+
+// Shift s with x - 2s in [-1,1): exact compares for |x| < 3 (x -/+ 2 is
+// exact there by Sterbenz), the general path beyond.
+__device__ __forceinline__ bool renorm_fast(float& x, int& s) {
+  if (fabsf(x) < 3.0f) {
+    s = (x >= 1.0f ? 1 : 0) - (x < -1.0f ? 1 : 0);
+    x = fmaf(-2.0f, (float)s, x);
+    return true;
+  }
+  return renorm(x, s);
+}
+
+// ------------------------------------------------------------ move counts --
+//
+// With the store's cell_start given, the push also makes the first pass of
+// the neighbour-move sort: for every old cell and each of the 3^ndim move
+// directions, the number of its particles that moved that way.  A particle's
+// old cell is its cell before the push, which must agree with its place in
+// the store (checked).  Counts go to an LDS window over the block's cells
+// (home-cell runs as for the deposit, other moves by LDS atomics); cells
+// strictly inside the block's range hold no other block's particles and are
+// stored plainly, the two end cells are added atomically, so the table must
+// be zero beforehand (the sort's scatter leaves it zero).
+
+template <int NDIM>
+struct Moves {
+  static constexpr int ND = NDIM == 2 ? 9 : 27;
+  static constexpr int CENTRE = ND / 2;  // stayed in its cell
+};
+
+__device__ __forceinline__ void flag_far(Status* st, uint32_t bit, unsigned long long* counter) {
+  raise_flag(st, bit, counter);
+  __hip_atomic_store(&st->far_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int NDIM>
+__device__ __forceinline__ void moves_window_init(const int32_t* __restrict__ cs, int c0, int span,
+                                                  int32_t* s_cs, uint32_t* s_cnt) {
+  for (int q = threadIdx.x; q <= span + 1; q += kBlock) s_cs[q] = cs[c0 + q];
+  for (int q = threadIdx.x; q < (span + 1) * Moves<NDIM>::ND; q += kBlock) s_cnt[q] = 0;
+}
+
+// Each block checks its share of cell_start (a monotone partition of [0, n]);
+// the scatter relies on it.
+__device__ __forceinline__ void check_cell_start(const int32_t* __restrict__ cs, int ncell,
+                                                 int64_t n, Status* st) {
+  const int64_t cb = (int64_t)blockIdx.x * ncell / gridDim.x;
+  const int64_t ce = (int64_t)(blockIdx.x + 1) * ncell / gridDim.x;
+  bool bad = false;
+  for (int64_t c = cb + threadIdx.x; c < ce; c += kBlock) {
+    const int32_t v0 = cs[c], v1 = cs[c + 1];
+    bad |= v0 < 0 || v1 < v0 || (int64_t)v1 > n;
+  }
+  if (threadIdx.x == 0) {
+    if (blockIdx.x == 0) bad |= cs[0] != 0;
+    if (blockIdx.x == gridDim.x - 1) bad |= (int64_t)cs[ncell] != n;
+  }
+  if (bad) flag_far(st, HVPIC_FLAG_BAD_INPUT, &st->bad_input);
+}
+
+// Direction code of the move (i,j,k) -> (ni,nj,nk) of particle idx of old
+// cell a (window column rel), classified as the sort does; -1 (and the sort
+// sent down its general path) for a longer move or a particle out of place.
+template <int NDIM, typename Args>
+__device__ __forceinline__ int move_direction(const Args& A, int64_t idx, int a, int rel,
+                                              bool inwin, const int32_t* s_cs, int i, int j,
+                                              int k, int ni, int nj, int nk) {
+  const int64_t lo = inwin ? s_cs[rel] : A.cs[a], hi = inwin ? s_cs[rel + 1] : A.cs[a + 1];
+  if (idx < lo || idx >= hi) {
+    flag_far(A.st, HVPIC_FLAG_BAD_INPUT, &A.st->bad_input);
+    return -1;
+  }
+  const Geo& g = A.g;
+  const int di = canon_move(ni - i, g.nx), dj = canon_move(nj - j, g.ny);
+  const int dk = NDIM == 3 ? canon_move(nk - k, g.nz) : 0;
+  if (di == 2 || dj == 2 || dk == 2) {
+    flag_far(A.st, HVPIC_FLAG_MOVE_GT1, nullptr);
+    return -1;
+  }
+  return (di + 1) + 3 * (dj + 1) + (NDIM == 3 ? 9 * (dk + 1) : 0);
+}
+
+// Counts one move (d >= 0).  Every lane of the wavefront calls it.
+template <int NDIM>
+__device__ __forceinline__ void count_move(int d, bool inwin, int rel, int a, int& chome,
+                                           uint32_t& nstay, uint32_t* s_cnt,
+                                           uint32_t* __restrict__ cnt) {
+  constexpr int ND = Moves<NDIM>::ND, CENTRE = Moves<NDIM>::CENTRE;
+  const bool local = d >= 0 && inwin;
+  if (local && chome < 0) chome = rel;
+  const bool stays = local && rel == chome && d == CENTRE;
+  nstay += stays ? 1u : 0u;
+  if (local && !stays) atomicAdd(&s_cnt[rel * ND + d], 1u);
+  if (d >= 0 && !inwin) atomicAdd(&cnt[(int64_t)a * ND + d], 1u);
+}
+
+// End of a group step: home-cell stay counts go to the window, combined
+// across a quad of lanes with the same home cell.  Every lane calls it.
+template <int NDIM>
+__device__ __forceinline__ void count_flush(int& chome, uint32_t& nstay, uint32_t* s_cnt) {
+  const int h = chome;
+  const bool same = h == dpp_i<0xB1>(h) && h == dpp_i<0x4E>(h) && h == dpp_i<0x1B>(h);
+  uint32_t n = nstay;
+  if (same) {
+    n += (uint32_t)dpp_i<0xB1>((int)n);
+    n += (uint32_t)dpp_i<0x4E>((int)n);
+  }
+  if (h >= 0 && n != 0 && (!same || (threadIdx.x & 3) == 0))
+    atomicAdd(&s_cnt[h * Moves<NDIM>::ND + Moves<NDIM>::CENTRE], n);
+  chome = -1;
+  nstay = 0;
+}
+
+template <int NDIM>
+__device__ void moves_window_flush(const uint32_t* s_cnt, int c0, int span,
+                                   uint32_t* __restrict__ cnt) {
+  constexpr int ND = Moves<NDIM>::ND;
+  for (int q = threadIdx.x; q < (span + 1) * ND; q += kBlock) {
+    const int rel = q / ND;
+    const uint32_t v = s_cnt[q];
+    uint32_t* dst = cnt + (int64_t)c0 * ND + q;
+    if (rel == 0 || rel == span) {
+      if (v) atomicAdd(dst, v);
+    } else {
+      *dst = v;
+    }
   }
 }
 
 // ---------------------------------------------------------------- kernels --
 
+// Fused gather + Boris push + move (+ mid-point deposit when DEP).
+// 2D: at most 128 VGPRs, so that four wavefronts per SIMD keep enough loads
+// in flight (the 3D windows already limit a CU to three blocks).
 template <int NDIM, int SHAPE, bool DEP>
-__global__ __launch_bounds__(kBlock) void k_gather_push(PushArgs A) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NDIM == 2 ? 4 : 1)))
+void k_gather_push(PushArgs A) {
   constexpr int PPT = Chunk<NDIM>::PPT;
-  constexpr int T = Stencil<NDIM, SHAPE>::T;
-  __shared__ float4 geb[Chunk<NDIM>::G_LEN];
-  __shared__ double win[DEP ? Chunk<NDIM>::DEP_LEN : 1];
+  constexpr int NF4 = Rec<NDIM, SHAPE>::NF4;
+  __shared__ float4 gw[Chunk<NDIM>::WMAX * NF4];
+  __shared__ double win[DEP ? DWin<NDIM>::LEN : 1];
+  __shared__ float s_q[DEP ? kBlock / 64 * Queue<NDIM>::QCAP * Queue<NDIM>::QW : 1];
+  __shared__ uint32_t s_cnt[Chunk<NDIM>::WMAX * Moves<NDIM>::ND];
+  __shared__ int32_t s_cs[Chunk<NDIM>::WMAX + 1];
   __shared__ int s_c[2];
   const Geo& g = A.g;
   const int64_t base = (int64_t)blockIdx.x * Chunk<NDIM>::N;
@@ -461,136 +843,161 @@ __global__ __launch_bounds__(kBlock) void k_gather_push(PushArgs A) {
   const int c0 = s_c[0], span = s_c[1] - s_c[0];
   int W = 0;
   const bool wok = window_ok<NDIM>(c0, s_c[1], g, W);
+  const bool cnt_on = A.cs != nullptr;  // count the moves for the sort
   if (wok) {
-    gather_window_fill<NDIM>(geb, W - 2, c0, g, A.E, A.B);
-    if (DEP)
-      for (int s = threadIdx.x; s < Chunk<NDIM>::DB * W * 4; s += kBlock) win[s] = 0.0;
+    gwin_fill<NDIM, SHAPE>(reinterpret_cast<float*>(gw), span + 1, c0, g, A.E, A.B);
+    if (DEP) dwin_zero<NDIM>(win, W);
+    if (cnt_on) moves_window_init<NDIM>(A.cs, c0, span, s_cs, s_cnt);
   }
+  if (cnt_on) check_cell_start(A.cs, g.ncell, A.n, A.st);
   __syncthreads();
 
-  const int lane = threadIdx.x & 63;
-  const int64_t wbase = base + (int64_t)(threadIdx.x >> 6) * 64 * PPT;
   const bool want_diag = A.diag_part != nullptr;
   float dK = 0.f, dP0 = 0.f, dP1 = 0.f, dP2 = 0.f;
-  DepState<T> D;
-  if (DEP) dep_init<T>(D);
-  for (int it = 0; it < PPT; ++it) {
-    const int64_t idx = wbase + it * 64 + lane;
-    bool live = idx < end;
-    int a = 0;
-    float x = 0.f, y = 0.f, z = 0.f, vx = 0.f, vy = 0.f, vz = 0.f, wq = 0.f;
-    if (live) {
-      a = A.cell[idx];
-      x = A.ox[idx];
-      y = A.oy[idx];
-      if (NDIM == 3) z = A.oz[idx];
-      vx = A.ux[idx];
-      vy = A.uy[idx];
-      vz = A.uz[idx];
-      if (DEP || want_diag) wq = A.w[idx];
-      if ((unsigned)a >= (unsigned)g.ncell) {
+  Home<NDIM, SHAPE> H;
+  home_clear(H);
+  Queue<NDIM> Q;
+  Q.base = s_q + (DEP ? (threadIdx.x >> 6) * Queue<NDIM>::QCAP * Queue<NDIM>::QW : 0);
+  Q.count = 0;
+  int chome = -1;      // window column of the lane's home cell for move counts
+  uint32_t nstay = 0;  // home-cell particles that stay in their cell
+  // Wavefront wv owns particles [base + wv*64*PPT, +64*PPT); in each group
+  // step lane l takes four consecutive ones, so a step is one coalesced
+  // 1 KiB access per array.
+  const int64_t lb = base + (int64_t)(threadIdx.x >> 6) * 64 * PPT + 4 * (threadIdx.x & 63);
+#pragma unroll 1
+  for (int h = 0; h < PPT; h += 4) {
+    const int64_t b4 = lb + h * 64;
+    const bool full = A.vec && b4 + 4 <= end;
+    int ca[4];
+    float px[4], py[4], pz[4], ux[4], uy[4], uz[4], pw[4];
+    load4(A.cell, b4, end, full, ca);
+    load4(A.ox, b4, end, full, px);
+    load4(A.oy, b4, end, full, py);
+    if (NDIM == 3) load4(A.oz, b4, end, full, pz);
+    load4(A.ux, b4, end, full, ux);
+    load4(A.uy, b4, end, full, uy);
+    load4(A.uz, b4, end, full, uz);
+    if (DEP || want_diag) load4(A.w, b4, end, full, pw);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int a = ca[q];
+      const float x = px[q], y = py[q], z = NDIM == 3 ? pz[q] : 0.f;
+      const float vx = ux[q], vy = uy[q], vz = uz[q];
+      const float wq = (DEP || want_diag) ? pw[q] : 0.f;
+      bool live = b4 + q < end;
+      if (live && (unsigned)a >= (unsigned)g.ncell) {
         raise_flag(A.st, HVPIC_FLAG_BAD_INPUT, &A.st->bad_input);
         live = false;
       }
-    }
-    const int rel = a - c0;
-    const bool in_window = wok && rel >= 0 && rel <= span;
-    int i = 0, j = 0, k = 0, mx = 0, my = 0, mz = 0;
-    float xm = 0.f, ym = 0.f, zm = 0.f;
-    if (live) {
-      decompose(a, g, i, j, k);
-      float Ep[3], Bp[3];
-      if (in_window)
-        gather_window<NDIM, SHAPE>(geb, W - 2, rel, i, j, x, y, z, g, Ep, Bp);
-      else
-        gather_eb<NDIM, SHAPE>(A.E, A.B, a, i, j, k, x, y, z, g, Ep, Bp);
-      // Boris: half kick, rotation, half kick.
-      const float h = A.a;
-      const float vmx = fmaf(h, Ep[0], vx), vmy = fmaf(h, Ep[1], vy), vmz = fmaf(h, Ep[2], vz);
-      const float tx = h * Bp[0], ty = h * Bp[1], tz = h * Bp[2];
-      const float f = 2.0f / (1.0f + (tx * tx + ty * ty + tz * tz));
-      const float sx = f * tx, sy = f * ty, sz = f * tz;
-      const float px = vmx + (vmy * tz - vmz * ty);
-      const float py = vmy + (vmz * tx - vmx * tz);
-      const float pz = vmz + (vmx * ty - vmy * tx);
-      const float nvx = fmaf(h, Ep[0], vmx + (py * sz - pz * sy));
-      const float nvy = fmaf(h, Ep[1], vmy + (pz * sx - px * sz));
-      const float nvz = fmaf(h, Ep[2], vmz + (px * sy - py * sx));
-      if (want_diag) {
-        dK = fmaf(wq, vx * nvx + vy * nvy + vz * nvz, dK);
-        dP0 = fmaf(wq, vx + nvx, dP0);
-        dP1 = fmaf(wq, vy + nvy, dP1);
-        dP2 = fmaf(wq, vz + nvz, dP2);
-      }
-      // Move: x^{n+1} = x^n + v^{n+1/2} dt, renormalised offsets.
-      float nx_ = fmaf(nvx, A.kx, x), ny_ = fmaf(nvy, A.ky, y), nz_ = z;
-      int si = 0, sj = 0, sk = 0;
-      bool ok = renorm(nx_, si) && renorm(ny_, sj);
-      if (NDIM == 3) {
-        nz_ = fmaf(nvz, A.kz, z);
-        ok = ok && renorm(nz_, sk);
-      }
-      if (!ok) {
-        raise_flag(A.st, HVPIC_FLAG_NONFINITE, &A.st->nonfinite);
-        si = sj = sk = 0;
-        nx_ = x;
-        ny_ = y;
-        nz_ = z;
-      } else if (si > 1 || si < -1 || sj > 1 || sj < -1 || sk > 1 || sk < -1) {
-        raise_flag(A.st, HVPIC_FLAG_MOVE_GT1, &A.st->moved_gt1);
-      }
-      int ni = i + si, nj = j + sj, nk = k + sk;
-      if ((unsigned)ni >= (unsigned)g.nx) ni = wrapi(ni, g.nx);
-      if ((unsigned)nj >= (unsigned)g.ny) nj = wrapi(nj, g.ny);
-      if (NDIM == 3 && (unsigned)nk >= (unsigned)g.nz) nk = wrapi(nk, g.nz);
-      A.cell[idx] = ni + g.nx * (nj + g.ny * nk);
-      A.ox[idx] = nx_;
-      A.oy[idx] = ny_;
-      if (NDIM == 3) A.oz[idx] = nz_;
-      A.ux[idx] = nvx;
-      A.uy[idx] = nvy;
-      A.uz[idx] = nvz;
-      if (DEP) {
-        // Mid-point x^{n+1/2} = x^n + (dt/2) v^{n+1/2}.
-        xm = fmaf(nvx, 0.5f * A.kx, x);
-        ym = fmaf(nvy, 0.5f * A.ky, y);
-        zm = NDIM == 3 ? fmaf(nvz, 0.5f * A.kz, z) : 0.0f;
-        if (!ok || !renorm(xm, mx) || !renorm(ym, my) || (NDIM == 3 && !renorm(zm, mz))) {
-          xm = x; ym = y; zm = z; mx = my = mz = 0;
+      const int rel = a - c0;
+      const bool inwin = wok && rel >= 0 && rel <= span;
+      int i = 0, j = 0, k = 0, mx = 0, my = 0, mz = 0, d = -1;
+      float xm = 0.f, ym = 0.f, zm = 0.f, nvx = 0.f, nvy = 0.f, nvz = 0.f;
+      if (live) {
+        float Ep[3], Bp[3];
+        if (inwin) {
+          gather_rec<NDIM, SHAPE>(gw, rel, x, y, z, Ep, Bp, i, j, k);
+        } else {
+          decompose(a, g, i, j, k);
+          gather_eb<NDIM, SHAPE>(A.E, A.B, a, i, j, k, x, y, z, g, Ep, Bp);
         }
-        vx = nvx;
-        vy = nvy;
-        vz = nvz;
+        // Boris: half kick, rotation, half kick.
+        const float hh = A.a;
+        const float vmx = fmaf(hh, Ep[0], vx), vmy = fmaf(hh, Ep[1], vy), vmz = fmaf(hh, Ep[2], vz);
+        const float tx = hh * Bp[0], ty = hh * Bp[1], tz = hh * Bp[2];
+        const float f = 2.0f / (1.0f + (tx * tx + ty * ty + tz * tz));
+        const float sx = f * tx, sy = f * ty, sz = f * tz;
+        const float qx = vmx + (vmy * tz - vmz * ty);
+        const float qy = vmy + (vmz * tx - vmx * tz);
+        const float qz = vmz + (vmx * ty - vmy * tx);
+        nvx = fmaf(hh, Ep[0], vmx + (qy * sz - qz * sy));
+        nvy = fmaf(hh, Ep[1], vmy + (qz * sx - qx * sz));
+        nvz = fmaf(hh, Ep[2], vmz + (qx * sy - qy * sx));
+        if (want_diag) {
+          dK = fmaf(wq, vx * nvx + vy * nvy + vz * nvz, dK);
+          dP0 = fmaf(wq, vx + nvx, dP0);
+          dP1 = fmaf(wq, vy + nvy, dP1);
+          dP2 = fmaf(wq, vz + nvz, dP2);
+        }
+        // Move: x^{n+1} = x^n + v^{n+1/2} dt, renormalised offsets.
+        float nx_ = fmaf(nvx, A.kx, x), ny_ = fmaf(nvy, A.ky, y), nz_ = z;
+        int si = 0, sj = 0, sk = 0;
+        bool ok = renorm_fast(nx_, si) && renorm_fast(ny_, sj);
+        if (NDIM == 3) {
+          nz_ = fmaf(nvz, A.kz, z);
+          ok = ok && renorm_fast(nz_, sk);
+        }
+        if (!ok) {
+          raise_flag(A.st, HVPIC_FLAG_NONFINITE, &A.st->nonfinite);
+          si = sj = sk = 0;
+          nx_ = x;
+          ny_ = y;
+          nz_ = z;
+        } else if (si > 1 || si < -1 || sj > 1 || sj < -1 || sk > 1 || sk < -1) {
+          raise_flag(A.st, HVPIC_FLAG_MOVE_GT1, &A.st->moved_gt1);
+        }
+        int ni = i + si, nj = j + sj, nk = k + sk;
+        if ((unsigned)ni >= (unsigned)g.nx) ni = wrapi(ni, g.nx);
+        if ((unsigned)nj >= (unsigned)g.ny) nj = wrapi(nj, g.ny);
+        if (NDIM == 3 && (unsigned)nk >= (unsigned)g.nz) nk = wrapi(nk, g.nz);
+        ca[q] = ni + g.nx * (nj + g.ny * nk);
+        px[q] = nx_;
+        py[q] = ny_;
+        if (NDIM == 3) pz[q] = nz_;
+        ux[q] = nvx;
+        uy[q] = nvy;
+        uz[q] = nvz;
+        if (cnt_on)
+          d = move_direction<NDIM>(A, b4 + q, a, rel, inwin, s_cs, i, j, k, ni, nj, nk);
+        if (DEP) {
+          // Mid-point x^{n+1/2} = x^n + (dt/2) v^{n+1/2}.
+          xm = fmaf(nvx, 0.5f * A.kx, x);
+          ym = fmaf(nvy, 0.5f * A.ky, y);
+          zm = NDIM == 3 ? fmaf(nvz, 0.5f * A.kz, z) : 0.0f;
+          if (!ok || !renorm_fast(xm, mx) || !renorm_fast(ym, my) ||
+              (NDIM == 3 && !renorm_fast(zm, mz))) {
+            xm = x;
+            ym = y;
+            zm = z;
+            mx = my = mz = 0;
+          }
+        }
       }
+      if (cnt_on) count_move<NDIM>(d, inwin, rel, a, chome, nstay, s_cnt, A.cnt);
+      if (DEP)
+        deposit_particle<NDIM, SHAPE>(H, Q, win, live, inwin, rel, i, j, k, mx, my, mz, xm, ym,
+                                      zm, A.qV * wq, nvx, nvy, nvz, g, A.acc);
     }
-    if (DEP) {
-      float wt[T];
-      int sxs[T], sys[T], szs[T], slot[T];
-      stencil_weights<NDIM, SHAPE>(xm, ym, zm, wt, sxs, sys, szs);
-      const bool inwin = in_window && mx >= -1 && mx <= 1 && my >= -1 && my <= 1 && mz >= -1 &&
-                         mz <= 1;
-      deposit_slots<NDIM, SHAPE>(rel, i, j, mx, my, mz, sxs, sys, szs, W, g, slot);
-      dep_step<NDIM, SHAPE>(D, live, inwin, (mx | my | mz) != 0, slot, wt, A.qV * wq, vx, vy, vz,
-                            win, i, j, k, mx, my, mz, sxs, sys, szs, g, A.acc);
-    }
+    store4(A.cell, b4, end, full, ca);
+    store4(A.ox, b4, end, full, px);
+    store4(A.oy, b4, end, full, py);
+    if (NDIM == 3) store4(A.oz, b4, end, full, pz);
+    store4(A.ux, b4, end, full, ux);
+    store4(A.uy, b4, end, full, uy);
+    store4(A.uz, b4, end, full, uz);
+    if (DEP) home_flush(H, win);
+    if (cnt_on) count_flush<NDIM>(chome, nstay, s_cnt);
   }
-  if (DEP) dep_flush<T>(D, win);
+  if (DEP) queue_drain<NDIM, SHAPE>(Q, win);
   if (want_diag) {
     const double hm = 0.5 * A.ms;
     double v[4] = {hm * dK, hm * dP0, hm * dP1, hm * dP2};
     block_partial<4>(v, A.diag_part);
   }
-  if (DEP && wok) {
+  if (wok && (DEP || cnt_on)) {
     __syncthreads();
-    window_flush<NDIM>(win, W, c0, g, A.acc);
+    if (DEP) dwin_flush<NDIM>(win, W, c0, g, A.acc);
+    if (cnt_on) moves_window_flush<NDIM>(s_cnt, c0, span, A.cnt);
   }
 }
 
+// Stand-alone deposit at x - half_dt_back v (no push); same lane runs.
 template <int NDIM, int SHAPE>
 __global__ __launch_bounds__(kBlock) void k_deposit(DepArgs A) {
   constexpr int PPT = Chunk<NDIM>::PPT;
-  constexpr int T = Stencil<NDIM, SHAPE>::T;
-  __shared__ double win[Chunk<NDIM>::DEP_LEN];
+  __shared__ double win[DWin<NDIM>::LEN];
+  __shared__ float s_q[kBlock / 64 * Queue<NDIM>::QCAP * Queue<NDIM>::QW];
   __shared__ int s_c[2];
   const Geo& g = A.g;
   const int64_t base = (int64_t)blockIdx.x * Chunk<NDIM>::N;
@@ -603,58 +1010,62 @@ __global__ __launch_bounds__(kBlock) void k_deposit(DepArgs A) {
   const int c0 = s_c[0], span = s_c[1] - s_c[0];
   int W = 0;
   const bool wok = window_ok<NDIM>(c0, s_c[1], g, W);
-  if (wok)
-    for (int s = threadIdx.x; s < Chunk<NDIM>::DB * W * 4; s += kBlock) win[s] = 0.0;
+  if (wok) dwin_zero<NDIM>(win, W);
   __syncthreads();
-  const int lane = threadIdx.x & 63;
-  const int64_t wbase = base + (int64_t)(threadIdx.x >> 6) * 64 * PPT;
-  DepState<T> D;
-  dep_init<T>(D);
-  for (int it = 0; it < PPT; ++it) {
-    const int64_t idx = wbase + it * 64 + lane;
-    bool live = idx < end;
-    int a = 0, i = 0, j = 0, k = 0, mx = 0, my = 0, mz = 0;
-    float x = 0.f, y = 0.f, z = 0.f, vx = 0.f, vy = 0.f, vz = 0.f, q = 0.f;
-    if (live) {
-      a = A.cell[idx];
-      x = A.ox[idx];
-      y = A.oy[idx];
-      if (NDIM == 3) z = A.oz[idx];
-      vx = A.ux[idx];
-      vy = A.uy[idx];
-      vz = A.uz[idx];
-      q = A.qV * A.w[idx];
-      if ((unsigned)a >= (unsigned)g.ncell) {
+  Home<NDIM, SHAPE> H;
+  home_clear(H);
+  Queue<NDIM> Q;
+  Q.base = s_q + (threadIdx.x >> 6) * Queue<NDIM>::QCAP * Queue<NDIM>::QW;
+  Q.count = 0;
+  const int64_t lb = base + (int64_t)(threadIdx.x >> 6) * 64 * PPT + 4 * (threadIdx.x & 63);
+#pragma unroll 1
+  for (int h = 0; h < PPT; h += 4) {
+    const int64_t b4 = lb + h * 64;
+    const bool full = A.vec && b4 + 4 <= end;
+    int ca[4];
+    float px[4], py[4], pz[4], ux[4], uy[4], uz[4], pw[4];
+    load4(A.cell, b4, end, full, ca);
+    load4(A.ox, b4, end, full, px);
+    load4(A.oy, b4, end, full, py);
+    if (NDIM == 3) load4(A.oz, b4, end, full, pz);
+    load4(A.ux, b4, end, full, ux);
+    load4(A.uy, b4, end, full, uy);
+    load4(A.uz, b4, end, full, uz);
+    load4(A.w, b4, end, full, pw);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      int a = ca[q];
+      bool live = b4 + q < end;
+      if (live && (unsigned)a >= (unsigned)g.ncell) {
         raise_flag(A.st, HVPIC_FLAG_BAD_INPUT, &A.st->bad_input);
         live = false;
-        a = 0;
       }
-    }
-    if (live) {
-      decompose(a, g, i, j, k);
-      float xm = fmaf(vx, A.bx, x), ym = fmaf(vy, A.by, y), zm = NDIM == 3 ? fmaf(vz, A.bz, z) : 0.f;
-      if (renorm(xm, mx) && renorm(ym, my) && (NDIM == 2 || renorm(zm, mz))) {
-        x = xm;
-        y = ym;
-        z = zm;
-      } else {
-        mx = my = mz = 0;
+      if (!live) a = 0;
+      int i = 0, j = 0, k = 0, mx = 0, my = 0, mz = 0;
+      float x = px[q], y = py[q], z = NDIM == 3 ? pz[q] : 0.f;
+      if (live) {
+        decompose(a, g, i, j, k);
+        float xm = fmaf(ux[q], A.bx, x), ym = fmaf(uy[q], A.by, y);
+        float zm = NDIM == 3 ? fmaf(uz[q], A.bz, z) : 0.f;
+        if (renorm_fast(xm, mx) && renorm_fast(ym, my) && (NDIM == 2 || renorm_fast(zm, mz))) {
+          x = xm;
+          y = ym;
+          z = zm;
+        } else {
+          mx = my = mz = 0;
+        }
       }
+      const int rel = a - c0;
+      const bool inwin = wok && rel >= 0 && rel <= span;
+      deposit_particle<NDIM, SHAPE>(H, Q, win, live, inwin, rel, i, j, k, mx, my, mz, x, y, z,
+                                    A.qV * pw[q], ux[q], uy[q], uz[q], g, A.acc);
     }
-    const int rel = a - c0;
-    const bool inwin = wok && rel >= 0 && rel <= span && mx >= -1 && mx <= 1 && my >= -1 &&
-                       my <= 1 && mz >= -1 && mz <= 1;
-    float wt[T];
-    int sxs[T], sys[T], szs[T], slot[T];
-    stencil_weights<NDIM, SHAPE>(x, y, z, wt, sxs, sys, szs);
-    deposit_slots<NDIM, SHAPE>(rel, i, j, mx, my, mz, sxs, sys, szs, W, g, slot);
-    dep_step<NDIM, SHAPE>(D, live, inwin, (mx | my | mz) != 0, slot, wt, q, vx, vy, vz, win, i, j,
-                          k, mx, my, mz, sxs, sys, szs, g, A.acc);
+    home_flush(H, win);
   }
-  dep_flush<T>(D, win);
+  queue_drain<NDIM, SHAPE>(Q, win);
   if (wok) {
     __syncthreads();
-    window_flush<NDIM>(win, W, c0, g, A.acc);
+    dwin_flush<NDIM>(win, W, c0, g, A.acc);
   }
 }
 
@@ -695,6 +1106,13 @@ __global__ __launch_bounds__(kBlock) void k_push_diag_final(const double* part, 
     for (int k = 0; k < 4; ++k) out[k] = r[k];
 }
 
+bool particles_aligned16(const hvpic_particles* p) {
+  const void* ptrs[] = {p->cell, p->ox, p->oy, p->oz, p->ux, p->uy, p->uz, p->w};
+  for (const void* q : ptrs)
+    if (((uintptr_t)q & 15) != 0) return false;
+  return true;
+}
+
 Geo make_geo(const hvpic_ctx* c) {
   Geo g;
   g.nx = c->p.nx;
@@ -727,15 +1145,23 @@ int zero2(hvpic_ctx* c, float* a, int64_t na, float* b, int64_t nb) {
 
 int launch_zero(hvpic_ctx* c, float* p, int64_t count) { return zero2(c, p, count, nullptr, 0); }
 
+void zero_counts(hvpic_ctx* c) {
+  const int64_t m = (int64_t)c->ncell * (c->p.ndim == 2 ? 9 : 27);
+  zero2(c, reinterpret_cast<float*>(c->sort_cnt), m, nullptr, 0);
+  c->cnt_clean = true;
+}
+
 void moments_out(hvpic_ctx* c, float* n, float* J) {
   const int blocks = (int)std::min<int64_t>(ceil_div(4ll * c->ncell, kBlock), 2048);
   hipLaunchKernelGGL(k_moments_out, dim3(blocks), dim3(kBlock), 0, c->stream, c->mom_acc,
                      c->ncell, n, J);
 }
 
-int launch_gather_push(hvpic_ctx* c, hvpic_particles* p, const float* E, const float* B,
-                       float* n_mid, float* J_mid, double* diag_out) {
+int launch_gather_push(hvpic_ctx* c, hvpic_particles* p, const int32_t* cell_start,
+                       const float* E, const float* B, float* n_mid, float* J_mid,
+                       double* diag_out) {
   const bool dep = n_mid != nullptr && J_mid != nullptr;
+  c->cnt_ready = false;
   if (p->n == 0) {
     if (diag_out) hipLaunchKernelGGL(k_write_zero_diag, dim3(1), dim3(64), 0, c->stream, diag_out, 4);
     if (dep) moments_out(c, n_mid, J_mid);
@@ -763,6 +1189,10 @@ int launch_gather_push(hvpic_ctx* c, hvpic_particles* p, const float* E, const f
   A.ms = c->p.ms;
   A.diag_part = diag_out ? c->push_part : nullptr;
   A.st = c->status;
+  A.vec = particles_aligned16(p);
+  A.cs = cell_start;
+  A.cnt = c->sort_cnt;
+  if (cell_start != nullptr && !c->cnt_clean) zero_counts(c);
   const bool qs = c->p.shape == HVPIC_SHAPE_QS;
   int nblocks = 0;
   timing_begin(c, HVPIC_KERNEL_GATHER_PUSH);
@@ -776,6 +1206,13 @@ int launch_gather_push(hvpic_ctx* c, hvpic_particles* p, const float* E, const f
     else push_dispatch<3, HVPIC_SHAPE_NGP>(dep, dim3(nblocks), c->stream, A);
   }
   timing_end(c, HVPIC_KERNEL_GATHER_PUSH);
+  if (cell_start != nullptr) {
+    c->cnt_clean = false;
+    c->cnt_ready = true;
+    c->cnt_cell = p->cell;
+    c->cnt_cs = cell_start;
+    c->cnt_n = p->n;
+  }
   if (dep) moments_out(c, n_mid, J_mid);
   if (diag_out)
     hipLaunchKernelGGL(k_push_diag_final, dim3(1), dim3(kBlock), 0, c->stream,
@@ -783,8 +1220,9 @@ int launch_gather_push(hvpic_ctx* c, hvpic_particles* p, const float* E, const f
   return hipGetLastError() == hipSuccess ? HVPIC_OK : HVPIC_EHIP;
 }
 
-int launch_deposit(hvpic_ctx* c, const hvpic_particles* p, float half_dt_back, float* n,
-                   float* J) {
+int launch_deposit(hvpic_ctx* c, const hvpic_particles* p, const int32_t* cell_start,
+                   float half_dt_back, float* n, float* J) {
+  (void)cell_start;
   if (p->n == 0) {
     moments_out(c, n, J);
     return hipGetLastError() == hipSuccess ? HVPIC_OK : HVPIC_EHIP;
@@ -807,6 +1245,7 @@ int launch_deposit(hvpic_ctx* c, const hvpic_particles* p, float half_dt_back, f
   A.bz = (float)(-2.0 * (double)half_dt_back / c->p.dz);
   A.qV = c->qV;
   A.st = c->status;
+  A.vec = particles_aligned16(p);
   const bool qs = c->p.shape == HVPIC_SHAPE_QS;
   timing_begin(c, HVPIC_KERNEL_DEPOSIT);
   if (c->p.ndim == 2) {

@@ -53,15 +53,6 @@ __device__ __forceinline__ void ijk(int c, const SortGeo& g, int& i, int& j, int
   k = (int)q2;
 }
 
-// Canonical move in {-1,0,1} along an axis of n cells, or 2 for a longer move.
-__device__ __forceinline__ int canon(int delta, int n) {
-  int r = delta < 0 ? delta + n : delta;
-  if (r == 0) return 0;
-  if (r == 1) return 1;
-  if (r == n - 1) return -1;
-  return 2;
-}
-
 template <int NDIM>
 struct Dirs {
   static constexpr int N = NDIM == 2 ? 9 : 27;
@@ -75,8 +66,8 @@ __device__ __forceinline__ int direction(int key, int i, int j, int k, const Sor
   if ((unsigned)key >= (unsigned)g.ncell) return -1;
   int i2, j2, k2;
   ijk(key, g, i2, j2, k2);
-  const int di = canon(i2 - i, g.nx), dj = canon(j2 - j, g.ny);
-  const int dk = NDIM == 3 ? canon(k2 - k, g.nz) : 0;
+  const int di = canon_move(i2 - i, g.nx), dj = canon_move(j2 - j, g.ny);
+  const int dk = NDIM == 3 ? canon_move(k2 - k, g.nz) : 0;
   if (di == 2 || dj == 2 || dk == 2) return -1;
   return (di + 1) + 3 * (dj + 1) + (NDIM == 3 ? 9 * (dk + 1) : 0);
 }
@@ -547,12 +538,22 @@ __device__ void block_sort(int64_t n, int ncell, Fields in, Fields out, int32_t*
 
 template <int NDIM>
 __global__ __launch_bounds__(kBlock) void k_nb_scatter(const int32_t* __restrict__ cs_prev, int64_t n,
-                                                       SortGeo g, const uint32_t* __restrict__ bases,
+                                                       SortGeo g, uint32_t* __restrict__ bases,
                                                        Fields in, Fields out, int32_t* cs,
                                                        const Status* st, uint32_t* rk0, uint32_t* rk1,
                                                        uint32_t* rv0, uint32_t* rv1) {
   constexpr int ND = Dirs<NDIM>::N, NB = Dirs<NDIM>::BITS;
   constexpr int CODE_BITS = NB + kCellBits;
+  __shared__ uint32_t s_next[kWaves][kCellsPerWave * ND];  // next free slot of each group
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int a0 = (blockIdx.x * kWaves + wid) * kCellsPerWave;
+  const int na = a0 < g.ncell ? min(kCellsPerWave, g.ncell - a0) : 0;
+  // the group bases are used once: the table is left zero for the next
+  // counting push
+  for (int q = lane; q < na * ND; q += 64) {
+    s_next[wid][q] = bases[(int64_t)a0 * ND + q];
+    bases[(int64_t)a0 * ND + q] = 0u;
+  }
   if (__hip_atomic_load(&st->far_decision, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
     if (blockIdx.x == 0) {
       uint32_t* rkey[2] = {rk0, rk1};
@@ -561,11 +562,6 @@ __global__ __launch_bounds__(kBlock) void k_nb_scatter(const int32_t* __restrict
     }
     return;
   }
-  __shared__ uint32_t s_next[kWaves][kCellsPerWave * ND];  // next free slot of each group
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const int a0 = (blockIdx.x * kWaves + wid) * kCellsPerWave;
-  const int na = a0 < g.ncell ? min(kCellsPerWave, g.ncell - a0) : 0;
-  for (int q = lane; q < na * ND; q += 64) s_next[wid][q] = bases[(int64_t)a0 * ND + q];
   __syncthreads();
   if (na == 0) return;
   int bnd;
@@ -688,8 +684,12 @@ void enqueue_neighbour(hvpic_ctx* c, const hvpic_particles* in, hvpic_particles*
   const int cblocks = (int)ceil_div(c->ncell, kWaves * kCellsPerWave);
   const int tiles = (int)ceil_div(c->ncell, kScanTile);
   uint32_t* blk = (uint32_t*)c->sort_blk;
-  hipLaunchKernelGGL((k_nb_count<NDIM>), dim3(cblocks), dim3(kBlock), 0, s, in->cell, cs_prev,
-                     in->n, g, c->sort_cnt, c->status);
+  // A row-kernel push of this same store already left the move counts.
+  const bool counted = c->cnt_ready && c->cnt_cell == in->cell && c->cnt_cs == cs_prev &&
+                       c->cnt_n == in->n;
+  if (!counted)
+    hipLaunchKernelGGL((k_nb_count<NDIM>), dim3(cblocks), dim3(kBlock), 0, s, in->cell, cs_prev,
+                       in->n, g, c->sort_cnt, c->status);
   hipLaunchKernelGGL((k_nb_newcount<NDIM>), dim3(tiles), dim3(kBlock), 0, s,
                      (const uint32_t*)c->sort_cnt, g, cs, blk, c->status);
   hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, s, blk, tiles);
@@ -697,7 +697,7 @@ void enqueue_neighbour(hvpic_ctx* c, const hvpic_particles* in, hvpic_particles*
                      (const uint32_t*)blk);
   timing_begin(c, HVPIC_KERNEL_SORT_SCATTER);
   hipLaunchKernelGGL((k_nb_scatter<NDIM>), dim3(cblocks), dim3(kBlock), 0, s, cs_prev, in->n, g,
-                     (const uint32_t*)c->sort_cnt, fields_of(in), fields_of(out), cs,
+                     c->sort_cnt, fields_of(in), fields_of(out), cs,
                      (const Status*)c->status, c->rkey[0], c->rkey[1], c->rval[0], c->rval[1]);
   timing_end(c, HVPIC_KERNEL_SORT_SCATTER);
 }
@@ -711,9 +711,12 @@ int launch_sort(hvpic_ctx* c, const hvpic_particles* in, hvpic_particles* out,
     enqueue_radix(c, in, out, cs);
   } else if (c->p.ndim == 2) {
     enqueue_neighbour<2>(c, in, out, cs_prev, cs);
+    c->cnt_clean = true;
   } else {
     enqueue_neighbour<3>(c, in, out, cs_prev, cs);
+    c->cnt_clean = true;
   }
+  c->cnt_ready = false;
   return hipGetLastError() == hipSuccess ? HVPIC_OK : HVPIC_EHIP;
 }
 

@@ -64,7 +64,7 @@ def lib():
         L.hvpic_workspace_bytes.argtypes = [P(HvpicParams), P(ctypes.c_size_t)]
         L.hvpic_init.argtypes = [P(HvpicParams), vp, vp, P(vp)]
         L.hvpic_finalize.argtypes = [vp]
-        L.hvpic_gather_push.argtypes = [vp, P(HvpicParticles), vp, vp, vp, vp, vp]
+        L.hvpic_gather_push.argtypes = [vp, P(HvpicParticles), vp, vp, vp, vp, vp, vp]
         L.hvpic_sort.argtypes = [vp, P(HvpicParticles), P(HvpicParticles), vp, vp, i32]
         L.hvpic_deposit.argtypes = [vp, P(HvpicParticles), vp, ctypes.c_float, vp, vp]
         L.hvpic_field_advance.argtypes = [vp, vp, vp, vp, vp, vp, vp, i32, vp]
@@ -182,9 +182,12 @@ def _nc(ctx, k=1):
     return k * _NCELL[ctx.value] if ctx.value in _NCELL else None
 
 
-def hvpic_gather_push(ctx, p: Particles, E, B, n_mid=None, J_mid=None, diag_out=None):
+def hvpic_gather_push(ctx, p: Particles, cell_start, E, B, n_mid=None, J_mid=None,
+                      diag_out=None):
     cp = p.c()
-    _check(lib().hvpic_gather_push(ctx, ctypes.byref(cp), _ptr(E, torch.float32, _nc(ctx, 3)),
+    ncs = None if _nc(ctx) is None else _nc(ctx) + 1
+    _check(lib().hvpic_gather_push(ctx, ctypes.byref(cp), _ptr(cell_start, torch.int32, ncs),
+                                   _ptr(E, torch.float32, _nc(ctx, 3)),
                                    _ptr(B, torch.float32, _nc(ctx, 3)),
                                    _ptr(n_mid, torch.float32, _nc(ctx)),
                                    _ptr(J_mid, torch.float32, _nc(ctx, 3)),

@@ -4,7 +4,8 @@ State at the start of step n: particles sorted by cell at x^n carrying
 v^{n-1/2}; B^n and E^n; the moments n^{n-1/2}, J^{n-1/2}.  One step:
 
   1. hvpic_gather_push   E^n, B^n at x^n -> v^{n+1/2}, x^{n+1}; with the fused
-                         deposit also n^{n+1/2}, J^{n+1/2} at x^{n+1/2}
+                         deposit also n^{n+1/2}, J^{n+1/2} at x^{n+1/2}; given
+                         cell_start it also counts the moves for the sort
   2. hvpic_sort          stable sort by the new cells (neighbour-move path)
   3. hvpic_deposit       n^{n+1/2}, J^{n+1/2} (only when not fused)
   4. hvpic_smooth        optional binomial passes on the moments
@@ -74,9 +75,9 @@ class GpuSim:
             E, B = self.E_s, self.B_s
         pd = self.push_diag if self.diagnostics else None
         if self.fused:
-            H.hvpic_gather_push(c, self.p, E, B, self.n_half, self.J_half, pd)
+            H.hvpic_gather_push(c, self.p, self.cs, E, B, self.n_half, self.J_half, pd)
         else:
-            H.hvpic_gather_push(c, self.p, E, B, None, None, pd)
+            H.hvpic_gather_push(c, self.p, self.cs, E, B, None, None, pd)
         H.hvpic_sort(c, self.p, self.q, self.cs, self.cs_alt, full=False)
         self.p, self.q = self.q, self.p
         self.cs, self.cs_alt = self.cs_alt, self.cs

@@ -66,7 +66,7 @@ def test_init_rejects_bad_arguments_without_device_work(H):
     assert L.hvpic_init(ctypes.byref(p), None, None, ctypes.byref(ctx)) == H.HVPIC_EINVAL
     assert L.hvpic_init(ctypes.byref(p), None, ctypes.c_void_p(0x1001), ctypes.byref(ctx)) \
         == H.HVPIC_EINVAL  # misaligned workspace
-    assert L.hvpic_gather_push(None, None, None, None, None, None, None) == H.HVPIC_ESTATE
+    assert L.hvpic_gather_push(None, None, None, None, None, None, None, None) == H.HVPIC_ESTATE
     assert L.hvpic_sort(None, None, None, None, None, 0) == H.HVPIC_ESTATE
     assert L.hvpic_finalize(None) == H.HVPIC_ESTATE
     assert H.hvpic_strerror(H.HVPIC_EINVAL) == "invalid argument"

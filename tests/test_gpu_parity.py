@@ -57,15 +57,17 @@ def _sorted(cfg, parts):
 
 @pytest.mark.parametrize("name,cfg", CASES)
 @pytest.mark.parametrize("ppc", [3.7, 40.2])
-def test_gather_push(H, name, cfg, ppc):
-    announce("gather_push", name, ppc)
+@pytest.mark.parametrize("counted", [False, True])
+def test_gather_push(H, name, cfg, ppc, counted):
+    announce("gather_push", name, ppc, counted)
     _, parts, B = W.random_box(21, cfg, ppc)
-    parts, _ = _sorted(cfg, parts)
+    parts, cs0 = _sorted(cfg, parts)
     E = W.random_field(22, cfg, 0.3)
     ctx = H.Context(cfg, parts["cell"].size)
     p = H.Particles.from_numpy(parts, cfg.ndim)
     diag = torch.zeros(4, dtype=torch.float64, device="cuda")
-    H.hvpic_gather_push(ctx.ctx, p, dev(E), dev(B), None, None, diag)
+    cs = dev(cs0, np.int32) if counted else None
+    H.hvpic_gather_push(ctx.ctx, p, cs, dev(E), dev(B), None, None, diag)
     flags, counts = H.hvpic_sync_status(ctx.ctx)
     got = p.to_numpy()
     ref = O.particles64(parts)
@@ -73,6 +75,7 @@ def test_gather_push(H, name, cfg, ppc):
     compare_particles(cfg, got, ref)
     assert np.allclose(diag.cpu().numpy(), rd, rtol=1e-5, atol=1e-6 * abs(rd[0]))
     assert counts[0] == st.moved_gt1 and counts[1] == st.nonfinite
+    assert not flags & H.FLAG_BAD_INPUT
 
 
 @pytest.mark.parametrize("name,cfg", CASES)
@@ -85,23 +88,26 @@ def test_deposit(H, name, cfg, ppc, sorted_, back):
     # of a face; such points are kept out of the input
     keep = ~deposit_point_straddlers(cfg, parts, back)
     parts = {k: v[keep] for k, v in parts.items()}
+    cs = None
     if sorted_:
-        parts, _ = _sorted(cfg, parts)
+        parts, cs0 = _sorted(cfg, parts)
+        cs = dev(cs0, np.int32)
     ctx = H.Context(cfg, parts["cell"].size)
     p = H.Particles.from_numpy(parts, cfg.ndim)
     n = torch.full((cfg.ncell,), 7.0, device="cuda")   # overwritten
     J = torch.full((3, cfg.ncell), 7.0, device="cuda")
-    H.hvpic_deposit(ctx.ctx, p, None, back, n, J)
+    H.hvpic_deposit(ctx.ctx, p, cs, back, n, J)
     rn, rJ = O.deposit(cfg, O.particles64(parts), back)
     assert rel_l2(n.cpu().numpy(), rn) < 1e-5
     assert rel_l2(J.cpu().numpy(), rJ) < 1e-5
 
 
 @pytest.mark.parametrize("name,cfg", CASES)
-def test_fused_push_deposit(H, name, cfg):
+@pytest.mark.parametrize("counted", [False, True])
+def test_fused_push_deposit(H, name, cfg, counted):
     """Push with the mid-point deposit fused in == oracle push, then deposit at
     x^{n+1} - (dt/2) v^{n+1/2}."""
-    announce("fused", name)
+    announce("fused", name, counted)
     _, parts, B = W.random_box(41, cfg, 33.3)
     E = W.random_field(42, cfg, 0.3)
     ref = O.particles64(parts)
@@ -111,12 +117,13 @@ def test_fused_push_deposit(H, name, cfg):
     for k in offs:
         near |= (np.abs(ref[k] + 1) < 1e-5) | (np.abs(ref[k] - 1) < 1e-5)
     parts = {k: v[~near] for k, v in parts.items()}
-    parts, _ = _sorted(cfg, parts)
+    parts, cs0 = _sorted(cfg, parts)
     ctx = H.Context(cfg, parts["cell"].size)
     p = H.Particles.from_numpy(parts, cfg.ndim)
     n = torch.zeros(cfg.ncell, device="cuda")
     J = torch.zeros((3, cfg.ncell), device="cuda")
-    H.hvpic_gather_push(ctx.ctx, p, dev(E), dev(B), n, J, None)
+    H.hvpic_gather_push(ctx.ctx, p, dev(cs0, np.int32) if counted else None, dev(E), dev(B), n, J,
+                        None)
     ref = O.particles64(parts)
     O.push(cfg, ref, E, B)
     rn, rJ = O.deposit(cfg, ref, 0.5 * cfg.dt)
@@ -148,10 +155,12 @@ def test_full_sort(H, name, cfg, ppc):
 
 @pytest.mark.parametrize("name,cfg", CASES)
 @pytest.mark.parametrize("far", [False, True])
-def test_neighbour_sort_after_push(H, name, cfg, far):
+@pytest.mark.parametrize("counted", [False, True])
+def test_neighbour_sort_after_push(H, name, cfg, far, counted):
     """Sorted store -> push -> neighbour-move sort gives the stable order; with
-    a particle moved two cells the call falls back to the general sort."""
-    announce("nb_sort", name, far)
+    a particle moved two cells the call falls back to the general sort.  With
+    cell_start given to the push, the sort uses the push's move counts."""
+    announce("nb_sort", name, far, counted)
     _, parts, B = W.random_box(61, cfg, 20.0, vmax_cells=0.95)
     parts, cs0 = _sorted(cfg, parts)
     if far:
@@ -163,7 +172,7 @@ def test_neighbour_sort_after_push(H, name, cfg, far):
     q = H.Particles(cfg.ndim, n)
     cs_prev = dev(cs0, np.int32)
     cs = torch.zeros(cfg.ncell + 1, dtype=torch.int32, device="cuda")
-    H.hvpic_gather_push(ctx.ctx, p, dev(E), dev(B))
+    H.hvpic_gather_push(ctx.ctx, p, cs_prev if counted else None, dev(E), dev(B))
     pushed = p.to_numpy()
     H.hvpic_sort(ctx.ctx, p, q, cs_prev, cs, full=False)
     flags, counts = H.hvpic_sync_status(ctx.ctx)
@@ -221,9 +230,20 @@ def test_empty_and_single(H):
     E = torch.zeros((3, cfg.ncell), device="cuda")
     n = torch.ones(cfg.ncell, device="cuda")
     J = torch.ones((3, cfg.ncell), device="cuda")
-    H.hvpic_gather_push(ctx.ctx, p, E, E, n, J, diag)
+    H.hvpic_gather_push(ctx.ctx, p, None, E, E, n, J, diag)
     H.hvpic_sort(ctx.ctx, p, q, None, cs, full=True)
     assert np.all(diag.cpu().numpy() == 0) and np.all(cs.cpu().numpy() == 0)
+    assert float(n.abs().sum()) == 0 and float(J.abs().sum()) == 0
+    # the same with cell_start (all zero for an empty store) and a
+    # neighbour sort that takes the push's (zero) move counts
+    diag.fill_(9.0)
+    n.fill_(1.0)
+    cs2 = torch.full((cfg.ncell + 1,), -1, dtype=torch.int32, device="cuda")
+    H.hvpic_gather_push(ctx.ctx, p, cs, E, E, n, J, diag)
+    H.hvpic_sort(ctx.ctx, p, q, cs, cs2, full=False)
+    flags, _ = H.hvpic_sync_status(ctx.ctx)
+    assert flags == 0
+    assert np.all(diag.cpu().numpy() == 0) and np.all(cs2.cpu().numpy() == 0)
     assert float(n.abs().sum()) == 0 and float(J.abs().sum()) == 0
     announce("single")
     one = {k: v[:1] for k, v in W.random_box(3, cfg, 1.0)[1].items()}
@@ -234,10 +254,11 @@ def test_empty_and_single(H):
 
 
 @pytest.mark.parametrize("nx,ny", [(1, 5), (2, 3), (3, 1)])
-def test_tiny_grids(H, nx, ny):
+@pytest.mark.parametrize("counted", [False, True])
+def test_tiny_grids(H, nx, ny, counted):
     """Degenerate grids (periodic axes of 1-3 cells): push, sort, deposit."""
     cfg = cfg2(nx=nx, ny=ny)
-    announce("tiny", nx, ny)
+    announce("tiny", nx, ny, counted)
     _, parts, B = W.random_box(91, cfg, 50.0, vmax_cells=0.9)
     parts, cs0 = _sorted(cfg, parts)
     E = W.random_field(92, cfg, 0.1)
@@ -247,10 +268,11 @@ def test_tiny_grids(H, nx, ny):
     q = H.Particles(2, n)
     nd = torch.zeros(cfg.ncell, device="cuda")
     Jd = torch.zeros((3, cfg.ncell), device="cuda")
-    H.hvpic_gather_push(ctx.ctx, p, dev(E), dev(B), nd, Jd)
+    cs_prev = dev(cs0, np.int32)
+    H.hvpic_gather_push(ctx.ctx, p, cs_prev if counted else None, dev(E), dev(B), nd, Jd)
     pushed = p.to_numpy()
     cs = torch.zeros(cfg.ncell + 1, dtype=torch.int32, device="cuda")
-    H.hvpic_sort(ctx.ctx, p, q, dev(cs0, np.int32), cs, full=False)
+    H.hvpic_sort(ctx.ctx, p, q, cs_prev, cs, full=False)
     ref = O.particles64(parts)
     O.push(cfg, ref, E, B)
     compare_particles(cfg, pushed, ref)
@@ -259,11 +281,12 @@ def test_tiny_grids(H, nx, ny):
     assert rel_l2(nd.cpu().numpy(), rn) < 1e-5 and rel_l2(Jd.cpu().numpy(), rJ) < 1e-5
 
 
-def test_dense_single_cell(H):
+@pytest.mark.parametrize("counted", [False, True])
+def test_dense_single_cell(H, counted):
     """All particles in one cell: the neighbour sort's one-wavefront-per-cell
     loop and the deposit window see one long segment."""
     cfg = cfg2(nx=9, ny=8)
-    announce("dense")
+    announce("dense", counted)
     rng = np.random.Generator(np.random.PCG64(5))
     n = 20000
     parts = {"cell": np.full(n, 40, np.int32),
@@ -282,12 +305,53 @@ def test_dense_single_cell(H):
     q = H.Particles(2, n)
     nd = torch.zeros(cfg.ncell, device="cuda")
     Jd = torch.zeros((3, cfg.ncell), device="cuda")
-    H.hvpic_gather_push(ctx.ctx, p, dev(E), dev(B), nd, Jd)
+    cs_prev = dev(cs0)
+    H.hvpic_gather_push(ctx.ctx, p, cs_prev if counted else None, dev(E), dev(B), nd, Jd)
     pushed = p.to_numpy()
     cs = torch.zeros(cfg.ncell + 1, dtype=torch.int32, device="cuda")
-    H.hvpic_sort(ctx.ctx, p, q, dev(cs0), cs, full=False)
+    H.hvpic_sort(ctx.ctx, p, q, cs_prev, cs, full=False)
     _check_sorted(cfg, pushed, q.to_numpy(), cs.cpu().numpy())
     ref = O.particles64(parts)
     O.push(cfg, ref, E, B)
     rn, rJ = O.deposit(cfg, ref, 0.5 * cfg.dt)
     assert rel_l2(nd.cpu().numpy(), rn) < 1e-5 and rel_l2(Jd.cpu().numpy(), rJ) < 1e-5
+
+
+@pytest.mark.parametrize("name,cfg", [CASES[0], CASES[2]])
+def test_push_inconsistent_cell_start(H, name, cfg):
+    """A cell_start that disagrees with the store: the push flags bad input,
+    still pushes every particle from its own cell and deposits it, and the
+    next neighbour sort completes with the general sort."""
+    announce("push_bad_cs", name)
+    _, parts, B = W.random_box(95, cfg, 6.0, vmax_cells=0.9)
+    parts, cs0 = _sorted(cfg, parts)
+    E = W.random_field(96, cfg, 0.1)
+    ref = O.particles64(parts)
+    O.push(cfg, ref, E, B)
+    near = deposit_point_straddlers(cfg, ref, 0.5 * cfg.dt)
+    for k in ["ox", "oy"] + (["oz"] if cfg.ndim == 3 else []):
+        near |= (np.abs(ref[k] + 1) < 1e-5) | (np.abs(ref[k] - 1) < 1e-5)
+    parts = {k: v[~near] for k, v in parts.items()}
+    parts, cs0 = _sorted(cfg, parts)
+    bad = cs0.copy()
+    mid = cfg.ncell // 2
+    bad[mid] = bad[mid + 1]  # cell mid-1 claims cell mid's particles
+    n = parts["cell"].size
+    ctx = H.Context(cfg, n)
+    p = H.Particles.from_numpy(parts, cfg.ndim)
+    q = H.Particles(cfg.ndim, n)
+    nd = torch.zeros(cfg.ncell, device="cuda")
+    Jd = torch.zeros((3, cfg.ncell), device="cuda")
+    cs_bad = dev(bad, np.int32)
+    H.hvpic_gather_push(ctx.ctx, p, cs_bad, dev(E), dev(B), nd, Jd)
+    pushed = p.to_numpy()
+    cs = torch.zeros(cfg.ncell + 1, dtype=torch.int32, device="cuda")
+    H.hvpic_sort(ctx.ctx, p, q, cs_bad, cs, full=False)
+    flags, _ = H.hvpic_sync_status(ctx.ctx)
+    assert flags & H.FLAG_BAD_INPUT
+    ref = O.particles64(parts)
+    O.push(cfg, ref, E, B)
+    compare_particles(cfg, pushed, ref)
+    rn, rJ = O.deposit(cfg, ref, 0.5 * cfg.dt)
+    assert rel_l2(nd.cpu().numpy(), rn) < 1e-5 and rel_l2(Jd.cpu().numpy(), rJ) < 1e-5
+    _check_sorted(cfg, pushed, q.to_numpy(), cs.cpu().numpy())

@@ -105,7 +105,7 @@ def test_harris_full_size_one_step(mods):
     assert np.array_equal(g.cs.cpu().numpy(), o.cell_start)
     # step 1 by hand through the C-ABI to see the pushed store before the sort
     c = g.ctx.ctx
-    H.hvpic_gather_push(c, g.p, g.E, g.B, g.n_half, g.J_half, g.push_diag)
+    H.hvpic_gather_push(c, g.p, g.cs, g.E, g.B, g.n_half, g.J_half, g.push_diag)
     pushed = g.p.to_numpy()
     o.push_diag, _ = O.push(cfg, o.p, o.E, o.B)
     nstr = compare_particles(cfg, pushed, o.p)
