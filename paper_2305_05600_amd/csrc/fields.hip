@@ -363,7 +363,7 @@ __global__ __launch_bounds__(kBlock) void k_field_ohm_out(const float* __restric
 }
 
 // {W_B, W_dB} = {1/2 V sum |B|^2, 1/2 V (sum |B|^2 - |sum B|^2 / ncell)}.
-__global__ __launch_bounds__(kBlock) void k_field_diag_final(const double* part, int nblocks,
+__global__ __launch_bounds__(1024) void k_field_diag_final(const double* part, int nblocks,
                                                              double* out, double half_vol,
                                                              double inv_ncell) {
   double r[4];
@@ -485,7 +485,7 @@ int field_impl(hvpic_ctx* c, float* B, const float* n_half, const float* J_half,
                      g, aux, E_out, diag_out ? c->field_part : nullptr);
   if (diag_out) {
     const double V = c->p.dx * c->p.dy * c->p.dz;
-    hipLaunchKernelGGL(k_field_diag_final, dim3(1), blk, 0, s, (const double*)c->field_part,
+    hipLaunchKernelGGL(k_field_diag_final, dim3(1), dim3(1024), 0, s, (const double*)c->field_part,
                        (int)grid.x, diag_out, 0.5 * V, 1.0 / (double)nc);
   }
   return hipGetLastError() == hipSuccess ? HVPIC_OK : HVPIC_EHIP;

@@ -1098,8 +1098,9 @@ __global__ void k_write_zero_diag(double* out, int nv) {
   if (threadIdx.x < nv) out[threadIdx.x] = 0.0;
 }
 
-__global__ __launch_bounds__(kBlock) void k_push_diag_final(const double* part, int nblocks,
-                                                            double* out) {
+// One block of 1024 threads: up to 8192 partials in a single round of loads.
+__global__ __launch_bounds__(1024) void k_push_diag_final(const double* part, int nblocks,
+                                                          double* out) {
   double r[4];
   sum_partials<4>(part, nblocks, r);
   if (threadIdx.x == 0)
@@ -1215,7 +1216,7 @@ int launch_gather_push(hvpic_ctx* c, hvpic_particles* p, const int32_t* cell_sta
   }
   if (dep) moments_out(c, n_mid, J_mid);
   if (diag_out)
-    hipLaunchKernelGGL(k_push_diag_final, dim3(1), dim3(kBlock), 0, c->stream,
+    hipLaunchKernelGGL(k_push_diag_final, dim3(1), dim3(1024), 0, c->stream,
                        (const double*)c->push_part, nblocks, diag_out);
   return hipGetLastError() == hipSuccess ? HVPIC_OK : HVPIC_EHIP;
 }

@@ -100,6 +100,9 @@ __device__ __forceinline__ uint64_t match_code(int code, uint64_t valid, const u
 constexpr int kCellsPerWave = 2;
 constexpr int kCellBits = 1;
 constexpr int kCountBatches = 4;    // 64-particle batches whose keys are loaded together
+// The scatter takes kScatterCells cells per wavefront.
+constexpr int kScatterCells = 2;
+constexpr int kScatterCellBits = 1;
 constexpr int kScatterBatches = 4;  // batches whose fields are loaded together
 
 // Boundaries of the wavefront's cells: b(m) = cs_prev[a0 + m], m = 0..na,
@@ -543,18 +546,35 @@ __global__ __launch_bounds__(kBlock) void k_nb_scatter(const int32_t* __restrict
                                                        const Status* st, uint32_t* rk0, uint32_t* rk1,
                                                        uint32_t* rv0, uint32_t* rv1) {
   constexpr int ND = Dirs<NDIM>::N, NB = Dirs<NDIM>::BITS;
-  constexpr int CODE_BITS = NB + kCellBits;
-  __shared__ uint32_t s_next[kWaves][kCellsPerWave * ND];  // next free slot of each group
+  constexpr int CODE_BITS = NB + kScatterCellBits;
+  constexpr int NG = kScatterCells * ND;  // groups of the wavefront
+  constexpr int GPL = (NG + 63) / 64;     // groups per lane
+  __shared__ uint32_t s_next[kWaves][NG];  // next free slot of each group
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const int a0 = (blockIdx.x * kWaves + wid) * kCellsPerWave;
-  const int na = a0 < g.ncell ? min(kCellsPerWave, g.ncell - a0) : 0;
+  const int a0 = (blockIdx.x * kWaves + wid) * kScatterCells;
+  const int na = a0 < g.ncell ? min(kScatterCells, g.ncell - a0) : 0;
+  // The far decision, the group bases and the cell bounds are independent:
+  // their loads go out together.
+  const uint32_t far = __hip_atomic_load(&st->far_decision, __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
+  uint32_t bv[GPL];
+#pragma unroll
+  for (int u = 0; u < GPL; ++u) {
+    const int q = lane + 64 * u;
+    bv[u] = q < na * ND ? bases[(int64_t)a0 * ND + q] : 0u;
+  }
+  const int bnd = lane <= na ? cs_prev[a0 + lane] : 0;
   // the group bases are used once: the table is left zero for the next
   // counting push
-  for (int q = lane; q < na * ND; q += 64) {
-    s_next[wid][q] = bases[(int64_t)a0 * ND + q];
-    bases[(int64_t)a0 * ND + q] = 0u;
+#pragma unroll
+  for (int u = 0; u < GPL; ++u) {
+    const int q = lane + 64 * u;
+    if (q < na * ND) {
+      s_next[wid][q] = bv[u];
+      bases[(int64_t)a0 * ND + q] = 0u;
+    }
   }
-  if (__hip_atomic_load(&st->far_decision, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+  if (far != 0) {
     if (blockIdx.x == 0) {
       uint32_t* rkey[2] = {rk0, rk1};
       uint32_t* rval[2] = {rv0, rv1};
@@ -562,10 +582,15 @@ __global__ __launch_bounds__(kBlock) void k_nb_scatter(const int32_t* __restrict
     }
     return;
   }
-  __syncthreads();
   if (na == 0) return;
-  int bnd;
-  if (!wave_bounds(cs_prev, a0, na, n, lane, bnd)) return;
+  {
+    const int prev = __shfl_up(bnd, 1);
+    const bool bad = lane <= na && (bnd < 0 || bnd > n || (lane > 0 && bnd < prev));
+    if (__ballot(bad) != 0) return;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   const int64_t pb = __builtin_amdgcn_readlane(bnd, 0), pe = __builtin_amdgcn_readlane(bnd, na);
   for (int64_t q0 = pb; q0 < pe; q0 += 64 * kScatterBatches) {
    int keys[kScatterBatches];
@@ -696,7 +721,8 @@ void enqueue_neighbour(hvpic_ctx* c, const hvpic_particles* in, hvpic_particles*
   hipLaunchKernelGGL((k_nb_bases<NDIM>), dim3(tiles), dim3(kBlock), 0, s, c->sort_cnt, g, cs,
                      (const uint32_t*)blk);
   timing_begin(c, HVPIC_KERNEL_SORT_SCATTER);
-  hipLaunchKernelGGL((k_nb_scatter<NDIM>), dim3(cblocks), dim3(kBlock), 0, s, cs_prev, in->n, g,
+  const int sblocks = (int)ceil_div(c->ncell, kWaves * kScatterCells);
+  hipLaunchKernelGGL((k_nb_scatter<NDIM>), dim3(sblocks), dim3(kBlock), 0, s, cs_prev, in->n, g,
                      c->sort_cnt, fields_of(in), fields_of(out), cs,
                      (const Status*)c->status, c->rkey[0], c->rkey[1], c->rval[0], c->rval[1]);
   timing_end(c, HVPIC_KERNEL_SORT_SCATTER);
