@@ -11,11 +11,13 @@
 //   on the cell-centred grid.
 //
 // The moments are frozen during the subcycle, so one prep kernel forms
-// 1/n_f (in FP64), u_i and -grad(p_e)/n_f once per step.  Each RK2 stage is
-// then one kernel that evaluates Ohm's law at the 2*ndim neighbours of a cell
-// and takes the curl; E is never stored.  All grids are small enough to live in
-// the MI355X L2/MALL during the subcycle, so the stages are latency-bound and
-// each lane keeps its work independent.
+// 1/n_f (in FP64), u_i and -grad(p_e)/n_f once per step.  In 2D one kernel
+// runs a whole RK2 substep on LDS tiles with a 4-cell halo (B -> Ea -> B* ->
+// Eb -> B); in 3D each RK2 stage is one kernel that evaluates Ohm's law at the
+// 2*ndim neighbours of a cell and takes the curl.  E is never stored inside
+// the subcycle.  B is carried as an unevaluated sum hi + lo so that the many
+// small substep updates keep their low bits.  The grids fit in the MI355X
+// L2/MALL during the subcycle, so the substeps are latency-bound.
 #include "hvpic_internal.hpp"
 
 namespace hvpic {
