@@ -212,13 +212,14 @@ __global__ __launch_bounds__(kBlock) void k_field_stage(const float* __restrict_
 // fields in LDS: B (halo 4) -> Ea (halo 3) -> B* (halo 2) -> Eb (halo 1) ->
 // B_new on the tile.  Reads Bin, writes Bout (distinct buffers: neighbouring
 // tiles read the halo of Bin while this one writes).
-constexpr int kTX = 32, kTY = 16;
+constexpr int kTX = 32, kTY = 8;
+constexpr int kSubBlock = 512;  // threads per substep tile (8 wavefronts hide the load latency)
 constexpr int kBW = kTX + 8, kBH = kTY + 8;   // B with halo 4
 constexpr int kAW = kTX + 6, kAH = kTY + 6;   // aux and Ea with halo 3
 constexpr int kSW = kTX + 4, kSH = kTY + 4;   // B* with halo 2
 constexpr int kFW = kTX + 2, kFH = kTY + 2;   // Eb with halo 1
 
-__global__ __launch_bounds__(kBlock) void k_field_substep2d(const float* __restrict__ Bin,
+__global__ __launch_bounds__(kSubBlock) void k_field_substep2d(const float* __restrict__ Bin,
                                                             const float* __restrict__ Lin,
                                                             float* __restrict__ Bout,
                                                             float* __restrict__ Lout, float h,
@@ -235,14 +236,14 @@ __global__ __launch_bounds__(kBlock) void k_field_substep2d(const float* __restr
     y %= g.ny; if (y < 0) y += g.ny;
     return x + g.nx * y;
   };
-  for (int t = threadIdx.x; t < kBH * kBW; t += kBlock) {
+  for (int t = threadIdx.x; t < kBH * kBW; t += kSubBlock) {
     const int ly = t / kBW - 4, lx = t % kBW - 4;
     const int c = gidx(lx, ly);
     sB[0][t] = Bin[c];
     sB[1][t] = Bin[nc + c];
     sB[2][t] = Bin[2 * nc + c];
   }
-  for (int t = threadIdx.x; t < kAH * kAW; t += kBlock) {
+  for (int t = threadIdx.x; t < kAH * kAW; t += kSubBlock) {
     const int ly = t / kAW - 3, lx = t % kAW - 3;
     const int c = gidx(lx, ly);
     sA[0][t] = aux.inv[c];
@@ -263,7 +264,7 @@ __global__ __launch_bounds__(kBlock) void k_field_substep2d(const float* __restr
     e[2] = (w0 * b1 - w1 * b0) + sA[6][a] + eta * j2;
   };
   // Ea on the tile with halo 3 (from B with halo 4)
-  for (int t = threadIdx.x; t < kAH * kAW; t += kBlock) {
+  for (int t = threadIdx.x; t < kAH * kAW; t += kSubBlock) {
     const int ly = t / kAW, lx = t % kAW;      // B index = (ly+1, lx+1)
     const int b = (ly + 1) * kBW + lx + 1;
     const float j0 = (sB[2][b + kBW] - sB[2][b - kBW]) * g.idy2;
@@ -278,7 +279,7 @@ __global__ __launch_bounds__(kBlock) void k_field_substep2d(const float* __restr
   __syncthreads();
   // B* = B - (h/2) curl Ea on the tile with halo 2
   const float hh = 0.5f * h;
-  for (int t = threadIdx.x; t < kSH * kSW; t += kBlock) {
+  for (int t = threadIdx.x; t < kSH * kSW; t += kSubBlock) {
     const int ly = t / kSW, lx = t % kSW;
     const int e = (ly + 1) * kAW + lx + 1;     // Ea index
     const int b = (ly + 2) * kBW + lx + 2;     // B index
@@ -291,7 +292,7 @@ __global__ __launch_bounds__(kBlock) void k_field_substep2d(const float* __restr
   }
   __syncthreads();
   // Eb on the tile with halo 1 (stored in sE with the Eb row width)
-  for (int t = threadIdx.x; t < kFH * kFW; t += kBlock) {
+  for (int t = threadIdx.x; t < kFH * kFW; t += kSubBlock) {
     const int ly = t / kFW, lx = t % kFW;
     const int s = (ly + 1) * kSW + lx + 1;     // B* index
     const int a = (ly + 2) * kAW + lx + 2;     // aux index
@@ -307,7 +308,7 @@ __global__ __launch_bounds__(kBlock) void k_field_substep2d(const float* __restr
   }
   __syncthreads();
   // B_new = B - h curl Eb on the tile
-  for (int t = threadIdx.x; t < kTY * kTX; t += kBlock) {
+  for (int t = threadIdx.x; t < kTY * kTX; t += kSubBlock) {
     const int ly = t / kTX, lx = t % kTX;
     const int x = tx0 + lx, y = ty0 + ly;
     if (x >= g.nx || y >= g.ny) continue;
@@ -457,7 +458,8 @@ int field_impl(hvpic_ctx* c, float* B, const float* n_half, const float* J_half,
       float* dh = Xh;
       float* dl = Xl;
       for (int m = 0; m < c->p.nsub; ++m) {
-        hipLaunchKernelGGL(k_field_substep2d, tiles, blk, 0, s, sh, sl, dh, dl, h, eta, g, aux);
+        hipLaunchKernelGGL(k_field_substep2d, tiles, dim3(kSubBlock), 0, s, sh, sl, dh, dl, h, eta, g,
+                           aux);
         sh = dh;
         sl = dl;
         dh = dh == Xh ? Yh : Xh;

@@ -747,21 +747,33 @@ __device__ __forceinline__ void check_cell_start(const int32_t* __restrict__ cs,
   if (bad) flag_far(st, HVPIC_FLAG_BAD_INPUT, &st->bad_input);
 }
 
-// Direction code of the move (i,j,k) -> (ni,nj,nk) of particle idx of old
-// cell a (window column rel), classified as the sort does; -1 (and the sort
-// sent down its general path) for a longer move or a particle out of place.
+// Direction code of the move (i,j,k) -> (ni,nj,nk) (shift si,sj,sk) of
+// particle idx of old cell a (window column rel), classified as the sort does;
+// -1 (and the sort sent down its general path) for a longer move or a
+// particle out of place.
 template <int NDIM, typename Args>
 __device__ __forceinline__ int move_direction(const Args& A, int64_t idx, int a, int rel,
                                               bool inwin, const int32_t* s_cs, int i, int j,
-                                              int k, int ni, int nj, int nk) {
+                                              int k, int ni, int nj, int nk, int si, int sj,
+                                              int sk) {
   const int64_t lo = inwin ? s_cs[rel] : A.cs[a], hi = inwin ? s_cs[rel + 1] : A.cs[a + 1];
   if (idx < lo || idx >= hi) {
     flag_far(A.st, HVPIC_FLAG_BAD_INPUT, &A.st->bad_input);
     return -1;
   }
   const Geo& g = A.g;
-  const int di = canon_move(ni - i, g.nx), dj = canon_move(nj - j, g.ny);
-  const int dk = NDIM == 3 ? canon_move(nk - k, g.nz) : 0;
+  int di, dj, dk;
+  if (g.nx >= 3 && g.ny >= 3 && (NDIM == 2 || g.nz >= 3)) {
+    // with three or more cells per axis a shift of at most one cell is
+    // exactly the wrapped index difference
+    di = si < -1 || si > 1 ? 2 : si;
+    dj = sj < -1 || sj > 1 ? 2 : sj;
+    dk = sk < -1 || sk > 1 ? 2 : sk;
+  } else {
+    di = canon_move(ni - i, g.nx);
+    dj = canon_move(nj - j, g.ny);
+    dk = NDIM == 3 ? canon_move(nk - k, g.nz) : 0;
+  }
   if (di == 2 || dj == 2 || dk == 2) {
     flag_far(A.st, HVPIC_FLAG_MOVE_GT1, nullptr);
     return -1;
@@ -949,7 +961,8 @@ void k_gather_push(PushArgs A) {
         uy[q] = nvy;
         uz[q] = nvz;
         if (cnt_on)
-          d = move_direction<NDIM>(A, b4 + q, a, rel, inwin, s_cs, i, j, k, ni, nj, nk);
+          d = move_direction<NDIM>(A, b4 + q, a, rel, inwin, s_cs, i, j, k, ni, nj, nk, si, sj,
+                                   sk);
         if (DEP) {
           // Mid-point x^{n+1/2} = x^n + (dt/2) v^{n+1/2}.
           xm = fmaf(nvx, 0.5f * A.kx, x);
