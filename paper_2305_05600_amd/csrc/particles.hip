@@ -1094,8 +1094,18 @@ __global__ void k_zero(float* __restrict__ a, int64_t na, float* __restrict__ b,
 
 // FP64 moment accumulators -> FP32 outputs; leaves the accumulators at zero
 // for the next deposit.
-__global__ void k_moments_out(double* __restrict__ acc, int ncell, float* __restrict__ n,
-                              float* __restrict__ J) {
+__global__ __launch_bounds__(kBlock) void k_moments_out(double* __restrict__ acc, int ncell,
+                                                        float* __restrict__ n,
+                                                        float* __restrict__ J,
+                                                        const double* part, int nparts,
+                                                        double* diag_out) {
+  // block 0 also finishes the push diagnostics when asked (saves a launch)
+  if (diag_out != nullptr && blockIdx.x == 0) {
+    double r[4];
+    sum_partials<4>(part, nparts, r);
+    if (threadIdx.x == 0)
+      for (int k = 0; k < 4; ++k) diag_out[k] = r[k];
+  }
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < 4ll * ncell; i += stride) {
     const float v = (float)acc[i];
@@ -1165,10 +1175,12 @@ void zero_counts(hvpic_ctx* c) {
   c->cnt_clean = true;
 }
 
-void moments_out(hvpic_ctx* c, float* n, float* J) {
+// FP64 accumulators -> n, J; with diag_out also the push diagnostics from
+// nparts per-block partials.
+void moments_out(hvpic_ctx* c, float* n, float* J, int nparts = 0, double* diag_out = nullptr) {
   const int blocks = (int)std::min<int64_t>(ceil_div(4ll * c->ncell, kBlock), 2048);
   hipLaunchKernelGGL(k_moments_out, dim3(blocks), dim3(kBlock), 0, c->stream, c->mom_acc,
-                     c->ncell, n, J);
+                     c->ncell, n, J, (const double*)c->push_part, nparts, diag_out);
 }
 
 int launch_gather_push(hvpic_ctx* c, hvpic_particles* p, const int32_t* cell_start,
@@ -1227,8 +1239,9 @@ int launch_gather_push(hvpic_ctx* c, hvpic_particles* p, const int32_t* cell_sta
     c->cnt_cs = cell_start;
     c->cnt_n = p->n;
   }
-  if (dep) moments_out(c, n_mid, J_mid);
-  if (diag_out)
+  if (dep)
+    moments_out(c, n_mid, J_mid, nblocks, diag_out);
+  else if (diag_out)
     hipLaunchKernelGGL(k_push_diag_final, dim3(1), dim3(1024), 0, c->stream,
                        (const double*)c->push_part, nblocks, diag_out);
   return hipGetLastError() == hipSuccess ? HVPIC_OK : HVPIC_EHIP;

@@ -15,10 +15,11 @@
 // per-new-cell totals, the first slot of group (a, d) is cell_start[c] plus the
 // counts of the groups of c whose old cell index is smaller, and a particle's
 // slot adds its rank among the earlier particles of its own group, found with
-// wavefront ballots.  Kernels: count (one wavefront per old cell), tile totals
-// of the new counts, scan of tile totals, per-cell prefix + group bases,
-// scatter (one wavefront per old cell).  A particle that moved further (or an
-// inconsistent cell_start) is flagged by the count kernel; the flag is handed
+// wavefront ballots.  Kernels: count (one wavefront per old cell; skipped when
+// the push already counted), tile totals of the new counts, per-cell prefix +
+// group bases (each block adds up the tile totals before its own), scatter
+// (one wavefront per two old cells).  A particle that moved further (or an
+// inconsistent cell_start) is flagged by the count pass; the flag is handed
 // to the scatter kernel, in which one block then runs the general sort on its
 // own (slow, but it costs no extra launch in the common case and needs no host
 // round trip).
@@ -294,8 +295,24 @@ __global__ __launch_bounds__(1024) void k_scan_tiles(uint32_t* blk, int m) {
   if (threadIdx.x == 0) blk[m] = carry;
 }
 
+// Sum of v[0..m) by the whole block (every thread gets it).
+__device__ uint32_t block_sum(const uint32_t* __restrict__ v, int m) {
+  __shared__ uint32_t ws[kWaves];
+  uint32_t x = 0;
+  for (int i = threadIdx.x; i < m; i += kBlock) x += v[i];
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = x;
+  __syncthreads();
+  uint32_t t = 0;
+  for (int w = 0; w < kWaves; ++w) t += ws[w];
+  __syncthreads();
+  return t;
+}
+
 // cell_start from the per-cell totals, and the first slot of every group
-// (source cell, direction) of each new cell, written over cnt.
+// (source cell, direction) of each new cell, written over cnt.  blk holds
+// the tile totals; each block adds up those before it (a few hundred values
+// at most), which spares a separate scan launch.
 template <int NDIM>
 __global__ __launch_bounds__(kBlock) void k_nb_bases(uint32_t* __restrict__ cnt, SortGeo g,
                                                      int32_t* __restrict__ cs,
@@ -308,14 +325,14 @@ __global__ __launch_bounds__(kBlock) void k_nb_bases(uint32_t* __restrict__ cnt,
     s[q * kBlock + threadIdx.x] = c < g.ncell ? (uint32_t)cs[c] : 0u;
   }
   __syncthreads();
-  tile_exclusive_scan(s);
-  const uint32_t off = blk[blockIdx.x];
+  const uint32_t tile_total = tile_exclusive_scan(s);
+  const uint32_t off = block_sum(blk, blockIdx.x);
   for (int q = 0; q < kScanTile / kBlock; ++q) {
     const int64_t c = t0 + q * kBlock + threadIdx.x;
     if (c >= g.ncell) break;
     const uint32_t start = off + s[q * kBlock + threadIdx.x];
     cs[c] = (int32_t)start;
-    if (c == g.ncell - 1) cs[g.ncell] = (int32_t)blk[gridDim.x];
+    if (c == g.ncell - 1) cs[g.ncell] = (int32_t)(off + tile_total);
     int i, j, k;
     ijk((int)c, g, i, j, k);
     int src[ND];
@@ -717,7 +734,6 @@ void enqueue_neighbour(hvpic_ctx* c, const hvpic_particles* in, hvpic_particles*
                        in->n, g, c->sort_cnt, c->status);
   hipLaunchKernelGGL((k_nb_newcount<NDIM>), dim3(tiles), dim3(kBlock), 0, s,
                      (const uint32_t*)c->sort_cnt, g, cs, blk, c->status);
-  hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, s, blk, tiles);
   hipLaunchKernelGGL((k_nb_bases<NDIM>), dim3(tiles), dim3(kBlock), 0, s, c->sort_cnt, g, cs,
                      (const uint32_t*)blk);
   timing_begin(c, HVPIC_KERNEL_SORT_SCATTER);
