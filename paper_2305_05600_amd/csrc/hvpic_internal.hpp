@@ -137,7 +137,7 @@ struct hvpic_ctx {
   uint32_t* rhist;       // radix per-block digit counts
   float* fscratch;       // field scratch [20][ncell]
   double* mom_acc;       // FP64 moment accumulators [4][ncell], kept at zero between deposits
-  // Move counts left in sort_cnt by a row-kernel push, valid for the next
+  // Move counts left in sort_cnt by a counting push, valid for the next
   // neighbour-move sort of the same store (cell array, cell_start, size).
   bool cnt_ready;
   bool cnt_clean;  // sort_cnt is all zero (a counting push needs that)

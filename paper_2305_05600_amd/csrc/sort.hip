@@ -726,7 +726,7 @@ void enqueue_neighbour(hvpic_ctx* c, const hvpic_particles* in, hvpic_particles*
   const int cblocks = (int)ceil_div(c->ncell, kWaves * kCellsPerWave);
   const int tiles = (int)ceil_div(c->ncell, kScanTile);
   uint32_t* blk = (uint32_t*)c->sort_blk;
-  // A row-kernel push of this same store already left the move counts.
+  // A counting push of this same store already left the move counts.
   const bool counted = c->cnt_ready && c->cnt_cell == in->cell && c->cnt_cs == cs_prev &&
                        c->cnt_n == in->n;
   if (!counted)
