@@ -553,28 +553,86 @@ __device__ __forceinline__ void deposit_particle(Home<NDIM, SHAPE>& H, Queue<NDI
   if (live && !use_win) deposit_global<NDIM, SHAPE>(i, j, k, mx, my, mz, wt, q, vx, vy, vz, g, acc);
 }
 
-// End of a group step: the home sums go to the window; a quad of lanes with
-// the same home cell (consecutive particles, so the usual case) first
-// combines them across its lanes (DPP) and its first lane alone adds them,
-// which keeps concurrent LDS atomics on one address few.  Every lane of the
-// wavefront calls it.
+// DPP move of v from `lane - D` within each 16-lane row (row_shr:D); lanes
+// with no source get `fill`.
+template <int D>
+__device__ __forceinline__ float shr_f(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
+                                                                0x110 + D, 0xF, 0xF, false));
+}
+template <int D>
+__device__ __forceinline__ int shr_i(int v, int fill) {
+  return __builtin_amdgcn_update_dpp(fill, v, 0x110 + D, 0xF, 0xF, false);
+}
+// Lane 15 of each row into the next row (rows 1 and 3), lane 31 into rows 2
+// and 3 (row_bcast:15 / row_bcast:31); other lanes get `fill`.
+__device__ __forceinline__ float bc15_f(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
+                                                                0x142, 0xA, 0xF, false));
+}
+__device__ __forceinline__ float bc31_f(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
+                                                                0x143, 0xC, 0xF, false));
+}
+__device__ __forceinline__ int bc15_i(int v, int fill) {
+  return __builtin_amdgcn_update_dpp(fill, v, 0x142, 0xA, 0xF, false);
+}
+__device__ __forceinline__ int bc31_i(int v, int fill) {
+  return __builtin_amdgcn_update_dpp(fill, v, 0x143, 0xC, 0xF, false);
+}
+
+// End of a group step: the home sums go to the window.  Consecutive lanes
+// hold consecutive particles, so lanes with the same home cell form runs.
+// An inclusive segmented scan over the wavefront (DPP, with segment-head
+// flags, so runs are maximal stretches of equal adjacent keys whatever their
+// order) leaves each run's total in its last lane, which alone adds it to the
+// window: about one active lane per cell in each FP64 LDS atomic.  Every lane
+// of the wavefront calls it.
 template <int NDIM, int SHAPE>
 __device__ __forceinline__ void home_flush(Home<NDIM, SHAPE>& H, double* win) {
   constexpr int T = Stencil<NDIM, SHAPE>::T;
+  const int lane = threadIdx.x & 63;
   const int h = H.kw;
-  const bool same = h == dpp_i<0xB1>(h) && h == dpp_i<0x4E>(h) && h == dpp_i<0x1B>(h);
-  if (same) {
+  const int prev = __shfl_up(h, 1), next = __shfl_down(h, 1);
+  const bool last = lane == 63 || next != h;
+  // f: a run starts at or after the first lane that v already covers
+  int f = (lane == 0 || prev != h) ? 1 : 0;
+  int n1, n2, n4, n8, n15, n31;  // 1: add the neighbour's partial sum
+  n1 = f ? 0 : 1;
+  f |= shr_i<1>(f, 0);
+  n2 = f ? 0 : 1;
+  f |= shr_i<2>(f, 0);
+  n4 = f ? 0 : 1;
+  f |= shr_i<4>(f, 0);
+  n8 = f ? 0 : 1;
+  f |= shr_i<8>(f, 0);
+  n15 = f ? 0 : 1;
+  f |= bc15_i(f, 0);
+  n31 = f ? 0 : 1;
+  // n_d: the lane's flag was clear before level d, so it adds the partial sum
+  // d lanes back (lane 15 / 31 for the cross-row levels).  A lane with no
+  // source at a level receives 0 for both value and flag: unchanged.
 #pragma unroll
-    for (int t = 0; t < T; ++t)
+  for (int t = 0; t < T; ++t)
 #pragma unroll
-      for (int ch = 0; ch < 4; ++ch) {
-        float v = H.acc[t][ch];
-        v += dpp_f<0xB1>(v);  // quad_perm [1,0,3,2]
-        v += dpp_f<0x4E>(v);  // quad_perm [2,3,0,1]
-        H.acc[t][ch] = v;
-      }
-  }
-  if (h >= 0 && (!same || (threadIdx.x & 3) == 0)) {
+    for (int ch = 0; ch < 4; ++ch) {
+      float v = H.acc[t][ch];
+      float u;
+      u = shr_f<1>(v);
+      v += n1 ? u : 0.0f;
+      u = shr_f<2>(v);
+      v += n2 ? u : 0.0f;
+      u = shr_f<4>(v);
+      v += n4 ? u : 0.0f;
+      u = shr_f<8>(v);
+      v += n8 ? u : 0.0f;
+      u = bc15_f(v);
+      v += n15 ? u : 0.0f;
+      u = bc31_f(v);
+      v += n31 ? u : 0.0f;
+      H.acc[t][ch] = v;
+    }
+  if (h >= 0 && last) {
     int s[T];
     stencil_slots<NDIM, SHAPE>(h >> 4, h & 15, s);
 #pragma unroll
