@@ -39,7 +39,7 @@ namespace {
 // (cells per band).  A 3D chunk spans more bands, so it is kept shorter.
 template <int NDIM>
 struct Chunk {
-  static constexpr int PPT = NDIM == 2 ? 8 : 4;
+  static constexpr int PPT = NDIM == 2 ? 12 : 4;
   static constexpr int N = kBlock * PPT;
   static constexpr int WMAX = NDIM == 2 ? 64 : 24;
 };
@@ -597,18 +597,18 @@ __device__ __forceinline__ void home_flush(Home<NDIM, SHAPE>& H, double* win) {
   const bool last = lane == 63 || next != h;
   // f: a run starts at or after the first lane that v already covers
   int f = (lane == 0 || prev != h) ? 1 : 0;
-  int n1, n2, n4, n8, n15, n31;  // 1: add the neighbour's partial sum
-  n1 = f ? 0 : 1;
+  bool n1, n2, n4, n8, n15, n31;  // add the neighbour's partial sum
+  n1 = f == 0;
   f |= shr_i<1>(f, 0);
-  n2 = f ? 0 : 1;
+  n2 = f == 0;
   f |= shr_i<2>(f, 0);
-  n4 = f ? 0 : 1;
+  n4 = f == 0;
   f |= shr_i<4>(f, 0);
-  n8 = f ? 0 : 1;
+  n8 = f == 0;
   f |= shr_i<8>(f, 0);
-  n15 = f ? 0 : 1;
+  n15 = f == 0;
   f |= bc15_i(f, 0);
-  n31 = f ? 0 : 1;
+  n31 = f == 0;
   // n_d: the lane's flag was clear before level d, so it adds the partial sum
   // d lanes back (lane 15 / 31 for the cross-row levels).  A lane with no
   // source at a level receives 0 for both value and flag: unchanged.
@@ -704,45 +704,6 @@ __device__ __forceinline__ void store4(T* __restrict__ p, int64_t i, int64_t end
 #pragma unroll
     for (int q = 0; q < 4; ++q)
       if (i + q < end) p[i + q] = v[q];
-  }
-}
-
-// Group of four at p + b4 of which [lo, hi) is wanted: one 16-byte load when
-// `vec` (the whole group lies inside the array and it is 16-byte aligned),
-// else element by element.  Values outside [lo, hi) are unspecified.
-template <typename T>
-__device__ __forceinline__ void load4r(const T* __restrict__ p, int64_t b4, int64_t lo, int64_t hi,
-                                       bool vec, T v[4]) {
-  if (vec) {
-    using V = typename std::conditional<std::is_same<T, int>::value, int4, float4>::type;
-    const V u = *reinterpret_cast<const V*>(p + b4);
-    v[0] = u.x;
-    v[1] = u.y;
-    v[2] = u.z;
-    v[3] = u.w;
-  } else {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) v[q] = (b4 + q >= lo && b4 + q < hi) ? p[b4 + q] : T(0);
-  }
-}
-
-// Writes the elements [lo, hi) of the group at p + b4; one 16-byte store
-// when `full` (the group is exactly [lo, hi) and aligned).
-template <typename T>
-__device__ __forceinline__ void store4r(T* __restrict__ p, int64_t b4, int64_t lo, int64_t hi,
-                                        bool full, const T v[4]) {
-  if (full) {
-    using V = typename std::conditional<std::is_same<T, int>::value, int4, float4>::type;
-    V u;
-    u.x = v[0];
-    u.y = v[1];
-    u.z = v[2];
-    u.w = v[3];
-    *reinterpret_cast<V*>(p + b4) = u;
-  } else {
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-      if (b4 + q >= lo && b4 + q < hi) p[b4 + q] = v[q];
   }
 }
 
