@@ -7,7 +7,9 @@ FP32 particles and fields (seeded synthetic inputs).  One step = gather + push
 Faraday subcycle + extrapolation), FP64 diagnostics.
 
 Prints one JSON line.  `value` is ion pushes per second over whole steps with
-the inputs resident in HBM.  `roofline` refers to the dominant kernel (the
+the inputs resident in HBM; the field advance of a step runs on a second
+stream beside the sort (they touch disjoint data; --no-overlap serialises
+them).  `roofline` refers to the dominant kernel (the
 fused gather+push+deposit), timed by HIP events that the library records on
 its stream directly around each of its launches;
 `cpu_baseline` times the FP64 oracle on one step of the same workload.
@@ -78,6 +80,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--unfused", action="store_true", help="separate deposit pass")
+    ap.add_argument("--no-overlap", action="store_true",
+                    help="run the field advance on the particle stream (no overlap with the sort)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run three plain 512 MiB device copies (a known-size reference "
                          "for hardware traffic counters)")
@@ -104,51 +108,27 @@ def main() -> int:
 
     cfg, parts, B = W.harris_double()
     n = int(parts["cell"].size)
-    g = S.GpuSim(cfg, parts, B, fused=not args.unfused)
+    g = S.GpuSim(cfg, parts, B, fused=not args.unfused, overlap=not args.no_overlap)
     for _ in range(args.warmup):
         g.step()
-    torch.cuda.synchronize()
-
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    g.synchronize()
     c = g.ctx.ctx
     # HIP events recorded by the library on its own stream right around each
-    # launch of the dominant kernel
+    # launch of the dominant kernel (and of the sort's scatter)
     H.hvpic_timing_enable(c, args.steps)
-    pd = g.push_diag
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for s in range(args.steps):
-        e = ev[s]
-        e[0].record()
-        if g.fused:
-            H.hvpic_gather_push(c, g.p, g.cs, g.E, g.B, g.n_half, g.J_half, pd)
-        else:
-            H.hvpic_gather_push(c, g.p, g.cs, g.E, g.B, None, None, pd)
-        e[1].record()
-        H.hvpic_sort(c, g.p, g.q, g.cs, g.cs_alt, full=False)
-        g.p, g.q = g.q, g.p
-        g.cs, g.cs_alt = g.cs_alt, g.cs
-        if not g.fused:
-            H.hvpic_deposit(c, g.p, g.cs, 0.5 * cfg.dt, g.n_half, g.J_half)
-        e[2].record()
-        H.hvpic_field_advance(c, g.B, g.n_half, g.J_half, g.n_prev, g.J_prev, g.E, 0,
-                              g.field_diag)
-        g.n_prev, g.n_half = g.n_half, g.n_prev
-        g.J_prev, g.J_half = g.J_half, g.J_prev
-        e[3].record()
+    for _ in range(args.steps):
+        g.step()
+    g.synchronize()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    push_ms = np.mean([e[0].elapsed_time(e[1]) for e in ev])
-    sort_ms = np.mean([e[1].elapsed_time(e[2]) for e in ev])
-    field_ms = np.mean([e[2].elapsed_time(e[3]) for e in ev])
-    step_ms = np.mean([e[0].elapsed_time(e[3]) for e in ev])
-    kid = H.KERNEL_GATHER_PUSH
-    k_ms, k_launches = H.hvpic_timing_read(c, kid)
+    k_ms, k_launches = H.hvpic_timing_read(c, H.KERNEL_GATHER_PUSH)
     s_ms, s_launches = H.hvpic_timing_read(c, H.KERNEL_SORT_SCATTER)
     H.hvpic_timing_enable(c, 0)
     assert k_launches == args.steps, (k_launches, args.steps)
     kernel_ms = k_ms / k_launches
-    flags, counts = H.hvpic_sync_status(c)
+    flags, counts = g.status()
     ms_per_step = wall * 1e3 / args.steps
 
     per_launch = BYTES_PER_PARTICLE_2D * n + BYTES_PER_CELL_2D * cfg.ncell
@@ -175,10 +155,10 @@ def main() -> int:
                      "kernel": "k_gather_push (fused deposit)" if g.fused else "k_gather_push",
                      "kernel_ms": kernel_ms,
                      "algorithmic_bytes_per_launch": per_launch},
-        "phases_ms": {"gather_push_deposit": push_ms, "sort": sort_ms,
-                      "field_advance": field_ms, "step_events": step_ms,
-                      "sort_scatter_kernel": s_ms / max(s_launches, 1)},
-        "gather_push_deposit_pushes_per_s": n / (push_ms * 1e-3),
+        "kernels_ms": {"gather_push_deposit": kernel_ms,
+                       "sort_scatter": s_ms / max(s_launches, 1)},
+        "overlap_sort_with_field_advance": g.overlap,
+        "gather_push_deposit_pushes_per_s": n / (kernel_ms * 1e-3),
         "status_flags": flags,
     }
     if not args.no_cpu_baseline:

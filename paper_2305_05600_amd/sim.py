@@ -12,6 +12,12 @@ v^{n-1/2}; B^n and E^n; the moments n^{n-1/2}, J^{n-1/2}.  One step:
   5. hvpic_field_advance B^n -> B^{n+1} (subcycled), E^{n+1} from the
                          extrapolated moments
 
+Steps 2 and 4-5 touch disjoint data (the particle store and cell_start versus
+the moments, B and E), so with `overlap` the field work runs on a second
+stream and context, ordered by events: it waits for the moments of step 1,
+and the next push waits for its E and B.  The sort and the latency-bound
+field kernels then share the GPU.
+
 Initialisation (the paper leaves the first half step open): v^{-1/2} = v^0,
 and n^{-1/2}, J^{-1/2} are the moments deposited at x^0, so E^0 = Ohm(B^0,
 n^0, J^0).  This module only orders the calls and swaps buffers.
@@ -26,13 +32,18 @@ from . import hvpic as H
 
 class GpuSim:
     def __init__(self, cfg, parts: dict, B: np.ndarray, fused: bool = True, device="cuda",
-                 diagnostics: bool = True):
+                 diagnostics: bool = True, overlap: bool = True):
         self.cfg = cfg
         self.fused = fused
         self.device = device
+        self.overlap = overlap
         n = int(parts["cell"].size)
         self.np = n
-        self.ctx = H.Context(cfg, max(n, 1), device)
+        # particle work on s_p; field work on s_f (the same stream unless overlapping)
+        self.s_p = torch.cuda.Stream(device)
+        self.s_f = torch.cuda.Stream(device) if overlap else self.s_p
+        self.ctx = H.Context(cfg, max(n, 1), device, stream=self.s_p)
+        self.ctx_f = H.Context(cfg, 1, device, stream=self.s_f) if overlap else self.ctx
         nc = cfg.ncell
         self.p = H.Particles.from_numpy(parts, cfg.ndim, max(n, 1), device)
         self.q = H.Particles(cfg.ndim, max(n, 1), device)
@@ -51,31 +62,63 @@ class GpuSim:
         self.diagnostics = diagnostics
         self.push_diag = torch.zeros(4, dtype=torch.float64, device=device)
         self.field_diag = torch.zeros(2, dtype=torch.float64, device=device)
+        self.ev_moments = torch.cuda.Event()    # moments of the step are written
+        self.ev_fields = torch.cuda.Event()     # E, B of the step are written
+        self.ev_particles = torch.cuda.Event()  # the step's particle work is done
+        # the tensors above (and the contexts' workspaces) were filled on the
+        # current stream
+        torch.cuda.current_stream(device).synchronize()
         c = self.ctx.ctx
         # first sort of an arbitrary order
         H.hvpic_sort(c, self.p, self.q, None, self.cs, full=True)
         self.p, self.q = self.q, self.p
         H.hvpic_deposit(c, self.p, self.cs, 0.0, self.n_prev, self.J_prev)
-        if cfg.nsmooth:
-            H.hvpic_smooth(c, self.n_prev, cfg.nsmooth)
-            H.hvpic_smooth(c, self.J_prev, cfg.nsmooth)
-        H.hvpic_field_advance(c, self.B, self.n_prev, self.J_prev, None, None, self.E, mode=1,
-                              diag_out=self.field_diag if diagnostics else None)
+        self._fields_after_moments(mode=1, n_half=self.n_prev, J_half=self.J_prev)
         self.nstep = 0
+        cur = torch.cuda.current_stream(device)
+        cur.wait_stream(self.s_p)
+        cur.wait_stream(self.s_f)
+
+    def _fields_after_moments(self, mode, n_half, J_half):
+        """Smoothing of the moments and the field advance, on the field stream
+        once the moments are there."""
+        cfg = self.cfg
+        cf = self.ctx_f.ctx
+        if self.s_f is not self.s_p:
+            self.ev_moments.record(self.s_p)
+            self.s_f.wait_event(self.ev_moments)
+        if cfg.nsmooth:
+            H.hvpic_smooth(cf, n_half, cfg.nsmooth)
+            H.hvpic_smooth(cf, J_half, cfg.nsmooth)
+        diag = self.field_diag if self.diagnostics else None
+        if mode == 1:
+            H.hvpic_field_advance(cf, self.B, n_half, J_half, None, None, self.E, mode=1,
+                                  diag_out=diag)
+        else:
+            H.hvpic_field_advance(cf, self.B, n_half, J_half, self.n_prev, self.J_prev, self.E,
+                                  mode=0, diag_out=diag)
+        self.ev_fields.record(self.s_f)
 
     def step(self):
         cfg = self.cfg
         c = self.ctx.ctx
+        cur = torch.cuda.current_stream(self.device)
+        # E^n and B^n are written, and the moment buffers free, once the last
+        # field advance has ended.  (Writes into the simulation's tensors by
+        # the caller must be finished first: see synchronize().)
+        self.s_p.wait_event(self.ev_fields)
         E, B = self.E, self.B
         if cfg.nsmooth:
-            self.E_s.copy_(E)
-            self.B_s.copy_(B)
+            with torch.cuda.stream(self.s_p):
+                self.E_s.copy_(E)
+                self.B_s.copy_(B)
             H.hvpic_smooth(c, self.E_s, cfg.nsmooth)
             H.hvpic_smooth(c, self.B_s, cfg.nsmooth)
             E, B = self.E_s, self.B_s
         pd = self.push_diag if self.diagnostics else None
         if self.fused:
             H.hvpic_gather_push(c, self.p, self.cs, E, B, self.n_half, self.J_half, pd)
+            self._fields_after_moments(mode=0, n_half=self.n_half, J_half=self.J_half)
         else:
             H.hvpic_gather_push(c, self.p, self.cs, E, B, None, None, pd)
         H.hvpic_sort(c, self.p, self.q, self.cs, self.cs_alt, full=False)
@@ -83,18 +126,33 @@ class GpuSim:
         self.cs, self.cs_alt = self.cs_alt, self.cs
         if not self.fused:
             H.hvpic_deposit(c, self.p, self.cs, 0.5 * cfg.dt, self.n_half, self.J_half)
-        if cfg.nsmooth:
-            H.hvpic_smooth(c, self.n_half, cfg.nsmooth)
-            H.hvpic_smooth(c, self.J_half, cfg.nsmooth)
-        H.hvpic_field_advance(c, self.B, self.n_half, self.J_half, self.n_prev, self.J_prev,
-                              self.E, mode=0,
-                              diag_out=self.field_diag if self.diagnostics else None)
+            self._fields_after_moments(mode=0, n_half=self.n_half, J_half=self.J_half)
         self.n_prev, self.n_half = self.n_half, self.n_prev
         self.J_prev, self.J_half = self.J_half, self.J_prev
         self.nstep += 1
+        # later work on the caller's stream (reads of E, B, the moments, the
+        # store) sees this step; the next step's launches do not wait for it
+        self.ev_particles.record(self.s_p)
+        cur.wait_event(self.ev_particles)
+        if self.s_f is not self.s_p:
+            cur.wait_event(self.ev_fields)
+
+    def synchronize(self):
+        """Waits for all queued work (host and the caller's stream).  Call it
+        after writing into the simulation's tensors from another stream."""
+        torch.cuda.current_stream(self.device).synchronize()
+        self.s_p.synchronize()
+        self.s_f.synchronize()
 
     def status(self):
-        return H.hvpic_sync_status(self.ctx.ctx)
+        """Sticky status bits and counts of both contexts (waits for both streams)."""
+        flags, counts = H.hvpic_sync_status(self.ctx.ctx)
+        if self.ctx_f is not self.ctx:
+            f2, c2 = H.hvpic_sync_status(self.ctx_f.ctx)
+            flags |= f2
+            counts = tuple(a + b for a, b in zip(counts, c2))
+        return flags, counts
 
     def particles(self) -> dict:
+        self.synchronize()
         return self.p.to_numpy()
