@@ -75,7 +75,7 @@ Layout workspace_layout(const hvpic_params* p) {
   const int64_t cap = std::max<int64_t>(p->np_capacity, 1);
   const int ndir = p->ndim == 2 ? 9 : 27;
   const int64_t ntiles = ceil_div(cap, kRadixTile);
-  const int64_t nblk = std::max(ceil_div(nc, kScanTile), ceil_div(kRadixBins * ntiles, kScanTile)) + 1;
+  const int64_t nblk = std::max(ceil_div(nc, kNbTileSmall), ceil_div(kRadixBins * ntiles, kScanTile)) + 1;
   size_t off = 0;
   L.status = off;    off += align256(sizeof(Status));
   // per-block partials: particle-chunk blocks (>= 1024 particles each) or

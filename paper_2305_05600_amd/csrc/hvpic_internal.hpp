@@ -194,6 +194,7 @@ constexpr int kRadixBins = 1 << kRadixBits;
 constexpr int kRadixItems = 8;  // keys per thread per radix tile
 constexpr int kRadixTile = kBlock * kRadixItems;
 constexpr int kScanTile = 2048;  // elements per block of the prefix scans
+constexpr int kNbTileSmall = 512;  // cells per block of the neighbour sort's scans (small grids)
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 

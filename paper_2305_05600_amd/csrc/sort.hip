@@ -190,15 +190,17 @@ __global__ __launch_bounds__(kBlock) void k_nb_count(const int32_t* __restrict__
   for (int q = lane; q < na * ND; q += 64) cnt[(int64_t)a0 * ND + q] = s_cnt[wid][q];
 }
 
-// Block-level exclusive scan of kScanTile values held in LDS `s`; returns the
-// tile total.  Thread t owns elements [t*8, t*8+8).
+// Block-level exclusive scan of TILE values held in LDS `s`; returns the
+// tile total.  Thread t owns elements [t*PER, t*PER+PER).
+template <int TILE = kScanTile>
 __device__ uint32_t tile_exclusive_scan(uint32_t* s) {
+  constexpr int PER = TILE / kBlock;
   __shared__ uint32_t wsum[kWaves];
   const int t = threadIdx.x;
-  uint32_t v[8], acc = 0;
+  uint32_t v[PER], acc = 0;
 #pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    v[q] = s[t * 8 + q];
+  for (int q = 0; q < PER; ++q) {
+    v[q] = s[t * PER + q];
     acc += v[q];
   }
   // inclusive scan of acc over the block
@@ -219,16 +221,17 @@ __device__ uint32_t tile_exclusive_scan(uint32_t* s) {
   }
   uint32_t run = woff + x - acc;  // exclusive prefix of this thread
 #pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    s[t * 8 + q] = run;
+  for (int q = 0; q < PER; ++q) {
+    s[t * PER + q] = run;
     run += v[q];
   }
   __syncthreads();
   return total;
 }
 
-// Per-new-cell totals, written to cs[c], and their per-tile sums.
-template <int NDIM>
+// Per-new-cell totals, written to cs[c], and their per-tile sums (tiles of
+// TILE cells).
+template <int NDIM, int TILE>
 __global__ __launch_bounds__(kBlock) void k_nb_newcount(const uint32_t* __restrict__ cnt, SortGeo g,
                                                         int32_t* __restrict__ cs,
                                                         uint32_t* __restrict__ blk, Status* st) {
@@ -239,9 +242,9 @@ __global__ __launch_bounds__(kBlock) void k_nb_newcount(const uint32_t* __restri
     __hip_atomic_store(&st->far_decision, f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __hip_atomic_store(&st->far_flag, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
-  const int64_t t0 = (int64_t)blockIdx.x * kScanTile;
+  const int64_t t0 = (int64_t)blockIdx.x * TILE;
   uint32_t local = 0;
-  for (int q = 0; q < kScanTile / kBlock; ++q) {
+  for (int q = 0; q < TILE / kBlock; ++q) {
     const int64_t c = t0 + q * kBlock + threadIdx.x;
     if (c >= g.ncell) break;
     int i, j, k;
@@ -313,21 +316,21 @@ __device__ uint32_t block_sum(const uint32_t* __restrict__ v, int m) {
 // (source cell, direction) of each new cell, written over cnt.  blk holds
 // the tile totals; each block adds up those before it (a few hundred values
 // at most), which spares a separate scan launch.
-template <int NDIM>
+template <int NDIM, int TILE>
 __global__ __launch_bounds__(kBlock) void k_nb_bases(uint32_t* __restrict__ cnt, SortGeo g,
                                                      int32_t* __restrict__ cs,
                                                      const uint32_t* __restrict__ blk) {
   constexpr int ND = Dirs<NDIM>::N;
-  __shared__ uint32_t s[kScanTile];
-  const int64_t t0 = (int64_t)blockIdx.x * kScanTile;
-  for (int q = 0; q < kScanTile / kBlock; ++q) {
+  __shared__ uint32_t s[TILE];
+  const int64_t t0 = (int64_t)blockIdx.x * TILE;
+  for (int q = 0; q < TILE / kBlock; ++q) {
     const int64_t c = t0 + q * kBlock + threadIdx.x;
     s[q * kBlock + threadIdx.x] = c < g.ncell ? (uint32_t)cs[c] : 0u;
   }
   __syncthreads();
-  const uint32_t tile_total = tile_exclusive_scan(s);
+  const uint32_t tile_total = tile_exclusive_scan<TILE>(s);
   const uint32_t off = block_sum(blk, blockIdx.x);
-  for (int q = 0; q < kScanTile / kBlock; ++q) {
+  for (int q = 0; q < TILE / kBlock; ++q) {
     const int64_t c = t0 + q * kBlock + threadIdx.x;
     if (c >= g.ncell) break;
     const uint32_t start = off + s[q * kBlock + threadIdx.x];
@@ -724,7 +727,6 @@ void enqueue_neighbour(hvpic_ctx* c, const hvpic_particles* in, hvpic_particles*
   hipStream_t s = c->stream;
   const SortGeo g = sort_geo(c);
   const int cblocks = (int)ceil_div(c->ncell, kWaves * kCellsPerWave);
-  const int tiles = (int)ceil_div(c->ncell, kScanTile);
   uint32_t* blk = (uint32_t*)c->sort_blk;
   // A counting push of this same store already left the move counts.
   const bool counted = c->cnt_ready && c->cnt_cell == in->cell && c->cnt_cs == cs_prev &&
@@ -732,10 +734,21 @@ void enqueue_neighbour(hvpic_ctx* c, const hvpic_particles* in, hvpic_particles*
   if (!counted)
     hipLaunchKernelGGL((k_nb_count<NDIM>), dim3(cblocks), dim3(kBlock), 0, s, in->cell, cs_prev,
                        in->n, g, c->sort_cnt, c->status);
-  hipLaunchKernelGGL((k_nb_newcount<NDIM>), dim3(tiles), dim3(kBlock), 0, s,
-                     (const uint32_t*)c->sort_cnt, g, cs, blk, c->status);
-  hipLaunchKernelGGL((k_nb_bases<NDIM>), dim3(tiles), dim3(kBlock), 0, s, c->sort_cnt, g, cs,
-                     (const uint32_t*)blk);
+  // small tiles spread the two short passes over more CUs while each block's
+  // sum over the preceding tile totals stays short
+  if (c->ncell <= kNbTileSmall * 512) {
+    const int tiles = (int)ceil_div(c->ncell, kNbTileSmall);
+    hipLaunchKernelGGL((k_nb_newcount<NDIM, kNbTileSmall>), dim3(tiles), dim3(kBlock), 0, s,
+                       (const uint32_t*)c->sort_cnt, g, cs, blk, c->status);
+    hipLaunchKernelGGL((k_nb_bases<NDIM, kNbTileSmall>), dim3(tiles), dim3(kBlock), 0, s,
+                       c->sort_cnt, g, cs, (const uint32_t*)blk);
+  } else {
+    const int tiles = (int)ceil_div(c->ncell, kScanTile);
+    hipLaunchKernelGGL((k_nb_newcount<NDIM, kScanTile>), dim3(tiles), dim3(kBlock), 0, s,
+                       (const uint32_t*)c->sort_cnt, g, cs, blk, c->status);
+    hipLaunchKernelGGL((k_nb_bases<NDIM, kScanTile>), dim3(tiles), dim3(kBlock), 0, s,
+                       c->sort_cnt, g, cs, (const uint32_t*)blk);
+  }
   timing_begin(c, HVPIC_KERNEL_SORT_SCATTER);
   const int sblocks = (int)ceil_div(c->ncell, kWaves * kScatterCells);
   hipLaunchKernelGGL((k_nb_scatter<NDIM>), dim3(sblocks), dim3(kBlock), 0, s, cs_prev, in->n, g,

@@ -355,3 +355,24 @@ def test_push_inconsistent_cell_start(H, name, cfg):
     rn, rJ = O.deposit(cfg, ref, 0.5 * cfg.dt)
     assert rel_l2(nd.cpu().numpy(), rn) < 1e-5 and rel_l2(Jd.cpu().numpy(), rJ) < 1e-5
     _check_sorted(cfg, pushed, q.to_numpy(), cs.cpu().numpy())
+
+
+def test_neighbour_sort_large_grid(H):
+    """A grid above 512*512 cells takes the sort's large-tile scan path."""
+    cfg = cfg2(nx=1031, ny=517)
+    announce("nb_sort_large", cfg.ncell)
+    _, parts, B = W.random_box(97, cfg, 0.7, vmax_cells=0.9)
+    parts, cs0 = _sorted(cfg, parts)
+    E = W.random_field(98, cfg, 0.01)
+    n = parts["cell"].size
+    ctx = H.Context(cfg, n)
+    p = H.Particles.from_numpy(parts, cfg.ndim)
+    q = H.Particles(cfg.ndim, n)
+    cs_prev = dev(cs0, np.int32)
+    cs = torch.zeros(cfg.ncell + 1, dtype=torch.int32, device="cuda")
+    H.hvpic_gather_push(ctx.ctx, p, cs_prev, dev(E), dev(B))
+    pushed = p.to_numpy()
+    H.hvpic_sort(ctx.ctx, p, q, cs_prev, cs, full=False)
+    flags, _ = H.hvpic_sync_status(ctx.ctx)
+    assert flags == 0
+    _check_sorted(cfg, pushed, q.to_numpy(), cs.cpu().numpy())
