@@ -554,82 +554,55 @@ __device__ __forceinline__ void deposit_particle(Home<NDIM, SHAPE>& H, Queue<NDI
 }
 
 // DPP move of v from `lane - D` within each 16-lane row (row_shr:D); lanes
-// with no source get `fill`.
+// with no source get 0 (float) or `fill` (int).
 template <int D>
 __device__ __forceinline__ float shr_f(float v) {
   return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
-                                                                0x110 + D, 0xF, 0xF, false));
+                                                                0x110 + D, 0xF, 0xF, true));
 }
 template <int D>
 __device__ __forceinline__ int shr_i(int v, int fill) {
   return __builtin_amdgcn_update_dpp(fill, v, 0x110 + D, 0xF, 0xF, false);
 }
-// Lane 15 of each row into the next row (rows 1 and 3), lane 31 into rows 2
-// and 3 (row_bcast:15 / row_bcast:31); other lanes get `fill`.
-__device__ __forceinline__ float bc15_f(float v) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
-                                                                0x142, 0xA, 0xF, false));
-}
-__device__ __forceinline__ float bc31_f(float v) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
-                                                                0x143, 0xC, 0xF, false));
-}
-__device__ __forceinline__ int bc15_i(int v, int fill) {
-  return __builtin_amdgcn_update_dpp(fill, v, 0x142, 0xA, 0xF, false);
-}
-__device__ __forceinline__ int bc31_i(int v, int fill) {
-  return __builtin_amdgcn_update_dpp(fill, v, 0x143, 0xC, 0xF, false);
+// The same from `lane + 1` within the row (row_shl:1).
+__device__ __forceinline__ int shl1_i(int v, int fill) {
+  return __builtin_amdgcn_update_dpp(fill, v, 0x101, 0xF, 0xF, false);
 }
 
 // End of a group step: the home sums go to the window.  Consecutive lanes
 // hold consecutive particles, so lanes with the same home cell form runs.
-// An inclusive segmented scan over the wavefront (DPP, with segment-head
+// An inclusive segmented scan within each 16-lane row (DPP, with segment-head
 // flags, so runs are maximal stretches of equal adjacent keys whatever their
-// order) leaves each run's total in its last lane, which alone adds it to the
-// window: about one active lane per cell in each FP64 LDS atomic.  Every lane
-// of the wavefront calls it.
+// order, cut at row ends) leaves each run's total in its last lane, which
+// alone adds it to the window: a few active lanes per cell in each FP64 LDS
+// atomic.  A level adds the neighbour's partial sum times 0 or 1, a DPP move
+// and one FMA.  Every lane of the wavefront calls it.
 template <int NDIM, int SHAPE>
 __device__ __forceinline__ void home_flush(Home<NDIM, SHAPE>& H, double* win) {
   constexpr int T = Stencil<NDIM, SHAPE>::T;
-  const int lane = threadIdx.x & 63;
+  const int r = threadIdx.x & 15;
   const int h = H.kw;
-  const int prev = __shfl_up(h, 1), next = __shfl_down(h, 1);
-  const bool last = lane == 63 || next != h;
+  const int prev = shr_i<1>(h, -2), next = shl1_i(h, -2);
+  const bool last = r == 15 || next != h;
   // f: a run starts at or after the first lane that v already covers
-  int f = (lane == 0 || prev != h) ? 1 : 0;
-  bool n1, n2, n4, n8, n15, n31;  // add the neighbour's partial sum
-  n1 = f == 0;
-  f |= shr_i<1>(f, 0);
-  n2 = f == 0;
-  f |= shr_i<2>(f, 0);
-  n4 = f == 0;
-  f |= shr_i<4>(f, 0);
-  n8 = f == 0;
-  f |= shr_i<8>(f, 0);
-  n15 = f == 0;
-  f |= bc15_i(f, 0);
-  n31 = f == 0;
-  // n_d: the lane's flag was clear before level d, so it adds the partial sum
-  // d lanes back (lane 15 / 31 for the cross-row levels).  A lane with no
-  // source at a level receives 0 for both value and flag: unchanged.
+  int f = (r == 0 || prev != h) ? 1 : 0;
+  float m1, m2, m4, m8;  // 1: add the partial sum d lanes back
+  m1 = f ? 0.0f : 1.0f;
+  f |= shr_i<1>(f, 1);
+  m2 = f ? 0.0f : 1.0f;
+  f |= shr_i<2>(f, 1);
+  m4 = f ? 0.0f : 1.0f;
+  f |= shr_i<4>(f, 1);
+  m8 = f ? 0.0f : 1.0f;
 #pragma unroll
   for (int t = 0; t < T; ++t)
 #pragma unroll
     for (int ch = 0; ch < 4; ++ch) {
       float v = H.acc[t][ch];
-      float u;
-      u = shr_f<1>(v);
-      v += n1 ? u : 0.0f;
-      u = shr_f<2>(v);
-      v += n2 ? u : 0.0f;
-      u = shr_f<4>(v);
-      v += n4 ? u : 0.0f;
-      u = shr_f<8>(v);
-      v += n8 ? u : 0.0f;
-      u = bc15_f(v);
-      v += n15 ? u : 0.0f;
-      u = bc31_f(v);
-      v += n31 ? u : 0.0f;
+      v = fmaf(shr_f<1>(v), m1, v);
+      v = fmaf(shr_f<2>(v), m2, v);
+      v = fmaf(shr_f<4>(v), m4, v);
+      v = fmaf(shr_f<8>(v), m8, v);
       H.acc[t][ch] = v;
     }
   if (h >= 0 && last) {
@@ -671,22 +644,22 @@ __device__ void dwin_flush(const double* win, int W, int c0, const Geo& g,
 
 // ------------------------------------------------------ particle I/O -----
 
-// Four consecutive values at p + i: one 16-byte access when `full` (i + 4 <=
-// end and 16-byte aligned arrays), else element by element up to end.
+// Four consecutive values at p + i as one 16-byte access (16-byte aligned).
 template <typename T>
-__device__ __forceinline__ void load4(const T* __restrict__ p, int64_t i, int64_t end, bool full,
-                                      T v[4]) {
-  if (full) {
-    using V = typename std::conditional<std::is_same<T, int>::value, int4, float4>::type;
-    const V u = *reinterpret_cast<const V*>(p + i);
-    v[0] = u.x;
-    v[1] = u.y;
-    v[2] = u.z;
-    v[3] = u.w;
-  } else {
+__device__ __forceinline__ void load4v(const T* __restrict__ p, int64_t i, T v[4]) {
+  using V = typename std::conditional<std::is_same<T, int>::value, int4, float4>::type;
+  const V u = *reinterpret_cast<const V*>(p + i);
+  v[0] = u.x;
+  v[1] = u.y;
+  v[2] = u.z;
+  v[3] = u.w;
+}
+
+// The same element by element up to end (zero beyond).
+template <typename T>
+__device__ __forceinline__ void load4e(const T* __restrict__ p, int64_t i, int64_t end, T v[4]) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) v[q] = i + q < end ? p[i + q] : T(0);
-  }
+  for (int q = 0; q < 4; ++q) v[q] = i + q < end ? p[i + q] : T(0);
 }
 
 template <typename T>
@@ -704,6 +677,44 @@ __device__ __forceinline__ void store4(T* __restrict__ p, int64_t i, int64_t end
 #pragma unroll
     for (int q = 0; q < 4; ++q)
       if (i + q < end) p[i + q] = v[q];
+  }
+}
+
+// One group step's particles of a lane: four consecutive ones.
+template <int NDIM>
+struct Group {
+  int ca[4];
+  float px[4], py[4], pz[4], ux[4], uy[4], uz[4], pw[4];
+};
+
+// Loads a lane's group at b4 from the particle arrays of A: 16-byte accesses
+// when `full`, which must be the same on all lanes of the wavefront (one
+// branch for the whole group, so that the compiler keeps the vector loads
+// together and in flight at once), else element-wise ones.
+template <int NDIM, typename Args>
+__device__ __forceinline__ void load_group(const Args& A, int64_t b4, int64_t end, bool full,
+                                           bool wq, Group<NDIM>& G) {
+  if (full) {
+    load4v(A.cell, b4, G.ca);
+    load4v(A.ox, b4, G.px);
+    load4v(A.oy, b4, G.py);
+    if (NDIM == 3) load4v(A.oz, b4, G.pz);
+    load4v(A.ux, b4, G.ux);
+    load4v(A.uy, b4, G.uy);
+    load4v(A.uz, b4, G.uz);
+    if (wq) load4v(A.w, b4, G.pw);
+  } else {
+    load4e(A.cell, b4, end, G.ca);
+    load4e(A.ox, b4, end, G.px);
+    load4e(A.oy, b4, end, G.py);
+    if (NDIM == 3) load4e(A.oz, b4, end, G.pz);
+    load4e(A.ux, b4, end, G.ux);
+    load4e(A.uy, b4, end, G.uy);
+    load4e(A.uz, b4, end, G.uz);
+    if (wq) load4e(A.w, b4, end, G.pw);
+    // vmcnt(0): these loads are complete here, so that code after the branch
+    // need not wait for them (nor for older loads in flight)
+    __builtin_amdgcn_s_waitcnt(0x0F70);
   }
 }
 
@@ -775,7 +786,18 @@ __device__ __forceinline__ int move_direction(const Args& A, int64_t idx, int a,
                                               bool inwin, const int32_t* s_cs, int i, int j,
                                               int k, int ni, int nj, int nk, int si, int sj,
                                               int sk) {
-  const int64_t lo = inwin ? s_cs[rel] : A.cs[a], hi = inwin ? s_cs[rel + 1] : A.cs[a + 1];
+  // the window's copy, or the global table for a particle outside it (read
+  // as relaxed atomics, which the compiler cannot merge with the LDS reads
+  // into one flat read through a select of the two addresses)
+  const int rw = inwin ? rel : 0;
+  int64_t lo = s_cs[rw], hi = s_cs[rw + 1];
+  if (!inwin) {
+    lo = __hip_atomic_load(A.cs + a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    hi = __hip_atomic_load(A.cs + a + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // vmcnt(0) here, so that the common path after the branch need not wait
+    // for these (and with them for every older load in flight)
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+  }
   if (idx < lo || idx >= hi) {
     flag_far(A.st, HVPIC_FLAG_BAD_INPUT, &A.st->bad_input);
     return -1;
@@ -871,6 +893,18 @@ void k_gather_push(PushArgs A) {
     s_c[1] = A.cell[end - 1];
   }
   __syncthreads();
+  const bool want_diag = A.diag_part != nullptr;
+  const bool wq = DEP || want_diag;  // the weights are needed
+  // Wavefront wv owns particles [base + wv*64*PPT, +64*PPT); in each group
+  // step lane l takes four consecutive ones, so a step is one coalesced
+  // 1 KiB access per array.  The first step's particles are loaded during the
+  // set-up below.
+  const int64_t wb = base + (int64_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6) * 64 * PPT;
+  const int64_t lb = wb + 4 * (threadIdx.x & 63);
+  // a step of the wavefront is all in range, or it takes element-wise accesses
+  auto step_full = [&](int h) { return A.vec && wb + h * 64 + 256 <= end; };
+  Group<NDIM> cur;
+  load_group<NDIM>(A, lb, end, step_full(0), wq, cur);
   const int c0 = s_c[0], span = s_c[1] - s_c[0];
   int W = 0;
   const bool wok = window_ok<NDIM>(c0, s_c[1], g, W);
@@ -883,7 +917,6 @@ void k_gather_push(PushArgs A) {
   if (cnt_on) check_cell_start(A.cs, g.ncell, A.n, A.st);
   __syncthreads();
 
-  const bool want_diag = A.diag_part != nullptr;
   float dK = 0.f, dP0 = 0.f, dP1 = 0.f, dP2 = 0.f;
   Home<NDIM, SHAPE> H;
   home_clear(H);
@@ -892,30 +925,20 @@ void k_gather_push(PushArgs A) {
   Q.count = 0;
   int chome = -1;      // window column of the lane's home cell for move counts
   uint32_t nstay = 0;  // home-cell particles that stay in their cell
-  // Wavefront wv owns particles [base + wv*64*PPT, +64*PPT); in each group
-  // step lane l takes four consecutive ones, so a step is one coalesced
-  // 1 KiB access per array.
-  const int64_t lb = base + (int64_t)(threadIdx.x >> 6) * 64 * PPT + 4 * (threadIdx.x & 63);
 #pragma unroll 1
   for (int h = 0; h < PPT; h += 4) {
     const int64_t b4 = lb + h * 64;
-    const bool full = A.vec && b4 + 4 <= end;
-    int ca[4];
-    float px[4], py[4], pz[4], ux[4], uy[4], uz[4], pw[4];
-    load4(A.cell, b4, end, full, ca);
-    load4(A.ox, b4, end, full, px);
-    load4(A.oy, b4, end, full, py);
-    if (NDIM == 3) load4(A.oz, b4, end, full, pz);
-    load4(A.ux, b4, end, full, ux);
-    load4(A.uy, b4, end, full, uy);
-    load4(A.uz, b4, end, full, uz);
-    if (DEP || want_diag) load4(A.w, b4, end, full, pw);
+    const bool full = step_full(h);
+    if (h > 0) load_group<NDIM>(A, b4, end, full, wq, cur);
+    int* ca = cur.ca;
+    float *px = cur.px, *py = cur.py, *pz = cur.pz, *ux = cur.ux, *uy = cur.uy, *uz = cur.uz;
+    const float* pw = cur.pw;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int a = ca[q];
       const float x = px[q], y = py[q], z = NDIM == 3 ? pz[q] : 0.f;
       const float vx = ux[q], vy = uy[q], vz = uz[q];
-      const float wq = (DEP || want_diag) ? pw[q] : 0.f;
+      const float wgt = wq ? pw[q] : 0.f;
       bool live = b4 + q < end;
       if (live && (unsigned)a >= (unsigned)g.ncell) {
         raise_flag(A.st, HVPIC_FLAG_BAD_INPUT, &A.st->bad_input);
@@ -946,10 +969,10 @@ void k_gather_push(PushArgs A) {
         nvy = fmaf(hh, Ep[1], vmy + (qz * sx - qx * sz));
         nvz = fmaf(hh, Ep[2], vmz + (qx * sy - qy * sx));
         if (want_diag) {
-          dK = fmaf(wq, vx * nvx + vy * nvy + vz * nvz, dK);
-          dP0 = fmaf(wq, vx + nvx, dP0);
-          dP1 = fmaf(wq, vy + nvy, dP1);
-          dP2 = fmaf(wq, vz + nvz, dP2);
+          dK = fmaf(wgt, vx * nvx + vy * nvy + vz * nvz, dK);
+          dP0 = fmaf(wgt, vx + nvx, dP0);
+          dP1 = fmaf(wgt, vy + nvy, dP1);
+          dP2 = fmaf(wgt, vz + nvz, dP2);
         }
         // Move: x^{n+1} = x^n + v^{n+1/2} dt, renormalised offsets.
         float nx_ = fmaf(nvx, A.kx, x), ny_ = fmaf(nvy, A.ky, y), nz_ = z;
@@ -999,7 +1022,7 @@ void k_gather_push(PushArgs A) {
       if (cnt_on) count_move<NDIM>(d, inwin, rel, a, chome, nstay, s_cnt, A.cnt);
       if (DEP)
         deposit_particle<NDIM, SHAPE>(H, Q, win, live, inwin, rel, i, j, k, mx, my, mz, xm, ym,
-                                      zm, A.qV * wq, nvx, nvy, nvz, g, A.acc);
+                                      zm, A.qV * wgt, nvx, nvy, nvz, g, A.acc);
     }
     store4(A.cell, b4, end, full, ca);
     store4(A.ox, b4, end, full, px);
@@ -1049,21 +1072,18 @@ __global__ __launch_bounds__(kBlock) void k_deposit(DepArgs A) {
   Queue<NDIM> Q;
   Q.base = s_q + (threadIdx.x >> 6) * Queue<NDIM>::QCAP * Queue<NDIM>::QW;
   Q.count = 0;
-  const int64_t lb = base + (int64_t)(threadIdx.x >> 6) * 64 * PPT + 4 * (threadIdx.x & 63);
+  const int64_t wb = base + (int64_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6) * 64 * PPT;
+  const int64_t lb = wb + 4 * (threadIdx.x & 63);
 #pragma unroll 1
   for (int h = 0; h < PPT; h += 4) {
     const int64_t b4 = lb + h * 64;
-    const bool full = A.vec && b4 + 4 <= end;
-    int ca[4];
-    float px[4], py[4], pz[4], ux[4], uy[4], uz[4], pw[4];
-    load4(A.cell, b4, end, full, ca);
-    load4(A.ox, b4, end, full, px);
-    load4(A.oy, b4, end, full, py);
-    if (NDIM == 3) load4(A.oz, b4, end, full, pz);
-    load4(A.ux, b4, end, full, ux);
-    load4(A.uy, b4, end, full, uy);
-    load4(A.uz, b4, end, full, uz);
-    load4(A.w, b4, end, full, pw);
+    // the same on all lanes of the wavefront (see load_group)
+    const bool full = A.vec && wb + h * 64 + 256 <= end;
+    Group<NDIM> G;
+    load_group<NDIM>(A, b4, end, full, true, G);
+    const int* ca = G.ca;
+    const float *px = G.px, *py = G.py, *pz = G.pz, *ux = G.ux, *uy = G.uy, *uz = G.uz;
+    const float* pw = G.pw;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       int a = ca[q];
