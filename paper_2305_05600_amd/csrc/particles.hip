@@ -550,7 +550,10 @@ __device__ __forceinline__ void deposit_particle(Home<NDIM, SHAPE>& H, Queue<NDI
     H.acc[t][3] = fmaf(a, vz, H.acc[t][3]);
   }
   queue_push<NDIM, SHAPE>(Q, win, use_win && !stay, kw, x, y, z, q, vx, vy, vz);
-  if (live && !use_win) deposit_global<NDIM, SHAPE>(i, j, k, mx, my, mz, wt, q, vx, vy, vz, g, acc);
+  const bool global = live && !use_win;
+  if (__ballot(global) != 0) {
+    if (global) deposit_global<NDIM, SHAPE>(i, j, k, mx, my, mz, wt, q, vx, vy, vz, g, acc);
+  }
 }
 
 // DPP move of v from `lane - D` within each 16-lane row (row_shr:D); lanes
@@ -718,11 +721,22 @@ __device__ __forceinline__ void load_group(const Args& A, int64_t b4, int64_t en
   }
 }
 
-// Shift s with x - 2s in [-1,1): exact compares for |x| < 3 (x -/+ 2 is
-// exact there by Sterbenz), the general path beyond.
+// Shift s with x - 2s in [-1,1) for |x| < 3: one exact compare each way (x -/+
+// 2 is exact there by Sterbenz), branch-free.  Callers send any other value
+// down renorm.
+__device__ __forceinline__ int near_shift(float x) {
+  return (x >= 1.0f ? 1 : 0) - (x < -1.0f ? 1 : 0);
+}
+
+// Wrap of a cell index at most one cell outside [0, n).
+__device__ __forceinline__ int wrap_near(int t, int n) {
+  return t < 0 ? t + n : (t >= n ? t - n : t);
+}
+
+// Stand-alone shift (deposit kernel): the near case, else the general path.
 __device__ __forceinline__ bool renorm_fast(float& x, int& s) {
   if (fabsf(x) < 3.0f) {
-    s = (x >= 1.0f ? 1 : 0) - (x < -1.0f ? 1 : 0);
+    s = near_shift(x);
     x = fmaf(-2.0f, (float)s, x);
     return true;
   }
@@ -778,30 +792,32 @@ __device__ __forceinline__ void check_cell_start(const int32_t* __restrict__ cs,
 }
 
 // Direction code of the move (i,j,k) -> (ni,nj,nk) (shift si,sj,sk) of
-// particle idx of old cell a (window column rel), classified as the sort does;
-// -1 (and the sort sent down its general path) for a longer move or a
-// particle out of place.
+// particle idx of old cell a (window column rel; a is read only outside the
+// window), classified as the sort does; -1 (and the sort sent down its
+// general path) for a longer move or a particle out of place, and for a lane
+// that is not live.  Every lane of the wavefront calls it: the rare cases
+// take wavefront-uniform branches.
 template <int NDIM, typename Args>
 __device__ __forceinline__ int move_direction(const Args& A, int64_t idx, int a, int rel,
-                                              bool inwin, const int32_t* s_cs, int i, int j,
-                                              int k, int ni, int nj, int nk, int si, int sj,
-                                              int sk) {
-  // the window's copy, or the global table for a particle outside it (read
-  // as relaxed atomics, which the compiler cannot merge with the LDS reads
-  // into one flat read through a select of the two addresses)
+                                              bool live, bool inwin, const int32_t* s_cs, int i,
+                                              int j, int k, int ni, int nj, int nk, int si,
+                                              int sj, int sk) {
   const int rw = inwin ? rel : 0;
   int64_t lo = s_cs[rw], hi = s_cs[rw + 1];
-  if (!inwin) {
-    lo = __hip_atomic_load(A.cs + a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    hi = __hip_atomic_load(A.cs + a + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const bool outwin = live && !inwin;
+  if (__ballot(outwin) != 0) {
+    // the global table for a particle outside the window (relaxed atomics,
+    // which the compiler cannot merge with the LDS reads into one flat read
+    // through a select of the two addresses)
+    if (outwin) {
+      lo = __hip_atomic_load(A.cs + a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      hi = __hip_atomic_load(A.cs + a + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
     // vmcnt(0) here, so that the common path after the branch need not wait
     // for these (and with them for every older load in flight)
     __builtin_amdgcn_s_waitcnt(0x0F70);
   }
-  if (idx < lo || idx >= hi) {
-    flag_far(A.st, HVPIC_FLAG_BAD_INPUT, &A.st->bad_input);
-    return -1;
-  }
+  const bool misplaced = live && (idx < lo || idx >= hi);
   const Geo& g = A.g;
   int di, dj, dk;
   if (g.nx >= 3 && g.ny >= 3 && (NDIM == 2 || g.nz >= 3)) {
@@ -815,14 +831,17 @@ __device__ __forceinline__ int move_direction(const Args& A, int64_t idx, int a,
     dj = canon_move(nj - j, g.ny);
     dk = NDIM == 3 ? canon_move(nk - k, g.nz) : 0;
   }
-  if (di == 2 || dj == 2 || dk == 2) {
-    flag_far(A.st, HVPIC_FLAG_MOVE_GT1, nullptr);
-    return -1;
+  const bool far = live && !misplaced && (di == 2 || dj == 2 || dk == 2);
+  if (__ballot(misplaced || far) != 0) {
+    if (misplaced) flag_far(A.st, HVPIC_FLAG_BAD_INPUT, &A.st->bad_input);
+    if (far) flag_far(A.st, HVPIC_FLAG_MOVE_GT1, nullptr);
   }
-  return (di + 1) + 3 * (dj + 1) + (NDIM == 3 ? 9 * (dk + 1) : 0);
+  return live && !misplaced && !far ? (di + 1) + 3 * (dj + 1) + (NDIM == 3 ? 9 * (dk + 1) : 0)
+                                    : -1;
 }
 
-// Counts one move (d >= 0).  Every lane of the wavefront calls it.
+// Counts one move (d >= 0) of a particle of old cell a (window column rel; a
+// is read only outside the window).  Every lane of the wavefront calls it.
 template <int NDIM>
 __device__ __forceinline__ void count_move(int d, bool inwin, int rel, int a, int& chome,
                                            uint32_t& nstay, uint32_t* s_cnt,
@@ -832,8 +851,11 @@ __device__ __forceinline__ void count_move(int d, bool inwin, int rel, int a, in
   if (local && chome < 0) chome = rel;
   const bool stays = local && rel == chome && d == CENTRE;
   nstay += stays ? 1u : 0u;
-  if (local && !stays) atomicAdd(&s_cnt[rel * ND + d], 1u);
-  if (d >= 0 && !inwin) atomicAdd(&cnt[(int64_t)a * ND + d], 1u);
+  const bool to_lds = local && !stays, to_global = d >= 0 && !inwin;
+  if (__ballot(to_lds || to_global) != 0) {
+    if (to_lds) atomicAdd(&s_cnt[rel * ND + d], 1u);
+    if (to_global) atomicAdd(&cnt[(int64_t)a * ND + d], 1u);
+  }
 }
 
 // End of a group step: home-cell stay counts go to the window, combined
@@ -869,6 +891,53 @@ __device__ void moves_window_flush(const uint32_t* s_cnt, int c0, int span,
   }
 }
 
+// The move of one lane outside the near case (an offset beyond three
+// half-cells of the centre, or a non-finite one): the general shift, the
+// status flags, the wrap of any shift, and the mid-point the same way (kept at
+// x^n when it cannot be renormalised).  A non-finite position keeps the
+// particle where it was.
+template <int NDIM, bool DEP>
+__device__ void move_general(const PushArgs& A, float x, float y, float z, float nvx, float nvy,
+                             float nvz, int i, int j, int k, float& nx_, float& ny_, float& nz_,
+                             int& si, int& sj, int& sk, int& ni, int& nj, int& nk, float& xm,
+                             float& ym, float& zm, int& mx, int& my, int& mz) {
+  const Geo& g = A.g;
+  nx_ = fmaf(nvx, A.kx, x);
+  ny_ = fmaf(nvy, A.ky, y);
+  nz_ = NDIM == 3 ? fmaf(nvz, A.kz, z) : z;
+  si = sj = sk = 0;
+  bool ok = renorm(nx_, si);
+  ok = renorm(ny_, sj) && ok;
+  if (NDIM == 3) ok = renorm(nz_, sk) && ok;
+  if (!ok) {
+    raise_flag(A.st, HVPIC_FLAG_NONFINITE, &A.st->nonfinite);
+    si = sj = sk = 0;
+    nx_ = x;
+    ny_ = y;
+    nz_ = z;
+  } else if (si > 1 || si < -1 || sj > 1 || sj < -1 || sk > 1 || sk < -1) {
+    raise_flag(A.st, HVPIC_FLAG_MOVE_GT1, &A.st->moved_gt1);
+  }
+  ni = wrapi(i + si, g.nx);
+  nj = wrapi(j + sj, g.ny);
+  nk = NDIM == 3 ? wrapi(k + sk, g.nz) : 0;
+  if (DEP) {
+    xm = fmaf(nvx, 0.5f * A.kx, x);
+    ym = fmaf(nvy, 0.5f * A.ky, y);
+    zm = NDIM == 3 ? fmaf(nvz, 0.5f * A.kz, z) : 0.0f;
+    mx = my = mz = 0;
+    bool okm = ok && renorm(xm, mx);
+    okm = okm && renorm(ym, my);
+    if (NDIM == 3) okm = okm && renorm(zm, mz);
+    if (!okm) {
+      xm = x;
+      ym = y;
+      zm = z;
+      mx = my = mz = 0;
+    }
+  }
+}
+
 // ---------------------------------------------------------------- kernels --
 
 // Fused gather + Boris push + move (+ mid-point deposit when DEP).
@@ -898,7 +967,7 @@ void k_gather_push(PushArgs A) {
   // Wavefront wv owns particles [base + wv*64*PPT, +64*PPT); in each group
   // step lane l takes four consecutive ones, so a step is one coalesced
   // 1 KiB access per array.  The first step's particles are loaded during the
-  // set-up below.
+  // set-up below, each later step's right after the previous step's stores.
   const int64_t wb = base + (int64_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6) * 64 * PPT;
   const int64_t lb = wb + 4 * (threadIdx.x & 63);
   // a step of the wavefront is all in range, or it takes element-wise accesses
@@ -929,97 +998,110 @@ void k_gather_push(PushArgs A) {
   for (int h = 0; h < PPT; h += 4) {
     const int64_t b4 = lb + h * 64;
     const bool full = step_full(h);
-    if (h > 0) load_group<NDIM>(A, b4, end, full, wq, cur);
     int* ca = cur.ca;
     float *px = cur.px, *py = cur.py, *pz = cur.pz, *ux = cur.ux, *uy = cur.uy, *uz = cur.uz;
     const float* pw = cur.pw;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
+      // Every lane runs the common path; a lane past the end or with a bad
+      // cell computes on finite stand-in values and has no effect.  Rare
+      // cases (outside the windows, far or non-finite moves, flags) take
+      // wavefront-uniform branches.
       const int a = ca[q];
       const float x = px[q], y = py[q], z = NDIM == 3 ? pz[q] : 0.f;
       const float vx = ux[q], vy = uy[q], vz = uz[q];
-      const float wgt = wq ? pw[q] : 0.f;
-      bool live = b4 + q < end;
-      if (live && (unsigned)a >= (unsigned)g.ncell) {
-        raise_flag(A.st, HVPIC_FLAG_BAD_INPUT, &A.st->bad_input);
-        live = false;
+      const bool inrange = b4 + q < end;
+      const bool badcell = inrange && (unsigned)a >= (unsigned)g.ncell;
+      const bool live = inrange && !badcell;
+      const float wgt = wq && live ? pw[q] : 0.f;
+      if (__ballot(badcell) != 0) {
+        if (badcell) raise_flag(A.st, HVPIC_FLAG_BAD_INPUT, &A.st->bad_input);
       }
       const int rel = a - c0;
       const bool inwin = wok && rel >= 0 && rel <= span;
-      int i = 0, j = 0, k = 0, mx = 0, my = 0, mz = 0, d = -1;
-      float xm = 0.f, ym = 0.f, zm = 0.f, nvx = 0.f, nvy = 0.f, nvz = 0.f;
-      if (live) {
-        float Ep[3], Bp[3];
-        if (inwin) {
-          gather_rec<NDIM, SHAPE>(gw, rel, x, y, z, Ep, Bp, i, j, k);
-        } else {
+      int i = 0, j = 0, k = 0;
+      float Ep[3] = {0.f, 0.f, 0.f}, Bp[3] = {0.f, 0.f, 0.f};
+      if (wok) gather_rec<NDIM, SHAPE>(gw, inwin ? rel : 0, x, y, z, Ep, Bp, i, j, k);
+      // outside the windows: the cell index for the global tables, rebuilt
+      // from its indices (a value of its own, so that the 64-bit address
+      // arithmetic of this rare path does not move the loaded cells into
+      // aligned register pairs on the common path)
+      int ag = 0;
+      const bool outwin = live && !inwin;
+      if (__ballot(outwin) != 0) {
+        if (outwin) {
           decompose(a, g, i, j, k);
-          gather_eb<NDIM, SHAPE>(A.E, A.B, a, i, j, k, x, y, z, g, Ep, Bp);
-        }
-        // Boris: half kick, rotation, half kick.
-        const float hh = A.a;
-        const float vmx = fmaf(hh, Ep[0], vx), vmy = fmaf(hh, Ep[1], vy), vmz = fmaf(hh, Ep[2], vz);
-        const float tx = hh * Bp[0], ty = hh * Bp[1], tz = hh * Bp[2];
-        const float f = 2.0f / (1.0f + (tx * tx + ty * ty + tz * tz));
-        const float sx = f * tx, sy = f * ty, sz = f * tz;
-        const float qx = vmx + (vmy * tz - vmz * ty);
-        const float qy = vmy + (vmz * tx - vmx * tz);
-        const float qz = vmz + (vmx * ty - vmy * tx);
-        nvx = fmaf(hh, Ep[0], vmx + (qy * sz - qz * sy));
-        nvy = fmaf(hh, Ep[1], vmy + (qz * sx - qx * sz));
-        nvz = fmaf(hh, Ep[2], vmz + (qx * sy - qy * sx));
-        if (want_diag) {
-          dK = fmaf(wgt, vx * nvx + vy * nvy + vz * nvz, dK);
-          dP0 = fmaf(wgt, vx + nvx, dP0);
-          dP1 = fmaf(wgt, vy + nvy, dP1);
-          dP2 = fmaf(wgt, vz + nvz, dP2);
-        }
-        // Move: x^{n+1} = x^n + v^{n+1/2} dt, renormalised offsets.
-        float nx_ = fmaf(nvx, A.kx, x), ny_ = fmaf(nvy, A.ky, y), nz_ = z;
-        int si = 0, sj = 0, sk = 0;
-        bool ok = renorm_fast(nx_, si) && renorm_fast(ny_, sj);
-        if (NDIM == 3) {
-          nz_ = fmaf(nvz, A.kz, z);
-          ok = ok && renorm_fast(nz_, sk);
-        }
-        if (!ok) {
-          raise_flag(A.st, HVPIC_FLAG_NONFINITE, &A.st->nonfinite);
-          si = sj = sk = 0;
-          nx_ = x;
-          ny_ = y;
-          nz_ = z;
-        } else if (si > 1 || si < -1 || sj > 1 || sj < -1 || sk > 1 || sk < -1) {
-          raise_flag(A.st, HVPIC_FLAG_MOVE_GT1, &A.st->moved_gt1);
-        }
-        int ni = i + si, nj = j + sj, nk = k + sk;
-        if ((unsigned)ni >= (unsigned)g.nx) ni = wrapi(ni, g.nx);
-        if ((unsigned)nj >= (unsigned)g.ny) nj = wrapi(nj, g.ny);
-        if (NDIM == 3 && (unsigned)nk >= (unsigned)g.nz) nk = wrapi(nk, g.nz);
-        ca[q] = ni + g.nx * (nj + g.ny * nk);
-        px[q] = nx_;
-        py[q] = ny_;
-        if (NDIM == 3) pz[q] = nz_;
-        ux[q] = nvx;
-        uy[q] = nvy;
-        uz[q] = nvz;
-        if (cnt_on)
-          d = move_direction<NDIM>(A, b4 + q, a, rel, inwin, s_cs, i, j, k, ni, nj, nk, si, sj,
-                                   sk);
-        if (DEP) {
-          // Mid-point x^{n+1/2} = x^n + (dt/2) v^{n+1/2}.
-          xm = fmaf(nvx, 0.5f * A.kx, x);
-          ym = fmaf(nvy, 0.5f * A.ky, y);
-          zm = NDIM == 3 ? fmaf(nvz, 0.5f * A.kz, z) : 0.0f;
-          if (!ok || !renorm_fast(xm, mx) || !renorm_fast(ym, my) ||
-              (NDIM == 3 && !renorm_fast(zm, mz))) {
-            xm = x;
-            ym = y;
-            zm = z;
-            mx = my = mz = 0;
-          }
+          ag = i + g.nx * (j + g.ny * k);
+          gather_eb<NDIM, SHAPE>(A.E, A.B, ag, i, j, k, x, y, z, g, Ep, Bp);
         }
       }
-      if (cnt_on) count_move<NDIM>(d, inwin, rel, a, chome, nstay, s_cnt, A.cnt);
+      // Boris: half kick, rotation, half kick.
+      const float hh = A.a;
+      const float vmx = fmaf(hh, Ep[0], vx), vmy = fmaf(hh, Ep[1], vy), vmz = fmaf(hh, Ep[2], vz);
+      const float tx = hh * Bp[0], ty = hh * Bp[1], tz = hh * Bp[2];
+      const float f = 2.0f / (1.0f + (tx * tx + ty * ty + tz * tz));
+      const float sx = f * tx, sy = f * ty, sz = f * tz;
+      const float qx = vmx + (vmy * tz - vmz * ty);
+      const float qy = vmy + (vmz * tx - vmx * tz);
+      const float qz = vmz + (vmx * ty - vmy * tx);
+      const float nvx = fmaf(hh, Ep[0], vmx + (qy * sz - qz * sy));
+      const float nvy = fmaf(hh, Ep[1], vmy + (qz * sx - qx * sz));
+      const float nvz = fmaf(hh, Ep[2], vmz + (qx * sy - qy * sx));
+      if (want_diag) {
+        dK = fmaf(wgt, vx * nvx + vy * nvy + vz * nvz, dK);
+        dP0 = fmaf(wgt, vx + nvx, dP0);
+        dP1 = fmaf(wgt, vy + nvy, dP1);
+        dP2 = fmaf(wgt, vz + nvz, dP2);
+      }
+      // Move: x^{n+1} = x^n + v^{n+1/2} dt, and for the deposit the mid-point
+      // x^{n+1/2} = x^n + (dt/2) v^{n+1/2}, with renormalised offsets.
+      float nx_ = fmaf(nvx, A.kx, x), ny_ = fmaf(nvy, A.ky, y);
+      float nz_ = NDIM == 3 ? fmaf(nvz, A.kz, z) : z;
+      float xm = 0.f, ym = 0.f, zm = 0.f;
+      if (DEP) {
+        xm = fmaf(nvx, 0.5f * A.kx, x);
+        ym = fmaf(nvy, 0.5f * A.ky, y);
+        zm = NDIM == 3 ? fmaf(nvz, 0.5f * A.kz, z) : 0.0f;
+      }
+      bool near = fabsf(nx_) < 3.0f && fabsf(ny_) < 3.0f && (NDIM == 2 || fabsf(nz_) < 3.0f);
+      if (DEP)
+        near = near && fabsf(xm) < 3.0f && fabsf(ym) < 3.0f && (NDIM == 2 || fabsf(zm) < 3.0f);
+      int si = near_shift(nx_), sj = near_shift(ny_), sk = NDIM == 3 ? near_shift(nz_) : 0;
+      nx_ = fmaf(-2.0f, (float)si, nx_);
+      ny_ = fmaf(-2.0f, (float)sj, ny_);
+      if (NDIM == 3) nz_ = fmaf(-2.0f, (float)sk, nz_);
+      int mx = 0, my = 0, mz = 0;
+      if (DEP) {
+        mx = near_shift(xm);
+        my = near_shift(ym);
+        xm = fmaf(-2.0f, (float)mx, xm);
+        ym = fmaf(-2.0f, (float)my, ym);
+        if (NDIM == 3) {
+          mz = near_shift(zm);
+          zm = fmaf(-2.0f, (float)mz, zm);
+        }
+      }
+      int ni = wrap_near(i + si, g.nx), nj = wrap_near(j + sj, g.ny);
+      int nk = NDIM == 3 ? wrap_near(k + sk, g.nz) : 0;
+      const bool general = live && !near;
+      if (__ballot(general) != 0) {
+        if (general)
+          move_general<NDIM, DEP>(A, x, y, z, nvx, nvy, nvz, i, j, k, nx_, ny_, nz_, si, sj, sk,
+                                  ni, nj, nk, xm, ym, zm, mx, my, mz);
+      }
+      // a lane that is not live keeps its values
+      ca[q] = live ? ni + g.nx * (nj + g.ny * nk) : a;
+      px[q] = live ? nx_ : x;
+      py[q] = live ? ny_ : y;
+      if (NDIM == 3) pz[q] = live ? nz_ : z;
+      ux[q] = live ? nvx : vx;
+      uy[q] = live ? nvy : vy;
+      uz[q] = live ? nvz : vz;
+      if (cnt_on) {
+        const int d = move_direction<NDIM>(A, b4 + q, ag, rel, live, inwin, s_cs, i, j, k, ni, nj,
+                                           nk, si, sj, sk);
+        count_move<NDIM>(d, inwin, rel, ag, chome, nstay, s_cnt, A.cnt);
+      }
       if (DEP)
         deposit_particle<NDIM, SHAPE>(H, Q, win, live, inwin, rel, i, j, k, mx, my, mz, xm, ym,
                                       zm, A.qV * wgt, nvx, nvy, nvz, g, A.acc);
@@ -1031,6 +1113,8 @@ void k_gather_push(PushArgs A) {
     store4(A.ux, b4, end, full, ux);
     store4(A.uy, b4, end, full, uy);
     store4(A.uz, b4, end, full, uz);
+    // the next step's particles arrive during the flushes below
+    if (h + 4 < PPT) load_group<NDIM>(A, b4 + 256, end, step_full(h + 4), wq, cur);
     if (DEP) home_flush(H, win);
     if (cnt_on) count_flush<NDIM>(chome, nstay, s_cnt);
   }
