@@ -1039,7 +1039,9 @@ void k_gather_push(PushArgs A) {
       const float hh = A.a;
       const float vmx = fmaf(hh, Ep[0], vx), vmy = fmaf(hh, Ep[1], vy), vmz = fmaf(hh, Ep[2], vz);
       const float tx = hh * Bp[0], ty = hh * Bp[1], tz = hh * Bp[2];
-      const float f = 2.0f / (1.0f + (tx * tx + ty * ty + tz * tz));
+      // 2 / (1 + |t|^2) through the hardware reciprocal (within 1 ulp; the
+      // operand lies in [1, inf), so no denormals)
+      const float f = 2.0f * __builtin_amdgcn_rcpf(1.0f + (tx * tx + ty * ty + tz * tz));
       const float sx = f * tx, sy = f * ty, sz = f * tz;
       const float qx = vmx + (vmy * tz - vmz * ty);
       const float qy = vmy + (vmz * tx - vmx * tz);
