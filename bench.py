@@ -9,7 +9,10 @@ Faraday subcycle + extrapolation), FP64 diagnostics.
 Prints one JSON line.  `value` is ion pushes per second over whole steps with
 the inputs resident in HBM; the field advance of a step runs on a second
 stream beside the sort (they touch disjoint data; --no-overlap serialises
-them).  `roofline` refers to the dominant kernel (the
+them).  The sort leaves the stable order as a gather map that the next push
+reads through, writing the pushed store in sorted order, so the particles
+cross HBM once per step (--no-gather-map moves the store in the sort instead;
+results are bit-identical).  `roofline` refers to the dominant kernel (the
 fused gather+push+deposit), timed by HIP events that the library records on
 its stream directly around each of its launches;
 `cpu_baseline` times the FP64 oracle on one step of the same workload.
@@ -31,8 +34,10 @@ METRIC = "ion pushes/s (gather+push+deposit) & HBM GB/s %peak; step time surroga
 HBM_PEAK_GBS = 8000.0
 # Algorithmic bytes of the fused gather+push+deposit (2D, FP32 SoA):
 # per particle read cell 4 + offsets 8 + velocity 12 + weight 4, write
-# cell 4 + offsets 8 + velocity 12; per cell read E,B 24, write n,J 16.
-BYTES_PER_PARTICLE_2D = 52
+# cell 4 + offsets 8 + velocity 12 (in place); per cell read E,B 24, write
+# n,J 16.  Through a gather map it also reads the map entry (4) and writes
+# the weight (4) to the sorted store.
+BYTES_PER_PARTICLE_2D = {"in place": 52, "gather map": 60}
 BYTES_PER_CELL_2D = 40
 
 
@@ -43,7 +48,7 @@ def _source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def _traffic(n_particles: int):
+def _traffic(n_particles: int, mode: str):
     """HBM bytes per launch of the dominant kernel from committed rocprofv3
     counter runs, or None if none match the current kernel source."""
     path = ROOT / "profiles" / "traffic_gather_push_harris.json"
@@ -53,7 +58,8 @@ def _traffic(n_particles: int):
         rec = json.loads(path.read_text())
     except ValueError:
         return None
-    if rec.get("source_hash") != _source_hash() or rec.get("n_particles") != n_particles:
+    if (rec.get("source_hash") != _source_hash() or rec.get("n_particles") != n_particles
+            or rec.get("mode", "in place") != mode):
         return None
     return rec.get("bytes_per_launch")
 
@@ -80,6 +86,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--unfused", action="store_true", help="separate deposit pass")
+    ap.add_argument("--no-gather-map", action="store_true",
+                    help="move the store in the sort and push it in place")
     ap.add_argument("--no-overlap", action="store_true",
                     help="run the field advance on the particle stream (no overlap with the sort)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -108,7 +116,9 @@ def main() -> int:
 
     cfg, parts, B = W.harris_double()
     n = int(parts["cell"].size)
-    g = S.GpuSim(cfg, parts, B, fused=not args.unfused, overlap=not args.no_overlap)
+    g = S.GpuSim(cfg, parts, B, fused=not args.unfused, overlap=not args.no_overlap,
+                 gather_map=not (args.unfused or args.no_gather_map))
+    mode = "gather map" if g.gather_map else "in place"
     for _ in range(args.warmup):
         g.step()
     g.synchronize()
@@ -131,7 +141,7 @@ def main() -> int:
     flags, counts = g.status()
     ms_per_step = wall * 1e3 / args.steps
 
-    per_launch = BYTES_PER_PARTICLE_2D * n + BYTES_PER_CELL_2D * cfg.ncell
+    per_launch = BYTES_PER_PARTICLE_2D[mode] * n + BYTES_PER_CELL_2D * cfg.ncell
     achieved = per_launch / (kernel_ms * 1e-3) / 1e9
     out = {
         "metric": METRIC,
@@ -148,11 +158,13 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": cfg.name, "cells": [cfg.nx, cfg.ny], "particles": n,
                    "shape": "QS", "b_subcycles": cfg.nsub, "dt": cfg.dt,
-                   "fused_deposit": g.fused},
+                   "fused_deposit": g.fused, "push_reads": mode},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": _traffic(n),
-                     "kernel": "k_gather_push (fused deposit)" if g.fused else "k_gather_push",
+                     "traffic": _traffic(n, mode),
+                     "kernel": ("k_gather_push (fused deposit"
+                                + (", read through the gather map)" if g.gather_map else ")")
+                                if g.fused else "k_gather_push"),
                      "kernel_ms": kernel_ms,
                      "algorithmic_bytes_per_launch": per_launch},
         "kernels_ms": {"gather_push_deposit": kernel_ms,

@@ -158,6 +158,30 @@ int hvpic_gather_push(hvpic_ctx* ctx, hvpic_particles* p, const int32_t* cell_st
 int hvpic_sort(hvpic_ctx* ctx, const hvpic_particles* in, hvpic_particles* out,
                const int32_t* cell_start_prev, int32_t* cell_start, int full);
 
+/* The same sort given as a gather map instead of a moved store: perm
+   (device int32 [in->n]) receives, for each position k of the stable order
+   by cell, the index in `in` of the particle that goes there; cell_start
+   [ncell+1] is written as hvpic_sort writes it.  Nothing else is written and
+   `in` is only read (its cell array).  Same paths, checks and flags as
+   hvpic_sort with full == 0 (cell_start_prev == NULL: the general sort).
+   Together with hvpic_gather_push_perm this lets the next push read the
+   store in sorted order, so the particles move once per step instead of
+   twice. */
+int hvpic_sort_perm(hvpic_ctx* ctx, const hvpic_particles* in, const int32_t* cell_start_prev,
+                    int32_t* perm, int32_t* cell_start);
+
+/* hvpic_gather_push of the store `in` read through a gather map: particle k
+   of the step is element perm[k] of `in` (perm as hvpic_sort_perm writes
+   it), and the pushed particle, weight included, is written to position k
+   of `out` (out->n is set to in->n).  cell_start describes that order, as
+   for hvpic_gather_push; the move counts it leaves are those of `out`.
+   `in` and `out` must not overlap; in->w is always read.  Results are
+   bit-identical to hvpic_sort into `out` followed by hvpic_gather_push on
+   `out`. */
+int hvpic_gather_push_perm(hvpic_ctx* ctx, const hvpic_particles* in, const int32_t* perm,
+                           hvpic_particles* out, const int32_t* cell_start, const float* E,
+                           const float* B, float* n_mid, float* J_mid, double* diag_out);
+
 /* Moments of the ion species (Sec. II.A n_e, J_i; eq:ngp / eq:quad) at
    x - half_dt_back * v (half_dt_back = dt/2 after a push gives
    x^{n+1/2}; 0 deposits at x).  Contributions per particle: n += qs w W/V_c,

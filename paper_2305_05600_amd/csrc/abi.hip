@@ -171,6 +171,29 @@ int hvpic_gather_push(hvpic_ctx* ctx, hvpic_particles* p, const int32_t* cell_st
   return launch_gather_push(ctx, p, cell_start, E, B, n_mid, J_mid, diag_out);
 }
 
+int hvpic_gather_push_perm(hvpic_ctx* ctx, const hvpic_particles* in, const int32_t* perm,
+                           hvpic_particles* out, const int32_t* cell_start, const float* E,
+                           const float* B, float* n_mid, float* J_mid, double* diag_out) {
+  if (!ctx_ok(ctx)) return HVPIC_ESTATE;
+  if (!parts_ok(ctx, in, true) || !out || !E || !B) return HVPIC_EINVAL;
+  if ((n_mid == nullptr) != (J_mid == nullptr)) return HVPIC_EINVAL;
+  if (in->n > 0) {
+    if (!perm || !out->cell || !out->ox || !out->oy || !out->ux || !out->uy || !out->uz ||
+        !out->w)
+      return HVPIC_EINVAL;
+    if (ctx->p.ndim == 3 && !out->oz) return HVPIC_EINVAL;
+    if (out->cell == in->cell || out->ox == in->ox || out->ux == in->ux || out->w == in->w)
+      return HVPIC_EINVAL;
+  }
+  return launch_gather_push_perm(ctx, in, perm, out, cell_start, E, B, n_mid, J_mid, diag_out);
+}
+int hvpic_sort_perm(hvpic_ctx* ctx, const hvpic_particles* in, const int32_t* cell_start_prev,
+                    int32_t* perm, int32_t* cell_start) {
+  if (!ctx_ok(ctx)) return HVPIC_ESTATE;
+  if (!parts_ok(ctx, in, false) || !cell_start) return HVPIC_EINVAL;
+  if (in->n > 0 && !perm) return HVPIC_EINVAL;
+  return launch_sort_perm(ctx, in, cell_start_prev, perm, cell_start);
+}
 int hvpic_sort(hvpic_ctx* ctx, const hvpic_particles* in, hvpic_particles* out,
                const int32_t* cell_start_prev, int32_t* cell_start, int full) {
   if (!ctx_ok(ctx)) return HVPIC_ESTATE;

@@ -158,10 +158,15 @@ constexpr int32_t kMagic = 0x68767063;
 int launch_gather_push(hvpic_ctx* c, hvpic_particles* p, const int32_t* cell_start,
                        const float* E, const float* B, float* n_mid, float* J_mid,
                        double* diag_out);
+int launch_gather_push_perm(hvpic_ctx* c, const hvpic_particles* in, const int32_t* perm,
+                            hvpic_particles* out, const int32_t* cell_start, const float* E,
+                            const float* B, float* n_mid, float* J_mid, double* diag_out);
 int launch_deposit(hvpic_ctx* c, const hvpic_particles* p, const int32_t* cell_start,
                    float half_dt_back, float* n, float* J);
 int launch_sort(hvpic_ctx* c, const hvpic_particles* in, hvpic_particles* out,
                 const int32_t* cs_prev, int32_t* cs, int full);
+int launch_sort_perm(hvpic_ctx* c, const hvpic_particles* in, const int32_t* cs_prev,
+                     int32_t* perm, int32_t* cs);
 int launch_field_advance(hvpic_ctx* c, float* B, const float* n_half, const float* J_half,
                          const float* n_prev, const float* J_prev, float* E_out, int mode,
                          double* diag_out);

@@ -72,6 +72,13 @@ struct PushArgs {
   bool vec;                 // all particle arrays 16-byte aligned
   const int32_t* cs;        // cell_start of the sorted store, or null
   uint32_t* cnt;            // moves per (old cell, direction), written when cs is given
+  // Read through a gather map: particle k of the step is element perm[k] of
+  // the source arrays below, and the pushed store (weights included) goes to
+  // the arrays above.  perm null: the store above is read and written in place.
+  const int32_t* perm;
+  const int32_t* icell;
+  const float *iox, *ioy, *ioz, *iux, *iuy, *iuz, *iw;
+  float* wo;
 };
 
 struct DepArgs {
@@ -338,6 +345,13 @@ struct DWin {
   static constexpr int LEN = NB * SW * 4;       // doubles
 };
 
+// The block's deposit window in LDS: the FP64 sums, and per slot the wrap
+// bits (as in stencil_slots) of that slot's cell.
+struct WinLds {
+  double* acc;
+  const uint8_t* wrap;
+};
+
 // Window slots of the stencil cells of the cell at slot `key`; wrap bit 0/1:
 // its +x/-x neighbour wraps around the x boundary, bit 2/3 the same for y (3D).
 template <int NDIM, int SHAPE>
@@ -367,21 +381,20 @@ __device__ __forceinline__ int wrap_bits(int i, int j, const Geo& g) {
   return w;
 }
 
-// Window slot << 4 | wrap bits of the cell (mx, my, mz) away from the cell
-// of window column `rel` with indices (i, j).
+// Window slot of the cell (mx, my, mz) away from the cell of window column
+// `rel` with indices (i, j).
 template <int NDIM>
-__device__ __forceinline__ int slot_wrap(int rel, int i, int j, int mx, int my, int mz,
-                                         const Geo& g) {
+__device__ __forceinline__ int window_slot(int rel, int i, int j, int mx, int my, int mz,
+                                           const Geo& g) {
   const int t1 = i + mx;
   const int wx = t1 < 0 ? 1 : (t1 >= g.nx ? -1 : 0);
-  int band = my + wx + 3, t2 = 0, wy = 0;
+  int band = my + wx + 3;
   if (NDIM == 3) {
-    t2 = j + my;
-    wy = t2 < 0 ? 1 : (t2 >= g.ny ? -1 : 0);
+    const int t2 = j + my;
+    const int wy = t2 < 0 ? 1 : (t2 >= g.ny ? -1 : 0);
     band += 7 * (mz + wy + 3);
   }
-  return ((band * DWin<NDIM>::SW + rel + mx + 2) << 4) |
-         wrap_bits<NDIM>(t1 + wx * g.nx, t2 + wy * g.ny, g);
+  return band * DWin<NDIM>::SW + rel + mx + 2;
 }
 
 // Deposit straight into the FP64 global accumulators (particles outside the
@@ -439,8 +452,8 @@ __device__ __forceinline__ void wave_sync_lds() {
 }
 
 // Per-wavefront queue (LDS, structure-of-arrays of QCAP entries) of deposits
-// that do not add to their lane's running sums: word 0 = window slot << 4 |
-// wrap bits, then the deposit offsets, the charge factor and the velocity.
+// that do not add to their lane's running sums: word 0 = window slot, then
+// the deposit offsets, the charge factor and the velocity.
 template <int NDIM>
 struct Queue {
   static constexpr int QCAP = 64;
@@ -451,7 +464,7 @@ struct Queue {
 
 // Adds every queued deposit to the window, lane e taking entry e.
 template <int NDIM, int SHAPE>
-__device__ __forceinline__ void queue_drain(Queue<NDIM>& Q, double* win) {
+__device__ __forceinline__ void queue_drain(Queue<NDIM>& Q, const WinLds& wl) {
   constexpr int T = Stencil<NDIM, SHAPE>::T;
   constexpr int QC = Queue<NDIM>::QCAP, o = NDIM == 3 ? 4 : 3;
   if (Q.count == 0) return;
@@ -459,7 +472,7 @@ __device__ __forceinline__ void queue_drain(Queue<NDIM>& Q, double* win) {
   const int e = threadIdx.x & 63;
   if (e < Q.count) {
     const float* b = Q.base;
-    const int kw = __float_as_int(b[e]);
+    const int key = __float_as_int(b[e]);
     const float x = b[QC + e], y = b[2 * QC + e];
     const float z = NDIM == 3 ? b[3 * QC + e] : 0.0f;
     const float q = b[o * QC + e], vx = b[(o + 1) * QC + e];
@@ -467,14 +480,14 @@ __device__ __forceinline__ void queue_drain(Queue<NDIM>& Q, double* win) {
     float wt[T];
     dep_weights<NDIM, SHAPE>(x, y, z, wt);
     int s[T];
-    stencil_slots<NDIM, SHAPE>(kw >> 4, kw & 15, s);
+    stencil_slots<NDIM, SHAPE>(key, wl.wrap[key], s);
 #pragma unroll
     for (int t = 0; t < T; ++t) {
       const float nq = q * wt[t];
-      atomicAdd(win + s[t] * 4 + 0, (double)nq);
-      atomicAdd(win + s[t] * 4 + 1, (double)(nq * vx));
-      atomicAdd(win + s[t] * 4 + 2, (double)(nq * vy));
-      atomicAdd(win + s[t] * 4 + 3, (double)(nq * vz));
+      atomicAdd(wl.acc + s[t] * 4 + 0, (double)nq);
+      atomicAdd(wl.acc + s[t] * 4 + 1, (double)(nq * vx));
+      atomicAdd(wl.acc + s[t] * 4 + 2, (double)(nq * vy));
+      atomicAdd(wl.acc + s[t] * 4 + 3, (double)(nq * vz));
     }
   }
   wave_sync_lds();
@@ -483,18 +496,18 @@ __device__ __forceinline__ void queue_drain(Queue<NDIM>& Q, double* win) {
 
 // Queues this lane's deposit when `exc`; every lane of the wavefront calls it.
 template <int NDIM, int SHAPE>
-__device__ __forceinline__ void queue_push(Queue<NDIM>& Q, double* win, bool exc, int kw, float x,
-                                           float y, float z, float q, float vx, float vy,
-                                           float vz) {
+__device__ __forceinline__ void queue_push(Queue<NDIM>& Q, const WinLds& wl, bool exc, int key,
+                                           float x, float y, float z, float q, float vx,
+                                           float vy, float vz) {
   constexpr int QC = Queue<NDIM>::QCAP, o = NDIM == 3 ? 4 : 3;
   const uint64_t m = __ballot(exc);
   if (m == 0) return;
   const int add = __builtin_popcountll(m);
-  if (Q.count + add > QC) queue_drain<NDIM, SHAPE>(Q, win);
+  if (Q.count + add > QC) queue_drain<NDIM, SHAPE>(Q, wl);
   if (exc) {
     const int e = Q.count + lanes_below_count(m);
     float* b = Q.base;
-    b[e] = __int_as_float(kw);
+    b[e] = __int_as_float(key);
     b[QC + e] = x;
     b[2 * QC + e] = y;
     if (NDIM == 3) b[3 * QC + e] = z;
@@ -511,12 +524,12 @@ __device__ __forceinline__ void queue_push(Queue<NDIM>& Q, double* win, bool exc
 template <int NDIM, int SHAPE>
 struct Home {
   float acc[Stencil<NDIM, SHAPE>::T][4];
-  int kw;  // slot << 4 | wrap of the home cell, -1 if none yet
+  int key;  // window slot of the home cell, -1 if none yet
 };
 
 template <int NDIM, int SHAPE>
 __device__ __forceinline__ void home_clear(Home<NDIM, SHAPE>& H) {
-  H.kw = -1;
+  H.key = -1;
 #pragma unroll
   for (int t = 0; t < Stencil<NDIM, SHAPE>::T; ++t)
     H.acc[t][0] = H.acc[t][1] = H.acc[t][2] = H.acc[t][3] = 0.0f;
@@ -527,7 +540,7 @@ __device__ __forceinline__ void home_clear(Home<NDIM, SHAPE>& H) {
 // Every lane of the wavefront calls it.
 template <int NDIM, int SHAPE>
 __device__ __forceinline__ void deposit_particle(Home<NDIM, SHAPE>& H, Queue<NDIM>& Q,
-                                                 double* win, bool live, bool inwin, int rel,
+                                                 const WinLds& wl, bool live, bool inwin, int rel,
                                                  int i, int j, int k, int mx, int my, int mz,
                                                  float x, float y, float z, float q, float vx,
                                                  float vy, float vz, const Geo& g,
@@ -535,9 +548,9 @@ __device__ __forceinline__ void deposit_particle(Home<NDIM, SHAPE>& H, Queue<NDI
   constexpr int T = Stencil<NDIM, SHAPE>::T;
   const bool use_win = live && inwin && mx >= -1 && mx <= 1 && my >= -1 && my <= 1 &&
                        mz >= -1 && mz <= 1;
-  const int kw = use_win ? slot_wrap<NDIM>(rel, i, j, mx, my, mz, g) : -1;
-  if (use_win && H.kw < 0) H.kw = kw;
-  const bool stay = use_win && kw == H.kw;
+  const int key = use_win ? window_slot<NDIM>(rel, i, j, mx, my, mz, g) : -1;
+  if (use_win && H.key < 0) H.key = key;
+  const bool stay = use_win && key == H.key;
   float wt[T];
   dep_weights<NDIM, SHAPE>(x, y, z, wt);
   const float qm = stay ? q : 0.0f;
@@ -549,7 +562,7 @@ __device__ __forceinline__ void deposit_particle(Home<NDIM, SHAPE>& H, Queue<NDI
     H.acc[t][2] = fmaf(a, vy, H.acc[t][2]);
     H.acc[t][3] = fmaf(a, vz, H.acc[t][3]);
   }
-  queue_push<NDIM, SHAPE>(Q, win, use_win && !stay, kw, x, y, z, q, vx, vy, vz);
+  queue_push<NDIM, SHAPE>(Q, wl, use_win && !stay, key, x, y, z, q, vx, vy, vz);
   const bool global = live && !use_win;
   if (__ballot(global) != 0) {
     if (global) deposit_global<NDIM, SHAPE>(i, j, k, mx, my, mz, wt, q, vx, vy, vz, g, acc);
@@ -581,10 +594,10 @@ __device__ __forceinline__ int shl1_i(int v, int fill) {
 // atomic.  A level adds the neighbour's partial sum times 0 or 1, a DPP move
 // and one FMA.  Every lane of the wavefront calls it.
 template <int NDIM, int SHAPE>
-__device__ __forceinline__ void home_flush(Home<NDIM, SHAPE>& H, double* win) {
+__device__ __forceinline__ void home_flush(Home<NDIM, SHAPE>& H, const WinLds& wl) {
   constexpr int T = Stencil<NDIM, SHAPE>::T;
   const int r = threadIdx.x & 15;
-  const int h = H.kw;
+  const int h = H.key;
   const int prev = shr_i<1>(h, -2), next = shl1_i(h, -2);
   const bool last = r == 15 || next != h;
   // f: a run starts at or after the first lane that v already covers
@@ -610,22 +623,29 @@ __device__ __forceinline__ void home_flush(Home<NDIM, SHAPE>& H, double* win) {
     }
   if (h >= 0 && last) {
     int s[T];
-    stencil_slots<NDIM, SHAPE>(h >> 4, h & 15, s);
+    stencil_slots<NDIM, SHAPE>(h, wl.wrap[h], s);
 #pragma unroll
     for (int t = 0; t < T; ++t)
 #pragma unroll
-      for (int ch = 0; ch < 4; ++ch) atomicAdd(win + s[t] * 4 + ch, (double)H.acc[t][ch]);
+      for (int ch = 0; ch < 4; ++ch) atomicAdd(wl.acc + s[t] * 4 + ch, (double)H.acc[t][ch]);
   }
   home_clear(H);
 }
 
-// Clears columns [0, W) of every band of the deposit window.
+// Clears columns [0, W) of every band of the deposit window (column 0 = cell
+// c0 - 2) and fills the wrap bits of their cells.
 template <int NDIM>
-__device__ void dwin_zero(double* win, int W) {
+__device__ void dwin_init(double* win, uint8_t* wrap, int W, int c0, const Geo& g) {
   constexpr int SW = DWin<NDIM>::SW;
   for (int s = threadIdx.x; s < DWin<NDIM>::NB * W * 4; s += kBlock) {
     const int band = s / (W * 4), rest = s - band * W * 4;
     win[band * SW * 4 + rest] = 0.0;
+  }
+  for (int s = threadIdx.x; s < DWin<NDIM>::NB * W; s += kBlock) {
+    const int band = s / W, col = s - band * W;
+    const int c = (int)window_cell(c0, col, band % 7 - 3, band / 7 - 3, g);
+    const int i = c % g.nx, j = (c / g.nx) % g.ny;
+    wrap[band * SW + col] = (uint8_t)wrap_bits<NDIM>(i, j, g);
   }
 }
 
@@ -719,6 +739,42 @@ __device__ __forceinline__ void load_group(const Args& A, int64_t b4, int64_t en
     // need not wait for them (nor for older loads in flight)
     __builtin_amdgcn_s_waitcnt(0x0F70);
   }
+}
+
+// The same through the gather map A.perm (16-byte aligned, like the
+// destination store): four map entries, then element loads of the source.
+template <int NDIM>
+__device__ __forceinline__ void load_group_perm(const PushArgs& A, int64_t b4, int64_t end,
+                                                bool full, Group<NDIM>& G) {
+  int src[4];
+  if (full)
+    load4v(A.perm, b4, src);
+  else
+    load4e(A.perm, b4, end, src);
+  // an entry outside [0, n) is read as element 0 and flagged (0 past the
+  // end: a valid element, never stored)
+  bool bad = false;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    bad |= (uint32_t)src[q] >= (uint32_t)A.n;
+    src[q] = (uint32_t)src[q] >= (uint32_t)A.n ? 0 : src[q];
+  }
+  if (__ballot(bad) != 0) {
+    if (bad) raise_flag(A.st, HVPIC_FLAG_BAD_INPUT, &A.st->bad_input);
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int64_t e = src[q];
+    G.ca[q] = A.icell[e];
+    G.px[q] = A.iox[e];
+    G.py[q] = A.ioy[e];
+    if (NDIM == 3) G.pz[q] = A.ioz[e];
+    G.ux[q] = A.iux[e];
+    G.uy[q] = A.iuy[e];
+    G.uz[q] = A.iuz[e];
+    G.pw[q] = A.iw[e];
+  }
+  if (!full) __builtin_amdgcn_s_waitcnt(0x0F70);  // as in load_group
 }
 
 // Shift s with x - 2s in [-1,1) for |x| < 3: one exact compare each way (x -/+
@@ -950,6 +1006,7 @@ void k_gather_push(PushArgs A) {
   constexpr int NF4 = Rec<NDIM, SHAPE>::NF4;
   __shared__ float4 gw[Chunk<NDIM>::WMAX * NF4];
   __shared__ double win[DEP ? DWin<NDIM>::LEN : 1];
+  __shared__ uint8_t s_wrap[DEP ? DWin<NDIM>::NB * DWin<NDIM>::SW : 1];
   __shared__ float s_q[DEP ? kBlock / 64 * Queue<NDIM>::QCAP * Queue<NDIM>::QW : 1];
   __shared__ uint32_t s_cnt[Chunk<NDIM>::WMAX * Moves<NDIM>::ND];
   __shared__ int32_t s_cs[Chunk<NDIM>::WMAX + 1];
@@ -958,12 +1015,19 @@ void k_gather_push(PushArgs A) {
   const int64_t base = (int64_t)blockIdx.x * Chunk<NDIM>::N;
   const int64_t end = min(base + (int64_t)Chunk<NDIM>::N, A.n);
   if (threadIdx.x == 0) {
-    s_c[0] = A.cell[base];
-    s_c[1] = A.cell[end - 1];
+    if (A.perm) {
+      // (entries outside [0, n) are flagged where the particles are loaded)
+      const uint32_t e0 = (uint32_t)A.perm[base], e1 = (uint32_t)A.perm[end - 1];
+      s_c[0] = A.icell[e0 < (uint32_t)A.n ? e0 : 0];
+      s_c[1] = A.icell[e1 < (uint32_t)A.n ? e1 : 0];
+    } else {
+      s_c[0] = A.cell[base];
+      s_c[1] = A.cell[end - 1];
+    }
   }
   __syncthreads();
   const bool want_diag = A.diag_part != nullptr;
-  const bool wq = DEP || want_diag;  // the weights are needed
+  const bool wq = DEP || want_diag || A.perm;  // the weights are needed
   // Wavefront wv owns particles [base + wv*64*PPT, +64*PPT); in each group
   // step lane l takes four consecutive ones, so a step is one coalesced
   // 1 KiB access per array.  The first step's particles are loaded during the
@@ -973,20 +1037,24 @@ void k_gather_push(PushArgs A) {
   // a step of the wavefront is all in range, or it takes element-wise accesses
   auto step_full = [&](int h) { return A.vec && wb + h * 64 + 256 <= end; };
   Group<NDIM> cur;
-  load_group<NDIM>(A, lb, end, step_full(0), wq, cur);
+  if (A.perm)
+    load_group_perm<NDIM>(A, lb, end, step_full(0), cur);
+  else
+    load_group<NDIM>(A, lb, end, step_full(0), wq, cur);
   const int c0 = s_c[0], span = s_c[1] - s_c[0];
   int W = 0;
   const bool wok = window_ok<NDIM>(c0, s_c[1], g, W);
   const bool cnt_on = A.cs != nullptr;  // count the moves for the sort
   if (wok) {
     gwin_fill<NDIM, SHAPE>(reinterpret_cast<float*>(gw), span + 1, c0, g, A.E, A.B);
-    if (DEP) dwin_zero<NDIM>(win, W);
+    if (DEP) dwin_init<NDIM>(win, s_wrap, W, c0, g);
     if (cnt_on) moves_window_init<NDIM>(A.cs, c0, span, s_cs, s_cnt);
   }
   if (cnt_on) check_cell_start(A.cs, g.ncell, A.n, A.st);
   __syncthreads();
 
   float dK = 0.f, dP0 = 0.f, dP1 = 0.f, dP2 = 0.f;
+  const WinLds wl{win, s_wrap};
   Home<NDIM, SHAPE> H;
   home_clear(H);
   Queue<NDIM> Q;
@@ -1105,7 +1173,7 @@ void k_gather_push(PushArgs A) {
         count_move<NDIM>(d, inwin, rel, ag, chome, nstay, s_cnt, A.cnt);
       }
       if (DEP)
-        deposit_particle<NDIM, SHAPE>(H, Q, win, live, inwin, rel, i, j, k, mx, my, mz, xm, ym,
+        deposit_particle<NDIM, SHAPE>(H, Q, wl, live, inwin, rel, i, j, k, mx, my, mz, xm, ym,
                                       zm, A.qV * wgt, nvx, nvy, nvz, g, A.acc);
     }
     store4(A.cell, b4, end, full, ca);
@@ -1115,12 +1183,18 @@ void k_gather_push(PushArgs A) {
     store4(A.ux, b4, end, full, ux);
     store4(A.uy, b4, end, full, uy);
     store4(A.uz, b4, end, full, uz);
+    if (A.perm) store4(A.wo, b4, end, full, pw);
     // the next step's particles arrive during the flushes below
-    if (h + 4 < PPT) load_group<NDIM>(A, b4 + 256, end, step_full(h + 4), wq, cur);
-    if (DEP) home_flush(H, win);
+    if (h + 4 < PPT) {
+      if (A.perm)
+        load_group_perm<NDIM>(A, b4 + 256, end, step_full(h + 4), cur);
+      else
+        load_group<NDIM>(A, b4 + 256, end, step_full(h + 4), wq, cur);
+    }
+    if (DEP) home_flush(H, wl);
     if (cnt_on) count_flush<NDIM>(chome, nstay, s_cnt);
   }
-  if (DEP) queue_drain<NDIM, SHAPE>(Q, win);
+  if (DEP) queue_drain<NDIM, SHAPE>(Q, wl);
   if (want_diag) {
     const double hm = 0.5 * A.ms;
     double v[4] = {hm * dK, hm * dP0, hm * dP1, hm * dP2};
@@ -1138,6 +1212,7 @@ template <int NDIM, int SHAPE>
 __global__ __launch_bounds__(kBlock) void k_deposit(DepArgs A) {
   constexpr int PPT = Chunk<NDIM>::PPT;
   __shared__ double win[DWin<NDIM>::LEN];
+  __shared__ uint8_t s_wrap[DWin<NDIM>::NB * DWin<NDIM>::SW];
   __shared__ float s_q[kBlock / 64 * Queue<NDIM>::QCAP * Queue<NDIM>::QW];
   __shared__ int s_c[2];
   const Geo& g = A.g;
@@ -1151,8 +1226,9 @@ __global__ __launch_bounds__(kBlock) void k_deposit(DepArgs A) {
   const int c0 = s_c[0], span = s_c[1] - s_c[0];
   int W = 0;
   const bool wok = window_ok<NDIM>(c0, s_c[1], g, W);
-  if (wok) dwin_zero<NDIM>(win, W);
+  if (wok) dwin_init<NDIM>(win, s_wrap, W, c0, g);
   __syncthreads();
+  const WinLds wl{win, s_wrap};
   Home<NDIM, SHAPE> H;
   home_clear(H);
   Queue<NDIM> Q;
@@ -1195,12 +1271,12 @@ __global__ __launch_bounds__(kBlock) void k_deposit(DepArgs A) {
       }
       const int rel = a - c0;
       const bool inwin = wok && rel >= 0 && rel <= span;
-      deposit_particle<NDIM, SHAPE>(H, Q, win, live, inwin, rel, i, j, k, mx, my, mz, x, y, z,
+      deposit_particle<NDIM, SHAPE>(H, Q, wl, live, inwin, rel, i, j, k, mx, my, mz, x, y, z,
                                     A.qV * pw[q], ux[q], uy[q], uz[q], g, A.acc);
     }
-    home_flush(H, win);
+    home_flush(H, wl);
   }
-  queue_drain<NDIM, SHAPE>(Q, win);
+  queue_drain<NDIM, SHAPE>(Q, wl);
   if (wok) {
     __syncthreads();
     dwin_flush<NDIM>(win, W, c0, g, A.acc);
@@ -1308,9 +1384,13 @@ void moments_out(hvpic_ctx* c, float* n, float* J, int nparts = 0, double* diag_
                      c->ncell, n, J, (const double*)c->push_part, nparts, diag_out);
 }
 
-int launch_gather_push(hvpic_ctx* c, hvpic_particles* p, const int32_t* cell_start,
-                       const float* E, const float* B, float* n_mid, float* J_mid,
-                       double* diag_out) {
+namespace {
+
+// The push of store `in` read through `perm` (null: in place, in == out) into
+// store `out`.
+int launch_push(hvpic_ctx* c, const hvpic_particles* in, const int32_t* perm,
+                hvpic_particles* p, const int32_t* cell_start, const float* E, const float* B,
+                float* n_mid, float* J_mid, double* diag_out) {
   const bool dep = n_mid != nullptr && J_mid != nullptr;
   c->cnt_ready = false;
   if (p->n == 0) {
@@ -1340,9 +1420,19 @@ int launch_gather_push(hvpic_ctx* c, hvpic_particles* p, const int32_t* cell_sta
   A.ms = c->p.ms;
   A.diag_part = diag_out ? c->push_part : nullptr;
   A.st = c->status;
-  A.vec = particles_aligned16(p);
+  A.vec = particles_aligned16(p) && ((uintptr_t)perm & 15) == 0;
   A.cs = cell_start;
   A.cnt = c->sort_cnt;
+  A.perm = perm;
+  A.icell = in->cell;
+  A.iox = in->ox;
+  A.ioy = in->oy;
+  A.ioz = in->oz;
+  A.iux = in->ux;
+  A.iuy = in->uy;
+  A.iuz = in->uz;
+  A.iw = in->w;
+  A.wo = p->w;
   if (cell_start != nullptr && !c->cnt_clean) zero_counts(c);
   const bool qs = c->p.shape == HVPIC_SHAPE_QS;
   int nblocks = 0;
@@ -1370,6 +1460,21 @@ int launch_gather_push(hvpic_ctx* c, hvpic_particles* p, const int32_t* cell_sta
     hipLaunchKernelGGL(k_push_diag_final, dim3(1), dim3(1024), 0, c->stream,
                        (const double*)c->push_part, nblocks, diag_out);
   return hipGetLastError() == hipSuccess ? HVPIC_OK : HVPIC_EHIP;
+}
+
+}  // namespace
+
+int launch_gather_push(hvpic_ctx* c, hvpic_particles* p, const int32_t* cell_start,
+                       const float* E, const float* B, float* n_mid, float* J_mid,
+                       double* diag_out) {
+  return launch_push(c, p, nullptr, p, cell_start, E, B, n_mid, J_mid, diag_out);
+}
+
+int launch_gather_push_perm(hvpic_ctx* c, const hvpic_particles* in, const int32_t* perm,
+                            hvpic_particles* out, const int32_t* cell_start, const float* E,
+                            const float* B, float* n_mid, float* J_mid, double* diag_out) {
+  out->n = in->n;
+  return launch_push(c, in, perm, out, cell_start, E, B, n_mid, J_mid, diag_out);
 }
 
 int launch_deposit(hvpic_ctx* c, const hvpic_particles* p, const int32_t* cell_start,

@@ -357,7 +357,9 @@ __global__ __launch_bounds__(kBlock) void k_nb_bases(uint32_t* __restrict__ cnt,
 
 struct Fields {
   int32_t* cell;
-  float* f[7];  // ox, oy, oz, ux, uy, uz, w (oz may be null)
+  float* f[7];    // ox, oy, oz, ux, uy, uz, w (oz may be null)
+  int32_t* perm;  // output only: if set, the order is written as this gather
+                  // map (sorted position -> input index) and nothing else moves
 };
 
 // ------------------------------------------------------------- radix path --
@@ -411,10 +413,14 @@ __device__ void gather_fields(const uint32_t* keys, const uint32_t* perm, int64_
     for (int c = kprev + 1; c <= knext && c <= ncell; ++c) cs[c] = (int32_t)r;
     if (r < n) {
       const uint32_t src = perm ? perm[r] : (uint32_t)r;
-      out.cell[r] = in.cell[src];
+      if (out.perm) {
+        out.perm[r] = (int32_t)src;
+      } else {
+        out.cell[r] = in.cell[src];
 #pragma unroll
-      for (int f = 0; f < 7; ++f)
-        if (in.f[f]) out.f[f][r] = in.f[f][src];
+        for (int f = 0; f < 7; ++f)
+          if (in.f[f]) out.f[f][r] = in.f[f][src];
+      }
     }
   }
 }
@@ -621,7 +627,7 @@ __global__ __launch_bounds__(kBlock) void k_nb_scatter(const int32_t* __restrict
      const bool v = p < pe;
      keys[b] = v ? in.cell[p] : 0;
 #pragma unroll
-     for (int f = 0; f < 7; ++f) vals[b][f] = (v && in.f[f]) ? in.f[f][p] : 0.0f;
+     for (int f = 0; f < 7; ++f) vals[b][f] = (v && in.f[f] && !out.perm) ? in.f[f][p] : 0.0f;
    }
 #pragma unroll
    for (int b = 0; b < kScatterBatches; ++b) {
@@ -651,10 +657,14 @@ __global__ __launch_bounds__(kBlock) void k_nb_scatter(const int32_t* __restrict
     if (ok && before == 0) s_next[wid][slot] += (uint32_t)__builtin_popcountll(mine);
     __builtin_amdgcn_wave_barrier();
     if (ok && dst < n) {
-      out.cell[dst] = key;
+      if (out.perm) {
+        out.perm[dst] = (int32_t)p;
+      } else {
+        out.cell[dst] = key;
 #pragma unroll
-      for (int f = 0; f < 7; ++f)
-        if (in.f[f]) out.f[f][dst] = vals[b][f];
+        for (int f = 0; f < 7; ++f)
+          if (in.f[f]) out.f[f][dst] = vals[b][f];
+      }
     }
    }
   }
@@ -670,6 +680,7 @@ Fields fields_of(const hvpic_particles* p) {
   f.f[4] = p->uy;
   f.f[5] = p->uz;
   f.f[6] = p->w;
+  f.perm = nullptr;
   return f;
 }
 
@@ -690,7 +701,7 @@ int radix_bits(int ncell) {
   return b;
 }
 
-void enqueue_radix(hvpic_ctx* c, const hvpic_particles* in, hvpic_particles* out, int32_t* cs) {
+void enqueue_radix(hvpic_ctx* c, const hvpic_particles* in, const Fields& out, int32_t* cs) {
   hipStream_t s = c->stream;
   const int64_t n = in->n;
   const int ncell = c->ncell;
@@ -718,11 +729,11 @@ void enqueue_radix(hvpic_ctx* c, const hvpic_particles* in, hvpic_particles* out
   }
   const int fblocks = (int)std::min<int64_t>(ceil_div(n + 1, kBlock), 65536);
   hipLaunchKernelGGL(k_radix_final, dim3(fblocks), dim3(kBlock), 0, s, kin, vin, n, fields_of(in),
-                     fields_of(out), cs, ncell);
+                     out, cs, ncell);
 }
 
 template <int NDIM>
-void enqueue_neighbour(hvpic_ctx* c, const hvpic_particles* in, hvpic_particles* out,
+void enqueue_neighbour(hvpic_ctx* c, const hvpic_particles* in, const Fields& out,
                        const int32_t* cs_prev, int32_t* cs) {
   hipStream_t s = c->stream;
   const SortGeo g = sort_geo(c);
@@ -752,16 +763,17 @@ void enqueue_neighbour(hvpic_ctx* c, const hvpic_particles* in, hvpic_particles*
   timing_begin(c, HVPIC_KERNEL_SORT_SCATTER);
   const int sblocks = (int)ceil_div(c->ncell, kWaves * kScatterCells);
   hipLaunchKernelGGL((k_nb_scatter<NDIM>), dim3(sblocks), dim3(kBlock), 0, s, cs_prev, in->n, g,
-                     c->sort_cnt, fields_of(in), fields_of(out), cs,
+                     c->sort_cnt, fields_of(in), out, cs,
                      (const Status*)c->status, c->rkey[0], c->rkey[1], c->rval[0], c->rval[1]);
   timing_end(c, HVPIC_KERNEL_SORT_SCATTER);
 }
 
 }  // namespace
 
-int launch_sort(hvpic_ctx* c, const hvpic_particles* in, hvpic_particles* out,
-                const int32_t* cs_prev, int32_t* cs, int full) {
-  out->n = in->n;
+namespace {
+
+int sort_to(hvpic_ctx* c, const hvpic_particles* in, const Fields& out, const int32_t* cs_prev,
+            int32_t* cs, int full) {
   if (full || cs_prev == nullptr) {
     enqueue_radix(c, in, out, cs);
   } else if (c->p.ndim == 2) {
@@ -773,6 +785,21 @@ int launch_sort(hvpic_ctx* c, const hvpic_particles* in, hvpic_particles* out,
   }
   c->cnt_ready = false;
   return hipGetLastError() == hipSuccess ? HVPIC_OK : HVPIC_EHIP;
+}
+
+}  // namespace
+
+int launch_sort(hvpic_ctx* c, const hvpic_particles* in, hvpic_particles* out,
+                const int32_t* cs_prev, int32_t* cs, int full) {
+  out->n = in->n;
+  return sort_to(c, in, fields_of(out), cs_prev, cs, full);
+}
+
+int launch_sort_perm(hvpic_ctx* c, const hvpic_particles* in, const int32_t* cs_prev,
+                     int32_t* perm, int32_t* cs) {
+  Fields out{};
+  out.perm = perm;
+  return sort_to(c, in, out, cs_prev, cs, 0);
 }
 
 }  // namespace hvpic

@@ -22,7 +22,8 @@ HVPIC_SHAPE_NGP, HVPIC_SHAPE_QS = 0, 1
 FLAG_MOVE_GT1, FLAG_FLOOR_HIT, FLAG_NONFINITE, FLAG_BAD_INPUT = 1, 2, 4, 8
 
 EXPORTS = ("hvpic_workspace_bytes", "hvpic_init", "hvpic_finalize", "hvpic_gather_push",
-           "hvpic_sort", "hvpic_deposit", "hvpic_field_advance", "hvpic_smooth",
+           "hvpic_gather_push_perm", "hvpic_sort", "hvpic_sort_perm", "hvpic_deposit",
+           "hvpic_field_advance", "hvpic_smooth",
            "hvpic_sync_status", "hvpic_timing_enable", "hvpic_timing_read", "hvpic_strerror")
 KERNEL_GATHER_PUSH, KERNEL_DEPOSIT, KERNEL_SORT_SCATTER = 0, 1, 2
 
@@ -65,7 +66,10 @@ def lib():
         L.hvpic_init.argtypes = [P(HvpicParams), vp, vp, P(vp)]
         L.hvpic_finalize.argtypes = [vp]
         L.hvpic_gather_push.argtypes = [vp, P(HvpicParticles), vp, vp, vp, vp, vp, vp]
+        L.hvpic_gather_push_perm.argtypes = [vp, P(HvpicParticles), vp, P(HvpicParticles), vp, vp,
+                                             vp, vp, vp, vp]
         L.hvpic_sort.argtypes = [vp, P(HvpicParticles), P(HvpicParticles), vp, vp, i32]
+        L.hvpic_sort_perm.argtypes = [vp, P(HvpicParticles), vp, vp, vp]
         L.hvpic_deposit.argtypes = [vp, P(HvpicParticles), vp, ctypes.c_float, vp, vp]
         L.hvpic_field_advance.argtypes = [vp, vp, vp, vp, vp, vp, vp, i32, vp]
         L.hvpic_smooth.argtypes = [vp, vp, i32, i32]
@@ -193,6 +197,31 @@ def hvpic_gather_push(ctx, p: Particles, cell_start, E, B, n_mid=None, J_mid=Non
                                    _ptr(J_mid, torch.float32, _nc(ctx, 3)),
                                    _ptr(diag_out, torch.float64, 4)),
            "hvpic_gather_push")
+
+
+def hvpic_gather_push_perm(ctx, pin: Particles, perm, pout: Particles, cell_start, E, B,
+                           n_mid=None, J_mid=None, diag_out=None):
+    ci, co = pin.c(), pout.c()
+    if pout.capacity < pin.n:
+        raise HvpicError("output store too small")
+    ncs = None if _nc(ctx) is None else _nc(ctx) + 1
+    _check(lib().hvpic_gather_push_perm(ctx, ctypes.byref(ci), _ptr(perm, torch.int32, pin.n),
+                                        ctypes.byref(co), _ptr(cell_start, torch.int32, ncs),
+                                        _ptr(E, torch.float32, _nc(ctx, 3)),
+                                        _ptr(B, torch.float32, _nc(ctx, 3)),
+                                        _ptr(n_mid, torch.float32, _nc(ctx)),
+                                        _ptr(J_mid, torch.float32, _nc(ctx, 3)),
+                                        _ptr(diag_out, torch.float64, 4)),
+           "hvpic_gather_push_perm")
+    pout.n = co.n
+
+
+def hvpic_sort_perm(ctx, pin: Particles, cell_start_prev, perm, cell_start):
+    ci = pin.c()
+    ncs = None if _nc(ctx) is None else _nc(ctx) + 1
+    _check(lib().hvpic_sort_perm(ctx, ctypes.byref(ci), _ptr(cell_start_prev, torch.int32, ncs),
+                                 _ptr(perm, torch.int32, pin.n),
+                                 _ptr(cell_start, torch.int32, ncs)), "hvpic_sort_perm")
 
 
 def hvpic_sort(ctx, pin: Particles, pout: Particles, cell_start_prev, cell_start, full=False):

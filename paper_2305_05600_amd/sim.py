@@ -18,6 +18,14 @@ stream and context, ordered by events: it waits for the moments of step 1,
 and the next push waits for its E and B.  The sort and the latency-bound
 field kernels then share the GPU.
 
+With `gather_map` (fused deposit only) the sort leaves the stable order as a
+gather map instead of moving the store (hvpic_sort_perm), and the next push
+reads the store through it and writes the pushed particles in sorted order
+to the other buffer (hvpic_gather_push_perm): the particle data then crosses
+HBM once per step instead of twice.  The state is the store `p` plus `perm`;
+particles() returns it in sorted order.  Results are bit-identical to the
+plain sequence.
+
 Initialisation (the paper leaves the first half step open): v^{-1/2} = v^0,
 and n^{-1/2}, J^{-1/2} are the moments deposited at x^0, so E^0 = Ohm(B^0,
 n^0, J^0).  This module only orders the calls and swaps buffers.
@@ -32,9 +40,12 @@ from . import hvpic as H
 
 class GpuSim:
     def __init__(self, cfg, parts: dict, B: np.ndarray, fused: bool = True, device="cuda",
-                 diagnostics: bool = True, overlap: bool = True):
+                 diagnostics: bool = True, overlap: bool = True, gather_map: bool = False):
+        if gather_map and not fused:
+            raise ValueError("gather_map needs the fused deposit")
         self.cfg = cfg
         self.fused = fused
+        self.gather_map = gather_map
         self.device = device
         self.overlap = overlap
         n = int(parts["cell"].size)
@@ -72,20 +83,28 @@ class GpuSim:
         # first sort of an arbitrary order
         H.hvpic_sort(c, self.p, self.q, None, self.cs, full=True)
         self.p, self.q = self.q, self.p
+        # the sorted store read through the identity map
+        self.perm = (torch.arange(max(n, 1), dtype=torch.int32, device=device)
+                     if gather_map else None)
         H.hvpic_deposit(c, self.p, self.cs, 0.0, self.n_prev, self.J_prev)
+        self._moments_ready()
         self._fields_after_moments(mode=1, n_half=self.n_prev, J_half=self.J_prev)
         self.nstep = 0
         cur = torch.cuda.current_stream(device)
         cur.wait_stream(self.s_p)
         cur.wait_stream(self.s_f)
 
+    def _moments_ready(self):
+        """Marks the moments of the step as written (on the particle stream)."""
+        if self.s_f is not self.s_p:
+            self.ev_moments.record(self.s_p)
+
     def _fields_after_moments(self, mode, n_half, J_half):
         """Smoothing of the moments and the field advance, on the field stream
-        once the moments are there."""
+        once the moments are there (_moments_ready before)."""
         cfg = self.cfg
         cf = self.ctx_f.ctx
         if self.s_f is not self.s_p:
-            self.ev_moments.record(self.s_p)
             self.s_f.wait_event(self.ev_moments)
         if cfg.nsmooth:
             H.hvpic_smooth(cf, n_half, cfg.nsmooth)
@@ -116,17 +135,30 @@ class GpuSim:
             H.hvpic_smooth(c, self.B_s, cfg.nsmooth)
             E, B = self.E_s, self.B_s
         pd = self.push_diag if self.diagnostics else None
-        if self.fused:
+        if self.gather_map:
+            # p read through perm -> q in sorted order; then the map of the
+            # next order over q
+            H.hvpic_gather_push_perm(c, self.p, self.perm, self.q, self.cs, E, B, self.n_half,
+                                     self.J_half, pd)
+            self._moments_ready()
+            H.hvpic_sort_perm(c, self.q, self.cs, self.perm, self.cs_alt)
+            self.p, self.q = self.q, self.p
+            self.cs, self.cs_alt = self.cs_alt, self.cs
+        elif self.fused:
             H.hvpic_gather_push(c, self.p, self.cs, E, B, self.n_half, self.J_half, pd)
-            self._fields_after_moments(mode=0, n_half=self.n_half, J_half=self.J_half)
+            self._moments_ready()
         else:
             H.hvpic_gather_push(c, self.p, self.cs, E, B, None, None, pd)
-        H.hvpic_sort(c, self.p, self.q, self.cs, self.cs_alt, full=False)
-        self.p, self.q = self.q, self.p
-        self.cs, self.cs_alt = self.cs_alt, self.cs
+        if not self.gather_map:
+            # the sort is enqueued before the field work, so that the field
+            # stream's launches do not hold back the particle stream's
+            H.hvpic_sort(c, self.p, self.q, self.cs, self.cs_alt, full=False)
+            self.p, self.q = self.q, self.p
+            self.cs, self.cs_alt = self.cs_alt, self.cs
         if not self.fused:
             H.hvpic_deposit(c, self.p, self.cs, 0.5 * cfg.dt, self.n_half, self.J_half)
-            self._fields_after_moments(mode=0, n_half=self.n_half, J_half=self.J_half)
+            self._moments_ready()
+        self._fields_after_moments(mode=0, n_half=self.n_half, J_half=self.J_half)
         self.n_prev, self.n_half = self.n_half, self.n_prev
         self.J_prev, self.J_half = self.J_half, self.J_prev
         self.nstep += 1
@@ -154,5 +186,10 @@ class GpuSim:
         return flags, counts
 
     def particles(self) -> dict:
+        """The particle store in sorted order (host copy)."""
         self.synchronize()
-        return self.p.to_numpy()
+        d = self.p.to_numpy()
+        if self.gather_map:
+            idx = self.perm[:self.p.n].cpu().numpy()
+            d = {k: v[idx] for k, v in d.items()}
+        return d

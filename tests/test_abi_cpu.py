@@ -68,6 +68,9 @@ def test_init_rejects_bad_arguments_without_device_work(H):
         == H.HVPIC_EINVAL  # misaligned workspace
     assert L.hvpic_gather_push(None, None, None, None, None, None, None, None) == H.HVPIC_ESTATE
     assert L.hvpic_sort(None, None, None, None, None, 0) == H.HVPIC_ESTATE
+    assert L.hvpic_sort_perm(None, None, None, None, None) == H.HVPIC_ESTATE
+    assert L.hvpic_gather_push_perm(None, None, None, None, None, None, None, None, None,
+                                    None) == H.HVPIC_ESTATE
     assert L.hvpic_finalize(None) == H.HVPIC_ESTATE
     assert H.hvpic_strerror(H.HVPIC_EINVAL) == "invalid argument"
     assert L.hvpic_timing_enable(None, 4) == H.HVPIC_ESTATE

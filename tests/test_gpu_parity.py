@@ -183,6 +183,90 @@ def test_neighbour_sort_after_push(H, name, cfg, far, counted):
     _check_sorted(cfg, pushed, q.to_numpy(), cs.cpu().numpy())
 
 
+@pytest.mark.parametrize("name,cfg", CASES)
+@pytest.mark.parametrize("path", ["neighbour", "neighbour-counted", "far", "general"])
+def test_sort_perm(H, name, cfg, path):
+    """The gather-map form of the sort is the oracle's stable order itself
+    (the permutation of a stable sort is unique) with the same cell_start, on
+    the neighbour path (with or without the push's counts), on the fallback
+    for a far mover, and on the general path."""
+    announce("sort_perm", name, path)
+    _, parts, B = W.random_box(63, cfg, 20.0, vmax_cells=0.95)
+    parts, cs0 = _sorted(cfg, parts)
+    if path == "far":
+        parts["ux"][len(parts["ux"]) // 3] = np.float32(2.5 * cfg.dx / cfg.dt)
+    E = W.random_field(64, cfg, 0.01)
+    n = parts["cell"].size
+    ctx = H.Context(cfg, n)
+    p = H.Particles.from_numpy(parts, cfg.ndim)
+    cs_prev = dev(cs0, np.int32)
+    cs = torch.zeros(cfg.ncell + 1, dtype=torch.int32, device="cuda")
+    perm = torch.full((n,), -1, dtype=torch.int32, device="cuda")
+    H.hvpic_gather_push(ctx.ctx, p, cs_prev if path == "neighbour-counted" else None, dev(E),
+                        dev(B))
+    pushed = p.to_numpy()
+    H.hvpic_sort_perm(ctx.ctx, p, None if path == "general" else cs_prev, perm, cs)
+    flags, _ = H.hvpic_sync_status(ctx.ctx)
+    rperm, rcs = O.sort(cfg, pushed["cell"])
+    assert np.array_equal(perm.cpu().numpy(), rperm)
+    assert np.array_equal(cs.cpu().numpy(), rcs)
+    assert bool(flags & H.FLAG_MOVE_GT1) == (path == "far")
+    # nothing but the map and cell_start was written
+    for k, v in p.to_numpy().items():
+        assert np.array_equal(v, pushed[k]), k
+
+
+@pytest.mark.parametrize("name,cfg", CASES)
+@pytest.mark.parametrize("fused", [False, True])
+def test_gather_push_perm(H, name, cfg, fused):
+    """The push through a gather map equals the sort into a store followed by
+    the push of that store, bit for bit: particles, moments, diagnostics, and
+    the move counts (through the next sort of each)."""
+    announce("gather_push_perm", name, fused)
+    _, parts, B = W.random_box(65, cfg, 9.0, vmax_cells=0.9)
+    E = W.random_field(66, cfg, 0.05)
+    n = parts["cell"].size
+    Ed, Bd = dev(E), dev(B)
+    z = lambda *shape: torch.zeros(*shape, dtype=torch.float32, device="cuda")
+    cs = torch.zeros(cfg.ncell + 1, dtype=torch.int32, device="cuda")
+    runs = {}
+    for mode in ("plain", "perm"):
+        ctx = H.Context(cfg, n)
+        p = H.Particles.from_numpy(parts, cfg.ndim)
+        q = H.Particles(cfg.ndim, n)
+        r = H.Particles(cfg.ndim, n)
+        diag = torch.zeros(4, dtype=torch.float64, device="cuda")
+        nm, Jm = (z(cfg.ncell), z(3, cfg.ncell)) if fused else (None, None)
+        cs1 = torch.zeros_like(cs)
+        if mode == "plain":
+            H.hvpic_sort(ctx.ctx, p, q, None, cs, full=True)
+            H.hvpic_gather_push(ctx.ctx, q, cs, Ed, Bd, nm, Jm, diag)
+            H.hvpic_sort(ctx.ctx, q, r, cs, cs1, full=False)
+            out = q.to_numpy()
+            nxt = r.to_numpy()
+        else:
+            perm = torch.empty(n, dtype=torch.int32, device="cuda")
+            H.hvpic_sort_perm(ctx.ctx, p, None, perm, cs)
+            H.hvpic_gather_push_perm(ctx.ctx, p, perm, q, cs, Ed, Bd, nm, Jm, diag)
+            perm1 = torch.empty(n, dtype=torch.int32, device="cuda")
+            H.hvpic_sort_perm(ctx.ctx, q, cs, perm1, cs1)
+            out = q.to_numpy()
+            idx = perm1.cpu().numpy()
+            nxt = {k: v[idx] for k, v in out.items()}
+        flags, _ = H.hvpic_sync_status(ctx.ctx)
+        runs[mode] = (out, nxt, cs1.cpu().numpy(), diag.cpu().numpy(),
+                      None if nm is None else (nm.cpu().numpy(), Jm.cpu().numpy()), flags)
+    a, b = runs["plain"], runs["perm"]
+    for k in a[0]:
+        assert np.array_equal(a[0][k], b[0][k]), k
+        assert np.array_equal(a[1][k], b[1][k]), k
+    assert np.array_equal(a[2], b[2])
+    assert np.array_equal(a[3], b[3])
+    if fused:
+        assert np.array_equal(a[4][0], b[4][0]) and np.array_equal(a[4][1], b[4][1])
+    assert a[5] == b[5] == 0
+
+
 @pytest.mark.parametrize("name,cfg", [CASES[0], CASES[2]])
 @pytest.mark.parametrize("mode", [0, 1])
 @pytest.mark.parametrize("gamma", [1.0, 5.0 / 3.0])
