@@ -329,12 +329,34 @@ def test_empty_and_single(H):
     assert flags == 0
     assert np.all(diag.cpu().numpy() == 0) and np.all(cs2.cpu().numpy() == 0)
     assert float(n.abs().sum()) == 0 and float(J.abs().sum()) == 0
+    # the gather-map forms on the empty store
+    perm = torch.full((4,), -1, dtype=torch.int32, device="cuda")
+    cs3 = torch.full((cfg.ncell + 1,), -1, dtype=torch.int32, device="cuda")
+    H.hvpic_sort_perm(ctx.ctx, p, None, perm, cs3)
+    diag.fill_(9.0)
+    n.fill_(1.0)
+    H.hvpic_gather_push_perm(ctx.ctx, p, perm, q, cs3, E, E, n, J, diag)
+    flags, _ = H.hvpic_sync_status(ctx.ctx)
+    assert flags == 0 and q.n == 0
+    assert np.all(diag.cpu().numpy() == 0) and np.all(cs3.cpu().numpy() == 0)
+    assert float(n.abs().sum()) == 0 and float(J.abs().sum()) == 0
     announce("single")
     one = {k: v[:1] for k, v in W.random_box(3, cfg, 1.0)[1].items()}
     p = H.Particles.from_numpy(one, 2, capacity=4)
     H.hvpic_sort(ctx.ctx, p, q, None, cs, full=True)
     got = cs.cpu().numpy()
     assert got[0] == 0 and got[-1] == 1 and np.all(np.diff(got) >= 0)
+    # one particle through the map equals the in-place push of the sorted copy
+    H.hvpic_sort_perm(ctx.ctx, p, None, perm, cs3)
+    assert perm.cpu().numpy()[0] == 0 and np.array_equal(cs3.cpu().numpy(), got)
+    r = H.Particles(2, 4)
+    Bf = dev(W.random_field(4, cfg, 0.3, (0.2, 0.1, 1.0)))
+    Ef = dev(W.random_field(5, cfg, 0.1))
+    H.hvpic_gather_push_perm(ctx.ctx, p, perm, r, cs3, Ef, Bf)
+    H.hvpic_gather_push(ctx.ctx, q, cs, Ef, Bf)
+    a, b = q.to_numpy(), r.to_numpy()
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
 
 
 @pytest.mark.parametrize("nx,ny", [(1, 5), (2, 3), (3, 1)])
