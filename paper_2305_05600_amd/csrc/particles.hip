@@ -99,6 +99,18 @@ struct DepArgs {
   bool vec;
 };
 
+// Chunk of the store for hardware block b of nb.  The GPU hands blocks out
+// round-robin over its 8 XCDs, each with its own L2, so XCD x takes a
+// contiguous eighth of the chunks: blocks working on neighbouring rows of
+// cells (the stencil halos, the deposit windows, particles read from the
+// next row over) then share one L2.  A bijection of [0, nb).
+__device__ __forceinline__ int xcd_chunk(int b, int nb) {
+  constexpr int X = 8;
+  const int per = nb / X, rem = nb % X;
+  const int x = b % X, i = b / X;
+  return x * per + min(x, rem) + i;
+}
+
 __device__ __forceinline__ void decompose(int a, const Geo& g, int& i, int& j, int& k) {
   uint32_t q = fdiv((uint32_t)a, g.fnx);
   i = a - (int)q * g.nx;
@@ -1012,7 +1024,7 @@ void k_gather_push(PushArgs A) {
   __shared__ int32_t s_cs[Chunk<NDIM>::WMAX + 1];
   __shared__ int s_c[2];
   const Geo& g = A.g;
-  const int64_t base = (int64_t)blockIdx.x * Chunk<NDIM>::N;
+  const int64_t base = (int64_t)xcd_chunk(blockIdx.x, gridDim.x) * Chunk<NDIM>::N;
   const int64_t end = min(base + (int64_t)Chunk<NDIM>::N, A.n);
   if (threadIdx.x == 0) {
     if (A.perm) {
@@ -1216,7 +1228,7 @@ __global__ __launch_bounds__(kBlock) void k_deposit(DepArgs A) {
   __shared__ float s_q[kBlock / 64 * Queue<NDIM>::QCAP * Queue<NDIM>::QW];
   __shared__ int s_c[2];
   const Geo& g = A.g;
-  const int64_t base = (int64_t)blockIdx.x * Chunk<NDIM>::N;
+  const int64_t base = (int64_t)xcd_chunk(blockIdx.x, gridDim.x) * Chunk<NDIM>::N;
   const int64_t end = min(base + (int64_t)Chunk<NDIM>::N, A.n);
   if (threadIdx.x == 0) {
     s_c[0] = A.cell[base];
