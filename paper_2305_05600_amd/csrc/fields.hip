@@ -10,14 +10,17 @@
 //   full step as 3/2 (n+1/2) - 1/2 (n-1/2); gradients are centred differences
 //   on the cell-centred grid.
 //
-// The moments are frozen during the subcycle, so one prep kernel forms
-// 1/n_f (in FP64), u_i and -grad(p_e)/n_f once per step.  In 2D one kernel
-// runs a whole RK2 substep on LDS tiles with a 4-cell halo (B -> Ea -> B* ->
-// Eb -> B); in 3D each RK2 stage is one kernel that evaluates Ohm's law at the
-// 2*ndim neighbours of a cell and takes the curl.  E is never stored inside
-// the subcycle.  B is carried as an unevaluated sum hi + lo so that the many
-// small substep updates keep their low bits.  The grids fit in the MI355X
-// L2/MALL during the subcycle, so the substeps are latency-bound.
+// The moments are frozen during the subcycle, so the terms that depend on them
+// alone (1/n_f in FP64, u_i and -grad(p_e)/n_f) are formed once per cell.  In
+// 2D one kernel runs two whole RK2 substeps on an LDS tile with an 8-cell halo
+// (B -> Ea -> B* -> Eb -> B, twice), forming those terms on its own halo; in
+// 3D a prep kernel stores them and each RK2 stage is one kernel that evaluates
+// Ohm's law at the 2*ndim neighbours of a cell and takes the curl.  E is never
+// stored inside the subcycle.  B is carried as an unevaluated sum hi + lo so
+// that the many small substep updates keep their low bits.  One last kernel
+// writes E from the extrapolated moments, the final B and the diagnostics.
+// The grids fit in the MI355X L2/MALL during the subcycle, so the substeps are
+// latency-bound: fewer, larger launches are what shortens them.
 #include "hvpic_internal.hpp"
 
 namespace hvpic {
@@ -59,16 +62,18 @@ __device__ __forceinline__ Nbr neighbours(int c, int i, int j, int k, const FGeo
   return n;
 }
 
-// B held as an unevaluated sum hi + lo (lo may be null): the compensation
-// term carries the low bits that the subcycle's small updates would round away.
-struct BPair {
+// B held as an unevaluated sum hi + lo (HAS_LO; otherwise hi alone): the
+// compensation term carries the low bits that the subcycle's small updates
+// would round away.
+template <bool HAS_LO>
+struct BSum {
   const float* hi;
   const float* lo;
-  __device__ __forceinline__ float operator()(int q) const { return lo ? hi[q] + lo[q] : hi[q]; }
+  __device__ __forceinline__ float operator()(int q) const { return HAS_LO ? hi[q] + lo[q] : hi[q]; }
 };
 
-template <int NDIM>
-__device__ __forceinline__ void curl_at(BPair A, int c, const FGeo& g, float out[3]) {
+template <int NDIM, class BA>
+__device__ __forceinline__ void curl_at(BA A, int c, const FGeo& g, float out[3]) {
   int i, j, k;
   fijk(c, g, i, j, k);
   const Nbr n = neighbours(c, i, j, k, g);
@@ -88,8 +93,8 @@ __device__ __forceinline__ void curl_at(BPair A, int c, const FGeo& g, float out
 }
 
 // Ohm's law at cell c with the frozen-moment terms precomputed in aux.
-template <int NDIM>
-__device__ __forceinline__ void ohm_at(BPair B, const Aux& aux, float eta, int c, const FGeo& g,
+template <int NDIM, class BA>
+__device__ __forceinline__ void ohm_at(BA B, const Aux& aux, float eta, int c, const FGeo& g,
                                        float E[3]) {
   const int nc = g.ncell;
   float J[3];
@@ -117,19 +122,15 @@ __global__ __launch_bounds__(kBlock) void k_field_prep(const float* __restrict__
                                                        const float* __restrict__ Ja,
                                                        const float* __restrict__ Jb, float ca,
                                                        float cb, FGeo g, float nfloor, float te_n0,
-                                                       float n0, float gam, int iso, Aux aux,
-                                                       Status* st, int count_floor) {
+                                                       float n0, float gam, int iso, Aux aux) {
   const int c = blockIdx.x * kBlock + threadIdx.x;
-  const bool live = c < g.ncell;
-  bool below = false;
-  if (live) {
+  if (c < g.ncell) {
     const int nc = g.ncell;
     int i, j, k;
     fijk(c, g, i, j, k);
     const Nbr nn = neighbours(c, i, j, k, g);
     auto dens = [&](int q) { return nb ? ca * na[q] + cb * nb[q] : na[q]; };
     const float n = dens(c);
-    below = n < nfloor;
     const float nf = fmaxf(n, nfloor);
     const float inv = (float)(1.0 / (double)nf);
     aux.inv[c] = inv;
@@ -151,13 +152,6 @@ __global__ __launch_bounds__(kBlock) void k_field_prep(const float* __restrict__
     }
     aux.gp[2 * nc + c] = gz;
   }
-  if (count_floor) {
-    const uint64_t m = __ballot(live && below);
-    if ((threadIdx.x & 63) == 0 && m) {
-      atomicOr(&st->flags, (uint32_t)HVPIC_FLAG_FLOOR_HIT);
-      atomicAdd(&st->floor_hits, (unsigned long long)__builtin_popcountll(m));
-    }
-  }
 }
 
 // One RK2 stage: B_dst = B_base - coef * curl(Ohm(B_src)).  With lo non-null
@@ -176,7 +170,7 @@ __global__ __launch_bounds__(kBlock) void k_field_stage(const float* __restrict_
   fijk(c, g, i, j, k);
   const Nbr n = neighbours(c, i, j, k, g);
   float Exp[3], Exm[3], Eyp[3], Eym[3];
-  const BPair Bp{Bsrc, nullptr};
+  const BSum<false> Bp{Bsrc, nullptr};
   ohm_at<NDIM>(Bp, aux, eta, n.xp, g, Exp);
   ohm_at<NDIM>(Bp, aux, eta, n.xm, g, Exm);
   ohm_at<NDIM>(Bp, aux, eta, n.yp, g, Eyp);
@@ -208,164 +202,332 @@ __global__ __launch_bounds__(kBlock) void k_field_stage(const float* __restrict_
 }
 
 
-// One whole RK2 substep for a 2D tile of TX x TY cells with all intermediate
-// fields in LDS: B (halo 4) -> Ea (halo 3) -> B* (halo 2) -> Eb (halo 1) ->
-// B_new on the tile.  Reads Bin, writes Bout (distinct buffers: neighbouring
-// tiles read the halo of Bin while this one writes).
-constexpr int kTX = 32, kTY = 8;
-constexpr int kSubBlock = 512;  // threads per substep tile (8 wavefronts hide the load latency)
-constexpr int kBW = kTX + 8, kBH = kTY + 8;   // B with halo 4
-constexpr int kAW = kTX + 6, kAH = kTY + 6;   // aux and Ea with halo 3
-constexpr int kSW = kTX + 4, kSH = kTY + 4;   // B* with halo 2
-constexpr int kFW = kTX + 2, kFH = kTY + 2;   // Eb with halo 1
+// Equation of state and floor for the frozen-moment terms.
+struct Eos {
+  float nfloor, te_n0, n0, gam;
+  int iso;
+};
 
-__global__ __launch_bounds__(kSubBlock) void k_field_substep2d(const float* __restrict__ Bin,
-                                                            const float* __restrict__ Lin,
-                                                            float* __restrict__ Bout,
-                                                            float* __restrict__ Lout, float h,
-                                                            float eta, FGeo g, Aux aux) {
-  __shared__ float sB[3][kBH * kBW];
-  __shared__ float sA[7][kAH * kAW];
-  __shared__ float sE[3][kAH * kAW];
-  __shared__ float sS[3][kSH * kSW];
+// K whole RK2 substeps for a 2D tile of kTX x kTY cells, all intermediate
+// fields in LDS.  Each substep needs B on a 4-cell halo (B -> Ea on halo 3 ->
+// B* on halo 2 -> Eb on halo 1 -> B_new), so the tile reads B on a 4K halo and
+// recomputes the overlap with its neighbours instead of a launch per substep.
+// The frozen terms (1/n_f, u_i, -grad(p_e)/n_f) are formed here from the
+// moments, on a halo of 4K - 1.  B enters as the sum hi + lo: Ohm's law sees
+// hi only; each substep's increment goes to lo first (compensated sum), over
+// the cells that the next substep reads.  Reads Bin/Lin, writes Bout/Lout
+// (distinct buffers: neighbouring tiles read the halo of Bin while this one
+// writes).
+constexpr int kTX = 32, kTY = 8;
+// 256 threads per tile.  The tile's LDS is sized at launch: with a static
+// size the compiler would pad the VGPR allocation up to the occupancy that
+// the LDS allows (169 per wave instead of the 45 used), and such a tile
+// would not fit in the room that one retiring block of a concurrently
+// running particle kernel leaves.
+constexpr int kSubBlock = 256;
+
+// One LDS plane: the tile with a halo of HALO cells, row-major.
+template <int HALO>
+struct Plane {
+  static constexpr int W = kTX + 2 * HALO, H = kTY + 2 * HALO, N = W * H;
+  __device__ static int at(int lx, int ly) { return (ly + HALO) * W + lx + HALO; }
+};
+
+template <int K>
+struct SubLds {
+  static constexpr int HB = 4 * K;
+  using PB = Plane<HB>;      // B hi (and the pressure while the frozen terms are formed)
+  using PA = Plane<HB - 1>;  // six frozen-term planes, then E (Ea, later Eb)
+  using PS = Plane<HB - 2>;  // B*
+  using PL = Plane<HB - 4>;  // lo over the output region of the first substep
+  static constexpr int B0 = 0, A0 = 3 * PB::N, E0 = A0 + 6 * PA::N, S0 = E0 + 3 * PA::N,
+                       L0 = S0 + 3 * PS::N, TOTAL = L0 + 3 * PL::N;
+  static_assert(3 * PA::N + 3 * PS::N >= PB::N, "pressure plane overlays E and B*");
+};
+
+template <int K, bool HAS_LIN>
+__global__ __launch_bounds__(kSubBlock) void k_field_sub2d(
+    const float* __restrict__ Bin, const float* __restrict__ Lin, float* __restrict__ Bout,
+    float* __restrict__ Lout, const float* __restrict__ nm, const float* __restrict__ Jm, float h,
+    float eta, FGeo g, Eos eos) {
+  using L = SubLds<K>;
+  using PB = typename L::PB;
+  using PA = typename L::PA;
+  using PS = typename L::PS;
+  using PL = typename L::PL;
+  constexpr int HB = L::HB;
+  extern __shared__ float sm[];  // L::TOTAL floats
+  float* sB = sm + L::B0;
+  float* sA = sm + L::A0;
+  float* sE = sm + L::E0;
+  float* sS = sm + L::S0;
+  float* sL = sm + L::L0;
+  float* sP = sE;  // pressure, only until the frozen terms are formed
   const int nc = g.ncell;
   const int tx0 = blockIdx.x * kTX, ty0 = blockIdx.y * kTY;
+  // periodic cell of tile-relative (lx, ly), for any halo width and grid size
   auto gidx = [&](int lx, int ly) {
     int x = tx0 + lx, y = ty0 + ly;
     x %= g.nx; if (x < 0) x += g.nx;
     y %= g.ny; if (y < 0) y += g.ny;
     return x + g.nx * y;
   };
-  for (int t = threadIdx.x; t < kBH * kBW; t += kSubBlock) {
-    const int ly = t / kBW - 4, lx = t % kBW - 4;
-    const int c = gidx(lx, ly);
-    sB[0][t] = Bin[c];
-    sB[1][t] = Bin[nc + c];
-    sB[2][t] = Bin[2 * nc + c];
-  }
-  for (int t = threadIdx.x; t < kAH * kAW; t += kSubBlock) {
-    const int ly = t / kAW - 3, lx = t % kAW - 3;
-    const int c = gidx(lx, ly);
-    sA[0][t] = aux.inv[c];
-    sA[1][t] = aux.u[c];
-    sA[2][t] = aux.u[nc + c];
-    sA[3][t] = aux.u[2 * nc + c];
-    sA[4][t] = aux.gp[c];
-    sA[5][t] = aux.gp[nc + c];
-    sA[6][t] = aux.gp[2 * nc + c];
-  }
-  __syncthreads();
-  // Ohm's law at a cell given B there, curl B there and the aux slot.
-  auto ohm = [&](float b0, float b1, float b2, float j0, float j1, float j2, int a, float* e) {
-    const float inv = sA[0][a];
-    const float w0 = j0 * inv - sA[1][a], w1 = j1 * inv - sA[2][a], w2 = j2 * inv - sA[3][a];
-    e[0] = (w1 * b2 - w2 * b1) + sA[4][a] + eta * j0;
-    e[1] = (w2 * b0 - w0 * b2) + sA[5][a] + eta * j1;
-    e[2] = (w0 * b1 - w1 * b0) + sA[6][a] + eta * j2;
-  };
-  // Ea on the tile with halo 3 (from B with halo 4)
-  for (int t = threadIdx.x; t < kAH * kAW; t += kSubBlock) {
-    const int ly = t / kAW, lx = t % kAW;      // B index = (ly+1, lx+1)
-    const int b = (ly + 1) * kBW + lx + 1;
-    const float j0 = (sB[2][b + kBW] - sB[2][b - kBW]) * g.idy2;
-    const float j1 = -(sB[2][b + 1] - sB[2][b - 1]) * g.idx2;
-    const float j2 = (sB[1][b + 1] - sB[1][b - 1]) * g.idx2 - (sB[0][b + kBW] - sB[0][b - kBW]) * g.idy2;
-    float e[3];
-    ohm(sB[0][b], sB[1][b], sB[2][b], j0, j1, j2, t, e);
-    sE[0][t] = e[0];
-    sE[1][t] = e[1];
-    sE[2][t] = e[2];
-  }
-  __syncthreads();
-  // B* = B - (h/2) curl Ea on the tile with halo 2
-  const float hh = 0.5f * h;
-  for (int t = threadIdx.x; t < kSH * kSW; t += kSubBlock) {
-    const int ly = t / kSW, lx = t % kSW;
-    const int e = (ly + 1) * kAW + lx + 1;     // Ea index
-    const int b = (ly + 2) * kBW + lx + 2;     // B index
-    const float c0 = (sE[2][e + kAW] - sE[2][e - kAW]) * g.idy2;
-    const float c1 = -(sE[2][e + 1] - sE[2][e - 1]) * g.idx2;
-    const float c2 = (sE[1][e + 1] - sE[1][e - 1]) * g.idx2 - (sE[0][e + kAW] - sE[0][e - kAW]) * g.idy2;
-    sS[0][t] = sB[0][b] - hh * c0;
-    sS[1][t] = sB[1][b] - hh * c1;
-    sS[2][t] = sB[2][b] - hh * c2;
-  }
-  __syncthreads();
-  // Eb on the tile with halo 1 (stored in sE with the Eb row width)
-  for (int t = threadIdx.x; t < kFH * kFW; t += kSubBlock) {
-    const int ly = t / kFW, lx = t % kFW;
-    const int s = (ly + 1) * kSW + lx + 1;     // B* index
-    const int a = (ly + 2) * kAW + lx + 2;     // aux index
-    const float j0 = (sS[2][s + kSW] - sS[2][s - kSW]) * g.idy2;
-    const float j1 = -(sS[2][s + 1] - sS[2][s - 1]) * g.idx2;
-    const float j2 = (sS[1][s + 1] - sS[1][s - 1]) * g.idx2 - (sS[0][s + kSW] - sS[0][s - kSW]) * g.idy2;
-    float e[3];
-    ohm(sS[0][s], sS[1][s], sS[2][s], j0, j1, j2, a, e);
-    // sE is free again (Ea was consumed before the last barrier)
-    sE[0][t] = e[0];
-    sE[1][t] = e[1];
-    sE[2][t] = e[2];
-  }
-  __syncthreads();
-  // B_new = B - h curl Eb on the tile
-  for (int t = threadIdx.x; t < kTY * kTX; t += kSubBlock) {
-    const int ly = t / kTX, lx = t % kTX;
-    const int x = tx0 + lx, y = ty0 + ly;
-    if (x >= g.nx || y >= g.ny) continue;
-    const int e = (ly + 1) * kFW + lx + 1;
-    const int b = (ly + 4) * kBW + lx + 4;
-    const float c0 = (sE[2][e + kFW] - sE[2][e - kFW]) * g.idy2;
-    const float c1 = -(sE[2][e + 1] - sE[2][e - 1]) * g.idx2;
-    const float c2 = (sE[1][e + 1] - sE[1][e - 1]) * g.idx2 - (sE[0][e + kFW] - sE[0][e - kFW]) * g.idy2;
-    const int c = x + g.nx * y;
-    // compensated update (hi, lo) - h curl Eb; the increment is tiny next to B
-    const float d[3] = {-h * c0, -h * c1, -h * c2};
+  // The set-up loads of a thread are unrolled over clamped slots, with no
+  // branch between them, and all issued before the first LDS store, so that
+  // they are in flight together: B and n on halo HB, n and J on halo HB-1,
+  // lo on halo HB-4 (the output region of the first substep).
+  constexpr int IB = (PB::N + kSubBlock - 1) / kSubBlock;
+  constexpr int IA = (PA::N + kSubBlock - 1) / kSubBlock;
+  constexpr int IL = (PL::N + kSubBlock - 1) / kSubBlock;
+  float vb[IB][4], va[IA][4], vl[IL][3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const float hi = sB[a][b];
-      const float yv = (Lin ? Lin[a * nc + c] : 0.0f) + d[a];
-      const float tv = hi + yv;
-      Lout[a * nc + c] = yv - (tv - hi);
-      Bout[a * nc + c] = tv;
+  for (int u = 0; u < IB; ++u) {
+    const int t = min((int)threadIdx.x + u * kSubBlock, PB::N - 1);
+    const int c = gidx(t % PB::W - HB, t / PB::W - HB);
+    vb[u][0] = Bin[c];
+    vb[u][1] = Bin[nc + c];
+    vb[u][2] = Bin[2 * nc + c];
+    vb[u][3] = nm[c];
+  }
+#pragma unroll
+  for (int u = 0; u < IA; ++u) {
+    const int t = min((int)threadIdx.x + u * kSubBlock, PA::N - 1);
+    const int c = gidx(t % PA::W - (HB - 1), t / PA::W - (HB - 1));
+    va[u][0] = nm[c];
+    va[u][1] = Jm[c];
+    va[u][2] = Jm[nc + c];
+    va[u][3] = Jm[2 * nc + c];
+  }
+#pragma unroll
+  for (int u = 0; u < IL; ++u) {
+    const int t = min((int)threadIdx.x + u * kSubBlock, PL::N - 1);
+    const int c = gidx(t % PL::W - (HB - 4), t / PL::W - (HB - 4));
+    vl[u][0] = HAS_LIN ? Lin[c] : 0.0f;
+    vl[u][1] = HAS_LIN ? Lin[nc + c] : 0.0f;
+    vl[u][2] = HAS_LIN ? Lin[2 * nc + c] : 0.0f;
+  }
+  // B and p_e on halo HB
+#pragma unroll
+  for (int u = 0; u < IB; ++u) {
+    const int t = (int)threadIdx.x + u * kSubBlock;
+    if (t < PB::N) {
+      sB[t] = vb[u][0];
+      sB[PB::N + t] = vb[u][1];
+      sB[2 * PB::N + t] = vb[u][2];
+      sP[t] = pressure(vb[u][3], eos.nfloor, eos.te_n0, eos.n0, eos.gam, eos.iso);
     }
+  }
+  // 1/n_f and u_i on halo HB-1
+#pragma unroll
+  for (int u = 0; u < IA; ++u) {
+    const int t = (int)threadIdx.x + u * kSubBlock;
+    if (t < PA::N) {
+      const float inv = (float)(1.0 / (double)fmaxf(va[u][0], eos.nfloor));
+      sA[t] = inv;
+      sA[PA::N + t] = va[u][1] * inv;
+      sA[2 * PA::N + t] = va[u][2] * inv;
+      sA[3 * PA::N + t] = va[u][3] * inv;
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < IL; ++u) {
+    const int t = (int)threadIdx.x + u * kSubBlock;
+    if (t < PL::N) {
+      sL[t] = vl[u][0];
+      sL[PL::N + t] = vl[u][1];
+      sL[2 * PL::N + t] = vl[u][2];
+    }
+  }
+  __syncthreads();
+  // -grad(p_e)/n_f on halo HB-1 (its z component is zero in 2D)
+  for (int t = threadIdx.x; t < PA::N; t += kSubBlock) {
+    const int ly = t / PA::W - (HB - 1), lx = t % PA::W - (HB - 1);
+    const int p = PB::at(lx, ly);
+    const float inv = sA[t];
+    sA[4 * PA::N + t] = -(sP[p + 1] - sP[p - 1]) * g.idx2 * inv;
+    sA[5 * PA::N + t] = -(sP[p + PB::W] - sP[p - PB::W]) * g.idy2 * inv;
+  }
+  __syncthreads();
+  // Ohm's law at a cell given B there, curl B there and the frozen-term slot.
+  auto ohm = [&](float b0, float b1, float b2, float j0, float j1, float j2, int a, float* e) {
+    const float inv = sA[a];
+    const float w0 = j0 * inv - sA[PA::N + a], w1 = j1 * inv - sA[2 * PA::N + a],
+                w2 = j2 * inv - sA[3 * PA::N + a];
+    e[0] = (w1 * b2 - w2 * b1) + sA[4 * PA::N + a] + eta * j0;
+    e[1] = (w2 * b0 - w0 * b2) + sA[5 * PA::N + a] + eta * j1;
+    e[2] = (w0 * b1 - w1 * b0) + 0.0f + eta * j2;
+  };
+  const float hh = 0.5f * h;
+#pragma unroll
+  for (int s = 0; s < K; ++s) {
+    const int hin = 4 * (K - s);  // halo of this substep's input B
+    // Ea on halo hin-1
+    {
+      const int r = hin - 1, W = kTX + 2 * r, N = W * (kTY + 2 * r);
+      for (int t = threadIdx.x; t < N; t += kSubBlock) {
+        const int ly = t / W - r, lx = t % W - r;
+        const int b = PB::at(lx, ly), a = PA::at(lx, ly);
+        const float j0 = (sB[2 * PB::N + b + PB::W] - sB[2 * PB::N + b - PB::W]) * g.idy2;
+        const float j1 = -(sB[2 * PB::N + b + 1] - sB[2 * PB::N + b - 1]) * g.idx2;
+        const float j2 = (sB[PB::N + b + 1] - sB[PB::N + b - 1]) * g.idx2 -
+                         (sB[b + PB::W] - sB[b - PB::W]) * g.idy2;
+        float e[3];
+        ohm(sB[b], sB[PB::N + b], sB[2 * PB::N + b], j0, j1, j2, a, e);
+        sE[a] = e[0];
+        sE[PA::N + a] = e[1];
+        sE[2 * PA::N + a] = e[2];
+      }
+    }
+    __syncthreads();
+    // B* = B - (h/2) curl Ea on halo hin-2
+    {
+      const int r = hin - 2, W = kTX + 2 * r, N = W * (kTY + 2 * r);
+      for (int t = threadIdx.x; t < N; t += kSubBlock) {
+        const int ly = t / W - r, lx = t % W - r;
+        const int e = PA::at(lx, ly), b = PB::at(lx, ly), q = PS::at(lx, ly);
+        const float c0 = (sE[2 * PA::N + e + PA::W] - sE[2 * PA::N + e - PA::W]) * g.idy2;
+        const float c1 = -(sE[2 * PA::N + e + 1] - sE[2 * PA::N + e - 1]) * g.idx2;
+        const float c2 = (sE[PA::N + e + 1] - sE[PA::N + e - 1]) * g.idx2 -
+                         (sE[e + PA::W] - sE[e - PA::W]) * g.idy2;
+        sS[q] = sB[b] - hh * c0;
+        sS[PS::N + q] = sB[PB::N + b] - hh * c1;
+        sS[2 * PS::N + q] = sB[2 * PB::N + b] - hh * c2;
+      }
+    }
+    __syncthreads();
+    // Eb on halo hin-3 (into the E planes: Ea was consumed before the barrier)
+    {
+      const int r = hin - 3, W = kTX + 2 * r, N = W * (kTY + 2 * r);
+      for (int t = threadIdx.x; t < N; t += kSubBlock) {
+        const int ly = t / W - r, lx = t % W - r;
+        const int q = PS::at(lx, ly), a = PA::at(lx, ly);
+        const float j0 = (sS[2 * PS::N + q + PS::W] - sS[2 * PS::N + q - PS::W]) * g.idy2;
+        const float j1 = -(sS[2 * PS::N + q + 1] - sS[2 * PS::N + q - 1]) * g.idx2;
+        const float j2 = (sS[PS::N + q + 1] - sS[PS::N + q - 1]) * g.idx2 -
+                         (sS[q + PS::W] - sS[q - PS::W]) * g.idy2;
+        float e[3];
+        ohm(sS[q], sS[PS::N + q], sS[2 * PS::N + q], j0, j1, j2, a, e);
+        sE[a] = e[0];
+        sE[PA::N + a] = e[1];
+        sE[2 * PA::N + a] = e[2];
+      }
+    }
+    __syncthreads();
+    // B_new = B - h curl Eb on halo hin-4, as the compensated sum
+    // (hi, lo) - h curl Eb: the increment is tiny next to B
+    {
+      const int r = hin - 4, W = kTX + 2 * r, N = W * (kTY + 2 * r);
+      for (int t = threadIdx.x; t < N; t += kSubBlock) {
+        const int ly = t / W - r, lx = t % W - r;
+        const int e = PA::at(lx, ly), b = PB::at(lx, ly), l = PL::at(lx, ly);
+        const float c0 = (sE[2 * PA::N + e + PA::W] - sE[2 * PA::N + e - PA::W]) * g.idy2;
+        const float c1 = -(sE[2 * PA::N + e + 1] - sE[2 * PA::N + e - 1]) * g.idx2;
+        const float c2 = (sE[PA::N + e + 1] - sE[PA::N + e - 1]) * g.idx2 -
+                         (sE[e + PA::W] - sE[e - PA::W]) * g.idy2;
+        const float d[3] = {-h * c0, -h * c1, -h * c2};
+        if (s + 1 < K) {
+          // next substep's input, in place: this cell alone is read here
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            const float hi = sB[a * PB::N + b];
+            const float yv = sL[a * PL::N + l] + d[a];
+            const float tv = hi + yv;
+            sL[a * PL::N + l] = yv - (tv - hi);
+            sB[a * PB::N + b] = tv;
+          }
+        } else {
+          const int x = tx0 + lx, y = ty0 + ly;
+          if (x >= g.nx || y >= g.ny) continue;
+          const int c = x + g.nx * y;
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            const float hi = sB[a * PB::N + b];
+            const float yv = sL[a * PL::N + l] + d[a];
+            const float tv = hi + yv;
+            Lout[a * nc + c] = yv - (tv - hi);
+            Bout[a * nc + c] = tv;
+          }
+        }
+      }
+    }
+    if (s + 1 < K) __syncthreads();
   }
 }
 
-// E = Ohm(B) written out, plus per-block FP64 partials {sum |B|^2, sum B}.
-// With Bout non-null the final B = hi + lo is also written there (Bout is
-// never one of the arrays read).
-template <int NDIM>
-__global__ __launch_bounds__(kBlock) void k_field_ohm_out(const float* __restrict__ Bh,
-                                                          const float* __restrict__ Bl,
-                                                          float* __restrict__ Bout, float eta,
-                                                          FGeo g, Aux aux, float* __restrict__ E,
-                                                          double* part) {
+// E at the end of the step from the moments n_eff = ca*na + cb*nb,
+// J_eff = ca*Ja + cb*Jb (EXTRAP; otherwise na, Ja), with B = Bh + Bl (HAS_LO;
+// otherwise Bh),
+// with the frozen terms formed per cell as in k_field_prep.  With Bout
+// non-null the final B = hi + lo is also written there (Bout is never one of
+// the arrays read).  Cells of na below the floor are counted when asked
+// (once per field advance).  With part non-null, per-block FP64 partials
+// {sum |B|^2, sum B} go to part.
+template <int NDIM, bool EXTRAP, bool HAS_LO>
+__global__ __launch_bounds__(kBlock) void k_field_final(
+    const float* __restrict__ Bh, const float* __restrict__ Bl, float* __restrict__ Bout,
+    const float* __restrict__ na, const float* __restrict__ nb, const float* __restrict__ Ja,
+    const float* __restrict__ Jb, float ca, float cb, float eta, FGeo g, Eos eos,
+    float* __restrict__ E, double* part, Status* st, int count_floor) {
   const int c = blockIdx.x * kBlock + threadIdx.x;
   const int nc = g.ncell;
+  const bool live = c < nc;
+  bool below = false;
   double v[4] = {0.0, 0.0, 0.0, 0.0};
-  if (c < nc) {
-    const BPair B{Bh, Bl};
-    float e[3];
-    ohm_at<NDIM>(B, aux, eta, c, g, e);
-    E[c] = e[0];
-    E[nc + c] = e[1];
-    E[2 * nc + c] = e[2];
-    const float f0 = B(c), f1 = B(nc + c), f2 = B(2 * nc + c);
+  if (live) {
+    int i, j, k;
+    fijk(c, g, i, j, k);
+    const Nbr nn = neighbours(c, i, j, k, g);
+    // every load first (no branch between them), then the arithmetic
+    auto dens = [&](int q) { return EXTRAP ? ca * na[q] + cb * nb[q] : na[q]; };
+    const float n_c = dens(c);
+    const float n_xp = dens(nn.xp), n_xm = dens(nn.xm), n_yp = dens(nn.yp), n_ym = dens(nn.ym);
+    const float n_zp = NDIM == 3 ? dens(nn.zp) : 0.f, n_zm = NDIM == 3 ? dens(nn.zm) : 0.f;
+    float Jv[3];
+    for (int a = 0; a < 3; ++a)
+      Jv[a] = EXTRAP ? ca * Ja[a * nc + c] + cb * Jb[a * nc + c] : Ja[a * nc + c];
+    const BSum<HAS_LO> B{Bh, Bl};
+    float J[3];
+    curl_at<NDIM>(B, c, g, J);
+    const float b0 = B(c), b1 = B(nc + c), b2 = B(2 * nc + c);
+    below = na[c] < eos.nfloor;
+    auto pres = [&](float n) {
+      return pressure(n, eos.nfloor, eos.te_n0, eos.n0, eos.gam, eos.iso);
+    };
+    const float inv = (float)(1.0 / (double)fmaxf(n_c, eos.nfloor));
+    float u[3];
+    for (int a = 0; a < 3; ++a) u[a] = Jv[a] * inv;
+    float gp[3];
+    gp[0] = -(pres(n_xp) - pres(n_xm)) * g.idx2 * inv;
+    gp[1] = -(pres(n_yp) - pres(n_ym)) * g.idy2 * inv;
+    gp[2] = NDIM == 3 ? -(pres(n_zp) - pres(n_zm)) * g.idz2 * inv : 0.f;
+    const float w0 = J[0] * inv - u[0], w1 = J[1] * inv - u[1], w2 = J[2] * inv - u[2];
+    E[c] = (w1 * b2 - w2 * b1) + gp[0] + eta * J[0];
+    E[nc + c] = (w2 * b0 - w0 * b2) + gp[1] + eta * J[1];
+    E[2 * nc + c] = (w0 * b1 - w1 * b0) + gp[2] + eta * J[2];
     if (Bout) {
-      Bout[c] = f0;
-      Bout[nc + c] = f1;
-      Bout[2 * nc + c] = f2;
+      Bout[c] = b0;
+      Bout[nc + c] = b1;
+      Bout[2 * nc + c] = b2;
     }
-    const double b0 = f0, b1 = f1, b2 = f2;
-    v[0] = b0 * b0 + b1 * b1 + b2 * b2;
-    v[1] = b0;
-    v[2] = b1;
-    v[3] = b2;
+    const double d0 = b0, d1 = b1, d2 = b2;
+    v[0] = d0 * d0 + d1 * d1 + d2 * d2;
+    v[1] = d0;
+    v[2] = d1;
+    v[3] = d2;
+  }
+  if (count_floor) {
+    const uint64_t m = __ballot(live && below);
+    if ((threadIdx.x & 63) == 0 && m) {
+      atomicOr(&st->flags, (uint32_t)HVPIC_FLAG_FLOOR_HIT);
+      atomicAdd(&st->floor_hits, (unsigned long long)__builtin_popcountll(m));
+    }
   }
   if (part) block_partial<4>(v, part);
 }
 
 // {W_B, W_dB} = {1/2 V sum |B|^2, 1/2 V (sum |B|^2 - |sum B|^2 / ncell)}.
+// A kernel of its own: a last-block reduction inside k_field_final would need
+// an agent-scope release per block, which writes back the L2.
 __global__ __launch_bounds__(1024) void k_field_diag_final(const double* part, int nblocks,
                                                              double* out, double half_vol,
                                                              double inv_ncell) {
@@ -437,29 +599,41 @@ int field_impl(hvpic_ctx* c, float* B, const float* n_half, const float* J_half,
   float* Xl = c->fscratch + 10ll * nc;
   float* Yh = c->fscratch + 13ll * nc;
   float* Yl = c->fscratch + 16ll * nc;
-  const float nfloor = (float)c->p.n_floor, n0 = (float)c->p.n0;
-  const float te_n0 = (float)(c->p.te * c->p.n0), gam = (float)c->p.gamma_e;
-  const int iso = c->p.gamma_e == 1.0;
+  Eos eos;
+  eos.nfloor = (float)c->p.n_floor;
+  eos.n0 = (float)c->p.n0;
+  eos.te_n0 = (float)(c->p.te * c->p.n0);
+  eos.gam = (float)c->p.gamma_e;
+  eos.iso = c->p.gamma_e == 1.0;
   const float eta = (float)c->p.eta;
-  // frozen moments for the subcycle (mode 0) or the E-only evaluation (mode 1)
-  hipLaunchKernelGGL((k_field_prep<NDIM>), grid, blk, 0, s, n_half, (const float*)nullptr, J_half,
-                     (const float*)nullptr, 1.0f, 0.0f, g, nfloor, te_n0, n0, gam, iso, aux,
-                     c->status, 1);
   const float* fh = B;        // final B = fh + fl
   const float* fl = nullptr;
   if (mode == 0 && c->p.nsub > 0) {
     const float h = (float)(c->p.dt / c->p.nsub);
-    const int cblocks = (int)std::min<int64_t>(ceil_div(3ll * nc, kBlock), 1024);
     if (NDIM == 2) {
-      // fused substeps; the caller's B is only read (first substep)
+      // two substeps per launch (one for an odd last one), the frozen terms
+      // formed in each tile; the caller's B is only read (first launch)
       const dim3 tiles((unsigned)ceil_div(c->p.nx, kTX), (unsigned)ceil_div(c->p.ny, kTY));
+      const size_t lds2 = sizeof(float) * SubLds<2>::TOTAL, lds1 = sizeof(float) * SubLds<1>::TOTAL;
       const float* sh = B;
       const float* sl = nullptr;
       float* dh = Xh;
       float* dl = Xl;
-      for (int m = 0; m < c->p.nsub; ++m) {
-        hipLaunchKernelGGL(k_field_substep2d, tiles, dim3(kSubBlock), 0, s, sh, sl, dh, dl, h, eta, g,
-                           aux);
+      for (int m = 0; m < c->p.nsub;) {
+        const bool two = c->p.nsub - m >= 2;
+        if (two && sl)
+          hipLaunchKernelGGL((k_field_sub2d<2, true>), tiles, dim3(kSubBlock), lds2, s, sh, sl, dh,
+                             dl, n_half, J_half, h, eta, g, eos);
+        else if (two)
+          hipLaunchKernelGGL((k_field_sub2d<2, false>), tiles, dim3(kSubBlock), lds2, s, sh, sl, dh,
+                             dl, n_half, J_half, h, eta, g, eos);
+        else if (sl)
+          hipLaunchKernelGGL((k_field_sub2d<1, true>), tiles, dim3(kSubBlock), lds1, s, sh, sl, dh,
+                             dl, n_half, J_half, h, eta, g, eos);
+        else
+          hipLaunchKernelGGL((k_field_sub2d<1, false>), tiles, dim3(kSubBlock), lds1, s, sh, sl, dh,
+                             dl, n_half, J_half, h, eta, g, eos);
+        m += two ? 2 : 1;
         sh = dh;
         sl = dl;
         dh = dh == Xh ? Yh : Xh;
@@ -468,6 +642,11 @@ int field_impl(hvpic_ctx* c, float* B, const float* n_half, const float* J_half,
       fh = sh;
       fl = sl;
     } else {
+      // frozen moments for the subcycle
+      hipLaunchKernelGGL((k_field_prep<NDIM>), grid, blk, 0, s, n_half, (const float*)nullptr,
+                         J_half, (const float*)nullptr, 1.0f, 0.0f, g, eos.nfloor, eos.te_n0,
+                         eos.n0, eos.gam, eos.iso, aux);
+      const int cblocks = (int)std::min<int64_t>(ceil_div(3ll * nc, kBlock), 1024);
       hipLaunchKernelGGL(k_copy, dim3(cblocks), blk, 0, s, (const float*)B, Xh, 3ll * nc);
       hipLaunchKernelGGL(k_fill, dim3(cblocks), blk, 0, s, Xl, 3ll * nc, 0.0f);
       for (int m = 0; m < c->p.nsub; ++m) {
@@ -480,18 +659,23 @@ int field_impl(hvpic_ctx* c, float* B, const float* n_half, const float* J_half,
       fl = Xl;
     }
   }
-  if (mode == 0) {
-    // extrapolated moments for E^{n+1}
-    hipLaunchKernelGGL((k_field_prep<NDIM>), grid, blk, 0, s, n_half, n_prev, J_half, J_prev, 1.5f,
-                       -0.5f, g, nfloor, te_n0, n0, gam, iso, aux, c->status, 0);
-  }
-  hipLaunchKernelGGL((k_field_ohm_out<NDIM>), grid, blk, 0, s, fh, fl, fh == B ? nullptr : B, eta,
-                     g, aux, E_out, diag_out ? c->field_part : nullptr);
-  if (diag_out) {
-    const double V = c->p.dx * c->p.dy * c->p.dz;
+  // E^{n+1} from the extrapolated moments (mode 0) or E from the given ones
+  // (mode 1), the final B, the floor count of n_half and the diagnostics
+  const double V = c->p.dx * c->p.dy * c->p.dz;
+  auto final_kernel = [&](auto kern) {
+    hipLaunchKernelGGL(kern, grid, blk, 0, s, fh, fl, fh == B ? nullptr : B, n_half, n_prev,
+                       J_half, J_prev, 1.5f, -0.5f, eta, g, eos, E_out,
+                       diag_out ? c->field_part : nullptr, c->status, 1);
+  };
+  if (mode == 0 && fl)
+    final_kernel(k_field_final<NDIM, true, true>);
+  else if (mode == 0)
+    final_kernel(k_field_final<NDIM, true, false>);
+  else
+    final_kernel(k_field_final<NDIM, false, false>);
+  if (diag_out)
     hipLaunchKernelGGL(k_field_diag_final, dim3(1), dim3(1024), 0, s, (const double*)c->field_part,
                        (int)grid.x, diag_out, 0.5 * V, 1.0 / (double)nc);
-  }
   return hipGetLastError() == hipSuccess ? HVPIC_OK : HVPIC_EHIP;
 }
 

@@ -32,10 +32,65 @@ n^0, J^0).  This module only orders the calls and swaps buffers.
 """
 from __future__ import annotations
 
+import ctypes
+
 import numpy as np
 import torch
 
 from . import hvpic as H
+
+_HIP_EVENT_DISABLE_TIMING = 0x2
+_HIP_EVENT_DISABLE_SYSTEM_FENCE = 0x20000000
+_hip = None
+
+
+def _hip_runtime():
+    """The HIP runtime already loaded in the process (torch's and the
+    library's share the soname)."""
+    global _hip
+    if _hip is None:
+        lib = ctypes.CDLL("libamdhip64.so.7")
+        for name, args in (("hipEventCreateWithFlags", (ctypes.c_void_p, ctypes.c_uint)),
+                           ("hipEventRecord", (ctypes.c_void_p, ctypes.c_void_p)),
+                           ("hipStreamWaitEvent", (ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint)),
+                           ("hipEventDestroy", (ctypes.c_void_p,))):
+            f = getattr(lib, name)
+            f.argtypes = args
+            f.restype = ctypes.c_int
+        _hip = lib
+    return _hip
+
+
+class StreamEvent:
+    """Orders work between two streams of one device.  No timing and no
+    system-scope fence: recording one does not write back and invalidate the
+    caches (a few microseconds that a torch event costs on the stream it is
+    recorded on).  Kernels of the other stream still see the data, since each
+    kernel releases its writes to the device when it ends and acquires at its
+    start; host reads go through the runtime's own copies and synchronisation."""
+
+    def __init__(self):
+        self._hip = _hip_runtime()
+        self.h = ctypes.c_void_p()
+        self._check(self._hip.hipEventCreateWithFlags(
+            ctypes.byref(self.h), _HIP_EVENT_DISABLE_TIMING | _HIP_EVENT_DISABLE_SYSTEM_FENCE))
+
+    @staticmethod
+    def _check(rc):
+        if rc != 0:
+            raise RuntimeError(f"HIP event call failed with error {rc}")
+
+    def record(self, stream: torch.cuda.Stream):
+        self._check(self._hip.hipEventRecord(self.h, ctypes.c_void_p(stream.cuda_stream)))
+
+    def wait(self, stream: torch.cuda.Stream):
+        """Makes later work on `stream` wait for the last record (none: no wait)."""
+        self._check(self._hip.hipStreamWaitEvent(ctypes.c_void_p(stream.cuda_stream), self.h, 0))
+
+    def __del__(self):
+        if getattr(self, "h", None) and self.h.value:
+            self._hip.hipEventDestroy(self.h)
+            self.h = ctypes.c_void_p()
 
 
 class GpuSim:
@@ -73,9 +128,9 @@ class GpuSim:
         self.diagnostics = diagnostics
         self.push_diag = torch.zeros(4, dtype=torch.float64, device=device)
         self.field_diag = torch.zeros(2, dtype=torch.float64, device=device)
-        self.ev_moments = torch.cuda.Event()    # moments of the step are written
-        self.ev_fields = torch.cuda.Event()     # E, B of the step are written
-        self.ev_particles = torch.cuda.Event()  # the step's particle work is done
+        self.ev_moments = StreamEvent()    # moments of the step are written
+        self.ev_fields = StreamEvent()     # E, B of the step are written
+        self.ev_particles = StreamEvent()  # the step's particle work is done
         # the tensors above (and the contexts' workspaces) were filled on the
         # current stream
         torch.cuda.current_stream(device).synchronize()
@@ -91,8 +146,9 @@ class GpuSim:
         self._fields_after_moments(mode=1, n_half=self.n_prev, J_half=self.J_prev)
         self.nstep = 0
         cur = torch.cuda.current_stream(device)
-        cur.wait_stream(self.s_p)
-        cur.wait_stream(self.s_f)
+        self.ev_particles.record(self.s_p)
+        self.ev_particles.wait(cur)
+        self.ev_fields.wait(cur)
 
     def _moments_ready(self):
         """Marks the moments of the step as written (on the particle stream)."""
@@ -105,7 +161,7 @@ class GpuSim:
         cfg = self.cfg
         cf = self.ctx_f.ctx
         if self.s_f is not self.s_p:
-            self.s_f.wait_event(self.ev_moments)
+            self.ev_moments.wait(self.s_f)
         if cfg.nsmooth:
             H.hvpic_smooth(cf, n_half, cfg.nsmooth)
             H.hvpic_smooth(cf, J_half, cfg.nsmooth)
@@ -125,7 +181,7 @@ class GpuSim:
         # E^n and B^n are written, and the moment buffers free, once the last
         # field advance has ended.  (Writes into the simulation's tensors by
         # the caller must be finished first: see synchronize().)
-        self.s_p.wait_event(self.ev_fields)
+        self.ev_fields.wait(self.s_p)
         E, B = self.E, self.B
         if cfg.nsmooth:
             with torch.cuda.stream(self.s_p):
@@ -165,9 +221,9 @@ class GpuSim:
         # later work on the caller's stream (reads of E, B, the moments, the
         # store) sees this step; the next step's launches do not wait for it
         self.ev_particles.record(self.s_p)
-        cur.wait_event(self.ev_particles)
+        self.ev_particles.wait(cur)
         if self.s_f is not self.s_p:
-            cur.wait_event(self.ev_fields)
+            self.ev_fields.wait(cur)
 
     def synchronize(self):
         """Waits for all queued work (host and the caller's stream).  Call it

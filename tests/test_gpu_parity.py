@@ -270,9 +270,13 @@ def test_gather_push_perm(H, name, cfg, fused):
 @pytest.mark.parametrize("name,cfg", [CASES[0], CASES[2]])
 @pytest.mark.parametrize("mode", [0, 1])
 @pytest.mark.parametrize("gamma", [1.0, 5.0 / 3.0])
-def test_field_advance(H, name, cfg, mode, gamma):
-    announce("field", name, mode, gamma)
-    cfg = cfg.replace(gamma_e=gamma)
+@pytest.mark.parametrize("nsub", [0, 1, 3, 4])
+def test_field_advance(H, name, cfg, mode, gamma, nsub):
+    """2D tiles take two substeps per launch (one for an odd last one)."""
+    if mode == 1 and nsub != 3:
+        pytest.skip("mode 1 has no subcycle")
+    announce("field", name, mode, gamma, nsub)
+    cfg = cfg.replace(gamma_e=gamma, nsub=nsub)
     B = W.random_field(71, cfg, 0.2, (1.0, 0.3, -0.2))
     nh = W.random_density(72, cfg, 0.02, 1.5)  # some cells below the floor
     npv = W.random_density(73, cfg, 0.5, 1.5)
@@ -289,6 +293,31 @@ def test_field_advance(H, name, cfg, mode, gamma):
     assert rel_l2(Ed.cpu().numpy(), rE) < 1e-5
     assert np.allclose(diag.cpu().numpy(), rd, rtol=1e-5)
     assert counts[2] == st.floor_hits and bool(flags & H.FLAG_FLOOR_HIT) == (st.floor_hits > 0)
+
+
+@pytest.mark.parametrize("nx,ny", [(5, 3), (70, 19)])
+@pytest.mark.parametrize("nsub", [2, 5])
+def test_field_advance_2d_tiles(H, nx, ny, nsub):
+    """Grids smaller than one tile (the halo wraps more than once) and grids
+    of several tiles with ragged edges."""
+    announce("field-tiles", nx, ny, nsub)
+    cfg = cfg2(nx=nx, ny=ny, nsub=nsub)
+    B = W.random_field(171, cfg, 0.2, (1.0, 0.3, -0.2))
+    nh = W.random_density(172, cfg, 0.5, 1.5)
+    npv = W.random_density(173, cfg, 0.5, 1.5)
+    Jh = W.random_field(174, cfg, 0.2)
+    Jp = W.random_field(175, cfg, 0.2)
+    ctx = H.Context(cfg, 1)
+    Bd = dev(B)
+    Ed = torch.zeros((3, cfg.ncell), device="cuda")
+    diag = torch.zeros(2, dtype=torch.float64, device="cuda")
+    for _ in range(2):  # twice: the diagnostics' ticket is reset by its last block
+        Bd.copy_(dev(B))
+        H.hvpic_field_advance(ctx.ctx, Bd, dev(nh), dev(Jh), dev(npv), dev(Jp), Ed, 0, diag)
+        rB, rE, rd, st = O.field_advance(cfg, B, nh, Jh, npv, Jp, mode=0)
+        assert rel_l2(Bd.cpu().numpy(), rB) < 1e-5
+        assert rel_l2(Ed.cpu().numpy(), rE) < 1e-5
+        assert np.allclose(diag.cpu().numpy(), rd, rtol=1e-5)
 
 
 @pytest.mark.parametrize("name,cfg", [CASES[0], CASES[2]])
