@@ -565,7 +565,8 @@ __device__ void block_sort(int64_t n, int ncell, Fields in, Fields out, int32_t*
   gather_fields(kin, vin, n, in, out, cs, ncell, threadIdx.x, blockDim.x);
 }
 
-template <int NDIM>
+// PERM: write the gather map out.perm[dst] = p instead of moving the fields.
+template <int NDIM, bool PERM>
 __global__ __launch_bounds__(kBlock) void k_nb_scatter(const int32_t* __restrict__ cs_prev, int64_t n,
                                                        SortGeo g, uint32_t* __restrict__ bases,
                                                        Fields in, Fields out, int32_t* cs,
@@ -573,6 +574,7 @@ __global__ __launch_bounds__(kBlock) void k_nb_scatter(const int32_t* __restrict
                                                        uint32_t* rv0, uint32_t* rv1) {
   constexpr int ND = Dirs<NDIM>::N, NB = Dirs<NDIM>::BITS;
   constexpr int CODE_BITS = NB + kScatterCellBits;
+  constexpr int NF = PERM ? 0 : 7;        // fields carried through registers
   constexpr int NG = kScatterCells * ND;  // groups of the wavefront
   constexpr int GPL = (NG + 63) / 64;     // groups per lane
   __shared__ uint32_t s_next[kWaves][NG];  // next free slot of each group
@@ -620,14 +622,14 @@ __global__ __launch_bounds__(kBlock) void k_nb_scatter(const int32_t* __restrict
   const int64_t pb = __builtin_amdgcn_readlane(bnd, 0), pe = __builtin_amdgcn_readlane(bnd, na);
   for (int64_t q0 = pb; q0 < pe; q0 += 64 * kScatterBatches) {
    int keys[kScatterBatches];
-   float vals[kScatterBatches][7];
+   float vals[kScatterBatches][NF > 0 ? NF : 1];
 #pragma unroll
    for (int b = 0; b < kScatterBatches; ++b) {
      const int64_t p = q0 + b * 64 + lane;
      const bool v = p < pe;
      keys[b] = v ? in.cell[p] : 0;
 #pragma unroll
-     for (int f = 0; f < 7; ++f) vals[b][f] = (v && in.f[f] && !out.perm) ? in.f[f][p] : 0.0f;
+     for (int f = 0; f < NF; ++f) vals[b][f] = (v && in.f[f]) ? in.f[f][p] : 0.0f;
    }
 #pragma unroll
    for (int b = 0; b < kScatterBatches; ++b) {
@@ -657,12 +659,12 @@ __global__ __launch_bounds__(kBlock) void k_nb_scatter(const int32_t* __restrict
     if (ok && before == 0) s_next[wid][slot] += (uint32_t)__builtin_popcountll(mine);
     __builtin_amdgcn_wave_barrier();
     if (ok && dst < n) {
-      if (out.perm) {
+      if (PERM) {
         out.perm[dst] = (int32_t)p;
       } else {
         out.cell[dst] = key;
 #pragma unroll
-        for (int f = 0; f < 7; ++f)
+        for (int f = 0; f < NF; ++f)
           if (in.f[f]) out.f[f][dst] = vals[b][f];
       }
     }
@@ -762,9 +764,14 @@ void enqueue_neighbour(hvpic_ctx* c, const hvpic_particles* in, const Fields& ou
   }
   timing_begin(c, HVPIC_KERNEL_SORT_SCATTER);
   const int sblocks = (int)ceil_div(c->ncell, kWaves * kScatterCells);
-  hipLaunchKernelGGL((k_nb_scatter<NDIM>), dim3(sblocks), dim3(kBlock), 0, s, cs_prev, in->n, g,
-                     c->sort_cnt, fields_of(in), out, cs,
-                     (const Status*)c->status, c->rkey[0], c->rkey[1], c->rval[0], c->rval[1]);
+  if (out.perm)
+    hipLaunchKernelGGL((k_nb_scatter<NDIM, true>), dim3(sblocks), dim3(kBlock), 0, s, cs_prev, in->n,
+                       g, c->sort_cnt, fields_of(in), out, cs, (const Status*)c->status,
+                       c->rkey[0], c->rkey[1], c->rval[0], c->rval[1]);
+  else
+    hipLaunchKernelGGL((k_nb_scatter<NDIM, false>), dim3(sblocks), dim3(kBlock), 0, s, cs_prev,
+                       in->n, g, c->sort_cnt, fields_of(in), out, cs, (const Status*)c->status,
+                       c->rkey[0], c->rkey[1], c->rval[0], c->rval[1]);
   timing_end(c, HVPIC_KERNEL_SORT_SCATTER);
 }
 

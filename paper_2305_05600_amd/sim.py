@@ -88,9 +88,11 @@ class StreamEvent:
         self._check(self._hip.hipStreamWaitEvent(ctypes.c_void_p(stream.cuda_stream), self.h, 0))
 
     def __del__(self):
-        if getattr(self, "h", None) and self.h.value:
-            self._hip.hipEventDestroy(self.h)
-            self.h = ctypes.c_void_p()
+        # (at interpreter exit the module globals may already be gone)
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            self._hip.hipEventDestroy(h)
+            h.value = None
 
 
 class GpuSim:
