@@ -14,7 +14,8 @@ reads through, writing the pushed store in sorted order, so the particles
 cross HBM once per step (--no-gather-map moves the store in the sort instead;
 results are bit-identical).  `roofline` refers to the dominant kernel (the
 fused gather+push+deposit), timed by HIP events that the library records on
-its stream directly around each of its launches;
+its stream directly around every 10th of its launches over the timed steps
+(--time-every; each recorded event holds the stream a few microseconds);
 `cpu_baseline` times the FP64 oracle on one step of the same workload.
 """
 from __future__ import annotations
@@ -90,6 +91,9 @@ def main() -> int:
                     help="move the store in the sort and push it in place")
     ap.add_argument("--no-overlap", action="store_true",
                     help="run the field advance on the particle stream (no overlap with the sort)")
+    ap.add_argument("--time-every", type=int, default=10,
+                    help="bracket every k-th launch of the timed kernels with HIP events "
+                         "(each recorded event holds the stream a few microseconds)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run three plain 512 MiB device copies (a known-size reference "
                          "for hardware traffic counters)")
@@ -123,9 +127,12 @@ def main() -> int:
         g.step()
     g.synchronize()
     c = g.ctx.ctx
-    # HIP events recorded by the library on its own stream right around each
-    # launch of the dominant kernel (and of the sort's scatter)
-    H.hvpic_timing_enable(c, args.steps)
+    # HIP events recorded by the library on its own stream right around every
+    # k-th launch of the dominant kernel (and of the sort's scatter) over the
+    # timed steps
+    every = max(1, args.time_every)
+    n_timed = (args.steps + every - 1) // every
+    H.hvpic_timing_enable(c, n_timed, every)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -136,7 +143,7 @@ def main() -> int:
     k_ms, k_launches = H.hvpic_timing_read(c, H.KERNEL_GATHER_PUSH)
     s_ms, s_launches = H.hvpic_timing_read(c, H.KERNEL_SORT_SCATTER)
     H.hvpic_timing_enable(c, 0)
-    assert k_launches == args.steps, (k_launches, args.steps)
+    assert k_launches == n_timed, (k_launches, n_timed)
     kernel_ms = k_ms / k_launches
     flags, counts = g.status()
     ms_per_step = wall * 1e3 / args.steps
@@ -166,6 +173,7 @@ def main() -> int:
                                 + (", read through the gather map)" if g.gather_map else ")")
                                 if g.fused else "k_gather_push"),
                      "kernel_ms": kernel_ms,
+                     "kernel_timed_launches": f"{k_launches} of {args.steps} (every {every})",
                      "algorithmic_bytes_per_launch": per_launch},
         "kernels_ms": {"gather_push_deposit": kernel_ms,
                        "sort_scatter": s_ms / max(s_launches, 1)},

@@ -217,23 +217,27 @@ int hvpic_smooth(hvpic_ctx* ctx, float* F, int ncomp, int npasses);
 int hvpic_sync_status(hvpic_ctx* ctx, uint32_t* flags, int64_t* counts);
 
 /* Kernel timing on the context's stream (a measurement aid, not part of the
-   method).  hvpic_timing_enable(ctx, max_launches) creates HIP event pairs
-   for up to max_launches launches of each timed kernel (max_launches = 0
-   switches timing off and frees the events; at most 65536).  While enabled,
-   every launch of a timed kernel is bracketed by events recorded on the
-   context's stream, directly around that one kernel.  hvpic_timing_read
-   waits for the stream and returns, for kernel id `kernel`, the summed
-   duration in milliseconds and the number of timed launches, then restarts
-   the count.  Launches beyond max_launches are not timed.  Returns
-   HVPIC_EINVAL for an unknown id or max_launches out of range, HVPIC_EHIP if
-   an event call fails. */
+   method).  hvpic_timing_enable(ctx, max_launches, every) creates HIP event
+   pairs for up to max_launches timed launches of each timed kernel
+   (max_launches = 0 switches timing off and frees the events; at most 65536).
+   While enabled, launch number 0, every, 2*every, ... of each timed kernel
+   (counted from the enable call or the last read) is bracketed by events
+   recorded on the context's stream, directly around that one kernel; the
+   others run without them (each recorded event holds the stream a few
+   microseconds, so sampling keeps the timed sequence close to an untimed
+   one).  every = 1 times every launch.  hvpic_timing_read waits for the
+   stream and returns, for kernel id `kernel`, the summed duration in
+   milliseconds and the number of timed launches, then restarts the counts.
+   Launches beyond max_launches timed ones are not timed.  Returns
+   HVPIC_EINVAL for an unknown id, max_launches out of range or every < 1,
+   HVPIC_EHIP if an event call fails. */
 enum {
   HVPIC_KERNEL_GATHER_PUSH = 0,  /* fused gather + Boris push (+ deposit) */
   HVPIC_KERNEL_DEPOSIT = 1,      /* stand-alone moment deposit */
   HVPIC_KERNEL_SORT_SCATTER = 2, /* neighbour-move sort scatter */
   HVPIC_KERNEL_COUNT = 3
 };
-int hvpic_timing_enable(hvpic_ctx* ctx, int max_launches);
+int hvpic_timing_enable(hvpic_ctx* ctx, int max_launches, int every);
 int hvpic_timing_read(hvpic_ctx* ctx, int kernel, double* total_ms, int64_t* launches);
 
 /* Static description of an error code. */

@@ -155,7 +155,7 @@ int hvpic_init(const hvpic_params* params, void* hip_stream, void* workspace, hv
 
 int hvpic_finalize(hvpic_ctx* ctx) {
   if (!ctx_ok(ctx)) return HVPIC_ESTATE;
-  hvpic_timing_enable(ctx, 0);
+  hvpic_timing_enable(ctx, 0, 1);
   ctx->magic = 0;
   delete ctx;
   return HVPIC_OK;
@@ -250,9 +250,9 @@ int hvpic_sync_status(hvpic_ctx* ctx, uint32_t* flags, int64_t* counts) {
   return HVPIC_OK;
 }
 
-int hvpic_timing_enable(hvpic_ctx* ctx, int max_launches) {
+int hvpic_timing_enable(hvpic_ctx* ctx, int max_launches, int every) {
   if (!ctx_ok(ctx)) return HVPIC_ESTATE;
-  if (max_launches < 0 || max_launches > 65536) return HVPIC_EINVAL;
+  if (max_launches < 0 || max_launches > 65536 || every < 1) return HVPIC_EINVAL;
   int rc = HVPIC_OK;
   if (ctx->tev) {
     if (hipStreamSynchronize(ctx->stream) != hipSuccess) rc = HVPIC_EHIP;
@@ -263,7 +263,12 @@ int hvpic_timing_enable(hvpic_ctx* ctx, int max_launches) {
     ctx->tev = nullptr;
   }
   ctx->tmax = 0;
-  for (int k = 0; k < HVPIC_KERNEL_COUNT; ++k) ctx->tcount[k] = 0;
+  ctx->tevery = every;
+  for (int k = 0; k < HVPIC_KERNEL_COUNT; ++k) {
+    ctx->tcount[k] = 0;
+    ctx->tseen[k] = 0;
+    ctx->tarmed[k] = false;
+  }
   if (max_launches == 0 || rc != HVPIC_OK) return rc;
   const int64_t ne = (int64_t)HVPIC_KERNEL_COUNT * max_launches * 2;
   hipEvent_t* ev = new (std::nothrow) hipEvent_t[ne];
@@ -301,6 +306,7 @@ int hvpic_timing_read(hvpic_ctx* ctx, int kernel, double* total_ms, int64_t* lau
   *total_ms = t;
   *launches = ctx->tcount[kernel];
   ctx->tcount[kernel] = 0;
+  ctx->tseen[kernel] = 0;
   return HVPIC_OK;
 }
 

@@ -147,7 +147,10 @@ struct hvpic_ctx {
   // optional per-kernel timing: event pairs [kernel][slot][2]
   hipEvent_t* tev;
   int tmax;
-  int tcount[HVPIC_KERNEL_COUNT];
+  int tevery;                            // time launch 0, tevery, 2 tevery, ...
+  int tcount[HVPIC_KERNEL_COUNT];        // timed launches
+  int64_t tseen[HVPIC_KERNEL_COUNT];     // launches since enable / read
+  bool tarmed[HVPIC_KERNEL_COUNT];       // the current launch has its begin event
 };
 
 namespace hvpic {
@@ -174,16 +177,22 @@ int launch_smooth(hvpic_ctx* c, float* F, int ncomp, int npasses);
 int launch_zero(hvpic_ctx* c, float* p, int64_t count);
 void zero_counts(hvpic_ctx* c);  // enqueues the clearing of sort_cnt
 
-// Event bracket around one launch of kernel id k (no-op unless timing is on).
+// Event bracket around one launch of kernel id k (no-op unless timing is on
+// and the launch is one of the sampled ones).
 inline void timing_begin(hvpic_ctx* c, int k) {
-  if (c->tev && c->tcount[k] < c->tmax)
-    (void)hipEventRecord(c->tev[((int64_t)k * c->tmax + c->tcount[k]) * 2], c->stream);
+  c->tarmed[k] = false;
+  if (!c->tev || c->tcount[k] >= c->tmax) return;
+  const bool take = c->tseen[k] % c->tevery == 0;
+  ++c->tseen[k];
+  if (!take) return;
+  (void)hipEventRecord(c->tev[((int64_t)k * c->tmax + c->tcount[k]) * 2], c->stream);
+  c->tarmed[k] = true;
 }
 inline void timing_end(hvpic_ctx* c, int k) {
-  if (c->tev && c->tcount[k] < c->tmax) {
-    (void)hipEventRecord(c->tev[((int64_t)k * c->tmax + c->tcount[k]) * 2 + 1], c->stream);
-    ++c->tcount[k];
-  }
+  if (!c->tarmed[k]) return;
+  (void)hipEventRecord(c->tev[((int64_t)k * c->tmax + c->tcount[k]) * 2 + 1], c->stream);
+  ++c->tcount[k];
+  c->tarmed[k] = false;
 }
 int launch_init_workspace(hvpic_ctx* c);
 

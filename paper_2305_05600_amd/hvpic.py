@@ -74,7 +74,7 @@ def lib():
         L.hvpic_field_advance.argtypes = [vp, vp, vp, vp, vp, vp, vp, i32, vp]
         L.hvpic_smooth.argtypes = [vp, vp, i32, i32]
         L.hvpic_sync_status.argtypes = [vp, P(ctypes.c_uint32), P(ctypes.c_int64)]
-        L.hvpic_timing_enable.argtypes = [vp, i32]
+        L.hvpic_timing_enable.argtypes = [vp, i32, i32]
         L.hvpic_timing_read.argtypes = [vp, i32, P(ctypes.c_double), P(ctypes.c_int64)]
         L.hvpic_strerror.argtypes = [ctypes.c_int]
         L.hvpic_strerror.restype = ctypes.c_char_p
@@ -269,8 +269,8 @@ def hvpic_sync_status(ctx):
     return flags.value, tuple(counts)
 
 
-def hvpic_timing_enable(ctx, max_launches: int):
-    _check(lib().hvpic_timing_enable(ctx, max_launches), "hvpic_timing_enable")
+def hvpic_timing_enable(ctx, max_launches: int, every: int = 1):
+    _check(lib().hvpic_timing_enable(ctx, max_launches, every), "hvpic_timing_enable")
 
 
 def hvpic_timing_read(ctx, kernel: int):

@@ -144,10 +144,25 @@ def test_kernel_timing_counts_launches(mods):
     assert n == 3 and ms > 0.0
     assert H.hvpic_timing_read(c, H.KERNEL_DEPOSIT) == (0.0, 0)
     assert H.hvpic_timing_read(c, H.KERNEL_GATHER_PUSH) == (0.0, 0)  # count restarted
+    # sampled: launches 0, 2, 4, 6 of 7 (room for 10)
+    H.hvpic_timing_enable(c, 10, 2)
+    for _ in range(7):
+        g.step()
+    ms, n = H.hvpic_timing_read(c, H.KERNEL_GATHER_PUSH)
+    assert n == 4 and ms > 0.0
+    # at most max_launches timed ones: launches 0, 3 of 7
+    H.hvpic_timing_enable(c, 2, 3)
+    for _ in range(7):
+        g.step()
+    ms, n = H.hvpic_timing_read(c, H.KERNEL_SORT_SCATTER)
+    assert n == 2 and ms > 0.0
+    H.hvpic_timing_enable(c, 0)
     with pytest.raises(H.HvpicError):
         H.hvpic_timing_read(c, 7)
     with pytest.raises(H.HvpicError):
         H.hvpic_timing_enable(c, -1)
+    with pytest.raises(H.HvpicError):
+        H.hvpic_timing_enable(c, 3, 0)
     H.hvpic_timing_enable(c, 0)
     g.step()
     assert H.hvpic_timing_read(c, H.KERNEL_GATHER_PUSH) == (0.0, 0)
