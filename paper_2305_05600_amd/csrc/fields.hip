@@ -219,12 +219,11 @@ struct Eos {
 // (distinct buffers: neighbouring tiles read the halo of Bin while this one
 // writes).
 constexpr int kTX = 32, kTY = 8;
-// 256 threads per tile.  The tile's LDS is sized at launch: with a static
+// 512 threads per tile.  The tile's LDS is sized at launch: with a static
 // size the compiler would pad the VGPR allocation up to the occupancy that
-// the LDS allows (169 per wave instead of the 45 used), and such a tile
-// would not fit in the room that one retiring block of a concurrently
-// running particle kernel leaves.
-constexpr int kSubBlock = 256;
+// the LDS allows (169 per wave instead of the 64 used), and such tiles would
+// rarely find room on CUs busy with a concurrently running particle kernel.
+constexpr int kSubBlock = 512;
 
 // One LDS plane: the tile with a halo of HALO cells, row-major.
 template <int HALO>

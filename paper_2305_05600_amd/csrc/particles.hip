@@ -79,6 +79,7 @@ struct PushArgs {
   const int32_t* icell;
   const float *iox, *ioy, *ioz, *iux, *iuy, *iuz, *iw;
   float* wo;
+  bool off32;               // every source byte offset fits 32 bits (n < 2^30)
 };
 
 struct DepArgs {
@@ -755,7 +756,7 @@ __device__ __forceinline__ void load_group(const Args& A, int64_t b4, int64_t en
 
 // The same through the gather map A.perm (16-byte aligned, like the
 // destination store): four map entries, then element loads of the source.
-template <int NDIM>
+template <int NDIM, int PM>
 __device__ __forceinline__ void load_group_perm(const PushArgs& A, int64_t b4, int64_t end,
                                                 bool full, Group<NDIM>& G) {
   int src[4];
@@ -774,17 +775,37 @@ __device__ __forceinline__ void load_group_perm(const PushArgs& A, int64_t b4, i
   if (__ballot(bad) != 0) {
     if (bad) raise_flag(A.st, HVPIC_FLAG_BAD_INPUT, &A.st->bad_input);
   }
+  if (PM == 1) {
+    // one 32-bit byte offset per element shared by all arrays, whose bases
+    // stay in scalar registers (no 64-bit address per load)
+    auto at = [](const void* base, uint32_t o) {
+      return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(base) + o);
+    };
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int64_t e = src[q];
-    G.ca[q] = A.icell[e];
-    G.px[q] = A.iox[e];
-    G.py[q] = A.ioy[e];
-    if (NDIM == 3) G.pz[q] = A.ioz[e];
-    G.ux[q] = A.iux[e];
-    G.uy[q] = A.iuy[e];
-    G.uz[q] = A.iuz[e];
-    G.pw[q] = A.iw[e];
+    for (int q = 0; q < 4; ++q) {
+      const uint32_t o = (uint32_t)src[q] * 4u;
+      G.ca[q] = __float_as_int(at(A.icell, o));
+      G.px[q] = at(A.iox, o);
+      G.py[q] = at(A.ioy, o);
+      if (NDIM == 3) G.pz[q] = at(A.ioz, o);
+      G.ux[q] = at(A.iux, o);
+      G.uy[q] = at(A.iuy, o);
+      G.uz[q] = at(A.iuz, o);
+      G.pw[q] = at(A.iw, o);
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t e = src[q];
+      G.ca[q] = A.icell[e];
+      G.px[q] = A.iox[e];
+      G.py[q] = A.ioy[e];
+      if (NDIM == 3) G.pz[q] = A.ioz[e];
+      G.ux[q] = A.iux[e];
+      G.uy[q] = A.iuy[e];
+      G.uz[q] = A.iuz[e];
+      G.pw[q] = A.iw[e];
+    }
   }
   if (!full) __builtin_amdgcn_s_waitcnt(0x0F70);  // as in load_group
 }
@@ -1011,7 +1032,9 @@ __device__ void move_general(const PushArgs& A, float x, float y, float z, float
 // Fused gather + Boris push + move (+ mid-point deposit when DEP).
 // 2D: at most 128 VGPRs, so that four wavefronts per SIMD keep enough loads
 // in flight (the 3D windows already limit a CU to three blocks).
-template <int NDIM, int SHAPE, bool DEP>
+// PM: 0 reads and writes the store in place; 1 and 2 read it through the
+// gather map A.perm (1: all byte offsets of the source arrays fit 32 bits).
+template <int NDIM, int SHAPE, bool DEP, int PM>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NDIM == 2 ? 4 : 1)))
 void k_gather_push(PushArgs A) {
   constexpr int PPT = Chunk<NDIM>::PPT;
@@ -1027,7 +1050,7 @@ void k_gather_push(PushArgs A) {
   const int64_t base = (int64_t)xcd_chunk(blockIdx.x, gridDim.x) * Chunk<NDIM>::N;
   const int64_t end = min(base + (int64_t)Chunk<NDIM>::N, A.n);
   if (threadIdx.x == 0) {
-    if (A.perm) {
+    if (PM != 0) {
       // (entries outside [0, n) are flagged where the particles are loaded)
       const uint32_t e0 = (uint32_t)A.perm[base], e1 = (uint32_t)A.perm[end - 1];
       s_c[0] = A.icell[e0 < (uint32_t)A.n ? e0 : 0];
@@ -1039,7 +1062,7 @@ void k_gather_push(PushArgs A) {
   }
   __syncthreads();
   const bool want_diag = A.diag_part != nullptr;
-  const bool wq = DEP || want_diag || A.perm;  // the weights are needed
+  const bool wq = DEP || want_diag || PM != 0;  // the weights are needed
   // Wavefront wv owns particles [base + wv*64*PPT, +64*PPT); in each group
   // step lane l takes four consecutive ones, so a step is one coalesced
   // 1 KiB access per array.  The first step's particles are loaded during the
@@ -1049,8 +1072,8 @@ void k_gather_push(PushArgs A) {
   // a step of the wavefront is all in range, or it takes element-wise accesses
   auto step_full = [&](int h) { return A.vec && wb + h * 64 + 256 <= end; };
   Group<NDIM> cur;
-  if (A.perm)
-    load_group_perm<NDIM>(A, lb, end, step_full(0), cur);
+  if (PM != 0)
+    load_group_perm<NDIM, PM>(A, lb, end, step_full(0), cur);
   else
     load_group<NDIM>(A, lb, end, step_full(0), wq, cur);
   const int c0 = s_c[0], span = s_c[1] - s_c[0];
@@ -1195,11 +1218,11 @@ void k_gather_push(PushArgs A) {
     store4(A.ux, b4, end, full, ux);
     store4(A.uy, b4, end, full, uy);
     store4(A.uz, b4, end, full, uz);
-    if (A.perm) store4(A.wo, b4, end, full, pw);
+    if (PM != 0) store4(A.wo, b4, end, full, pw);
     // the next step's particles arrive during the flushes below
     if (h + 4 < PPT) {
-      if (A.perm)
-        load_group_perm<NDIM>(A, b4 + 256, end, step_full(h + 4), cur);
+      if (PM != 0)
+        load_group_perm<NDIM, PM>(A, b4 + 256, end, step_full(h + 4), cur);
       else
         load_group<NDIM>(A, b4 + 256, end, step_full(h + 4), wq, cur);
     }
@@ -1362,12 +1385,22 @@ Geo make_geo(const hvpic_ctx* c) {
   return g;
 }
 
+template <int NDIM, int SHAPE, int PM>
+void push_dispatch_pm(bool dep, dim3 grid, hipStream_t s, const PushArgs& A) {
+  if (dep)
+    hipLaunchKernelGGL((k_gather_push<NDIM, SHAPE, true, PM>), grid, dim3(kBlock), 0, s, A);
+  else
+    hipLaunchKernelGGL((k_gather_push<NDIM, SHAPE, false, PM>), grid, dim3(kBlock), 0, s, A);
+}
+
 template <int NDIM, int SHAPE>
 void push_dispatch(bool dep, dim3 grid, hipStream_t s, const PushArgs& A) {
-  if (dep)
-    hipLaunchKernelGGL((k_gather_push<NDIM, SHAPE, true>), grid, dim3(kBlock), 0, s, A);
+  if (!A.perm)
+    push_dispatch_pm<NDIM, SHAPE, 0>(dep, grid, s, A);
+  else if (A.off32)
+    push_dispatch_pm<NDIM, SHAPE, 1>(dep, grid, s, A);
   else
-    hipLaunchKernelGGL((k_gather_push<NDIM, SHAPE, false>), grid, dim3(kBlock), 0, s, A);
+    push_dispatch_pm<NDIM, SHAPE, 2>(dep, grid, s, A);
 }
 
 int zero2(hvpic_ctx* c, float* a, int64_t na, float* b, int64_t nb) {
@@ -1433,6 +1466,7 @@ int launch_push(hvpic_ctx* c, const hvpic_particles* in, const int32_t* perm,
   A.diag_part = diag_out ? c->push_part : nullptr;
   A.st = c->status;
   A.vec = particles_aligned16(p) && ((uintptr_t)perm & 15) == 0;
+  A.off32 = in->n < (int64_t(1) << 30);
   A.cs = cell_start;
   A.cnt = c->sort_cnt;
   A.perm = perm;
