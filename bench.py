@@ -7,9 +7,8 @@ FP32 particles and fields (seeded synthetic inputs).  One step = gather + push
 Faraday subcycle + extrapolation), FP64 diagnostics.
 
 Prints one JSON line.  `value` is ion pushes per second over whole steps with
-the inputs resident in HBM; the field advance of a step runs on a second
-stream beside the sort (they touch disjoint data; --no-overlap serialises
-them).  The sort leaves the stable order as a gather map that the next push
+the inputs resident in HBM; the sort of a step runs on a second stream beside
+the field advance (they touch disjoint data; --no-overlap serialises them).  The sort leaves the stable order as a gather map that the next push
 reads through, writing the pushed store in sorted order, so the particles
 cross HBM once per step (--no-gather-map moves the store in the sort instead;
 results are bit-identical).  `roofline` refers to the dominant kernel (the

@@ -114,6 +114,15 @@ int hvpic_init(const hvpic_params* params, void* hip_stream, void* workspace,
 /* Frees the host-side context only (never the caller's memory). */
 int hvpic_finalize(hvpic_ctx* ctx);
 
+/* Binds the context to another HIP stream (NULL = the null stream): later
+   calls enqueue their kernels there.  Nothing already enqueued is waited
+   for: ordering work between the old and the new stream (events) is the
+   caller's.  Lets one context's calls that touch disjoint data run on two
+   streams, e.g. the sort beside the field advance, while the move counts
+   and the rest of the workspace stay with the context.  Returns
+   HVPIC_ESTATE for an invalid context. */
+int hvpic_set_stream(hvpic_ctx* ctx, void* hip_stream);
+
 /* Gather + push (Sec. II.B eq:vadv, App. B eq:quadF): for each particle, E^n
    and B^n are interpolated at x^n with the context's shape, the velocity is
    advanced v^{n-1/2} -> v^{n+1/2} by the Boris method with

@@ -225,6 +225,12 @@ int hvpic_field_advance(hvpic_ctx* ctx, float* B, const float* n_half, const flo
   return launch_field_advance(ctx, B, n_half, J_half, n_prev, J_prev, E_out, mode, diag_out);
 }
 
+int hvpic_set_stream(hvpic_ctx* ctx, void* hip_stream) {
+  if (!ctx_ok(ctx)) return HVPIC_ESTATE;
+  ctx->stream = (hipStream_t)hip_stream;
+  return HVPIC_OK;
+}
+
 int hvpic_smooth(hvpic_ctx* ctx, float* F, int ncomp, int npasses) {
   if (!ctx_ok(ctx)) return HVPIC_ESTATE;
   if (!F || ncomp < 1 || ncomp > 3 || npasses < 0) return HVPIC_EINVAL;

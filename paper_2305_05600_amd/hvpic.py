@@ -21,7 +21,8 @@ HVPIC_OK, HVPIC_EINVAL, HVPIC_ENOMEM, HVPIC_EHIP, HVPIC_ESTATE = 0, -1, -2, -3, 
 HVPIC_SHAPE_NGP, HVPIC_SHAPE_QS = 0, 1
 FLAG_MOVE_GT1, FLAG_FLOOR_HIT, FLAG_NONFINITE, FLAG_BAD_INPUT = 1, 2, 4, 8
 
-EXPORTS = ("hvpic_workspace_bytes", "hvpic_init", "hvpic_finalize", "hvpic_gather_push",
+EXPORTS = ("hvpic_workspace_bytes", "hvpic_init", "hvpic_finalize", "hvpic_set_stream",
+           "hvpic_gather_push",
            "hvpic_gather_push_perm", "hvpic_sort", "hvpic_sort_perm", "hvpic_deposit",
            "hvpic_field_advance", "hvpic_smooth",
            "hvpic_sync_status", "hvpic_timing_enable", "hvpic_timing_read", "hvpic_strerror")
@@ -65,6 +66,7 @@ def lib():
         L.hvpic_workspace_bytes.argtypes = [P(HvpicParams), P(ctypes.c_size_t)]
         L.hvpic_init.argtypes = [P(HvpicParams), vp, vp, P(vp)]
         L.hvpic_finalize.argtypes = [vp]
+        L.hvpic_set_stream.argtypes = [vp, vp]
         L.hvpic_gather_push.argtypes = [vp, P(HvpicParticles), vp, vp, vp, vp, vp, vp]
         L.hvpic_gather_push_perm.argtypes = [vp, P(HvpicParticles), vp, P(HvpicParticles), vp, vp,
                                              vp, vp, vp, vp]
@@ -179,6 +181,11 @@ def hvpic_init(params: HvpicParams, stream, workspace: torch.Tensor):
 
 def hvpic_finalize(ctx):
     _check(lib().hvpic_finalize(ctx), "hvpic_finalize")
+
+
+def hvpic_set_stream(ctx, stream):
+    _check(lib().hvpic_set_stream(ctx, None if stream is None else ctypes.c_void_p(stream)),
+           "hvpic_set_stream")
     _NCELL.pop(ctx.value, None)
 
 
@@ -296,6 +303,11 @@ class Context:
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(device)
         self.ctx = hvpic_init(self.params, self.stream.cuda_stream, self.workspace)
+
+    def set_stream(self, stream):
+        """Later calls of this context enqueue on `stream` (ordering is the caller's)."""
+        hvpic_set_stream(self.ctx, stream.cuda_stream)
+        self.stream = stream
 
     def close(self):
         if self.ctx is not None:

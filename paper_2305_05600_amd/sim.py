@@ -12,11 +12,14 @@ v^{n-1/2}; B^n and E^n; the moments n^{n-1/2}, J^{n-1/2}.  One step:
   5. hvpic_field_advance B^n -> B^{n+1} (subcycled), E^{n+1} from the
                          extrapolated moments
 
-Steps 2 and 4-5 touch disjoint data (the particle store and cell_start versus
-the moments, B and E), so with `overlap` the field work runs on a second
-stream and context, ordered by events: it waits for the moments of step 1,
-and the next push waits for its E and B.  The sort and the latency-bound
-field kernels then share the GPU.
+Step 2 and steps 4-5 touch disjoint data (the particle store, the map and
+cell_start versus the moments, B and E), so with `overlap` (fused deposit)
+the sort runs on a side stream, ordered by events: it waits for the push,
+and the next push waits for it.  The push and the field advance, the step's
+critical path, stay in order on the particle stream, with no event between
+them; the sort's latency-bound kernels share the GPU with the field
+advance's.  The context is rebound to the side stream for the sort call, so
+the move counts the push left in its workspace are the ones the sort reads.
 
 With `gather_map` (fused deposit only) the sort leaves the stable order as a
 gather map instead of moving the store (hvpic_sort_perm), and the next push
@@ -107,11 +110,14 @@ class GpuSim:
         self.overlap = overlap
         n = int(parts["cell"].size)
         self.np = n
-        # particle work on s_p; field work on s_f (the same stream unless overlapping)
+        # push and field work on s_p; the sort on s_s (the same stream unless
+        # overlapping; the unfused deposit needs the sorted store, so there
+        # the sort stays in line)
+        self.overlap = overlap and fused
         self.s_p = torch.cuda.Stream(device)
-        self.s_f = torch.cuda.Stream(device) if overlap else self.s_p
+        self.s_s = torch.cuda.Stream(device) if self.overlap else self.s_p
         self.ctx = H.Context(cfg, max(n, 1), device, stream=self.s_p)
-        self.ctx_f = H.Context(cfg, 1, device, stream=self.s_f) if overlap else self.ctx
+        self.ctx_f = self.ctx
         nc = cfg.ncell
         self.p = H.Particles.from_numpy(parts, cfg.ndim, max(n, 1), device)
         self.q = H.Particles(cfg.ndim, max(n, 1), device)
@@ -130,9 +136,9 @@ class GpuSim:
         self.diagnostics = diagnostics
         self.push_diag = torch.zeros(4, dtype=torch.float64, device=device)
         self.field_diag = torch.zeros(2, dtype=torch.float64, device=device)
-        self.ev_moments = StreamEvent()    # moments of the step are written
-        self.ev_fields = StreamEvent()     # E, B of the step are written
-        self.ev_particles = StreamEvent()  # the step's particle work is done
+        self.ev_push = StreamEvent()  # the push of the step is done (the sort may start)
+        self.ev_sort = StreamEvent()  # the sort of the step is done (the next push may start)
+        self.ev_step = StreamEvent()  # the step's work on the particle stream is done
         # the tensors above (and the contexts' workspaces) were filled on the
         # current stream
         torch.cuda.current_stream(device).synchronize()
@@ -141,29 +147,21 @@ class GpuSim:
         H.hvpic_sort(c, self.p, self.q, None, self.cs, full=True)
         self.p, self.q = self.q, self.p
         # the sorted store read through the identity map
-        self.perm = (torch.arange(max(n, 1), dtype=torch.int32, device=device)
-                     if gather_map else None)
+        self.perm = None
+        if gather_map:
+            with torch.cuda.stream(self.s_p):
+                self.perm = torch.arange(max(n, 1), dtype=torch.int32, device=device)
         H.hvpic_deposit(c, self.p, self.cs, 0.0, self.n_prev, self.J_prev)
-        self._moments_ready()
-        self._fields_after_moments(mode=1, n_half=self.n_prev, J_half=self.J_prev)
+        self._fields(mode=1, n_half=self.n_prev, J_half=self.J_prev)
         self.nstep = 0
         cur = torch.cuda.current_stream(device)
-        self.ev_particles.record(self.s_p)
-        self.ev_particles.wait(cur)
-        self.ev_fields.wait(cur)
+        self.ev_step.record(self.s_p)
+        self.ev_step.wait(cur)
 
-    def _moments_ready(self):
-        """Marks the moments of the step as written (on the particle stream)."""
-        if self.s_f is not self.s_p:
-            self.ev_moments.record(self.s_p)
-
-    def _fields_after_moments(self, mode, n_half, J_half):
-        """Smoothing of the moments and the field advance, on the field stream
-        once the moments are there (_moments_ready before)."""
+    def _fields(self, mode, n_half, J_half):
+        """Smoothing of the moments and the field advance (particle stream)."""
         cfg = self.cfg
         cf = self.ctx_f.ctx
-        if self.s_f is not self.s_p:
-            self.ev_moments.wait(self.s_f)
         if cfg.nsmooth:
             H.hvpic_smooth(cf, n_half, cfg.nsmooth)
             H.hvpic_smooth(cf, J_half, cfg.nsmooth)
@@ -174,16 +172,39 @@ class GpuSim:
         else:
             H.hvpic_field_advance(cf, self.B, n_half, J_half, self.n_prev, self.J_prev, self.E,
                                   mode=0, diag_out=diag)
-        self.ev_fields.record(self.s_f)
+
+    def _sort(self):
+        """The neighbour-move sort of the pushed store: the gather map over q
+        (gather map) or the store moved into q; on the side stream once the
+        push is done."""
+        side = self.s_s is not self.s_p
+        if side:
+            self.ev_push.record(self.s_p)
+            self.ev_push.wait(self.s_s)
+            self.ctx.set_stream(self.s_s)
+        try:
+            c = self.ctx.ctx
+            if self.gather_map:
+                H.hvpic_sort_perm(c, self.q, self.cs, self.perm, self.cs_alt)
+            else:
+                H.hvpic_sort(c, self.p, self.q, self.cs, self.cs_alt, full=False)
+        finally:
+            if side:
+                self.ctx.set_stream(self.s_p)
+                self.ev_sort.record(self.s_s)
+        self.p, self.q = self.q, self.p
+        self.cs, self.cs_alt = self.cs_alt, self.cs
 
     def step(self):
         cfg = self.cfg
         c = self.ctx.ctx
         cur = torch.cuda.current_stream(self.device)
-        # E^n and B^n are written, and the moment buffers free, once the last
-        # field advance has ended.  (Writes into the simulation's tensors by
-        # the caller must be finished first: see synchronize().)
-        self.ev_fields.wait(self.s_p)
+        # the last sort's map (or store) and cell_start are written, and its
+        # workspace counts consumed, before the push.  (Writes into the
+        # simulation's tensors by the caller must be finished first: see
+        # synchronize().)
+        if self.s_s is not self.s_p:
+            self.ev_sort.wait(self.s_p)
         E, B = self.E, self.B
         if cfg.nsmooth:
             with torch.cuda.stream(self.s_p):
@@ -198,50 +219,36 @@ class GpuSim:
             # next order over q
             H.hvpic_gather_push_perm(c, self.p, self.perm, self.q, self.cs, E, B, self.n_half,
                                      self.J_half, pd)
-            self._moments_ready()
-            H.hvpic_sort_perm(c, self.q, self.cs, self.perm, self.cs_alt)
-            self.p, self.q = self.q, self.p
-            self.cs, self.cs_alt = self.cs_alt, self.cs
         elif self.fused:
             H.hvpic_gather_push(c, self.p, self.cs, E, B, self.n_half, self.J_half, pd)
-            self._moments_ready()
         else:
             H.hvpic_gather_push(c, self.p, self.cs, E, B, None, None, pd)
-        if not self.gather_map:
-            # the sort is enqueued before the field work, so that the field
-            # stream's launches do not hold back the particle stream's
-            H.hvpic_sort(c, self.p, self.q, self.cs, self.cs_alt, full=False)
-            self.p, self.q = self.q, self.p
-            self.cs, self.cs_alt = self.cs_alt, self.cs
+        # enqueued before the field work, so that it starts right after the push
+        self._sort()
         if not self.fused:
             H.hvpic_deposit(c, self.p, self.cs, 0.5 * cfg.dt, self.n_half, self.J_half)
-            self._moments_ready()
-        self._fields_after_moments(mode=0, n_half=self.n_half, J_half=self.J_half)
+        self._fields(mode=0, n_half=self.n_half, J_half=self.J_half)
         self.n_prev, self.n_half = self.n_half, self.n_prev
         self.J_prev, self.J_half = self.J_half, self.J_prev
         self.nstep += 1
         # later work on the caller's stream (reads of E, B, the moments, the
         # store) sees this step; the next step's launches do not wait for it
-        self.ev_particles.record(self.s_p)
-        self.ev_particles.wait(cur)
-        if self.s_f is not self.s_p:
-            self.ev_fields.wait(cur)
+        self.ev_step.record(self.s_p)
+        self.ev_step.wait(cur)
+        if self.s_s is not self.s_p:
+            self.ev_sort.wait(cur)
 
     def synchronize(self):
         """Waits for all queued work (host and the caller's stream).  Call it
         after writing into the simulation's tensors from another stream."""
         torch.cuda.current_stream(self.device).synchronize()
         self.s_p.synchronize()
-        self.s_f.synchronize()
+        self.s_s.synchronize()
 
     def status(self):
-        """Sticky status bits and counts of both contexts (waits for both streams)."""
-        flags, counts = H.hvpic_sync_status(self.ctx.ctx)
-        if self.ctx_f is not self.ctx:
-            f2, c2 = H.hvpic_sync_status(self.ctx_f.ctx)
-            flags |= f2
-            counts = tuple(a + b for a, b in zip(counts, c2))
-        return flags, counts
+        """Sticky status bits and counts (waits for both streams)."""
+        self.synchronize()
+        return H.hvpic_sync_status(self.ctx.ctx)
 
     def particles(self) -> dict:
         """The particle store in sorted order (host copy)."""

@@ -73,6 +73,7 @@ def test_init_rejects_bad_arguments_without_device_work(H):
                                     None) == H.HVPIC_ESTATE
     assert L.hvpic_finalize(None) == H.HVPIC_ESTATE
     assert H.hvpic_strerror(H.HVPIC_EINVAL) == "invalid argument"
+    assert L.hvpic_set_stream(None, None) == H.HVPIC_ESTATE
     assert L.hvpic_timing_enable(None, 4, 1) == H.HVPIC_ESTATE
     d, k = ctypes.c_double(), ctypes.c_int64()
     assert L.hvpic_timing_read(None, 0, ctypes.byref(d), ctypes.byref(k)) == H.HVPIC_ESTATE
