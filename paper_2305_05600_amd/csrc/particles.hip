@@ -1329,8 +1329,10 @@ __global__ void k_zero(float* __restrict__ a, int64_t na, float* __restrict__ b,
 }
 
 // FP64 moment accumulators -> FP32 outputs; leaves the accumulators at zero
-// for the next deposit.
-__global__ __launch_bounds__(kBlock) void k_moments_out(double* __restrict__ acc, int ncell,
+// for the next deposit.  Blocks of 1024 threads, so that block 0 sums the
+// push's per-block diagnostic partials in one round of loads.
+constexpr int kMomBlock = 1024;
+__global__ __launch_bounds__(kMomBlock) void k_moments_out(double* __restrict__ acc, int ncell,
                                                         float* __restrict__ n,
                                                         float* __restrict__ J,
                                                         const double* part, int nparts,
@@ -1424,8 +1426,8 @@ void zero_counts(hvpic_ctx* c) {
 // FP64 accumulators -> n, J; with diag_out also the push diagnostics from
 // nparts per-block partials.
 void moments_out(hvpic_ctx* c, float* n, float* J, int nparts = 0, double* diag_out = nullptr) {
-  const int blocks = (int)std::min<int64_t>(ceil_div(4ll * c->ncell, kBlock), 2048);
-  hipLaunchKernelGGL(k_moments_out, dim3(blocks), dim3(kBlock), 0, c->stream, c->mom_acc,
+  const int blocks = (int)std::min<int64_t>(ceil_div(4ll * c->ncell, kMomBlock), 512);
+  hipLaunchKernelGGL(k_moments_out, dim3(blocks), dim3(kMomBlock), 0, c->stream, c->mom_acc,
                      c->ncell, n, J, (const double*)c->push_part, nparts, diag_out);
 }
 
