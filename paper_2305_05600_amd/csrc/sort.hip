@@ -73,6 +73,27 @@ __device__ __forceinline__ int direction(int key, int i, int j, int k, const Sor
   return (di + 1) + 3 * (dj + 1) + (NDIM == 3 ? 9 * (dk + 1) : 0);
 }
 
+// The same for a 2D old cell a whose neighbours need no wrap (an interior
+// cell, one or more cells from every edge): from the index difference by two
+// compares instead of two divisions.  The neighbours of such a cell are
+// exactly the differences 0, +-1, +-nx, +-nx +- 1.
+__device__ __forceinline__ int direction_interior2d(int key, int a, int nx) {
+  const int delta = key - a;
+  const int dj = delta >= nx - 1 ? 1 : (delta <= 1 - nx ? -1 : 0);
+  const int di = delta - dj * nx;
+  return di >= -1 && di <= 1 ? (di + 1) + 3 * (dj + 1) : -1;
+}
+
+// Whether the wavefront's old cells a0 .. a0+na-1 are all 2D interior cells.
+template <int NDIM>
+__device__ __forceinline__ bool wave_interior(int a0, int na, const SortGeo& g) {
+  if (NDIM != 2 || g.nx < 3 || g.ny < 3) return false;
+  int i0, j0, k0, i1, j1, k1;
+  ijk(a0, g, i0, j0, k0);
+  ijk(a0 + na - 1, g, i1, j1, k1);
+  return i0 >= 1 && i1 <= g.nx - 2 && j0 >= 1 && j1 <= g.ny - 2 && j0 == j1;
+}
+
 // New cell reached from old cell a by direction d (wrapped).
 template <int NDIM>
 __device__ __forceinline__ int step_cell(int i, int j, int k, int d, const SortGeo& g) {
@@ -619,6 +640,7 @@ __global__ __launch_bounds__(kBlock) void k_nb_scatter(const int32_t* __restrict
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  const bool interior = wave_interior<NDIM>(a0, na, g);
   const int64_t pb = __builtin_amdgcn_readlane(bnd, 0), pe = __builtin_amdgcn_readlane(bnd, na);
   for (int64_t q0 = pb; q0 < pe; q0 += 64 * kScatterBatches) {
    int keys[kScatterBatches];
@@ -640,9 +662,14 @@ __global__ __launch_bounds__(kBlock) void k_nb_scatter(const int32_t* __restrict
     bool ok = false;
     const int m = cell_in_wave(p, bnd, na);
     if (valid) {
-      int i, j, k;
-      ijk(a0 + m, g, i, j, k);
-      const int d = direction<NDIM>(key, i, j, k, g);
+      int d;
+      if (interior) {
+        d = direction_interior2d(key, a0 + m, g.nx);
+      } else {
+        int i, j, k;
+        ijk(a0 + m, g, i, j, k);
+        d = direction<NDIM>(key, i, j, k, g);
+      }
       ok = d >= 0;
       code = (m << NB) | (ok ? d : 0);
     }
