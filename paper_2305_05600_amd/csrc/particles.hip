@@ -598,6 +598,31 @@ __device__ __forceinline__ int shl1_i(int v, int fill) {
   return __builtin_amdgcn_update_dpp(fill, v, 0x101, 0xF, 0xF, false);
 }
 
+// v += v[lane - D] * m for every home sum (lanes with no source add 0),
+// within each 16-lane row.
+template <int D, int T>
+__device__ __forceinline__ void scan_level(float (&acc)[T][4], float m) {
+  static_assert(D == 1 || D == 2 || D == 4 || D == 8, "row shift");
+  asm volatile("s_nop 1");
+#pragma unroll
+  for (int t = 0; t < T; ++t)
+#pragma unroll
+    for (int ch = 0; ch < 4; ++ch) {
+      if (D == 1)
+        asm volatile("v_fmac_f32_dpp %0, %0, %1 row_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1"
+                     : "+v"(acc[t][ch]) : "v"(m));
+      else if (D == 2)
+        asm volatile("v_fmac_f32_dpp %0, %0, %1 row_shr:2 row_mask:0xf bank_mask:0xf bound_ctrl:1"
+                     : "+v"(acc[t][ch]) : "v"(m));
+      else if (D == 4)
+        asm volatile("v_fmac_f32_dpp %0, %0, %1 row_shr:4 row_mask:0xf bank_mask:0xf bound_ctrl:1"
+                     : "+v"(acc[t][ch]) : "v"(m));
+      else
+        asm volatile("v_fmac_f32_dpp %0, %0, %1 row_shr:8 row_mask:0xf bank_mask:0xf bound_ctrl:1"
+                     : "+v"(acc[t][ch]) : "v"(m));
+    }
+}
+
 // End of a group step: the home sums go to the window.  Consecutive lanes
 // hold consecutive particles, so lanes with the same home cell form runs.
 // An inclusive segmented scan within each 16-lane row (DPP, with segment-head
@@ -623,17 +648,16 @@ __device__ __forceinline__ void home_flush(Home<NDIM, SHAPE>& H, const WinLds& w
   m4 = f ? 0.0f : 1.0f;
   f |= shr_i<4>(f, 1);
   m8 = f ? 0.0f : 1.0f;
-#pragma unroll
-  for (int t = 0; t < T; ++t)
-#pragma unroll
-    for (int ch = 0; ch < 4; ++ch) {
-      float v = H.acc[t][ch];
-      v = fmaf(shr_f<1>(v), m1, v);
-      v = fmaf(shr_f<2>(v), m2, v);
-      v = fmaf(shr_f<4>(v), m4, v);
-      v = fmaf(shr_f<8>(v), m8, v);
-      H.acc[t][ch] = v;
-    }
+  // One level for all sums at a time, each v += shr(v) * m as a single FMA
+  // with the DPP move on its first operand (the compiler emits a separate
+  // move for each).  A level's first read of a sum follows its last write by
+  // all the other sums' instructions, except after the deposit's own writes:
+  // the s_nop before each level covers the two wait states a DPP read needs
+  // after a VALU write of its operand.
+  scan_level<1, T>(H.acc, m1);
+  scan_level<2, T>(H.acc, m2);
+  scan_level<4, T>(H.acc, m4);
+  scan_level<8, T>(H.acc, m8);
   if (h >= 0 && last) {
     int s[T];
     stencil_slots<NDIM, SHAPE>(h, wl.wrap[h], s);
