@@ -8,7 +8,9 @@ Faraday subcycle + extrapolation), FP64 diagnostics.
 
 Prints one JSON line.  `value` is ion pushes per second over whole steps with
 the inputs resident in HBM; the sort of a step runs on a second stream beside
-the field advance (they touch disjoint data; --no-overlap serialises them).  The sort leaves the stable order as a gather map that the next push
+the field advance (they touch disjoint data; --no-overlap serialises them).
+The steps do not order the caller's stream one by one; the timed region ends
+with a synchronisation of every stream.  The sort leaves the stable order as a gather map that the next push
 reads through, writing the pushed store in sorted order, so the particles
 cross HBM once per step (--no-gather-map moves the store in the sort instead;
 results are bit-identical).  `roofline` refers to the dominant kernel (the
@@ -122,8 +124,9 @@ def main() -> int:
     g = S.GpuSim(cfg, parts, B, fused=not args.unfused, overlap=not args.no_overlap,
                  gather_map=not (args.unfused or args.no_gather_map))
     mode = "gather map" if g.gather_map else "in place"
+    # the steps need not order the caller's stream: synchronize() follows
     for _ in range(args.warmup):
-        g.step()
+        g.step(order_caller=False)
     g.synchronize()
     c = g.ctx.ctx
     # HIP events recorded by the library on its own stream right around every
@@ -135,7 +138,7 @@ def main() -> int:
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        g.step()
+        g.step(order_caller=False)
     g.synchronize()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
