@@ -82,7 +82,7 @@ Layout workspace_layout(const hvpic_params* p) {
   // cell-row blocks (>= 16 cells each)
   L.push_part = off;
   off += align256(sizeof(double) * 4 * std::max(ceil_div(cap, 1024), ceil_div(nc, 16)));
-  L.field_part = off; off += align256(sizeof(double) * 4 * ceil_div(nc, kBlock));
+  L.field_part = off; off += align256(sizeof(double) * 4 * field_part_slots(p));
   L.sort_cnt = off;  off += align256(sizeof(uint32_t) * ndir * nc);
   L.sort_blk = off;  off += align256(sizeof(uint32_t) * nblk);
   L.rkey0 = off;     off += align256(sizeof(uint32_t) * cap);

@@ -232,9 +232,10 @@ struct Plane {
   __device__ static int at(int lx, int ly) { return (ly + HALO) * W + lx + HALO; }
 };
 
-template <int K>
+template <int K, bool FINAL>
 struct SubLds {
-  static constexpr int HB = 4 * K;
+  // the final launch keeps its last substep's B on a 1-cell halo (for curl B)
+  static constexpr int HB = 4 * K + (FINAL ? 1 : 0);
   using PB = Plane<HB>;      // B hi (and the pressure while the frozen terms are formed)
   using PA = Plane<HB - 1>;  // six frozen-term planes, then E (Ea, later Eb)
   using PS = Plane<HB - 2>;  // B*
@@ -244,12 +245,44 @@ struct SubLds {
   static_assert(3 * PA::N + 3 * PS::N >= PB::N, "pressure plane overlays E and B*");
 };
 
-template <int K, bool HAS_LIN>
+// FP64 sums of the four values over the block (fixed order), thread 0 writes
+// them to out[0..3].
+__device__ void tile_partial(double* v, double* out) {
+  __shared__ double s_red[kSubBlock / 64][4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    for (int o = 32; o > 0; o >>= 1) v[k] += __shfl_xor(v[k], o);
+  const int wid = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0)
+    for (int k = 0; k < 4; ++k) s_red[wid][k] = v[k];
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 4; ++k) {
+      double t = 0.0;
+      for (int w = 0; w < kSubBlock / 64; ++w) t += s_red[w][k];
+      out[k] = t;
+    }
+}
+
+// Per-step outputs of the final launch (FINAL): E from the moments
+// extrapolated to the full step, n_eff = 1.5 nm - 0.5 np, J_eff = 1.5 Jm -
+// 0.5 Jp, the final B = hi + lo into Bfin, the count of cells of nm below the
+// floor, and per-tile FP64 partials {sum |B|^2, sum B} into part.
+struct SubFinal {
+  const float* np;
+  const float* Jp;
+  float* E;
+  float* Bfin;
+  double* part;
+  Status* st;
+};
+
+template <int K, bool HAS_LIN, bool FINAL>
 __global__ __launch_bounds__(kSubBlock) void k_field_sub2d(
     const float* __restrict__ Bin, const float* __restrict__ Lin, float* __restrict__ Bout,
     float* __restrict__ Lout, const float* __restrict__ nm, const float* __restrict__ Jm, float h,
-    float eta, FGeo g, Eos eos) {
-  using L = SubLds<K>;
+    float eta, FGeo g, Eos eos, SubFinal F) {
+  using L = SubLds<K, FINAL>;
   using PB = typename L::PB;
   using PA = typename L::PA;
   using PS = typename L::PS;
@@ -279,6 +312,27 @@ __global__ __launch_bounds__(kSubBlock) void k_field_sub2d(
   constexpr int IA = (PA::N + kSubBlock - 1) / kSubBlock;
   constexpr int IL = (PL::N + kSubBlock - 1) / kSubBlock;
   float vb[IB][4], va[IA][4], vl[IL][3];
+  // final launch: each of the first kTX*kTY threads owns one tile cell and
+  // loads its extrapolation inputs here, with the others (n at the cell and
+  // its four neighbours, J at the cell)
+  constexpr int NF = FINAL ? 16 : 1;
+  float vf[NF];
+  const int fx = (int)threadIdx.x % kTX, fy = (int)threadIdx.x / kTX;
+  const bool fown = FINAL && (int)threadIdx.x < kTX * kTY;
+  if (FINAL) {
+    const int cf[5] = {gidx(fx, fy), gidx(fx + 1, fy), gidx(fx - 1, fy), gidx(fx, fy + 1),
+                       gidx(fx, fy - 1)};
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+      vf[q] = nm[cf[q]];
+      vf[5 + q] = F.np[cf[q]];
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      vf[10 + a] = Jm[a * nc + cf[0]];
+      vf[13 + a] = F.Jp[a * nc + cf[0]];
+    }
+  }
 #pragma unroll
   for (int u = 0; u < IB; ++u) {
     const int t = min((int)threadIdx.x + u * kSubBlock, PB::N - 1);
@@ -359,7 +413,7 @@ __global__ __launch_bounds__(kSubBlock) void k_field_sub2d(
   const float hh = 0.5f * h;
 #pragma unroll
   for (int s = 0; s < K; ++s) {
-    const int hin = 4 * (K - s);  // halo of this substep's input B
+    const int hin = 4 * (K - s) + (FINAL ? 1 : 0);  // halo of this substep's input B
     // Ea on halo hin-1
     {
       const int r = hin - 1, W = kTX + 2 * r, N = W * (kTY + 2 * r);
@@ -424,8 +478,9 @@ __global__ __launch_bounds__(kSubBlock) void k_field_sub2d(
         const float c2 = (sE[PA::N + e + 1] - sE[PA::N + e - 1]) * g.idx2 -
                          (sE[e + PA::W] - sE[e - PA::W]) * g.idy2;
         const float d[3] = {-h * c0, -h * c1, -h * c2};
-        if (s + 1 < K) {
-          // next substep's input, in place: this cell alone is read here
+        if (s + 1 < K || FINAL) {
+          // next substep's input (or the final B on a 1-cell halo), in
+          // place: this cell alone is read here
 #pragma unroll
           for (int a = 0; a < 3; ++a) {
             const float hi = sB[a * PB::N + b];
@@ -449,7 +504,61 @@ __global__ __launch_bounds__(kSubBlock) void k_field_sub2d(
         }
       }
     }
-    if (s + 1 < K) __syncthreads();
+    if (s + 1 < K || FINAL) __syncthreads();
+  }
+  if (FINAL) {
+    // E at the tile's cells from the final B = hi + lo (curl on the 1-cell
+    // halo) and the extrapolated frozen terms, as k_field_final forms them
+    const int nc2 = g.ncell;
+    bool below = false;
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    const int x = tx0 + fx, y = ty0 + fy;
+    const bool live = fown && x < g.nx && y < g.ny;
+    if (live) {
+      auto Bf = [&](int a, int lx, int ly) {
+        const int b = PB::at(lx, ly), l = PL::at(lx, ly);
+        return sB[a * PB::N + b] + sL[a * PL::N + l];
+      };
+      const float ca = 1.5f, cb = -0.5f;
+      float ne[5];
+#pragma unroll
+      for (int q = 0; q < 5; ++q) ne[q] = ca * vf[q] + cb * vf[5 + q];
+      below = vf[0] < eos.nfloor;
+      auto pres = [&](float n) {
+        return pressure(n, eos.nfloor, eos.te_n0, eos.n0, eos.gam, eos.iso);
+      };
+      const float inv = (float)(1.0 / (double)fmaxf(ne[0], eos.nfloor));
+      float u[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) u[a] = (ca * vf[10 + a] + cb * vf[13 + a]) * inv;
+      const float gp0 = -(pres(ne[1]) - pres(ne[2])) * g.idx2 * inv;
+      const float gp1 = -(pres(ne[3]) - pres(ne[4])) * g.idy2 * inv;
+      // curl B at the cell (2D: no z derivatives)
+      const float j0 = (Bf(2, fx, fy + 1) - Bf(2, fx, fy - 1)) * g.idy2;
+      const float j1 = -(Bf(2, fx + 1, fy) - Bf(2, fx - 1, fy)) * g.idx2;
+      const float j2 = (Bf(1, fx + 1, fy) - Bf(1, fx - 1, fy)) * g.idx2 -
+                       (Bf(0, fx, fy + 1) - Bf(0, fx, fy - 1)) * g.idy2;
+      const float b0 = Bf(0, fx, fy), b1 = Bf(1, fx, fy), b2 = Bf(2, fx, fy);
+      const float w0 = j0 * inv - u[0], w1 = j1 * inv - u[1], w2 = j2 * inv - u[2];
+      const int c = x + g.nx * y;
+      F.E[c] = (w1 * b2 - w2 * b1) + gp0 + eta * j0;
+      F.E[nc2 + c] = (w2 * b0 - w0 * b2) + gp1 + eta * j1;
+      F.E[2 * nc2 + c] = (w0 * b1 - w1 * b0) + 0.f + eta * j2;
+      F.Bfin[c] = b0;
+      F.Bfin[nc2 + c] = b1;
+      F.Bfin[2 * nc2 + c] = b2;
+      const double d0 = b0, d1 = b1, d2 = b2;
+      v[0] = d0 * d0 + d1 * d1 + d2 * d2;
+      v[1] = d0;
+      v[2] = d1;
+      v[3] = d2;
+    }
+    const uint64_t m = __ballot(live && below);
+    if ((threadIdx.x & 63) == 0 && m) {
+      atomicOr(&F.st->flags, (uint32_t)HVPIC_FLAG_FLOOR_HIT);
+      atomicAdd(&F.st->floor_hits, (unsigned long long)__builtin_popcountll(m));
+    }
+    if (F.part) tile_partial(v, F.part + 4 * ((int64_t)blockIdx.y * gridDim.x + blockIdx.x));
   }
 }
 
@@ -607,31 +716,54 @@ int field_impl(hvpic_ctx* c, float* B, const float* n_half, const float* J_half,
   const float eta = (float)c->p.eta;
   const float* fh = B;        // final B = fh + fl
   const float* fl = nullptr;
+  bool fused_final = false;   // the last 2D tile launch wrote E, B and the partials
   if (mode == 0 && c->p.nsub > 0) {
     const float h = (float)(c->p.dt / c->p.nsub);
     if (NDIM == 2) {
       // two substeps per launch (one for an odd last one), the frozen terms
       // formed in each tile; the caller's B is only read (first launch)
       const dim3 tiles((unsigned)ceil_div(c->p.nx, kTX), (unsigned)ceil_div(c->p.ny, kTY));
-      const size_t lds2 = sizeof(float) * SubLds<2>::TOTAL, lds1 = sizeof(float) * SubLds<1>::TOTAL;
+      const size_t lds2 = sizeof(float) * SubLds<2, false>::TOTAL,
+                   lds1 = sizeof(float) * SubLds<1, false>::TOTAL,
+                   lds2f = sizeof(float) * SubLds<2, true>::TOTAL,
+                   lds1f = sizeof(float) * SubLds<1, true>::TOTAL;
       const float* sh = B;
       const float* sl = nullptr;
       float* dh = Xh;
       float* dl = Xl;
+      // With two or more launches the last one also writes E, the final B
+      // and the diagnostic partials (the first reads the caller's B, which
+      // the final one writes: never the same launch).
+      fused_final = c->p.nsub >= 3;
+      SubFinal F{};
+      F.np = n_prev;
+      F.Jp = J_prev;
+      F.E = E_out;
+      F.Bfin = B;
+      F.part = diag_out ? c->field_part : nullptr;
+      F.st = c->status;
+      const SubFinal none{};
       for (int m = 0; m < c->p.nsub;) {
         const bool two = c->p.nsub - m >= 2;
-        if (two && sl)
-          hipLaunchKernelGGL((k_field_sub2d<2, true>), tiles, dim3(kSubBlock), lds2, s, sh, sl, dh,
-                             dl, n_half, J_half, h, eta, g, eos);
+        const bool fin = fused_final && m + (two ? 2 : 1) >= c->p.nsub;
+        if (fin && two)
+          hipLaunchKernelGGL((k_field_sub2d<2, true, true>), tiles, dim3(kSubBlock), lds2f, s, sh,
+                             sl, dh, dl, n_half, J_half, h, eta, g, eos, F);
+        else if (fin)
+          hipLaunchKernelGGL((k_field_sub2d<1, true, true>), tiles, dim3(kSubBlock), lds1f, s, sh,
+                             sl, dh, dl, n_half, J_half, h, eta, g, eos, F);
+        else if (two && sl)
+          hipLaunchKernelGGL((k_field_sub2d<2, true, false>), tiles, dim3(kSubBlock), lds2, s, sh,
+                             sl, dh, dl, n_half, J_half, h, eta, g, eos, none);
         else if (two)
-          hipLaunchKernelGGL((k_field_sub2d<2, false>), tiles, dim3(kSubBlock), lds2, s, sh, sl, dh,
-                             dl, n_half, J_half, h, eta, g, eos);
+          hipLaunchKernelGGL((k_field_sub2d<2, false, false>), tiles, dim3(kSubBlock), lds2, s, sh,
+                             sl, dh, dl, n_half, J_half, h, eta, g, eos, none);
         else if (sl)
-          hipLaunchKernelGGL((k_field_sub2d<1, true>), tiles, dim3(kSubBlock), lds1, s, sh, sl, dh,
-                             dl, n_half, J_half, h, eta, g, eos);
+          hipLaunchKernelGGL((k_field_sub2d<1, true, false>), tiles, dim3(kSubBlock), lds1, s, sh,
+                             sl, dh, dl, n_half, J_half, h, eta, g, eos, none);
         else
-          hipLaunchKernelGGL((k_field_sub2d<1, false>), tiles, dim3(kSubBlock), lds1, s, sh, sl, dh,
-                             dl, n_half, J_half, h, eta, g, eos);
+          hipLaunchKernelGGL((k_field_sub2d<1, false, false>), tiles, dim3(kSubBlock), lds1, s, sh,
+                             sl, dh, dl, n_half, J_half, h, eta, g, eos, none);
         m += two ? 2 : 1;
         sh = dh;
         sl = dl;
@@ -661,6 +793,15 @@ int field_impl(hvpic_ctx* c, float* B, const float* n_half, const float* J_half,
   // E^{n+1} from the extrapolated moments (mode 0) or E from the given ones
   // (mode 1), the final B, the floor count of n_half and the diagnostics
   const double V = c->p.dx * c->p.dy * c->p.dz;
+  if (fused_final) {
+    if (diag_out) {
+      const dim3 tiles((unsigned)ceil_div(c->p.nx, kTX), (unsigned)ceil_div(c->p.ny, kTY));
+      hipLaunchKernelGGL(k_field_diag_final, dim3(1), dim3(1024), 0, s,
+                         (const double*)c->field_part, (int)(tiles.x * tiles.y), diag_out,
+                         0.5 * V, 1.0 / (double)nc);
+    }
+    return hipGetLastError() == hipSuccess ? HVPIC_OK : HVPIC_EHIP;
+  }
   auto final_kernel = [&](auto kern) {
     hipLaunchKernelGGL(kern, grid, blk, 0, s, fh, fl, fh == B ? nullptr : B, n_half, n_prev,
                        J_half, J_prev, 1.5f, -0.5f, eta, g, eos, E_out,
@@ -679,6 +820,13 @@ int field_impl(hvpic_ctx* c, float* B, const float* n_half, const float* J_half,
 }
 
 }  // namespace
+
+int64_t field_part_slots(const hvpic_params* p) {
+  const int64_t nc = (int64_t)p->nx * p->ny * p->nz;
+  const int64_t blocks = ceil_div(nc, kBlock);
+  const int64_t tiles = p->ndim == 2 ? ceil_div(p->nx, kTX) * ceil_div(p->ny, kTY) : 0;
+  return std::max(blocks, tiles);
+}
 
 int launch_field_advance(hvpic_ctx* c, float* B, const float* n_half, const float* J_half,
                          const float* n_prev, const float* J_prev, float* E_out, int mode,

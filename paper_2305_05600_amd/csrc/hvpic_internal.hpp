@@ -129,7 +129,7 @@ struct hvpic_ctx {
   // workspace carve-out
   hvpic::Status* status;
   double* push_part;     // per-block FP64 partials of the push diagnostics [blocks][4]
-  double* field_part;    // per-block FP64 partials of the field diagnostics [blocks][4]
+  double* field_part;    // per-block FP64 partials of the field diagnostics [slots][4]
   uint32_t* sort_cnt;    // [ncell][3^ndim]
   int32_t* sort_blk;     // scan block sums
   uint32_t* rkey[2];     // radix keys   [np_capacity]
@@ -174,6 +174,9 @@ int launch_field_advance(hvpic_ctx* c, float* B, const float* n_half, const floa
                          const float* n_prev, const float* J_prev, float* E_out, int mode,
                          double* diag_out);
 int launch_smooth(hvpic_ctx* c, float* F, int ncomp, int npasses);
+// Per-block partial slots the field diagnostics need (the larger of the
+// output kernel's blocks and the 2D subcycle's tiles).
+int64_t field_part_slots(const hvpic_params* p);
 int launch_zero(hvpic_ctx* c, float* p, int64_t count);
 void zero_counts(hvpic_ctx* c);  // enqueues the clearing of sort_cnt
 
