@@ -365,12 +365,26 @@ __global__ __launch_bounds__(kBlock) void k_nb_bases(uint32_t* __restrict__ cnt,
       src[d] = step_cell<NDIM>(i, j, k, ND - 1 - d, g);
       n[d] = cnt[(int64_t)src[d] * ND + d];
     }
-    // groups in increasing old-cell index (ties only between empty groups)
-    for (int d = 0; d < ND; ++d) {
+    // groups in increasing old-cell index (ties only between empty groups).
+    // For a cell whose neighbours need no wrap that order is d = ND-1 .. 0
+    // (the source index falls as d rises), so the slots are a suffix sum.
+    const bool interior = g.nx >= 3 && g.ny >= 3 && i >= 1 && i <= g.nx - 2 && j >= 1 &&
+                          j <= g.ny - 2 &&
+                          (NDIM == 2 || (g.nz >= 3 && k >= 1 && k <= g.nz - 2));
+    if (interior) {
       uint32_t before = 0;
-      for (int e = 0; e < ND; ++e)
-        if (src[e] < src[d] || (src[e] == src[d] && e < d)) before += n[e];
-      cnt[(int64_t)src[d] * ND + d] = start + before;
+#pragma unroll
+      for (int d = ND - 1; d >= 0; --d) {
+        cnt[(int64_t)src[d] * ND + d] = start + before;
+        before += n[d];
+      }
+    } else {
+      for (int d = 0; d < ND; ++d) {
+        uint32_t before = 0;
+        for (int e = 0; e < ND; ++e)
+          if (src[e] < src[d] || (src[e] == src[d] && e < d)) before += n[e];
+        cnt[(int64_t)src[d] * ND + d] = start + before;
+      }
     }
   }
 }
