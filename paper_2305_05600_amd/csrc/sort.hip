@@ -145,6 +145,13 @@ __device__ __forceinline__ int cell_in_wave(int64_t p, int bnd, int na) {
   for (int q = 1; q < na; ++q) m += p >= (int64_t)__builtin_amdgcn_readlane(bnd, q) ? 1 : 0;
   return m;
 }
+// The same for an unsigned 32-bit position (cell_start values are
+// non-negative int32, checked by the caller).
+__device__ __forceinline__ int cell_in_wave32(uint32_t p, int bnd, int na) {
+  int m = 0;
+  for (int q = 1; q < na; ++q) m += p >= (uint32_t)__builtin_amdgcn_readlane(bnd, q) ? 1 : 0;
+  return m;
+}
 
 template <int NDIM>
 __global__ __launch_bounds__(kBlock) void k_nb_count(const int32_t* __restrict__ key,
@@ -655,13 +662,17 @@ __global__ __launch_bounds__(kBlock) void k_nb_scatter(const int32_t* __restrict
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   const bool interior = wave_interior<NDIM>(a0, na, g);
-  const int64_t pb = __builtin_amdgcn_readlane(bnd, 0), pe = __builtin_amdgcn_readlane(bnd, na);
-  for (int64_t q0 = pb; q0 < pe; q0 += 64 * kScatterBatches) {
+  // positions in unsigned 32 bits: cell_start (and so n) is below 2^31, so
+  // a batch's positions (up to 255 past pe) cannot wrap
+  const uint32_t pb = (uint32_t)__builtin_amdgcn_readlane(bnd, 0);
+  const uint32_t pe = (uint32_t)__builtin_amdgcn_readlane(bnd, na);
+  const uint32_t n32 = (uint32_t)n;
+  for (uint32_t q0 = pb; q0 < pe; q0 += 64 * kScatterBatches) {
    int keys[kScatterBatches];
    float vals[kScatterBatches][NF > 0 ? NF : 1];
 #pragma unroll
    for (int b = 0; b < kScatterBatches; ++b) {
-     const int64_t p = q0 + b * 64 + lane;
+     const uint32_t p = q0 + b * 64 + lane;
      const bool v = p < pe;
      keys[b] = v ? in.cell[p] : 0;
 #pragma unroll
@@ -669,12 +680,12 @@ __global__ __launch_bounds__(kBlock) void k_nb_scatter(const int32_t* __restrict
    }
 #pragma unroll
    for (int b = 0; b < kScatterBatches; ++b) {
-    const int64_t p = q0 + b * 64 + lane;
+    const uint32_t p = q0 + b * 64 + lane;
     const bool valid = p < pe;
     int code = 0;
     const int key = keys[b];
     bool ok = false;
-    const int m = cell_in_wave(p, bnd, na);
+    const int m = cell_in_wave32(p, bnd, na);
     if (valid) {
       int d;
       if (interior) {
@@ -699,7 +710,7 @@ __global__ __launch_bounds__(kBlock) void k_nb_scatter(const int32_t* __restrict
     __builtin_amdgcn_wave_barrier();
     if (ok && before == 0) s_next[wid][slot] += (uint32_t)__builtin_popcountll(mine);
     __builtin_amdgcn_wave_barrier();
-    if (ok && dst < n) {
+    if (ok && dst < n32) {
       if (PERM) {
         out.perm[dst] = (int32_t)p;
       } else {
