@@ -509,7 +509,6 @@ __global__ __launch_bounds__(kSubBlock) void k_field_sub2d(
   if (FINAL) {
     // E at the tile's cells from the final B = hi + lo (curl on the 1-cell
     // halo) and the extrapolated frozen terms, as k_field_final forms them
-    const int nc2 = g.ncell;
     bool below = false;
     double v[4] = {0.0, 0.0, 0.0, 0.0};
     const int x = tx0 + fx, y = ty0 + fy;
@@ -542,11 +541,11 @@ __global__ __launch_bounds__(kSubBlock) void k_field_sub2d(
       const float w0 = j0 * inv - u[0], w1 = j1 * inv - u[1], w2 = j2 * inv - u[2];
       const int c = x + g.nx * y;
       F.E[c] = (w1 * b2 - w2 * b1) + gp0 + eta * j0;
-      F.E[nc2 + c] = (w2 * b0 - w0 * b2) + gp1 + eta * j1;
-      F.E[2 * nc2 + c] = (w0 * b1 - w1 * b0) + 0.f + eta * j2;
+      F.E[nc + c] = (w2 * b0 - w0 * b2) + gp1 + eta * j1;
+      F.E[2 * nc + c] = (w0 * b1 - w1 * b0) + 0.f + eta * j2;
       F.Bfin[c] = b0;
-      F.Bfin[nc2 + c] = b1;
-      F.Bfin[2 * nc2 + c] = b2;
+      F.Bfin[nc + c] = b1;
+      F.Bfin[2 * nc + c] = b2;
       const double d0 = b0, d1 = b1, d2 = b2;
       v[0] = d0 * d0 + d1 * d1 + d2 * d2;
       v[1] = d0;
