@@ -36,6 +36,7 @@ n^0, J^0).  This module only orders the calls and swaps buffers.
 from __future__ import annotations
 
 import ctypes
+import os
 
 import numpy as np
 import torch
@@ -49,19 +50,26 @@ _hip = None
 
 def _hip_runtime():
     """The HIP runtime already loaded in the process (torch's and the
-    library's share the soname)."""
+    library's share it; RTLD_NOLOAD never loads a second copy), or None."""
     global _hip
     if _hip is None:
-        lib = ctypes.CDLL("libamdhip64.so.7")
-        for name, args in (("hipEventCreateWithFlags", (ctypes.c_void_p, ctypes.c_uint)),
-                           ("hipEventRecord", (ctypes.c_void_p, ctypes.c_void_p)),
-                           ("hipStreamWaitEvent", (ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint)),
-                           ("hipEventDestroy", (ctypes.c_void_p,))):
-            f = getattr(lib, name)
-            f.argtypes = args
-            f.restype = ctypes.c_int
-        _hip = lib
-    return _hip
+        _hip = False
+        for soname in ("libamdhip64.so.7", "libamdhip64.so.6", "libamdhip64.so"):
+            try:
+                lib = ctypes.CDLL(soname, mode=os.RTLD_NOLOAD | os.RTLD_LAZY)
+            except OSError:
+                continue
+            for name, args in (("hipEventCreateWithFlags", (ctypes.c_void_p, ctypes.c_uint)),
+                               ("hipEventRecord", (ctypes.c_void_p, ctypes.c_void_p)),
+                               ("hipStreamWaitEvent",
+                                (ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint)),
+                               ("hipEventDestroy", (ctypes.c_void_p,))):
+                f = getattr(lib, name)
+                f.argtypes = args
+                f.restype = ctypes.c_int
+            _hip = lib
+            break
+    return _hip or None
 
 
 class StreamEvent:
@@ -75,8 +83,12 @@ class StreamEvent:
     def __init__(self):
         self._hip = _hip_runtime()
         self.h = ctypes.c_void_p()
-        self._check(self._hip.hipEventCreateWithFlags(
-            ctypes.byref(self.h), _HIP_EVENT_DISABLE_TIMING | _HIP_EVENT_DISABLE_SYSTEM_FENCE))
+        # without the runtime's entry points: a plain torch event (the same
+        # ordering, with the system-scope fence)
+        self._torch = torch.cuda.Event() if self._hip is None else None
+        if self._torch is None:
+            self._check(self._hip.hipEventCreateWithFlags(
+                ctypes.byref(self.h), _HIP_EVENT_DISABLE_TIMING | _HIP_EVENT_DISABLE_SYSTEM_FENCE))
 
     @staticmethod
     def _check(rc):
@@ -84,10 +96,16 @@ class StreamEvent:
             raise RuntimeError(f"HIP event call failed with error {rc}")
 
     def record(self, stream: torch.cuda.Stream):
+        if self._torch is not None:
+            self._torch.record(stream)
+            return
         self._check(self._hip.hipEventRecord(self.h, ctypes.c_void_p(stream.cuda_stream)))
 
     def wait(self, stream: torch.cuda.Stream):
         """Makes later work on `stream` wait for the last record (none: no wait)."""
+        if self._torch is not None:
+            stream.wait_event(self._torch)
+            return
         self._check(self._hip.hipStreamWaitEvent(ctypes.c_void_p(stream.cuda_stream), self.h, 0))
 
     def __del__(self):

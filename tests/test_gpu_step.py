@@ -205,6 +205,25 @@ def test_steps_without_caller_order(mods):
         assert np.array_equal(pa[k], pb[k]), k
 
 
+def test_torch_event_fallback(mods, monkeypatch):
+    """Without the HIP runtime's entry points the stream ordering falls back to
+    torch events: the same results bit for bit."""
+    H, S = mods
+    announce("torch_event_fallback")
+    cfg, parts, B = W.periodic_alfven()
+    monkeypatch.setattr(S, "_hip", False)
+    a = S.GpuSim(cfg, parts, B, fused=True, overlap=True, gather_map=True)
+    assert a.ev_push._torch is not None
+    monkeypatch.undo()
+    b = S.GpuSim(cfg, parts, B, fused=True, overlap=True, gather_map=True)
+    assert b.ev_push._torch is None
+    for _ in range(4):
+        a.step()
+        b.step()
+    for name in ("E", "B", "n_prev", "J_prev", "cs", "push_diag", "field_diag"):
+        assert torch.equal(getattr(a, name), getattr(b, name)), name
+
+
 @pytest.mark.parametrize("case", ["alfven", "beam3d", "harris"])
 @pytest.mark.parametrize("overlap", [False, True])
 def test_gather_map_matches_plain(mods, case, overlap):
