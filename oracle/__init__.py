@@ -181,10 +181,10 @@ def ohm(cfg, B, n, Ji):
 
 
 def field_advance(cfg, B, n_half, J_half, n_prev=None, J_prev=None, mode=0):
-    """Returns (B_new, E_out, diag[2], status); B is not modified."""
+    """Returns (B_new, E_out, diag[3] = {W_B, W_dB, W_e}, status); B is not modified."""
     B = f64(B).copy()
     E = np.zeros((3, cfg.ncell))
-    diag = np.zeros(2)
+    diag = np.zeros(3)
     st = OrcStatus()
     n_prev = f64(n_half if n_prev is None else n_prev)
     J_prev = f64(J_half if J_prev is None else J_prev)

@@ -328,10 +328,21 @@ void orc_ohm(const orc_params* p, const double* B, const double* n, const double
   free(J);
 }
 
-static void field_energy(const orc_params* p, const double* B, double diag[2]) {
+/* Field and electron energies of the state a field advance leaves behind:
+     W_B  = 1/2 sum |B|^2 V_c               (magnetic energy, mu0 = 1)
+     W_dB = 1/2 sum |B - <B>|^2 V_c          (energy of the fluctuations)
+     W_e  = electron internal energy of the density n the call's E was formed
+            from, with the floor applied as in Ohm's law:
+              gamma = 1:  te sum n ln(n/n0) V_c   (isothermal free energy)
+              else:       sum p_e V_c / (gamma - 1),  p_e = n0 te (n/n0)^gamma.
+   W_e is the electron term of the energy budget of the hybrid equations
+   (Sec. II.A): with eq:ohm, Ampere and Faraday the pressure work -u_e . grad p_e
+   is the time derivative of exactly this energy (electron continuity). */
+static void field_energy(const orc_params* p, const double* B, const double* n,
+                         double diag[3]) {
   int64_t nc = ncell_of(p);
   double V = cell_volume(p);
-  double mean[3] = {0, 0, 0}, wb = 0.0, wdb = 0.0;
+  double mean[3] = {0, 0, 0}, wb = 0.0, wdb = 0.0, we = 0.0;
   for (int a = 0; a < 3; ++a) {
     for (int64_t c = 0; c < nc; ++c) mean[a] += B[c + a * nc];
     mean[a] /= (double)nc;
@@ -342,8 +353,16 @@ static void field_energy(const orc_params* p, const double* B, double diag[2]) {
       wb += 0.5 * b * b * V;
       wdb += 0.5 * (b - mean[a]) * (b - mean[a]) * V;
     }
+  for (int64_t c = 0; c < nc; ++c) {
+    double ne = n[c] > p->n_floor ? n[c] : p->n_floor;
+    if (p->gamma_e == 1.0)
+      we += p->te * ne * log(ne / p->n0) * V;
+    else
+      we += p->n0 * p->te * pow(ne / p->n0, p->gamma_e) * V / (p->gamma_e - 1.0);
+  }
   diag[0] = wb;
   diag[1] = wdb;
+  diag[2] = we;
 }
 
 /* Faraday dB/dt = -curl E, subcycled nsub times per particle step (Sec. II.A).
@@ -355,14 +374,14 @@ static void field_energy(const orc_params* p, const double* B, double diag[2]) {
    and n the same way, and E^{n+1} = Ohm(B^{n+1}, n^{n+1}, J^{n+1}). */
 void orc_field_advance(const orc_params* p, double* B, const double* n_half,
                        const double* J_half, const double* n_prev, const double* J_prev,
-                       double* E_out, int32_t mode, double diag[2], orc_status* st) {
+                       double* E_out, int32_t mode, double diag[3], orc_status* st) {
   int64_t nc = ncell_of(p);
   if (st)
     for (int64_t c = 0; c < nc; ++c)
       if (n_half[c] < p->n_floor) st->floor_hits += 1;
   if (mode == 1) {
     orc_ohm(p, B, n_half, J_half, E_out);
-    if (diag) field_energy(p, B, diag);
+    if (diag) field_energy(p, B, n_half, diag);
     return;
   }
   size_t v3 = sizeof(double) * 3 * (size_t)nc;
@@ -382,7 +401,7 @@ void orc_field_advance(const orc_params* p, double* B, const double* n_half,
   for (int64_t c = 0; c < nc; ++c) n1[c] = 1.5 * n_half[c] - 0.5 * n_prev[c];
   for (int64_t c = 0; c < 3 * nc; ++c) Bs[c] = 1.5 * J_half[c] - 0.5 * J_prev[c];
   orc_ohm(p, B, n1, Bs, E_out);
-  if (diag) field_energy(p, B, diag);
+  if (diag) field_energy(p, B, n1, diag);
   free(n1);
   free(Ea);
   free(C);

@@ -87,11 +87,13 @@ void orc_ohm(const orc_params* p, const double* B, const double* n,
 /* Field advance.  mode 0: nsub RK2-midpoint Faraday substeps of B with the
    moments frozen at n+1/2, then J_i, n extrapolated to n+1 and
    E_out = Ohm(B^{n+1}, n^{n+1}, J^{n+1}).  mode 1: E_out = Ohm(B, n_half,
-   J_half) only.  diag[2] = {W_B, W_dB} of the B the call leaves behind. */
+   J_half) only.  diag[3] = {W_B, W_dB, W_e}: the magnetic energy and its
+   fluctuation part for the B the call leaves behind, and the electron
+   internal energy of the density E_out was formed from (floored). */
 void orc_field_advance(const orc_params* p, double* B, const double* n_half,
                        const double* J_half, const double* n_prev,
                        const double* J_prev, double* E_out, int32_t mode,
-                       double diag[2], orc_status* st);
+                       double diag[3], orc_status* st);
 
 #ifdef __cplusplus
 }

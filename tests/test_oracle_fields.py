@@ -184,3 +184,78 @@ def test_smoothing_transfer_function(ndim):
             g *= ((1 + math.cos(kz * cfg.dz)) / 2) ** npass
         assert np.allclose(S, 0.7 + g * (F - 0.7), atol=1e-14)
         assert S.mean() == pytest.approx(F.mean(), rel=1e-14)
+
+
+@pytest.mark.parametrize("gamma", [1.0, 5.0 / 3.0])
+@pytest.mark.parametrize("mode", [0, 1])
+def test_electron_energy_closed_forms(gamma, mode):
+    """W_e (third field diagnostic) for densities with a closed-form sum: half
+    the cells at n1, half at n2, with n2 below the floor (so the floored value
+    n_f enters).  gamma = 1: te sum n_f ln(n_f/n0) V; else
+    sum n0 te (n_f/n0)^gamma V / (gamma - 1).  Mode 0 takes the density
+    extrapolated to the full step, 3/2 n_half - 1/2 n_prev."""
+    cfg = _cfg(nx=6, ny=5, nsub=2, te=0.37, gamma_e=gamma, n0=1.3, n_floor=0.1)
+    V = cfg.dx * cfg.dy * cfg.dz
+    n1, n2 = 2.1, 0.04  # n2 < floor
+    lvl = np.where(np.arange(cfg.ncell) % 2 == 0, n1, n2)
+    if mode == 0:
+        # 3/2 n_half - 1/2 n_prev = lvl with n_prev = 2 lvl  ->  n_half = 4/3 lvl
+        n_half, n_prev = lvl * 4.0 / 3.0, 2.0 * lvl
+    else:
+        n_half, n_prev = lvl, None
+    B = np.zeros((3, cfg.ncell))
+    B[0] = 1.0
+    J = np.zeros((3, cfg.ncell))
+    _, _, diag, st = O.field_advance(cfg, B, n_half, J, n_prev, J, mode=mode)
+    half = cfg.ncell // 2
+    if gamma == 1.0:
+        per = lambda n: cfg.te * n * math.log(n / cfg.n0)
+    else:
+        per = lambda n: cfg.n0 * cfg.te * (n / cfg.n0) ** gamma / (gamma - 1.0)
+    expect = half * V * (per(n1) + per(cfg.n_floor))
+    assert diag[2] == pytest.approx(expect, rel=1e-13)
+
+
+def test_electron_energy_uniform_is_extensive():
+    """A uniform density n gives W_e = te n ln(n/n0) times the box volume; n = n0
+    gives 0."""
+    cfg = _cfg(nx=7, ny=3, nsub=1, te=0.5, n0=1.0)
+    Vbox = cfg.ncell * cfg.dx * cfg.dy * cfg.dz
+    B = np.zeros((3, cfg.ncell))
+    J = np.zeros((3, cfg.ncell))
+    for n in (1.0, 0.6, 3.0):
+        nn = np.full(cfg.ncell, n)
+        _, _, diag, _ = O.field_advance(cfg, B, nn, J, mode=1)
+        assert diag[2] == pytest.approx(0.5 * n * math.log(n) * Vbox, rel=1e-13, abs=1e-15)
+
+
+def test_fluctuation_energy_of_one_mode():
+    """W_dB of B = B0 + A cos(k x) yhat (a mode with 0 < m < nx/2):
+    sum cos^2 = ncell/2, so W_dB = A^2 ncell V / 4 and W_B = W_dB + |B0|^2 ncell V / 2."""
+    cfg = _cfg(nx=24, ny=5, nsub=0, te=0.0)
+    V = cfg.dx * cfg.dy * cfg.dz
+    x, _, _ = W.cell_centres(cfg)
+    A, B0 = 0.3, np.array([1.2, -0.4, 0.7])
+    B = np.zeros((3, cfg.ncell)) + B0[:, None]
+    B[1] += A * np.cos(2 * math.pi * 5 * x / (cfg.nx * cfg.dx))
+    n = np.ones(cfg.ncell)
+    J = np.zeros((3, cfg.ncell))
+    _, _, diag, _ = O.field_advance(cfg, B, n, J, n, J, mode=0)
+    assert diag[1] == pytest.approx(A * A * cfg.ncell * V / 4, rel=1e-12)
+    assert diag[0] == pytest.approx(diag[1] + (B0 @ B0) * cfg.ncell * V / 2, rel=1e-12)
+
+
+def test_floor_hits_count_cells_below_the_floor():
+    """The floor-hit count is the number of cells of n_half below n_floor (7 of
+    them here by construction; cells exactly at the floor do not count)."""
+    cfg = _cfg(nx=9, ny=4, nsub=1, n_floor=0.05)
+    n = np.full(cfg.ncell, 1.0)
+    below = [0, 3, 8, 11, 17, 30, 35]
+    n[below] = [0.0, 0.01, 0.049, 0.02, 0.001, 0.04999, 0.03]
+    n[5] = 0.05  # at the floor: not a hit
+    B = np.zeros((3, cfg.ncell))
+    B[0] = 1.0
+    J = np.zeros((3, cfg.ncell))
+    for mode in (0, 1):
+        _, _, _, st = O.field_advance(cfg, B, n, J, n, J, mode=mode)
+        assert st.floor_hits == len(below)

@@ -189,3 +189,62 @@ def test_nonfinite_is_counted_and_kept_in_place():
     _, st = O.push(cfg, p, Eg, Bg)
     assert st.nonfinite >= 1
     assert p["cell"][0] == 17
+
+
+def _many(cfg, u, w):
+    n = len(w)
+    p = {"cell": np.arange(n, dtype=np.int32) * 7 % cfg.ncell, "ox": np.zeros(n),
+         "oy": np.zeros(n), "ux": u[:, 0].copy(), "uy": u[:, 1].copy(),
+         "uz": u[:, 2].copy(), "w": np.asarray(w, float)}
+    if cfg.ndim == 3:
+        p["oz"] = np.zeros(n)
+    return p
+
+
+@pytest.mark.parametrize("qs,ms", [(1.0, 1.0), (2.0, 4.0), (-1.0, 0.5)])
+def test_push_diagnostics_in_uniform_b(qs, ms):
+    """The push's diagnostics K = sum 1/2 m w v^{n-1/2}.v^{n+1/2} and
+    P = sum m w vbar against closed forms of a pure gyration (E = 0, B = B zhat):
+    v_perp turns by theta = 2 atan(|q|B dt/(2m)) and keeps its length, v_par is
+    kept, so v^{n-1/2}.v^{n+1/2} = v_perp^2 cos(theta) + v_par^2 and the mean
+    velocity is v_perp cos(theta/2) along the direction half-way round, plus
+    v_par."""
+    cfg = _cfg(qs=qs, ms=ms, dt=0.1)
+    Bz = 2.5
+    E, B = _uniform_fields(cfg, (0, 0, 0), (0, 0, Bz))
+    rng = np.random.Generator(np.random.PCG64(5))
+    u = rng.normal(0, 1.5, (40, 3))
+    w = rng.uniform(0.2, 2.0, 40)
+    p = _many(cfg, u, w)
+    diag, _ = O.push(cfg, p, E, B)
+    theta = 2 * math.atan(abs(qs) * Bz * cfg.dt / (2 * ms))
+    vperp2 = u[:, 0] ** 2 + u[:, 1] ** 2
+    K = 0.5 * ms * np.sum(w * (vperp2 * math.cos(theta) + u[:, 2] ** 2))
+    # rotation sense: clockwise about B for q > 0 (angle -theta/2 half-way)
+    phi = -math.copysign(theta, qs) / 2
+    c, s = math.cos(phi), math.sin(phi)
+    vbx = math.cos(theta / 2) * (c * u[:, 0] - s * u[:, 1])
+    vby = math.cos(theta / 2) * (s * u[:, 0] + c * u[:, 1])
+    P = ms * np.array([np.sum(w * vbx), np.sum(w * vby), np.sum(w * u[:, 2])])
+    assert diag[0] == pytest.approx(K, rel=1e-12)
+    assert np.allclose(diag[1:], P, rtol=0, atol=1e-12 * np.abs(P).max())
+
+
+def test_push_diagnostics_under_uniform_e():
+    """B = 0: each velocity gets the exact kick (q/m) E dt, so
+    K = sum 1/2 m w v.(v + (q/m) E dt) and P = sum m w (v + (q/m) E dt / 2),
+    summed with the particle weights."""
+    qs, ms = 1.5, 3.0
+    cfg = _cfg(qs=qs, ms=ms, dt=0.2)
+    Ev = np.array([0.3, -1.1, 0.45])
+    E, B = _uniform_fields(cfg, Ev, (0, 0, 0))
+    rng = np.random.Generator(np.random.PCG64(6))
+    u = rng.normal(0, 1.0, (25, 3))
+    w = rng.uniform(0.5, 1.5, 25)
+    p = _many(cfg, u, w)
+    diag, _ = O.push(cfg, p, E, B)
+    kick = qs / ms * cfg.dt * Ev
+    K = 0.5 * ms * np.sum(w * np.sum(u * (u + kick), axis=1))
+    P = ms * (w @ (u + 0.5 * kick))
+    assert diag[0] == pytest.approx(K, rel=1e-12)
+    assert np.allclose(diag[1:], P, rtol=1e-12)
