@@ -119,14 +119,9 @@ void orc_boris(double a, const double E[3], const double B[3], double v[3]) {
 /* Offsets live in [-1,1) in half-cell units.  After xi' = xi + displacement,
    the shift s is the unique integer with xi' - 2 s in [-1,1): a particle that
    lands exactly on the right face (+1) belongs to the next cell at -1.
-   Returns s and updates *xi.  A non-finite or runaway xi' (|xi'| >= 1e6) keeps
-   the particle where it was and counts it in *bad. */
-static int reindex(double* xi, double disp, int64_t* gt1, int64_t* bad) {
+   Returns s and updates *xi (which must be finite). */
+static int reindex(double* xi, double disp) {
   double x = *xi + disp;
-  if (!(fabs(x) < 1.0e6)) {
-    if (bad) ++*bad;
-    return 0;
-  }
   int s;
   if (x >= 1.0) {
     s = x < 3.0 ? 1 : (int)floor((x + 1.0) * 0.5);
@@ -138,9 +133,20 @@ static int reindex(double* xi, double disp, int64_t* gt1, int64_t* bad) {
   x -= 2.0 * s;
   while (x >= 1.0) { x -= 2.0; ++s; }
   while (x < -1.0) { x += 2.0; --s; }
-  if ((s > 1 || s < -1) && gt1) ++*gt1;
   *xi = x;
   return s;
+}
+
+/* Moves a point with offsets off[0..ndim) by disp (half-cell units) and
+   writes the cell shifts to s.  If the new offset along any axis is
+   non-finite or runaway (|xi'| >= 1e6 half-cells) the whole point stays
+   where it was (shifts 0, offsets unchanged) and 0 is returned; else 1. */
+static int move_point(int ndim, double off[3], const double disp[3], int s[3]) {
+  s[0] = s[1] = s[2] = 0;
+  for (int a = 0; a < ndim; ++a)
+    if (!(fabs(off[a] + disp[a]) < 1.0e6)) return 0;
+  for (int a = 0; a < ndim; ++a) s[a] = reindex(&off[a], disp[a]);
+  return 1;
 }
 
 void orc_push(const orc_params* p, int64_t np, int32_t* cell, double* ox, double* oy,
@@ -163,16 +169,24 @@ void orc_push(const orc_params* p, int64_t np, int32_t* cell, double* ox, double
     uy[n] = v[1];
     uz[n] = v[2];
     /* x^{n+1} = x^n + v^{n+1/2} dt; in half-cell units the displacement
-       along an axis of width h is 2 v dt / h. */
+       along an axis of width h is 2 v dt / h.  A non-finite or runaway move
+       leaves the particle where it was, counted once. */
     int i, j, k;
     ijk_of(p, cell[n], &i, &j, &k);
-    int64_t far = 0;
-    int si = reindex(&ox[n], 2.0 * v[0] * p->dt / p->dx, &far, &bad);
-    int sj = reindex(&oy[n], 2.0 * v[1] * p->dt / p->dy, &far, &bad);
-    int sk = 0;
-    if (p->ndim == 3) sk = reindex(&oz[n], 2.0 * v[2] * p->dt / p->dz, &far, &bad);
-    if (far) ++gt1; /* counted once per particle */
-    cell[n] = (int32_t)cell_of(p, i + si, j + sj, k + sk);
+    double off[3] = {ox[n], oy[n], p->ndim == 3 ? oz[n] : 0.0};
+    double disp[3] = {2.0 * v[0] * p->dt / p->dx, 2.0 * v[1] * p->dt / p->dy,
+                      2.0 * v[2] * p->dt / p->dz};
+    int s[3];
+    if (!move_point(p->ndim, off, disp, s)) {
+      ++bad;
+      continue;
+    }
+    if (s[0] > 1 || s[0] < -1 || s[1] > 1 || s[1] < -1 || s[2] > 1 || s[2] < -1)
+      ++gt1; /* counted once per particle */
+    ox[n] = off[0];
+    oy[n] = off[1];
+    if (p->ndim == 3) oz[n] = off[2];
+    cell[n] = (int32_t)cell_of(p, i + s[0], j + s[1], k + s[2]);
   }
   if (diag) {
     diag[0] = K;
@@ -236,11 +250,17 @@ void orc_deposit(const orc_params* p, int64_t np, const int32_t* cell, const dou
     double u[3] = {ux[q], uy[q], uz[q]};
     int i, j, k;
     ijk_of(p, cell[q], &i, &j, &k);
-    double dx = ox[q], dy = oy[q], dz = (p->ndim == 3) ? oz[q] : 0.0;
-    /* x^{n+1/2} = x^{n+1} - (dt/2) v^{n+1/2}, re-indexed like a move. */
-    i += reindex(&dx, -2.0 * half_dt_back * u[0] / p->dx, NULL, NULL);
-    j += reindex(&dy, -2.0 * half_dt_back * u[1] / p->dy, NULL, NULL);
-    if (p->ndim == 3) k += reindex(&dz, -2.0 * half_dt_back * u[2] / p->dz, NULL, NULL);
+    /* x^{n+1/2} = x^{n+1} - (dt/2) v^{n+1/2}, re-indexed like a move (a
+       non-finite or runaway back step deposits at x itself). */
+    double off[3] = {ox[q], oy[q], (p->ndim == 3) ? oz[q] : 0.0};
+    double disp[3] = {-2.0 * half_dt_back * u[0] / p->dx, -2.0 * half_dt_back * u[1] / p->dy,
+                      -2.0 * half_dt_back * u[2] / p->dz};
+    int s[3];
+    move_point(p->ndim, off, disp, s);
+    i += s[0];
+    j += s[1];
+    k += s[2];
+    double dx = off[0], dy = off[1], dz = off[2];
     double qwV = p->qs * w[q] / V;
     if (p->shape == ORC_SHAPE_NGP) {
       accumulate(nc, n, J, cell_of(p, i, j, k), qwV, 1.0, u);

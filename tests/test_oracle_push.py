@@ -183,12 +183,25 @@ def test_free_streaming_positions(ndim):
 
 
 def test_nonfinite_is_counted_and_kept_in_place():
+    """A particle whose move is non-finite or runaway (1e6 half-cells or more)
+    along any axis stays where it was -- cell and every offset -- and is
+    counted once; its neighbours in the store move normally."""
     cfg = _cfg()
-    p = _one(cfg, 17, 0.2, -0.1, (np.nan, 0.0, 0.0))
-    Eg, Bg = _uniform_fields(cfg, (0, 0, 0), (0, 0, 1))
+    Eg, Bg = _uniform_fields(cfg, (0, 0, 0), (0, 0, 0))
+    p = {"cell": np.array([17, 40, 93], np.int32), "ox": np.array([0.2, -0.3, 0.5]),
+         "oy": np.array([-0.1, 0.4, 0.0]), "ux": np.array([np.nan, 1.0e9, 0.5]),
+         "uy": np.array([0.3, 0.2, 0.0]), "uz": np.zeros(3), "w": np.ones(3)}
     _, st = O.push(cfg, p, Eg, Bg)
-    assert st.nonfinite >= 1
-    assert p["cell"][0] == 17
+    assert st.nonfinite == 2 and st.moved_gt1 == 0
+    assert list(p["cell"][:2]) == [17, 40]
+    assert list(p["ox"][:2]) == [0.2, -0.3] and list(p["oy"][:2]) == [-0.1, 0.4]
+    # the third: 2 v dt / dx = 0.1 half-cells along x
+    assert p["cell"][2] == 93 and p["ox"][2] == pytest.approx(0.6, abs=1e-15)
+    # the deposit's back step of the NaN particle is kept at x as well
+    n, J = O.deposit(cfg, {k: v[:1] for k, v in p.items()}, 0.5 * cfg.dt)
+    ref, _ = O.deposit(cfg, {**{k: v[:1] for k, v in p.items()}, "ux": np.zeros(1),
+                             "uy": np.zeros(1)}, 0.0)
+    assert np.array_equal(n, ref)
 
 
 def _many(cfg, u, w):
