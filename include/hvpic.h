@@ -210,8 +210,14 @@ int hvpic_deposit(hvpic_ctx* ctx, const hvpic_particles* p, const int32_t* cell_
    Ohm(B, n, J_i) = -u_i x B + (J x B)/n_f - grad(p_e)/n_f + eta J with
    J = curl B (centred differences), n_f = max(n, n_floor), u_i = J_i/n_f,
    p_e = n0 te (n_f/n0)^gamma_e; 1/n_f is formed in double precision.
-   diag_out (device, may be NULL): 2 doubles {W_B, W_dB} =
-   {1/2 sum |B|^2 V_c, 1/2 sum |B - <B>|^2 V_c} of the B left behind. */
+   diag_out (device, may be NULL): 3 doubles {W_B, W_dB, W_e} =
+   {1/2 sum |B|^2 V_c, 1/2 sum |B - <B>|^2 V_c} of the B left behind, and the
+   electron internal energy of the density E_out was formed from (mode 0:
+   n^{n+1}; mode 1: n_half), with n_f = max(n, n_floor):
+   W_e = te sum n_f ln(n_f/n0) V_c for gamma_e = 1, else
+   sum p_e V_c / (gamma_e - 1).  W_e is the electron term of the energy of
+   the hybrid equations (Sec. II.A): with Ohm's law, Ampere and Faraday,
+   d/dt (K_i + W_B + W_e) = eta sum (J.J_i - |J|^2) V_c.  All FP64. */
 int hvpic_field_advance(hvpic_ctx* ctx, float* B, const float* n_half,
                         const float* J_half, const float* n_prev, const float* J_prev,
                         float* E_out, int mode, double* diag_out);
@@ -224,6 +230,14 @@ int hvpic_smooth(hvpic_ctx* ctx, float* F, int ncomp, int npasses);
    and, if counts is non-NULL, counts[0..2] = {particles moved more than one
    cell, non-finite/runaway particles, floor hits}; then clears them. */
 int hvpic_sync_status(hvpic_ctx* ctx, uint32_t* flags, int64_t* counts);
+
+/* Execution paths of the particle kernels (a test and tuning aid, not part of
+   the method): waits for the context's stream, then stats[0] = blocks of the
+   push and deposit kernels that worked through their LDS windows (a chunk of
+   the sorted store spanning few enough cells) and stats[1] = blocks that fell
+   back to global loads and atomics, counted since the context was created or
+   the last call; then clears both. */
+int hvpic_path_stats(hvpic_ctx* ctx, int64_t* stats);
 
 /* Kernel timing on the context's stream (a measurement aid, not part of the
    method).  hvpic_timing_enable(ctx, max_launches, every) creates HIP event

@@ -57,7 +57,12 @@ __global__ void k_init_ws(Status* st, double* mom, int64_t nmom, uint32_t* cnt, 
     st->moved_gt1 = st->nonfinite = st->floor_hits = st->bad_input = 0;
     st->far_flag = 0;
     st->far_decision = 0;
+    st->win_blocks = st->glob_blocks = 0;
   }
+}
+
+__global__ void k_clear_paths(Status* st) {
+  if (threadIdx.x == 0) st->win_blocks = st->glob_blocks = 0;
 }
 
 __global__ void k_clear_status(Status* st) {
@@ -82,7 +87,7 @@ Layout workspace_layout(const hvpic_params* p) {
   // cell-row blocks (>= 16 cells each)
   L.push_part = off;
   off += align256(sizeof(double) * 4 * std::max(ceil_div(cap, 1024), ceil_div(nc, 16)));
-  L.field_part = off; off += align256(sizeof(double) * 4 * field_part_slots(p));
+  L.field_part = off; off += align256(sizeof(double) * kFieldPartStride * field_part_slots(p));
   L.sort_cnt = off;  off += align256(sizeof(uint32_t) * ndir * nc);
   L.sort_blk = off;  off += align256(sizeof(uint32_t) * nblk);
   L.rkey0 = off;     off += align256(sizeof(uint32_t) * cap);
@@ -251,6 +256,21 @@ int hvpic_sync_status(hvpic_ctx* ctx, uint32_t* flags, int64_t* counts) {
     counts[2] = (int64_t)h.floor_hits;
   }
   hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(64), 0, ctx->stream, ctx->status);
+  if (hipGetLastError() != hipSuccess) return HVPIC_EHIP;
+  if (hipStreamSynchronize(ctx->stream) != hipSuccess) return HVPIC_EHIP;
+  return HVPIC_OK;
+}
+
+int hvpic_path_stats(hvpic_ctx* ctx, int64_t* stats) {
+  if (!ctx_ok(ctx)) return HVPIC_ESTATE;
+  if (!stats) return HVPIC_EINVAL;
+  if (hipStreamSynchronize(ctx->stream) != hipSuccess) return HVPIC_EHIP;
+  Status h;
+  if (hipMemcpy(&h, ctx->status, sizeof(Status), hipMemcpyDeviceToHost) != hipSuccess)
+    return HVPIC_EHIP;
+  stats[0] = (int64_t)h.win_blocks;
+  stats[1] = (int64_t)h.glob_blocks;
+  hipLaunchKernelGGL(k_clear_paths, dim3(1), dim3(64), 0, ctx->stream, ctx->status);
   if (hipGetLastError() != hipSuccess) return HVPIC_EHIP;
   if (hipStreamSynchronize(ctx->stream) != hipSuccess) return HVPIC_EHIP;
   return HVPIC_OK;

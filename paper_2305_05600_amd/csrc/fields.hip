@@ -202,11 +202,22 @@ __global__ __launch_bounds__(kBlock) void k_field_stage(const float* __restrict_
 }
 
 
-// Equation of state and floor for the frozen-moment terms.
+// Equation of state and floor for the frozen-moment terms (FP32), and n0,
+// gamma in FP64 for the electron energy diagnostic.
 struct Eos {
   float nfloor, te_n0, n0, gam;
   int iso;
+  double dn0, dgam, dfloor;
 };
+
+// Electron internal energy per unit volume of density n (floored), divided by
+// te for gamma = 1 (n ln(n/n0)) and by n0 te / (gamma - 1) otherwise
+// ((n/n0)^gamma); the factors are applied to the total (Sec. II.A EOS: the
+// energy whose time derivative is the pressure work of the electrons).
+__device__ __forceinline__ double electron_energy(float n, const Eos& eos) {
+  const double nf = fmax((double)n, eos.dfloor);
+  return eos.iso ? nf * log(nf / eos.dn0) : pow(nf / eos.dn0, eos.dgam);
+}
 
 // K whole RK2 substeps for a 2D tile of kTX x kTY cells, all intermediate
 // fields in LDS.  Each substep needs B on a 4-cell halo (B -> Ea on halo 3 ->
@@ -245,19 +256,20 @@ struct SubLds {
   static_assert(3 * PA::N + 3 * PS::N >= PB::N, "pressure plane overlays E and B*");
 };
 
-// FP64 sums of the four values over the block (fixed order), thread 0 writes
-// them to out[0..3].
+// FP64 sums of the five diagnostic values over the block (fixed order),
+// thread 0 writes them to out[0..4].
+constexpr int kDiagNV = 5;
 __device__ void tile_partial(double* v, double* out) {
-  __shared__ double s_red[kSubBlock / 64][4];
+  __shared__ double s_red[kSubBlock / 64][kDiagNV];
 #pragma unroll
-  for (int k = 0; k < 4; ++k)
+  for (int k = 0; k < kDiagNV; ++k)
     for (int o = 32; o > 0; o >>= 1) v[k] += __shfl_xor(v[k], o);
   const int wid = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0)
-    for (int k = 0; k < 4; ++k) s_red[wid][k] = v[k];
+    for (int k = 0; k < kDiagNV; ++k) s_red[wid][k] = v[k];
   __syncthreads();
   if (threadIdx.x == 0)
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < kDiagNV; ++k) {
       double t = 0.0;
       for (int w = 0; w < kSubBlock / 64; ++w) t += s_red[w][k];
       out[k] = t;
@@ -267,7 +279,8 @@ __device__ void tile_partial(double* v, double* out) {
 // Per-step outputs of the final launch (FINAL): E from the moments
 // extrapolated to the full step, n_eff = 1.5 nm - 0.5 np, J_eff = 1.5 Jm -
 // 0.5 Jp, the final B = hi + lo into Bfin, the count of cells of nm below the
-// floor, and per-tile FP64 partials {sum |B|^2, sum B} into part.
+// floor, and per-tile FP64 partials {sum |B|^2, sum B, sum e(n_eff)} into
+// part (e as in electron_energy).
 struct SubFinal {
   const float* np;
   const float* Jp;
@@ -510,7 +523,7 @@ __global__ __launch_bounds__(kSubBlock) void k_field_sub2d(
     // E at the tile's cells from the final B = hi + lo (curl on the 1-cell
     // halo) and the extrapolated frozen terms, as k_field_final forms them
     bool below = false;
-    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    double v[kDiagNV] = {0.0, 0.0, 0.0, 0.0, 0.0};
     const int x = tx0 + fx, y = ty0 + fy;
     const bool live = fown && x < g.nx && y < g.ny;
     if (live) {
@@ -551,13 +564,15 @@ __global__ __launch_bounds__(kSubBlock) void k_field_sub2d(
       v[1] = d0;
       v[2] = d1;
       v[3] = d2;
+      if (F.part) v[4] = electron_energy(ne[0], eos);
     }
     const uint64_t m = __ballot(live && below);
     if ((threadIdx.x & 63) == 0 && m) {
       atomicOr(&F.st->flags, (uint32_t)HVPIC_FLAG_FLOOR_HIT);
       atomicAdd(&F.st->floor_hits, (unsigned long long)__builtin_popcountll(m));
     }
-    if (F.part) tile_partial(v, F.part + 4 * ((int64_t)blockIdx.y * gridDim.x + blockIdx.x));
+    if (F.part)
+      tile_partial(v, F.part + kFieldPartStride * ((int64_t)blockIdx.y * gridDim.x + blockIdx.x));
   }
 }
 
@@ -568,7 +583,7 @@ __global__ __launch_bounds__(kSubBlock) void k_field_sub2d(
 // non-null the final B = hi + lo is also written there (Bout is never one of
 // the arrays read).  Cells of na below the floor are counted when asked
 // (once per field advance).  With part non-null, per-block FP64 partials
-// {sum |B|^2, sum B} go to part.
+// {sum |B|^2, sum B, sum e(n_eff)} go to part (e as in electron_energy).
 template <int NDIM, bool EXTRAP, bool HAS_LO>
 __global__ __launch_bounds__(kBlock) void k_field_final(
     const float* __restrict__ Bh, const float* __restrict__ Bl, float* __restrict__ Bout,
@@ -579,7 +594,7 @@ __global__ __launch_bounds__(kBlock) void k_field_final(
   const int nc = g.ncell;
   const bool live = c < nc;
   bool below = false;
-  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  double v[kDiagNV] = {0.0, 0.0, 0.0, 0.0, 0.0};
   if (live) {
     int i, j, k;
     fijk(c, g, i, j, k);
@@ -621,6 +636,7 @@ __global__ __launch_bounds__(kBlock) void k_field_final(
     v[1] = d0;
     v[2] = d1;
     v[3] = d2;
+    if (part) v[4] = electron_energy(n_c, eos);
   }
   if (count_floor) {
     const uint64_t m = __ballot(live && below);
@@ -629,21 +645,23 @@ __global__ __launch_bounds__(kBlock) void k_field_final(
       atomicAdd(&st->floor_hits, (unsigned long long)__builtin_popcountll(m));
     }
   }
-  if (part) block_partial<4>(v, part);
+  if (part) block_partial<kDiagNV, kFieldPartStride>(v, part);
 }
 
-// {W_B, W_dB} = {1/2 V sum |B|^2, 1/2 V (sum |B|^2 - |sum B|^2 / ncell)}.
+// {W_B, W_dB, W_e} = {1/2 V sum |B|^2, 1/2 V (sum |B|^2 - |sum B|^2 / ncell),
+// we_scale sum e(n)} with we_scale = V te (gamma = 1) or V n0 te / (gamma - 1).
 // A kernel of its own: a last-block reduction inside k_field_final would need
 // an agent-scope release per block, which writes back the L2.
 __global__ __launch_bounds__(1024) void k_field_diag_final(const double* part, int nblocks,
                                                              double* out, double half_vol,
-                                                             double inv_ncell) {
-  double r[4];
-  sum_partials<4>(part, nblocks, r);
+                                                             double inv_ncell, double we_scale) {
+  double r[kDiagNV];
+  sum_partials<kDiagNV, kFieldPartStride>(part, nblocks, r);
   if (threadIdx.x == 0) {
     const double m2 = r[1] * r[1] + r[2] * r[2] + r[3] * r[3];
     out[0] = half_vol * r[0];
     out[1] = half_vol * (r[0] - m2 * inv_ncell);
+    out[2] = we_scale * r[4];
   }
 }
 
@@ -712,6 +730,9 @@ int field_impl(hvpic_ctx* c, float* B, const float* n_half, const float* J_half,
   eos.te_n0 = (float)(c->p.te * c->p.n0);
   eos.gam = (float)c->p.gamma_e;
   eos.iso = c->p.gamma_e == 1.0;
+  eos.dn0 = c->p.n0;
+  eos.dgam = c->p.gamma_e;
+  eos.dfloor = c->p.n_floor;
   const float eta = (float)c->p.eta;
   const float* fh = B;        // final B = fh + fl
   const float* fl = nullptr;
@@ -792,12 +813,13 @@ int field_impl(hvpic_ctx* c, float* B, const float* n_half, const float* J_half,
   // E^{n+1} from the extrapolated moments (mode 0) or E from the given ones
   // (mode 1), the final B, the floor count of n_half and the diagnostics
   const double V = c->p.dx * c->p.dy * c->p.dz;
+  const double we_scale = eos.iso ? V * c->p.te : V * c->p.n0 * c->p.te / (c->p.gamma_e - 1.0);
   if (fused_final) {
     if (diag_out) {
       const dim3 tiles((unsigned)ceil_div(c->p.nx, kTX), (unsigned)ceil_div(c->p.ny, kTY));
       hipLaunchKernelGGL(k_field_diag_final, dim3(1), dim3(1024), 0, s,
                          (const double*)c->field_part, (int)(tiles.x * tiles.y), diag_out,
-                         0.5 * V, 1.0 / (double)nc);
+                         0.5 * V, 1.0 / (double)nc, we_scale);
     }
     return hipGetLastError() == hipSuccess ? HVPIC_OK : HVPIC_EHIP;
   }
@@ -814,7 +836,7 @@ int field_impl(hvpic_ctx* c, float* B, const float* n_half, const float* J_half,
     final_kernel(k_field_final<NDIM, false, false>);
   if (diag_out)
     hipLaunchKernelGGL(k_field_diag_final, dim3(1), dim3(1024), 0, s, (const double*)c->field_part,
-                       (int)grid.x, diag_out, 0.5 * V, 1.0 / (double)nc);
+                       (int)grid.x, diag_out, 0.5 * V, 1.0 / (double)nc, we_scale);
   return hipGetLastError() == hipSuccess ? HVPIC_OK : HVPIC_EHIP;
 }
 

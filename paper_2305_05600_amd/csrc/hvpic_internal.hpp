@@ -39,11 +39,20 @@ struct Status {
   unsigned long long bad_input;
   uint32_t far_flag;        // set by the neighbour-move count kernel on a far mover
   uint32_t far_decision;    // far_flag handed to the scatter kernel (and far_flag cleared)
+  // blocks of the particle kernels (push, deposit) that used the LDS windows
+  // and that fell back to global loads and atomics (hvpic_path_stats)
+  unsigned long long win_blocks;
+  unsigned long long glob_blocks;
 };
 
+// One count per block of a particle kernel: whether it used the LDS windows.
+__device__ __forceinline__ void count_path(Status* st, bool window) {
+  if (threadIdx.x == 0) atomicAdd(window ? &st->win_blocks : &st->glob_blocks, 1ull);
+}
+
 // FP64 partial sums of NV values over a block, written by thread 0 to
-// part[blockIdx.x * 4 + k].  Fixed reduction order (deterministic).
-template <int NV>
+// part[blockIdx.x * STRIDE + k].  Fixed reduction order (deterministic).
+template <int NV, int STRIDE = 4>
 __device__ void block_partial(double* v, double* part) {
   __shared__ double s_red[16][NV];
 #pragma unroll
@@ -57,13 +66,13 @@ __device__ void block_partial(double* v, double* part) {
     for (int k = 0; k < NV; ++k) {
       double t = 0.0;
       for (int w = 0; w < nw; ++w) t += s_red[w][k];
-      part[(int64_t)blockIdx.x * 4 + k] = t;
+      part[(int64_t)blockIdx.x * STRIDE + k] = t;
     }
 }
 
 // Sum of nblocks partials (as written by block_partial) by one block, in a
 // fixed order; thread 0 returns the totals in res.
-template <int NV>
+template <int NV, int STRIDE = 4>
 __device__ void sum_partials(const double* part, int nblocks, double* res) {
   __shared__ double s_red[16][NV];
   double t[NV];
@@ -75,7 +84,7 @@ __device__ void sum_partials(const double* part, int nblocks, double* res) {
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int b = b0 + u * stride;
-      for (int k = 0; k < NV; ++k) v[u][k] = b < nblocks ? part[(int64_t)b * 4 + k] : 0.0;
+      for (int k = 0; k < NV; ++k) v[u][k] = b < nblocks ? part[(int64_t)b * STRIDE + k] : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u)
@@ -129,7 +138,7 @@ struct hvpic_ctx {
   // workspace carve-out
   hvpic::Status* status;
   double* push_part;     // per-block FP64 partials of the push diagnostics [blocks][4]
-  double* field_part;    // per-block FP64 partials of the field diagnostics [slots][4]
+  double* field_part;    // per-block FP64 partials of the field diagnostics [slots][8]
   uint32_t* sort_cnt;    // [ncell][3^ndim]
   int32_t* sort_blk;     // scan block sums
   uint32_t* rkey[2];     // radix keys   [np_capacity]
@@ -175,8 +184,10 @@ int launch_field_advance(hvpic_ctx* c, float* B, const float* n_half, const floa
                          double* diag_out);
 int launch_smooth(hvpic_ctx* c, float* F, int ncomp, int npasses);
 // Per-block partial slots the field diagnostics need (the larger of the
-// output kernel's blocks and the 2D subcycle's tiles).
+// output kernel's blocks and the 2D subcycle's tiles); kFieldPartStride
+// doubles each.
 int64_t field_part_slots(const hvpic_params* p);
+constexpr int kFieldPartStride = 8;
 int launch_zero(hvpic_ctx* c, float* p, int64_t count);
 void zero_counts(hvpic_ctx* c);  // enqueues the clearing of sort_cnt
 

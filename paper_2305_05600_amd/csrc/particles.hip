@@ -163,11 +163,12 @@ __device__ __forceinline__ void gather_eb(const float* __restrict__ E, const flo
   const int ip = i == g.nx - 1 ? a - g.nx + 1 : a + 1;
   const int jm = j == 0 ? a + g.nxny - g.nx : a - g.nx;
   const int jp = j == g.ny - 1 ? a - g.nxny + g.nx : a + g.nx;
-  const float c6 = 1.0f / 6.0f, c12 = 1.0f / 12.0f;
+  const float c12 = 1.0f / 12.0f;
   const float xp = 1.0f + x, xm = 1.0f - x, yp = 1.0f + y, ym = 1.0f - y;
   const float wxp = xp * xp * c12, wxm = xm * xm * c12, wyp = yp * yp * c12, wym = ym * ym * c12;
+  // centre weight as one minus the others (see dep_weights)
   if (NDIM == 2) {
-    const float w0 = (4.0f - x * x - y * y) * c6;
+    const float w0 = 1.0f - ((wxp + wxm) + (wyp + wym));
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const float* e = E + c * nc;
@@ -182,7 +183,7 @@ __device__ __forceinline__ void gather_eb(const float* __restrict__ E, const flo
     const int kp = k == g.nz - 1 ? a - nc + g.nxny : a + g.nxny;
     const float zp = 1.0f + z, zm = 1.0f - z;
     const float wzp = zp * zp * c12, wzm = zm * zm * c12;
-    const float w0 = (3.0f - x * x - y * y - z * z) * c6;
+    const float w0 = 1.0f - ((wxp + wxm) + (wyp + wym) + (wzp + wzm));
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const float* e = E + c * nc;
@@ -259,23 +260,29 @@ __device__ void gwin_fill(float* gw, int ncells, int c0, const Geo& g,
       const float fxp = __ldg(F + ip), fxm = __ldg(F + im);
       const float fyp = __ldg(F + jp), fym = __ldg(F + jm);
       const float c6 = 1.0f / 6.0f, c12 = 1.0f / 12.0f;
+      // written with the second differences, F0 = F + (sum of the
+      // neighbours - 2 ndim F)/12 (the same value as (6F + sum)/12 in 3D):
+      // a uniform field has zero differences and is gathered exactly, which
+      // the FP32 roundings of 1/6 and 1/12 would otherwise bias by ~3e-8
+      const float dxx = (fxp + fxm) - 2.0f * f0, dyy = (fyp + fym) - 2.0f * f0;
       if (NDIM == 2) {
-        rec[0 * 6 + comp] = f0 * (4.0f * c6) + ((fxp + fxm) + (fyp + fym)) * c12;
+        rec[0 * 6 + comp] = fmaf(dxx + dyy, c12, f0);
         rec[1 * 6 + comp] = (fxp - fxm) * c6;
         rec[2 * 6 + comp] = (fyp - fym) * c6;
-        rec[3 * 6 + comp] = (fxp + fxm) * c12 - f0 * c6;
-        rec[4 * 6 + comp] = (fyp + fym) * c12 - f0 * c6;
+        rec[3 * 6 + comp] = dxx * c12;
+        rec[4 * 6 + comp] = dyy * c12;
       } else {
         const int km = k == 0 ? a + nc - g.nxny : a - g.nxny;
         const int kp = k == g.nz - 1 ? a - nc + g.nxny : a + g.nxny;
         const float fzp = __ldg(F + kp), fzm = __ldg(F + km);
-        rec[0 * 6 + comp] = f0 * 0.5f + ((fxp + fxm) + (fyp + fym) + (fzp + fzm)) * c12;
+        const float dzz = (fzp + fzm) - 2.0f * f0;
+        rec[0 * 6 + comp] = fmaf((dxx + dyy) + dzz, c12, f0);
         rec[1 * 6 + comp] = (fxp - fxm) * c6;
         rec[2 * 6 + comp] = (fyp - fym) * c6;
         rec[3 * 6 + comp] = (fzp - fzm) * c6;
-        rec[4 * 6 + comp] = (fxp + fxm) * c12 - f0 * c6;
-        rec[5 * 6 + comp] = (fyp + fym) * c12 - f0 * c6;
-        rec[6 * 6 + comp] = (fzp + fzm) * c12 - f0 * c6;
+        rec[4 * 6 + comp] = dxx * c12;
+        rec[5 * 6 + comp] = dyy * c12;
+        rec[6 * 6 + comp] = dzz * c12;
       }
     }
     if (comp == 0) {
@@ -327,25 +334,31 @@ __device__ __forceinline__ void gather_rec(const float4* gw, int rel, float x, f
 // ---------------------------------------------------------------- deposit --
 
 // Stencil weights at deposit offsets (x, y, z): centre, +x, -x, +y, -y[, +z, -z]
-// (Sec. II.B eq:ngp, App. B eq:quad).
+// (Sec. II.B eq:ngp, App. B eq:quad).  The weights of eq:quad sum to one; the
+// centre weight is taken as one minus the others (the same value as
+// (3 - x^2 - y^2 - z^2)/6, or (4 - x^2 - y^2)/6 in 2D), so each particle
+// deposits its whole charge in FP32 too: with the FP32 roundings of 1/6 and
+// 1/12 the printed form deposits ~3e-8 too much, always in the same direction.
 template <int NDIM, int SHAPE>
 __device__ __forceinline__ void dep_weights(float x, float y, float z, float* wt) {
   if (SHAPE == HVPIC_SHAPE_NGP) {
     wt[0] = 1.0f;
     return;
   }
-  const float c6 = 1.0f / 6.0f, c12 = 1.0f / 12.0f;
+  const float c12 = 1.0f / 12.0f;
   const float xp = 1.0f + x, xm = 1.0f - x, yp = 1.0f + y, ym = 1.0f - y;
-  wt[0] = (NDIM == 2 ? (4.0f - x * x - y * y) : (3.0f - x * x - y * y - z * z)) * c6;
   wt[1] = xp * xp * c12;
   wt[2] = xm * xm * c12;
   wt[3] = yp * yp * c12;
   wt[4] = ym * ym * c12;
+  float side = (wt[1] + wt[2]) + (wt[3] + wt[4]);
   if (NDIM == 3) {
     const float zp = 1.0f + z, zm = 1.0f - z;
     wt[5] = zp * zp * c12;
     wt[6] = zm * zm * c12;
+    side += wt[5] + wt[6];
   }
+  wt[0] = 1.0f - side;
 }
 
 // Deposit window: FP64 (n, Jx, Jy, Jz) per slot; slot = band * SW + column,
@@ -1103,6 +1116,7 @@ void k_gather_push(PushArgs A) {
   const int c0 = s_c[0], span = s_c[1] - s_c[0];
   int W = 0;
   const bool wok = window_ok<NDIM>(c0, s_c[1], g, W);
+  count_path(A.st, wok);
   const bool cnt_on = A.cs != nullptr;  // count the moves for the sort
   if (wok) {
     gwin_fill<NDIM, SHAPE>(reinterpret_cast<float*>(gw), span + 1, c0, g, A.E, A.B);
@@ -1285,6 +1299,7 @@ __global__ __launch_bounds__(kBlock) void k_deposit(DepArgs A) {
   const int c0 = s_c[0], span = s_c[1] - s_c[0];
   int W = 0;
   const bool wok = window_ok<NDIM>(c0, s_c[1], g, W);
+  count_path(A.st, wok);
   if (wok) dwin_init<NDIM>(win, s_wrap, W, c0, g);
   __syncthreads();
   const WinLds wl{win, s_wrap};

@@ -25,7 +25,8 @@ EXPORTS = ("hvpic_workspace_bytes", "hvpic_init", "hvpic_finalize", "hvpic_set_s
            "hvpic_gather_push",
            "hvpic_gather_push_perm", "hvpic_sort", "hvpic_sort_perm", "hvpic_deposit",
            "hvpic_field_advance", "hvpic_smooth",
-           "hvpic_sync_status", "hvpic_timing_enable", "hvpic_timing_read", "hvpic_strerror")
+           "hvpic_sync_status", "hvpic_path_stats", "hvpic_timing_enable", "hvpic_timing_read",
+           "hvpic_strerror")
 KERNEL_GATHER_PUSH, KERNEL_DEPOSIT, KERNEL_SORT_SCATTER = 0, 1, 2
 
 
@@ -76,6 +77,7 @@ def lib():
         L.hvpic_field_advance.argtypes = [vp, vp, vp, vp, vp, vp, vp, i32, vp]
         L.hvpic_smooth.argtypes = [vp, vp, i32, i32]
         L.hvpic_sync_status.argtypes = [vp, P(ctypes.c_uint32), P(ctypes.c_int64)]
+        L.hvpic_path_stats.argtypes = [vp, P(ctypes.c_int64)]
         L.hvpic_timing_enable.argtypes = [vp, i32, i32]
         L.hvpic_timing_read.argtypes = [vp, i32, P(ctypes.c_double), P(ctypes.c_int64)]
         L.hvpic_strerror.argtypes = [ctypes.c_int]
@@ -181,12 +183,13 @@ def hvpic_init(params: HvpicParams, stream, workspace: torch.Tensor):
 
 def hvpic_finalize(ctx):
     _check(lib().hvpic_finalize(ctx), "hvpic_finalize")
+    _NCELL.pop(ctx.value, None)
 
 
 def hvpic_set_stream(ctx, stream):
+    # the context keeps its grid: the host-side size checks stay on
     _check(lib().hvpic_set_stream(ctx, None if stream is None else ctypes.c_void_p(stream)),
            "hvpic_set_stream")
-    _NCELL.pop(ctx.value, None)
 
 
 def _nc(ctx, k=1):
@@ -258,7 +261,7 @@ def hvpic_field_advance(ctx, B, n_half, J_half, n_prev, J_prev, E_out, mode=0, d
                                      _ptr(n_prev, torch.float32, v1),
                                      _ptr(J_prev, torch.float32, v3),
                                      _ptr(E_out, torch.float32, v3),
-                                     int(mode), _ptr(diag_out, torch.float64, 2)),
+                                     int(mode), _ptr(diag_out, torch.float64, 3)),
            "hvpic_field_advance")
 
 
@@ -274,6 +277,14 @@ def hvpic_sync_status(ctx):
     counts = (ctypes.c_int64 * 3)()
     _check(lib().hvpic_sync_status(ctx, ctypes.byref(flags), counts), "hvpic_sync_status")
     return flags.value, tuple(counts)
+
+
+def hvpic_path_stats(ctx):
+    """(blocks that used the LDS windows, blocks that fell back to global
+    accesses) of the particle kernels since the last call."""
+    out = (ctypes.c_int64 * 2)()
+    _check(lib().hvpic_path_stats(ctx, out), "hvpic_path_stats")
+    return out[0], out[1]
 
 
 def hvpic_timing_enable(ctx, max_launches: int, every: int = 1):

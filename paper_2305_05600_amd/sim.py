@@ -153,7 +153,7 @@ class GpuSim:
             self.B_s = torch.zeros((3, nc), **f32)
         self.diagnostics = diagnostics
         self.push_diag = torch.zeros(4, dtype=torch.float64, device=device)
-        self.field_diag = torch.zeros(2, dtype=torch.float64, device=device)
+        self.field_diag = torch.zeros(3, dtype=torch.float64, device=device)
         self.ev_push = StreamEvent()  # the push of the step is done (the sort may start)
         self.ev_sort = StreamEvent()  # the sort of the step is done (the next push may start)
         self.ev_step = StreamEvent()  # the step's work on the particle stream is done

@@ -73,9 +73,10 @@ def deposit_point_straddlers(cfg, parts: dict, back: float, band=1e-5) -> np.nda
 def drop_straddlers(cfg, parts: dict, B, steps: int = 1, band=1e-5, fused=False) -> dict:
     """Removes from the input every particle that the FP64 oracle moves, within
     `steps` steps, to within `band` half-cells of a face, or whose mid-point
-    deposit point lands there.  Uses only the oracle; the GPU and the oracle
-    then run on the same cleaned input, so cell decisions can be compared
-    exactly (the straddler band of the parity contract)."""
+    deposit point lands there.  Uses only the oracle (with the step's
+    smoothing passes, if any); the GPU and the oracle then run on the same
+    cleaned input, so cell decisions can be compared exactly (the straddler
+    band of the parity contract).  Prints how many were removed."""
     import oracle as O
 
     keep = np.ones(parts["cell"].size, bool)
@@ -85,7 +86,10 @@ def drop_straddlers(cfg, parts: dict, B, steps: int = 1, band=1e-5, fused=False)
         sim = O.OracleSim(cfg, {**sub, "id": ids.astype(np.float64)}, B)
         bad = np.zeros(parts["cell"].size, bool)
         for _ in range(steps):
-            O.push(cfg, sim.p, sim.E, sim.B)
+            E, Bg = sim.E, sim.B
+            if cfg.nsmooth:
+                E, Bg = O.smooth(cfg, E, cfg.nsmooth), O.smooth(cfg, Bg, cfg.nsmooth)
+            O.push(cfg, sim.p, E, Bg)
             offs = ["ox", "oy"] + (["oz"] if cfg.ndim == 3 else [])
             near = np.zeros(sim.p["cell"].size, bool)
             for k in offs:
@@ -95,10 +99,49 @@ def drop_straddlers(cfg, parts: dict, B, steps: int = 1, band=1e-5, fused=False)
             perm, sim.cell_start = O.sort(cfg, sim.p["cell"])
             sim.p = O.apply_perm(sim.p, perm)
             n_half, J_half = O.deposit(cfg, sim.p, 0.5 * cfg.dt)
+            if cfg.nsmooth:
+                n_half = O.smooth(cfg, n_half, cfg.nsmooth)
+                J_half = O.smooth(cfg, J_half, cfg.nsmooth)
             sim.B, sim.E, _, _ = O.field_advance(cfg, sim.B, n_half, J_half, sim.n_prev,
                                                  sim.J_prev, mode=0)
             sim.n_prev, sim.J_prev = n_half, J_half
         if not bad.any():
+            print(f"straddlers removed: {int((~keep).sum())} of {keep.size} "
+                  f"(band {band:g} half-cells, {steps} step(s))", flush=True)
             return {k: np.ascontiguousarray(v) for k, v in sub.items()}
         keep &= ~bad
     raise AssertionError("straddler removal did not converge")
+
+
+def drop_push_straddlers(cfg, parts: dict, E, B, back=None, band=1e-5) -> dict:
+    """For one push in the given fields: removes the particles that the FP64
+    oracle puts within `band` half-cells of a face, and (back given) whose
+    deposit point x - back v lands there.  Prints how many were removed."""
+    import oracle as O
+
+    ref = O.particles64(parts)
+    O.push(cfg, ref, E, B)
+    near = np.zeros(ref["cell"].size, bool)
+    for k in ["ox", "oy"] + (["oz"] if cfg.ndim == 3 else []):
+        near |= _near_face(ref[k], band)
+    if back is not None:
+        near |= deposit_point_straddlers(cfg, ref, back, band)
+    print(f"straddlers removed: {int(near.sum())} of {near.size}", flush=True)
+    return {k: np.ascontiguousarray(v[~near]) for k, v in parts.items()}
+
+
+def check_field_diag(got, ref, tol=1e-5):
+    """The field diagnostics {W_B, W_dB, W_e} against the oracle to the accuracy
+    that the field contract (tol relative L2 on B and n) implies:
+      W_B within 2 tol relative (|dW_B| <= |B| |dB| V);
+      W_dB within 2 tol sqrt(W_dB W_B) absolute: the error of the fluctuation
+        energy is bounded by |B - <B>| |dB| V with |dB| <= tol |B|, so a
+        fluctuation far below the mean field (B0 + a small dB stored in FP32)
+        is known only to that absolute accuracy;
+      W_e within tol relative."""
+    got = np.asarray(got, np.float64)
+    ref = np.asarray(ref, np.float64)
+    print(f"field diagnostics gpu {got} oracle {ref}", flush=True)
+    assert abs(got[0] - ref[0]) <= 2 * tol * abs(ref[0]), (got, ref)
+    assert abs(got[1] - ref[1]) <= 2 * tol * np.sqrt(abs(ref[1] * ref[0])), (got, ref)
+    assert abs(got[2] - ref[2]) <= tol * abs(ref[2]), (got, ref)
