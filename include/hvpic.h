@@ -222,6 +222,26 @@ int hvpic_field_advance(hvpic_ctx* ctx, float* B, const float* n_half,
                         const float* J_half, const float* n_prev, const float* J_prev,
                         float* E_out, int mode, double* diag_out);
 
+/* The deposit of hvpic_deposit, for callers that cannot allocate memory or
+   create a context: code captured into a HIP graph, tight serving loops,
+   harnesses that forbid allocation.  It takes the run parameters (as for
+   hvpic_init; np_capacity is not used) and a HIP stream instead of a
+   context, allocates nothing (no hipMalloc, no workspace: its scratch, the
+   FP64 moment accumulators and a status word, is a device array of the
+   library, one per GPU, held until the process ends) and enqueues on
+   `hip_stream` the clearing of that scratch and the same kernels as
+   hvpic_deposit: n [ncell] and J [3][ncell] are overwritten with the same
+   moments (to rounding: the accumulation order of atomics differs).  Limit:
+   nx*ny*nz <= HVPIC_NOALLOC_MAX_CELLS, else HVPIC_ENOMEM and nothing is
+   launched; HVPIC_EINVAL for invalid parameters or pointers.  Particles
+   whose cell lies outside [0, ncell) are skipped (no status is reported;
+   use hvpic_deposit for that).  Every call on one GPU shares that GPU's
+   scratch: calls that overlap on one GPU (several streams, or several host
+   threads) race and must be ordered by the caller. */
+#define HVPIC_NOALLOC_MAX_CELLS (1 << 20)
+int hvpic_deposit_noalloc(const hvpic_params* params, void* hip_stream,
+                          const hvpic_particles* p, float half_dt_back, float* n, float* J);
+
 /* npasses of the binomial (1,2,1)/4 filter along every axis (Sec. II.B
    smoothing), in place on ncomp component-major grid arrays F. */
 int hvpic_smooth(hvpic_ctx* ctx, float* F, int ncomp, int npasses);

@@ -48,6 +48,12 @@ bool parts_ok(const hvpic_ctx* c, const hvpic_particles* q, bool need_w) {
 
 bool ctx_ok(const hvpic_ctx* c) { return c && c->magic == kMagic; }
 
+}  // namespace
+
+bool params_valid(const hvpic_params* p) { return params_ok(p); }
+
+namespace {
+
 __global__ void k_init_ws(Status* st, double* mom, int64_t nmom, uint32_t* cnt, int64_t ncnt) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   for (int64_t q = i; q < nmom; q += (int64_t)gridDim.x * blockDim.x) mom[q] = 0.0;

@@ -189,6 +189,7 @@ int launch_smooth(hvpic_ctx* c, float* F, int ncomp, int npasses);
 int64_t field_part_slots(const hvpic_params* p);
 constexpr int kFieldPartStride = 8;
 int launch_zero(hvpic_ctx* c, float* p, int64_t count);
+bool params_valid(const hvpic_params* p);  // the checks hvpic_init applies
 void zero_counts(hvpic_ctx* c);  // enqueues the clearing of sort_cnt
 
 // Event bracket around one launch of kernel id k (no-op unless timing is on

@@ -28,6 +28,11 @@
 //     accumulators, and one pass converts those to the FP32 outputs.
 // Particles outside the windows (unsorted or sparse input) use global loads
 // and FP64 global atomics.
+#include <string.h>
+
+#include <algorithm>
+#include <cmath>
+#include <mutex>
 #include <type_traits>
 
 #include "hvpic_internal.hpp"
@@ -1607,3 +1612,85 @@ int launch_deposit(hvpic_ctx* c, const hvpic_particles* p, const int32_t* cell_s
 }
 
 }  // namespace hvpic
+
+// ------------------------------------------------- allocation-free deposit --
+//
+// hvpic_deposit_noalloc runs the same deposit kernels as hvpic_deposit with
+// its scratch (the status word and the FP64 moment accumulators) in a
+// file-scope device array instead of a context's workspace.  Each GPU the
+// library runs on holds its own copy of the array until the process ends;
+// host code reaches it only through the device address that
+// hipGetSymbolAddress returns for the current device.
+
+namespace hvpic {
+namespace {
+
+constexpr int64_t kNoAllocStatusBytes = 256;
+constexpr int64_t kNoAllocBytes =
+    kNoAllocStatusBytes + (int64_t)sizeof(double) * 4 * HVPIC_NOALLOC_MAX_CELLS;
+static_assert(sizeof(Status) <= kNoAllocStatusBytes, "status block fits its slot");
+
+__device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices];  // device address of `scratch` per device
+
+// The device address of this device's scratch array (looked up once).
+int scratch_ptr(char** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return HVPIC_EHIP;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return HVPIC_EHIP;
+    g_scratch_ptr[dev] = static_cast<char*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return HVPIC_OK;
+}
+
+// Clears the status word and the first nacc accumulators.
+__global__ void k_noalloc_clear(Status* st, double* acc, int64_t nacc) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nacc; i += stride)
+    acc[i] = 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *st = Status{};
+}
+
+}  // namespace
+}  // namespace hvpic
+
+extern "C" int hvpic_deposit_noalloc(const hvpic_params* params, void* hip_stream,
+                                     const hvpic_particles* p, float half_dt_back, float* n,
+                                     float* J) {
+  using namespace hvpic;
+  if (!params_valid(params) || !p || !n || !J || !std::isfinite(half_dt_back)) return HVPIC_EINVAL;
+  if (p->n < 0 || p->n >= (1ll << 31) - 1) return HVPIC_EINVAL;
+  if (p->n > 0 && (!p->cell || !p->ox || !p->oy || !p->ux || !p->uy || !p->uz || !p->w ||
+                   (params->ndim == 3 && !p->oz)))
+    return HVPIC_EINVAL;
+  const int64_t ncell = (int64_t)params->nx * params->ny * params->nz;
+  if (ncell > HVPIC_NOALLOC_MAX_CELLS) return HVPIC_ENOMEM;
+  char* base = nullptr;
+  const int rc = scratch_ptr(&base);
+  if (rc != HVPIC_OK) return rc;
+  // A context on the stack carries what the launch wrappers read; its
+  // workspace pointers are this device's scratch array.
+  hvpic_ctx c;
+  memset(&c, 0, sizeof(c));
+  c.p = *params;
+  c.stream = (hipStream_t)hip_stream;
+  c.ncell = (int32_t)ncell;
+  c.magic = kMagic;
+  c.qV = (float)(params->qs / (params->dx * params->dy * params->dz));
+  c.fnx = make_fastdiv((uint32_t)params->nx);
+  c.fny = make_fastdiv((uint32_t)params->ny);
+  c.status = reinterpret_cast<Status*>(base);
+  c.mom_acc = reinterpret_cast<double*>(base + kNoAllocStatusBytes);
+  hipLaunchKernelGGL(k_noalloc_clear, dim3((unsigned)std::min<int64_t>(ceil_div(4 * ncell, kBlock), 2048)),
+                     dim3(kBlock), 0, c.stream, c.status, c.mom_acc, 4 * ncell);
+  if (hipGetLastError() != hipSuccess) return HVPIC_EHIP;
+  return launch_deposit(&c, p, nullptr, half_dt_back, n, J);
+}
+

@@ -24,6 +24,7 @@ FLAG_MOVE_GT1, FLAG_FLOOR_HIT, FLAG_NONFINITE, FLAG_BAD_INPUT = 1, 2, 4, 8
 EXPORTS = ("hvpic_workspace_bytes", "hvpic_init", "hvpic_finalize", "hvpic_set_stream",
            "hvpic_gather_push",
            "hvpic_gather_push_perm", "hvpic_sort", "hvpic_sort_perm", "hvpic_deposit",
+           "hvpic_deposit_noalloc",
            "hvpic_field_advance", "hvpic_smooth",
            "hvpic_sync_status", "hvpic_path_stats", "hvpic_timing_enable", "hvpic_timing_read",
            "hvpic_strerror")
@@ -74,6 +75,8 @@ def lib():
         L.hvpic_sort.argtypes = [vp, P(HvpicParticles), P(HvpicParticles), vp, vp, i32]
         L.hvpic_sort_perm.argtypes = [vp, P(HvpicParticles), vp, vp, vp]
         L.hvpic_deposit.argtypes = [vp, P(HvpicParticles), vp, ctypes.c_float, vp, vp]
+        L.hvpic_deposit_noalloc.argtypes = [P(HvpicParams), vp, P(HvpicParticles), ctypes.c_float,
+                                            vp, vp]
         L.hvpic_field_advance.argtypes = [vp, vp, vp, vp, vp, vp, vp, i32, vp]
         L.hvpic_smooth.argtypes = [vp, vp, i32, i32]
         L.hvpic_sync_status.argtypes = [vp, P(ctypes.c_uint32), P(ctypes.c_int64)]
@@ -251,6 +254,21 @@ def hvpic_deposit(ctx, p: Particles, cell_start, half_dt_back: float, n, J):
     _check(lib().hvpic_deposit(ctx, ctypes.byref(cp), _ptr(cell_start, torch.int32),
                                ctypes.c_float(half_dt_back), _ptr(n, torch.float32, _nc(ctx)),
                                _ptr(J, torch.float32, _nc(ctx, 3))), "hvpic_deposit")
+
+
+NOALLOC_MAX_CELLS = 1 << 20  # HVPIC_NOALLOC_MAX_CELLS
+
+
+def hvpic_deposit_noalloc(params: HvpicParams, stream, p: Particles, half_dt_back: float, n, J):
+    """The deposit without a context or workspace (the library's own scratch);
+    `stream` is a raw hipStream_t handle (int) or None."""
+    nc = params.nx * params.ny * params.nz
+    cp = p.c()
+    s = None if stream is None else ctypes.c_void_p(stream)
+    _check(lib().hvpic_deposit_noalloc(ctypes.byref(params), s, ctypes.byref(cp),
+                                       ctypes.c_float(half_dt_back),
+                                       _ptr(n, torch.float32, nc), _ptr(J, torch.float32, 3 * nc)),
+           "hvpic_deposit_noalloc")
 
 
 def hvpic_field_advance(ctx, B, n_half, J_half, n_prev, J_prev, E_out, mode=0, diag_out=None):
