@@ -34,13 +34,18 @@ sys.path.insert(0, str(ROOT))
 
 METRIC = "ion pushes/s (gather+push+deposit) & HBM GB/s %peak; step time surrogate vs plain"
 HBM_PEAK_GBS = 8000.0
-# Algorithmic bytes of the fused gather+push+deposit (2D, FP32 SoA):
-# per particle read cell 4 + offsets 8 + velocity 12 + weight 4, write
-# cell 4 + offsets 8 + velocity 12 (in place); per cell read E,B 24, write
-# n,J 16.  Through a gather map it also reads the map entry (4) and writes
-# the weight (4) to the sorted store.
-BYTES_PER_PARTICLE_2D = {"in place": 52, "gather map": 60}
+# Algorithmic bytes of the fused gather+push+deposit (2D, FP32 SoA): what
+# the method has to move once per step.  Per particle: read cell 4 +
+# offsets 8 + velocity 12 + weight 4, write cell 4 + offsets 8 + velocity
+# 12; per cell: read E, B 24, write n, J 16.  The roofline fraction is
+# taken against these bytes whatever the sequence.
+BYTES_PER_PARTICLE_2D = 52
 BYTES_PER_CELL_2D = 40
+# Bytes this implementation's sequence adds per particle: reading through
+# the gather map costs the map entry (4) and writing the weight to the
+# sorted store (4).  Reported beside, not counted.
+EXTRA_BYTES_PER_PARTICLE_2D = {"in place": 0, "gather map": 8}
+MIN_TIMED_LAUNCHES = 10
 
 
 def _source_hash() -> str:
@@ -66,19 +71,60 @@ def _traffic(n_particles: int, mode: str):
     return rec.get("bytes_per_launch")
 
 
+def _host_cpu() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return os.uname().machine
+
+
 def cpu_baseline(cfg, parts, B):
+    """The oracle (single-threaded FP64) on 3 whole steps of the workload;
+    also returns its state after the first step, for the error of the GPU
+    step against it."""
     import oracle as O
 
     sim = O.OracleSim(cfg, parts, B)
     steps = 3
+    first = None
     t0 = time.perf_counter()
-    for _ in range(steps):
+    for k in range(steps):
         sim.step()
+        if k == 0:
+            t_pause = time.perf_counter()
+            first = {"n": sim.n_prev.copy(), "J": sim.J_prev.copy(), "B": sim.B.copy(),
+                     "E": sim.E.copy()}
+            t0 += time.perf_counter() - t_pause  # the copies are not timed
     dt = time.perf_counter() - t0
     n = parts["cell"].size
-    return {"value": n * steps / dt, "unit": "pushes/s", "cores": 1, "kind": "oracle",
-            "sample": f"{steps} full FP64 steps (push, sort, deposit, field advance) of the "
-                      f"{cfg.name} workload, {n} particles, single-threaded, {dt:.1f} s"}
+    out = {"value": n * steps / dt, "unit": "pushes/s", "cores": 1, "kind": "oracle",
+           "sample": f"{steps} full FP64 steps (push, sort, deposit, field advance) of the "
+                     f"{cfg.name} workload, {n} particles, single-threaded, {dt:.1f} s",
+           "host_cpu": _host_cpu(), "host_threads": os.cpu_count()}
+    return out, first
+
+
+def timing_stride(steps: int, every: int) -> int:
+    """Stride of the timed launches: every `every`-th, but at least
+    MIN_TIMED_LAUNCHES of the `steps` (or all of them when there are fewer)."""
+    return max(1, min(every, steps // MIN_TIMED_LAUNCHES))
+
+
+def _changed_cell_fraction(g):
+    """Fraction of the ions whose cell changes in one (extra, untimed) step,
+    from the store before and after (gather-map sequence: position k of the
+    pushed store is map entry k of the old one); None in place."""
+    if not g.gather_map or g.np == 0:
+        return None
+    n = g.np
+    old = g.p.cell[:n][g.perm[:n].long()].cpu()
+    g.step(order_caller=True)
+    g.synchronize()
+    new = g.p.cell[:n].cpu()
+    return float((old != new).float().mean())
 
 
 def main() -> int:
@@ -123,6 +169,16 @@ def main() -> int:
     n = int(parts["cell"].size)
     g = S.GpuSim(cfg, parts, B, fused=not args.unfused, overlap=not args.no_overlap,
                  gather_map=not (args.unfused or args.no_gather_map))
+    # one step of a fresh copy of the same start, for the error against the
+    # oracle's first step (cpu_baseline leg)
+    g1 = None
+    if not args.no_cpu_baseline:
+        g1 = S.GpuSim(cfg, parts, B, fused=g.fused, overlap=g.overlap, gather_map=g.gather_map)
+        g1.step()
+        g1.synchronize()
+        first_gpu = {"n": g1.n_prev.cpu().numpy(), "J": g1.J_prev.cpu().numpy(),
+                     "B": g1.B.cpu().numpy(), "E": g1.E.cpu().numpy()}
+        del g1
     mode = "gather map" if g.gather_map else "in place"
     # the steps need not order the caller's stream: synchronize() follows
     for _ in range(args.warmup):
@@ -131,8 +187,8 @@ def main() -> int:
     c = g.ctx.ctx
     # HIP events recorded by the library on its own stream right around every
     # k-th launch of the dominant kernel (and of the sort's scatter) over the
-    # timed steps
-    every = max(1, args.time_every)
+    # timed steps; at least MIN_TIMED_LAUNCHES of them (or every step)
+    every = timing_stride(args.steps, args.time_every)
     n_timed = (args.steps + every - 1) // every
     H.hvpic_timing_enable(c, n_timed, every)
     torch.cuda.synchronize()
@@ -149,8 +205,10 @@ def main() -> int:
     kernel_ms = k_ms / k_launches
     flags, counts = g.status()
     ms_per_step = wall * 1e3 / args.steps
+    moved = _changed_cell_fraction(g)
 
-    per_launch = BYTES_PER_PARTICLE_2D[mode] * n + BYTES_PER_CELL_2D * cfg.ncell
+    per_launch = BYTES_PER_PARTICLE_2D * n + BYTES_PER_CELL_2D * cfg.ncell
+    impl_launch = per_launch + EXTRA_BYTES_PER_PARTICLE_2D[mode] * n
     achieved = per_launch / (kernel_ms * 1e-3) / 1e9
     out = {
         "metric": METRIC,
@@ -167,7 +225,8 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": cfg.name, "cells": [cfg.nx, cfg.ny], "particles": n,
                    "shape": "QS", "b_subcycles": cfg.nsub, "dt": cfg.dt,
-                   "fused_deposit": g.fused, "push_reads": mode},
+                   "fused_deposit": g.fused, "push_reads": mode,
+                   "ions_changing_cell_per_step": moved},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": _traffic(n, mode),
@@ -176,7 +235,9 @@ def main() -> int:
                                 if g.fused else "k_gather_push"),
                      "kernel_ms": kernel_ms,
                      "kernel_timed_launches": f"{k_launches} of {args.steps} (every {every})",
-                     "algorithmic_bytes_per_launch": per_launch},
+                     "algorithmic_bytes_per_launch": per_launch,
+                     "sequence_bytes_per_launch": impl_launch,
+                     "sequence_frac": impl_launch / (kernel_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "kernels_ms": {"gather_push_deposit": kernel_ms,
                        "sort_scatter": s_ms / max(s_launches, 1)},
         "overlap_sort_with_field_advance": g.overlap,
@@ -184,8 +245,12 @@ def main() -> int:
         "status_flags": flags,
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cfg, parts, B)
-        out["cpu_baseline"]["host"] = os.uname().machine
+        import numpy as np
+
+        out["cpu_baseline"], first = cpu_baseline(cfg, parts, B)
+        out["one_step_rel_l2_vs_oracle"] = {
+            k: float(np.linalg.norm(first_gpu[k] - first[k]) / np.linalg.norm(first[k]))
+            for k in ("n", "J", "B", "E")}
     print(json.dumps(out), flush=True)
     return 0
 

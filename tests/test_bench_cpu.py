@@ -22,13 +22,20 @@ def test_more_than_one_gpu_is_refused():
 def test_algorithmic_bytes_follow_the_store_layout():
     # 2D SoA store: cell int32, two offsets, three velocities, weight (FP32)
     store = 4 + 2 * 4 + 3 * 4 + 4
-    # in place: read the whole store, write all but the weight
-    assert bench.BYTES_PER_PARTICLE_2D["in place"] == store + (store - 4)
-    # through the map: read the map entry and the store, write the whole
-    # store (weights included) in sorted order
-    assert bench.BYTES_PER_PARTICLE_2D["gather map"] == 4 + store + store
+    # what the method moves: read the whole store, write all but the weight
+    assert bench.BYTES_PER_PARTICLE_2D == store + (store - 4)
+    # what the gather-map sequence adds: the map entry read, the weight written
+    assert bench.EXTRA_BYTES_PER_PARTICLE_2D == {"in place": 0, "gather map": 4 + 4}
     # per cell: E and B read (6 floats), n and J written (4 floats)
     assert bench.BYTES_PER_CELL_2D == 6 * 4 + 4 * 4
+
+
+def test_at_least_ten_launches_are_timed():
+    for steps, every in ((20, 10), (200, 10), (5, 10), (1000, 10), (35, 3), (10, 1)):
+        k = bench.timing_stride(steps, every)
+        assert 1 <= k <= every
+        timed = len(range(0, steps, k))  # launches 0, k, 2k, ... are timed
+        assert timed >= min(steps, bench.MIN_TIMED_LAUNCHES)
 
 
 def test_traffic_record_matches_only_its_workload_and_source():
