@@ -665,21 +665,66 @@ __global__ __launch_bounds__(1024) void k_field_diag_final(const double* part, i
   }
 }
 
-// One binomial (1,2,1)/4 pass along `axis` for ncomp component arrays.
-__global__ __launch_bounds__(kBlock) void k_smooth_axis(const float* __restrict__ in,
-                                                        float* __restrict__ out, int ncomp, int axis,
+// Binomial smoothing (Sec. II.B): one pass is the (1,2,1)/4 filter along x,
+// then y, then z.  A block smooths one component on one tile: it loads the
+// tile with a halo of kSmHalo cells (periodic indexing, so a grid smaller
+// than the halo wraps as often as needed), runs up to kSmHalo passes in LDS
+// (each axis filter is valid one cell further in, so after p passes the
+// tile itself is), and writes the tile.  Reads `in`, writes `out` (distinct:
+// neighbouring tiles read the halo of `in`).
+constexpr int kSmHalo = 4;
+template <int NDIM>
+struct SmTile {
+  static constexpr int TX = NDIM == 2 ? 32 : 8, TY = 8, TZ = NDIM == 2 ? 1 : 8;
+  static constexpr int H = kSmHalo, HZ = NDIM == 2 ? 0 : kSmHalo;
+  static constexpr int WX = TX + 2 * H, WY = TY + 2 * H, WZ = TZ + 2 * HZ;
+  static constexpr int N = WX * WY * WZ;
+};
+
+template <int NDIM>
+__global__ __launch_bounds__(kBlock) void k_smooth_tile(const float* __restrict__ in,
+                                                        float* __restrict__ out, int npasses,
                                                         FGeo g) {
-  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (t >= (int64_t)ncomp * g.ncell) return;
-  const int comp = (int)(t / g.ncell);
-  const int c = (int)(t - (int64_t)comp * g.ncell);
-  int i, j, k;
-  fijk(c, g, i, j, k);
-  const Nbr n = neighbours(c, i, j, k, g);
-  const int m = axis == 0 ? n.xm : (axis == 1 ? n.ym : n.zm);
-  const int p = axis == 0 ? n.xp : (axis == 1 ? n.yp : n.zp);
-  const float* f = in + (int64_t)comp * g.ncell;
-  out[(int64_t)comp * g.ncell + c] = 0.25f * (f[m] + 2.0f * f[c] + f[p]);
+  using T = SmTile<NDIM>;
+  __shared__ float A[T::N], Bf[T::N];
+  const int ntx = (g.nx + T::TX - 1) / T::TX, nty = (g.ny + T::TY - 1) / T::TY;
+  const int tile = blockIdx.x;
+  const int tx = tile % ntx, ty = (tile / ntx) % nty, tz = tile / (ntx * nty);
+  const int x0 = tx * T::TX - T::H, y0 = ty * T::TY - T::H, z0 = tz * T::TZ - T::HZ;
+  const float* f = in + (int64_t)blockIdx.y * g.ncell;
+  auto wrap = [](int a, int n) { a %= n; return a < 0 ? a + n : a; };
+  for (int q = threadIdx.x; q < T::N; q += kBlock) {
+    const int lx = q % T::WX, ly = (q / T::WX) % T::WY, lz = q / (T::WX * T::WY);
+    const int x = wrap(x0 + lx, g.nx), y = wrap(y0 + ly, g.ny), z = wrap(z0 + lz, g.nz);
+    A[q] = f[x + g.nx * (y + g.ny * z)];
+  }
+  __syncthreads();
+  float* cur = A;
+  float* nxt = Bf;
+  for (int pass = 0; pass < npasses; ++pass) {
+    for (int axis = 0; axis < NDIM; ++axis) {
+      const int st = axis == 0 ? 1 : (axis == 1 ? T::WX : T::WX * T::WY);
+      const int wa = axis == 0 ? T::WX : (axis == 1 ? T::WY : T::WZ);
+      for (int q = threadIdx.x; q < T::N; q += kBlock) {
+        const int la = axis == 0 ? q % T::WX : (axis == 1 ? (q / T::WX) % T::WY : q / (T::WX * T::WY));
+        // the cells at the buffer edge along this axis keep their value; they
+        // are outside the region still valid after this pass
+        nxt[q] = la > 0 && la < wa - 1 ? 0.25f * (cur[q - st] + 2.0f * cur[q] + cur[q + st]) : cur[q];
+      }
+      __syncthreads();
+      float* t = cur;
+      cur = nxt;
+      nxt = t;
+    }
+  }
+  float* o = out + (int64_t)blockIdx.y * g.ncell;
+  for (int q = threadIdx.x; q < T::TX * T::TY * T::TZ; q += kBlock) {
+    const int lx = q % T::TX, ly = (q / T::TX) % T::TY, lz = q / (T::TX * T::TY);
+    const int x = tx * T::TX + lx, y = ty * T::TY + ly, z = tz * T::TZ + lz;
+    if (x < g.nx && y < g.ny && z < g.nz)
+      o[x + g.nx * (y + g.ny * z)] =
+          cur[(lx + T::H) + T::WX * ((ly + T::H) + T::WY * (lz + T::HZ))];
+  }
 }
 
 __global__ void k_copy(const float* __restrict__ in, float* __restrict__ out, int64_t n) {
@@ -861,15 +906,21 @@ int launch_smooth(hvpic_ctx* c, float* F, int ncomp, int npasses) {
   const FGeo g = fgeo(c);
   const int64_t total = (int64_t)ncomp * c->ncell;
   if (total == 0 || npasses == 0) return HVPIC_OK;
-  const dim3 grid((unsigned)ceil_div(total, kBlock)), blk(kBlock);
-  float* T = c->fscratch;
-  for (int pass = 0; pass < npasses; ++pass) {
-    hipLaunchKernelGGL(k_smooth_axis, grid, blk, 0, c->stream, (const float*)F, T, ncomp, 0, g);
-    hipLaunchKernelGGL(k_smooth_axis, grid, blk, 0, c->stream, (const float*)T, F, ncomp, 1, g);
-    if (c->p.ndim == 3) {
-      hipLaunchKernelGGL(k_smooth_axis, grid, blk, 0, c->stream, (const float*)F, T, ncomp, 2, g);
-      hipLaunchKernelGGL(k_copy, dim3(1024), blk, 0, c->stream, (const float*)T, F, total);
-    }
+  float* T = c->fscratch;  // [ncomp][ncell] staging of one launch's output
+  auto tiles = [&](auto tile) {
+    return (unsigned)(ceil_div(c->p.nx, tile.TX) * ceil_div(c->p.ny, tile.TY) *
+                      ceil_div(c->p.nz, tile.TZ));
+  };
+  for (int done = 0; done < npasses; done += kSmHalo) {
+    const int p = std::min(kSmHalo, npasses - done);
+    if (c->p.ndim == 2)
+      hipLaunchKernelGGL(k_smooth_tile<2>, dim3(tiles(SmTile<2>{}), ncomp), dim3(kBlock), 0,
+                         c->stream, (const float*)F, T, p, g);
+    else
+      hipLaunchKernelGGL(k_smooth_tile<3>, dim3(tiles(SmTile<3>{}), ncomp), dim3(kBlock), 0,
+                         c->stream, (const float*)F, T, p, g);
+    hipLaunchKernelGGL(k_copy, dim3((unsigned)std::min<int64_t>(ceil_div(total, kBlock), 2048)),
+                       dim3(kBlock), 0, c->stream, (const float*)T, F, total);
   }
   return hipGetLastError() == hipSuccess ? HVPIC_OK : HVPIC_EHIP;
 }

@@ -320,14 +320,22 @@ def test_field_advance_2d_tiles(H, nx, ny, nsub):
         check_field_diag(diag.cpu().numpy(), rd)
 
 
-@pytest.mark.parametrize("name,cfg", [CASES[0], CASES[2]])
-def test_smooth(H, name, cfg):
-    announce("smooth", name)
-    F = W.random_field(81, cfg, 1.0)
+@pytest.mark.parametrize("name,cfg", [CASES[0], CASES[2], ("2d-3x2", cfg2(nx=3, ny=2)),
+                                      ("3d-1x5x2", cfg3(nx=1, ny=5, nz=2)),
+                                      ("2d-70x19", cfg2(nx=70, ny=19))])
+@pytest.mark.parametrize("npasses,ncomp", [(1, 3), (3, 3), (5, 1), (9, 3)])
+def test_smooth(H, name, cfg, npasses, ncomp):
+    """Binomial passes on LDS tiles (up to four per launch, so 5 and 9 take
+    several launches), grids with ragged tiles and axes shorter than the
+    halo, one or three components."""
+    announce("smooth", name, npasses, ncomp)
+    F = W.random_field(81, cfg, 1.0)[:ncomp].copy()
+    if ncomp == 1:
+        F = F[0].copy()
     ctx = H.Context(cfg, 1)
     Fd = dev(F)
-    H.hvpic_smooth(ctx.ctx, Fd, 3)
-    assert rel_l2(Fd.cpu().numpy(), O.smooth(cfg, F, 3)) < 1e-6
+    H.hvpic_smooth(ctx.ctx, Fd, npasses)
+    assert rel_l2(Fd.cpu().numpy(), O.smooth(cfg, F, npasses)) < 1e-6
 
 
 def test_empty_and_single(H):
