@@ -35,7 +35,8 @@ class OrcParams(ctypes.Structure):
         ("qs", ctypes.c_double), ("ms", ctypes.c_double),
         ("te", ctypes.c_double), ("gamma_e", ctypes.c_double), ("n0", ctypes.c_double),
         ("n_floor", ctypes.c_double),
-        ("eta", ctypes.c_double),
+        ("eta", ctypes.c_double), ("eta_h", ctypes.c_double),
+        ("energy_eq", _i32), ("kappa0", ctypes.c_double),
     ]
 
 
@@ -66,8 +67,13 @@ def lib():
         L.orc_curl.argtypes = [P, _dp, _dp]
         L.orc_ohm.argtypes = [P, _dp, _dp, _dp, _dp]
         L.orc_field_advance.argtypes = [P, _dp, _dp, _dp, _dp, _dp, _dp, _i32, _dp, S]
+        L.orc_ohm_pe.argtypes = [P, _dp, _dp, _dp, _dp, _dp]
+        L.orc_pe_rate.argtypes = [P, _dp, _dp, _dp, _dp, _dp]
+        L.orc_field_advance_pe.argtypes = [P, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _i32, _dp,
+                                           S]
         for f in ("orc_gather", "orc_boris", "orc_push", "orc_sort", "orc_deposit",
-                  "orc_smooth", "orc_curl", "orc_ohm", "orc_field_advance"):
+                  "orc_smooth", "orc_curl", "orc_ohm", "orc_field_advance", "orc_ohm_pe",
+                  "orc_pe_rate", "orc_field_advance_pe"):
             getattr(L, f).restype = None
         _LIB = L
     return _LIB
@@ -76,7 +82,8 @@ def lib():
 def params(cfg) -> OrcParams:
     return OrcParams(cfg.ndim, cfg.nx, cfg.ny, cfg.nz, cfg.dx, cfg.dy, cfg.dz, cfg.dt,
                      cfg.nsub, cfg.shape, cfg.nsmooth, cfg.qs, cfg.ms, cfg.te,
-                     cfg.gamma_e, cfg.n0, cfg.n_floor, cfg.eta)
+                     cfg.gamma_e, cfg.n0, cfg.n_floor, cfg.eta, cfg.eta_h,
+                     int(cfg.energy_eq), cfg.kappa0)
 
 
 def _d(a):
@@ -180,6 +187,45 @@ def ohm(cfg, B, n, Ji):
     return E
 
 
+def ohm_pe(cfg, B, n, Ji, pe):
+    E = np.zeros((3, cfg.ncell))
+    lib().orc_ohm_pe(ctypes.byref(params(cfg)), _d(f64(B)), _d(f64(n)), _d(f64(Ji)),
+                     _d(f64(pe)), _d(E))
+    return E
+
+
+def pe_rate(cfg, B, n, Ji, pe):
+    R = np.zeros(cfg.ncell)
+    lib().orc_pe_rate(ctypes.byref(params(cfg)), _d(f64(B)), _d(f64(n)), _d(f64(Ji)),
+                      _d(f64(pe)), _d(R))
+    return R
+
+
+def eos_pressure(cfg, n):
+    """p_e = n0 te (n/n0)^gamma of the floored density (Sec. II.A): the
+    starting pressure of a run with the energy equation."""
+    ne = np.maximum(f64(n), cfg.n_floor)
+    return cfg.n0 * cfg.te * (ne / cfg.n0) ** cfg.gamma_e
+
+
+def field_advance_pe(cfg, B, pe, n_half, J_half, n_prev=None, J_prev=None, mode=0):
+    """Field advance with p_e evolved by the energy equation.  Returns
+    (B_new, pe_new, E_out, diag[3], status); B and pe are not modified."""
+    if cfg.gamma_e == 1.0:
+        raise ValueError("the energy equation needs gamma_e != 1 (W_e = sum p_e V/(gamma-1))")
+    B = f64(B).copy()
+    pe = f64(pe).copy()
+    E = np.zeros((3, cfg.ncell))
+    diag = np.zeros(3)
+    st = OrcStatus()
+    n_prev = f64(n_half if n_prev is None else n_prev)
+    J_prev = f64(J_half if J_prev is None else J_prev)
+    lib().orc_field_advance_pe(ctypes.byref(params(cfg)), _d(B), _d(pe), _d(f64(n_half)),
+                               _d(f64(J_half)), _d(n_prev), _d(J_prev), _d(E), int(mode),
+                               _d(diag), ctypes.byref(st))
+    return B, pe, E, diag, st
+
+
 def field_advance(cfg, B, n_half, J_half, n_prev=None, J_prev=None, mode=0):
     """Returns (B_new, E_out, diag[3] = {W_B, W_dB, W_e}, status); B is not modified."""
     B = f64(B).copy()
@@ -213,8 +259,8 @@ class OracleSim:
         if cfg.nsmooth:
             self.n_prev = smooth(cfg, self.n_prev, cfg.nsmooth)
             self.J_prev = smooth(cfg, self.J_prev, cfg.nsmooth)
-        _, self.E, self.field_diag, _ = field_advance(cfg, self.B, self.n_prev,
-                                                      self.J_prev, mode=1)
+        self.pe = eos_pressure(cfg, self.n_prev) if cfg.energy_eq else None
+        self._advance(self.n_prev, self.J_prev, None, None, mode=1)
         self.status = OrcStatus()
         self.push_diag = np.zeros(4)
         self.nstep = 0
@@ -235,8 +281,19 @@ class OracleSim:
             n_half = smooth(cfg, n_half, cfg.nsmooth)
             J_half = smooth(cfg, J_half, cfg.nsmooth)
         self.n_half, self.J_half = n_half, J_half
-        self.B, self.E, self.field_diag, st = field_advance(
-            cfg, self.B, n_half, J_half, self.n_prev, self.J_prev, mode=0)
+        st = self._advance(n_half, J_half, self.n_prev, self.J_prev, mode=0)
         self.status.floor_hits += st.floor_hits
         self.n_prev, self.J_prev = n_half, J_half
         self.nstep += 1
+
+    def _advance(self, n_half, J_half, n_prev, J_prev, mode):
+        cfg = self.cfg
+        if cfg.energy_eq:
+            B, self.pe, self.E, self.field_diag, st = field_advance_pe(
+                cfg, self.B, self.pe, n_half, J_half, n_prev, J_prev, mode=mode)
+        else:
+            B, self.E, self.field_diag, st = field_advance(cfg, self.B, n_half, J_half,
+                                                           n_prev, J_prev, mode=mode)
+        if mode == 0:
+            self.B = B
+        return st

@@ -9,8 +9,9 @@
  *   boris ...... Sec. II.B, eq:vadv and the Boris description after it
  *   move ....... Sec. II.B, position update and the (I, dx,dy,dz) store
  *   deposit .... Sec. II.B eq:ngp (NGP); App. B eq:quad (QS)
- *   ohm ........ Sec. II.A eq:ohm, density floor, Ampere, EOS
+ *   ohm ........ Sec. II.A eq:ohm, density floor, Ampere, EOS, R_ei
  *   faraday .... Sec. II.A Faraday + subcycling; Sec. II.B extrapolation
+ *   energy eq .. Sec. II.A eq:dpdt with Q_e = -kappa grad T_e (H_ei = 0)
  *   gradients .. Sec. II.B centred differences on the cell-centred grid
  *   smoothing .. Sec. II.B (binomial passes; the cited method is not in the
  *                paper, the (1,2,1)/4 reading is documented)
@@ -314,19 +315,30 @@ void orc_curl(const orc_params* p, const double* A, double* C) {
   }
 }
 
+/* Compact second difference of scalar Q along axis a at (i,j,k):
+   (Q_{+1} - 2 Q + Q_{-1}) / Delta_a^2 (an axis of one cell gives 0). */
+static double d2(const orc_params* p, const double* Q, int a, int i, int j, int k) {
+  int di = a == 0, dj = a == 1, dk = a == 2;
+  double h = a == 0 ? p->dx : (a == 1 ? p->dy : p->dz);
+  return (Q[cell_of(p, i + di, j + dj, k + dk)] - 2.0 * Q[cell_of(p, i, j, k)] +
+          Q[cell_of(p, i - di, j - dj, k - dk)]) / (h * h);
+}
+
+/* Laplacian as the sum of the compact second differences (the reading of
+   nabla^2 in the hyper-resistive term and in div(kappa grad T_e)). */
+static double lap(const orc_params* p, const double* Q, int i, int j, int k) {
+  return d2(p, Q, 0, i, j, k) + d2(p, Q, 1, i, j, k) + d2(p, Q, 2, i, j, k);
+}
+
 /* Ohm's law (eq:ohm) with mu0 J = curl B (low-frequency Ampere), the density
-   floor n_e <- max(n_e, n_f) applied to every use of the density, the EOS
-   p_e = n0 te (n_e/n0)^gamma and R_ei = eta J:
-     E = -grad(p_e)/n_e - u_i x B + (J x B)/n_e + eta J,  u_i = J_i / n_e. */
-void orc_ohm(const orc_params* p, const double* B, const double* n, const double* Ji,
-             double* E) {
+   floor n_e <- max(n_e, n_f) applied to every use of the density, a given
+   electron pressure and R_ei = eta J - eta_h lap J:
+     E = -grad(p_e)/n_e - u_i x B + (J x B)/n_e + eta J - eta_h lap J,
+   u_i = J_i / n_e. */
+void orc_ohm_pe(const orc_params* p, const double* B, const double* n, const double* Ji,
+                const double* pe, double* E) {
   int64_t nc = ncell_of(p);
-  double* pe = (double*)malloc(sizeof(double) * (size_t)nc);
   double* J = (double*)malloc(sizeof(double) * 3 * (size_t)nc);
-  for (int64_t c = 0; c < nc; ++c) {
-    double ne = n[c] > p->n_floor ? n[c] : p->n_floor;
-    pe[c] = p->n0 * p->te * pow(ne / p->n0, p->gamma_e);
-  }
   orc_curl(p, B, J);
   for (int64_t c = 0; c < nc; ++c) {
     int i, j, k;
@@ -341,11 +353,70 @@ void orc_ohm(const orc_params* p, const double* B, const double* n, const double
                      ui[0] * b[1] - ui[1] * b[0]};
     double jxb[3] = {jt[1] * b[2] - jt[2] * b[1], jt[2] * b[0] - jt[0] * b[2],
                      jt[0] * b[1] - jt[1] * b[0]};
-    for (int a = 0; a < 3; ++a)
-      E[c + a * nc] = -gp[a] / ne - uxb[a] + jxb[a] / ne + p->eta * jt[a];
+    for (int a = 0; a < 3; ++a) {
+      double hyper = p->eta_h != 0.0 ? p->eta_h * lap(p, J + a * nc, i, j, k) : 0.0;
+      E[c + a * nc] = -gp[a] / ne - uxb[a] + jxb[a] / ne + p->eta * jt[a] - hyper;
+    }
   }
-  free(pe);
   free(J);
+}
+
+/* The EOS p_e = n0 te (n_e/n0)^gamma (Sec. II.A) of the floored density. */
+static void eos_pressure(const orc_params* p, const double* n, double* pe) {
+  int64_t nc = ncell_of(p);
+  for (int64_t c = 0; c < nc; ++c) {
+    double ne = n[c] > p->n_floor ? n[c] : p->n_floor;
+    pe[c] = p->n0 * p->te * pow(ne / p->n0, p->gamma_e);
+  }
+}
+
+void orc_ohm(const orc_params* p, const double* B, const double* n, const double* Ji,
+             double* E) {
+  int64_t nc = ncell_of(p);
+  double* pe = (double*)malloc(sizeof(double) * (size_t)nc);
+  eos_pressure(p, n, pe);
+  orc_ohm_pe(p, B, n, Ji, pe, E);
+  free(pe);
+}
+
+/* Electron energy equation (eq:dpdt) with H_ei = 0 and Q_e = -kappa0 grad T_e:
+     dp_e/dt = -gamma div(p_e u_e) + (gamma-1) u_e.grad p_e
+               + (gamma-1) kappa0 lap T_e,
+   u_e = -(curl B - J_i)/n_e (massless electrons, e = mu0 = 1), T_e = p_e/n_e,
+   n_e floored.  The divergence and gradient are centred differences, the
+   conduction term the compact Laplacian (a constant kappa0 makes
+   div(kappa0 grad T) = kappa0 lap T). */
+void orc_pe_rate(const orc_params* p, const double* B, const double* n, const double* Ji,
+                 const double* pe, double* rate) {
+  int64_t nc = ncell_of(p);
+  double g = p->gamma_e;
+  double* J = (double*)malloc(sizeof(double) * 3 * (size_t)nc);
+  double* ue = (double*)malloc(sizeof(double) * 3 * (size_t)nc);
+  double* flux = (double*)malloc(sizeof(double) * 3 * (size_t)nc);
+  double* T = (double*)malloc(sizeof(double) * (size_t)nc);
+  orc_curl(p, B, J);
+  for (int64_t c = 0; c < nc; ++c) {
+    double ne = n[c] > p->n_floor ? n[c] : p->n_floor;
+    for (int a = 0; a < 3; ++a) {
+      ue[c + a * nc] = (Ji[c + a * nc] - J[c + a * nc]) / ne;
+      flux[c + a * nc] = pe[c] * ue[c + a * nc];
+    }
+    T[c] = pe[c] / ne;
+  }
+  for (int64_t c = 0; c < nc; ++c) {
+    int i, j, k;
+    ijk_of(p, c, &i, &j, &k);
+    double div = 0.0, adv = 0.0;
+    for (int a = 0; a < 3; ++a) {
+      div += dcentred(p, flux + a * nc, a, i, j, k);
+      adv += ue[c + a * nc] * dcentred(p, pe, a, i, j, k);
+    }
+    rate[c] = -g * div + (g - 1.0) * adv + (g - 1.0) * p->kappa0 * lap(p, T, i, j, k);
+  }
+  free(J);
+  free(ue);
+  free(flux);
+  free(T);
 }
 
 /* Field and electron energies of the state a field advance leaves behind:
@@ -357,9 +428,10 @@ void orc_ohm(const orc_params* p, const double* B, const double* n, const double
               else:       sum p_e V_c / (gamma - 1),  p_e = n0 te (n/n0)^gamma.
    W_e is the electron term of the energy budget of the hybrid equations
    (Sec. II.A): with eq:ohm, Ampere and Faraday the pressure work -u_e . grad p_e
-   is the time derivative of exactly this energy (electron continuity). */
+   is the time derivative of exactly this energy (electron continuity).  With
+   an evolved pressure pe (energy equation) W_e = sum p_e V / (gamma - 1). */
 static void field_energy(const orc_params* p, const double* B, const double* n,
-                         double diag[3]) {
+                         const double* pe, double diag[3]) {
   int64_t nc = ncell_of(p);
   double V = cell_volume(p);
   double mean[3] = {0, 0, 0}, wb = 0.0, wdb = 0.0, we = 0.0;
@@ -375,7 +447,9 @@ static void field_energy(const orc_params* p, const double* B, const double* n,
     }
   for (int64_t c = 0; c < nc; ++c) {
     double ne = n[c] > p->n_floor ? n[c] : p->n_floor;
-    if (p->gamma_e == 1.0)
+    if (pe)
+      we += pe[c] * V / (p->gamma_e - 1.0);
+    else if (p->gamma_e == 1.0)
       we += p->te * ne * log(ne / p->n0) * V;
     else
       we += p->n0 * p->te * pow(ne / p->n0, p->gamma_e) * V / (p->gamma_e - 1.0);
@@ -401,7 +475,7 @@ void orc_field_advance(const orc_params* p, double* B, const double* n_half,
       if (n_half[c] < p->n_floor) st->floor_hits += 1;
   if (mode == 1) {
     orc_ohm(p, B, n_half, J_half, E_out);
-    if (diag) field_energy(p, B, n_half, diag);
+    if (diag) field_energy(p, B, n_half, NULL, diag);
     return;
   }
   size_t v3 = sizeof(double) * 3 * (size_t)nc;
@@ -421,9 +495,63 @@ void orc_field_advance(const orc_params* p, double* B, const double* n_half,
   for (int64_t c = 0; c < nc; ++c) n1[c] = 1.5 * n_half[c] - 0.5 * n_prev[c];
   for (int64_t c = 0; c < 3 * nc; ++c) Bs[c] = 1.5 * J_half[c] - 0.5 * J_prev[c];
   orc_ohm(p, B, n1, Bs, E_out);
-  if (diag) field_energy(p, B, n1, diag);
+  if (diag) field_energy(p, B, n1, NULL, diag);
   free(n1);
   free(Ea);
   free(C);
   free(Bs);
+}
+
+/* Field advance with the electron energy equation: the state (B, p_e) is
+   advanced by the same explicit midpoint rule per substep, with the moments
+   held at n+1/2 (eq:dpdt is integrated within the loop of the magnetic
+   field, Sec. II.A):
+     Ea = Ohm(B, p_e), Ra = rate(B, p_e),
+     B* = B - (h/2) curl Ea, p_e* = p_e + (h/2) Ra,
+     Eb = Ohm(B*, p_e*), Rb = rate(B*, p_e*),
+     B <- B - h curl Eb, p_e <- p_e + h Rb;
+   then E^{n+1} = Ohm(B^{n+1}, n^{n+1}, J^{n+1}, p_e^{n+1}) with the moments
+   extrapolated as in orc_field_advance. */
+void orc_field_advance_pe(const orc_params* p, double* B, double* pe, const double* n_half,
+                          const double* J_half, const double* n_prev, const double* J_prev,
+                          double* E_out, int32_t mode, double diag[3], orc_status* st) {
+  int64_t nc = ncell_of(p);
+  if (st)
+    for (int64_t c = 0; c < nc; ++c)
+      if (n_half[c] < p->n_floor) st->floor_hits += 1;
+  if (mode == 1) {
+    orc_ohm_pe(p, B, n_half, J_half, pe, E_out);
+    if (diag) field_energy(p, B, n_half, pe, diag);
+    return;
+  }
+  size_t v3 = sizeof(double) * 3 * (size_t)nc, v1 = sizeof(double) * (size_t)nc;
+  double* Ea = (double*)malloc(v3);
+  double* C = (double*)malloc(v3);
+  double* Bs = (double*)malloc(v3);
+  double* R = (double*)malloc(v1);
+  double* ps = (double*)malloc(v1);
+  double h = p->dt / p->nsub;
+  for (int m = 0; m < p->nsub; ++m) {
+    orc_ohm_pe(p, B, n_half, J_half, pe, Ea);
+    orc_pe_rate(p, B, n_half, J_half, pe, R);
+    orc_curl(p, Ea, C);
+    for (int64_t c = 0; c < 3 * nc; ++c) Bs[c] = B[c] - 0.5 * h * C[c];
+    for (int64_t c = 0; c < nc; ++c) ps[c] = pe[c] + 0.5 * h * R[c];
+    orc_ohm_pe(p, Bs, n_half, J_half, ps, Ea);
+    orc_pe_rate(p, Bs, n_half, J_half, ps, R);
+    orc_curl(p, Ea, C);
+    for (int64_t c = 0; c < 3 * nc; ++c) B[c] = B[c] - h * C[c];
+    for (int64_t c = 0; c < nc; ++c) pe[c] = pe[c] + h * R[c];
+  }
+  double* n1 = (double*)malloc(v1);
+  for (int64_t c = 0; c < nc; ++c) n1[c] = 1.5 * n_half[c] - 0.5 * n_prev[c];
+  for (int64_t c = 0; c < 3 * nc; ++c) Bs[c] = 1.5 * J_half[c] - 0.5 * J_prev[c];
+  orc_ohm_pe(p, B, n1, Bs, pe, E_out);
+  if (diag) field_energy(p, B, n1, pe, diag);
+  free(n1);
+  free(Ea);
+  free(C);
+  free(Bs);
+  free(R);
+  free(ps);
 }

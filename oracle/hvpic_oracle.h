@@ -37,7 +37,10 @@ typedef struct {
   int32_t nsub, shape, nsmooth;
   double qs, ms;                   /* species charge Z e and mass           */
   double te, gamma_e, n0, n_floor; /* p_e = n0 te (n/n0)^gamma, density floor */
-  double eta;                      /* resistivity in R_ei = eta J          */
+  double eta;                      /* resistivity in R_ei = eta J - eta_h lap J */
+  double eta_h;                    /* hyper-resistivity                    */
+  int32_t energy_eq;               /* 1: p_e evolved by the energy equation */
+  double kappa0;                   /* heat conductivity in Q_e = -kappa0 grad T_e */
 } orc_params;
 
 typedef struct {
@@ -80,9 +83,29 @@ void orc_smooth(const orc_params* p, double* F, int32_t ncomp, int32_t npasses);
 /* Centred-difference curl, C = D x A. */
 void orc_curl(const orc_params* p, const double* A, double* C);
 
-/* Ohm's law (eq:ohm) with the density floor; E[3*ncell] overwritten. */
+/* Ohm's law (eq:ohm) with the density floor and p_e from the EOS;
+   E[3*ncell] overwritten. */
 void orc_ohm(const orc_params* p, const double* B, const double* n,
              const double* Ji, double* E);
+
+/* The same with a given electron pressure pe[ncell] instead of the EOS. */
+void orc_ohm_pe(const orc_params* p, const double* B, const double* n,
+                const double* Ji, const double* pe, double* E);
+
+/* Right-hand side of the electron energy equation (eq:dpdt, H_ei = 0):
+   rate = -gamma div(p_e u_e) + (gamma-1) u_e.grad p_e + (gamma-1) kappa0 lap T_e,
+   u_e = (J_i - curl B)/n_f, T_e = p_e/n_f; rate[ncell] overwritten. */
+void orc_pe_rate(const orc_params* p, const double* B, const double* n,
+                 const double* Ji, const double* pe, double* rate);
+
+/* Field advance with the electron pressure evolved by eq:dpdt in the same
+   RK2 subcycle as B (pe[ncell] in/out); otherwise as orc_field_advance, with
+   E from the evolved p_e.  diag[3] = {W_B, W_dB, W_e = sum p_e V/(gamma-1)}. */
+void orc_field_advance_pe(const orc_params* p, double* B, double* pe,
+                          const double* n_half, const double* J_half,
+                          const double* n_prev, const double* J_prev,
+                          double* E_out, int32_t mode, double diag[3],
+                          orc_status* st);
 
 /* Field advance.  mode 0: nsub RK2-midpoint Faraday substeps of B with the
    moments frozen at n+1/2, then J_i, n extrapolated to n+1 and

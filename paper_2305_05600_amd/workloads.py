@@ -54,6 +54,8 @@ class Config:
     n_floor: float = 0.05
     eta: float = 1e-3
     eta_h: float = 0.0
+    energy_eq: int = 0
+    kappa0: float = 0.0
     steps: int = 1
 
     @property

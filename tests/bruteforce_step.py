@@ -13,7 +13,10 @@ is deliberately written another way wherever the method allows:
     the implicit midpoint rule, (I - T) v+ = (I + T) v-, with T v = v x t;
   * the stable sort is numpy's stable argsort;
   * the field solver (Sec. II.A eq:ohm, Ampere, Faraday) uses np.roll
-    stencils.
+    stencils; the Laplacian of the hyper-resistive and the conduction terms is
+    taken as a backward difference of a forward difference;
+  * with the electron energy equation (eq:dpdt) the pressure is advanced in
+    the same RK2 stages as B, and W_e = sum p_e V / (gamma - 1).
 The step order and the readings are those of the oracle: deposit at
 x^{n+1/2}; the moments extrapolated as 3/2 (n+1/2) - 1/2 (n-1/2); RK2
 subcycle with the moments frozen at n+1/2; v^{-1/2} = v^0 and the level -1/2
@@ -119,22 +122,55 @@ def curl(g: Grid, A):
                      dc(g, A[1], 0) - dc(g, A[0], 1)])
 
 
-def ohm(g: Grid, cfg, B, n, Ji):
+def lap(g: Grid, Q):
+    """Sum over the axes of D-(D+ Q), D+- the one-sided differences."""
+    shape = (g.n[2], g.n[1], g.n[0])
+    q = Q.reshape(shape)
+    out = np.zeros(shape)
+    for axis in range(3):
+        ax = 2 - axis
+        fwd = (np.roll(q, -1, ax) - q) / g.h[axis]
+        out += (fwd - np.roll(fwd, 1, ax)) / g.h[axis]
+    return out.reshape(-1)
+
+
+def eos(cfg, n):
     nf = np.maximum(n, cfg.n_floor)
-    pe = cfg.n0 * cfg.te * (nf / cfg.n0) ** cfg.gamma_e
+    return cfg.n0 * cfg.te * (nf / cfg.n0) ** cfg.gamma_e
+
+
+def ohm(g: Grid, cfg, B, n, Ji, pe=None):
+    nf = np.maximum(n, cfg.n_floor)
+    if pe is None:
+        pe = eos(cfg, n)
     J = curl(g, B)
     u = Ji / nf
     gp = np.stack([dc(g, pe, a) for a in range(3)])
-    return (-np.cross(u.T, B.T).T + np.cross(J.T, B.T).T / nf - gp / nf + cfg.eta * J)
+    E = -np.cross(u.T, B.T).T + np.cross(J.T, B.T).T / nf - gp / nf + cfg.eta * J
+    if cfg.eta_h:
+        E -= cfg.eta_h * np.stack([lap(g, J[a]) for a in range(3)])
+    return E
 
 
-def energies(g: Grid, cfg, B, n):
+def pe_rate(g: Grid, cfg, B, n, Ji, pe):
+    """eq:dpdt with H_ei = 0 and Q_e = -kappa0 grad(p_e/n_e)."""
+    nf = np.maximum(n, cfg.n_floor)
+    ue = (Ji - curl(g, B)) / nf
+    gam = cfg.gamma_e
+    div = sum(dc(g, pe * ue[a], a) for a in range(3))
+    adv = sum(ue[a] * dc(g, pe, a) for a in range(3))
+    return -gam * div + (gam - 1.0) * adv + (gam - 1.0) * cfg.kappa0 * lap(g, pe / nf)
+
+
+def energies(g: Grid, cfg, B, n, pe=None):
     V = cfg.dx * cfg.dy * cfg.dz
     wb = 0.5 * np.sum(B * B) * V
     dB = B - B.mean(axis=1, keepdims=True)
     wdb = 0.5 * np.sum(dB * dB) * V
     nf = np.maximum(n, cfg.n_floor)
-    if cfg.gamma_e == 1.0:
+    if pe is not None:
+        we = np.sum(pe) * V / (cfg.gamma_e - 1.0)
+    elif cfg.gamma_e == 1.0:
         we = cfg.te * np.sum(nf * np.log(nf / cfg.n0)) * V
     else:
         we = np.sum(cfg.n0 * cfg.te * (nf / cfg.n0) ** cfg.gamma_e) * V / (cfg.gamma_e - 1.0)
@@ -162,7 +198,8 @@ class BruteSim:
         cfg = self.cfg
         self.B = np.asarray(B, np.float64).copy()
         self.n_prev, self.J_prev = deposit(self.g, cfg, self.X, self.v, self.w)
-        self.E = ohm(self.g, cfg, self.B, self.n_prev, self.J_prev)
+        self.pe = eos(cfg, self.n_prev) if cfg.energy_eq else None
+        self.E = ohm(self.g, cfg, self.B, self.n_prev, self.J_prev, self.pe)
 
     def particles(self):
         cell, o = to_cell(self.g, self.X)
@@ -191,11 +228,18 @@ class BruteSim:
             Xm[2] = self.X[2]
         n_half, J_half = deposit(g, cfg, Xm, self.v, self.w)
         h = cfg.dt / cfg.nsub
+        pe = self.pe
         for _ in range(cfg.nsub):
-            Bs = self.B - 0.5 * h * curl(g, ohm(g, cfg, self.B, n_half, J_half))
-            self.B = self.B - h * curl(g, ohm(g, cfg, Bs, n_half, J_half))
+            Bs = self.B - 0.5 * h * curl(g, ohm(g, cfg, self.B, n_half, J_half, pe))
+            if pe is not None:
+                ps = pe + 0.5 * h * pe_rate(g, cfg, self.B, n_half, J_half, pe)
+                pe = pe + h * pe_rate(g, cfg, Bs, n_half, J_half, ps)
+            else:
+                ps = None
+            self.B = self.B - h * curl(g, ohm(g, cfg, Bs, n_half, J_half, ps))
+        self.pe = pe
         n1 = 1.5 * n_half - 0.5 * self.n_prev
         J1 = 1.5 * J_half - 0.5 * self.J_prev
-        self.E = ohm(g, cfg, self.B, n1, J1)
-        self.field_diag = energies(g, cfg, self.B, n1)
+        self.E = ohm(g, cfg, self.B, n1, J1, pe)
+        self.field_diag = energies(g, cfg, self.B, n1, pe)
         self.n_prev, self.J_prev = n_half, J_half

@@ -30,6 +30,13 @@ CASES = [
     ("3d-ngp-4x3x5", _cfg(3, 4, 3, 5, W.SHAPE_NGP), 5.0),
     ("2d-qs-2x7", _cfg(2, 2, 7, 1, W.SHAPE_QS), 20.0),
     ("2d-qs-1x5-gamma", _cfg(2, 1, 5, 1, W.SHAPE_QS, gamma_e=5.0 / 3.0), 60.0),
+    ("2d-qs-6x5-hyper", _cfg(2, 6, 5, 1, W.SHAPE_QS, eta_h=3e-3), 10.0),
+    ("2d-qs-6x5-energy", _cfg(2, 6, 5, 1, W.SHAPE_QS, gamma_e=5.0 / 3.0, energy_eq=1,
+                              kappa0=0.05, eta_h=1e-3), 10.0),
+    ("3d-qs-4x3x5-energy", _cfg(3, 4, 3, 5, W.SHAPE_QS, gamma_e=5.0 / 3.0, energy_eq=1,
+                                kappa0=0.05, eta_h=1e-3), 5.0),
+    ("2d-qs-2x7-energy", _cfg(2, 2, 7, 1, W.SHAPE_QS, gamma_e=2.0, energy_eq=1,
+                              kappa0=0.02), 20.0),
 ]
 
 
@@ -61,3 +68,5 @@ def test_two_steps_match(name, cfg, ppc):
         assert b.K == pytest.approx(o.push_diag[0], rel=1e-12)
         assert np.allclose(b.P, o.push_diag[1:], rtol=1e-12, atol=1e-12 * np.abs(b.P).max())
         assert np.allclose(b.field_diag, o.field_diag, rtol=1e-12, atol=1e-14)
+        if cfg.energy_eq:
+            assert _rel(b.pe, o.pe) < 1e-12, (name, step)
