@@ -9,9 +9,11 @@
  *   - particle shapes NGP (Sec. II.B, eq:ngp) and QS (App. B, eq:quad for the
  *     deposit, eq:quadFI + eq:quadF for the gather);
  *   - Ohm's law for massless electrons (Sec. II.A, eq:ohm) with the density
- *     floor, low-frequency Ampere, an isothermal/polytropic EOS and
- *     R_ei = eta J; Faraday's law subcycled inside the particle step;
- *     J_i extrapolated to the full step (Sec. II.B);
+ *     floor, low-frequency Ampere, an isothermal/polytropic EOS or the
+ *     electron energy equation (eq:dpdt with a heat flux -kappa0 grad T_e)
+ *     and R_ei = eta J - eta_h lap J; Faraday's law (and the energy
+ *     equation) subcycled inside the particle step; J_i extrapolated to the
+ *     full step (Sec. II.B);
  *   - a stable counting sort of the particle store by cell (the store keeps a
  *     cell index plus in-cell offsets, Sec. II.B).
  *
@@ -84,8 +86,12 @@ typedef struct {
   double qs, ms;             /* ion species charge (Z e) and mass               */
   double te, gamma_e, n0;    /* EOS p_e = n0 te (n/n0)^gamma_e (Sec. II.A)      */
   double n_floor;            /* density floor n_f of the field solver           */
-  double eta;                /* resistivity: R_ei = eta J                       */
-  double eta_h;              /* hyper-resistivity; must be 0 in this version    */
+  double eta;                /* resistivity: R_ei = eta J - eta_h lap J         */
+  double eta_h;              /* hyper-resistivity (>= 0)                        */
+  int32_t energy_eq;         /* 0: p_e from the EOS; 1: p_e evolved by the
+                                electron energy equation (gamma_e > 1), through
+                                hvpic_field_advance_pe                          */
+  double kappa0;             /* electron heat conductivity (>= 0; energy_eq)    */
   int64_t np_capacity;       /* largest particle count any call will pass       */
 } hvpic_params;
 
@@ -217,10 +223,40 @@ int hvpic_deposit(hvpic_ctx* ctx, const hvpic_particles* p, const int32_t* cell_
    W_e = te sum n_f ln(n_f/n0) V_c for gamma_e = 1, else
    sum p_e V_c / (gamma_e - 1).  W_e is the electron term of the energy of
    the hybrid equations (Sec. II.A): with Ohm's law, Ampere and Faraday,
-   d/dt (K_i + W_B + W_e) = eta sum (J.J_i - |J|^2) V_c.  All FP64. */
+   d/dt (K_i + W_B + W_e) = eta sum (J.J_i - |J|^2) V_c.  All FP64.
+   With eta_h > 0 Ohm's law gains -eta_h lap J, lap the compact
+   (+1, -2, +1)/h^2 second difference summed over the axes, and the
+   resistive work above becomes sum (eta J - eta_h lap J).(J_i - J) V_c.
+   Returns HVPIC_EINVAL if the context's energy_eq is set (the pressure is
+   then state: use hvpic_field_advance_pe). */
 int hvpic_field_advance(hvpic_ctx* ctx, float* B, const float* n_half,
                         const float* J_half, const float* n_prev, const float* J_prev,
                         float* E_out, int mode, double* diag_out);
+
+/* Field advance with the electron energy equation (Sec. II.A eq:dpdt with
+   no collisional exchange and the heat flux Q_e = -kappa0 grad T_e), for a
+   context with energy_eq = 1.  The electron pressure pe [ncell] is state:
+   in mode 0 it is advanced in the same substeps as B,
+       (B*, p*) = (B, p) + (h/2) rates(B, p),  (B, p) += h rates(B*, p*),
+       dp/dt = -gamma div(p u_e) + (gamma-1) u_e.grad p
+               + (gamma-1) kappa0 lap (p/n_f),  u_e = (J_i - curl B)/n_f,
+   with n_half and J_half held fixed (centred div and grad, compact lap),
+   and overwritten with the result; Ohm's law everywhere takes
+   -grad(p)/n_f from the pressure instead of the EOS, and E_out is formed
+   from the final B, p and the extrapolated moments.  mode 1: E_out from
+   B, pe, n_half, J_half; nothing else is written.  diag_out as for
+   hvpic_field_advance with W_e = sum p V_c/(gamma_e - 1) of the pressure
+   E_out was formed from; then, with eta = eta_h = 0,
+   d/dt (K_i + W_B + W_e) = 0 exactly in the spatially discrete equations.
+   HVPIC_EINVAL unless energy_eq = 1, or for NULL arrays. */
+int hvpic_field_advance_pe(hvpic_ctx* ctx, float* B, float* pe, const float* n_half,
+                           const float* J_half, const float* n_prev, const float* J_prev,
+                           float* E_out, int mode, double* diag_out);
+
+/* The pressure of the equation of state, pe = n0 te (n_f/n0)^gamma_e with
+   n_f = max(n, n_floor), into pe [ncell]: the starting value of the electron
+   pressure for a run with the energy equation (Sec. II.A). */
+int hvpic_eos_pressure(hvpic_ctx* ctx, const float* n, float* pe);
 
 /* The deposit of hvpic_deposit, for callers that cannot allocate memory or
    create a context: code captured into a HIP graph, tight serving loops,

@@ -30,7 +30,10 @@ bool params_ok(const hvpic_params* p) {
       !finite_pos(p->n_floor))
     return false;
   if (!isfinite(p->eta) || p->eta < 0.0) return false;
-  if (p->eta_h != 0.0) return false;  // hyper-resistivity is not implemented
+  if (!isfinite(p->eta_h) || p->eta_h < 0.0) return false;
+  if (p->energy_eq != 0 && p->energy_eq != 1) return false;
+  if (p->energy_eq && !(p->gamma_e > 1.0)) return false;  // W_e = sum p V/(gamma-1)
+  if (!isfinite(p->kappa0) || p->kappa0 < 0.0) return false;
   if (p->np_capacity < 0 || p->np_capacity >= (1ll << 31) - 1) return false;
   return true;
 }
@@ -101,7 +104,7 @@ Layout workspace_layout(const hvpic_params* p) {
   L.rval0 = off;     off += align256(sizeof(uint32_t) * cap);
   L.rval1 = off;     off += align256(sizeof(uint32_t) * cap);
   L.rhist = off;     off += align256(sizeof(uint32_t) * kRadixBins * ntiles);
-  L.fscratch = off;  off += align256(sizeof(float) * 20 * nc);
+  L.fscratch = off;  off += align256(sizeof(float) * 25 * nc);
   L.mom_acc = off;   off += align256(sizeof(double) * 4 * nc);
   L.total = off;
   return L;
@@ -233,7 +236,29 @@ int hvpic_field_advance(hvpic_ctx* ctx, float* B, const float* n_half, const flo
   if (!B || !n_half || !J_half || !E_out) return HVPIC_EINVAL;
   if (mode != 0 && mode != 1) return HVPIC_EINVAL;
   if (mode == 0 && (!n_prev || !J_prev)) return HVPIC_EINVAL;
+  if (ctx->p.energy_eq) return HVPIC_EINVAL;
+  if (ctx->p.eta_h != 0.0)
+    return launch_field_advance_ext(ctx, B, nullptr, n_half, J_half, n_prev, J_prev, E_out, mode,
+                                    diag_out);
   return launch_field_advance(ctx, B, n_half, J_half, n_prev, J_prev, E_out, mode, diag_out);
+}
+
+int hvpic_field_advance_pe(hvpic_ctx* ctx, float* B, float* pe, const float* n_half,
+                           const float* J_half, const float* n_prev, const float* J_prev,
+                           float* E_out, int mode, double* diag_out) {
+  if (!ctx_ok(ctx)) return HVPIC_ESTATE;
+  if (!ctx->p.energy_eq) return HVPIC_EINVAL;
+  if (!B || !pe || !n_half || !J_half || !E_out) return HVPIC_EINVAL;
+  if (mode != 0 && mode != 1) return HVPIC_EINVAL;
+  if (mode == 0 && (!n_prev || !J_prev)) return HVPIC_EINVAL;
+  return launch_field_advance_ext(ctx, B, pe, n_half, J_half, n_prev, J_prev, E_out, mode,
+                                  diag_out);
+}
+
+int hvpic_eos_pressure(hvpic_ctx* ctx, const float* n, float* pe) {
+  if (!ctx_ok(ctx)) return HVPIC_ESTATE;
+  if (!n || !pe) return HVPIC_EINVAL;
+  return launch_eos_pressure(ctx, n, pe);
 }
 
 int hvpic_set_stream(hvpic_ctx* ctx, void* hip_stream) {

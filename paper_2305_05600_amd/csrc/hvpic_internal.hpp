@@ -182,6 +182,12 @@ int launch_sort_perm(hvpic_ctx* c, const hvpic_particles* in, const int32_t* cs_
 int launch_field_advance(hvpic_ctx* c, float* B, const float* n_half, const float* J_half,
                          const float* n_prev, const float* J_prev, float* E_out, int mode,
                          double* diag_out);
+// With hyper-resistivity and/or the energy equation (pe non-null): the
+// stencil-per-stage path of fields_ext.hip.
+int launch_field_advance_ext(hvpic_ctx* c, float* B, float* pe, const float* n_half,
+                             const float* J_half, const float* n_prev, const float* J_prev,
+                             float* E_out, int mode, double* diag_out);
+int launch_eos_pressure(hvpic_ctx* c, const float* n, float* pe);
 int launch_smooth(hvpic_ctx* c, float* F, int ncomp, int npasses);
 // Per-block partial slots the field diagnostics need (the larger of the
 // output kernel's blocks and the 2D subcycle's tiles); kFieldPartStride

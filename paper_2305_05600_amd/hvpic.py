@@ -25,7 +25,7 @@ EXPORTS = ("hvpic_workspace_bytes", "hvpic_init", "hvpic_finalize", "hvpic_set_s
            "hvpic_gather_push",
            "hvpic_gather_push_perm", "hvpic_sort", "hvpic_sort_perm", "hvpic_deposit",
            "hvpic_deposit_noalloc",
-           "hvpic_field_advance", "hvpic_smooth",
+           "hvpic_field_advance", "hvpic_field_advance_pe", "hvpic_eos_pressure", "hvpic_smooth",
            "hvpic_sync_status", "hvpic_path_stats", "hvpic_timing_enable", "hvpic_timing_read",
            "hvpic_strerror")
 KERNEL_GATHER_PUSH, KERNEL_DEPOSIT, KERNEL_SORT_SCATTER = 0, 1, 2
@@ -42,6 +42,7 @@ class HvpicParams(ctypes.Structure):
         ("te", ctypes.c_double), ("gamma_e", ctypes.c_double), ("n0", ctypes.c_double),
         ("n_floor", ctypes.c_double),
         ("eta", ctypes.c_double), ("eta_h", ctypes.c_double),
+        ("energy_eq", ctypes.c_int32), ("kappa0", ctypes.c_double),
         ("np_capacity", ctypes.c_int64),
     ]
 
@@ -78,6 +79,8 @@ def lib():
         L.hvpic_deposit_noalloc.argtypes = [P(HvpicParams), vp, P(HvpicParticles), ctypes.c_float,
                                             vp, vp]
         L.hvpic_field_advance.argtypes = [vp, vp, vp, vp, vp, vp, vp, i32, vp]
+        L.hvpic_field_advance_pe.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, i32, vp]
+        L.hvpic_eos_pressure.argtypes = [vp, vp, vp]
         L.hvpic_smooth.argtypes = [vp, vp, i32, i32]
         L.hvpic_sync_status.argtypes = [vp, P(ctypes.c_uint32), P(ctypes.c_int64)]
         L.hvpic_path_stats.argtypes = [vp, P(ctypes.c_int64)]
@@ -113,7 +116,8 @@ def _ptr(t, dtype=None, numel=None):
 def params_from(cfg, np_capacity: int) -> HvpicParams:
     return HvpicParams(cfg.ndim, cfg.nx, cfg.ny, cfg.nz, cfg.dx, cfg.dy, cfg.dz, cfg.dt,
                        cfg.nsub, cfg.shape, cfg.nsmooth, cfg.qs, cfg.ms, cfg.te, cfg.gamma_e,
-                       cfg.n0, cfg.n_floor, cfg.eta, cfg.eta_h, int(np_capacity))
+                       cfg.n0, cfg.n_floor, cfg.eta, cfg.eta_h, int(cfg.energy_eq),
+                       cfg.kappa0, int(np_capacity))
 
 
 class Particles:
@@ -281,6 +285,26 @@ def hvpic_field_advance(ctx, B, n_half, J_half, n_prev, J_prev, E_out, mode=0, d
                                      _ptr(E_out, torch.float32, v3),
                                      int(mode), _ptr(diag_out, torch.float64, 3)),
            "hvpic_field_advance")
+
+
+def hvpic_field_advance_pe(ctx, B, pe, n_half, J_half, n_prev, J_prev, E_out, mode=0,
+                           diag_out=None):
+    v1, v3 = _nc(ctx), _nc(ctx, 3)
+    _check(lib().hvpic_field_advance_pe(ctx, _ptr(B, torch.float32, v3),
+                                        _ptr(pe, torch.float32, v1),
+                                        _ptr(n_half, torch.float32, v1),
+                                        _ptr(J_half, torch.float32, v3),
+                                        _ptr(n_prev, torch.float32, v1),
+                                        _ptr(J_prev, torch.float32, v3),
+                                        _ptr(E_out, torch.float32, v3),
+                                        int(mode), _ptr(diag_out, torch.float64, 3)),
+           "hvpic_field_advance_pe")
+
+
+def hvpic_eos_pressure(ctx, n, pe):
+    v1 = _nc(ctx)
+    _check(lib().hvpic_eos_pressure(ctx, _ptr(n, torch.float32, v1), _ptr(pe, torch.float32, v1)),
+           "hvpic_eos_pressure")
 
 
 def hvpic_smooth(ctx, F, npasses: int):

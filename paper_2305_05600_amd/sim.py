@@ -10,7 +10,10 @@ v^{n-1/2}; B^n and E^n; the moments n^{n-1/2}, J^{n-1/2}.  One step:
   3. hvpic_deposit       n^{n+1/2}, J^{n+1/2} (only when not fused)
   4. hvpic_smooth        optional binomial passes on the moments
   5. hvpic_field_advance B^n -> B^{n+1} (subcycled), E^{n+1} from the
-                         extrapolated moments
+                         extrapolated moments (hvpic_field_advance_pe with
+                         the electron energy equation: p_e is advanced in
+                         the same substeps, starting from the EOS pressure
+                         of the first moments)
 
 Step 2 and steps 4-5 touch disjoint data (the particle store, the map and
 cell_start versus the moments, B and E), so with `overlap` (fused deposit)
@@ -148,6 +151,8 @@ class GpuSim:
         self.J_prev = torch.zeros((3, nc), **f32)
         self.n_half = torch.zeros(nc, **f32)
         self.J_half = torch.zeros((3, nc), **f32)
+        # electron pressure, state of the energy equation (Sec. II.A eq:dpdt)
+        self.pe = torch.zeros(nc, **f32) if cfg.energy_eq else None
         if cfg.nsmooth:
             self.E_s = torch.zeros((3, nc), **f32)
             self.B_s = torch.zeros((3, nc), **f32)
@@ -184,7 +189,14 @@ class GpuSim:
             H.hvpic_smooth(cf, n_half, cfg.nsmooth)
             H.hvpic_smooth(cf, J_half, cfg.nsmooth)
         diag = self.field_diag if self.diagnostics else None
-        if mode == 1:
+        if cfg.energy_eq:
+            if mode == 1:  # the start: the pressure of the EOS of the first moments
+                H.hvpic_eos_pressure(cf, n_half, self.pe)
+            H.hvpic_field_advance_pe(cf, self.B, self.pe, n_half, J_half,
+                                     None if mode == 1 else self.n_prev,
+                                     None if mode == 1 else self.J_prev, self.E, mode=mode,
+                                     diag_out=diag)
+        elif mode == 1:
             H.hvpic_field_advance(cf, self.B, n_half, J_half, None, None, self.E, mode=1,
                                   diag_out=diag)
         else:

@@ -102,8 +102,7 @@ def drop_straddlers(cfg, parts: dict, B, steps: int = 1, band=1e-5, fused=False)
             if cfg.nsmooth:
                 n_half = O.smooth(cfg, n_half, cfg.nsmooth)
                 J_half = O.smooth(cfg, J_half, cfg.nsmooth)
-            sim.B, sim.E, _, _ = O.field_advance(cfg, sim.B, n_half, J_half, sim.n_prev,
-                                                 sim.J_prev, mode=0)
+            sim._advance(n_half, J_half, sim.n_prev, sim.J_prev, mode=0)
             sim.n_prev, sim.J_prev = n_half, J_half
         if not bad.any():
             print(f"straddlers removed: {int((~keep).sum())} of {keep.size} "

@@ -38,8 +38,14 @@ def test_exports_every_declared_symbol(H):
 
 
 def test_struct_layout_matches_header(H):
-    # hvpic_params: 4 int32, 4 double, 3 int32 (+pad), 8 double, int64
-    assert ctypes.sizeof(H.HvpicParams) == 16 + 32 + 16 + 64 + 8
+    # hvpic_params: 4 int32, 4 double, 3 int32 (+pad), 8 double, int32 (+pad),
+    # double, int64
+    assert ctypes.sizeof(H.HvpicParams) == 16 + 32 + 16 + 64 + 16 + 8
+    text = (ROOT / "include" / "hvpic.h").read_text()
+    body = text[text.index("typedef struct {"):text.index("} hvpic_params;")]
+    fields = re.findall(r"(?:int32_t|int64_t|double)\s+([\w, ]+);", body)
+    names = [n.strip() for f in fields for n in f.split(",")]
+    assert names == [f[0] for f in H.HvpicParams._fields_]
     assert ctypes.sizeof(H.HvpicParticles) == 8 * 9
 
 
@@ -49,13 +55,20 @@ def test_workspace_bytes_and_validation(H):
     nb = H.hvpic_workspace_bytes(p)
     assert nb > 65536 * 16
     bad = [dict(ndim=4), dict(nz=2), dict(dx=0.0), dict(dt=float("nan")), dict(shape=7),
-           dict(n_floor=0.0), dict(eta_h=1e-3), dict(np_capacity=-1), dict(nsub=-1)]
+           dict(n_floor=0.0), dict(eta_h=-1e-3), dict(eta_h=float("nan")),
+           dict(energy_eq=2), dict(energy_eq=1, gamma_e=1.0), dict(energy_eq=1, gamma_e=0.5),
+           dict(kappa0=-0.1), dict(kappa0=float("inf")), dict(np_capacity=-1), dict(nsub=-1)]
     for b in bad:
         q = H.params_from(cfg, 65536)
         for k, v in b.items():
             setattr(q, k, v)
         n = ctypes.c_size_t(0)
         assert H.lib().hvpic_workspace_bytes(ctypes.byref(q), ctypes.byref(n)) == H.HVPIC_EINVAL, b
+    for good in (dict(eta_h=1e-3), dict(energy_eq=1, gamma_e=5.0 / 3.0, kappa0=0.1)):
+        q = H.params_from(cfg, 65536)
+        for k, v in good.items():
+            setattr(q, k, v)
+        assert H.hvpic_workspace_bytes(q) == nb, good
 
 
 def test_init_rejects_bad_arguments_without_device_work(H):
@@ -72,6 +85,9 @@ def test_init_rejects_bad_arguments_without_device_work(H):
     assert L.hvpic_gather_push_perm(None, None, None, None, None, None, None, None, None,
                                     None) == H.HVPIC_ESTATE
     assert L.hvpic_finalize(None) == H.HVPIC_ESTATE
+    assert L.hvpic_field_advance_pe(None, None, None, None, None, None, None, None, 0,
+                                    None) == H.HVPIC_ESTATE
+    assert L.hvpic_eos_pressure(None, None, None) == H.HVPIC_ESTATE
     assert H.hvpic_strerror(H.HVPIC_EINVAL) == "invalid argument"
     assert L.hvpic_set_stream(None, None) == H.HVPIC_ESTATE
     assert L.hvpic_timing_enable(None, 4, 1) == H.HVPIC_ESTATE
