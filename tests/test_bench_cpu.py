@@ -20,14 +20,15 @@ def test_more_than_one_gpu_is_refused():
 
 
 def test_algorithmic_bytes_follow_the_store_layout():
-    # 2D SoA store: cell int32, two offsets, three velocities, weight (FP32)
-    store = 4 + 2 * 4 + 3 * 4 + 4
-    # what the method moves: read the whole store, write all but the weight
-    assert bench.BYTES_PER_PARTICLE_2D == store + (store - 4)
+    for ndim in (2, 3):
+        # SoA store: cell int32, ndim offsets, three velocities, weight (FP32)
+        store = 4 + ndim * 4 + 3 * 4 + 4
+        # what the method moves: read the whole store, write all but the weight
+        assert bench.BYTES_PER_PARTICLE[ndim] == store + (store - 4)
     # what the gather-map sequence adds: the map entry read, the weight written
-    assert bench.EXTRA_BYTES_PER_PARTICLE_2D == {"in place": 0, "gather map": 4 + 4}
+    assert bench.EXTRA_BYTES_PER_PARTICLE == {"in place": 0, "gather map": 4 + 4}
     # per cell: E and B read (6 floats), n and J written (4 floats)
-    assert bench.BYTES_PER_CELL_2D == 6 * 4 + 4 * 4
+    assert bench.BYTES_PER_CELL == 6 * 4 + 4 * 4
 
 
 def test_at_least_ten_launches_are_timed():
