@@ -322,6 +322,101 @@ int hvpic_timing_read(hvpic_ctx* ctx, int kernel, double* total_ms, int64_t* lau
 /* Static description of an error code. */
 const char* hvpic_strerror(int code);
 
+/* ------------------------------------------------------------ ensembles --
+   Many independent 2D periodic runs stepped together (the batching form of
+   the step).  Each run is the step of the calls above in the gather-map
+   sequence: hvpic_gather_push_perm with the fused deposit and the move
+   counts, hvpic_sort_perm, hvpic_field_advance (mode 0), with its own
+   context, grid, particles and parameters.  Every phase of the step (push,
+   moment output, the sort's three passes, each subcycle tile launch, the
+   field diagnostics) is one persistent launch over the work items (run,
+   chunk or tile) of all runs, so small runs share the GPU instead of each
+   paying its launches.  The step's results per run are those of the plain
+   calls (bit for bit but for the accumulation order of the atomics).
+
+   A run's state rotates between two sets of buffers every step, as the plain
+   sequence swaps them: at an even step count (store[0], cell_start[0],
+   n[0], J[0]) hold the current sorted store (read through perm), its
+   cell_start and the moments of level n-1/2; store[1], cell_start[1], n[1],
+   J[1] are written; at an odd count the roles swap.  E, B and perm are
+   updated in place.  Set up the even state with the plain calls (sort,
+   deposit at x^n, field advance mode 1, an identity perm), or take the state
+   a plain gather-map step left. */
+typedef struct {
+  hvpic_ctx* ctx;            /* the run's context: parameters and workspace   */
+  hvpic_particles store[2];  /* two stores of the same n particles            */
+  int32_t* perm;             /* [n] gather map over the current store         */
+  int32_t* cell_start[2];    /* [ncell+1] each                                */
+  float* E;                  /* [3][ncell] E^n                                */
+  float* B;                  /* [3][ncell] B^n                                */
+  float* n[2];               /* [ncell] each: n^{n-1/2} and the next level    */
+  float* J[2];               /* [3][ncell] each                               */
+  double* push_diag;         /* [4] {K, P} of the last step, or NULL          */
+  double* field_diag;        /* [3] {W_B, W_dB, W_e}, or NULL                 */
+} hvpic_run;
+
+/* The choices the autotuner makes.  push_chunk[c]: particles per push block
+   for runs of class c of particles per cell (c = 0: below 64, 1: below 128,
+   2: more), 0/1/2 = 1024/2048/3072; a chunk must span few enough cells for
+   the block's LDS windows.  field_tile[c]: subcycle tile for runs of grid
+   class c (0: below 128^2 cells, 1: larger), 0 = 32x8, 1 = 16x16, 2 = 64x4.
+   blocks_per_cu[k]: persistent workgroups per CU of the push, the moment
+   output, the sort passes and the tile launches (1..64). */
+typedef struct {
+  int32_t push_chunk[3];
+  int32_t field_tile[2];
+  int32_t blocks_per_cu[4];
+} hvpic_tuning;
+
+typedef struct hvpic_ensemble hvpic_ensemble;
+
+/* Device workspace the ensemble needs (tables of per-run arguments for both
+   parities and the work-item lists).  HVPIC_EINVAL unless every run is 2D,
+   periodic as all runs here are, without smoothing, hyper-resistivity or the
+   energy equation, with 3 <= nsub <= 128 (the same for all runs), the same particle
+   shape, 1 <= n < 2^30 particles in both stores, at most 512^2 cells, and all
+   pointers set (the diagnostics may be NULL). */
+int hvpic_ensemble_workspace_bytes(const hvpic_run* runs, int nruns, size_t* bytes);
+
+/* The plain path's choices (3072-particle push blocks, 32x8 tiles). */
+int hvpic_tuning_default(hvpic_tuning* t);
+
+/* Creates an ensemble of nruns runs (the array is copied; the buffers and
+   contexts are the caller's and must outlive it) on `hip_stream` with its
+   tables in `workspace` (device memory of hvpic_ensemble_workspace_bytes,
+   256-byte aligned).  tuning NULL: the defaults.  Uploads the tables with
+   synchronous copies and enqueues the clearing of the runs' move counts. */
+int hvpic_ensemble_init(const hvpic_run* runs, int nruns, void* hip_stream, void* workspace,
+                        const hvpic_tuning* tuning, hvpic_ensemble** out);
+int hvpic_ensemble_finalize(hvpic_ensemble* e);
+
+/* One step of every run, enqueued on the ensemble's stream (by replaying
+   the captured graph of the step's parity when capture is on). */
+int hvpic_ensemble_step(hvpic_ensemble* e);
+
+/* Steps taken so far (its parity says which buffers hold the state). */
+int hvpic_ensemble_steps(const hvpic_ensemble* e, int64_t* steps);
+
+/* enable = 1: captures the two parities of the step into HIP graphs (the
+   ensemble's stream must not be the null stream), which later steps
+   replay; 0: steps launch their kernels directly. */
+int hvpic_ensemble_capture(hvpic_ensemble* e, int enable);
+
+int hvpic_ensemble_get_tuning(const hvpic_ensemble* e, hvpic_tuning* t);
+/* Waits for the ensemble's stream, then rebuilds the tables (and the graphs,
+   if captured) for the new choices. */
+int hvpic_ensemble_set_tuning(hvpic_ensemble* e, const hvpic_tuning* t);
+
+/* The autotuner: tries the push chunk per class of particles per cell, the
+   persistent grids and the tile shape per grid class, one knob at a time,
+   keeping what takes least time; each candidate is timed with HIP events
+   over `reps` REAL steps of the ensemble (all choices compute the same
+   step, so the tuning steps advance the runs: hvpic_ensemble_steps counts
+   them).  Leaves the best choices in force, returns them in *best (may be
+   NULL) and the timed phases {push, moments + sort, fields} in ms[3] (may be
+   NULL).  Waits for the stream. */
+int hvpic_ensemble_autotune(hvpic_ensemble* e, int reps, hvpic_tuning* best, double* ms);
+
 #ifdef __cplusplus
 }
 #endif

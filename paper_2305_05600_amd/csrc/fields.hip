@@ -21,6 +21,8 @@
 // writes E from the extrapolated moments, the final B and the diagnostics.
 // The grids fit in the MI355X L2/MALL during the subcycle, so the substeps are
 // latency-bound: fewer, larger launches are what shortens them.
+#include <string.h>
+
 #include "fields_common.hpp"
 
 namespace hvpic {
@@ -109,20 +111,20 @@ constexpr int kTX = 32, kTY = 8;
 constexpr int kSubBlock = 512;
 
 // One LDS plane: the tile with a halo of HALO cells, row-major.
-template <int HALO>
+template <int TX, int TY, int HALO>
 struct Plane {
-  static constexpr int W = kTX + 2 * HALO, H = kTY + 2 * HALO, N = W * H;
+  static constexpr int W = TX + 2 * HALO, H = TY + 2 * HALO, N = W * H;
   __device__ static int at(int lx, int ly) { return (ly + HALO) * W + lx + HALO; }
 };
 
-template <int K, bool FINAL>
+template <int TX, int TY, int K, bool FINAL>
 struct SubLds {
   // the final launch keeps its last substep's B on a 1-cell halo (for curl B)
   static constexpr int HB = 4 * K + (FINAL ? 1 : 0);
-  using PB = Plane<HB>;      // B hi (and the pressure while the frozen terms are formed)
-  using PA = Plane<HB - 1>;  // six frozen-term planes, then E (Ea, later Eb)
-  using PS = Plane<HB - 2>;  // B*
-  using PL = Plane<HB - 4>;  // lo over the output region of the first substep
+  using PB = Plane<TX, TY, HB>;      // B hi (and the pressure while the frozen terms are formed)
+  using PA = Plane<TX, TY, HB - 1>;  // six frozen-term planes, then E (Ea, later Eb)
+  using PS = Plane<TX, TY, HB - 2>;  // B*
+  using PL = Plane<TX, TY, HB - 4>;  // lo over the output region of the first substep
   static constexpr int B0 = 0, A0 = 3 * PB::N, E0 = A0 + 6 * PA::N, S0 = E0 + 3 * PA::N,
                        L0 = S0 + 3 * PS::N, TOTAL = L0 + 3 * PL::N;
   static_assert(3 * PA::N + 3 * PS::N >= PB::N, "pressure plane overlays E and B*");
@@ -161,12 +163,12 @@ struct SubFinal {
   Status* st;
 };
 
-template <int K, bool HAS_LIN, bool FINAL>
-__global__ __launch_bounds__(kSubBlock) void k_field_sub2d(
+template <int TX, int TY, int K, bool HAS_LIN, bool FINAL>
+__device__ __forceinline__ void field_sub2d_body(
     const float* __restrict__ Bin, const float* __restrict__ Lin, float* __restrict__ Bout,
     float* __restrict__ Lout, const float* __restrict__ nm, const float* __restrict__ Jm, float h,
-    float eta, FGeo g, Eos eos, SubFinal F) {
-  using L = SubLds<K, FINAL>;
+    float eta, const FGeo& g, const Eos& eos, const SubFinal& F, int bx, int by, int slot) {
+  using L = SubLds<TX, TY, K, FINAL>;
   using PB = typename L::PB;
   using PA = typename L::PA;
   using PS = typename L::PS;
@@ -180,7 +182,7 @@ __global__ __launch_bounds__(kSubBlock) void k_field_sub2d(
   float* sL = sm + L::L0;
   float* sP = sE;  // pressure, only until the frozen terms are formed
   const int nc = g.ncell;
-  const int tx0 = blockIdx.x * kTX, ty0 = blockIdx.y * kTY;
+  const int tx0 = bx * TX, ty0 = by * TY;
   // periodic cell of tile-relative (lx, ly), for any halo width and grid size
   auto gidx = [&](int lx, int ly) {
     int x = tx0 + lx, y = ty0 + ly;
@@ -196,13 +198,13 @@ __global__ __launch_bounds__(kSubBlock) void k_field_sub2d(
   constexpr int IA = (PA::N + kSubBlock - 1) / kSubBlock;
   constexpr int IL = (PL::N + kSubBlock - 1) / kSubBlock;
   float vb[IB][4], va[IA][4], vl[IL][3];
-  // final launch: each of the first kTX*kTY threads owns one tile cell and
+  // final launch: each of the first TX*TY threads owns one tile cell and
   // loads its extrapolation inputs here, with the others (n at the cell and
   // its four neighbours, J at the cell)
   constexpr int NF = FINAL ? 16 : 1;
   float vf[NF];
-  const int fx = (int)threadIdx.x % kTX, fy = (int)threadIdx.x / kTX;
-  const bool fown = FINAL && (int)threadIdx.x < kTX * kTY;
+  const int fx = (int)threadIdx.x % TX, fy = (int)threadIdx.x / TX;
+  const bool fown = FINAL && (int)threadIdx.x < TX * TY;
   if (FINAL) {
     const int cf[5] = {gidx(fx, fy), gidx(fx + 1, fy), gidx(fx - 1, fy), gidx(fx, fy + 1),
                        gidx(fx, fy - 1)};
@@ -300,7 +302,7 @@ __global__ __launch_bounds__(kSubBlock) void k_field_sub2d(
     const int hin = 4 * (K - s) + (FINAL ? 1 : 0);  // halo of this substep's input B
     // Ea on halo hin-1
     {
-      const int r = hin - 1, W = kTX + 2 * r, N = W * (kTY + 2 * r);
+      const int r = hin - 1, W = TX + 2 * r, N = W * (TY + 2 * r);
       for (int t = threadIdx.x; t < N; t += kSubBlock) {
         const int ly = t / W - r, lx = t % W - r;
         const int b = PB::at(lx, ly), a = PA::at(lx, ly);
@@ -318,7 +320,7 @@ __global__ __launch_bounds__(kSubBlock) void k_field_sub2d(
     __syncthreads();
     // B* = B - (h/2) curl Ea on halo hin-2
     {
-      const int r = hin - 2, W = kTX + 2 * r, N = W * (kTY + 2 * r);
+      const int r = hin - 2, W = TX + 2 * r, N = W * (TY + 2 * r);
       for (int t = threadIdx.x; t < N; t += kSubBlock) {
         const int ly = t / W - r, lx = t % W - r;
         const int e = PA::at(lx, ly), b = PB::at(lx, ly), q = PS::at(lx, ly);
@@ -334,7 +336,7 @@ __global__ __launch_bounds__(kSubBlock) void k_field_sub2d(
     __syncthreads();
     // Eb on halo hin-3 (into the E planes: Ea was consumed before the barrier)
     {
-      const int r = hin - 3, W = kTX + 2 * r, N = W * (kTY + 2 * r);
+      const int r = hin - 3, W = TX + 2 * r, N = W * (TY + 2 * r);
       for (int t = threadIdx.x; t < N; t += kSubBlock) {
         const int ly = t / W - r, lx = t % W - r;
         const int q = PS::at(lx, ly), a = PA::at(lx, ly);
@@ -353,7 +355,7 @@ __global__ __launch_bounds__(kSubBlock) void k_field_sub2d(
     // B_new = B - h curl Eb on halo hin-4, as the compensated sum
     // (hi, lo) - h curl Eb: the increment is tiny next to B
     {
-      const int r = hin - 4, W = kTX + 2 * r, N = W * (kTY + 2 * r);
+      const int r = hin - 4, W = TX + 2 * r, N = W * (TY + 2 * r);
       for (int t = threadIdx.x; t < N; t += kSubBlock) {
         const int ly = t / W - r, lx = t % W - r;
         const int e = PA::at(lx, ly), b = PB::at(lx, ly), l = PL::at(lx, ly);
@@ -443,8 +445,18 @@ __global__ __launch_bounds__(kSubBlock) void k_field_sub2d(
       atomicAdd(&F.st->floor_hits, (unsigned long long)__builtin_popcountll(m));
     }
     if (F.part)
-      tile_partial(v, F.part + kFieldPartStride * ((int64_t)blockIdx.y * gridDim.x + blockIdx.x));
+      tile_partial(v, F.part + kFieldPartStride * (int64_t)slot);
   }
+}
+
+template <int K, bool HAS_LIN, bool FINAL>
+__global__ __launch_bounds__(kSubBlock) void k_field_sub2d(
+    const float* __restrict__ Bin, const float* __restrict__ Lin, float* __restrict__ Bout,
+    float* __restrict__ Lout, const float* __restrict__ nm, const float* __restrict__ Jm, float h,
+    float eta, FGeo g, Eos eos, SubFinal F) {
+  field_sub2d_body<kTX, kTY, K, HAS_LIN, FINAL>(Bin, Lin, Bout, Lout, nm, Jm, h, eta, g, eos, F,
+                                                blockIdx.x, blockIdx.y,
+                                                blockIdx.y * gridDim.x + blockIdx.x);
 }
 
 // E at the end of the step from the moments n_eff = ca*na + cb*nb,
@@ -609,10 +621,10 @@ int field_impl(hvpic_ctx* c, float* B, const float* n_half, const float* J_half,
       // two substeps per launch (one for an odd last one), the frozen terms
       // formed in each tile; the caller's B is only read (first launch)
       const dim3 tiles((unsigned)ceil_div(c->p.nx, kTX), (unsigned)ceil_div(c->p.ny, kTY));
-      const size_t lds2 = sizeof(float) * SubLds<2, false>::TOTAL,
-                   lds1 = sizeof(float) * SubLds<1, false>::TOTAL,
-                   lds2f = sizeof(float) * SubLds<2, true>::TOTAL,
-                   lds1f = sizeof(float) * SubLds<1, true>::TOTAL;
+      const size_t lds2 = sizeof(float) * SubLds<kTX, kTY, 2, false>::TOTAL,
+                   lds1 = sizeof(float) * SubLds<kTX, kTY, 1, false>::TOTAL,
+                   lds2f = sizeof(float) * SubLds<kTX, kTY, 2, true>::TOTAL,
+                   lds1f = sizeof(float) * SubLds<kTX, kTY, 1, true>::TOTAL;
       const float* sh = B;
       const float* sl = nullptr;
       float* dh = Xh;
@@ -708,11 +720,171 @@ int field_impl(hvpic_ctx* c, float* B, const float* n_half, const float* J_half,
 
 }  // namespace
 
+// 2D tile shapes of the subcycle kernel: the plain path uses shape 0; the
+// ensemble's tuner picks one per run.
+constexpr int kTileW[kTileShapes] = {32, 16, 64};
+constexpr int kTileH[kTileShapes] = {8, 16, 4};
+static_assert(kTileW[0] == kTX && kTileH[0] == kTY, "shape 0 is the plain path's tile");
+
 int64_t field_part_slots(const hvpic_params* p) {
   const int64_t nc = (int64_t)p->nx * p->ny * p->nz;
-  const int64_t blocks = ceil_div(nc, kBlock);
-  const int64_t tiles = p->ndim == 2 ? ceil_div(p->nx, kTX) * ceil_div(p->ny, kTY) : 0;
-  return std::max(blocks, tiles);
+  int64_t slots = ceil_div(nc, kBlock);
+  if (p->ndim == 2)
+    for (int t = 0; t < kTileShapes; ++t)
+      slots = std::max(slots, ceil_div(p->nx, kTileW[t]) * ceil_div(p->ny, kTileH[t]));
+  return slots;
+}
+
+// ------------------------------------------------------------ ensembles --
+// The 2D subcycle (tile launches of one or two substeps, the last also
+// writing E, the final B and the diagnostic partials) and the diagnostics'
+// final sums, batched over the runs of an ensemble: per launch one record
+// per run, one persistent launch over the (run, tile) items.
+
+namespace {
+
+struct FieldArgs {
+  const float* Bin;
+  const float* Lin;
+  float* Bout;
+  float* Lout;
+  const float* nm;
+  const float* Jm;
+  float h, eta;
+  FGeo g;
+  Eos eos;
+  SubFinal F;
+  int ntx;  // tiles along x
+};
+
+template <int TX, int TY, int K, bool HAS_LIN, bool FINAL>
+__global__ __launch_bounds__(kSubBlock) void k_field_sub2d_batch(const FieldArgs* __restrict__ tab,
+                                                                 const Item* __restrict__ items,
+                                                                 int nitems) {
+  for_items(nitems, [&](int it) {
+    const Item item = items[it];
+    const FieldArgs A = tab[item.run];
+    field_sub2d_body<TX, TY, K, HAS_LIN, FINAL>(A.Bin, A.Lin, A.Bout, A.Lout, A.nm, A.Jm, A.h,
+                                                A.eta, A.g, A.eos, A.F, item.idx % A.ntx,
+                                                item.idx / A.ntx, item.idx);
+    __syncthreads();
+  });
+}
+
+__global__ __launch_bounds__(1024) void k_field_diag_batch(const DiagArgs* __restrict__ tab,
+                                                           int nruns) {
+  for (int r = blockIdx.x; r < nruns; r += gridDim.x) {
+    const DiagArgs D = tab[r];
+    if (D.out) field_diag_body(D);  // uniform per block
+    __syncthreads();
+  }
+}
+
+template <int TX, int TY>
+int field_batch_shape(hipStream_t s, int K, bool has_lin, bool fin, const FieldArgs* t,
+                      const Item* items, int nitems, int grid) {
+  auto go = [&](auto kern, size_t lds) {
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kSubBlock), lds, s, t, items, nitems);
+  };
+  constexpr size_t f = sizeof(float);
+  if (fin && K == 2)
+    go(k_field_sub2d_batch<TX, TY, 2, true, true>, f * SubLds<TX, TY, 2, true>::TOTAL);
+  else if (fin)
+    go(k_field_sub2d_batch<TX, TY, 1, true, true>, f * SubLds<TX, TY, 1, true>::TOTAL);
+  else if (K == 2 && has_lin)
+    go(k_field_sub2d_batch<TX, TY, 2, true, false>, f * SubLds<TX, TY, 2, false>::TOTAL);
+  else if (K == 2)
+    go(k_field_sub2d_batch<TX, TY, 2, false, false>, f * SubLds<TX, TY, 2, false>::TOTAL);
+  else if (has_lin)
+    go(k_field_sub2d_batch<TX, TY, 1, true, false>, f * SubLds<TX, TY, 1, false>::TOTAL);
+  else
+    go(k_field_sub2d_batch<TX, TY, 1, false, false>, f * SubLds<TX, TY, 1, false>::TOTAL);
+  return hipGetLastError() == hipSuccess ? HVPIC_OK : HVPIC_EHIP;
+}
+
+}  // namespace
+
+int ens_field_tiles(const hvpic_ctx* c, int shape) {
+  return (int)(ceil_div(c->p.nx, kTileW[shape]) * ceil_div(c->p.ny, kTileH[shape]));
+}
+
+int ens_field_launches(const hvpic_ctx* c, int* K, int* has_lin, int* fin) {
+  int n = 0;
+  for (int m = 0; m < c->p.nsub; ++n) {
+    const bool two = c->p.nsub - m >= 2;
+    if (K) K[n] = two ? 2 : 1;
+    if (has_lin) has_lin[n] = m > 0;
+    m += two ? 2 : 1;
+    if (fin) fin[n] = m >= c->p.nsub;
+  }
+  return n;
+}
+
+size_t ens_field_record(hvpic_ctx* c, float* B, const float* n_half, const float* J_half,
+                        const float* n_prev, const float* J_prev, float* E_out, bool diag,
+                        int launch, int shape, void* dst) {
+  if (dst) {
+    const int nc = c->ncell;
+    // the ping-pong of the (hi, lo) pairs as the plain path runs it: launch
+    // 0 reads the caller's B, launch m writes X for even m and Y for odd m
+    float* Xh = c->fscratch + 7ll * nc;
+    float* Xl = c->fscratch + 10ll * nc;
+    float* Yh = c->fscratch + 13ll * nc;
+    float* Yl = c->fscratch + 16ll * nc;
+    FieldArgs A{};
+    A.Bin = launch == 0 ? B : (launch % 2 == 1 ? Xh : Yh);
+    A.Lin = launch == 0 ? nullptr : (launch % 2 == 1 ? Xl : Yl);
+    A.Bout = launch % 2 == 0 ? Xh : Yh;
+    A.Lout = launch % 2 == 0 ? Xl : Yl;
+    A.nm = n_half;
+    A.Jm = J_half;
+    A.h = (float)(c->p.dt / c->p.nsub);
+    A.eta = (float)c->p.eta;
+    A.g = fgeo(c);
+    A.eos = make_eos(c);
+    int fin[64];
+    const int nl = ens_field_launches(c, nullptr, nullptr, fin);
+    if (launch == nl - 1) {
+      A.F.np = n_prev;
+      A.F.Jp = J_prev;
+      A.F.E = E_out;
+      A.F.Bfin = B;
+      A.F.part = diag ? c->field_part : nullptr;
+      A.F.st = c->status;
+    }
+    A.ntx = (int)ceil_div(c->p.nx, kTileW[shape]);
+    memcpy(dst, &A, sizeof(A));
+  }
+  return sizeof(FieldArgs);
+}
+
+size_t ens_field_diag_record(hvpic_ctx* c, double* out, int shape, void* dst) {
+  if (dst) {
+    const Eos eos = make_eos(c);
+    const double V = c->p.dx * c->p.dy * c->p.dz;
+    const double we_scale =
+        eos.iso ? V * c->p.te : V * c->p.n0 * c->p.te / (c->p.gamma_e - 1.0);
+    const DiagArgs D{c->field_part, ens_field_tiles(c, shape), out, 0.5 * V,
+                     1.0 / (double)c->ncell, we_scale};
+    memcpy(dst, &D, sizeof(D));
+  }
+  return sizeof(DiagArgs);
+}
+
+int ens_launch_field(hipStream_t s, int shape, int K, int has_lin, int fin, const void* tab,
+                     const Item* items, int nitems, int grid) {
+  if (nitems == 0) return HVPIC_OK;
+  const FieldArgs* t = static_cast<const FieldArgs*>(tab);
+  if (shape == 1) return field_batch_shape<16, 16>(s, K, has_lin, fin, t, items, nitems, grid);
+  if (shape == 2) return field_batch_shape<64, 4>(s, K, has_lin, fin, t, items, nitems, grid);
+  return field_batch_shape<32, 8>(s, K, has_lin, fin, t, items, nitems, grid);
+}
+
+int ens_launch_field_diag(hipStream_t s, const void* tab, int nruns) {
+  if (nruns == 0) return HVPIC_OK;
+  hipLaunchKernelGGL(k_field_diag_batch, dim3((unsigned)std::min(nruns, 1024)), dim3(1024), 0, s,
+                     static_cast<const DiagArgs*>(tab), nruns);
+  return hipGetLastError() == hipSuccess ? HVPIC_OK : HVPIC_EHIP;
 }
 
 int launch_field_advance(hvpic_ctx* c, float* B, const float* n_half, const float* J_half,

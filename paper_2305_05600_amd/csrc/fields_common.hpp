@@ -158,17 +158,28 @@ constexpr int kDiagNV = 5;
 // we_scale sum e(n)} with we_scale = V te (gamma = 1) or V n0 te / (gamma - 1).
 // A kernel of its own: a last-block reduction inside k_field_final would need
 // an agent-scope release per block, which writes back the L2.
+struct DiagArgs {
+  const double* part;
+  int nblocks;
+  double* out;
+  double half_vol, inv_ncell, we_scale;
+};
+
+__device__ __forceinline__ void field_diag_body(const DiagArgs& D) {
+  double r[kDiagNV];
+  sum_partials<kDiagNV, kFieldPartStride>(D.part, D.nblocks, r);
+  if (threadIdx.x == 0) {
+    const double m2 = r[1] * r[1] + r[2] * r[2] + r[3] * r[3];
+    D.out[0] = D.half_vol * r[0];
+    D.out[1] = D.half_vol * (r[0] - m2 * D.inv_ncell);
+    D.out[2] = D.we_scale * r[4];
+  }
+}
+
 __global__ __launch_bounds__(1024) void k_field_diag_final(const double* part, int nblocks,
                                                              double* out, double half_vol,
                                                              double inv_ncell, double we_scale) {
-  double r[kDiagNV];
-  sum_partials<kDiagNV, kFieldPartStride>(part, nblocks, r);
-  if (threadIdx.x == 0) {
-    const double m2 = r[1] * r[1] + r[2] * r[2] + r[3] * r[3];
-    out[0] = half_vol * r[0];
-    out[1] = half_vol * (r[0] - m2 * inv_ncell);
-    out[2] = we_scale * r[4];
-  }
+  field_diag_body(DiagArgs{part, nblocks, out, half_vol, inv_ncell, we_scale});
 }
 
 __global__ void k_copy(const float* __restrict__ in, float* __restrict__ out, int64_t n) {

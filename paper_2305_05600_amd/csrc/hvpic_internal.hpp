@@ -50,10 +50,30 @@ __device__ __forceinline__ void count_path(Status* st, bool window) {
   if (threadIdx.x == 0) atomicAdd(window ? &st->win_blocks : &st->glob_blocks, 1ull);
 }
 
+// One work item of a batched launch over the runs of an ensemble: block idx
+// of the nb blocks that run `run`'s share of the launch would take on its own.
+struct Item {
+  int32_t run, idx, nb;
+};
+
+// Calls f(it) for the items this block takes of a persistent launch over
+// nitems items (gridDim.x a multiple of 8).  The GPU hands blocks out
+// round-robin over its 8 XCDs, each with its own L2, so XCD x takes the
+// contiguous x-th eighth of the item list (neighbouring chunks of one run
+// share an L2) and its blocks stride through it.
+template <class F>
+__device__ __forceinline__ void for_items(int nitems, F f) {
+  const int x = blockIdx.x & 7, l = blockIdx.x >> 3, g8 = gridDim.x >> 3;
+  const int per = nitems >> 3, rem = nitems & 7;
+  const int start = x * per + (x < rem ? x : rem), len = per + (x < rem ? 1 : 0);
+  for (int j = l; j < len; j += g8) f(start + j);
+}
+
 // FP64 partial sums of NV values over a block, written by thread 0 to
-// part[blockIdx.x * STRIDE + k].  Fixed reduction order (deterministic).
+// part[slot * STRIDE + k] (slot = blockIdx.x by default).  Fixed reduction
+// order (deterministic).
 template <int NV, int STRIDE = 4>
-__device__ void block_partial(double* v, double* part) {
+__device__ void block_partial(double* v, double* part, int64_t slot) {
   __shared__ double s_red[16][NV];
 #pragma unroll
   for (int k = 0; k < NV; ++k)
@@ -66,8 +86,13 @@ __device__ void block_partial(double* v, double* part) {
     for (int k = 0; k < NV; ++k) {
       double t = 0.0;
       for (int w = 0; w < nw; ++w) t += s_red[w][k];
-      part[(int64_t)blockIdx.x * STRIDE + k] = t;
+      part[slot * STRIDE + k] = t;
     }
+}
+
+template <int NV, int STRIDE = 4>
+__device__ void block_partial(double* v, double* part) {
+  block_partial<NV, STRIDE>(v, part, blockIdx.x);
 }
 
 // Sum of nblocks partials (as written by block_partial) by one block, in a
@@ -189,6 +214,41 @@ int launch_field_advance_ext(hvpic_ctx* c, float* B, float* pe, const float* n_h
                              float* E_out, int mode, double* diag_out);
 int launch_eos_pressure(hvpic_ctx* c, const float* n, float* pe);
 int launch_smooth(hvpic_ctx* c, float* F, int ncomp, int npasses);
+
+// Ensemble support: per-run argument records of the batched kernels, built on
+// the host into `dst` (returning the record size; dst may be null to ask
+// it), and the batched launches over work items (tables and items in device
+// memory, grid a multiple of 8).  2D, gather-map sequence, fused deposit.
+size_t ens_push_record(hvpic_ctx* c, const hvpic_particles* in, const int32_t* perm,
+                       hvpic_particles* out, const int32_t* cs, const float* E, const float* B,
+                       bool diag, void* dst);
+size_t ens_moments_record(hvpic_ctx* c, float* n, float* J, int nparts, double* diag_out,
+                          void* dst);
+int ens_moment_blocks(const hvpic_ctx* c);
+int ens_launch_push(hipStream_t s, int shape, int ppt, const void* tab, const Item* items,
+                    int nitems, int grid);
+int ens_launch_moments(hipStream_t s, const void* tab, const Item* items, int nitems, int grid);
+size_t ens_sort_record(hvpic_ctx* c, const hvpic_particles* in, const int32_t* cs_prev,
+                       int32_t* perm, int32_t* cs, void* dst);
+int ens_sort_tiles(const hvpic_ctx* c);          // items of passes 0 and 1
+int ens_sort_scatter_blocks(const hvpic_ctx* c); // items of pass 2
+bool ens_sort_fits(const hvpic_ctx* c);          // the batched sort's tile size suits the grid
+int ens_launch_sort(hipStream_t s, int pass, const void* tab, const Item* items, int nitems,
+                    int grid);
+constexpr int kTileShapes = 3;  // 2D subcycle tiles: 0 = 32x8, 1 = 16x16, 2 = 64x4
+int ens_field_tiles(const hvpic_ctx* c, int shape);
+// tile launches of a field advance; per launch its substeps K, whether it
+// reads a lo part and whether it is the final one (arrays of >= 64 or null)
+int ens_field_launches(const hvpic_ctx* c, int* K, int* has_lin, int* fin);
+size_t ens_field_record(hvpic_ctx* c, float* B, const float* n_half, const float* J_half,
+                        const float* n_prev, const float* J_prev, float* E_out, bool diag,
+                        int launch, int shape, void* dst);
+size_t ens_field_diag_record(hvpic_ctx* c, double* out, int shape, void* dst);
+int ens_launch_field(hipStream_t s, int shape, int K, int has_lin, int fin, const void* tab,
+                     const Item* items, int nitems, int grid);
+int ens_launch_field_diag(hipStream_t s, const void* tab, int nruns);
+// particles per chunk of the 2D push for ppt particles per lane
+constexpr int ens_chunk(int ppt) { return 256 * ppt; }
 // Per-block partial slots the field diagnostics need (the larger of the
 // output kernel's blocks and the 2D subcycle's tiles); kFieldPartStride
 // doubles each.

@@ -907,17 +907,17 @@ __device__ __forceinline__ void moves_window_init(const int32_t* __restrict__ cs
 // Each block checks its share of cell_start (a monotone partition of [0, n]);
 // the scatter relies on it.
 __device__ __forceinline__ void check_cell_start(const int32_t* __restrict__ cs, int ncell,
-                                                 int64_t n, Status* st) {
-  const int64_t cb = (int64_t)blockIdx.x * ncell / gridDim.x;
-  const int64_t ce = (int64_t)(blockIdx.x + 1) * ncell / gridDim.x;
+                                                 int64_t n, Status* st, int bid, int nb) {
+  const int64_t cb = (int64_t)bid * ncell / nb;
+  const int64_t ce = (int64_t)(bid + 1) * ncell / nb;
   bool bad = false;
   for (int64_t c = cb + threadIdx.x; c < ce; c += kBlock) {
     const int32_t v0 = cs[c], v1 = cs[c + 1];
     bad |= v0 < 0 || v1 < v0 || (int64_t)v1 > n;
   }
   if (threadIdx.x == 0) {
-    if (blockIdx.x == 0) bad |= cs[0] != 0;
-    if (blockIdx.x == gridDim.x - 1) bad |= (int64_t)cs[ncell] != n;
+    if (bid == 0) bad |= cs[0] != 0;
+    if (bid == nb - 1) bad |= (int64_t)cs[ncell] != n;
   }
   if (bad) flag_far(st, HVPIC_FLAG_BAD_INPUT, &st->bad_input);
 }
@@ -1076,11 +1076,13 @@ __device__ void move_general(const PushArgs& A, float x, float y, float z, float
 // in flight (the 3D windows already limit a CU to three blocks).
 // PM: 0 reads and writes the store in place; 1 and 2 read it through the
 // gather map A.perm (1: all byte offsets of the source arrays fit 32 bits).
-template <int NDIM, int SHAPE, bool DEP, int PM>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NDIM == 2 ? 4 : 1)))
-void k_gather_push(PushArgs A) {
-  constexpr int PPT = Chunk<NDIM>::PPT;
+// The push of one chunk of PPT*kBlock consecutive particles of the store
+// (chunk `chunk` of the nb chunks of that store; bid = chunk as well: it
+// picks the block's share of the cell_start check and its diagnostic slot).
+template <int NDIM, int SHAPE, bool DEP, int PM, int PPT>
+__device__ __forceinline__ void push_chunk(const PushArgs& A, int chunk, int nb) {
   constexpr int NF4 = Rec<NDIM, SHAPE>::NF4;
+  constexpr int CN = kBlock * PPT;  // particles per chunk
   __shared__ float4 gw[Chunk<NDIM>::WMAX * NF4];
   __shared__ double win[DEP ? DWin<NDIM>::LEN : 1];
   __shared__ uint8_t s_wrap[DEP ? DWin<NDIM>::NB * DWin<NDIM>::SW : 1];
@@ -1089,8 +1091,8 @@ void k_gather_push(PushArgs A) {
   __shared__ int32_t s_cs[Chunk<NDIM>::WMAX + 1];
   __shared__ int s_c[2];
   const Geo& g = A.g;
-  const int64_t base = (int64_t)xcd_chunk(blockIdx.x, gridDim.x) * Chunk<NDIM>::N;
-  const int64_t end = min(base + (int64_t)Chunk<NDIM>::N, A.n);
+  const int64_t base = (int64_t)chunk * CN;
+  const int64_t end = min(base + (int64_t)CN, A.n);
   if (threadIdx.x == 0) {
     if (PM != 0) {
       // (entries outside [0, n) are flagged where the particles are loaded)
@@ -1128,7 +1130,7 @@ void k_gather_push(PushArgs A) {
     if (DEP) dwin_init<NDIM>(win, s_wrap, W, c0, g);
     if (cnt_on) moves_window_init<NDIM>(A.cs, c0, span, s_cs, s_cnt);
   }
-  if (cnt_on) check_cell_start(A.cs, g.ncell, A.n, A.st);
+  if (cnt_on) check_cell_start(A.cs, g.ncell, A.n, A.st, chunk, nb);
   __syncthreads();
 
   float dK = 0.f, dP0 = 0.f, dP1 = 0.f, dP2 = 0.f;
@@ -1276,13 +1278,20 @@ void k_gather_push(PushArgs A) {
   if (want_diag) {
     const double hm = 0.5 * A.ms;
     double v[4] = {hm * dK, hm * dP0, hm * dP1, hm * dP2};
-    block_partial<4>(v, A.diag_part);
+    block_partial<4>(v, A.diag_part, chunk);
   }
   if (wok && (DEP || cnt_on)) {
     __syncthreads();
     if (DEP) dwin_flush<NDIM>(win, W, c0, g, A.acc);
     if (cnt_on) moves_window_flush<NDIM>(s_cnt, c0, span, A.cnt);
   }
+}
+
+template <int NDIM, int SHAPE, bool DEP, int PM>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NDIM == 2 ? 4 : 1)))
+void k_gather_push(PushArgs A) {
+  push_chunk<NDIM, SHAPE, DEP, PM, Chunk<NDIM>::PPT>(A, xcd_chunk(blockIdx.x, gridDim.x),
+                                                     gridDim.x);
 }
 
 // Stand-alone deposit at x - half_dt_back v (no push); same lane runs.
@@ -1376,27 +1385,38 @@ __global__ void k_zero(float* __restrict__ a, int64_t na, float* __restrict__ b,
 // for the next deposit.  Blocks of 1024 threads, so that block 0 sums the
 // push's per-block diagnostic partials in one round of loads.
 constexpr int kMomBlock = 1024;
-__global__ __launch_bounds__(kMomBlock) void k_moments_out(double* __restrict__ acc, int ncell,
-                                                        float* __restrict__ n,
-                                                        float* __restrict__ J,
-                                                        const double* part, int nparts,
-                                                        double* diag_out) {
+struct MomArgs {
+  double* acc;
+  int ncell;
+  float* n;
+  float* J;
+  const double* part;
+  int nparts;
+  double* diag_out;
+};
+
+// Block bid of nb (blocks of kMomBlock threads) of the moment output.
+__device__ __forceinline__ void moments_out_body(const MomArgs& M, int bid, int nb) {
   // block 0 also finishes the push diagnostics when asked (saves a launch)
-  if (diag_out != nullptr && blockIdx.x == 0) {
+  if (M.diag_out != nullptr && bid == 0) {
     double r[4];
-    sum_partials<4>(part, nparts, r);
+    sum_partials<4>(M.part, M.nparts, r);
     if (threadIdx.x == 0)
-      for (int k = 0; k < 4; ++k) diag_out[k] = r[k];
+      for (int k = 0; k < 4; ++k) M.diag_out[k] = r[k];
   }
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < 4ll * ncell; i += stride) {
-    const float v = (float)acc[i];
-    acc[i] = 0.0;
-    if (i < ncell)
-      n[i] = v;
+  const int64_t stride = (int64_t)nb * kMomBlock;
+  for (int64_t i = (int64_t)bid * kMomBlock + threadIdx.x; i < 4ll * M.ncell; i += stride) {
+    const float v = (float)M.acc[i];
+    M.acc[i] = 0.0;
+    if (i < M.ncell)
+      M.n[i] = v;
     else
-      J[i - ncell] = v;
+      M.J[i - M.ncell] = v;
   }
+}
+
+__global__ __launch_bounds__(kMomBlock) void k_moments_out(MomArgs M) {
+  moments_out_body(M, blockIdx.x, gridDim.x);
 }
 
 __global__ void k_write_zero_diag(double* out, int nv) {
@@ -1469,26 +1489,26 @@ void zero_counts(hvpic_ctx* c) {
 
 // FP64 accumulators -> n, J; with diag_out also the push diagnostics from
 // nparts per-block partials.
+int moment_blocks(const hvpic_ctx* c) {
+  return (int)std::min<int64_t>(ceil_div(4ll * c->ncell, kMomBlock), 512);
+}
+
+MomArgs mom_args(hvpic_ctx* c, float* n, float* J, int nparts, double* diag_out) {
+  return MomArgs{c->mom_acc, c->ncell, n, J, (const double*)c->push_part, nparts, diag_out};
+}
+
 void moments_out(hvpic_ctx* c, float* n, float* J, int nparts = 0, double* diag_out = nullptr) {
-  const int blocks = (int)std::min<int64_t>(ceil_div(4ll * c->ncell, kMomBlock), 512);
-  hipLaunchKernelGGL(k_moments_out, dim3(blocks), dim3(kMomBlock), 0, c->stream, c->mom_acc,
-                     c->ncell, n, J, (const double*)c->push_part, nparts, diag_out);
+  hipLaunchKernelGGL(k_moments_out, dim3(moment_blocks(c)), dim3(kMomBlock), 0, c->stream,
+                     mom_args(c, n, J, nparts, diag_out));
 }
 
 namespace {
 
-// The push of store `in` read through `perm` (null: in place, in == out) into
-// store `out`.
-int launch_push(hvpic_ctx* c, const hvpic_particles* in, const int32_t* perm,
-                hvpic_particles* p, const int32_t* cell_start, const float* E, const float* B,
-                float* n_mid, float* J_mid, double* diag_out) {
-  const bool dep = n_mid != nullptr && J_mid != nullptr;
-  c->cnt_ready = false;
-  if (p->n == 0) {
-    if (diag_out) hipLaunchKernelGGL(k_write_zero_diag, dim3(1), dim3(64), 0, c->stream, diag_out, 4);
-    if (dep) moments_out(c, n_mid, J_mid);
-    return hipGetLastError() == hipSuccess ? HVPIC_OK : HVPIC_EHIP;
-  }
+// The arguments of the push of store `in` read through `perm` (null: in
+// place) into store `p`.
+PushArgs push_args(hvpic_ctx* c, const hvpic_particles* in, const int32_t* perm,
+                   hvpic_particles* p, const int32_t* cell_start, const float* E,
+                   const float* B, double* diag_out) {
   PushArgs A;
   A.n = p->n;
   A.cell = p->cell;
@@ -1525,6 +1545,22 @@ int launch_push(hvpic_ctx* c, const hvpic_particles* in, const int32_t* perm,
   A.iuz = in->uz;
   A.iw = in->w;
   A.wo = p->w;
+  return A;
+}
+
+// The push of store `in` read through `perm` (null: in place, in == out) into
+// store `out`.
+int launch_push(hvpic_ctx* c, const hvpic_particles* in, const int32_t* perm,
+                hvpic_particles* p, const int32_t* cell_start, const float* E, const float* B,
+                float* n_mid, float* J_mid, double* diag_out) {
+  const bool dep = n_mid != nullptr && J_mid != nullptr;
+  c->cnt_ready = false;
+  if (p->n == 0) {
+    if (diag_out) hipLaunchKernelGGL(k_write_zero_diag, dim3(1), dim3(64), 0, c->stream, diag_out, 4);
+    if (dep) moments_out(c, n_mid, J_mid);
+    return hipGetLastError() == hipSuccess ? HVPIC_OK : HVPIC_EHIP;
+  }
+  PushArgs A = push_args(c, in, perm, p, cell_start, E, B, diag_out);
   if (cell_start != nullptr && !c->cnt_clean) zero_counts(c);
   const bool qs = c->p.shape == HVPIC_SHAPE_QS;
   int nblocks = 0;
@@ -1555,6 +1591,7 @@ int launch_push(hvpic_ctx* c, const hvpic_particles* in, const int32_t* perm,
 }
 
 }  // namespace
+
 
 int launch_gather_push(hvpic_ctx* c, hvpic_particles* p, const int32_t* cell_start,
                        const float* E, const float* B, float* n_mid, float* J_mid,
@@ -1608,6 +1645,92 @@ int launch_deposit(hvpic_ctx* c, const hvpic_particles* p, const int32_t* cell_s
   }
   timing_end(c, HVPIC_KERNEL_DEPOSIT);
   moments_out(c, n, J);
+  return hipGetLastError() == hipSuccess ? HVPIC_OK : HVPIC_EHIP;
+}
+
+// ------------------------------------------------------------ ensembles --
+// Batched forms of the push (gather-map sequence, fused deposit, move counts,
+// diagnostics) and of the moment output for an ensemble of independent 2D
+// runs: one persistent launch covers the chunks of every run, each work item
+// taking its run's arguments from a table in device memory.
+
+namespace {
+
+template <int SHAPE, int PPT>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4)))
+void k_gather_push_batch(const PushArgs* __restrict__ tab, const Item* __restrict__ items,
+                         int nitems) {
+  for_items(nitems, [&](int it) {
+    const Item item = items[it];
+    const PushArgs A = tab[item.run];
+    push_chunk<2, SHAPE, true, 1, PPT>(A, item.idx, item.nb);
+    __syncthreads();  // the next item reuses the LDS
+  });
+}
+
+__global__ __launch_bounds__(kMomBlock) void k_moments_out_batch(const MomArgs* __restrict__ tab,
+                                                                 const Item* __restrict__ items,
+                                                                 int nitems) {
+  for_items(nitems, [&](int it) {
+    const Item item = items[it];
+    const MomArgs M = tab[item.run];
+    moments_out_body(M, item.idx, item.nb);
+    __syncthreads();
+  });
+}
+
+template <int SHAPE>
+void push_batch_ppt(hipStream_t s, int ppt, const PushArgs* tab, const Item* items, int nitems,
+                    int grid) {
+  if (ppt == 4)
+    hipLaunchKernelGGL((k_gather_push_batch<SHAPE, 4>), dim3(grid), dim3(kBlock), 0, s, tab, items,
+                       nitems);
+  else if (ppt == 8)
+    hipLaunchKernelGGL((k_gather_push_batch<SHAPE, 8>), dim3(grid), dim3(kBlock), 0, s, tab, items,
+                       nitems);
+  else
+    hipLaunchKernelGGL((k_gather_push_batch<SHAPE, 12>), dim3(grid), dim3(kBlock), 0, s, tab,
+                       items, nitems);
+}
+
+}  // namespace
+
+size_t ens_push_record(hvpic_ctx* c, const hvpic_particles* in, const int32_t* perm,
+                       hvpic_particles* out, const int32_t* cs, const float* E, const float* B,
+                       bool diag, void* dst) {
+  if (dst) {
+    const PushArgs A = push_args(c, in, perm, out, cs, E, B, diag ? c->push_part : nullptr);
+    memcpy(dst, &A, sizeof(A));
+  }
+  return sizeof(PushArgs);
+}
+
+size_t ens_moments_record(hvpic_ctx* c, float* n, float* J, int nparts, double* diag_out,
+                          void* dst) {
+  if (dst) {
+    const MomArgs M = mom_args(c, n, J, nparts, diag_out);
+    memcpy(dst, &M, sizeof(M));
+  }
+  return sizeof(MomArgs);
+}
+
+int ens_moment_blocks(const hvpic_ctx* c) { return moment_blocks(c); }
+
+int ens_launch_push(hipStream_t s, int shape, int ppt, const void* tab, const Item* items,
+                    int nitems, int grid) {
+  if (nitems == 0) return HVPIC_OK;
+  const PushArgs* t = static_cast<const PushArgs*>(tab);
+  if (shape == HVPIC_SHAPE_QS)
+    push_batch_ppt<HVPIC_SHAPE_QS>(s, ppt, t, items, nitems, grid);
+  else
+    push_batch_ppt<HVPIC_SHAPE_NGP>(s, ppt, t, items, nitems, grid);
+  return hipGetLastError() == hipSuccess ? HVPIC_OK : HVPIC_EHIP;
+}
+
+int ens_launch_moments(hipStream_t s, const void* tab, const Item* items, int nitems, int grid) {
+  if (nitems == 0) return HVPIC_OK;
+  hipLaunchKernelGGL(k_moments_out_batch, dim3(grid), dim3(kMomBlock), 0, s,
+                     static_cast<const MomArgs*>(tab), items, nitems);
   return hipGetLastError() == hipSuccess ? HVPIC_OK : HVPIC_EHIP;
 }
 

@@ -29,6 +29,8 @@
 // histogram, and a stable scatter whose in-tile ranks come from per-wavefront
 // match masks.  The permutation then gathers the particle fields.  The same
 // tile ranking drives the single-block fallback.
+#include <string.h>
+
 #include "hvpic_internal.hpp"
 
 namespace hvpic {
@@ -260,17 +262,17 @@ __device__ uint32_t tile_exclusive_scan(uint32_t* s) {
 // Per-new-cell totals, written to cs[c], and their per-tile sums (tiles of
 // TILE cells).
 template <int NDIM, int TILE>
-__global__ __launch_bounds__(kBlock) void k_nb_newcount(const uint32_t* __restrict__ cnt, SortGeo g,
-                                                        int32_t* __restrict__ cs,
-                                                        uint32_t* __restrict__ blk, Status* st) {
+__device__ __forceinline__ void nb_newcount_body(const uint32_t* __restrict__ cnt, const SortGeo& g,
+                                                 int32_t* __restrict__ cs,
+                                                 uint32_t* __restrict__ blk, Status* st, int bid) {
   constexpr int ND = Dirs<NDIM>::N;
   __shared__ uint32_t wsum[kWaves];
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (bid == 0 && threadIdx.x == 0) {
     const uint32_t f = __hip_atomic_load(&st->far_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __hip_atomic_store(&st->far_decision, f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __hip_atomic_store(&st->far_flag, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
-  const int64_t t0 = (int64_t)blockIdx.x * TILE;
+  const int64_t t0 = (int64_t)bid * TILE;
   uint32_t local = 0;
   for (int q = 0; q < TILE / kBlock; ++q) {
     const int64_t c = t0 + q * kBlock + threadIdx.x;
@@ -291,8 +293,15 @@ __global__ __launch_bounds__(kBlock) void k_nb_newcount(const uint32_t* __restri
   if (threadIdx.x == 0) {
     uint32_t s = 0;
     for (int w = 0; w < kWaves; ++w) s += wsum[w];
-    blk[blockIdx.x] = s;
+    blk[bid] = s;
   }
+}
+
+template <int NDIM, int TILE>
+__global__ __launch_bounds__(kBlock) void k_nb_newcount(const uint32_t* __restrict__ cnt, SortGeo g,
+                                                        int32_t* __restrict__ cs,
+                                                        uint32_t* __restrict__ blk, Status* st) {
+  nb_newcount_body<NDIM, TILE>(cnt, g, cs, blk, st, blockIdx.x);
 }
 
 // Exclusive scan of m tile totals in one block (in place); blk[m] = total.
@@ -345,19 +354,19 @@ __device__ uint32_t block_sum(const uint32_t* __restrict__ v, int m) {
 // the tile totals; each block adds up those before it (a few hundred values
 // at most), which spares a separate scan launch.
 template <int NDIM, int TILE>
-__global__ __launch_bounds__(kBlock) void k_nb_bases(uint32_t* __restrict__ cnt, SortGeo g,
-                                                     int32_t* __restrict__ cs,
-                                                     const uint32_t* __restrict__ blk) {
+__device__ __forceinline__ void nb_bases_body(uint32_t* __restrict__ cnt, const SortGeo& g,
+                                              int32_t* __restrict__ cs,
+                                              const uint32_t* __restrict__ blk, int bid) {
   constexpr int ND = Dirs<NDIM>::N;
   __shared__ uint32_t s[TILE];
-  const int64_t t0 = (int64_t)blockIdx.x * TILE;
+  const int64_t t0 = (int64_t)bid * TILE;
   for (int q = 0; q < TILE / kBlock; ++q) {
     const int64_t c = t0 + q * kBlock + threadIdx.x;
     s[q * kBlock + threadIdx.x] = c < g.ncell ? (uint32_t)cs[c] : 0u;
   }
   __syncthreads();
   const uint32_t tile_total = tile_exclusive_scan<TILE>(s);
-  const uint32_t off = block_sum(blk, blockIdx.x);
+  const uint32_t off = block_sum(blk, bid);
   for (int q = 0; q < TILE / kBlock; ++q) {
     const int64_t c = t0 + q * kBlock + threadIdx.x;
     if (c >= g.ncell) break;
@@ -394,6 +403,13 @@ __global__ __launch_bounds__(kBlock) void k_nb_bases(uint32_t* __restrict__ cnt,
       }
     }
   }
+}
+
+template <int NDIM, int TILE>
+__global__ __launch_bounds__(kBlock) void k_nb_bases(uint32_t* __restrict__ cnt, SortGeo g,
+                                                     int32_t* __restrict__ cs,
+                                                     const uint32_t* __restrict__ blk) {
+  nb_bases_body<NDIM, TILE>(cnt, g, cs, blk, blockIdx.x);
 }
 
 
@@ -609,11 +625,11 @@ __device__ void block_sort(int64_t n, int ncell, Fields in, Fields out, int32_t*
 
 // PERM: write the gather map out.perm[dst] = p instead of moving the fields.
 template <int NDIM, bool PERM>
-__global__ __launch_bounds__(kBlock) void k_nb_scatter(const int32_t* __restrict__ cs_prev, int64_t n,
-                                                       SortGeo g, uint32_t* __restrict__ bases,
-                                                       Fields in, Fields out, int32_t* cs,
-                                                       const Status* st, uint32_t* rk0, uint32_t* rk1,
-                                                       uint32_t* rv0, uint32_t* rv1) {
+__device__ __forceinline__ void nb_scatter_body(const int32_t* __restrict__ cs_prev, int64_t n,
+                                                const SortGeo& g, uint32_t* __restrict__ bases,
+                                                const Fields& in, const Fields& out, int32_t* cs,
+                                                const Status* st, uint32_t* rk0, uint32_t* rk1,
+                                                uint32_t* rv0, uint32_t* rv1, int bid) {
   constexpr int ND = Dirs<NDIM>::N, NB = Dirs<NDIM>::BITS;
   constexpr int CODE_BITS = NB + kScatterCellBits;
   constexpr int NF = PERM ? 0 : 7;        // fields carried through registers
@@ -621,7 +637,7 @@ __global__ __launch_bounds__(kBlock) void k_nb_scatter(const int32_t* __restrict
   constexpr int GPL = (NG + 63) / 64;     // groups per lane
   __shared__ uint32_t s_next[kWaves][NG];  // next free slot of each group
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const int a0 = (blockIdx.x * kWaves + wid) * kScatterCells;
+  const int a0 = (bid * kWaves + wid) * kScatterCells;
   const int na = a0 < g.ncell ? min(kScatterCells, g.ncell - a0) : 0;
   // The far decision, the group bases and the cell bounds are independent:
   // their loads go out together.
@@ -645,7 +661,7 @@ __global__ __launch_bounds__(kBlock) void k_nb_scatter(const int32_t* __restrict
     }
   }
   if (far != 0) {
-    if (blockIdx.x == 0) {
+    if (bid == 0) {
       uint32_t* rkey[2] = {rk0, rk1};
       uint32_t* rval[2] = {rv0, rv1};
       block_sort(n, g.ncell, in, out, cs, rkey, rval);
@@ -722,6 +738,64 @@ __global__ __launch_bounds__(kBlock) void k_nb_scatter(const int32_t* __restrict
     }
    }
   }
+}
+
+template <int NDIM, bool PERM>
+__global__ __launch_bounds__(kBlock) void k_nb_scatter(const int32_t* __restrict__ cs_prev, int64_t n,
+                                                       SortGeo g, uint32_t* __restrict__ bases,
+                                                       Fields in, Fields out, int32_t* cs,
+                                                       const Status* st, uint32_t* rk0, uint32_t* rk1,
+                                                       uint32_t* rv0, uint32_t* rv1) {
+  nb_scatter_body<NDIM, PERM>(cs_prev, n, g, bases, in, out, cs, st, rk0, rk1, rv0, rv1,
+                              blockIdx.x);
+}
+
+// Batched neighbour sort (gather-map form) over the runs of an ensemble:
+// per run the arguments of the three passes, per pass one persistent launch.
+struct NbArgs {
+  const int32_t* cs_prev;
+  int64_t n;
+  SortGeo g;
+  uint32_t* cnt;
+  uint32_t* blk;
+  Fields in, out;
+  int32_t* cs;
+  Status* st;
+  uint32_t *rk0, *rk1, *rv0, *rv1;
+};
+
+__global__ __launch_bounds__(kBlock) void k_nb_newcount_batch(const NbArgs* __restrict__ tab,
+                                                              const Item* __restrict__ items,
+                                                              int nitems) {
+  for_items(nitems, [&](int it) {
+    const Item item = items[it];
+    const NbArgs A = tab[item.run];
+    nb_newcount_body<2, kNbTileSmall>(A.cnt, A.g, A.cs, A.blk, A.st, item.idx);
+    __syncthreads();
+  });
+}
+
+__global__ __launch_bounds__(kBlock) void k_nb_bases_batch(const NbArgs* __restrict__ tab,
+                                                           const Item* __restrict__ items,
+                                                           int nitems) {
+  for_items(nitems, [&](int it) {
+    const Item item = items[it];
+    const NbArgs A = tab[item.run];
+    nb_bases_body<2, kNbTileSmall>(A.cnt, A.g, A.cs, A.blk, item.idx);
+    __syncthreads();
+  });
+}
+
+__global__ __launch_bounds__(kBlock) void k_nb_scatter_batch(const NbArgs* __restrict__ tab,
+                                                             const Item* __restrict__ items,
+                                                             int nitems) {
+  for_items(nitems, [&](int it) {
+    const Item item = items[it];
+    const NbArgs A = tab[item.run];
+    nb_scatter_body<2, true>(A.cs_prev, A.n, A.g, A.cnt, A.in, A.out, A.cs, A.st, A.rk0, A.rk1,
+                             A.rv0, A.rv1, item.idx);
+    __syncthreads();
+  });
 }
 
 Fields fields_of(const hvpic_particles* p) {
@@ -859,6 +933,48 @@ int launch_sort_perm(hvpic_ctx* c, const hvpic_particles* in, const int32_t* cs_
   Fields out{};
   out.perm = perm;
   return sort_to(c, in, out, cs_prev, cs, 0);
+}
+
+size_t ens_sort_record(hvpic_ctx* c, const hvpic_particles* in, const int32_t* cs_prev,
+                       int32_t* perm, int32_t* cs, void* dst) {
+  if (dst) {
+    NbArgs A;
+    A.cs_prev = cs_prev;
+    A.n = in->n;
+    A.g = sort_geo(c);
+    A.cnt = c->sort_cnt;
+    A.blk = (uint32_t*)c->sort_blk;
+    A.in = fields_of(in);
+    A.out = Fields{};
+    A.out.perm = perm;
+    A.cs = cs;
+    A.st = c->status;
+    A.rk0 = c->rkey[0];
+    A.rk1 = c->rkey[1];
+    A.rv0 = c->rval[0];
+    A.rv1 = c->rval[1];
+    memcpy(dst, &A, sizeof(A));
+  }
+  return sizeof(NbArgs);
+}
+
+int ens_sort_tiles(const hvpic_ctx* c) { return (int)ceil_div(c->ncell, kNbTileSmall); }
+int ens_sort_scatter_blocks(const hvpic_ctx* c) {
+  return (int)ceil_div(c->ncell, kWaves * kScatterCells);
+}
+bool ens_sort_fits(const hvpic_ctx* c) { return c->ncell <= kNbTileSmall * 512; }
+
+int ens_launch_sort(hipStream_t s, int pass, const void* tab, const Item* items, int nitems,
+                    int grid) {
+  if (nitems == 0) return HVPIC_OK;
+  const NbArgs* t = static_cast<const NbArgs*>(tab);
+  if (pass == 0)
+    hipLaunchKernelGGL(k_nb_newcount_batch, dim3(grid), dim3(kBlock), 0, s, t, items, nitems);
+  else if (pass == 1)
+    hipLaunchKernelGGL(k_nb_bases_batch, dim3(grid), dim3(kBlock), 0, s, t, items, nitems);
+  else
+    hipLaunchKernelGGL(k_nb_scatter_batch, dim3(grid), dim3(kBlock), 0, s, t, items, nitems);
+  return hipGetLastError() == hipSuccess ? HVPIC_OK : HVPIC_EHIP;
 }
 
 }  // namespace hvpic

@@ -27,6 +27,10 @@ EXPORTS = ("hvpic_workspace_bytes", "hvpic_init", "hvpic_finalize", "hvpic_set_s
            "hvpic_deposit_noalloc",
            "hvpic_field_advance", "hvpic_field_advance_pe", "hvpic_eos_pressure", "hvpic_smooth",
            "hvpic_sync_status", "hvpic_path_stats", "hvpic_timing_enable", "hvpic_timing_read",
+           "hvpic_ensemble_workspace_bytes", "hvpic_tuning_default", "hvpic_ensemble_init",
+           "hvpic_ensemble_finalize", "hvpic_ensemble_step", "hvpic_ensemble_steps",
+           "hvpic_ensemble_capture", "hvpic_ensemble_get_tuning", "hvpic_ensemble_set_tuning",
+           "hvpic_ensemble_autotune",
            "hvpic_strerror")
 KERNEL_GATHER_PUSH, KERNEL_DEPOSIT, KERNEL_SORT_SCATTER = 0, 1, 2
 
@@ -52,6 +56,22 @@ class HvpicParticles(ctypes.Structure):
                 ("ox", ctypes.c_void_p), ("oy", ctypes.c_void_p), ("oz", ctypes.c_void_p),
                 ("ux", ctypes.c_void_p), ("uy", ctypes.c_void_p), ("uz", ctypes.c_void_p),
                 ("w", ctypes.c_void_p)]
+
+
+class HvpicRun(ctypes.Structure):
+    _fields_ = [("ctx", ctypes.c_void_p), ("store", HvpicParticles * 2), ("perm", ctypes.c_void_p),
+                ("cell_start", ctypes.c_void_p * 2), ("E", ctypes.c_void_p),
+                ("B", ctypes.c_void_p), ("n", ctypes.c_void_p * 2), ("J", ctypes.c_void_p * 2),
+                ("push_diag", ctypes.c_void_p), ("field_diag", ctypes.c_void_p)]
+
+
+class HvpicTuning(ctypes.Structure):
+    _fields_ = [("push_chunk", ctypes.c_int32 * 3), ("field_tile", ctypes.c_int32 * 2),
+                ("blocks_per_cu", ctypes.c_int32 * 4)]
+
+    def as_dict(self) -> dict:
+        return {"push_chunk": list(self.push_chunk), "field_tile": list(self.field_tile),
+                "blocks_per_cu": list(self.blocks_per_cu)}
 
 
 class HvpicError(RuntimeError):
@@ -86,6 +106,17 @@ def lib():
         L.hvpic_path_stats.argtypes = [vp, P(ctypes.c_int64)]
         L.hvpic_timing_enable.argtypes = [vp, i32, i32]
         L.hvpic_timing_read.argtypes = [vp, i32, P(ctypes.c_double), P(ctypes.c_int64)]
+        RP, TP = P(HvpicRun), P(HvpicTuning)
+        L.hvpic_ensemble_workspace_bytes.argtypes = [RP, i32, P(ctypes.c_size_t)]
+        L.hvpic_tuning_default.argtypes = [TP]
+        L.hvpic_ensemble_init.argtypes = [RP, i32, vp, vp, TP, P(vp)]
+        L.hvpic_ensemble_finalize.argtypes = [vp]
+        L.hvpic_ensemble_step.argtypes = [vp]
+        L.hvpic_ensemble_steps.argtypes = [vp, P(ctypes.c_int64)]
+        L.hvpic_ensemble_capture.argtypes = [vp, i32]
+        L.hvpic_ensemble_get_tuning.argtypes = [vp, TP]
+        L.hvpic_ensemble_set_tuning.argtypes = [vp, TP]
+        L.hvpic_ensemble_autotune.argtypes = [vp, i32, TP, P(ctypes.c_double)]
         L.hvpic_strerror.argtypes = [ctypes.c_int]
         L.hvpic_strerror.restype = ctypes.c_char_p
         for f in EXPORTS[:-1]:
@@ -344,6 +375,64 @@ def hvpic_timing_read(ctx, kernel: int):
 
 def hvpic_strerror(code: int) -> str:
     return lib().hvpic_strerror(code).decode()
+
+
+def hvpic_ensemble_workspace_bytes(runs) -> int:
+    n = ctypes.c_size_t(0)
+    _check(lib().hvpic_ensemble_workspace_bytes(runs, len(runs), ctypes.byref(n)),
+           "hvpic_ensemble_workspace_bytes")
+    return n.value
+
+
+def hvpic_tuning_default() -> HvpicTuning:
+    t = HvpicTuning()
+    _check(lib().hvpic_tuning_default(ctypes.byref(t)), "hvpic_tuning_default")
+    return t
+
+
+def hvpic_ensemble_init(runs, stream, workspace: torch.Tensor, tuning=None):
+    e = ctypes.c_void_p()
+    _check(lib().hvpic_ensemble_init(runs, len(runs), stream, _ptr(workspace, torch.uint8),
+                                     None if tuning is None else ctypes.byref(tuning),
+                                     ctypes.byref(e)),
+           "hvpic_ensemble_init")
+    return e
+
+
+def hvpic_ensemble_finalize(e):
+    _check(lib().hvpic_ensemble_finalize(e), "hvpic_ensemble_finalize")
+
+
+def hvpic_ensemble_step(e):
+    _check(lib().hvpic_ensemble_step(e), "hvpic_ensemble_step")
+
+
+def hvpic_ensemble_steps(e) -> int:
+    k = ctypes.c_int64(0)
+    _check(lib().hvpic_ensemble_steps(e, ctypes.byref(k)), "hvpic_ensemble_steps")
+    return k.value
+
+
+def hvpic_ensemble_capture(e, enable: bool = True):
+    _check(lib().hvpic_ensemble_capture(e, int(bool(enable))), "hvpic_ensemble_capture")
+
+
+def hvpic_ensemble_get_tuning(e) -> HvpicTuning:
+    t = HvpicTuning()
+    _check(lib().hvpic_ensemble_get_tuning(e, ctypes.byref(t)), "hvpic_ensemble_get_tuning")
+    return t
+
+
+def hvpic_ensemble_set_tuning(e, tuning: HvpicTuning):
+    _check(lib().hvpic_ensemble_set_tuning(e, ctypes.byref(tuning)), "hvpic_ensemble_set_tuning")
+
+
+def hvpic_ensemble_autotune(e, reps: int = 2):
+    t = HvpicTuning()
+    ms = (ctypes.c_double * 3)()
+    _check(lib().hvpic_ensemble_autotune(e, int(reps), ctypes.byref(t), ms),
+           "hvpic_ensemble_autotune")
+    return t, tuple(ms)
 
 
 class Context:

@@ -293,3 +293,106 @@ class GpuSim:
             idx = self.perm[:self.p.n].cpu().numpy()
             d = {k: v[idx] for k, v in d.items()}
         return d
+
+
+class Ensemble:
+    """Independent 2D runs stepped together (hvpic_ensemble_*): every phase of
+    the step is one persistent launch over the work items of all runs.
+
+    Takes GpuSim objects set up for the gather-map sequence (their current
+    state is the start) and steps them on a stream of its own; their
+    tensors hold the state, rotating between the two buffer sets every step
+    as GpuSim.step swaps them.  state(r) returns run r's current tensors.
+    The GpuSim objects must not be stepped while the ensemble is in use."""
+
+    def __init__(self, sims, tuning=None, device="cuda"):
+        for g in sims:
+            if not (g.gather_map and g.fused) or g.cfg.nsmooth or g.cfg.ndim != 2:
+                raise ValueError("ensemble runs use the fused gather-map sequence in 2D")
+            g.synchronize()
+        self.sims = list(sims)
+        self.stream = torch.cuda.Stream(device)
+        recs = (H.HvpicRun * len(self.sims))()
+        for r, g in enumerate(self.sims):
+            g.q.n = g.p.n
+            R = recs[r]
+            R.ctx = g.ctx.ctx
+            R.store[0] = g.p.c()
+            R.store[1] = g.q.c()
+            R.perm = g.perm.data_ptr()
+            R.cell_start[0], R.cell_start[1] = g.cs.data_ptr(), g.cs_alt.data_ptr()
+            R.E, R.B = g.E.data_ptr(), g.B.data_ptr()
+            R.n[0], R.n[1] = g.n_prev.data_ptr(), g.n_half.data_ptr()
+            R.J[0], R.J[1] = g.J_prev.data_ptr(), g.J_half.data_ptr()
+            R.push_diag = g.push_diag.data_ptr() if g.diagnostics else None
+            R.field_diag = g.field_diag.data_ptr() if g.diagnostics else None
+        self._recs = recs
+        # the even state: the sims' tensors as they are now
+        self._bufs = [dict(p=(g.p, g.q), cs=(g.cs, g.cs_alt), n=(g.n_prev, g.n_half),
+                           J=(g.J_prev, g.J_half)) for g in self.sims]
+        nbytes = H.hvpic_ensemble_workspace_bytes(recs)
+        self.workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+        self.e = H.hvpic_ensemble_init(recs, self.stream.cuda_stream, self.workspace, tuning)
+
+    @property
+    def steps(self) -> int:
+        return H.hvpic_ensemble_steps(self.e)
+
+    def step(self):
+        H.hvpic_ensemble_step(self.e)
+
+    def capture(self, enable: bool = True):
+        H.hvpic_ensemble_capture(self.e, enable)
+
+    def autotune(self, reps: int = 2):
+        """Tunes on real steps (they advance the runs); returns (choices, phase ms)."""
+        t, ms = H.hvpic_ensemble_autotune(self.e, reps)
+        return t.as_dict(), ms
+
+    @property
+    def tuning(self) -> dict:
+        return H.hvpic_ensemble_get_tuning(self.e).as_dict()
+
+    def set_tuning(self, tuning: dict):
+        """Changes the given choices (the others stay)."""
+        t = H.hvpic_ensemble_get_tuning(self.e)
+        for k, v in tuning.items():
+            getattr(t, k)[:] = v
+        H.hvpic_ensemble_set_tuning(self.e, t)
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+    def state(self, r: int) -> dict:
+        """Run r's current state (tensors; no copy): store, perm, cell_start,
+        E, B, n, J at level n-1/2, and the diagnostics."""
+        self.synchronize()
+        k = self.steps & 1
+        b = self._bufs[r]
+        g = self.sims[r]
+        return dict(p=b["p"][k], perm=g.perm, cs=b["cs"][k], E=g.E, B=g.B, n_prev=b["n"][k],
+                    J_prev=b["J"][k], push_diag=g.push_diag, field_diag=g.field_diag)
+
+    def particles(self, r: int) -> dict:
+        """Run r's particle store in sorted order (host copy)."""
+        s = self.state(r)
+        d = s["p"].to_numpy()
+        idx = s["perm"][:s["p"].n].cpu().numpy()
+        return {k: v[idx] for k, v in d.items()}
+
+    def status(self, r: int):
+        self.synchronize()
+        return H.hvpic_sync_status(self.sims[r].ctx.ctx)
+
+    def close(self):
+        if getattr(self, "e", None) is not None:
+            self.synchronize()
+            H.hvpic_ensemble_finalize(self.e)
+            self.e = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+

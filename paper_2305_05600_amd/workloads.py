@@ -151,6 +151,34 @@ def periodic_alfven(seed: int = 1, nx: int = 32, ny: int = 32, ppc: int = 64,
     return cfg, parts, B
 
 
+def ensemble_specs(seed: int = 4, nruns: int = 64, side=(64, 256), ppc=(32, 200),
+                   amp=(0.001, 0.05), te_ratio=(0.1, 1.0), vth: float = 0.5) -> list:
+    """Parameters of an ensemble of independent 2D periodic runs of uneven
+    size: per run a square grid with side uniform in [side], particles per
+    cell uniform in [ppc], a transverse wave of amplitude uniform in [amp]
+    (in B0) and T_e/T_i uniform in [te_ratio], otherwise the small periodic
+    case (0.5 d_i cells, v_th = 0.5, eta = 1e-3, dt = 0.01, 4 B-subcycles).
+    Returns one dict per run for ensemble_run."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    sides = rng.integers(side[0], side[1] + 1, nruns)
+    ppcs = rng.integers(ppc[0], ppc[1] + 1, nruns)
+    amps = rng.uniform(amp[0], amp[1], nruns)
+    ratios = rng.uniform(te_ratio[0], te_ratio[1], nruns)
+    return [dict(seed=int(seed * 1000 + r), side=int(sides[r]), ppc=int(ppcs[r]),
+                 amp=float(amps[r]), te_ratio=float(ratios[r]), vth=vth) for r in range(nruns)]
+
+
+def ensemble_run(spec: dict, shape: int = SHAPE_QS):
+    """(cfg, parts, B) of one run of ensemble_specs."""
+    cfg, parts, B = periodic_alfven(seed=spec["seed"], nx=spec["side"], ny=spec["side"],
+                                    ppc=spec["ppc"], vth=spec["vth"], amp=spec["amp"],
+                                    shape=shape)
+    te = spec["te_ratio"] * spec["vth"] ** 2
+    cfg = cfg.replace(te=te, name=f"2d-periodic-{spec['side']}^2-ppc{spec['ppc']}-a{spec['amp']:.3g}"
+                                  f"-te{te:.3g}")
+    return cfg, parts, B
+
+
 def harris_double(seed: int = 2, nx: int = 512, ny: int = 256, ppc: float = 100.0,
                   steps: int = 1000):
     """Periodic double Harris current sheet (2D, 512x256 cells of 0.125 d_i).
