@@ -4,7 +4,9 @@ Workload (default, --workload harris): the 2D periodic double Harris current
 sheet, 512x256 cells, 100 ions per cell on average (13,107,200 particles), QS
 shape, 10 B-subcycles, FP32 particles and fields (seeded synthetic inputs).
 --workload beam3d: the 3D periodic core + beam box, 128^3 cells, 64 ions per
-cell (134,217,728 particles), QS shape, 4 B-subcycles.  One step = gather +
+cell (134,217,728 particles), QS shape, 4 B-subcycles.  --workload ensemble:
+64 independent 2D periodic runs of uneven size stepped together (see
+bench_ensemble).  One step = gather +
 push + fused mid-point deposit, neighbour-move sort, field advance (Ohm + RK2
 Faraday subcycle + extrapolation), FP64 diagnostics.
 
@@ -136,12 +138,150 @@ def _changed_cell_fraction(g):
     return float((old != new).float().mean())
 
 
+def bench_ensemble(args) -> dict:
+    """The ensemble of 64 independent 2D periodic runs of uneven size (sides
+    64..256, 32..200 ions per cell): K steps of every run stepped one after
+    another by the plain sequence, then K steps of the same runs as one
+    ensemble (tuned by the autotuner on real steps, the step replayed from a
+    hipGraph).  `value` is the ensemble's ion pushes/s; the speedup is
+    against the plain steps of the same runs."""
+    import numpy as np
+    import torch
+
+    from paper_2305_05600_amd import sim as S
+    from paper_2305_05600_amd import workloads as W
+
+    specs = W.ensemble_specs()
+    sims, cells, n_total = [], 0, 0
+    for sp in specs:
+        cfg, parts, B = W.ensemble_run(sp)
+        sims.append(S.GpuSim(cfg, parts, B, fused=True, gather_map=True))
+        cells += cfg.ncell
+        n_total += int(parts["cell"].size)
+        del parts
+    print(f"# ensemble: {len(sims)} runs, {n_total} particles, {cells} cells", file=sys.stderr,
+          flush=True)
+    steps, warm = args.steps, args.warmup
+    # plain: every run stepped in turn, each on its own streams
+    for _ in range(warm):
+        for g in sims:
+            g.step(order_caller=False)
+    for g in sims:
+        g.synchronize()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for g in sims:
+            g.step(order_caller=False)
+    for g in sims:
+        g.synchronize()
+    torch.cuda.synchronize()
+    plain_ms = (time.perf_counter() - t0) * 1e3 / steps
+    print(f"# plain steps: {plain_ms:.3f} ms per step of all runs", file=sys.stderr, flush=True)
+    ens = S.Ensemble(sims)
+    choices, _ = ens.autotune(reps=2)
+    phase_ms = ens.time_phases(max(MIN_TIMED_LAUNCHES, 10))
+    ens.capture(True)
+    for _ in range(warm):
+        ens.step()
+    ens.synchronize()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ens.step()
+    ens.synchronize()
+    torch.cuda.synchronize()
+    ens_ms = (time.perf_counter() - t0) * 1e3 / steps
+    print(f"# ensemble steps: {ens_ms:.3f} ms per step, phases {phase_ms}", file=sys.stderr,
+          flush=True)
+    flags = [ens.status(r)[0] for r in range(len(sims))]
+    per_launch = BYTES_PER_PARTICLE[2] * n_total + BYTES_PER_CELL * cells
+    achieved = per_launch / (phase_ms[0] * 1e-3) / 1e9
+    sides = [sp["side"] for sp in specs]
+    ppcs = [sp["ppc"] for sp in specs]
+    out = {
+        "metric": METRIC,
+        "value": n_total / (ens_ms * 1e-3),
+        "unit": "pushes/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warm,
+        "ms_per_step": ens_ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"ensemble-{len(sims)}-periodic-2d-runs",
+                   "runs": len(sims), "particles": n_total, "cells": cells,
+                   "side_range": [min(sides), max(sides)], "ppc_range": [min(ppcs), max(ppcs)],
+                   "shape": "QS", "b_subcycles": 4, "dt": 0.01, "tuning": choices,
+                   "step": "hipGraph replay of one persistent launch per phase"},
+        "plain_steps_ms_per_step": plain_ms,
+        "speedup_vs_plain_steps": plain_ms / ens_ms,
+        "phase_ms": {"push": phase_ms[0], "moments_and_sort": phase_ms[1],
+                     "fields": phase_ms[2]},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_gather_push_batch (all chunks of all runs, fused deposit, "
+                               "read through the gather map)",
+                     "kernel_ms": phase_ms[0],
+                     "kernel_timed_launches": f"{max(MIN_TIMED_LAUNCHES, 10)} eager steps",
+                     "algorithmic_bytes_per_launch": per_launch},
+        "status_flags": int(np.bitwise_or.reduce(flags)),
+    }
+    if not args.no_cpu_baseline:
+        import contextlib
+
+        from tests.helpers import drop_straddlers
+
+        # the oracle on the run of median size; the ensemble's error on a
+        # fresh copy of the first four runs against the same runs stepped
+        # plainly, and the median run's one step against the oracle
+        order = sorted(range(len(specs)), key=lambda r: sides[r] ** 2 * ppcs[r])
+        cfg, parts, B = W.ensemble_run(specs[order[len(order) // 2]])
+        with contextlib.redirect_stdout(sys.stderr):
+            clean = drop_straddlers(cfg, parts, B)
+        dropped = int(parts["cell"].size - clean["cell"].size)
+        g1 = S.GpuSim(cfg, clean, B, fused=True, gather_map=True)
+        g1.step()
+        g1.synchronize()
+        first_gpu = {"n": g1.n_prev.cpu().numpy(), "J": g1.J_prev.cpu().numpy(),
+                     "B": g1.B.cpu().numpy(), "E": g1.E.cpu().numpy()}
+        del g1
+        out["cpu_baseline"], first = cpu_baseline(cfg, clean, B)
+        out["one_step_rel_l2_vs_oracle_case"] = f"{cfg.name} without {dropped} face straddlers"
+        out["one_step_rel_l2_vs_oracle"] = {
+            k: float(np.linalg.norm(first_gpu[k] - first[k]) / np.linalg.norm(first[k]))
+            for k in ("n", "J", "B", "E")}
+        sub = [W.ensemble_run(sp) for sp in specs[:4]]
+        a = [S.GpuSim(*r, fused=True, gather_map=True) for r in sub]
+        b = [S.GpuSim(*r, fused=True, gather_map=True) for r in sub]
+        e2 = S.Ensemble(a)
+        e2.set_tuning(choices)
+        for _ in range(3):
+            e2.step()
+            for g in b:
+                g.step()
+        worst = 0.0
+        for r, g in enumerate(b):
+            st = e2.state(r)
+            g.synchronize()
+            for k, ref in (("E", g.E), ("B", g.B), ("n_prev", g.n_prev), ("J_prev", g.J_prev)):
+                ref = ref.cpu().numpy()
+                worst = max(worst, float(np.linalg.norm(st[k].cpu().numpy() - ref) /
+                                         np.linalg.norm(ref)))
+        out["ensemble_vs_plain_rel_l2"] = {"max_over_E_B_n_J": worst,
+                                           "case": "the first 4 runs, 3 steps, tuned choices"}
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=("harris", "beam3d"), default="harris",
+    ap.add_argument("--workload", choices=("harris", "beam3d", "ensemble"), default="harris",
                     help="harris: 2D double Harris sheet 512x256, 13.1M ions; beam3d: 3D core + "
-                         "beam 128^3, 134M ions")
+                         "beam 128^3, 134M ions; ensemble: 64 independent 2D runs of uneven size")
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -161,6 +301,10 @@ def main() -> int:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
               "sharding of the step is a design note, not part of this build", file=sys.stderr)
         return 2
+
+    if args.workload == "ensemble":
+        print(json.dumps(bench_ensemble(args)), flush=True)
+        return 0
 
     import numpy as np
     import torch

@@ -417,6 +417,12 @@ int hvpic_ensemble_set_tuning(hvpic_ensemble* e, const hvpic_tuning* t);
    NULL).  Waits for the stream. */
 int hvpic_ensemble_autotune(hvpic_ensemble* e, int reps, hvpic_tuning* best, double* ms);
 
+/* Runs `steps` real steps launching their kernels directly, with HIP events
+   at the phase boundaries, waits for them, and returns the mean time per
+   step of each phase in ms[3] = {push (all chunks of all runs), moment
+   output + sort, field advance + diagnostics}. */
+int hvpic_ensemble_time_phases(hvpic_ensemble* e, int steps, double* ms);
+
 #ifdef __cplusplus
 }
 #endif

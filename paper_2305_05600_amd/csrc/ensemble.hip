@@ -566,4 +566,30 @@ int hvpic_ensemble_autotune(hvpic_ensemble* e, int reps, hvpic_tuning* best_out,
   return rc;
 }
 
+int hvpic_ensemble_time_phases(hvpic_ensemble* e, int steps, double* ms) {
+  if (!ens_ok(e)) return HVPIC_ESTATE;
+  if (steps < 1 || steps > 100000 || !ms) return HVPIC_EINVAL;
+  std::vector<hipEvent_t> ev(4 * (size_t)steps);
+  for (auto& x : ev)
+    if (hipEventCreate(&x) != hipSuccess) return HVPIC_EHIP;
+  int rc = HVPIC_OK;
+  for (int k = 0; k < steps && rc == HVPIC_OK; ++k) {
+    rc = enqueue(e, (int)(e->steps & 1), ev.data() + 4 * (size_t)k);
+    if (rc == HVPIC_OK) ++e->steps;
+  }
+  double sum[3] = {0.0, 0.0, 0.0};
+  if (rc == HVPIC_OK && hipStreamSynchronize(e->stream) != hipSuccess) rc = HVPIC_EHIP;
+  for (int k = 0; k < steps && rc == HVPIC_OK; ++k)
+    for (int ph = 0; ph < 3; ++ph) {
+      float a = 0.f;
+      if (hipEventElapsedTime(&a, ev[4 * (size_t)k + ph], ev[4 * (size_t)k + ph + 1]) != hipSuccess)
+        rc = HVPIC_EHIP;
+      sum[ph] += a;
+    }
+  for (auto& x : ev) (void)hipEventDestroy(x);
+  if (rc == HVPIC_OK)
+    for (int ph = 0; ph < 3; ++ph) ms[ph] = sum[ph] / steps;
+  return rc;
+}
+
 }  // extern "C"

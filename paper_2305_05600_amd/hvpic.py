@@ -30,7 +30,7 @@ EXPORTS = ("hvpic_workspace_bytes", "hvpic_init", "hvpic_finalize", "hvpic_set_s
            "hvpic_ensemble_workspace_bytes", "hvpic_tuning_default", "hvpic_ensemble_init",
            "hvpic_ensemble_finalize", "hvpic_ensemble_step", "hvpic_ensemble_steps",
            "hvpic_ensemble_capture", "hvpic_ensemble_get_tuning", "hvpic_ensemble_set_tuning",
-           "hvpic_ensemble_autotune",
+           "hvpic_ensemble_autotune", "hvpic_ensemble_time_phases",
            "hvpic_strerror")
 KERNEL_GATHER_PUSH, KERNEL_DEPOSIT, KERNEL_SORT_SCATTER = 0, 1, 2
 
@@ -117,6 +117,7 @@ def lib():
         L.hvpic_ensemble_get_tuning.argtypes = [vp, TP]
         L.hvpic_ensemble_set_tuning.argtypes = [vp, TP]
         L.hvpic_ensemble_autotune.argtypes = [vp, i32, TP, P(ctypes.c_double)]
+        L.hvpic_ensemble_time_phases.argtypes = [vp, i32, P(ctypes.c_double)]
         L.hvpic_strerror.argtypes = [ctypes.c_int]
         L.hvpic_strerror.restype = ctypes.c_char_p
         for f in EXPORTS[:-1]:
@@ -433,6 +434,12 @@ def hvpic_ensemble_autotune(e, reps: int = 2):
     _check(lib().hvpic_ensemble_autotune(e, int(reps), ctypes.byref(t), ms),
            "hvpic_ensemble_autotune")
     return t, tuple(ms)
+
+
+def hvpic_ensemble_time_phases(e, steps: int):
+    ms = (ctypes.c_double * 3)()
+    _check(lib().hvpic_ensemble_time_phases(e, int(steps), ms), "hvpic_ensemble_time_phases")
+    return tuple(ms)
 
 
 class Context:

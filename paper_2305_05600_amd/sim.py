@@ -349,6 +349,11 @@ class Ensemble:
         t, ms = H.hvpic_ensemble_autotune(self.e, reps)
         return t.as_dict(), ms
 
+    def time_phases(self, steps: int = 10):
+        """Mean ms per step of {push, moments + sort, fields} over `steps`
+        real steps launched directly (they advance the runs)."""
+        return H.hvpic_ensemble_time_phases(self.e, steps)
+
     @property
     def tuning(self) -> dict:
         return H.hvpic_ensemble_get_tuning(self.e).as_dict()

@@ -176,6 +176,9 @@ def test_autotune_steps_are_real_steps(mods):
     assert all(1 <= b <= 64 for b in choices["blocks_per_cu"])
     assert ens.tuning == choices
     print(f"autotune: {choices}, phase ms {ms}, {k} steps", flush=True)
+    phases = ens.time_phases(3)
+    assert all(m > 0.0 for m in phases) and ens.steps == k + 3
+    k = ens.steps
     plain = _sims(S, runs)
     for _ in range(k):
         for g in plain:
