@@ -423,6 +423,71 @@ int hvpic_ensemble_autotune(hvpic_ensemble* e, int reps, hvpic_tuning* best, dou
    output + sort, field advance + diagnostics}. */
 int hvpic_ensemble_time_phases(hvpic_ensemble* e, int steps, double* ms);
 
+/* ------------------------------------------------- neural-operator surrogate --
+   A small convolutional neural operator that proposes the result of the
+   subcycled field advance of Sec. II.A on 2D periodic grids,
+       B^{n+1} ~ B^n + out_std * NO((B^n, n^{n+1/2}, J_i^{n+1/2}) normalised),
+   NO = four periodic 3x3 convolutions 7 -> 32 -> 32 -> 32 -> 3 with tanh
+   between them, run on the matrix cores with BF16 operands and FP32
+   accumulation, trained here on snapshots of the plain solver (MSE of the
+   normalised increment, Adam).  The plain subcycle stays the judge: a
+   proposal is used only if its residual against Faraday's law with Ohm's
+   law at the midpoint,
+       r = (B' - B^n)/dt + curl E((B^n + B')/2)   (moments held at n+1/2),
+   satisfies ||r|| <= tol ||(B' - B^n)/dt||; otherwise the plain subcycle
+   runs.  The decision is taken on the device (no host round trip).
+
+   The parameter block (hvpic_no_params_bytes, device memory of the caller)
+   holds the FP32 weights and biases, Adam's moments, the normalisation and
+   the BF16 copies the kernels read.  Logical weight layout for load/store:
+   the four layers concatenated, each [Cout][9][Cin] with tap t = 3(dy+1) +
+   (dx+1) reading x[j+dy][i+dx] (periodic), biases concatenated, and the
+   normalisation {mean[7], std[7], out_std[3]} of the input channels
+   (B_x, B_y, B_z, n, J_x, J_y, J_z) and of the increment. */
+int hvpic_no_params_bytes(size_t* bytes);
+/* Device workspace (activations) for `batch` samples of an nx x ny grid. */
+int hvpic_no_workspace_bytes(int nx, int ny, int batch, size_t* bytes);
+/* Loads weights, biases and the normalisation (device arrays in the logical
+   layout) into the block; clears Adam's state.  Enqueued on hip_stream. */
+int hvpic_no_load(void* params, const float* w, const float* b, const float* norm,
+                  void* hip_stream);
+/* Copies the block's weights and biases out in the logical layout. */
+int hvpic_no_store(const void* params, float* w, float* b, void* hip_stream);
+/* The proposal B_out [3][nx*ny] for one state (B [3][P], n [P], J [3][P]). */
+int hvpic_no_predict(const void* params, void* workspace, int nx, int ny, const float* B,
+                     const float* n, const float* J, float* B_out, void* hip_stream);
+/* One training step on the `batch` samples idx[0..batch) (device int32) of a
+   data set B [S][3][P], n [S][P], J [S][3][P], B_target [S][3][P]: forward,
+   the loss mean((d - (B_target - B)/out_std)^2) into *loss_out (device
+   double, may be NULL), backward and one Adam step of rate lr. */
+int hvpic_no_train_step(void* params, void* workspace, int nx, int ny, const float* B,
+                        const float* n, const float* J, const float* B_target, const int32_t* idx,
+                        int batch, float lr, double* loss_out, void* hip_stream);
+/* The field advance (mode 0) with the operator's proposal in place of the
+   subcycle when it passes the residual test (2D contexts without hyper-
+   resistivity or the energy equation).  Same outputs as hvpic_field_advance;
+   stats (device, may be NULL) <- {||r|| / ||rate||, 1 if accepted}.  The
+   workspace is one of hvpic_no_workspace_bytes(nx, ny, 1). */
+int hvpic_field_advance_no(hvpic_ctx* ctx, const void* params, void* workspace, float* B,
+                           const float* n_half, const float* J_half, const float* n_prev,
+                           const float* J_prev, float* E_out, double* diag_out, float tol,
+                           double* stats);
+/* One periodic 3x3 layer of the operator's kernels on nimg images (x: BF16
+   [N][cinp], w: BF16 [coutp][9][cinp], bias FP32 [coutp]): mode 0 out = BF16
+   tanh(conv + bias), 1 out = FP32 conv + bias, 2 out = BF16 conv * (1 - h^2)
+   with h BF16 [N][coutp] (no bias).  (cinp, coutp, mode) in {(16,32,0),
+   (32,32,0), (32,16,1), (16,32,2), (32,32,2)}. */
+int hvpic_no_conv3x3(int nimg, int nx, int ny, int cinp, int coutp, int mode, const void* x,
+                     const void* w, const float* bias, const void* h, void* out,
+                     void* hip_stream);
+/* Its weight gradient, added to dw [coutp][9][cinp] and db [coutp] (FP32):
+   dw[o][t][c] += sum_p dz[p][o] x[p + off(t)][c], db[o] += sum_p dz[p][o].
+   (cinp, coutp) in {(32,16), (32,32), (16,32)}; workspace as for a batch of
+   nimg. */
+int hvpic_no_conv3x3_wgrad(int nimg, int nx, int ny, int cinp, int coutp, const void* x,
+                           const void* dz, float* dw, float* db, void* workspace,
+                           void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -161,6 +161,7 @@ struct SubFinal {
   float* Bfin;
   double* part;
   Status* st;
+  const uint32_t* skip;  // non-null: the launch does nothing when *skip is set
 };
 
 template <int TX, int TY, int K, bool HAS_LIN, bool FINAL>
@@ -168,6 +169,7 @@ __device__ __forceinline__ void field_sub2d_body(
     const float* __restrict__ Bin, const float* __restrict__ Lin, float* __restrict__ Bout,
     float* __restrict__ Lout, const float* __restrict__ nm, const float* __restrict__ Jm, float h,
     float eta, const FGeo& g, const Eos& eos, const SubFinal& F, int bx, int by, int slot) {
+  if (F.skip && *F.skip) return;  // uniform: the surrogate's proposal was accepted
   using L = SubLds<TX, TY, K, FINAL>;
   using PB = typename L::PB;
   using PA = typename L::PA;
@@ -718,7 +720,140 @@ int field_impl(hvpic_ctx* c, float* B, const float* n_half, const float* J_half,
   return hipGetLastError() == hipSuccess ? HVPIC_OK : HVPIC_EHIP;
 }
 
+// Surrogate check: per-block FP64 partials of sum |Bno - T|^2 and
+// sum |Bno - B|^2, where T = B - dt curl E((B + Bno)/2) (so that
+// (Bno - T)/dt is the residual r and (Bno - B)/dt the proposed rate).
+__global__ __launch_bounds__(kBlock) void k_no_resid(const float* __restrict__ Bno,
+                                                     const float* __restrict__ T,
+                                                     const float* __restrict__ B, int ncell,
+                                                     double* part) {
+  const int c = blockIdx.x * kBlock + threadIdx.x;
+  double v[2] = {0.0, 0.0};
+  if (c < ncell)
+    for (int a = 0; a < 3; ++a) {
+      const int q = a * ncell + c;
+      const double r = (double)Bno[q] - (double)T[q], d = (double)Bno[q] - (double)B[q];
+      v[0] += r * r;
+      v[1] += d * d;
+    }
+  block_partial<2, kFieldPartStride>(v, part);
+}
+
+// The decision: accepted when ||r|| <= tol ||rate|| (finite, nonzero rate).
+__global__ __launch_bounds__(1024) void k_no_decide(const double* part, int nblocks, float tol,
+                                                    Status* st, double* stats) {
+  double r[2];
+  sum_partials<2, kFieldPartStride>(part, nblocks, r);
+  if (threadIdx.x == 0) {
+    const double ratio = r[1] > 0.0 ? sqrt(r[0] / r[1]) : INFINITY;
+    const bool ok = isfinite(ratio) && ratio <= (double)tol;
+    st->no_accept = ok ? 1u : 0u;
+    if (stats) {
+      stats[0] = ratio;
+      stats[1] = ok ? 1.0 : 0.0;
+    }
+  }
+}
+
+__global__ void k_mid(const float* __restrict__ a, const float* __restrict__ b,
+                      float* __restrict__ m, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) m[i] = 0.5f * (a[i] + b[i]);
+}
+
+// The accepted proposal becomes the subcycle's result (hi = Bno, lo = 0).
+__global__ void k_no_take(const float* __restrict__ Bno, float* __restrict__ hi,
+                          float* __restrict__ lo, int64_t n, const Status* st) {
+  if (!st->no_accept) return;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    hi[i] = Bno[i];
+    lo[i] = 0.0f;
+  }
+}
+
 }  // namespace
+
+int launch_field_advance_no(hvpic_ctx* c, float* B, const float* n_half, const float* J_half,
+                            const float* n_prev, const float* J_prev, float* E_out,
+                            double* diag_out, const float* Bno, float tol, double* stats) {
+  const FGeo g = fgeo(c);
+  const int nc = c->ncell;
+  const dim3 grid((unsigned)ceil_div(nc, kBlock)), blk(kBlock);
+  hipStream_t s = c->stream;
+  const Eos eos = make_eos(c);
+  const float eta = (float)c->p.eta;
+  Aux aux;
+  aux.inv = c->fscratch;
+  aux.u = c->fscratch + nc;
+  aux.gp = c->fscratch + 4ll * nc;
+  float* Xh = c->fscratch + 7ll * nc;
+  float* Xl = c->fscratch + 10ll * nc;
+  float* Yh = c->fscratch + 13ll * nc;
+  float* Yl = c->fscratch + 16ll * nc;
+  float* Bmid = c->fscratch + 19ll * nc;
+  float* T = Yl;  // consumed before the fallback's second launch writes Y
+  const int64_t n3 = 3ll * nc;
+  const unsigned g3 = (unsigned)ceil_div(n3, kBlock);
+  // residual test of the proposal
+  hipLaunchKernelGGL(k_mid, dim3(g3), blk, 0, s, (const float*)B, Bno, Bmid, n3);
+  hipLaunchKernelGGL((k_field_prep<2>), grid, blk, 0, s, n_half, (const float*)nullptr, J_half,
+                     (const float*)nullptr, 1.0f, 0.0f, g, eos.nfloor, eos.te_n0, eos.n0, eos.gam,
+                     eos.iso, aux);
+  hipLaunchKernelGGL((k_field_stage<2>), grid, blk, 0, s, (const float*)Bmid, (const float*)B, T,
+                     (float*)nullptr, (float)c->p.dt, eta, g, aux);
+  hipLaunchKernelGGL(k_no_resid, grid, blk, 0, s, Bno, (const float*)T, (const float*)B, nc,
+                     c->field_part);
+  hipLaunchKernelGGL(k_no_decide, dim3(1), dim3(1024), 0, s, (const double*)c->field_part,
+                     (int)grid.x, tol, c->status, stats);
+  // the plain subcycle, skipped by its kernels when the proposal was accepted
+  const float h = (float)(c->p.dt / c->p.nsub);
+  const dim3 tiles((unsigned)ceil_div(c->p.nx, kTX), (unsigned)ceil_div(c->p.ny, kTY));
+  const size_t lds2 = sizeof(float) * SubLds<kTX, kTY, 2, false>::TOTAL,
+               lds1 = sizeof(float) * SubLds<kTX, kTY, 1, false>::TOTAL;
+  SubFinal guard{};
+  guard.skip = &c->status->no_accept;
+  const float* sh = B;
+  const float* sl = nullptr;
+  float* dh = Xh;
+  float* dl = Xl;
+  for (int m = 0; m < c->p.nsub;) {
+    const bool two = c->p.nsub - m >= 2;
+    if (two && sl)
+      hipLaunchKernelGGL((k_field_sub2d<2, true, false>), tiles, dim3(kSubBlock), lds2, s, sh, sl,
+                         dh, dl, n_half, J_half, h, eta, g, eos, guard);
+    else if (two)
+      hipLaunchKernelGGL((k_field_sub2d<2, false, false>), tiles, dim3(kSubBlock), lds2, s, sh, sl,
+                         dh, dl, n_half, J_half, h, eta, g, eos, guard);
+    else if (sl)
+      hipLaunchKernelGGL((k_field_sub2d<1, true, false>), tiles, dim3(kSubBlock), lds1, s, sh, sl,
+                         dh, dl, n_half, J_half, h, eta, g, eos, guard);
+    else
+      hipLaunchKernelGGL((k_field_sub2d<1, false, false>), tiles, dim3(kSubBlock), lds1, s, sh,
+                         sl, dh, dl, n_half, J_half, h, eta, g, eos, guard);
+    m += two ? 2 : 1;
+    sh = dh;
+    sl = dl;
+    dh = dh == Xh ? Yh : Xh;
+    dl = dl == Xl ? Yl : Xl;
+  }
+  float* fh = const_cast<float*>(sh);
+  float* fl = const_cast<float*>(sl);
+  hipLaunchKernelGGL(k_no_take, dim3(g3), blk, 0, s, Bno, fh, fl, n3,
+                     (const Status*)c->status);
+  // E^{n+1}, the final B, the floor count and the diagnostics
+  hipLaunchKernelGGL((k_field_final<2, true, true>), grid, blk, 0, s, (const float*)fh,
+                     (const float*)fl, B, n_half, n_prev, J_half, J_prev, 1.5f, -0.5f, eta, g, eos,
+                     E_out, diag_out ? c->field_part : nullptr, c->status, 1);
+  if (diag_out) {
+    const double V = c->p.dx * c->p.dy * c->p.dz;
+    const double we_scale =
+        eos.iso ? V * c->p.te : V * c->p.n0 * c->p.te / (c->p.gamma_e - 1.0);
+    hipLaunchKernelGGL(k_field_diag_final, dim3(1), dim3(1024), 0, s, (const double*)c->field_part,
+                       (int)grid.x, diag_out, 0.5 * V, 1.0 / (double)nc, we_scale);
+  }
+  return hipGetLastError() == hipSuccess ? HVPIC_OK : HVPIC_EHIP;
+}
 
 // 2D tile shapes of the subcycle kernel: the plain path uses shape 0; the
 // ensemble's tuner picks one per run.

@@ -43,6 +43,10 @@ struct Status {
   // and that fell back to global loads and atomics (hvpic_path_stats)
   unsigned long long win_blocks;
   unsigned long long glob_blocks;
+  // the surrogate field advance: 1 if the last proposal passed its residual
+  // test (read by the kernels of the fallback and of the acceptance)
+  uint32_t no_accept;
+  uint32_t no_pad;
 };
 
 // One count per block of a particle kernel: whether it used the LDS windows.
@@ -213,6 +217,16 @@ int launch_field_advance_ext(hvpic_ctx* c, float* B, float* pe, const float* n_h
                              const float* J_half, const float* n_prev, const float* J_prev,
                              float* E_out, int mode, double* diag_out);
 int launch_eos_pressure(hvpic_ctx* c, const float* n, float* pe);
+// The surrogate field advance (2D, mode 0): residual test of the proposal
+// Bno, the plain subcycle as the fallback, then E, B and the diagnostics;
+// stats (device, may be null) <- {residual ratio, accepted}.
+int launch_field_advance_no(hvpic_ctx* c, float* B, const float* n_half, const float* J_half,
+                            const float* n_prev, const float* J_prev, float* E_out,
+                            double* diag_out, const float* Bno, float tol, double* stats);
+// the operator's proposal for one sample (surrogate.hip)
+size_t no_params_bytes();
+int no_predict(hipStream_t s, const void* params, void* ws, int nx, int ny, const float* B,
+               const float* n, const float* J, float* B_out);
 int launch_smooth(hvpic_ctx* c, float* F, int ncomp, int npasses);
 
 // Ensemble support: per-run argument records of the batched kernels, built on

@@ -31,6 +31,9 @@ EXPORTS = ("hvpic_workspace_bytes", "hvpic_init", "hvpic_finalize", "hvpic_set_s
            "hvpic_ensemble_finalize", "hvpic_ensemble_step", "hvpic_ensemble_steps",
            "hvpic_ensemble_capture", "hvpic_ensemble_get_tuning", "hvpic_ensemble_set_tuning",
            "hvpic_ensemble_autotune", "hvpic_ensemble_time_phases",
+           "hvpic_no_params_bytes", "hvpic_no_workspace_bytes", "hvpic_no_load", "hvpic_no_store",
+           "hvpic_no_predict", "hvpic_no_train_step", "hvpic_field_advance_no",
+           "hvpic_no_conv3x3", "hvpic_no_conv3x3_wgrad",
            "hvpic_strerror")
 KERNEL_GATHER_PUSH, KERNEL_DEPOSIT, KERNEL_SORT_SCATTER = 0, 1, 2
 
@@ -118,6 +121,17 @@ def lib():
         L.hvpic_ensemble_set_tuning.argtypes = [vp, TP]
         L.hvpic_ensemble_autotune.argtypes = [vp, i32, TP, P(ctypes.c_double)]
         L.hvpic_ensemble_time_phases.argtypes = [vp, i32, P(ctypes.c_double)]
+        L.hvpic_no_params_bytes.argtypes = [P(ctypes.c_size_t)]
+        L.hvpic_no_workspace_bytes.argtypes = [i32, i32, i32, P(ctypes.c_size_t)]
+        L.hvpic_no_load.argtypes = [vp, vp, vp, vp, vp]
+        L.hvpic_no_store.argtypes = [vp, vp, vp, vp]
+        L.hvpic_no_predict.argtypes = [vp, vp, i32, i32, vp, vp, vp, vp, vp]
+        L.hvpic_no_train_step.argtypes = [vp, vp, i32, i32, vp, vp, vp, vp, vp, i32,
+                                          ctypes.c_float, vp, vp]
+        L.hvpic_field_advance_no.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp,
+                                             ctypes.c_float, vp]
+        L.hvpic_no_conv3x3.argtypes = [i32, i32, i32, i32, i32, i32, vp, vp, vp, vp, vp, vp]
+        L.hvpic_no_conv3x3_wgrad.argtypes = [i32, i32, i32, i32, i32, vp, vp, vp, vp, vp, vp]
         L.hvpic_strerror.argtypes = [ctypes.c_int]
         L.hvpic_strerror.restype = ctypes.c_char_p
         for f in EXPORTS[:-1]:
@@ -440,6 +454,81 @@ def hvpic_ensemble_time_phases(e, steps: int):
     ms = (ctypes.c_double * 3)()
     _check(lib().hvpic_ensemble_time_phases(e, int(steps), ms), "hvpic_ensemble_time_phases")
     return tuple(ms)
+
+
+def _stream(stream):
+    return (stream if stream is not None else torch.cuda.current_stream()).cuda_stream
+
+
+def hvpic_no_params_bytes() -> int:
+    n = ctypes.c_size_t(0)
+    _check(lib().hvpic_no_params_bytes(ctypes.byref(n)), "hvpic_no_params_bytes")
+    return n.value
+
+
+def hvpic_no_workspace_bytes(nx: int, ny: int, batch: int) -> int:
+    n = ctypes.c_size_t(0)
+    _check(lib().hvpic_no_workspace_bytes(nx, ny, batch, ctypes.byref(n)),
+           "hvpic_no_workspace_bytes")
+    return n.value
+
+
+def hvpic_no_load(params, w, b, norm, stream=None):
+    _check(lib().hvpic_no_load(_ptr(params, torch.uint8), _ptr(w, torch.float32),
+                               _ptr(b, torch.float32), _ptr(norm, torch.float32),
+                               _stream(stream)), "hvpic_no_load")
+
+
+def hvpic_no_store(params, w, b, stream=None):
+    _check(lib().hvpic_no_store(_ptr(params, torch.uint8), _ptr(w, torch.float32),
+                                _ptr(b, torch.float32), _stream(stream)), "hvpic_no_store")
+
+
+def hvpic_no_predict(params, workspace, nx, ny, B, n, J, B_out, stream=None):
+    P = nx * ny
+    _check(lib().hvpic_no_predict(_ptr(params, torch.uint8), _ptr(workspace, torch.uint8), nx, ny,
+                                  _ptr(B, torch.float32, 3 * P), _ptr(n, torch.float32, P),
+                                  _ptr(J, torch.float32, 3 * P), _ptr(B_out, torch.float32, 3 * P),
+                                  _stream(stream)), "hvpic_no_predict")
+
+
+def hvpic_no_train_step(params, workspace, nx, ny, B, n, J, B_target, idx, lr, loss_out=None,
+                        stream=None):
+    batch = int(idx.numel())
+    _check(lib().hvpic_no_train_step(_ptr(params, torch.uint8), _ptr(workspace, torch.uint8), nx,
+                                     ny, _ptr(B, torch.float32), _ptr(n, torch.float32),
+                                     _ptr(J, torch.float32), _ptr(B_target, torch.float32),
+                                     _ptr(idx, torch.int32), batch, float(lr),
+                                     _ptr(loss_out, torch.float64, 1), _stream(stream)),
+           "hvpic_no_train_step")
+
+
+def hvpic_field_advance_no(ctx, params, workspace, B, n_half, J_half, n_prev, J_prev, E_out,
+                           tol, diag_out=None, stats=None):
+    v1, v3 = _nc(ctx), _nc(ctx, 3)
+    _check(lib().hvpic_field_advance_no(ctx, _ptr(params, torch.uint8),
+                                        _ptr(workspace, torch.uint8), _ptr(B, torch.float32, v3),
+                                        _ptr(n_half, torch.float32, v1),
+                                        _ptr(J_half, torch.float32, v3),
+                                        _ptr(n_prev, torch.float32, v1),
+                                        _ptr(J_prev, torch.float32, v3),
+                                        _ptr(E_out, torch.float32, v3),
+                                        _ptr(diag_out, torch.float64, 3), float(tol),
+                                        _ptr(stats, torch.float64, 2)),
+           "hvpic_field_advance_no")
+
+
+def hvpic_no_conv3x3(nimg, nx, ny, cinp, coutp, mode, x, w, bias, h, out, stream=None):
+    _check(lib().hvpic_no_conv3x3(nimg, nx, ny, cinp, coutp, mode, _ptr(x), _ptr(w),
+                                  _ptr(bias, torch.float32), _ptr(h), _ptr(out), _stream(stream)),
+           "hvpic_no_conv3x3")
+
+
+def hvpic_no_conv3x3_wgrad(nimg, nx, ny, cinp, coutp, x, dz, dw, db, workspace, stream=None):
+    _check(lib().hvpic_no_conv3x3_wgrad(nimg, nx, ny, cinp, coutp, _ptr(x), _ptr(dz),
+                                        _ptr(dw, torch.float32), _ptr(db, torch.float32),
+                                        _ptr(workspace, torch.uint8), _stream(stream)),
+           "hvpic_no_conv3x3_wgrad")
 
 
 class Context:

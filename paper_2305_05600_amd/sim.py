@@ -157,6 +157,9 @@ class GpuSim:
             self.E_s = torch.zeros((3, nc), **f32)
             self.B_s = torch.zeros((3, nc), **f32)
         self.diagnostics = diagnostics
+        self.surrogate = None  # (Surrogate, tol): the field advance by the operator
+        self.no_stats = None   # per step {residual ratio, accepted} of the surrogate
+        self.record = None     # (B, n, J, B_target, k): snapshots of the field advance
         self.push_diag = torch.zeros(4, dtype=torch.float64, device=device)
         self.field_diag = torch.zeros(3, dtype=torch.float64, device=device)
         self.ev_push = StreamEvent()  # the push of the step is done (the sort may start)
@@ -189,7 +192,19 @@ class GpuSim:
             H.hvpic_smooth(cf, n_half, cfg.nsmooth)
             H.hvpic_smooth(cf, J_half, cfg.nsmooth)
         diag = self.field_diag if self.diagnostics else None
-        if cfg.energy_eq:
+        if mode == 0 and self.record is not None:
+            Bs, ns, Js, Bts, k = self.record
+            with torch.cuda.stream(self.s_p):
+                Bs[k].copy_(self.B)
+                ns[k].copy_(n_half)
+                Js[k].copy_(J_half)
+        if mode == 0 and self.surrogate is not None:
+            surr, tol = self.surrogate
+            k = self.nstep % self.no_stats.shape[0]
+            H.hvpic_field_advance_no(cf, surr.params, surr.ws_one, self.B, n_half, J_half,
+                                     self.n_prev, self.J_prev, self.E, tol, diag_out=diag,
+                                     stats=self.no_stats[k])
+        elif cfg.energy_eq:
             if mode == 1:  # the start: the pressure of the EOS of the first moments
                 H.hvpic_eos_pressure(cf, n_half, self.pe)
             H.hvpic_field_advance_pe(cf, self.B, self.pe, n_half, J_half,
@@ -202,6 +217,11 @@ class GpuSim:
         else:
             H.hvpic_field_advance(cf, self.B, n_half, J_half, self.n_prev, self.J_prev, self.E,
                                   mode=0, diag_out=diag)
+        if mode == 0 and self.record is not None:
+            Bs, ns, Js, Bts, k = self.record
+            with torch.cuda.stream(self.s_p):
+                Bts[k].copy_(self.B)
+            self.record = None
 
     def _sort(self):
         """The neighbour-move sort of the pushed store: the gather map over q
@@ -400,4 +420,65 @@ class Ensemble:
             self.close()
         except Exception:
             pass
+
+
+class Surrogate:
+    """The convolutional neural operator of the field subcycle on one 2D grid
+    (hvpic_no_*): its parameter block, a training workspace for `batch`
+    samples and an inference workspace, in device memory.  Weights are lists
+    of (W [Cout][9][Cin], b [Cout]) per layer; norm = (mean[7], std[7],
+    out_std[3])."""
+
+    LAYERS = ((7, 32), (32, 32), (32, 32), (32, 3))
+
+    def __init__(self, nx: int, ny: int, batch: int = 8, device="cuda"):
+        self.nx, self.ny, self.batch = nx, ny, batch
+        self.device = device
+        self.params = torch.zeros(H.hvpic_no_params_bytes(), dtype=torch.uint8, device=device)
+        self.ws_train = torch.empty(H.hvpic_no_workspace_bytes(nx, ny, batch), dtype=torch.uint8,
+                                    device=device)
+        self.ws_one = torch.empty(H.hvpic_no_workspace_bytes(nx, ny, 1), dtype=torch.uint8,
+                                  device=device)
+
+    def load(self, weights, norm):
+        w = np.concatenate([np.asarray(wl, np.float32).ravel() for wl, _ in weights])
+        b = np.concatenate([np.asarray(bl, np.float32).ravel() for _, bl in weights])
+        nm = np.concatenate([np.asarray(a, np.float32).ravel() for a in norm])
+        dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(self.device)
+        H.hvpic_no_load(self.params, dev(w), dev(b), dev(nm))
+        torch.cuda.current_stream(self.device).synchronize()
+
+    def weights(self):
+        nw = sum(o * 9 * i for i, o in self.LAYERS)
+        nb = sum(o for _, o in self.LAYERS)
+        w = torch.zeros(nw, dtype=torch.float32, device=self.device)
+        b = torch.zeros(nb, dtype=torch.float32, device=self.device)
+        H.hvpic_no_store(self.params, w, b)
+        w, b = w.cpu().numpy(), b.cpu().numpy()
+        out, ow, ob = [], 0, 0
+        for i, o in self.LAYERS:
+            out.append((w[ow:ow + o * 9 * i].reshape(o, 9, i).astype(np.float64),
+                        b[ob:ob + o].astype(np.float64)))
+            ow += o * 9 * i
+            ob += o
+        return out
+
+    def predict(self, B, n, J):
+        out = torch.empty_like(B)
+        H.hvpic_no_predict(self.params, self.ws_one, self.nx, self.ny, B, n, J, out)
+        return out
+
+    def train(self, data, steps: int, lr: float, seed: int = 0):
+        """`steps` Adam steps on random batches of the snapshots data = (B, n,
+        J, B_target) (device tensors [S][...]); returns the loss per step."""
+        B, n, J, Bt = data
+        S = B.shape[0]
+        rng = np.random.Generator(np.random.PCG64(seed))
+        idx = torch.from_numpy(np.stack([rng.choice(S, self.batch, replace=False)
+                                         for _ in range(steps)]).astype(np.int32)).to(self.device)
+        losses = torch.zeros(steps, dtype=torch.float64, device=self.device)
+        for k in range(steps):
+            H.hvpic_no_train_step(self.params, self.ws_train, self.nx, self.ny, B, n, J, Bt,
+                                  idx[k], lr, losses[k:k + 1])
+        return losses
 
