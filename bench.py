@@ -6,7 +6,9 @@ shape, 10 B-subcycles, FP32 particles and fields (seeded synthetic inputs).
 --workload beam3d: the 3D periodic core + beam box, 128^3 cells, 64 ions per
 cell (134,217,728 particles), QS shape, 4 B-subcycles.  --workload ensemble:
 64 independent 2D periodic runs of uneven size stepped together (see
-bench_ensemble).  One step = gather +
+bench_ensemble).  --workload surrogate: the Harris workload with the field
+subcycle replaced by the trained neural operator where its proposal passes
+the residual test (see bench_surrogate).  One step = gather +
 push + fused mid-point deposit, neighbour-move sort, field advance (Ohm + RK2
 Faraday subcycle + extrapolation), FP64 diagnostics.
 
@@ -276,10 +278,148 @@ def bench_ensemble(args) -> dict:
     return out
 
 
+def bench_surrogate(args) -> dict:
+    """The Harris workload with the field subcycle replaced by the neural
+    operator where its proposal passes the residual test (tolerance
+    --no-tol, 1e-2 by default): snapshots of the plain run, training on them
+    (time-budgeted), then timed steps with the surrogate against plain
+    steps of the same run.  The plain subcycle is the fallback and the judge
+    of the error: the increment error of the proposals on held-out
+    snapshots is reported, and so is the residual ratio of the plain
+    subcycle's own result under the same test (the oracle's Ohm's law and
+    curl, FP64)."""
+    import numpy as np
+    import torch
+
+    from paper_2305_05600_amd import sim as S
+    from paper_2305_05600_amd import workloads as W
+
+    cfg, parts, B = W.harris_double()
+    n = int(parts["cell"].size)
+    P = cfg.ncell
+    g = S.GpuSim(cfg, parts, B, fused=True, gather_map=True)
+    del parts
+    for _ in range(args.warmup):
+        g.step(order_caller=False)
+    # plain step time
+    g.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        g.step(order_caller=False)
+    g.synchronize()
+    plain_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    # snapshots of the field advance: (B^n, n^{n+1/2}, J^{n+1/2}) -> B^{n+1}
+    S_tot = args.snapshots
+    f32 = dict(dtype=torch.float32, device="cuda")
+    data = (torch.empty((S_tot, 3, P), **f32), torch.empty((S_tot, P), **f32),
+            torch.empty((S_tot, 3, P), **f32), torch.empty((S_tot, 3, P), **f32))
+    for k in range(S_tot):
+        g.record = data + (k,)
+        g.step(order_caller=False)
+    g.synchronize()
+    print(f"# {S_tot} snapshots; plain step {plain_ms:.3f} ms", file=sys.stderr, flush=True)
+    n_train = int(0.9 * S_tot)
+    # normalisation from a subset of the training snapshots (host, FP64)
+    sub = np.linspace(0, n_train - 1, 20).astype(int)
+    Bh = data[0][sub].double().cpu().numpy()
+    nh = data[1][sub].double().cpu().numpy()
+    Jh = data[2][sub].double().cpu().numpy()
+    dB = (data[3][sub].double() - data[0][sub].double()).cpu().numpy()
+    chans = [Bh[:, 0], Bh[:, 1], Bh[:, 2], nh, Jh[:, 0], Jh[:, 1], Jh[:, 2]]
+    norm = (np.array([c.mean() for c in chans]), np.array([max(c.std(), 1e-6) for c in chans]),
+            np.array([max(dB[:, c].std(), 1e-12) for c in range(3)]))
+    surr = S.Surrogate(cfg.nx, cfg.ny, batch=args.no_batch)
+    surr.load(S.Surrogate.initial_weights(args.seed), norm)
+    train = tuple(t[:n_train] for t in data)
+    losses, steps_done = [], 0
+    t0 = time.perf_counter()
+    while True:
+        lr = args.no_lr * (0.3 if time.perf_counter() - t0 > 0.6 * args.train_seconds else 1.0)
+        losses.append(surr.train(train, steps=50, lr=lr, seed=steps_done))
+        steps_done += 50
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        print(f"# trained {steps_done} steps, {el:.1f} s, loss {float(losses[-1][-1]):.4e}",
+              file=sys.stderr, flush=True)
+        if el > args.train_seconds:
+            break
+    train_s = time.perf_counter() - t0
+    loss_hist = torch.cat(losses).cpu().numpy()
+    # held-out proposals against the plain subcycle
+    errs, ratios_plain = [], []
+    for k in range(n_train, S_tot, max(1, (S_tot - n_train) // 8)):
+        prop = surr.predict(data[0][k].contiguous(), data[1][k].contiguous(),
+                            data[2][k].contiguous())
+        Bt = data[3][k]
+        inc = (Bt - data[0][k]).double()
+        errs.append(float(torch.linalg.vector_norm(prop.double() - Bt.double()) /
+                          torch.linalg.vector_norm(inc)))
+        if len(ratios_plain) < 3 and not args.no_cpu_baseline:
+            # CPU leg: the FP64 oracle's residual of the plain subcycle's result
+            from oracle import no_oracle as NO
+
+            ratios_plain.append(NO.residual(cfg, data[0][k].cpu().numpy(), Bt.cpu().numpy(),
+                                            data[1][k].cpu().numpy(), data[2][k].cpu().numpy()))
+    # steps with the surrogate (the run continues from its state)
+    g.surrogate = (surr, args.no_tol)
+    g.no_stats = torch.zeros((args.steps, 2), dtype=torch.float64, device="cuda")
+    for _ in range(args.warmup):
+        g.step(order_caller=False)
+    g.synchronize()
+    g.no_stats.zero_()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        g.step(order_caller=False)
+    g.synchronize()
+    surr_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    st = g.no_stats.cpu().numpy()
+    flags, _ = g.status()
+    out = {
+        "metric": METRIC,
+        "value": n / (surr_ms * 1e-3),
+        "unit": "pushes/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": surr_ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 particles and fields; bf16 operator with f32 accumulation",
+        "data": "synthetic",
+        "config": {"workload": cfg.name + "-surrogate-subcycle", "cells": [cfg.nx, cfg.ny],
+                   "particles": n, "b_subcycles_replaced": cfg.nsub, "dt": cfg.dt,
+                   "operator": "4 periodic 3x3 conv layers 7-32-32-32-3, tanh",
+                   "snapshots": S_tot, "train_snapshots": n_train, "batch": args.no_batch,
+                   "residual_tolerance": args.no_tol},
+        "step_time_plain_ms": plain_ms,
+        "step_time_surrogate_ms": surr_ms,
+        "speedup_vs_plain": plain_ms / surr_ms,
+        "accepted_fraction": float(st[:, 1].mean()),
+        "residual_ratio": {"median": float(np.median(st[:, 0])), "min": float(st[:, 0].min()),
+                           "max": float(st[:, 0].max())},
+        "residual_ratio_of_plain_subcycle": ratios_plain,
+        "heldout_increment_rel_l2_vs_plain": {"mean": float(np.mean(errs)),
+                                              "max": float(np.max(errs))},
+        "training": {"steps": steps_done, "seconds": train_s,
+                     "loss_first": float(loss_hist[:20].mean()),
+                     "loss_last": float(loss_hist[-20:].mean())},
+        "status_flags": flags,
+    }
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=("harris", "beam3d", "ensemble"), default="harris",
+    ap.add_argument("--snapshots", type=int, default=2000, help="surrogate: training snapshots")
+    ap.add_argument("--train-seconds", type=float, default=60.0, help="surrogate: training budget")
+    ap.add_argument("--no-batch", type=int, default=8, help="surrogate: batch")
+    ap.add_argument("--no-lr", type=float, default=1e-3, help="surrogate: Adam rate")
+    ap.add_argument("--no-tol", type=float, default=1e-2, help="surrogate: residual tolerance")
+    ap.add_argument("--seed", type=int, default=7, help="surrogate: starting weights")
+    ap.add_argument("--workload", choices=("harris", "beam3d", "ensemble", "surrogate"),
+                    default="harris",
                     help="harris: 2D double Harris sheet 512x256, 13.1M ions; beam3d: 3D core + "
                          "beam 128^3, 134M ions; ensemble: 64 independent 2D runs of uneven size")
     ap.add_argument("--steps", type=int, default=200)
@@ -304,6 +444,9 @@ def main() -> int:
 
     if args.workload == "ensemble":
         print(json.dumps(bench_ensemble(args)), flush=True)
+        return 0
+    if args.workload == "surrogate":
+        print(json.dumps(bench_surrogate(args)), flush=True)
         return 0
 
     import numpy as np

@@ -440,6 +440,18 @@ class Surrogate:
         self.ws_one = torch.empty(H.hvpic_no_workspace_bytes(nx, ny, 1), dtype=torch.uint8,
                                   device=device)
 
+    @classmethod
+    def initial_weights(cls, seed: int):
+        """Seeded starting weights: uniform in +-sqrt(3/(9 Cin)) per layer
+        (unit variance of the pre-activation for unit-variance inputs), zero
+        biases."""
+        rng = np.random.Generator(np.random.PCG64(seed))
+        out = []
+        for cin, cout in cls.LAYERS:
+            lim = np.sqrt(3.0 / (9 * cin))
+            out.append((rng.uniform(-lim, lim, (cout, 9, cin)), np.zeros(cout)))
+        return out
+
     def load(self, weights, norm):
         w = np.concatenate([np.asarray(wl, np.float32).ravel() for wl, _ in weights])
         b = np.concatenate([np.asarray(bl, np.float32).ravel() for _, bl in weights])
