@@ -37,7 +37,14 @@ class OrcParams(ctypes.Structure):
         ("n_floor", ctypes.c_double),
         ("eta", ctypes.c_double), ("eta_h", ctypes.c_double),
         ("energy_eq", _i32), ("kappa0", ctypes.c_double),
+        ("open_x", _i32), ("buffer_cells", _i32), ("eta_h_buffer", ctypes.c_double),
     ]
+
+
+class OrcInflow(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_double), ("ux", ctypes.c_double), ("uy", ctypes.c_double),
+                ("uz", ctypes.c_double), ("vth", ctypes.c_double), ("ppc", _i32),
+                ("faces", _i32)]
 
 
 class OrcStatus(ctypes.Structure):
@@ -71,6 +78,23 @@ def lib():
         L.orc_pe_rate.argtypes = [P, _dp, _dp, _dp, _dp, _dp]
         L.orc_field_advance_pe.argtypes = [P, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _i32, _dp,
                                            S]
+        I = ctypes.POINTER(OrcInflow)
+        L.orc_open_fill.argtypes = [P, _dp, _i32]
+        L.orc_open_curl.argtypes = [P, _dp, _dp]
+        L.orc_open_ohm.argtypes = [P, _dp, _dp, _dp, _dp, _dp]
+        L.orc_open_field_advance.argtypes = [P, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _i32,
+                                             _dp, S]
+        L.orc_open_absorb.argtypes = [P, _i64, _ip]
+        L.orc_open_absorb.restype = _i64
+        L.orc_inflow_expected.argtypes = [P, I, _i32]
+        L.orc_inflow_expected.restype = ctypes.c_double
+        L.orc_open_inject.argtypes = [P, I, ctypes.c_uint64, _i64, _i64, _i64, _ip, _dp, _dp,
+                                      _dp, _dp, _dp, _dp]
+        L.orc_open_inject.restype = _i64
+        L.orc_uniform.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
+        L.orc_uniform.restype = ctypes.c_double
+        for f in ("orc_open_fill", "orc_open_curl", "orc_open_ohm", "orc_open_field_advance"):
+            getattr(L, f).restype = None
         for f in ("orc_gather", "orc_boris", "orc_push", "orc_sort", "orc_deposit",
                   "orc_smooth", "orc_curl", "orc_ohm", "orc_field_advance", "orc_ohm_pe",
                   "orc_pe_rate", "orc_field_advance_pe"):
@@ -83,7 +107,8 @@ def params(cfg) -> OrcParams:
     return OrcParams(cfg.ndim, cfg.nx, cfg.ny, cfg.nz, cfg.dx, cfg.dy, cfg.dz, cfg.dt,
                      cfg.nsub, cfg.shape, cfg.nsmooth, cfg.qs, cfg.ms, cfg.te,
                      cfg.gamma_e, cfg.n0, cfg.n_floor, cfg.eta, cfg.eta_h,
-                     int(cfg.energy_eq), cfg.kappa0)
+                     int(cfg.energy_eq), cfg.kappa0, int(cfg.open_x), int(cfg.buffer_cells),
+                     cfg.eta_h_buffer)
 
 
 def _d(a):
@@ -297,3 +322,114 @@ class OracleSim:
         if mode == 0:
             self.B = B
         return st
+
+
+# ------------------------------------------------------ open boundaries --
+
+def inflow(spec: dict) -> OrcInflow:
+    return OrcInflow(spec["n"], spec["ux"], spec["uy"], spec["uz"], spec["vth"], int(spec["ppc"]),
+                     int(spec.get("faces", 3)))
+
+
+def open_fill(cfg, F):
+    F = f64(F).copy()
+    ncomp = 1 if F.ndim == 1 else F.shape[0]
+    lib().orc_open_fill(ctypes.byref(params(cfg)), _d(F), ncomp)
+    return F
+
+
+def open_curl(cfg, A):
+    C = np.zeros((3, cfg.ncell))
+    lib().orc_open_curl(ctypes.byref(params(cfg)), _d(f64(A)), _d(C))
+    return C
+
+
+def open_ohm(cfg, B0, B1, n, Ji):
+    E = np.zeros((3, cfg.ncell))
+    lib().orc_open_ohm(ctypes.byref(params(cfg)), _d(f64(B0)), _d(f64(B1)), _d(f64(n)),
+                       _d(f64(Ji)), _d(E))
+    return E
+
+
+def open_field_advance(cfg, B0, B1, n_half, J_half, n_prev=None, J_prev=None, mode=0):
+    """Returns (B1_new, E_out, Btot, diag[3], status); B1 is not modified."""
+    B1 = f64(B1).copy()
+    E = np.zeros((3, cfg.ncell))
+    Bt = np.zeros((3, cfg.ncell))
+    diag = np.zeros(3)
+    st = OrcStatus()
+    n_prev = f64(n_half if n_prev is None else n_prev)
+    J_prev = f64(J_half if J_prev is None else J_prev)
+    lib().orc_open_field_advance(ctypes.byref(params(cfg)), _d(f64(B0)), _d(B1), _d(f64(n_half)),
+                                 _d(f64(J_half)), _d(n_prev), _d(J_prev), _d(E), _d(Bt),
+                                 int(mode), _d(diag), ctypes.byref(st))
+    return B1, E, Bt, diag, st
+
+
+def open_absorb(cfg, parts: dict) -> int:
+    return int(lib().orc_open_absorb(ctypes.byref(params(cfg)), parts["cell"].size,
+                                     _i(parts["cell"])))
+
+
+def inflow_expected(cfg, spec: dict, face: int) -> float:
+    return float(lib().orc_inflow_expected(ctypes.byref(params(cfg)),
+                                           ctypes.byref(inflow(spec)), int(face)))
+
+
+def uniform(seed: int, ctr: int) -> float:
+    return float(lib().orc_uniform(seed, ctr))
+
+
+def open_inject(cfg, spec: dict, seed: int, step: int, parts: dict, cap_extra: int = 1 << 20):
+    """parts with the ions injected this step appended."""
+    n = parts["cell"].size
+    cap = n + cap_extra
+    out = {k: np.concatenate([v, np.zeros(cap_extra, v.dtype)]) for k, v in parts.items()}
+    out = {k: np.ascontiguousarray(v) for k, v in out.items()}
+    m = lib().orc_open_inject(ctypes.byref(params(cfg)), ctypes.byref(inflow(spec)), seed, step,
+                              n, cap, _i(out["cell"]), _d(out["ox"]), _d(out["oy"]),
+                              _d(out["ux"]), _d(out["uy"]), _d(out["uz"]), _d(out["w"]))
+    return {k: np.ascontiguousarray(v[:m]) for k, v in out.items()}
+
+
+class OpenOracleSim:
+    """The 2D step with open x boundaries (Sec. II.C) in FP64, in the order
+    the GPU runs it: push; the mid-point deposit of the pushed store; ions
+    in the ghost columns absorbed and fresh ions injected through the faces;
+    the stable sort with the absorbed ions last (and dropped); the moments'
+    ghost columns filled; the field advance of B1 with B = B0 + B1."""
+
+    def __init__(self, cfg, parts: dict, B0, B1, spec: dict, seed: int):
+        self.cfg, self.spec, self.seed = cfg, spec, seed
+        self.p = particles64(parts)
+        perm, self.cell_start = sort(cfg, self.p["cell"])
+        self.p = apply_perm(self.p, perm)
+        self.B0 = f64(B0).copy()
+        self.B1 = open_fill(cfg, B1)
+        n0, J0 = deposit(cfg, self.p, 0.0)
+        self.n_prev, self.J_prev = open_fill(cfg, n0), open_fill(cfg, J0)
+        self.B1, self.E, self.Btot, self.field_diag, _ = open_field_advance(
+            cfg, self.B0, self.B1, self.n_prev, self.J_prev, mode=1)
+        self.nstep = 0
+        self.absorbed = self.injected = 0
+
+    def step(self):
+        cfg = self.cfg
+        self.push_diag, _ = push(cfg, self.p, self.E, self.Btot)
+        n_half, J_half = deposit(cfg, self.p, 0.5 * cfg.dt)
+        self.absorbed += open_absorb(cfg, self.p)
+        n_before = self.p["cell"].size
+        self.p = open_inject(cfg, self.spec, self.seed, self.nstep, self.p)
+        self.injected += self.p["cell"].size - n_before
+        key = self.p["cell"]
+        order = np.argsort(key, kind="stable")
+        alive = int(np.sum(key < cfg.ncell))
+        self.p = {k: np.ascontiguousarray(v[order][:alive]) for k, v in self.p.items()}
+        self.cell_start = np.concatenate([[0], np.cumsum(np.bincount(self.p["cell"],
+                                                                     minlength=cfg.ncell))])
+        self.n_half, self.J_half = open_fill(cfg, n_half), open_fill(cfg, J_half)
+        self.B1, self.E, self.Btot, self.field_diag, _ = open_field_advance(
+            cfg, self.B0, self.B1, self.n_half, self.J_half, self.n_prev, self.J_prev, mode=0)
+        self.n_prev, self.J_prev = self.n_half, self.J_half
+        self.nstep += 1
+

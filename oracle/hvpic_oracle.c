@@ -555,3 +555,282 @@ void orc_field_advance_pe(const orc_params* p, double* B, double* pe, const doub
   free(R);
   free(ps);
 }
+
+/* ------------------------------------------------------------------------
+ * Open boundaries in x (Sec. II.C), 2D.  The grid's columns 0 and nx-1 are
+ * ghost columns outside the domain.  B = B0 + B1 with B0 fixed (a vacuum
+ * field: curl B0 = 0) and only B1 advanced; the plasma current of the Hall
+ * and resistive terms is J = curl B1.  B1 and the moments in a ghost cell
+ * equal their interior neighbour; Ohm's law in a ghost cell keeps the
+ * gradients along the boundary and drops those normal to it.  A layer of
+ * buffer_cells cells at each open boundary has eta_h raised by
+ * eta_h_buffer, ramping linearly to zero inward.  Ions in a ghost column
+ * are absorbed; fresh ions enter through the faces from a drifting
+ * Maxwellian, with the flux-weighted distribution of the normal velocity.
+ * ------------------------------------------------------------------------ */
+
+static int ghost_col(const orc_params* p, int i) {
+  return p->open_x && (i == 0 || i == p->nx - 1);
+}
+
+void orc_open_fill(const orc_params* p, double* F, int32_t ncomp) {
+  if (!p->open_x) return;
+  int64_t nc = ncell_of(p);
+  for (int a = 0; a < ncomp; ++a)
+    for (int k = 0; k < p->nz; ++k)
+      for (int j = 0; j < p->ny; ++j) {
+        double* f = F + a * nc;
+        f[cell_of(p, 0, j, k)] = f[cell_of(p, 1, j, k)];
+        f[cell_of(p, p->nx - 1, j, k)] = f[cell_of(p, p->nx - 2, j, k)];
+      }
+}
+
+/* centred difference, zero along x in a ghost column */
+static double dopen(const orc_params* p, const double* Q, int a, int i, int j, int k) {
+  if (a == 0 && ghost_col(p, i)) return 0.0;
+  return dcentred(p, Q, a, i, j, k);
+}
+
+static double lap_open(const orc_params* p, const double* Q, int i, int j, int k) {
+  double r = d2(p, Q, 1, i, j, k) + d2(p, Q, 2, i, j, k);
+  if (!ghost_col(p, i)) r += d2(p, Q, 0, i, j, k);
+  return r;
+}
+
+void orc_open_curl(const orc_params* p, const double* A, double* C) {
+  int64_t nc = ncell_of(p);
+  const double *Ax = A, *Ay = A + nc, *Az = A + 2 * nc;
+  for (int64_t c = 0; c < nc; ++c) {
+    int i, j, k;
+    ijk_of(p, c, &i, &j, &k);
+    C[c] = dopen(p, Az, 1, i, j, k) - dopen(p, Ay, 2, i, j, k);
+    C[c + nc] = dopen(p, Ax, 2, i, j, k) - dopen(p, Az, 0, i, j, k);
+    C[c + 2 * nc] = dopen(p, Ay, 0, i, j, k) - dopen(p, Ax, 1, i, j, k);
+  }
+}
+
+/* eta_h at column i: the buffer adds eta_h_buffer * (1 - d/w), d the
+   column's distance in cells from the outermost interior column */
+static double eta_h_at(const orc_params* p, int i) {
+  double e = p->eta_h;
+  if (p->open_x && p->buffer_cells > 0) {
+    int d = i < p->nx - 1 - i ? i : p->nx - 1 - i;  /* ghost: 0, first interior: 1 */
+    d = d > 0 ? d - 1 : 0;
+    if (d < p->buffer_cells) e += p->eta_h_buffer * (1.0 - (double)d / p->buffer_cells);
+  }
+  return e;
+}
+
+void orc_open_ohm(const orc_params* p, const double* B0, const double* B1, const double* n,
+                  const double* Ji, double* E) {
+  int64_t nc = ncell_of(p);
+  double* J = (double*)malloc(sizeof(double) * 3 * (size_t)nc);
+  double* pe = (double*)malloc(sizeof(double) * (size_t)nc);
+  orc_open_curl(p, B1, J);
+  eos_pressure(p, n, pe);
+  for (int64_t c = 0; c < nc; ++c) {
+    int i, j, k;
+    ijk_of(p, c, &i, &j, &k);
+    double ne = n[c] > p->n_floor ? n[c] : p->n_floor;
+    double b[3] = {B0[c] + B1[c], B0[c + nc] + B1[c + nc], B0[c + 2 * nc] + B1[c + 2 * nc]};
+    double jt[3] = {J[c], J[c + nc], J[c + 2 * nc]};
+    double ui[3] = {Ji[c] / ne, Ji[c + nc] / ne, Ji[c + 2 * nc] / ne};
+    double gp[3] = {dopen(p, pe, 0, i, j, k), dopen(p, pe, 1, i, j, k), dopen(p, pe, 2, i, j, k)};
+    double uxb[3] = {ui[1] * b[2] - ui[2] * b[1], ui[2] * b[0] - ui[0] * b[2],
+                     ui[0] * b[1] - ui[1] * b[0]};
+    double jxb[3] = {jt[1] * b[2] - jt[2] * b[1], jt[2] * b[0] - jt[0] * b[2],
+                     jt[0] * b[1] - jt[1] * b[0]};
+    double eh = eta_h_at(p, i);
+    for (int a = 0; a < 3; ++a) {
+      double hyper = eh != 0.0 ? eh * lap_open(p, J + a * nc, i, j, k) : 0.0;
+      E[c + a * nc] = -gp[a] / ne - uxb[a] + jxb[a] / ne + p->eta * jt[a] - hyper;
+    }
+  }
+  free(J);
+  free(pe);
+}
+
+/* W_B, W_dB of the total B and W_e over the interior cells */
+static void open_energy(const orc_params* p, const double* B, const double* n, double diag[3]) {
+  int64_t nc = ncell_of(p);
+  double V = cell_volume(p), wb = 0.0, we = 0.0, sum[3] = {0.0, 0.0, 0.0};
+  int64_t cnt = 0;
+  for (int64_t c = 0; c < nc; ++c) {
+    int i, j, k;
+    ijk_of(p, c, &i, &j, &k);
+    if (ghost_col(p, i)) continue;
+    ++cnt;
+    for (int a = 0; a < 3; ++a) {
+      wb += 0.5 * B[c + a * nc] * B[c + a * nc] * V;
+      sum[a] += B[c + a * nc];
+    }
+    double ne = n[c] > p->n_floor ? n[c] : p->n_floor;
+    if (p->gamma_e == 1.0)
+      we += p->te * ne * log(ne / p->n0) * V;
+    else
+      we += p->n0 * p->te * pow(ne / p->n0, p->gamma_e) * V / (p->gamma_e - 1.0);
+  }
+  double m2 = sum[0] * sum[0] + sum[1] * sum[1] + sum[2] * sum[2];
+  diag[0] = wb;
+  diag[1] = wb - 0.5 * V * m2 / (double)cnt;
+  diag[2] = we;
+}
+
+void orc_open_field_advance(const orc_params* p, const double* B0, double* B1,
+                            const double* n_half, const double* J_half, const double* n_prev,
+                            const double* J_prev, double* E_out, double* Btot, int32_t mode,
+                            double diag[3], orc_status* st) {
+  int64_t nc = ncell_of(p);
+  if (st)
+    for (int64_t c = 0; c < nc; ++c)
+      if (n_half[c] < p->n_floor) st->floor_hits += 1;
+  size_t v3 = sizeof(double) * 3 * (size_t)nc;
+  double* n1 = (double*)malloc(sizeof(double) * (size_t)nc);
+  double* J1 = (double*)malloc(v3);
+  if (mode == 0) {
+    double* Ea = (double*)malloc(v3);
+    double* C = (double*)malloc(v3);
+    double* Bs = (double*)malloc(v3);
+    double h = p->dt / p->nsub;
+    orc_open_fill(p, B1, 3);
+    for (int m = 0; m < p->nsub; ++m) {
+      orc_open_ohm(p, B0, B1, n_half, J_half, Ea);
+      orc_open_curl(p, Ea, C);
+      for (int64_t c = 0; c < 3 * nc; ++c) Bs[c] = B1[c] - 0.5 * h * C[c];
+      orc_open_fill(p, Bs, 3);
+      orc_open_ohm(p, B0, Bs, n_half, J_half, Ea);
+      orc_open_curl(p, Ea, C);
+      for (int64_t c = 0; c < 3 * nc; ++c) B1[c] = B1[c] - h * C[c];
+      orc_open_fill(p, B1, 3);
+    }
+    for (int64_t c = 0; c < nc; ++c) n1[c] = 1.5 * n_half[c] - 0.5 * n_prev[c];
+    for (int64_t c = 0; c < 3 * nc; ++c) J1[c] = 1.5 * J_half[c] - 0.5 * J_prev[c];
+    free(Ea);
+    free(C);
+    free(Bs);
+  } else {
+    for (int64_t c = 0; c < nc; ++c) n1[c] = n_half[c];
+    for (int64_t c = 0; c < 3 * nc; ++c) J1[c] = J_half[c];
+  }
+  orc_open_ohm(p, B0, B1, n1, J1, E_out);
+  for (int64_t c = 0; c < 3 * nc; ++c) Btot[c] = B0[c] + B1[c];
+  if (diag) open_energy(p, Btot, n1, diag);
+  free(n1);
+  free(J1);
+}
+
+int64_t orc_open_absorb(const orc_params* p, int64_t np, int32_t* cell) {
+  int64_t nc = ncell_of(p), k = 0;
+  for (int64_t q = 0; q < np; ++q) {
+    int i, j, kk;
+    ijk_of(p, cell[q], &i, &j, &kk);
+    if (ghost_col(p, i)) {
+      cell[q] = (int32_t)nc;
+      ++k;
+    }
+  }
+  return k;
+}
+
+/* splitmix64's finaliser (Steele, Lea & Flood 2014) */
+static uint64_t mix64(uint64_t z) {
+  z += 0x9e3779b97f4a7c15ull;
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+double orc_uniform(uint64_t seed, uint64_t ctr) {
+  return (double)(mix64(seed + mix64(ctr)) >> 11) * (1.0 / 9007199254740992.0);
+}
+
+/* counter of draw d of ion m of row j of face f at a step */
+static uint64_t draw_ctr(int64_t step, int f, int j, int64_t m, int d) {
+  return ((((uint64_t)step * 2u + (uint64_t)f) << 16 | (uint64_t)j) << 20 | (uint64_t)m) << 7 |
+         (uint64_t)d;
+}
+
+/* a standard normal from draws d and d+1 (Box-Muller) */
+static double normal_draw(uint64_t seed, int64_t step, int f, int j, int64_t m, int d) {
+  double u1 = orc_uniform(seed, draw_ctr(step, f, j, m, d));
+  double u2 = orc_uniform(seed, draw_ctr(step, f, j, m, d + 1));
+  return sqrt(-2.0 * log(1.0 - u1)) * cos(6.283185307179586 * u2);
+}
+
+/* flux per unit density into the domain of a drifting Maxwellian with
+   normal drift u (into the domain) and thermal speed vth:
+   integral over v > 0 of v f(v) dv */
+static double inflow_flux(double u, double vth) {
+  return vth / sqrt(2.0 * 3.141592653589793) * exp(-0.5 * u * u / (vth * vth)) +
+         0.5 * u * (1.0 + erf(u / (sqrt(2.0) * vth)));
+}
+
+/* integral over 0 < t < v of t exp(-(t-u)^2 / (2 vth^2)) dt, in closed form:
+   with x = (t-u)/(sqrt(2) vth) it is
+   vth u sqrt(pi/2) [erf(x1) - erf(x0)] + vth^2 [exp(-x0^2) - exp(-x1^2)] */
+static double flux_integral(double u, double vth, double v) {
+  double x0 = -u / (sqrt(2.0) * vth), x1 = (v - u) / (sqrt(2.0) * vth);
+  return vth * u * sqrt(0.5 * 3.141592653589793) * (erf(x1) - erf(x0)) +
+         vth * vth * (exp(-x0 * x0) - exp(-x1 * x1));
+}
+
+/* the speed v > 0 at which the distribution function of v exp(-(v-u)^2 /
+   (2 vth^2)) reaches U: 60 bisection steps on [0, max(u, 0) + 10 vth] */
+static double inflow_speed(double u, double vth, double U) {
+  double lo = 0.0, hi = (u > 0.0 ? u : 0.0) + 10.0 * vth;
+  double target = U * flux_integral(u, vth, hi);
+  for (int it = 0; it < 60; ++it) {
+    double mid = 0.5 * (lo + hi);
+    if (flux_integral(u, vth, mid) < target)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+double orc_inflow_expected(const orc_params* p, const orc_inflow* in, int32_t face) {
+  double un = face == 0 ? in->ux : -in->ux;
+  /* n F dt dy dz ions of weight n dx dy dz / ppc */
+  return in->ppc * p->dt / p->dx * inflow_flux(un, in->vth);
+}
+
+int64_t orc_open_inject(const orc_params* p, const orc_inflow* in, uint64_t seed, int64_t step,
+                        int64_t np, int64_t cap, int32_t* cell, double* ox, double* oy,
+                        double* ux, double* uy, double* uz, double* w) {
+  double wb = in->n * p->dx * p->dy * p->dz / in->ppc;
+  for (int f = 0; f < 2; ++f) {
+    if (!((in->faces >> f) & 1)) continue;
+    double un = f == 0 ? in->ux : -in->ux;
+    double nexp = orc_inflow_expected(p, in, f);
+    int col = f == 0 ? 1 : p->nx - 2;
+    for (int j = 0; j < p->ny; ++j) {
+      int64_t k = (int64_t)floor(nexp + orc_uniform(seed, draw_ctr(step, f, j, 0, 127)));
+      for (int64_t m = 0; m < k && np < cap; ++m) {
+        /* normal speed: drifting Maxwellian weighted by v (v > 0), by
+           inverting its distribution function at a uniform draw */
+        double v = inflow_speed(un, in->vth, orc_uniform(seed, draw_ctr(step, f, j, m, 0)));
+        double vy = in->uy + in->vth * normal_draw(seed, step, f, j, m, 96);
+        double vz = in->uz + in->vth * normal_draw(seed, step, f, j, m, 98);
+        /* entered at a uniform time within the step: depth v dt tau */
+        double s = v * p->dt * orc_uniform(seed, draw_ctr(step, f, j, m, 100));
+        double o = -1.0 + 2.0 * s / p->dx;
+        if (o >= 1.0) o = 1.0 - 1e-7;
+        /* the store holds FP32 values: the injected ion is what FP32 keeps */
+        double xo = f == 0 ? o : -o;
+        if (xo >= 1.0) xo = 1.0 - 1e-7;
+        cell[np] = (int32_t)cell_of(p, col, j, 0);
+        ox[np] = (double)(float)xo;
+        if (ox[np] >= 1.0) ox[np] = (double)nextafterf(1.0f, 0.0f);
+        oy[np] = (double)(float)(-1.0 + 2.0 * orc_uniform(seed, draw_ctr(step, f, j, m, 101)));
+        if (oy[np] >= 1.0) oy[np] = (double)nextafterf(1.0f, 0.0f);
+        ux[np] = (double)(float)(f == 0 ? v : -v);
+        uy[np] = (double)(float)vy;
+        uz[np] = (double)(float)vz;
+        w[np] = (double)(float)wb;
+        ++np;
+      }
+    }
+  }
+  return np;
+}

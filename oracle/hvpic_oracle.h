@@ -41,7 +41,20 @@ typedef struct {
   double eta_h;                    /* hyper-resistivity                    */
   int32_t energy_eq;               /* 1: p_e evolved by the energy equation */
   double kappa0;                   /* heat conductivity in Q_e = -kappa0 grad T_e */
+  int32_t open_x;                  /* 1: x boundaries open (2D): columns 0 and
+                                      nx-1 are ghost columns                 */
+  int32_t buffer_cells;            /* width of the enhanced eta_h layer        */
+  double eta_h_buffer;             /* eta_h added at the open boundary (ramp)  */
 } orc_params;
+
+/* Plasma injected through the open faces (Sec. II.C): density, drift and
+   per-component thermal speed; ppc particles per cell at that density; faces
+   bit 0 = x-min face, bit 1 = x-max face. */
+typedef struct {
+  double n, ux, uy, uz, vth;
+  int32_t ppc;
+  int32_t faces;
+} orc_inflow;
 
 typedef struct {
   int64_t moved_gt1;  /* particles whose move crossed more than one cell face */
@@ -117,6 +130,45 @@ void orc_field_advance(const orc_params* p, double* B, const double* n_half,
                        const double* J_half, const double* n_prev,
                        const double* J_prev, double* E_out, int32_t mode,
                        double diag[3], orc_status* st);
+
+/* ---- open boundaries in x (Sec. II.C), 2D, on a grid whose columns 0 and
+   nx-1 are ghost columns ---- */
+
+/* Ghost columns of ncomp component-major arrays set to their interior
+   neighbours (B1 and the plasma moments). */
+void orc_open_fill(const orc_params* p, double* F, int32_t ncomp);
+
+/* curl with no x-derivatives in the ghost columns. */
+void orc_open_curl(const orc_params* p, const double* A, double* C);
+
+/* Ohm's law with B = B0 + B1 and J = curl B1 (the split of Sec. II.C), no
+   gradients normal to an open boundary in the ghost columns, and eta_h
+   raised over the buffer layer. */
+void orc_open_ohm(const orc_params* p, const double* B0, const double* B1, const double* n,
+                  const double* Ji, double* E);
+
+/* The field advance of B1 (mode 0) or E only (mode 1) on the open grid;
+   Btot = B0 + B1 afterwards; diag over the interior cells. */
+void orc_open_field_advance(const orc_params* p, const double* B0, double* B1,
+                            const double* n_half, const double* J_half, const double* n_prev,
+                            const double* J_prev, double* E_out, double* Btot, int32_t mode,
+                            double diag[3], orc_status* st);
+
+/* Ions in the ghost columns are absorbed: their cell becomes ncell (the key
+   that sorts them last); returns how many. */
+int64_t orc_open_absorb(const orc_params* p, int64_t np, int32_t* cell);
+
+/* Expected ions entering one boundary row of a face per step. */
+double orc_inflow_expected(const orc_params* p, const orc_inflow* in, int32_t face);
+
+/* Appends the ions injected this step (counter-based draws of seed and
+   step) after the np stored ones; returns the new count (at most cap). */
+int64_t orc_open_inject(const orc_params* p, const orc_inflow* in, uint64_t seed, int64_t step,
+                        int64_t np, int64_t cap, int32_t* cell, double* ox, double* oy,
+                        double* ux, double* uy, double* uz, double* w);
+
+/* The uniform in [0, 1) of counter ctr and seed (splitmix64 mixing). */
+double orc_uniform(uint64_t seed, uint64_t ctr);
 
 #ifdef __cplusplus
 }

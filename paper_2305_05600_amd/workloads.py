@@ -56,6 +56,9 @@ class Config:
     eta_h: float = 0.0
     energy_eq: int = 0
     kappa0: float = 0.0
+    open_x: int = 0
+    buffer_cells: int = 0
+    eta_h_buffer: float = 0.0
     steps: int = 1
 
     @property
@@ -177,6 +180,45 @@ def ensemble_run(spec: dict, shape: int = SHAPE_QS):
     cfg = cfg.replace(te=te, name=f"2d-periodic-{spec['side']}^2-ppc{spec['ppc']}-a{spec['amp']:.3g}"
                                   f"-te{te:.3g}")
     return cfg, parts, B
+
+
+def open_flow(seed: int = 9, nx: int = 64, ny: int = 32, ppc: int = 32, ux: float = 0.5,
+              vth: float = 0.3, b0=(0.0, 1.0, 0.0), amp: float = 0.02, buffer_cells: int = 4,
+              eta_h_buffer: float = 0.02, dt: float = 0.02, nsub: int = 4):
+    """A plasma drifting along x through a 2D box open in x (Sec. II.C) and
+    periodic in y, across a fixed external field B0 (uniform, curl-free),
+    with a transverse B1 wave of amplitude amp in B1_z.
+
+    The grid has nx interior columns plus a ghost column at each x end
+    (columns 0 and nx+1); ions (ppc per cell, density 1, drift ux, thermal
+    speed vth per component, T_e = vth^2) fill the interior columns.  The
+    same plasma enters through both faces (the inflow spec).  eta = 1e-3
+    and a hyper-resistive buffer of buffer_cells cells with eta_h_buffer.
+    Returns (cfg, parts, B0, B1, inflow)."""
+    cfg = Config(name=f"2d-open-flow-{nx}x{ny}-ppc{ppc}", ndim=2, nx=nx + 2, ny=ny, nz=1,
+                 dx=0.5, dy=0.5, dz=1.0, dt=dt, nsub=nsub, shape=SHAPE_QS, te=vth * vth,
+                 eta=1e-3, open_x=1, buffer_cells=buffer_cells, eta_h_buffer=eta_h_buffer)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ncol = nx * ny
+    n = ncol * ppc
+    col = np.repeat(np.arange(ncol, dtype=np.int64), ppc)
+    i = col % nx + 1
+    j = col // nx
+    ox = _offsets(rng.uniform(-1.0, 1.0, n))
+    oy = _offsets(rng.uniform(-1.0, 1.0, n))
+    u = rng.normal(0.0, vth, (3, n))
+    u[0] += ux
+    w = np.full(n, cfg.dx * cfg.dy * cfg.dz / ppc)
+    parts = _particles(cfg, i, j, 0 * i, ox, oy, None, u[0], u[1], u[2], w,
+                       order=rng.permutation(n))
+    B0 = field_zeros(cfg)
+    for a in range(3):
+        B0[a] = np.float32(b0[a])
+    x, _, _ = cell_centres(cfg)
+    B1 = field_zeros(cfg)
+    B1[2] = _f32(amp * np.sin(2.0 * math.pi * x / (cfg.nx * cfg.dx)))
+    spec = dict(n=1.0, ux=ux, uy=0.0, uz=0.0, vth=vth, ppc=ppc, faces=3)
+    return cfg, parts, B0, B1, spec
 
 
 def harris_double(seed: int = 2, nx: int = 512, ny: int = 256, ppc: float = 100.0,
