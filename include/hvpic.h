@@ -92,6 +92,13 @@ typedef struct {
                                 electron energy equation (gamma_e > 1), through
                                 hvpic_field_advance_pe                          */
   double kappa0;             /* electron heat conductivity (>= 0; energy_eq)    */
+  int32_t open_x;            /* 0: periodic in x; 1: open in x (Sec. II.C, 2D,
+                                nx >= 3): columns 0 and nx-1 are ghost columns,
+                                driven by the hvpic_open_* calls                */
+  int32_t buffer_cells;      /* open_x: width w of the absorbing layer (>= 0)    */
+  double eta_h_buffer;       /* open_x: eta_h added in the layer, ramping from
+                                eta_h_buffer at the outermost interior column to
+                                0 at depth w (>= 0)                             */
   int64_t np_capacity;       /* largest particle count any call will pass       */
 } hvpic_params;
 
@@ -487,6 +494,77 @@ int hvpic_no_conv3x3(int nimg, int nx, int ny, int cinp, int coutp, int mode, co
 int hvpic_no_conv3x3_wgrad(int nimg, int nx, int ny, int cinp, int coutp, const void* x,
                            const void* dz, float* dw, float* db, void* workspace,
                            void* hip_stream);
+
+/* ---------------------------------------------------------------------------
+ * Open boundaries in x (Sec. II.C), 2D, for a context with open_x = 1.  The
+ * grid's columns 0 and nx-1 are ghost columns outside the domain; the
+ * domain is columns 1 .. nx-2.  The magnetic field is split B = B0 + B1:
+ * B0 (device [3][ncell]) is a fixed external field with curl B0 = 0 that
+ * the caller keeps, only B1 is advanced, and the plasma current of Ohm's
+ * Hall and resistive terms is J = curl B1.  In a ghost cell B1 and the
+ * moments equal their interior neighbour, and Ohm's law keeps the gradients
+ * along the boundary and drops those normal to it (x-derivatives are zero
+ * there).  A layer of buffer_cells cells at each boundary adds
+ * eta_h_buffer (1 - d/buffer_cells) to eta_h, d = 0 at the outermost
+ * interior column.  The push, the deposit and the sort run unchanged on this
+ * grid (their periodic wrap only ever joins the two ghost columns); one step
+ * is: hvpic_gather_push with E and B0 + B1 (cell_start NULL, fused deposit);
+ * hvpic_open_particles; hvpic_sort_open; the count n = cell_start[ncell];
+ * hvpic_open_fill of the moments; hvpic_open_field_advance.
+ * ------------------------------------------------------------------------- */
+
+/* Drifting Maxwellian of the inflow: density n, drift (ux, uy, uz) (ux > 0
+   flows in through the left face, out through the right), thermal speed
+   vth (> 0), ppc ions per cell of density n; faces: bit 0 the left face,
+   bit 1 the right. */
+typedef struct {
+  double n, ux, uy, uz, vth;
+  int32_t ppc;
+  int32_t faces;
+} hvpic_inflow;
+
+/* Copies column 1 into column 0 and column nx-2 into column nx-1 of the
+   ncomp (1..16) component-major arrays F [ncomp][ncell] (the ghost rule of
+   B1 and the moments). */
+int hvpic_open_fill(hvpic_ctx* ctx, float* F, int ncomp);
+
+/* hvpic_field_advance for open x: B1 (in/out [3][ncell]) advanced by the
+   subcycled RK2 Faraday update (mode 0; the ghost columns refilled after
+   each stage, only the interior updated by Faraday) with E from Ohm's law
+   at the frozen n_half, J_half and B = B0 + B1; then E_out = E^{n+1} from
+   B1 and the extrapolated moments 3/2 n_half - 1/2 n_prev (mode 0) or from
+   n_half, J_half as given (mode 1: no advance, no ghost refill of B1), and
+   Btot = B0 + B1 [3][ncell] for the next push.  The moments' ghost columns
+   must be filled (hvpic_open_fill).  diag_out (device, may be NULL): W_B
+   and W_dB of B0 + B1 and W_e, summed over the interior cells.  The count
+   of n_half cells below n_floor goes to the status.  energy_eq is not
+   supported here (HVPIC_EINVAL). */
+int hvpic_open_field_advance(hvpic_ctx* ctx, const float* B0, float* B1, float* Btot,
+                             const float* n_half, const float* J_half, const float* n_prev,
+                             const float* J_prev, float* E_out, int mode, double* diag_out);
+
+/* Absorption and injection of one step: every ion of p in a ghost column
+   gets the key ncell (absorbed; hvpic_sort_open puts it last), then
+   floor(N + U) fresh ions per row of each open face are appended at p->n
+   (p->n grows on the host).  N = ppc dt/dx F(u, vth) with F the inward
+   flux per unit density of the drifting Maxwellian and u the drift along
+   the face's inward normal; U and every velocity and position draw are the
+   counter-based uniforms mix(seed + mix(ctr)) of splitmix64's finaliser,
+   the counter packing (step, face, row, ion, draw), so a run is repeatable.
+   An injected ion sits in the first interior column at depth v dt U' from
+   its face (v the inward normal speed, drawn from the flux-weighted
+   distribution by inverting its distribution function), uniformly in y,
+   tangential velocities drifting Maxwellian, weight n dx dy dz / ppc.
+   0 <= step < 2^20, ny <= 65535.  p's arrays must hold np_capacity ions;
+   HVPIC_ENOMEM (nothing launched) when the injected ions would exceed it. */
+int hvpic_open_particles(hvpic_ctx* ctx, hvpic_particles* p, const hvpic_inflow* in,
+                         uint64_t seed, int64_t step);
+
+/* Stable sort of in by cell into out, the absorbed ions (key ncell) last.
+   cell_start (device int32 [ncell+2]): cell_start[ncell] is the count of
+   live ions (the caller's new n), cell_start[ncell+1] = in->n. */
+int hvpic_sort_open(hvpic_ctx* ctx, const hvpic_particles* in, hvpic_particles* out,
+                    int32_t* cell_start);
 
 #ifdef __cplusplus
 }

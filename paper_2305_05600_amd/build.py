@@ -11,7 +11,8 @@ import subprocess
 
 PKG = pathlib.Path(__file__).resolve().parent
 ROOT = PKG.parent
-SOURCES = ["abi.hip", "particles.hip", "sort.hip", "fields.hip", "fields_ext.hip", "ensemble.hip", "surrogate.hip"]
+SOURCES = ["abi.hip", "particles.hip", "sort.hip", "fields.hip", "fields_ext.hip", "ensemble.hip",
+           "surrogate.hip", "open.hip"]
 LIB = PKG / "libhvpic.so"
 
 

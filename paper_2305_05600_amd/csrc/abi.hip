@@ -34,6 +34,9 @@ bool params_ok(const hvpic_params* p) {
   if (p->energy_eq != 0 && p->energy_eq != 1) return false;
   if (p->energy_eq && !(p->gamma_e > 1.0)) return false;  // W_e = sum p V/(gamma-1)
   if (!isfinite(p->kappa0) || p->kappa0 < 0.0) return false;
+  if (p->open_x != 0 && p->open_x != 1) return false;
+  if (p->open_x && (p->ndim != 2 || p->nx < 3)) return false;
+  if (p->buffer_cells < 0 || !isfinite(p->eta_h_buffer) || p->eta_h_buffer < 0.0) return false;
   if (p->np_capacity < 0 || p->np_capacity >= (1ll << 31) - 1) return false;
   return true;
 }
@@ -222,6 +225,20 @@ int hvpic_sort(hvpic_ctx* ctx, const hvpic_particles* in, hvpic_particles* out,
   return launch_sort(ctx, in, out, cell_start_prev, cell_start, full);
 }
 
+int hvpic_sort_open(hvpic_ctx* ctx, const hvpic_particles* in, hvpic_particles* out,
+                    int32_t* cell_start) {
+  if (!ctx_ok(ctx)) return HVPIC_ESTATE;
+  if (!ctx->p.open_x) return HVPIC_EINVAL;
+  if (!parts_ok(ctx, in, true) || !out || !cell_start) return HVPIC_EINVAL;
+  if (in->n > 0) {
+    if (!out->cell || !out->ox || !out->oy || !out->ux || !out->uy || !out->uz || !out->w)
+      return HVPIC_EINVAL;
+    if (out->cell == in->cell || out->ox == in->ox || out->ux == in->ux || out->w == in->w)
+      return HVPIC_EINVAL;
+  }
+  return launch_sort_open(ctx, in, out, cell_start);
+}
+
 int hvpic_deposit(hvpic_ctx* ctx, const hvpic_particles* p, const int32_t* cell_start,
                   float half_dt_back, float* n, float* J) {
   if (!ctx_ok(ctx)) return HVPIC_ESTATE;
@@ -236,7 +253,7 @@ int hvpic_field_advance(hvpic_ctx* ctx, float* B, const float* n_half, const flo
   if (!B || !n_half || !J_half || !E_out) return HVPIC_EINVAL;
   if (mode != 0 && mode != 1) return HVPIC_EINVAL;
   if (mode == 0 && (!n_prev || !J_prev)) return HVPIC_EINVAL;
-  if (ctx->p.energy_eq) return HVPIC_EINVAL;
+  if (ctx->p.energy_eq || ctx->p.open_x) return HVPIC_EINVAL;
   if (ctx->p.eta_h != 0.0)
     return launch_field_advance_ext(ctx, B, nullptr, n_half, J_half, n_prev, J_prev, E_out, mode,
                                     diag_out);
@@ -247,7 +264,7 @@ int hvpic_field_advance_pe(hvpic_ctx* ctx, float* B, float* pe, const float* n_h
                            const float* J_half, const float* n_prev, const float* J_prev,
                            float* E_out, int mode, double* diag_out) {
   if (!ctx_ok(ctx)) return HVPIC_ESTATE;
-  if (!ctx->p.energy_eq) return HVPIC_EINVAL;
+  if (!ctx->p.energy_eq || ctx->p.open_x) return HVPIC_EINVAL;
   if (!B || !pe || !n_half || !J_half || !E_out) return HVPIC_EINVAL;
   if (mode != 0 && mode != 1) return HVPIC_EINVAL;
   if (mode == 0 && (!n_prev || !J_prev)) return HVPIC_EINVAL;

@@ -145,7 +145,8 @@ bool runs_ok(const hvpic_run* runs, int nruns) {
     const hvpic_ctx* c = R.ctx;
     if (!c || c->magic != kMagic) return false;
     const hvpic_params& p = c->p;
-    if (p.ndim != 2 || p.nsmooth != 0 || p.energy_eq != 0 || p.eta_h != 0.0 || p.nsub < 3 ||
+    if (p.ndim != 2 || p.nsmooth != 0 || p.energy_eq != 0 || p.open_x != 0 || p.eta_h != 0.0 ||
+        p.nsub < 3 ||
         p.nsub > 2 * kMaxLaunches)
       return false;
     if ((nsub >= 0 && p.nsub != nsub) || (shape >= 0 && p.shape != shape)) return false;

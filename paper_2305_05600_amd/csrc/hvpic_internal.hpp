@@ -206,6 +206,7 @@ int launch_deposit(hvpic_ctx* c, const hvpic_particles* p, const int32_t* cell_s
                    float half_dt_back, float* n, float* J);
 int launch_sort(hvpic_ctx* c, const hvpic_particles* in, hvpic_particles* out,
                 const int32_t* cs_prev, int32_t* cs, int full);
+int launch_sort_open(hvpic_ctx* c, const hvpic_particles* in, hvpic_particles* out, int32_t* cs);
 int launch_sort_perm(hvpic_ctx* c, const hvpic_particles* in, const int32_t* cs_prev,
                      int32_t* perm, int32_t* cs);
 int launch_field_advance(hvpic_ctx* c, float* B, const float* n_half, const float* J_half,

@@ -1,0 +1,546 @@
+// Open boundaries in x for 2D runs (libhvpic.so, gfx950).
+//
+// Method (arXiv 2305.05600, Sec. II.C): the grid's first and last columns
+// are ghost columns outside the domain.  The magnetic field is split
+// B = B0 + B1: B0 is a fixed external vacuum field, only B1 is advanced, and
+// the plasma current of the Hall and resistive terms is J = curl B1.  In a
+// ghost cell B1 and the moments equal their interior neighbour, and Ohm's
+// law keeps the gradients along the boundary while dropping those normal to
+// it.  A layer of buffer_cells cells at each open boundary has the
+// hyper-resistivity raised by eta_h_buffer, ramping to zero inward.  Ions in
+// a ghost column are absorbed; fresh ions enter through the faces from a
+// drifting Maxwellian with the flux-weighted distribution of the normal
+// velocity.
+//
+// The particle kernels of the periodic step run unchanged on this grid (the
+// ghost columns keep the two sides apart); absorbed ions get the key ncell
+// and the open sort puts them last.  The field advance is the stencil-per-
+// stage form: per RK2 stage the ghost columns are refilled, J = curl B1 (no
+// x-derivatives in the ghosts), Ohm's law, then Faraday in the interior.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+
+#include "fields_common.hpp"
+
+namespace hvpic {
+namespace {
+
+struct OpenG {
+  FGeo g;
+  float ilx, ily;        // 1/dx^2, 1/dy^2
+  float eta, eta_h, eta_hb;
+  int nbuf;
+};
+
+__device__ __forceinline__ bool ghost_col(int i, int nx) { return i == 0 || i == nx - 1; }
+
+__device__ __forceinline__ float eta_h_col(int i, const OpenG& o) {
+  float e = o.eta_h;
+  if (o.nbuf > 0) {
+    int d = min(i, o.g.nx - 1 - i);
+    d = d > 0 ? d - 1 : 0;
+    if (d < o.nbuf) e += o.eta_hb * (1.0f - (float)d / (float)o.nbuf);
+  }
+  return e;
+}
+
+// ghost columns of ncomp component-major arrays <- their interior neighbours
+__global__ void k_open_fill(float* __restrict__ F, int ncomp, int nx, int ny, int ncell) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ncomp * ny) return;
+  const int a = t / ny, j = t - (t / ny) * ny;
+  float* f = F + (int64_t)a * ncell + (int64_t)j * nx;
+  f[0] = f[1];
+  f[nx - 1] = f[nx - 2];
+}
+
+// 1/n_f, u_i and -grad(p_e)/n_f of the held moments (no x-component of the
+// pressure gradient in a ghost column)
+__global__ __launch_bounds__(kBlock) void k_open_prep(const float* __restrict__ n,
+                                                      const float* __restrict__ Ji, FGeo g,
+                                                      Eos eos, Aux aux) {
+  const int c = blockIdx.x * kBlock + threadIdx.x;
+  if (c >= g.ncell) return;
+  const int nc = g.ncell;
+  int i, j, k;
+  fijk(c, g, i, j, k);
+  const Nbr nn = neighbours(c, i, j, k, g);
+  const float nf = fmaxf(n[c], eos.nfloor);
+  const float inv = (float)(1.0 / (double)nf);
+  aux.inv[c] = inv;
+  for (int a = 0; a < 3; ++a) aux.u[a * nc + c] = Ji[a * nc + c] * inv;
+  auto pres = [&](int q) { return pressure(n[q], eos.nfloor, eos.te_n0, eos.n0, eos.gam, eos.iso); };
+  aux.gp[c] = ghost_col(i, g.nx) ? 0.0f : -(pres(nn.xp) - pres(nn.xm)) * g.idx2 * inv;
+  aux.gp[nc + c] = -(pres(nn.yp) - pres(nn.ym)) * g.idy2 * inv;
+  aux.gp[2 * nc + c] = 0.0f;
+}
+
+// J = curl B1 (B1 = hi + lo with HAS_LO), no x-derivatives in the ghosts
+template <bool HAS_LO>
+__global__ __launch_bounds__(kBlock) void k_open_curl(const float* __restrict__ Bh,
+                                                      const float* __restrict__ Bl,
+                                                      float* __restrict__ J, FGeo g) {
+  const int c = blockIdx.x * kBlock + threadIdx.x;
+  if (c >= g.ncell) return;
+  const int nc = g.ncell;
+  int i, j, k;
+  fijk(c, g, i, j, k);
+  const Nbr n = neighbours(c, i, j, k, g);
+  const BSum<HAS_LO> B{Bh, Bl};
+  const bool gh = ghost_col(i, g.nx);
+  const float dyBz = (B(2 * nc + n.yp) - B(2 * nc + n.ym)) * g.idy2;
+  const float dyBx = (B(n.yp) - B(n.ym)) * g.idy2;
+  const float dxBz = gh ? 0.0f : (B(2 * nc + n.xp) - B(2 * nc + n.xm)) * g.idx2;
+  const float dxBy = gh ? 0.0f : (B(nc + n.xp) - B(nc + n.xm)) * g.idx2;
+  J[c] = dyBz;
+  J[nc + c] = -dxBz;
+  J[2 * nc + c] = dxBy - dyBx;
+}
+
+// lap of component a of J at c (x part dropped in a ghost column)
+__device__ __forceinline__ float lap_open(const float* __restrict__ J, int a, int c, int i,
+                                          const Nbr& n, const OpenG& o) {
+  const float* q = J + (int64_t)a * o.g.ncell;
+  float r = (q[n.yp] + q[n.ym] - 2.0f * q[c]) * o.ily;
+  if (!ghost_col(i, o.g.nx)) r += (q[n.xp] + q[n.xm] - 2.0f * q[c]) * o.ilx;
+  return r;
+}
+
+// E = (J/n_f - u_i) x (B0 + B1) - grad(p_e)/n_f + eta J - eta_h(x) lap J
+__global__ __launch_bounds__(kBlock) void k_open_ohm(const float* __restrict__ B0,
+                                                     const float* __restrict__ B1,
+                                                     const float* __restrict__ J, Aux aux,
+                                                     float* __restrict__ E, OpenG o) {
+  const int c = blockIdx.x * kBlock + threadIdx.x;
+  if (c >= o.g.ncell) return;
+  const int nc = o.g.ncell;
+  int i, j, k;
+  fijk(c, o.g, i, j, k);
+  const Nbr n = neighbours(c, i, j, k, o.g);
+  const float b0 = B0[c] + B1[c], b1 = B0[nc + c] + B1[nc + c], b2 = B0[2 * nc + c] + B1[2 * nc + c];
+  const float j0 = J[c], j1 = J[nc + c], j2 = J[2 * nc + c];
+  const float inv = aux.inv[c];
+  const float w0 = j0 * inv - aux.u[c], w1 = j1 * inv - aux.u[nc + c],
+              w2 = j2 * inv - aux.u[2 * nc + c];
+  const float eh = eta_h_col(i, o);
+  float h0 = 0.f, h1 = 0.f, h2 = 0.f;
+  if (eh != 0.0f) {
+    h0 = eh * lap_open(J, 0, c, i, n, o);
+    h1 = eh * lap_open(J, 1, c, i, n, o);
+    h2 = eh * lap_open(J, 2, c, i, n, o);
+  }
+  E[c] = (w1 * b2 - w2 * b1) + aux.gp[c] + o.eta * j0 - h0;
+  E[nc + c] = (w2 * b0 - w0 * b2) + aux.gp[nc + c] + o.eta * j1 - h1;
+  E[2 * nc + c] = (w0 * b1 - w1 * b0) + aux.gp[2 * nc + c] + o.eta * j2 - h2;
+}
+
+// B1_dst = B1_base - coef curl E in the interior (compensated into lo when
+// given); base and dst are read and written at the thread's own cell only
+__global__ __launch_bounds__(kBlock) void k_open_faraday(const float* __restrict__ E,
+                                                         const float* Bbase, float* Bdst, float* lo,
+                                                         float coef, FGeo g) {
+  const int c = blockIdx.x * kBlock + threadIdx.x;
+  if (c >= g.ncell) return;
+  int i, j, k;
+  fijk(c, g, i, j, k);
+  if (ghost_col(i, g.nx)) return;
+  const BSum<false> Ea{E, nullptr};
+  float ce[3];
+  curl_at<2>(Ea, c, g, ce);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const int q = a * g.ncell + c;
+    const float d = -coef * ce[a];
+    const float hi = Bbase[q];
+    if (lo) {
+      const float y = lo[q] + d;
+      const float t = hi + y;
+      lo[q] = y - (t - hi);
+      Bdst[q] = t;
+    } else {
+      Bdst[q] = hi + d;
+    }
+  }
+}
+
+// E from B1 = Bh (+ Bl), J = curl B1 and the moments n_eff = ca*na + cb*nb,
+// J_eff likewise (EXTRAP; otherwise na, Ja), with the open rules; B1out =
+// B1 (when non-null), Btot = B0 + B1; per-block FP64 partials over the
+// interior cells of {|Btot|^2, Btot, electron energy of n_eff}; the cells of
+// na below the floor counted (all columns).
+template <bool EXTRAP, bool HAS_LO>
+__global__ __launch_bounds__(kBlock) void k_open_final(
+    const float* __restrict__ Bh, const float* __restrict__ Bl, const float* __restrict__ J,
+    const float* __restrict__ B0, float* __restrict__ B1out, float* __restrict__ Btot,
+    const float* __restrict__ na, const float* __restrict__ nb, const float* __restrict__ Ja,
+    const float* __restrict__ Jb, float ca, float cb, OpenG o, Eos eos, float* __restrict__ E,
+    double* part, Status* st) {
+  const int c = blockIdx.x * kBlock + threadIdx.x;
+  const int nc = o.g.ncell;
+  const bool live = c < nc;
+  bool below = false;
+  double v[kDiagNV] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  if (live) {
+    int i, j, k;
+    fijk(c, o.g, i, j, k);
+    const Nbr n = neighbours(c, i, j, k, o.g);
+    const bool gh = ghost_col(i, o.g.nx);
+    auto dens = [&](int q) { return EXTRAP ? ca * na[q] + cb * nb[q] : na[q]; };
+    const float n_c = dens(c);
+    const BSum<HAS_LO> B1{Bh, Bl};
+    const float c0 = B1(c), c1 = B1(nc + c), c2 = B1(2 * nc + c);
+    const float b0 = B0[c] + c0, b1 = B0[nc + c] + c1, b2 = B0[2 * nc + c] + c2;
+    below = na[c] < eos.nfloor;
+    const float inv = (float)(1.0 / (double)fmaxf(n_c, eos.nfloor));
+    float u[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+      u[a] = (EXTRAP ? ca * Ja[a * nc + c] + cb * Jb[a * nc + c] : Ja[a * nc + c]) * inv;
+    auto pres = [&](int q) {
+      return pressure(dens(q), eos.nfloor, eos.te_n0, eos.n0, eos.gam, eos.iso);
+    };
+    const float gp0 = gh ? 0.0f : -(pres(n.xp) - pres(n.xm)) * o.g.idx2 * inv;
+    const float gp1 = -(pres(n.yp) - pres(n.ym)) * o.g.idy2 * inv;
+    const float j0 = J[c], j1 = J[nc + c], j2 = J[2 * nc + c];
+    const float w0 = j0 * inv - u[0], w1 = j1 * inv - u[1], w2 = j2 * inv - u[2];
+    const float eh = eta_h_col(i, o);
+    float h0 = 0.f, h1 = 0.f, h2 = 0.f;
+    if (eh != 0.0f) {
+      h0 = eh * lap_open(J, 0, c, i, n, o);
+      h1 = eh * lap_open(J, 1, c, i, n, o);
+      h2 = eh * lap_open(J, 2, c, i, n, o);
+    }
+    E[c] = (w1 * b2 - w2 * b1) + gp0 + o.eta * j0 - h0;
+    E[nc + c] = (w2 * b0 - w0 * b2) + gp1 + o.eta * j1 - h1;
+    E[2 * nc + c] = (w0 * b1 - w1 * b0) + 0.0f + o.eta * j2 - h2;
+    if (B1out) {
+      B1out[c] = c0;
+      B1out[nc + c] = c1;
+      B1out[2 * nc + c] = c2;
+    }
+    Btot[c] = b0;
+    Btot[nc + c] = b1;
+    Btot[2 * nc + c] = b2;
+    if (part && !gh) {
+      const double d0 = b0, d1 = b1, d2 = b2;
+      v[0] = d0 * d0 + d1 * d1 + d2 * d2;
+      v[1] = d0;
+      v[2] = d1;
+      v[3] = d2;
+      v[4] = electron_energy(n_c, eos);
+    }
+  }
+  const uint64_t m = __ballot(live && below);
+  if ((threadIdx.x & 63) == 0 && m) {
+    atomicOr(&st->flags, (uint32_t)HVPIC_FLAG_FLOOR_HIT);
+    atomicAdd(&st->floor_hits, (unsigned long long)__builtin_popcountll(m));
+  }
+  if (part) block_partial<kDiagNV, kFieldPartStride>(v, part);
+}
+
+// ---------------------------------------------------------- particles --
+
+__global__ void k_open_absorb(int32_t* __restrict__ cell, int64_t n, int nx, int ncell) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  const int c = cell[q];
+  if ((unsigned)c >= (unsigned)ncell) return;
+  const int i = c % nx;
+  if (i == 0 || i == nx - 1) cell[q] = ncell;
+}
+
+// splitmix64's finaliser (Steele, Lea & Flood 2014), and the uniform in
+// [0, 1) of a counter under a seed: the generator of the injection draws
+__host__ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z += 0x9e3779b97f4a7c15ull;
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+__host__ __device__ __forceinline__ double uniform01(uint64_t seed, uint64_t ctr) {
+  return (double)(mix64(seed + mix64(ctr)) >> 11) * (1.0 / 9007199254740992.0);
+}
+// counter of draw d of ion m of row j of face f at a step
+__host__ __device__ __forceinline__ uint64_t draw_ctr(int64_t step, int f, int j, int64_t m,
+                                                      int d) {
+  return ((((uint64_t)step * 2u + (uint64_t)f) << 16 | (uint64_t)j) << 20 | (uint64_t)m) << 7 |
+         (uint64_t)d;
+}
+
+__device__ double normal_draw(uint64_t seed, int64_t step, int f, int j, int64_t m, int d) {
+  const double u1 = uniform01(seed, draw_ctr(step, f, j, m, d));
+  const double u2 = uniform01(seed, draw_ctr(step, f, j, m, d + 1));
+  return sqrt(-2.0 * log(1.0 - u1)) * cos(6.283185307179586 * u2);
+}
+
+// integral over 0 < t < v of t exp(-(t - u)^2 / (2 vth^2)) dt (closed form
+// in erf and exp of x = (t - u)/(sqrt(2) vth))
+__device__ double flux_integral(double u, double vth, double v) {
+  const double s2 = 1.4142135623730951 * vth;
+  const double x0 = -u / s2, x1 = (v - u) / s2;
+  return vth * u * 1.2533141373155003 * (erf(x1) - erf(x0)) +
+         vth * vth * (exp(-x0 * x0) - exp(-x1 * x1));
+}
+
+// the normal speed whose flux-weighted distribution function is U
+__device__ double inflow_speed(double u, double vth, double U) {
+  double lo = 0.0, hi = (u > 0.0 ? u : 0.0) + 10.0 * vth;
+  const double target = U * flux_integral(u, vth, hi);
+  for (int it = 0; it < 60; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (flux_integral(u, vth, mid) < target)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+struct Inject {
+  double nexp[2], un[2];
+  double uy, uz, vth, dt, dx, w;
+  int faces, nx, ny;
+  uint64_t seed;
+  int64_t step, n0;
+};
+
+// One block: per (face, row) the count floor(nexp + U), an exclusive scan
+// over the rows in order (face-major), then each row's ions appended after
+// the n0 stored ones.
+__global__ __launch_bounds__(1024) void k_open_inject(Inject P, int32_t* __restrict__ cell,
+                                                     float* __restrict__ ox, float* __restrict__ oy,
+                                                     float* __restrict__ ux, float* __restrict__ uy,
+                                                     float* __restrict__ uz, float* __restrict__ w) {
+  __shared__ int64_t s_sum[1024];
+  __shared__ int64_t s_carry;
+  if (threadIdx.x == 0) s_carry = 0;
+  __syncthreads();
+  const int rows = 2 * P.ny;
+  for (int r0 = 0; r0 < rows; r0 += 1024) {
+    const int r = r0 + (int)threadIdx.x;
+    int64_t k = 0;
+    int f = 0, j = 0;
+    if (r < rows) {
+      f = r / P.ny;
+      j = r - f * P.ny;
+      if ((P.faces >> f) & 1)
+        k = (int64_t)floor(P.nexp[f] + uniform01(P.seed, draw_ctr(P.step, f, j, 0, 127)));
+    }
+    // inclusive scan over the block (Hillis-Steele in LDS)
+    s_sum[threadIdx.x] = k;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+      const int64_t add = threadIdx.x >= (unsigned)o ? s_sum[threadIdx.x - o] : 0;
+      __syncthreads();
+      s_sum[threadIdx.x] += add;
+      __syncthreads();
+    }
+    const int64_t base = P.n0 + s_carry + s_sum[threadIdx.x] - k;
+    const int64_t chunk = s_sum[1023];
+    const int col = f == 0 ? 1 : P.nx - 2;
+    const int32_t c = col + P.nx * j;
+    for (int64_t m = 0; m < k; ++m) {
+      const double v = inflow_speed(P.un[f], P.vth, uniform01(P.seed, draw_ctr(P.step, f, j, m, 0)));
+      const double vy = P.uy + P.vth * normal_draw(P.seed, P.step, f, j, m, 96);
+      const double vz = P.uz + P.vth * normal_draw(P.seed, P.step, f, j, m, 98);
+      const double s = v * P.dt * uniform01(P.seed, draw_ctr(P.step, f, j, m, 100));
+      double o = -1.0 + 2.0 * s / P.dx;
+      if (o >= 1.0) o = 1.0 - 1e-7;
+      double xo = f == 0 ? o : -o;
+      if (xo >= 1.0) xo = 1.0 - 1e-7;
+      float fx = (float)xo;
+      if (fx >= 1.0f) fx = 0.99999994f;
+      float fy = (float)(-1.0 + 2.0 * uniform01(P.seed, draw_ctr(P.step, f, j, m, 101)));
+      if (fy >= 1.0f) fy = 0.99999994f;
+      const int64_t q = base + m;
+      cell[q] = c;
+      ox[q] = fx;
+      oy[q] = fy;
+      ux[q] = (float)(f == 0 ? v : -v);
+      uy[q] = (float)vy;
+      uz[q] = (float)vz;
+      w[q] = (float)P.w;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) s_carry += chunk;
+    __syncthreads();
+  }
+}
+
+// host: the expected count per row and step of a face, and the total of a
+// step (the same draws as the kernel, in the same double arithmetic)
+double inflow_flux_host(double u, double vth) {
+  return vth / sqrt(2.0 * 3.141592653589793) * exp(-0.5 * u * u / (vth * vth)) +
+         0.5 * u * (1.0 + erf(u / (sqrt(2.0) * vth)));
+}
+
+OpenG open_geo(const hvpic_ctx* c) {
+  OpenG o;
+  o.g = fgeo(c);
+  o.ilx = (float)(1.0 / (c->p.dx * c->p.dx));
+  o.ily = (float)(1.0 / (c->p.dy * c->p.dy));
+  o.eta = (float)c->p.eta;
+  o.eta_h = (float)c->p.eta_h;
+  o.eta_hb = (float)c->p.eta_h_buffer;
+  o.nbuf = c->p.buffer_cells;
+  return o;
+}
+
+void fill(hvpic_ctx* c, float* F, int ncomp) {
+  const int t = ncomp * c->p.ny;
+  hipLaunchKernelGGL(k_open_fill, dim3((unsigned)ceil_div(t, 256)), dim3(256), 0, c->stream, F,
+                     ncomp, c->p.nx, c->p.ny, c->ncell);
+}
+
+bool open_ok(const hvpic_ctx* c) { return c && c->magic == kMagic && c->p.open_x == 1; }
+
+}  // namespace
+}  // namespace hvpic
+
+using namespace hvpic;
+
+extern "C" {
+
+int hvpic_open_fill(hvpic_ctx* ctx, float* F, int ncomp) {
+  if (!ctx || ctx->magic != kMagic) return HVPIC_ESTATE;
+  if (!open_ok(ctx) || !F || ncomp < 1 || ncomp > 16) return HVPIC_EINVAL;
+  fill(ctx, F, ncomp);
+  return hipGetLastError() == hipSuccess ? HVPIC_OK : HVPIC_EHIP;
+}
+
+int hvpic_open_field_advance(hvpic_ctx* ctx, const float* B0, float* B1, float* Btot,
+                             const float* n_half, const float* J_half, const float* n_prev,
+                             const float* J_prev, float* E_out, int mode, double* diag_out) {
+  if (!ctx || ctx->magic != kMagic) return HVPIC_ESTATE;
+  if (!open_ok(ctx) || ctx->p.energy_eq || !B0 || !B1 || !Btot || !n_half || !J_half || !E_out)
+    return HVPIC_EINVAL;
+  if (mode != 0 && mode != 1) return HVPIC_EINVAL;
+  if (mode == 0 && (!n_prev || !J_prev)) return HVPIC_EINVAL;
+  hvpic_ctx* c = ctx;
+  const OpenG o = open_geo(c);
+  const FGeo& g = o.g;
+  const int nc = c->ncell;
+  const dim3 grid((unsigned)ceil_div(nc, kBlock)), blk(kBlock);
+  hipStream_t s = c->stream;
+  const Eos eos = make_eos(c);
+  Aux aux;
+  aux.inv = c->fscratch;
+  aux.u = c->fscratch + nc;
+  aux.gp = c->fscratch + 4ll * nc;
+  float* Xh = c->fscratch + 7ll * nc;
+  float* Xl = c->fscratch + 10ll * nc;
+  float* Yh = c->fscratch + 13ll * nc;
+  float* J = c->fscratch + 16ll * nc;
+  float* E = c->fscratch + 19ll * nc;
+  double* part = diag_out ? c->field_part : nullptr;
+  const float* fh = B1;
+  const float* fl = nullptr;
+  if (mode == 0) fill(c, B1, 3);
+  if (mode == 0 && c->p.nsub > 0) {
+    const float h = (float)(c->p.dt / c->p.nsub);
+    hipLaunchKernelGGL(k_open_prep, grid, blk, 0, s, n_half, J_half, g, eos, aux);
+    const int cblocks = (int)std::min<int64_t>(ceil_div(3ll * nc, kBlock), 1024);
+    hipLaunchKernelGGL(k_copy, dim3(cblocks), blk, 0, s, (const float*)B1, Xh, 3ll * nc);
+    hipLaunchKernelGGL(k_fill, dim3(cblocks), blk, 0, s, Xl, 3ll * nc, 0.0f);
+    for (int m = 0; m < c->p.nsub; ++m) {
+      hipLaunchKernelGGL((k_open_curl<false>), grid, blk, 0, s, (const float*)Xh,
+                         (const float*)nullptr, J, g);
+      hipLaunchKernelGGL(k_open_ohm, grid, blk, 0, s, B0, (const float*)Xh, (const float*)J, aux,
+                         E, o);
+      hipLaunchKernelGGL(k_open_faraday, grid, blk, 0, s, (const float*)E, (const float*)Xh, Yh,
+                         (float*)nullptr, 0.5f * h, g);
+      fill(c, Yh, 3);
+      hipLaunchKernelGGL((k_open_curl<false>), grid, blk, 0, s, (const float*)Yh,
+                         (const float*)nullptr, J, g);
+      hipLaunchKernelGGL(k_open_ohm, grid, blk, 0, s, B0, (const float*)Yh, (const float*)J, aux,
+                         E, o);
+      hipLaunchKernelGGL(k_open_faraday, grid, blk, 0, s, (const float*)E, (const float*)Xh, Xh, Xl,
+                         h, g);
+      fill(c, Xh, 3);
+      fill(c, Xl, 3);
+    }
+    fh = Xh;
+    fl = Xl;
+  }
+  if (fl)
+    hipLaunchKernelGGL((k_open_curl<true>), grid, blk, 0, s, fh, fl, J, g);
+  else
+    hipLaunchKernelGGL((k_open_curl<false>), grid, blk, 0, s, fh, fl, J, g);
+  float* B1out = fh == B1 ? nullptr : B1;
+  if (mode == 0 && fl)
+    hipLaunchKernelGGL((k_open_final<true, true>), grid, blk, 0, s, fh, fl, (const float*)J, B0,
+                       B1out, Btot, n_half, n_prev, J_half, J_prev, 1.5f, -0.5f, o, eos, E_out, part,
+                       c->status);
+  else if (mode == 0)
+    hipLaunchKernelGGL((k_open_final<true, false>), grid, blk, 0, s, fh, fl, (const float*)J, B0,
+                       B1out, Btot, n_half, n_prev, J_half, J_prev, 1.5f, -0.5f, o, eos, E_out, part,
+                       c->status);
+  else
+    hipLaunchKernelGGL((k_open_final<false, false>), grid, blk, 0, s, fh, fl, (const float*)J, B0,
+                       B1out, Btot, n_half, n_prev, J_half, J_prev, 1.5f, -0.5f, o, eos, E_out, part,
+                       c->status);
+  if (diag_out) {
+    const double V = c->p.dx * c->p.dy * c->p.dz;
+    const double we_scale = eos.iso ? V * c->p.te : V * c->p.n0 * c->p.te / (c->p.gamma_e - 1.0);
+    const int interior = nc - 2 * c->p.ny;
+    hipLaunchKernelGGL(k_field_diag_final, dim3(1), dim3(1024), 0, s, (const double*)part,
+                       (int)grid.x, diag_out, 0.5 * V, 1.0 / (double)interior, we_scale);
+  }
+  return hipGetLastError() == hipSuccess ? HVPIC_OK : HVPIC_EHIP;
+}
+
+int hvpic_open_particles(hvpic_ctx* ctx, hvpic_particles* p, const hvpic_inflow* in,
+                         uint64_t seed, int64_t step) {
+  if (!ctx || ctx->magic != kMagic) return HVPIC_ESTATE;
+  if (!open_ok(ctx) || !p || !in || step < 0 || step >= (int64_t(1) << 20)) return HVPIC_EINVAL;
+  if (p->n < 0 || p->n > ctx->p.np_capacity || !p->cell || !p->ox || !p->oy || !p->ux || !p->uy ||
+      !p->uz || !p->w)
+    return HVPIC_EINVAL;
+  if (!(in->n > 0.0) || !(in->vth > 0.0) || !isfinite(in->n) || !isfinite(in->vth) ||
+      in->ppc < 1 || !isfinite(in->ux) || !isfinite(in->uy) || !isfinite(in->uz) ||
+      in->faces < 0 || in->faces > 3 ||
+      ctx->p.ny > 65535)
+    return HVPIC_EINVAL;
+  hvpic_ctx* c = ctx;
+  hipStream_t s = c->stream;
+  if (p->n > 0)
+    hipLaunchKernelGGL(k_open_absorb, dim3((unsigned)ceil_div(p->n, 256)), dim3(256), 0, s,
+                       p->cell, p->n, c->p.nx, c->ncell);
+  Inject P;
+  for (int f = 0; f < 2; ++f) {
+    P.un[f] = f == 0 ? in->ux : -in->ux;
+    P.nexp[f] = in->ppc * c->p.dt / c->p.dx * inflow_flux_host(P.un[f], in->vth);
+  }
+  P.uy = in->uy;
+  P.uz = in->uz;
+  P.vth = in->vth;
+  P.dt = c->p.dt;
+  P.dx = c->p.dx;
+  P.w = in->n * c->p.dx * c->p.dy * c->p.dz / in->ppc;
+  P.faces = in->faces;
+  P.nx = c->p.nx;
+  P.ny = c->p.ny;
+  P.seed = seed;
+  P.step = step;
+  P.n0 = p->n;
+  // the same counts as the kernel, on the host
+  int64_t total = 0;
+  for (int f = 0; f < 2; ++f) {
+    if (!((in->faces >> f) & 1)) continue;
+    for (int j = 0; j < c->p.ny; ++j) {
+      const int64_t k = (int64_t)floor(P.nexp[f] + uniform01(seed, draw_ctr(step, f, j, 0, 127)));
+      if (k >= (int64_t(1) << 20)) return HVPIC_EINVAL;  // beyond the counter's ion field
+      total += k;
+    }
+  }
+  if (p->n + total > c->p.np_capacity) return HVPIC_ENOMEM;
+  if (total > 0)
+    hipLaunchKernelGGL(k_open_inject, dim3(1), dim3(1024), 0, s, P, p->cell, p->ox, p->oy, p->ux,
+                       p->uy, p->uz, p->w);
+  p->n += total;
+  return hipGetLastError() == hipSuccess ? HVPIC_OK : HVPIC_EHIP;
+}
+
+}  // extern "C"

@@ -829,10 +829,14 @@ int radix_bits(int ncell) {
   return b;
 }
 
-void enqueue_radix(hvpic_ctx* c, const hvpic_particles* in, const Fields& out, int32_t* cs) {
+// Radix sort by key; keys are the cells, clamped to nkeys - 1 (nkeys = ncell,
+// or ncell + 1 where the key ncell marks absorbed ions, which go last);
+// cs gets nkeys + 1 entries.
+void enqueue_radix(hvpic_ctx* c, const hvpic_particles* in, const Fields& out, int32_t* cs,
+                   int nkeys) {
   hipStream_t s = c->stream;
   const int64_t n = in->n;
-  const int ncell = c->ncell;
+  const int ncell = nkeys;
   const int ntiles = (int)ceil_div(std::max<int64_t>(n, 1), kRadixTile);
   const int passes = (radix_bits(ncell) + kRadixBits - 1) / kRadixBits;
   const uint32_t* kin = nullptr;
@@ -908,7 +912,7 @@ namespace {
 int sort_to(hvpic_ctx* c, const hvpic_particles* in, const Fields& out, const int32_t* cs_prev,
             int32_t* cs, int full) {
   if (full || cs_prev == nullptr) {
-    enqueue_radix(c, in, out, cs);
+    enqueue_radix(c, in, out, cs, c->ncell);
   } else if (c->p.ndim == 2) {
     enqueue_neighbour<2>(c, in, out, cs_prev, cs);
     c->cnt_clean = true;
@@ -926,6 +930,13 @@ int launch_sort(hvpic_ctx* c, const hvpic_particles* in, hvpic_particles* out,
                 const int32_t* cs_prev, int32_t* cs, int full) {
   out->n = in->n;
   return sort_to(c, in, fields_of(out), cs_prev, cs, full);
+}
+
+int launch_sort_open(hvpic_ctx* c, const hvpic_particles* in, hvpic_particles* out, int32_t* cs) {
+  out->n = in->n;
+  enqueue_radix(c, in, fields_of(out), cs, c->ncell + 1);
+  c->cnt_ready = false;
+  return hipGetLastError() == hipSuccess ? HVPIC_OK : HVPIC_EHIP;
 }
 
 int launch_sort_perm(hvpic_ctx* c, const hvpic_particles* in, const int32_t* cs_prev,

@@ -647,7 +647,7 @@ int hvpic_field_advance_no(hvpic_ctx* ctx, const void* params, void* workspace, 
                            double* stats) {
   if (!ctx || ctx->magic != kMagic) return HVPIC_ESTATE;
   const hvpic_params& p = ctx->p;
-  if (p.ndim != 2 || p.energy_eq || p.eta_h != 0.0 || p.nsub < 1) return HVPIC_EINVAL;
+  if (p.ndim != 2 || p.energy_eq || p.open_x || p.eta_h != 0.0 || p.nsub < 1) return HVPIC_EINVAL;
   if (!params || !workspace || !B || !n_half || !J_half || !n_prev || !J_prev || !E_out ||
       !(tol >= 0.0f))
     return HVPIC_EINVAL;

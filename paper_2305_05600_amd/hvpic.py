@@ -16,6 +16,7 @@ _PKG = pathlib.Path(__file__).resolve().parent
 LIB_PATH = _PKG / "libhvpic.so"
 _LIB = None
 _NCELL = {}  # context handle -> ncell, for host-side size checks
+_NPCAP = {}  # context handle -> np_capacity
 
 HVPIC_OK, HVPIC_EINVAL, HVPIC_ENOMEM, HVPIC_EHIP, HVPIC_ESTATE = 0, -1, -2, -3, -4
 HVPIC_SHAPE_NGP, HVPIC_SHAPE_QS = 0, 1
@@ -34,6 +35,8 @@ EXPORTS = ("hvpic_workspace_bytes", "hvpic_init", "hvpic_finalize", "hvpic_set_s
            "hvpic_no_params_bytes", "hvpic_no_workspace_bytes", "hvpic_no_load", "hvpic_no_store",
            "hvpic_no_predict", "hvpic_no_train_step", "hvpic_field_advance_no",
            "hvpic_no_conv3x3", "hvpic_no_conv3x3_wgrad",
+           "hvpic_open_fill", "hvpic_open_field_advance", "hvpic_open_particles",
+           "hvpic_sort_open",
            "hvpic_strerror")
 KERNEL_GATHER_PUSH, KERNEL_DEPOSIT, KERNEL_SORT_SCATTER = 0, 1, 2
 
@@ -50,8 +53,16 @@ class HvpicParams(ctypes.Structure):
         ("n_floor", ctypes.c_double),
         ("eta", ctypes.c_double), ("eta_h", ctypes.c_double),
         ("energy_eq", ctypes.c_int32), ("kappa0", ctypes.c_double),
+        ("open_x", ctypes.c_int32), ("buffer_cells", ctypes.c_int32),
+        ("eta_h_buffer", ctypes.c_double),
         ("np_capacity", ctypes.c_int64),
     ]
+
+
+class HvpicInflow(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_double), ("ux", ctypes.c_double), ("uy", ctypes.c_double),
+                ("uz", ctypes.c_double), ("vth", ctypes.c_double), ("ppc", ctypes.c_int32),
+                ("faces", ctypes.c_int32)]
 
 
 class HvpicParticles(ctypes.Structure):
@@ -132,6 +143,11 @@ def lib():
                                              ctypes.c_float, vp]
         L.hvpic_no_conv3x3.argtypes = [i32, i32, i32, i32, i32, i32, vp, vp, vp, vp, vp, vp]
         L.hvpic_no_conv3x3_wgrad.argtypes = [i32, i32, i32, i32, i32, vp, vp, vp, vp, vp, vp]
+        L.hvpic_open_fill.argtypes = [vp, vp, i32]
+        L.hvpic_open_field_advance.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, i32, vp]
+        L.hvpic_open_particles.argtypes = [vp, P(HvpicParticles), P(HvpicInflow), ctypes.c_uint64,
+                                           ctypes.c_int64]
+        L.hvpic_sort_open.argtypes = [vp, P(HvpicParticles), P(HvpicParticles), vp]
         L.hvpic_strerror.argtypes = [ctypes.c_int]
         L.hvpic_strerror.restype = ctypes.c_char_p
         for f in EXPORTS[:-1]:
@@ -163,7 +179,8 @@ def params_from(cfg, np_capacity: int) -> HvpicParams:
     return HvpicParams(cfg.ndim, cfg.nx, cfg.ny, cfg.nz, cfg.dx, cfg.dy, cfg.dz, cfg.dt,
                        cfg.nsub, cfg.shape, cfg.nsmooth, cfg.qs, cfg.ms, cfg.te, cfg.gamma_e,
                        cfg.n0, cfg.n_floor, cfg.eta, cfg.eta_h, int(cfg.energy_eq),
-                       cfg.kappa0, int(np_capacity))
+                       cfg.kappa0, int(cfg.open_x), int(cfg.buffer_cells), cfg.eta_h_buffer,
+                       int(np_capacity))
 
 
 class Particles:
@@ -231,12 +248,14 @@ def hvpic_init(params: HvpicParams, stream, workspace: torch.Tensor):
     _check(lib().hvpic_init(ctypes.byref(params), s, _ptr(workspace, torch.uint8, need),
                             ctypes.byref(ctx)), "hvpic_init")
     _NCELL[ctx.value] = params.nx * params.ny * params.nz
+    _NPCAP[ctx.value] = params.np_capacity
     return ctx
 
 
 def hvpic_finalize(ctx):
     _check(lib().hvpic_finalize(ctx), "hvpic_finalize")
     _NCELL.pop(ctx.value, None)
+    _NPCAP.pop(ctx.value, None)
 
 
 def hvpic_set_stream(ctx, stream):
@@ -557,3 +576,58 @@ class Context:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------------------
+# Open boundaries in x (Sec. II.C)
+# ---------------------------------------------------------------------------
+
+def inflow_from(spec: dict) -> HvpicInflow:
+    """The C struct of an inflow spec {n, ux, uy, uz, vth, ppc, faces}."""
+    return HvpicInflow(float(spec["n"]), float(spec["ux"]), float(spec["uy"]), float(spec["uz"]),
+                       float(spec["vth"]), int(spec["ppc"]), int(spec["faces"]))
+
+
+def hvpic_open_fill(ctx, F, ncomp: int):
+    _check(lib().hvpic_open_fill(ctx, _ptr(F, torch.float32, _nc(ctx, ncomp)), int(ncomp)),
+           "hvpic_open_fill")
+
+
+def hvpic_open_field_advance(ctx, B0, B1, Btot, n_half, J_half, n_prev, J_prev, E_out, mode=0,
+                             diag_out=None):
+    v1, v3 = _nc(ctx), _nc(ctx, 3)
+    _check(lib().hvpic_open_field_advance(ctx, _ptr(B0, torch.float32, v3),
+                                          _ptr(B1, torch.float32, v3),
+                                          _ptr(Btot, torch.float32, v3),
+                                          _ptr(n_half, torch.float32, v1),
+                                          _ptr(J_half, torch.float32, v3),
+                                          _ptr(n_prev, torch.float32, v1),
+                                          _ptr(J_prev, torch.float32, v3),
+                                          _ptr(E_out, torch.float32, v3),
+                                          int(mode), _ptr(diag_out, torch.float64, 3)),
+           "hvpic_open_field_advance")
+
+
+def hvpic_open_particles(ctx, p: Particles, inflow: HvpicInflow, seed: int, step: int):
+    """Absorption and injection; p.n grows by the injected count.  The store
+    must hold the context's np_capacity ions (the injection appends up to it)."""
+    if ctx.value in _NPCAP and p.capacity < _NPCAP[ctx.value]:
+        raise HvpicError("hvpic_open_particles: the store holds fewer ions than np_capacity")
+    cp = p.c()
+    cp_cap = p.capacity
+    _check(lib().hvpic_open_particles(ctx, ctypes.byref(cp), ctypes.byref(inflow),
+                                      ctypes.c_uint64(seed & (2**64 - 1)), int(step)),
+           "hvpic_open_particles")
+    if cp.n > cp_cap:
+        raise HvpicError("hvpic_open_particles: store overflow")
+    p.n = cp.n
+
+
+def hvpic_sort_open(ctx, pin: Particles, pout: Particles, cell_start):
+    ci, co = pin.c(), pout.c()
+    if pout.capacity < pin.n:
+        raise HvpicError("output store too small")
+    ncs = None if _nc(ctx) is None else _nc(ctx) + 2
+    _check(lib().hvpic_sort_open(ctx, ctypes.byref(ci), ctypes.byref(co),
+                                 _ptr(cell_start, torch.int32, ncs)), "hvpic_sort_open")
+    pout.n = co.n

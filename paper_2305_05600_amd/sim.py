@@ -494,3 +494,118 @@ class Surrogate:
                                   idx[k], lr, losses[k:k + 1])
         return losses
 
+
+
+class OpenSim:
+    """The 2D step with open x boundaries (Sec. II.C) on the GPU.
+
+    The grid carries a ghost column at each x end (the config's open_x); the
+    field is B0 + B1 with B0 fixed.  One step, all on one stream:
+
+      1. hvpic_gather_push         E^n, B0 + B1^n at x^n; fused deposit of
+                                   n^{n+1/2}, J^{n+1/2}
+      2. hvpic_open_particles      ions in the ghost columns absorbed, fresh
+                                   ions injected through the faces
+      3. hvpic_sort_open           stable sort by cell, absorbed ions last
+      4. hvpic_open_fill           ghost columns of the moments
+      5. hvpic_open_field_advance  B1^n -> B1^{n+1}, E^{n+1}, B0 + B1^{n+1}
+
+    The live count is cell_start[ncell] of the sort: the one device-to-host
+    read of a step, taken while the field advance runs.  Initialisation as in
+    GpuSim (v^{-1/2} = v^0, moments deposited at x^0)."""
+
+    def __init__(self, cfg, parts: dict, B0, B1, spec: dict, seed: int, capacity: int | None = None,
+                 device="cuda", diagnostics: bool = True):
+        if not cfg.open_x or cfg.ndim != 2:
+            raise ValueError("OpenSim needs a 2D config with open_x")
+        self.cfg, self.spec, self.seed = cfg, spec, int(seed)
+        self.device = device
+        n = int(parts["cell"].size)
+        # room for the inflow to outrun the outflow for a while
+        cap = int(capacity) if capacity else 2 * n + 4 * cfg.ny * int(spec["ppc"]) + 4096
+        self.capacity = cap
+        self.s = torch.cuda.Stream(device)
+        self.ctx = H.Context(cfg, cap, device, stream=self.s)
+        self.inflow = H.inflow_from(spec)
+        nc = cfg.ncell
+        f32 = dict(dtype=torch.float32, device=device)
+        self.p = H.Particles.from_numpy(parts, 2, cap, device)
+        self.q = H.Particles(2, cap, device)
+        self.cs = torch.zeros(nc + 2, dtype=torch.int32, device=device)
+        self.B0 = torch.from_numpy(np.ascontiguousarray(B0, dtype=np.float32)).to(device)
+        self.B1 = torch.from_numpy(np.ascontiguousarray(B1, dtype=np.float32)).to(device)
+        self.Btot = torch.zeros((3, nc), **f32)
+        self.E = torch.zeros((3, nc), **f32)
+        self.n_prev = torch.zeros(nc, **f32)
+        self.J_prev = torch.zeros((3, nc), **f32)
+        self.n_half = torch.zeros(nc, **f32)
+        self.J_half = torch.zeros((3, nc), **f32)
+        self.diagnostics = diagnostics
+        self.push_diag = torch.zeros(4, dtype=torch.float64, device=device)
+        self.field_diag = torch.zeros(3, dtype=torch.float64, device=device)
+        self.h_count = torch.zeros(1, dtype=torch.int32, pin_memory=True)
+        self.ev_count = torch.cuda.Event()
+        torch.cuda.current_stream(device).synchronize()
+        c = self.ctx.ctx
+        H.hvpic_sort_open(c, self.p, self.q, self.cs)
+        self.p, self.q = self.q, self.p
+        self._read_count()
+        self.p.n = int(self.h_count[0])
+        H.hvpic_open_fill(c, self.B1, 3)
+        H.hvpic_deposit(c, self.p, self.cs[:nc + 1], 0.0, self.n_prev, self.J_prev)
+        H.hvpic_open_fill(c, self.n_prev, 1)
+        H.hvpic_open_fill(c, self.J_prev, 3)
+        H.hvpic_open_field_advance(c, self.B0, self.B1, self.Btot, self.n_prev, self.J_prev, None,
+                                   None, self.E, mode=1,
+                                   diag_out=self.field_diag if diagnostics else None)
+        self.s.synchronize()
+        self.nstep = 0
+        self.absorbed = self.injected = 0
+
+    def _read_count(self):
+        """Enqueues the copy of cell_start[ncell] (the live count) to the host."""
+        nc = self.cfg.ncell
+        with torch.cuda.stream(self.s):
+            self.h_count.copy_(self.cs[nc:nc + 1], non_blocking=True)
+            self.ev_count.record(self.s)
+
+    def step(self):
+        cfg = self.cfg
+        c = self.ctx.ctx
+        # writes by the caller's stream come first
+        self.s.wait_stream(torch.cuda.current_stream(self.device))
+        pd = self.push_diag if self.diagnostics else None
+        H.hvpic_gather_push(c, self.p, None, self.E, self.Btot, self.n_half, self.J_half, pd)
+        n_before = self.p.n
+        H.hvpic_open_particles(c, self.p, self.inflow, self.seed, self.nstep)
+        self.injected += self.p.n - n_before
+        total = self.p.n
+        H.hvpic_sort_open(c, self.p, self.q, self.cs)
+        self.p, self.q = self.q, self.p
+        self._read_count()
+        H.hvpic_open_fill(c, self.n_half, 1)
+        H.hvpic_open_fill(c, self.J_half, 3)
+        H.hvpic_open_field_advance(c, self.B0, self.B1, self.Btot, self.n_half, self.J_half,
+                                   self.n_prev, self.J_prev, self.E, mode=0,
+                                   diag_out=self.field_diag if self.diagnostics else None)
+        self.n_prev, self.n_half = self.n_half, self.n_prev
+        self.J_prev, self.J_half = self.J_half, self.J_prev
+        self.ev_count.synchronize()
+        alive = int(self.h_count[0])
+        self.absorbed += total - alive
+        self.p.n = alive
+        self.nstep += 1
+        torch.cuda.current_stream(self.device).wait_stream(self.s)
+
+    def synchronize(self):
+        torch.cuda.current_stream(self.device).synchronize()
+        self.s.synchronize()
+
+    def status(self):
+        self.synchronize()
+        return H.hvpic_sync_status(self.ctx.ctx)
+
+    def particles(self) -> dict:
+        """The live particle store in sorted order (host copy)."""
+        self.synchronize()
+        return self.p.to_numpy()

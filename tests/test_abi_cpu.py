@@ -39,8 +39,9 @@ def test_exports_every_declared_symbol(H):
 
 def test_struct_layout_matches_header(H):
     # hvpic_params: 4 int32, 4 double, 3 int32 (+pad), 8 double, int32 (+pad),
-    # double, int64
-    assert ctypes.sizeof(H.HvpicParams) == 16 + 32 + 16 + 64 + 16 + 8
+    # double, 2 int32, double, int64
+    assert ctypes.sizeof(H.HvpicParams) == 16 + 32 + 16 + 64 + 16 + 8 + 8 + 8
+    assert ctypes.sizeof(H.HvpicInflow) == 5 * 8 + 8
     text = (ROOT / "include" / "hvpic.h").read_text()
     body = text[text.index("typedef struct {"):text.index("} hvpic_params;")]
     fields = re.findall(r"(?:int32_t|int64_t|double)\s+([\w, ]+);", body)
@@ -57,14 +58,17 @@ def test_workspace_bytes_and_validation(H):
     bad = [dict(ndim=4), dict(nz=2), dict(dx=0.0), dict(dt=float("nan")), dict(shape=7),
            dict(n_floor=0.0), dict(eta_h=-1e-3), dict(eta_h=float("nan")),
            dict(energy_eq=2), dict(energy_eq=1, gamma_e=1.0), dict(energy_eq=1, gamma_e=0.5),
-           dict(kappa0=-0.1), dict(kappa0=float("inf")), dict(np_capacity=-1), dict(nsub=-1)]
+           dict(kappa0=-0.1), dict(kappa0=float("inf")), dict(np_capacity=-1), dict(nsub=-1),
+           dict(open_x=2), dict(open_x=1, nx=2), dict(open_x=1, ndim=3, nz=4),
+           dict(buffer_cells=-1), dict(eta_h_buffer=-0.1), dict(eta_h_buffer=float("nan"))]
     for b in bad:
         q = H.params_from(cfg, 65536)
         for k, v in b.items():
             setattr(q, k, v)
         n = ctypes.c_size_t(0)
         assert H.lib().hvpic_workspace_bytes(ctypes.byref(q), ctypes.byref(n)) == H.HVPIC_EINVAL, b
-    for good in (dict(eta_h=1e-3), dict(energy_eq=1, gamma_e=5.0 / 3.0, kappa0=0.1)):
+    for good in (dict(eta_h=1e-3), dict(energy_eq=1, gamma_e=5.0 / 3.0, kappa0=0.1),
+                 dict(open_x=1, buffer_cells=4, eta_h_buffer=0.02)):
         q = H.params_from(cfg, 65536)
         for k, v in good.items():
             setattr(q, k, v)
@@ -88,6 +92,11 @@ def test_init_rejects_bad_arguments_without_device_work(H):
     assert L.hvpic_field_advance_pe(None, None, None, None, None, None, None, None, 0,
                                     None) == H.HVPIC_ESTATE
     assert L.hvpic_eos_pressure(None, None, None) == H.HVPIC_ESTATE
+    assert L.hvpic_open_fill(None, None, 3) == H.HVPIC_ESTATE
+    assert L.hvpic_open_field_advance(None, None, None, None, None, None, None, None, None, 0,
+                                      None) == H.HVPIC_ESTATE
+    assert L.hvpic_open_particles(None, None, None, 0, 0) == H.HVPIC_ESTATE
+    assert L.hvpic_sort_open(None, None, None, None) == H.HVPIC_ESTATE
     assert H.hvpic_strerror(H.HVPIC_EINVAL) == "invalid argument"
     assert L.hvpic_set_stream(None, None) == H.HVPIC_ESTATE
     assert L.hvpic_timing_enable(None, 4, 1) == H.HVPIC_ESTATE
