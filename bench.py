@@ -8,7 +8,10 @@ cell (134,217,728 particles), QS shape, 4 B-subcycles.  --workload ensemble:
 64 independent 2D periodic runs of uneven size stepped together (see
 bench_ensemble).  --workload surrogate: the Harris workload with the field
 subcycle replaced by the trained neural operator where its proposal passes
-the residual test (see bench_surrogate).  One step = gather +
+the residual test (see bench_surrogate).  --workload open: the 2D solar-wind
+box open in x, 800x1600 cells, 100 ions per cell (128,000,000), NGP, 5
+B-subcycles, with absorption and injection every step (see bench_open).
+One step = gather +
 push + fused mid-point deposit, neighbour-move sort, field advance (Ohm + RK2
 Faraday subcycle + extrapolation), FP64 diagnostics.
 
@@ -409,6 +412,131 @@ def bench_surrogate(args) -> dict:
     return out
 
 
+def bench_open(args) -> dict:
+    """The open solar-wind box (W.solar_wind_box: the Sec. III.A
+    magnetosphere run without its planet, open x boundaries of Sec. II.C).
+    One step = gather + push + fused deposit, absorption and injection, the
+    sort with the absorbed ions last, the moments' ghost fill, the open
+    field advance of B1 (sim.OpenSim).  `value` counts the ions pushed per
+    second (the live count of each step).  The roofline is the push's, as
+    for the periodic workloads.  The oracle's sample is a 200x400 box of the
+    same recipe, cleaned of face straddlers for the one-step error."""
+    import contextlib
+
+    import numpy as np
+    import torch
+
+    from paper_2305_05600_amd import hvpic as H
+    from paper_2305_05600_amd import sim as S
+    from paper_2305_05600_amd import workloads as W
+
+    seed = 12
+    cfg, parts, B0, B1, spec = W.solar_wind_box()
+    sample = W.solar_wind_box(nx=200, ny=400)
+    dropped = first_gpu = None
+    if not args.no_cpu_baseline:
+        from tests.helpers import drop_open_straddlers
+
+        with contextlib.redirect_stdout(sys.stderr):
+            clean = drop_open_straddlers(*sample, seed)
+        dropped = int(sample[1]["cell"].size - clean["cell"].size)
+        sample = (sample[0], clean) + tuple(sample[2:])
+        g1 = S.OpenSim(*sample, seed, gather_map=not args.no_gather_map)
+        g1.step()
+        g1.synchronize()
+        first_gpu = {"n": g1.n_prev.cpu().numpy(), "J": g1.J_prev.cpu().numpy(),
+                     "B1": g1.B1.cpu().numpy(), "E": g1.E.cpu().numpy()}
+        del g1
+    n0 = int(parts["cell"].size)
+    print(f"# workload {cfg.name}: {n0} particles, {cfg.ncell} cells", file=sys.stderr,
+          flush=True)
+    g = S.OpenSim(cfg, parts, B0, B1, spec, seed, gather_map=not args.no_gather_map)
+    del parts
+    for _ in range(args.warmup):
+        g.step()
+    g.synchronize()
+    c = g.ctx.ctx
+    every = timing_stride(args.steps, args.time_every)
+    n_timed = (args.steps + every - 1) // every
+    H.hvpic_timing_enable(c, n_timed, every)
+    pushed = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        pushed += g.live
+        g.step()
+    g.synchronize()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    k_ms, k_launches = H.hvpic_timing_read(c, H.KERNEL_GATHER_PUSH)
+    H.hvpic_timing_enable(c, 0)
+    assert k_launches == n_timed, (k_launches, n_timed)
+    kernel_ms = k_ms / k_launches
+    flags, counts = g.status()
+    n = g.live
+    per_launch = BYTES_PER_PARTICLE[2] * n + BYTES_PER_CELL * cfg.ncell
+    achieved = per_launch / (kernel_ms * 1e-3) / 1e9
+    out = {
+        "metric": METRIC,
+        "value": pushed / wall,
+        "unit": "pushes/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": cfg.name, "cells": [cfg.nx, cfg.ny],
+                   "ghost_columns": 2, "particles_start": n0, "particles_end": n,
+                   "shape": "NGP", "b_subcycles": cfg.nsub, "dt": cfg.dt,
+                   "inflow": spec, "buffer_cells": cfg.buffer_cells,
+                   "eta_h_buffer": cfg.eta_h_buffer,
+                   "absorbed_total": g.absorbed, "injected_total": g.injected,
+                   "steps_run": g.nstep},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": ("k_gather_push (fused deposit, read through the gather map)"
+                                if g.gather_map else "k_gather_push (fused deposit, in place)"),
+                     "kernel_ms": kernel_ms,
+                     "kernel_timed_launches": f"{k_launches} of {args.steps} (every {every})",
+                     "algorithmic_bytes_per_launch": per_launch},
+        "status_flags": flags,
+        "general_path_steps": g.fallbacks,
+    }
+    if not args.no_cpu_baseline:
+        import oracle as O
+
+        sim = O.OpenOracleSim(*sample, seed)
+        steps = 3
+        t0 = time.perf_counter()
+        first = None
+        npush = 0
+        for k in range(steps):
+            npush += sim.p["cell"].size
+            sim.step()
+            if k == 0:
+                t_pause = time.perf_counter()
+                first = {"n": sim.n_prev.copy(), "J": sim.J_prev.copy(), "B1": sim.B1.copy(),
+                         "E": sim.E.copy()}
+                t0 += time.perf_counter() - t_pause
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {
+            "value": npush / dt, "unit": "pushes/s", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} full FP64 open steps (push, deposit, absorption, injection, "
+                      f"sort, field advance) of the {sample[0].name} box, "
+                      f"{sample[1]['cell'].size} particles, single-threaded, {dt:.1f} s",
+            "steps": steps, "host_cpu": _host_cpu(), "host_threads": os.cpu_count()}
+        out["one_step_rel_l2_vs_oracle_case"] = (
+            f"{sample[0].name} without {dropped} face straddlers")
+        out["one_step_rel_l2_vs_oracle"] = {
+            k: float(np.linalg.norm(first_gpu[k] - first[k]) / np.linalg.norm(first[k]))
+            for k in ("n", "J", "B1", "E")}
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -418,10 +546,11 @@ def main() -> int:
     ap.add_argument("--no-lr", type=float, default=1e-3, help="surrogate: Adam rate")
     ap.add_argument("--no-tol", type=float, default=1e-2, help="surrogate: residual tolerance")
     ap.add_argument("--seed", type=int, default=7, help="surrogate: starting weights")
-    ap.add_argument("--workload", choices=("harris", "beam3d", "ensemble", "surrogate"),
+    ap.add_argument("--workload", choices=("harris", "beam3d", "ensemble", "surrogate", "open"),
                     default="harris",
                     help="harris: 2D double Harris sheet 512x256, 13.1M ions; beam3d: 3D core + "
-                         "beam 128^3, 134M ions; ensemble: 64 independent 2D runs of uneven size")
+                         "beam 128^3, 134M ions; ensemble: 64 independent 2D runs of uneven size; "
+                         "open: 2D solar-wind box open in x, 800x1600, 128M ions")
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -447,6 +576,9 @@ def main() -> int:
         return 0
     if args.workload == "surrogate":
         print(json.dumps(bench_surrogate(args)), flush=True)
+        return 0
+    if args.workload == "open":
+        print(json.dumps(bench_open(args)), flush=True)
         return 0
 
     import numpy as np

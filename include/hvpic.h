@@ -204,6 +204,16 @@ int hvpic_gather_push_perm(hvpic_ctx* ctx, const hvpic_particles* in, const int3
                            hvpic_particles* out, const int32_t* cell_start, const float* E,
                            const float* B, float* n_mid, float* J_mid, double* diag_out);
 
+/* hvpic_gather_push_perm for a map that selects n_map (<= in->n) of the
+   in->n ions of `in` (its entries index below in->n): pushes those n_map
+   in map order into out (out->n = n_map).  The open step's map leaves
+   absorbed ions out and takes the injected ones, which sit past the
+   pushed ones in the store. */
+int hvpic_gather_push_select(hvpic_ctx* ctx, const hvpic_particles* in, int64_t n_map,
+                             const int32_t* perm, hvpic_particles* out,
+                             const int32_t* cell_start, const float* E, const float* B,
+                             float* n_mid, float* J_mid, double* diag_out);
+
 /* Moments of the ion species (Sec. II.A n_e, J_i; eq:ngp / eq:quad) at
    x - half_dt_back * v (half_dt_back = dt/2 after a push gives
    x^{n+1/2}; 0 deposits at x).  Contributions per particle: n += qs w W/V_c,
@@ -507,10 +517,14 @@ int hvpic_no_conv3x3_wgrad(int nimg, int nx, int ny, int cinp, int coutp, const 
  * there).  A layer of buffer_cells cells at each boundary adds
  * eta_h_buffer (1 - d/buffer_cells) to eta_h, d = 0 at the outermost
  * interior column.  The push, the deposit and the sort run unchanged on this
- * grid (their periodic wrap only ever joins the two ghost columns); one step
- * is: hvpic_gather_push with E and B0 + B1 (cell_start NULL, fused deposit);
- * hvpic_open_particles; hvpic_sort_open; the count n = cell_start[ncell];
- * hvpic_open_fill of the moments; hvpic_open_field_advance.
+ * grid (their periodic wrap only ever joins the two ghost columns).  One
+ * step in the gather-map form: hvpic_gather_push_perm with E and B0 + B1
+ * (counting moves, fused deposit) into the second store; hvpic_open_inject
+ * appends the fresh ions to it; hvpic_sort_open_perm orders it, leaving the
+ * absorbed ions out, and its info gives the live count; hvpic_open_fill of
+ * the moments; hvpic_open_field_advance.  When the sort reports that it
+ * could not take its neighbour path (far movers), hvpic_open_absorb and
+ * hvpic_sort_open (the general radix path) order the store instead.
  * ------------------------------------------------------------------------- */
 
 /* Drifting Maxwellian of the inflow: density n, drift (ux, uy, uz) (ux > 0
@@ -542,6 +556,31 @@ int hvpic_open_fill(hvpic_ctx* ctx, float* F, int ncomp);
 int hvpic_open_field_advance(hvpic_ctx* ctx, const float* B0, float* B1, float* Btot,
                              const float* n_half, const float* J_half, const float* n_prev,
                              const float* J_prev, float* E_out, int mode, double* diag_out);
+
+/* Absorption: every ion of p in a ghost column gets the key ncell (the
+   general path's mark; hvpic_sort_open puts such ions last). */
+int hvpic_open_absorb(hvpic_ctx* ctx, hvpic_particles* p);
+
+/* Injection alone (hvpic_open_particles without the absorption), recorded
+   for the next hvpic_sort_open_perm of the same store. */
+int hvpic_open_inject(hvpic_ctx* ctx, hvpic_particles* p, const hvpic_inflow* in, uint64_t seed,
+                      int64_t step);
+
+/* The neighbour-move sort of the open step as a gather map (as
+   hvpic_sort_perm): in's first n_pushed ions are the store that the
+   counting push wrote in the order of cell_start_prev [ncell+1], moved by
+   at most one cell; the ions after them (in->n - n_pushed) must be those
+   the last hvpic_open_inject appended to this store.  Ions now in a ghost
+   column are absorbed: left out of the order.  Writes perm[0 .. live) and
+   cell_start [ncell+1] (cell_start[ncell] = live); each cell holds its
+   moved ions in input order, then its injected ones.  info (device int32[2],
+   may be NULL): info[0] = 1 when a far mover or an inconsistent
+   cell_start_prev keeps the sort from its neighbour path (then nothing
+   else is written and the caller takes the general path), else 0;
+   info[1] = live. */
+int hvpic_sort_open_perm(hvpic_ctx* ctx, const hvpic_particles* in, int64_t n_pushed,
+                         const int32_t* cell_start_prev, int32_t* perm, int32_t* cell_start,
+                         int32_t* info);
 
 /* Absorption and injection of one step: every ion of p in a ghost column
    gets the key ncell (absorbed; hvpic_sort_open puts it last), then

@@ -109,6 +109,7 @@ Layout workspace_layout(const hvpic_params* p) {
   L.rhist = off;     off += align256(sizeof(uint32_t) * kRadixBins * ntiles);
   L.fscratch = off;  off += align256(sizeof(float) * 25 * nc);
   L.mom_acc = off;   off += align256(sizeof(double) * 4 * nc);
+  L.open_rows = off; off += align256(p->open_x ? sizeof(int32_t) * 3 * 2 * (size_t)p->ny : 0);
   L.total = off;
   return L;
 }
@@ -158,6 +159,7 @@ int hvpic_init(const hvpic_params* params, void* hip_stream, void* workspace, hv
   c->rhist = (uint32_t*)(c->ws + L.rhist);
   c->fscratch = (float*)(c->ws + L.fscratch);
   c->mom_acc = (double*)(c->ws + L.mom_acc);
+  c->open_rows = params->open_x ? (int32_t*)(c->ws + L.open_rows) : nullptr;
   hipLaunchKernelGGL(k_init_ws, dim3(256), dim3(256), 0, c->stream, c->status, c->mom_acc,
                      4ll * c->ncell, c->sort_cnt,
                      (int64_t)c->ncell * (params->ndim == 2 ? 9 : 27));
@@ -203,6 +205,25 @@ int hvpic_gather_push_perm(hvpic_ctx* ctx, const hvpic_particles* in, const int3
       return HVPIC_EINVAL;
   }
   return launch_gather_push_perm(ctx, in, perm, out, cell_start, E, B, n_mid, J_mid, diag_out);
+}
+int hvpic_gather_push_select(hvpic_ctx* ctx, const hvpic_particles* in, int64_t n_map,
+                             const int32_t* perm, hvpic_particles* out,
+                             const int32_t* cell_start, const float* E, const float* B,
+                             float* n_mid, float* J_mid, double* diag_out) {
+  if (!ctx_ok(ctx)) return HVPIC_ESTATE;
+  if (!parts_ok(ctx, in, true) || !out || !E || !B) return HVPIC_EINVAL;
+  if (n_map < 0 || n_map > in->n) return HVPIC_EINVAL;
+  if ((n_mid == nullptr) != (J_mid == nullptr)) return HVPIC_EINVAL;
+  if (n_map > 0) {
+    if (!perm || !out->cell || !out->ox || !out->oy || !out->ux || !out->uy || !out->uz ||
+        !out->w)
+      return HVPIC_EINVAL;
+    if (ctx->p.ndim == 3 && !out->oz) return HVPIC_EINVAL;
+    if (out->cell == in->cell || out->ox == in->ox || out->ux == in->ux || out->w == in->w)
+      return HVPIC_EINVAL;
+  }
+  return launch_gather_push_select(ctx, in, n_map, perm, out, cell_start, E, B, n_mid, J_mid,
+                                   diag_out);
 }
 int hvpic_sort_perm(hvpic_ctx* ctx, const hvpic_particles* in, const int32_t* cell_start_prev,
                     int32_t* perm, int32_t* cell_start) {

@@ -182,6 +182,12 @@ struct hvpic_ctx {
   const int32_t* cnt_cell;
   const int32_t* cnt_cs;
   int64_t cnt_n;
+  // open boundaries: per face row the injected count, its offset within
+  // the injected block and the first slot in the sorted order [3][2][ny]
+  int32_t* open_rows;
+  // the last injection: the store it appended to, its size before, count
+  const int32_t* inj_cell;
+  int64_t inj_n0, inj_k;
   // optional per-kernel timing: event pairs [kernel][slot][2]
   hipEvent_t* tev;
   int tmax;
@@ -202,11 +208,18 @@ int launch_gather_push(hvpic_ctx* c, hvpic_particles* p, const int32_t* cell_sta
 int launch_gather_push_perm(hvpic_ctx* c, const hvpic_particles* in, const int32_t* perm,
                             hvpic_particles* out, const int32_t* cell_start, const float* E,
                             const float* B, float* n_mid, float* J_mid, double* diag_out);
+int launch_gather_push_select(hvpic_ctx* c, const hvpic_particles* in, int64_t n_map,
+                              const int32_t* perm, hvpic_particles* out,
+                              const int32_t* cell_start, const float* E, const float* B,
+                              float* n_mid, float* J_mid, double* diag_out);
 int launch_deposit(hvpic_ctx* c, const hvpic_particles* p, const int32_t* cell_start,
                    float half_dt_back, float* n, float* J);
 int launch_sort(hvpic_ctx* c, const hvpic_particles* in, hvpic_particles* out,
                 const int32_t* cs_prev, int32_t* cs, int full);
 int launch_sort_open(hvpic_ctx* c, const hvpic_particles* in, hvpic_particles* out, int32_t* cs);
+int launch_sort_open_perm(hvpic_ctx* c, const hvpic_particles* in, int64_t n_pushed,
+                          const int32_t* cs_prev, int32_t* perm, int32_t* cs, int32_t* info,
+                          const int32_t* inj_cnt, const int32_t* inj_off, int32_t* inj_base);
 int launch_sort_perm(hvpic_ctx* c, const hvpic_particles* in, const int32_t* cs_prev,
                      int32_t* perm, int32_t* cs);
 int launch_field_advance(hvpic_ctx* c, float* B, const float* n_half, const float* J_half,
@@ -295,7 +308,7 @@ int launch_init_workspace(hvpic_ctx* c);
 // Workspace layout (bytes from the start; each region 256-byte aligned).
 struct Layout {
   size_t status, push_part, field_part, sort_cnt, sort_blk, rkey0, rkey1, rval0, rval1, rhist,
-      fscratch, mom_acc, total;
+      fscratch, mom_acc, open_rows, total;
 };
 Layout workspace_layout(const hvpic_params* p);
 

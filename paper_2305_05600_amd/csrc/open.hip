@@ -306,67 +306,87 @@ struct Inject {
   int64_t step, n0;
 };
 
-// One block: per (face, row) the count floor(nexp + U), an exclusive scan
-// over the rows in order (face-major), then each row's ions appended after
-// the n0 stored ones.
-__global__ __launch_bounds__(1024) void k_open_inject(Inject P, int32_t* __restrict__ cell,
-                                                     float* __restrict__ ox, float* __restrict__ oy,
-                                                     float* __restrict__ ux, float* __restrict__ uy,
-                                                     float* __restrict__ uz, float* __restrict__ w) {
-  __shared__ int64_t s_sum[1024];
-  __shared__ int64_t s_carry;
+// One block: per (face, row) the count floor(nexp + U) and its exclusive
+// prefix over the rows in order (face-major): the injected ions of row r
+// are stored from n0 + off[r].
+__global__ __launch_bounds__(1024) void k_open_inject_count(Inject P, int32_t* __restrict__ cnt,
+                                                           int32_t* __restrict__ off) {
+  __shared__ int32_t s_sum[1024];
+  __shared__ int32_t s_carry;
   if (threadIdx.x == 0) s_carry = 0;
   __syncthreads();
   const int rows = 2 * P.ny;
   for (int r0 = 0; r0 < rows; r0 += 1024) {
     const int r = r0 + (int)threadIdx.x;
-    int64_t k = 0;
-    int f = 0, j = 0;
+    int k = 0;
     if (r < rows) {
-      f = r / P.ny;
-      j = r - f * P.ny;
+      const int f = r / P.ny, j = r - f * P.ny;
       if ((P.faces >> f) & 1)
-        k = (int64_t)floor(P.nexp[f] + uniform01(P.seed, draw_ctr(P.step, f, j, 0, 127)));
+        k = (int)floor(P.nexp[f] + uniform01(P.seed, draw_ctr(P.step, f, j, 0, 127)));
     }
     // inclusive scan over the block (Hillis-Steele in LDS)
     s_sum[threadIdx.x] = k;
     __syncthreads();
     for (int o = 1; o < 1024; o <<= 1) {
-      const int64_t add = threadIdx.x >= (unsigned)o ? s_sum[threadIdx.x - o] : 0;
+      const int add = threadIdx.x >= (unsigned)o ? s_sum[threadIdx.x - o] : 0;
       __syncthreads();
       s_sum[threadIdx.x] += add;
       __syncthreads();
     }
-    const int64_t base = P.n0 + s_carry + s_sum[threadIdx.x] - k;
-    const int64_t chunk = s_sum[1023];
-    const int col = f == 0 ? 1 : P.nx - 2;
-    const int32_t c = col + P.nx * j;
-    for (int64_t m = 0; m < k; ++m) {
-      const double v = inflow_speed(P.un[f], P.vth, uniform01(P.seed, draw_ctr(P.step, f, j, m, 0)));
-      const double vy = P.uy + P.vth * normal_draw(P.seed, P.step, f, j, m, 96);
-      const double vz = P.uz + P.vth * normal_draw(P.seed, P.step, f, j, m, 98);
-      const double s = v * P.dt * uniform01(P.seed, draw_ctr(P.step, f, j, m, 100));
-      double o = -1.0 + 2.0 * s / P.dx;
-      if (o >= 1.0) o = 1.0 - 1e-7;
-      double xo = f == 0 ? o : -o;
-      if (xo >= 1.0) xo = 1.0 - 1e-7;
-      float fx = (float)xo;
-      if (fx >= 1.0f) fx = 0.99999994f;
-      float fy = (float)(-1.0 + 2.0 * uniform01(P.seed, draw_ctr(P.step, f, j, m, 101)));
-      if (fy >= 1.0f) fy = 0.99999994f;
-      const int64_t q = base + m;
-      cell[q] = c;
-      ox[q] = fx;
-      oy[q] = fy;
-      ux[q] = (float)(f == 0 ? v : -v);
-      uy[q] = (float)vy;
-      uz[q] = (float)vz;
-      w[q] = (float)P.w;
+    if (r < rows) {
+      cnt[r] = k;
+      off[r] = s_carry + s_sum[threadIdx.x] - k;
     }
+    const int chunk = s_sum[1023];
     __syncthreads();
     if (threadIdx.x == 0) s_carry += chunk;
     __syncthreads();
   }
+}
+
+// One thread per injected ion t < total: its row r is the last with
+// off[r] <= t (that row holds it: off[r+1] = off[r] + cnt[r] > t), its rank
+// m = t - off[r]; the ion's draws are those of (step, face, row, m).
+__global__ __launch_bounds__(256) void k_open_inject_draw(Inject P, const int32_t* __restrict__ off,
+                                                         int64_t total, int32_t* __restrict__ cell,
+                                                         float* __restrict__ ox,
+                                                         float* __restrict__ oy,
+                                                         float* __restrict__ ux,
+                                                         float* __restrict__ uy,
+                                                         float* __restrict__ uz,
+                                                         float* __restrict__ w) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= total) return;
+  int lo = 0, hi = 2 * P.ny - 1;  // off[0] = 0 <= t
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if ((int64_t)off[mid] <= t)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const int r = lo, f = r / P.ny, j = r - f * P.ny;
+  const int64_t m = t - off[r];
+  const double v = inflow_speed(P.un[f], P.vth, uniform01(P.seed, draw_ctr(P.step, f, j, m, 0)));
+  const double vy = P.uy + P.vth * normal_draw(P.seed, P.step, f, j, m, 96);
+  const double vz = P.uz + P.vth * normal_draw(P.seed, P.step, f, j, m, 98);
+  const double s = v * P.dt * uniform01(P.seed, draw_ctr(P.step, f, j, m, 100));
+  double o = -1.0 + 2.0 * s / P.dx;
+  if (o >= 1.0) o = 1.0 - 1e-7;
+  double xo = f == 0 ? o : -o;
+  if (xo >= 1.0) xo = 1.0 - 1e-7;
+  float fx = (float)xo;
+  if (fx >= 1.0f) fx = 0.99999994f;
+  float fy = (float)(-1.0 + 2.0 * uniform01(P.seed, draw_ctr(P.step, f, j, m, 101)));
+  if (fy >= 1.0f) fy = 0.99999994f;
+  const int64_t q = P.n0 + t;
+  cell[q] = (f == 0 ? 1 : P.nx - 2) + P.nx * j;
+  ox[q] = fx;
+  oy[q] = fy;
+  ux[q] = (float)(f == 0 ? v : -v);
+  uy[q] = (float)vy;
+  uz[q] = (float)vz;
+  w[q] = (float)P.w;
 }
 
 // host: the expected count per row and step of a face, and the total of a
@@ -395,6 +415,64 @@ void fill(hvpic_ctx* c, float* F, int ncomp) {
 }
 
 bool open_ok(const hvpic_ctx* c) { return c && c->magic == kMagic && c->p.open_x == 1; }
+
+// Checks and the host's count of an injection (the kernel draws the same
+// counts): HVPIC_OK with the kernel arguments and the total, else the error
+// (nothing launched).
+int inject_plan(hvpic_ctx* c, const hvpic_particles* p, const hvpic_inflow* in, uint64_t seed,
+                int64_t step, Inject& P, int64_t& total) {
+  if (!open_ok(c) || !p || !in || step < 0 || step >= (int64_t(1) << 20)) return HVPIC_EINVAL;
+  if (p->n < 0 || p->n > c->p.np_capacity || !p->cell || !p->ox || !p->oy || !p->ux || !p->uy ||
+      !p->uz || !p->w)
+    return HVPIC_EINVAL;
+  if (!(in->n > 0.0) || !(in->vth > 0.0) || !isfinite(in->n) || !isfinite(in->vth) ||
+      in->ppc < 1 || !isfinite(in->ux) || !isfinite(in->uy) || !isfinite(in->uz) ||
+      in->faces < 0 || in->faces > 3 || c->p.ny > 65535)
+    return HVPIC_EINVAL;
+  for (int f = 0; f < 2; ++f) {
+    P.un[f] = f == 0 ? in->ux : -in->ux;
+    P.nexp[f] = in->ppc * c->p.dt / c->p.dx * inflow_flux_host(P.un[f], in->vth);
+  }
+  P.uy = in->uy;
+  P.uz = in->uz;
+  P.vth = in->vth;
+  P.dt = c->p.dt;
+  P.dx = c->p.dx;
+  P.w = in->n * c->p.dx * c->p.dy * c->p.dz / in->ppc;
+  P.faces = in->faces;
+  P.nx = c->p.nx;
+  P.ny = c->p.ny;
+  P.seed = seed;
+  P.step = step;
+  P.n0 = p->n;
+  total = 0;
+  for (int f = 0; f < 2; ++f) {
+    if (!((in->faces >> f) & 1)) continue;
+    for (int j = 0; j < c->p.ny; ++j) {
+      const int64_t k = (int64_t)floor(P.nexp[f] + uniform01(seed, draw_ctr(step, f, j, 0, 127)));
+      if (k >= (int64_t(1) << 20)) return HVPIC_EINVAL;  // beyond the counter's ion field
+      total += k;
+    }
+  }
+  if (p->n + total > c->p.np_capacity) return HVPIC_ENOMEM;
+  return HVPIC_OK;
+}
+
+// Enqueues a planned injection and records it for hvpic_sort_open_perm.
+void inject_launch(hvpic_ctx* c, hvpic_particles* p, const Inject& P, int64_t total) {
+  c->inj_cell = p->cell;
+  c->inj_n0 = p->n;
+  c->inj_k = total;
+  if (total > 0) {
+    int32_t* cnt = c->open_rows;
+    int32_t* off = c->open_rows + 2 * c->p.ny;
+    hipLaunchKernelGGL(k_open_inject_count, dim3(1), dim3(1024), 0, c->stream, P, cnt, off);
+    hipLaunchKernelGGL(k_open_inject_draw, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0,
+                       c->stream, P, (const int32_t*)off, total, p->cell, p->ox, p->oy, p->ux,
+                       p->uy, p->uz, p->w);
+  }
+  p->n += total;
+}
 
 }  // namespace
 }  // namespace hvpic
@@ -491,56 +569,59 @@ int hvpic_open_field_advance(hvpic_ctx* ctx, const float* B0, float* B1, float* 
   return hipGetLastError() == hipSuccess ? HVPIC_OK : HVPIC_EHIP;
 }
 
+int hvpic_open_absorb(hvpic_ctx* ctx, hvpic_particles* p) {
+  if (!ctx || ctx->magic != kMagic) return HVPIC_ESTATE;
+  if (!open_ok(ctx) || !p || p->n < 0 || p->n > ctx->p.np_capacity || (p->n > 0 && !p->cell))
+    return HVPIC_EINVAL;
+  if (p->n > 0)
+    hipLaunchKernelGGL(k_open_absorb, dim3((unsigned)ceil_div(p->n, 256)), dim3(256), 0,
+                       ctx->stream, p->cell, p->n, ctx->p.nx, ctx->ncell);
+  return hipGetLastError() == hipSuccess ? HVPIC_OK : HVPIC_EHIP;
+}
+
+int hvpic_open_inject(hvpic_ctx* ctx, hvpic_particles* p, const hvpic_inflow* in, uint64_t seed,
+                      int64_t step) {
+  if (!ctx || ctx->magic != kMagic) return HVPIC_ESTATE;
+  Inject P;
+  int64_t total = 0;
+  const int rc = inject_plan(ctx, p, in, seed, step, P, total);
+  if (rc != HVPIC_OK) return rc;
+  inject_launch(ctx, p, P, total);
+  return hipGetLastError() == hipSuccess ? HVPIC_OK : HVPIC_EHIP;
+}
+
 int hvpic_open_particles(hvpic_ctx* ctx, hvpic_particles* p, const hvpic_inflow* in,
                          uint64_t seed, int64_t step) {
   if (!ctx || ctx->magic != kMagic) return HVPIC_ESTATE;
-  if (!open_ok(ctx) || !p || !in || step < 0 || step >= (int64_t(1) << 20)) return HVPIC_EINVAL;
-  if (p->n < 0 || p->n > ctx->p.np_capacity || !p->cell || !p->ox || !p->oy || !p->ux || !p->uy ||
-      !p->uz || !p->w)
-    return HVPIC_EINVAL;
-  if (!(in->n > 0.0) || !(in->vth > 0.0) || !isfinite(in->n) || !isfinite(in->vth) ||
-      in->ppc < 1 || !isfinite(in->ux) || !isfinite(in->uy) || !isfinite(in->uz) ||
-      in->faces < 0 || in->faces > 3 ||
-      ctx->p.ny > 65535)
-    return HVPIC_EINVAL;
-  hvpic_ctx* c = ctx;
-  hipStream_t s = c->stream;
-  if (p->n > 0)
-    hipLaunchKernelGGL(k_open_absorb, dim3((unsigned)ceil_div(p->n, 256)), dim3(256), 0, s,
-                       p->cell, p->n, c->p.nx, c->ncell);
   Inject P;
-  for (int f = 0; f < 2; ++f) {
-    P.un[f] = f == 0 ? in->ux : -in->ux;
-    P.nexp[f] = in->ppc * c->p.dt / c->p.dx * inflow_flux_host(P.un[f], in->vth);
-  }
-  P.uy = in->uy;
-  P.uz = in->uz;
-  P.vth = in->vth;
-  P.dt = c->p.dt;
-  P.dx = c->p.dx;
-  P.w = in->n * c->p.dx * c->p.dy * c->p.dz / in->ppc;
-  P.faces = in->faces;
-  P.nx = c->p.nx;
-  P.ny = c->p.ny;
-  P.seed = seed;
-  P.step = step;
-  P.n0 = p->n;
-  // the same counts as the kernel, on the host
   int64_t total = 0;
-  for (int f = 0; f < 2; ++f) {
-    if (!((in->faces >> f) & 1)) continue;
-    for (int j = 0; j < c->p.ny; ++j) {
-      const int64_t k = (int64_t)floor(P.nexp[f] + uniform01(seed, draw_ctr(step, f, j, 0, 127)));
-      if (k >= (int64_t(1) << 20)) return HVPIC_EINVAL;  // beyond the counter's ion field
-      total += k;
-    }
-  }
-  if (p->n + total > c->p.np_capacity) return HVPIC_ENOMEM;
-  if (total > 0)
-    hipLaunchKernelGGL(k_open_inject, dim3(1), dim3(1024), 0, s, P, p->cell, p->ox, p->oy, p->ux,
-                       p->uy, p->uz, p->w);
-  p->n += total;
+  const int rc = inject_plan(ctx, p, in, seed, step, P, total);
+  if (rc != HVPIC_OK) return rc;
+  if (p->n > 0)
+    hipLaunchKernelGGL(k_open_absorb, dim3((unsigned)ceil_div(p->n, 256)), dim3(256), 0,
+                       ctx->stream, p->cell, p->n, ctx->p.nx, ctx->ncell);
+  inject_launch(ctx, p, P, total);
   return hipGetLastError() == hipSuccess ? HVPIC_OK : HVPIC_EHIP;
+}
+
+int hvpic_sort_open_perm(hvpic_ctx* ctx, const hvpic_particles* in, int64_t n_pushed,
+                         const int32_t* cell_start_prev, int32_t* perm, int32_t* cell_start,
+                         int32_t* info) {
+  if (!ctx || ctx->magic != kMagic) return HVPIC_ESTATE;
+  if (!open_ok(ctx) || !in || !cell_start_prev || !cell_start) return HVPIC_EINVAL;
+  if (in->n < 0 || in->n > ctx->p.np_capacity || n_pushed < 0 || n_pushed > in->n)
+    return HVPIC_EINVAL;
+  if (in->n > 0 && (!in->cell || !perm)) return HVPIC_EINVAL;
+  hvpic_ctx* c = ctx;
+  const int32_t* inj_cnt = nullptr;
+  if (in->n > n_pushed) {
+    // the ions past n_pushed must be the last injection into this store
+    if (c->inj_cell != in->cell || c->inj_n0 != n_pushed || c->inj_n0 + c->inj_k != in->n)
+      return HVPIC_EINVAL;
+    inj_cnt = c->open_rows;
+  }
+  return launch_sort_open_perm(c, in, n_pushed, cell_start_prev, perm, cell_start, info, inj_cnt,
+                               c->open_rows + 2 * c->p.ny, c->open_rows + 4 * c->p.ny);
 }
 
 }  // extern "C"

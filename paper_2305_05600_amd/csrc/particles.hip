@@ -81,6 +81,7 @@ struct PushArgs {
   // the source arrays below, and the pushed store (weights included) goes to
   // the arrays above.  perm null: the store above is read and written in place.
   const int32_t* perm;
+  int64_t nsrc;             // elements of the source arrays (map entries index below it)
   const int32_t* icell;
   const float *iox, *ioy, *ioz, *iux, *iuy, *iuz, *iw;
   float* wo;
@@ -811,8 +812,8 @@ __device__ __forceinline__ void load_group_perm(const PushArgs& A, int64_t b4, i
   bool bad = false;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    bad |= (uint32_t)src[q] >= (uint32_t)A.n;
-    src[q] = (uint32_t)src[q] >= (uint32_t)A.n ? 0 : src[q];
+    bad |= (uint32_t)src[q] >= (uint32_t)A.nsrc;
+    src[q] = (uint32_t)src[q] >= (uint32_t)A.nsrc ? 0 : src[q];
   }
   if (__ballot(bad) != 0) {
     if (bad) raise_flag(A.st, HVPIC_FLAG_BAD_INPUT, &A.st->bad_input);
@@ -1097,8 +1098,8 @@ __device__ __forceinline__ void push_chunk(const PushArgs& A, int chunk, int nb)
     if (PM != 0) {
       // (entries outside [0, n) are flagged where the particles are loaded)
       const uint32_t e0 = (uint32_t)A.perm[base], e1 = (uint32_t)A.perm[end - 1];
-      s_c[0] = A.icell[e0 < (uint32_t)A.n ? e0 : 0];
-      s_c[1] = A.icell[e1 < (uint32_t)A.n ? e1 : 0];
+      s_c[0] = A.icell[e0 < (uint32_t)A.nsrc ? e0 : 0];
+      s_c[1] = A.icell[e1 < (uint32_t)A.nsrc ? e1 : 0];
     } else {
       s_c[0] = A.cell[base];
       s_c[1] = A.cell[end - 1];
@@ -1536,6 +1537,7 @@ PushArgs push_args(hvpic_ctx* c, const hvpic_particles* in, const int32_t* perm,
   A.cs = cell_start;
   A.cnt = c->sort_cnt;
   A.perm = perm;
+  A.nsrc = in->n;
   A.icell = in->cell;
   A.iox = in->ox;
   A.ioy = in->oy;
@@ -1603,6 +1605,14 @@ int launch_gather_push_perm(hvpic_ctx* c, const hvpic_particles* in, const int32
                             hvpic_particles* out, const int32_t* cell_start, const float* E,
                             const float* B, float* n_mid, float* J_mid, double* diag_out) {
   out->n = in->n;
+  return launch_push(c, in, perm, out, cell_start, E, B, n_mid, J_mid, diag_out);
+}
+
+int launch_gather_push_select(hvpic_ctx* c, const hvpic_particles* in, int64_t n_map,
+                              const int32_t* perm, hvpic_particles* out,
+                              const int32_t* cell_start, const float* E, const float* B,
+                              float* n_mid, float* J_mid, double* diag_out) {
+  out->n = n_map;
   return launch_push(c, in, perm, out, cell_start, E, B, n_mid, J_mid, diag_out);
 }
 

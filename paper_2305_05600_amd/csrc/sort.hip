@@ -259,18 +259,33 @@ __device__ uint32_t tile_exclusive_scan(uint32_t* s) {
   return total;
 }
 
+// Open x boundaries (Sec. II.C): columns 0 and nx-1 are ghost columns.
+// Ions whose new cell is a ghost cell are absorbed (left out of the order);
+// inj_cnt[f*ny + j] ions injected through face f into row j follow the
+// pushed ions in the store and come last in their cell (column 1 for f = 0,
+// nx-2 for f = 1).  inj_base receives the first slot of each such group;
+// info[0] = 1 when the neighbour path cannot be taken (far movers or an
+// inconsistent cell_start: nothing else is then written).
+struct OpenSort {
+  const int32_t* inj_cnt;  // [2][ny] or null (no injection)
+  int32_t* inj_base;       // [2][ny]
+  int32_t* info;           // device int32[2] or null
+};
+
 // Per-new-cell totals, written to cs[c], and their per-tile sums (tiles of
 // TILE cells).
-template <int NDIM, int TILE>
+template <int NDIM, int TILE, bool OPEN = false>
 __device__ __forceinline__ void nb_newcount_body(const uint32_t* __restrict__ cnt, const SortGeo& g,
                                                  int32_t* __restrict__ cs,
-                                                 uint32_t* __restrict__ blk, Status* st, int bid) {
+                                                 uint32_t* __restrict__ blk, Status* st, int bid,
+                                                 const OpenSort& os = OpenSort{}) {
   constexpr int ND = Dirs<NDIM>::N;
   __shared__ uint32_t wsum[kWaves];
   if (bid == 0 && threadIdx.x == 0) {
     const uint32_t f = __hip_atomic_load(&st->far_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __hip_atomic_store(&st->far_decision, f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __hip_atomic_store(&st->far_flag, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (OPEN && os.info) os.info[0] = f != 0u ? 1 : 0;
   }
   const int64_t t0 = (int64_t)bid * TILE;
   uint32_t local = 0;
@@ -283,6 +298,14 @@ __device__ __forceinline__ void nb_newcount_body(const uint32_t* __restrict__ cn
     for (int d = 0; d < ND; ++d) {
       const int src = step_cell<NDIM>(i, j, k, ND - 1 - d, g);  // c - d == c + (ND-1-d)
       s += cnt[(int64_t)src * ND + d];
+    }
+    if (OPEN) {
+      if (i == 0 || i == g.nx - 1) {
+        s = 0;
+      } else if (os.inj_cnt) {
+        if (i == 1) s += (uint32_t)os.inj_cnt[j];
+        if (i == g.nx - 2) s += (uint32_t)os.inj_cnt[g.ny + j];
+      }
     }
     cs[c] = (int32_t)s;
     local += s;
@@ -353,10 +376,11 @@ __device__ uint32_t block_sum(const uint32_t* __restrict__ v, int m) {
 // (source cell, direction) of each new cell, written over cnt.  blk holds
 // the tile totals; each block adds up those before it (a few hundred values
 // at most), which spares a separate scan launch.
-template <int NDIM, int TILE>
+template <int NDIM, int TILE, bool OPEN = false>
 __device__ __forceinline__ void nb_bases_body(uint32_t* __restrict__ cnt, const SortGeo& g,
                                               int32_t* __restrict__ cs,
-                                              const uint32_t* __restrict__ blk, int bid) {
+                                              const uint32_t* __restrict__ blk, int bid,
+                                              const OpenSort& os = OpenSort{}) {
   constexpr int ND = Dirs<NDIM>::N;
   __shared__ uint32_t s[TILE];
   const int64_t t0 = (int64_t)bid * TILE;
@@ -387,6 +411,15 @@ __device__ __forceinline__ void nb_bases_body(uint32_t* __restrict__ cnt, const 
     const bool interior = g.nx >= 3 && g.ny >= 3 && i >= 1 && i <= g.nx - 2 && j >= 1 &&
                           j <= g.ny - 2 &&
                           (NDIM == 2 || (g.nz >= 3 && k >= 1 && k <= g.nz - 2));
+    if (OPEN && os.inj_cnt && (i == 1 || i == g.nx - 2)) {
+      // the injected ions of the cell follow all the moved ones
+      uint32_t moved = 0;
+      for (int d = 0; d < ND; ++d) moved += n[d];
+      if (i == 1) os.inj_base[j] = (int32_t)(start + moved);
+      if (i == g.nx - 2)
+        os.inj_base[g.ny + j] =
+            (int32_t)(start + moved + (i == 1 ? (uint32_t)os.inj_cnt[j] : 0u));
+    }
     if (interior) {
       uint32_t before = 0;
 #pragma unroll
@@ -624,7 +657,7 @@ __device__ void block_sort(int64_t n, int ncell, Fields in, Fields out, int32_t*
 }
 
 // PERM: write the gather map out.perm[dst] = p instead of moving the fields.
-template <int NDIM, bool PERM>
+template <int NDIM, bool PERM, bool OPEN = false>
 __device__ __forceinline__ void nb_scatter_body(const int32_t* __restrict__ cs_prev, int64_t n,
                                                 const SortGeo& g, uint32_t* __restrict__ bases,
                                                 const Fields& in, const Fields& out, int32_t* cs,
@@ -661,7 +694,8 @@ __device__ __forceinline__ void nb_scatter_body(const int32_t* __restrict__ cs_p
     }
   }
   if (far != 0) {
-    if (bid == 0) {
+    // open boundaries: the caller takes the general path (info[0])
+    if (!OPEN && bid == 0) {
       uint32_t* rkey[2] = {rk0, rk1};
       uint32_t* rval[2] = {rv0, rv1};
       block_sort(n, g.ncell, in, out, cs, rkey, rval);
@@ -678,6 +712,12 @@ __device__ __forceinline__ void nb_scatter_body(const int32_t* __restrict__ cs_p
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   const bool interior = wave_interior<NDIM>(a0, na, g);
+  // open: the column of the wave's first cell (an interior wave lies in one row)
+  int col0 = 0;
+  if (OPEN) {
+    int j0, k0;
+    ijk(a0, g, col0, j0, k0);
+  }
   // positions in unsigned 32 bits: cell_start (and so n) is below 2^31, so
   // a batch's positions (up to 255 past pe) cannot wrap
   const uint32_t pb = (uint32_t)__builtin_amdgcn_readlane(bnd, 0);
@@ -704,14 +744,22 @@ __device__ __forceinline__ void nb_scatter_body(const int32_t* __restrict__ cs_p
     const int m = cell_in_wave32(p, bnd, na);
     if (valid) {
       int d;
+      int iold = col0 + m;
       if (interior) {
         d = direction_interior2d(key, a0 + m, g.nx);
       } else {
         int i, j, k;
         ijk(a0 + m, g, i, j, k);
         d = direction<NDIM>(key, i, j, k, g);
+        iold = i;
       }
       ok = d >= 0;
+      if (OPEN && ok) {
+        // absorbed: the new cell is in a ghost column
+        int inew = iold + d % 3 - 1;
+        if (inew < 0) inew += g.nx; else if (inew >= g.nx) inew -= g.nx;
+        if (inew == 0 || inew == g.nx - 1) ok = false;
+      }
       code = (m << NB) | (ok ? d : 0);
     }
     uint64_t bal[CODE_BITS];
@@ -748,6 +796,53 @@ __global__ __launch_bounds__(kBlock) void k_nb_scatter(const int32_t* __restrict
                                                        uint32_t* rv0, uint32_t* rv1) {
   nb_scatter_body<NDIM, PERM>(cs_prev, n, g, bases, in, out, cs, st, rk0, rk1, rv0, rv1,
                               blockIdx.x);
+}
+
+// The open-boundary form (gather map, 2D): absorbed ions left out, injected
+// ions appended to their cells.
+template <int TILE>
+__global__ __launch_bounds__(kBlock) void k_nb_newcount_open(const uint32_t* __restrict__ cnt,
+                                                             SortGeo g, int32_t* __restrict__ cs,
+                                                             uint32_t* __restrict__ blk,
+                                                             Status* st, OpenSort os) {
+  nb_newcount_body<2, TILE, true>(cnt, g, cs, blk, st, blockIdx.x, os);
+}
+
+template <int TILE>
+__global__ __launch_bounds__(kBlock) void k_nb_bases_open(uint32_t* __restrict__ cnt, SortGeo g,
+                                                          int32_t* __restrict__ cs,
+                                                          const uint32_t* __restrict__ blk,
+                                                          OpenSort os) {
+  nb_bases_body<2, TILE, true>(cnt, g, cs, blk, blockIdx.x, os);
+}
+
+__global__ __launch_bounds__(kBlock) void k_nb_scatter_open(const int32_t* __restrict__ cs_prev,
+                                                            int64_t n, SortGeo g,
+                                                            uint32_t* __restrict__ bases,
+                                                            Fields in, Fields out, int32_t* cs,
+                                                            const Status* st) {
+  nb_scatter_body<2, true, true>(cs_prev, n, g, bases, in, out, cs, st, nullptr, nullptr,
+                                 nullptr, nullptr, blockIdx.x);
+}
+
+// The gather-map entries of the injected ions (row r's ions are stored
+// contiguously from n_pushed + inj_off[r]) and info[1] = the live count.
+__global__ void k_open_inject_perm(const int32_t* __restrict__ inj_cnt,
+                                   const int32_t* __restrict__ inj_off,
+                                   const int32_t* __restrict__ inj_base, int rows, int64_t n_pushed,
+                                   int32_t* __restrict__ perm, const Status* st,
+                                   int32_t* __restrict__ info, const int32_t* __restrict__ cs,
+                                   int ncell) {
+  const uint32_t far = __hip_atomic_load(&st->far_decision, __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
+  if (far != 0) return;
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (inj_cnt && r < rows) {
+    const int k = inj_cnt[r], b = inj_base[r];
+    const int64_t src = n_pushed + inj_off[r];
+    for (int m = 0; m < k; ++m) perm[b + m] = (int32_t)(src + m);
+  }
+  if (r == 0 && info) info[1] = cs[ncell];
 }
 
 // Batched neighbour sort (gather-map form) over the runs of an ensemble:
@@ -935,6 +1030,49 @@ int launch_sort(hvpic_ctx* c, const hvpic_particles* in, hvpic_particles* out,
 int launch_sort_open(hvpic_ctx* c, const hvpic_particles* in, hvpic_particles* out, int32_t* cs) {
   out->n = in->n;
   enqueue_radix(c, in, fields_of(out), cs, c->ncell + 1);
+  c->cnt_ready = false;
+  return hipGetLastError() == hipSuccess ? HVPIC_OK : HVPIC_EHIP;
+}
+
+int launch_sort_open_perm(hvpic_ctx* c, const hvpic_particles* in, int64_t n_pushed,
+                          const int32_t* cs_prev, int32_t* perm, int32_t* cs, int32_t* info,
+                          const int32_t* inj_cnt, const int32_t* inj_off, int32_t* inj_base) {
+  hipStream_t s = c->stream;
+  const SortGeo g = sort_geo(c);
+  uint32_t* blk = (uint32_t*)c->sort_blk;
+  const bool counted = c->cnt_ready && c->cnt_cell == in->cell && c->cnt_cs == cs_prev &&
+                       c->cnt_n == n_pushed;
+  if (!counted) {
+    const int cblocks = (int)ceil_div(c->ncell, kWaves * kCellsPerWave);
+    hipLaunchKernelGGL((k_nb_count<2>), dim3(cblocks), dim3(kBlock), 0, s, in->cell, cs_prev,
+                       n_pushed, g, c->sort_cnt, c->status);
+  }
+  const OpenSort os{inj_cnt, inj_base, info};
+  if (c->ncell <= kNbTileSmall * 512) {
+    const int tiles = (int)ceil_div(c->ncell, kNbTileSmall);
+    hipLaunchKernelGGL((k_nb_newcount_open<kNbTileSmall>), dim3(tiles), dim3(kBlock), 0, s,
+                       (const uint32_t*)c->sort_cnt, g, cs, blk, c->status, os);
+    hipLaunchKernelGGL((k_nb_bases_open<kNbTileSmall>), dim3(tiles), dim3(kBlock), 0, s,
+                       c->sort_cnt, g, cs, (const uint32_t*)blk, os);
+  } else {
+    const int tiles = (int)ceil_div(c->ncell, kScanTile);
+    hipLaunchKernelGGL((k_nb_newcount_open<kScanTile>), dim3(tiles), dim3(kBlock), 0, s,
+                       (const uint32_t*)c->sort_cnt, g, cs, blk, c->status, os);
+    hipLaunchKernelGGL((k_nb_bases_open<kScanTile>), dim3(tiles), dim3(kBlock), 0, s,
+                       c->sort_cnt, g, cs, (const uint32_t*)blk, os);
+  }
+  Fields out{};
+  out.perm = perm;
+  timing_begin(c, HVPIC_KERNEL_SORT_SCATTER);
+  const int sblocks = (int)ceil_div(c->ncell, kWaves * kScatterCells);
+  hipLaunchKernelGGL(k_nb_scatter_open, dim3(sblocks), dim3(kBlock), 0, s, cs_prev, in->n, g,
+                     c->sort_cnt, fields_of(in), out, cs, (const Status*)c->status);
+  timing_end(c, HVPIC_KERNEL_SORT_SCATTER);
+  const int rows = 2 * c->p.ny;
+  hipLaunchKernelGGL(k_open_inject_perm, dim3((unsigned)ceil_div(rows, 256)), dim3(256), 0, s,
+                     inj_cnt, inj_off, (const int32_t*)inj_base, rows, n_pushed, perm,
+                     (const Status*)c->status, info, (const int32_t*)cs, c->ncell);
+  c->cnt_clean = true;
   c->cnt_ready = false;
   return hipGetLastError() == hipSuccess ? HVPIC_OK : HVPIC_EHIP;
 }

@@ -24,7 +24,7 @@ FLAG_MOVE_GT1, FLAG_FLOOR_HIT, FLAG_NONFINITE, FLAG_BAD_INPUT = 1, 2, 4, 8
 
 EXPORTS = ("hvpic_workspace_bytes", "hvpic_init", "hvpic_finalize", "hvpic_set_stream",
            "hvpic_gather_push",
-           "hvpic_gather_push_perm", "hvpic_sort", "hvpic_sort_perm", "hvpic_deposit",
+           "hvpic_gather_push_perm", "hvpic_gather_push_select", "hvpic_sort", "hvpic_sort_perm", "hvpic_deposit",
            "hvpic_deposit_noalloc",
            "hvpic_field_advance", "hvpic_field_advance_pe", "hvpic_eos_pressure", "hvpic_smooth",
            "hvpic_sync_status", "hvpic_path_stats", "hvpic_timing_enable", "hvpic_timing_read",
@@ -36,7 +36,7 @@ EXPORTS = ("hvpic_workspace_bytes", "hvpic_init", "hvpic_finalize", "hvpic_set_s
            "hvpic_no_predict", "hvpic_no_train_step", "hvpic_field_advance_no",
            "hvpic_no_conv3x3", "hvpic_no_conv3x3_wgrad",
            "hvpic_open_fill", "hvpic_open_field_advance", "hvpic_open_particles",
-           "hvpic_sort_open",
+           "hvpic_sort_open", "hvpic_open_absorb", "hvpic_open_inject", "hvpic_sort_open_perm",
            "hvpic_strerror")
 KERNEL_GATHER_PUSH, KERNEL_DEPOSIT, KERNEL_SORT_SCATTER = 0, 1, 2
 
@@ -107,6 +107,8 @@ def lib():
         L.hvpic_gather_push.argtypes = [vp, P(HvpicParticles), vp, vp, vp, vp, vp, vp]
         L.hvpic_gather_push_perm.argtypes = [vp, P(HvpicParticles), vp, P(HvpicParticles), vp, vp,
                                              vp, vp, vp, vp]
+        L.hvpic_gather_push_select.argtypes = [vp, P(HvpicParticles), ctypes.c_int64, vp,
+                                               P(HvpicParticles), vp, vp, vp, vp, vp, vp]
         L.hvpic_sort.argtypes = [vp, P(HvpicParticles), P(HvpicParticles), vp, vp, i32]
         L.hvpic_sort_perm.argtypes = [vp, P(HvpicParticles), vp, vp, vp]
         L.hvpic_deposit.argtypes = [vp, P(HvpicParticles), vp, ctypes.c_float, vp, vp]
@@ -148,6 +150,10 @@ def lib():
         L.hvpic_open_particles.argtypes = [vp, P(HvpicParticles), P(HvpicInflow), ctypes.c_uint64,
                                            ctypes.c_int64]
         L.hvpic_sort_open.argtypes = [vp, P(HvpicParticles), P(HvpicParticles), vp]
+        L.hvpic_open_absorb.argtypes = [vp, P(HvpicParticles)]
+        L.hvpic_open_inject.argtypes = [vp, P(HvpicParticles), P(HvpicInflow), ctypes.c_uint64,
+                                        ctypes.c_int64]
+        L.hvpic_sort_open_perm.argtypes = [vp, P(HvpicParticles), ctypes.c_int64, vp, vp, vp, vp]
         L.hvpic_strerror.argtypes = [ctypes.c_int]
         L.hvpic_strerror.restype = ctypes.c_char_p
         for f in EXPORTS[:-1]:
@@ -279,6 +285,24 @@ def hvpic_gather_push(ctx, p: Particles, cell_start, E, B, n_mid=None, J_mid=Non
                                    _ptr(J_mid, torch.float32, _nc(ctx, 3)),
                                    _ptr(diag_out, torch.float64, 4)),
            "hvpic_gather_push")
+
+
+def hvpic_gather_push_select(ctx, pin: Particles, n_map: int, perm, pout: Particles, cell_start,
+                             E, B, n_mid=None, J_mid=None, diag_out=None):
+    ci, co = pin.c(), pout.c()
+    if pout.capacity < n_map:
+        raise HvpicError("output store too small")
+    ncs = None if _nc(ctx) is None else _nc(ctx) + 1
+    _check(lib().hvpic_gather_push_select(ctx, ctypes.byref(ci), int(n_map),
+                                          _ptr(perm, torch.int32, n_map), ctypes.byref(co),
+                                          _ptr(cell_start, torch.int32, ncs),
+                                          _ptr(E, torch.float32, _nc(ctx, 3)),
+                                          _ptr(B, torch.float32, _nc(ctx, 3)),
+                                          _ptr(n_mid, torch.float32, _nc(ctx)),
+                                          _ptr(J_mid, torch.float32, _nc(ctx, 3)),
+                                          _ptr(diag_out, torch.float64, 4)),
+           "hvpic_gather_push_select")
+    pout.n = co.n
 
 
 def hvpic_gather_push_perm(ctx, pin: Particles, perm, pout: Particles, cell_start, E, B,
@@ -631,3 +655,30 @@ def hvpic_sort_open(ctx, pin: Particles, pout: Particles, cell_start):
     _check(lib().hvpic_sort_open(ctx, ctypes.byref(ci), ctypes.byref(co),
                                  _ptr(cell_start, torch.int32, ncs)), "hvpic_sort_open")
     pout.n = co.n
+
+
+def hvpic_open_absorb(ctx, p: Particles):
+    cp = p.c()
+    _check(lib().hvpic_open_absorb(ctx, ctypes.byref(cp)), "hvpic_open_absorb")
+
+
+def hvpic_open_inject(ctx, p: Particles, inflow: HvpicInflow, seed: int, step: int):
+    """Injection alone; p.n grows by the injected count."""
+    if ctx.value in _NPCAP and p.capacity < _NPCAP[ctx.value]:
+        raise HvpicError("hvpic_open_inject: the store holds fewer ions than np_capacity")
+    cp = p.c()
+    _check(lib().hvpic_open_inject(ctx, ctypes.byref(cp), ctypes.byref(inflow),
+                                   ctypes.c_uint64(seed & (2**64 - 1)), int(step)),
+           "hvpic_open_inject")
+    p.n = cp.n
+
+
+def hvpic_sort_open_perm(ctx, pin: Particles, n_pushed: int, cell_start_prev, perm, cell_start,
+                         info=None):
+    ci = pin.c()
+    ncs = None if _nc(ctx) is None else _nc(ctx) + 1
+    _check(lib().hvpic_sort_open_perm(ctx, ctypes.byref(ci), int(n_pushed),
+                                      _ptr(cell_start_prev, torch.int32, ncs),
+                                      _ptr(perm, torch.int32, pin.n),  # live <= in.n entries
+                                      _ptr(cell_start, torch.int32, ncs),
+                                      _ptr(info, torch.int32, 2)), "hvpic_sort_open_perm")

@@ -500,26 +500,37 @@ class OpenSim:
     """The 2D step with open x boundaries (Sec. II.C) on the GPU.
 
     The grid carries a ghost column at each x end (the config's open_x); the
-    field is B0 + B1 with B0 fixed.  One step, all on one stream:
+    field is B0 + B1 with B0 fixed.  One step, all on one stream, in the
+    gather-map form (the default):
 
-      1. hvpic_gather_push         E^n, B0 + B1^n at x^n; fused deposit of
-                                   n^{n+1/2}, J^{n+1/2}
-      2. hvpic_open_particles      ions in the ghost columns absorbed, fresh
-                                   ions injected through the faces
-      3. hvpic_sort_open           stable sort by cell, absorbed ions last
+      1. hvpic_gather_push_perm    the store read through the map: E^n,
+                                   B0 + B1^n at x^n; the pushed ions written
+                                   in order to the second store, their moves
+                                   counted; fused deposit of n^{n+1/2},
+                                   J^{n+1/2}
+      2. hvpic_open_inject         fresh ions appended to the second store
+      3. hvpic_sort_open_perm      the next map: ions now in a ghost column
+                                   left out (absorbed), injected ions last
+                                   in their cells
       4. hvpic_open_fill           ghost columns of the moments
       5. hvpic_open_field_advance  B1^n -> B1^{n+1}, E^{n+1}, B0 + B1^{n+1}
 
-    The live count is cell_start[ncell] of the sort: the one device-to-host
-    read of a step, taken while the field advance runs.  Initialisation as in
-    GpuSim (v^{-1/2} = v^0, moments deposited at x^0)."""
+    The sort's info (its fallback flag and the live count) is the one
+    device-to-host read of a step, taken while the field advance runs.  When
+    far movers keep the sort from its neighbour path, hvpic_open_absorb and
+    the general hvpic_sort_open order the store instead (the map restarts as
+    the identity).  With gather_map=False every step takes that general
+    path: push in place, absorb and inject, radix sort with the absorbed
+    ions last.  Initialisation as in GpuSim (v^{-1/2} = v^0, moments
+    deposited at x^0)."""
 
     def __init__(self, cfg, parts: dict, B0, B1, spec: dict, seed: int, capacity: int | None = None,
-                 device="cuda", diagnostics: bool = True):
+                 device="cuda", diagnostics: bool = True, gather_map: bool = True):
         if not cfg.open_x or cfg.ndim != 2:
             raise ValueError("OpenSim needs a 2D config with open_x")
         self.cfg, self.spec, self.seed = cfg, spec, int(seed)
         self.device = device
+        self.gather_map = gather_map
         n = int(parts["cell"].size)
         # room for the inflow to outrun the outflow for a while
         cap = int(capacity) if capacity else 2 * n + 4 * cfg.ny * int(spec["ppc"]) + 4096
@@ -532,6 +543,9 @@ class OpenSim:
         self.p = H.Particles.from_numpy(parts, 2, cap, device)
         self.q = H.Particles(2, cap, device)
         self.cs = torch.zeros(nc + 2, dtype=torch.int32, device=device)
+        self.cs_alt = torch.zeros(nc + 2, dtype=torch.int32, device=device)
+        self.perm = torch.zeros(cap, dtype=torch.int32, device=device) if gather_map else None
+        self.info = torch.zeros(2, dtype=torch.int32, device=device)
         self.B0 = torch.from_numpy(np.ascontiguousarray(B0, dtype=np.float32)).to(device)
         self.B1 = torch.from_numpy(np.ascontiguousarray(B1, dtype=np.float32)).to(device)
         self.Btot = torch.zeros((3, nc), **f32)
@@ -543,14 +557,12 @@ class OpenSim:
         self.diagnostics = diagnostics
         self.push_diag = torch.zeros(4, dtype=torch.float64, device=device)
         self.field_diag = torch.zeros(3, dtype=torch.float64, device=device)
-        self.h_count = torch.zeros(1, dtype=torch.int32, pin_memory=True)
-        self.ev_count = torch.cuda.Event()
+        self.h_info = torch.zeros(2, dtype=torch.int32, pin_memory=True)
+        self.ev_info = torch.cuda.Event()
+        self.fallbacks = 0  # steps that took the general path (gather-map form)
         torch.cuda.current_stream(device).synchronize()
         c = self.ctx.ctx
-        H.hvpic_sort_open(c, self.p, self.q, self.cs)
-        self.p, self.q = self.q, self.p
-        self._read_count()
-        self.p.n = int(self.h_count[0])
+        self._general_sort(absorb=True)
         H.hvpic_open_fill(c, self.B1, 3)
         H.hvpic_deposit(c, self.p, self.cs[:nc + 1], 0.0, self.n_prev, self.J_prev)
         H.hvpic_open_fill(c, self.n_prev, 1)
@@ -562,27 +574,57 @@ class OpenSim:
         self.nstep = 0
         self.absorbed = self.injected = 0
 
-    def _read_count(self):
-        """Enqueues the copy of cell_start[ncell] (the live count) to the host."""
-        nc = self.cfg.ncell
+    def _copy_info(self, src):
+        """Enqueues the copy of two int32 (the sort's info) to the host."""
         with torch.cuda.stream(self.s):
-            self.h_count.copy_(self.cs[nc:nc + 1], non_blocking=True)
-            self.ev_count.record(self.s)
+            self.h_info.copy_(src, non_blocking=True)
+            self.ev_info.record(self.s)
+
+    def _general_sort(self, absorb: bool):
+        """Orders the current store p (all p.n ions) by the radix path with
+        the absorbed ions last, into p; the map restarts as the identity.
+        Waits for the live count."""
+        c = self.ctx.ctx
+        nc = self.cfg.ncell
+        if absorb:
+            H.hvpic_open_absorb(c, self.p)
+        H.hvpic_sort_open(c, self.p, self.q, self.cs)
+        self.p, self.q = self.q, self.p
+        self._copy_info(self.cs[nc:nc + 2])
+        self.ev_info.synchronize()
+        self.p.n = int(self.h_info[0])
+        self.live = self.p.n
+        if self.gather_map:
+            with torch.cuda.stream(self.s):
+                torch.arange(self.p.n, dtype=torch.int32, device=self.device,
+                             out=self.perm[:self.p.n])
 
     def step(self):
         cfg = self.cfg
         c = self.ctx.ctx
+        nc = cfg.ncell
         # writes by the caller's stream come first
         self.s.wait_stream(torch.cuda.current_stream(self.device))
         pd = self.push_diag if self.diagnostics else None
-        H.hvpic_gather_push(c, self.p, None, self.E, self.Btot, self.n_half, self.J_half, pd)
-        n_before = self.p.n
-        H.hvpic_open_particles(c, self.p, self.inflow, self.seed, self.nstep)
-        self.injected += self.p.n - n_before
-        total = self.p.n
-        H.hvpic_sort_open(c, self.p, self.q, self.cs)
-        self.p, self.q = self.q, self.p
-        self._read_count()
+        if self.gather_map:
+            # the store p holds p.n ions; the map selects the live ones
+            H.hvpic_gather_push_select(c, self.p, self.live, self.perm, self.q, self.cs, self.E,
+                                       self.Btot, self.n_half, self.J_half, pd)
+            n_pushed = self.q.n
+            H.hvpic_open_inject(c, self.q, self.inflow, self.seed, self.nstep)
+            self.injected += self.q.n - n_pushed
+            total = self.q.n
+            H.hvpic_sort_open_perm(c, self.q, n_pushed, self.cs, self.perm, self.cs_alt,
+                                   self.info)
+            self._copy_info(self.info)
+        else:
+            H.hvpic_gather_push(c, self.p, None, self.E, self.Btot, self.n_half, self.J_half, pd)
+            n_before = self.p.n
+            H.hvpic_open_particles(c, self.p, self.inflow, self.seed, self.nstep)
+            self.injected += self.p.n - n_before
+            total = self.p.n
+            H.hvpic_sort_open(c, self.p, self.q, self.cs)
+            self._copy_info(self.cs[nc:nc + 2])
         H.hvpic_open_fill(c, self.n_half, 1)
         H.hvpic_open_fill(c, self.J_half, 3)
         H.hvpic_open_field_advance(c, self.B0, self.B1, self.Btot, self.n_half, self.J_half,
@@ -590,10 +632,25 @@ class OpenSim:
                                    diag_out=self.field_diag if self.diagnostics else None)
         self.n_prev, self.n_half = self.n_half, self.n_prev
         self.J_prev, self.J_half = self.J_half, self.J_prev
-        self.ev_count.synchronize()
-        alive = int(self.h_count[0])
+        self.ev_info.synchronize()
+        if self.gather_map:
+            if int(self.h_info[0]) != 0:
+                # far movers: the general path on the pushed and injected store
+                self.fallbacks += 1
+                self.p, self.q = self.q, self.p
+                self._general_sort(absorb=True)
+                alive = self.p.n
+            else:
+                alive = int(self.h_info[1])
+                self.p, self.q = self.q, self.p
+                self.cs, self.cs_alt = self.cs_alt, self.cs
+                self.live = alive
+        else:
+            alive = int(self.h_info[0])
+            self.p, self.q = self.q, self.p
+            self.p.n = alive
+            self.live = alive
         self.absorbed += total - alive
-        self.p.n = alive
         self.nstep += 1
         torch.cuda.current_stream(self.device).wait_stream(self.s)
 
@@ -608,4 +665,8 @@ class OpenSim:
     def particles(self) -> dict:
         """The live particle store in sorted order (host copy)."""
         self.synchronize()
-        return self.p.to_numpy()
+        d = self.p.to_numpy()
+        if self.gather_map:
+            idx = self.perm[:self.live].cpu().numpy()
+            d = {k: v[idx] for k, v in d.items()}
+        return d

@@ -184,7 +184,8 @@ def ensemble_run(spec: dict, shape: int = SHAPE_QS):
 
 def open_flow(seed: int = 9, nx: int = 64, ny: int = 32, ppc: int = 32, ux: float = 0.5,
               vth: float = 0.3, b0=(0.0, 1.0, 0.0), amp: float = 0.02, buffer_cells: int = 4,
-              eta_h_buffer: float = 0.02, dt: float = 0.02, nsub: int = 4):
+              eta_h_buffer: float = 0.02, dt: float = 0.02, nsub: int = 4, dx: float = 0.5,
+              shape: int = SHAPE_QS, name: str | None = None):
     """A plasma drifting along x through a 2D box open in x (Sec. II.C) and
     periodic in y, across a fixed external field B0 (uniform, curl-free),
     with a transverse B1 wave of amplitude amp in B1_z.
@@ -195,8 +196,8 @@ def open_flow(seed: int = 9, nx: int = 64, ny: int = 32, ppc: int = 32, ux: floa
     same plasma enters through both faces (the inflow spec).  eta = 1e-3
     and a hyper-resistive buffer of buffer_cells cells with eta_h_buffer.
     Returns (cfg, parts, B0, B1, inflow)."""
-    cfg = Config(name=f"2d-open-flow-{nx}x{ny}-ppc{ppc}", ndim=2, nx=nx + 2, ny=ny, nz=1,
-                 dx=0.5, dy=0.5, dz=1.0, dt=dt, nsub=nsub, shape=SHAPE_QS, te=vth * vth,
+    cfg = Config(name=name or f"2d-open-flow-{nx}x{ny}-ppc{ppc}", ndim=2, nx=nx + 2, ny=ny,
+                 nz=1, dx=dx, dy=dx, dz=1.0, dt=dt, nsub=nsub, shape=shape, te=vth * vth,
                  eta=1e-3, open_x=1, buffer_cells=buffer_cells, eta_h_buffer=eta_h_buffer)
     rng = np.random.Generator(np.random.PCG64(seed))
     ncol = nx * ny
@@ -219,6 +220,21 @@ def open_flow(seed: int = 9, nx: int = 64, ny: int = 32, ppc: int = 32, ux: floa
     B1[2] = _f32(amp * np.sin(2.0 * math.pi * x / (cfg.nx * cfg.dx)))
     spec = dict(n=1.0, ux=ux, uy=0.0, uz=0.0, vth=vth, ppc=ppc, faces=3)
     return cfg, parts, B0, B1, spec
+
+
+def solar_wind_box(seed: int = 12, nx: int = 800, ny: int = 1600, ppc: int = 100):
+    """The 2D global-magnetosphere run of Sec. III.A without its planet: a
+    uniform solar wind through a box open in x (Sec. II.C), periodic in y.
+    800 x 1600 cells of 2 d_i, 100 ions per cell (128,000,000 at full
+    size), NGP shape, dt = 0.002 / Omega_i with 5 field subcycles,
+    isothermal electrons.  The wind flows along +x at Alfven Mach 10 with
+    beta_i = beta_e = 0.5 (T = 0.25, thermal speed 0.5 v_A) across a uniform
+    interplanetary field B0 = y (in the plane, normal to the flow), with a
+    transverse B1 wave of amplitude 0.05; both faces inject the wind, and
+    8 buffer cells add eta_h = 1 at each boundary."""
+    return open_flow(seed=seed, nx=nx, ny=ny, ppc=ppc, ux=10.0, vth=0.5, b0=(0.0, 1.0, 0.0),
+                     amp=0.05, buffer_cells=8, eta_h_buffer=1.0, dt=0.002, nsub=5, dx=2.0,
+                     shape=SHAPE_NGP, name=f"2d-open-solar-wind-{nx}x{ny}-ppc{ppc}")
 
 
 def harris_double(seed: int = 2, nx: int = 512, ny: int = 256, ppc: float = 100.0,

@@ -72,7 +72,9 @@ def test_workspace_bytes_and_validation(H):
         q = H.params_from(cfg, 65536)
         for k, v in good.items():
             setattr(q, k, v)
-        assert H.hvpic_workspace_bytes(q) == nb, good
+        # open x adds the injection's per-row counts, offsets and slots
+        extra = -(-3 * 2 * cfg.ny * 4 // 256) * 256 if good.get("open_x") else 0
+        assert H.hvpic_workspace_bytes(q) == nb + extra, good
 
 
 def test_init_rejects_bad_arguments_without_device_work(H):
