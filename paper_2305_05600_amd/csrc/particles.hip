@@ -368,12 +368,15 @@ __device__ __forceinline__ void dep_weights(float x, float y, float z, float* wt
 }
 
 // Deposit window: FP64 (n, Jx, Jy, Jz) per slot; slot = band * SW + column,
-// band = (by + 3) [+ 7 (bz + 3)] for band offsets by, bz in -3..3.
+// band = (by + 2) [+ 5 (bz + 2)] for band offsets by, bz in -2..2.  A home
+// cell (a particle's deposit cell) takes bands -1..1 only, so that its
+// stencil stays inside; the rare deposit cell further out (a diagonal
+// mid-point at a wrapped x or y edge) goes to the global accumulators.
 template <int NDIM>
 struct DWin {
   static constexpr int SW = Chunk<NDIM>::WMAX;  // slots per band
-  static constexpr int BZ = 7 * SW;             // slots per z band row (3D)
-  static constexpr int NB = NDIM == 2 ? 7 : 49;
+  static constexpr int BZ = 5 * SW;             // slots per z band row (3D)
+  static constexpr int NB = NDIM == 2 ? 5 : 25;
   static constexpr int LEN = NB * SW * 4;       // doubles
 };
 
@@ -414,18 +417,22 @@ __device__ __forceinline__ int wrap_bits(int i, int j, const Geo& g) {
 }
 
 // Window slot of the cell (mx, my, mz) away from the cell of window column
-// `rel` with indices (i, j).
+// `rel` with indices (i, j), as a home cell; -1 when its band offset is
+// beyond -1..1 (the particle then deposits to the global accumulators).
 template <int NDIM>
 __device__ __forceinline__ int window_slot(int rel, int i, int j, int mx, int my, int mz,
                                            const Geo& g) {
   const int t1 = i + mx;
   const int wx = t1 < 0 ? 1 : (t1 >= g.nx ? -1 : 0);
-  int band = my + wx + 3;
+  const int by = my + wx;
+  int bz = 0;
   if (NDIM == 3) {
     const int t2 = j + my;
     const int wy = t2 < 0 ? 1 : (t2 >= g.ny ? -1 : 0);
-    band += 7 * (mz + wy + 3);
+    bz = mz + wy;
   }
+  if (by < -1 || by > 1 || bz < -1 || bz > 1) return -1;
+  const int band = NDIM == 3 ? (by + 2) + 5 * (bz + 2) : by + 2;
   return band * DWin<NDIM>::SW + rel + mx + 2;
 }
 
@@ -578,9 +585,10 @@ __device__ __forceinline__ void deposit_particle(Home<NDIM, SHAPE>& H, Queue<NDI
                                                  float vy, float vz, const Geo& g,
                                                  double* __restrict__ acc) {
   constexpr int T = Stencil<NDIM, SHAPE>::T;
-  const bool use_win = live && inwin && mx >= -1 && mx <= 1 && my >= -1 && my <= 1 &&
-                       mz >= -1 && mz <= 1;
-  const int key = use_win ? window_slot<NDIM>(rel, i, j, mx, my, mz, g) : -1;
+  const bool near = live && inwin && mx >= -1 && mx <= 1 && my >= -1 && my <= 1 &&
+                    mz >= -1 && mz <= 1;
+  const int key = near ? window_slot<NDIM>(rel, i, j, mx, my, mz, g) : -1;
+  const bool use_win = key >= 0;
   if (use_win && H.key < 0) H.key = key;
   const bool stay = use_win && key == H.key;
   float wt[T];
@@ -699,7 +707,7 @@ __device__ void dwin_init(double* win, uint8_t* wrap, int W, int c0, const Geo& 
   }
   for (int s = threadIdx.x; s < DWin<NDIM>::NB * W; s += kBlock) {
     const int band = s / W, col = s - band * W;
-    const int c = (int)window_cell(c0, col, band % 7 - 3, band / 7 - 3, g);
+    const int c = (int)window_cell(c0, col, band % 5 - 2, band / 5 - 2, g);
     const int i = c % g.nx, j = (c / g.nx) % g.ny;
     wrap[band * SW + col] = (uint8_t)wrap_bits<NDIM>(i, j, g);
   }
@@ -716,7 +724,7 @@ __device__ void dwin_flush(const double* win, int W, int c0, const Geo& g,
     const double v = win[band * SW * 4 + rest];
     if (v == 0.0) continue;
     const int ch = rest & 3, off = rest >> 2;
-    const int64_t c = window_cell(c0, off, band % 7 - 3, band / 7 - 3, g);
+    const int64_t c = window_cell(c0, off, band % 5 - 2, band / 5 - 2, g);
     unsafeAtomicAdd(acc + (int64_t)ch * g.ncell + c, v);
   }
 }
@@ -824,17 +832,44 @@ __device__ __forceinline__ void load_group_perm(const PushArgs& A, int64_t b4, i
     auto at = [](const void* base, uint32_t o) {
       return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(base) + o);
     };
+    // a lane whose four entries are a run of the source (no mover among
+    // them, the common case) takes each array's four values with one
+    // 16-byte access at a 4-byte aligned address
+    const bool run = src[1] == src[0] + 1 && src[2] == src[0] + 2 && src[3] == src[0] + 3;
+    if (run) {
+      typedef float F4u __attribute__((ext_vector_type(4), aligned(4)));
+      const uint32_t o = (uint32_t)src[0] * 4u;
+      auto at4 = [](const void* base, uint32_t o, float v[4]) {
+        const F4u u = *reinterpret_cast<const F4u*>(reinterpret_cast<const char*>(base) + o);
+        v[0] = u.x;
+        v[1] = u.y;
+        v[2] = u.z;
+        v[3] = u.w;
+      };
+      float ci[4];
+      at4(A.icell, o, ci);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const uint32_t o = (uint32_t)src[q] * 4u;
-      G.ca[q] = __float_as_int(at(A.icell, o));
-      G.px[q] = at(A.iox, o);
-      G.py[q] = at(A.ioy, o);
-      if (NDIM == 3) G.pz[q] = at(A.ioz, o);
-      G.ux[q] = at(A.iux, o);
-      G.uy[q] = at(A.iuy, o);
-      G.uz[q] = at(A.iuz, o);
-      G.pw[q] = at(A.iw, o);
+      for (int q = 0; q < 4; ++q) G.ca[q] = __float_as_int(ci[q]);
+      at4(A.iox, o, G.px);
+      at4(A.ioy, o, G.py);
+      if (NDIM == 3) at4(A.ioz, o, G.pz);
+      at4(A.iux, o, G.ux);
+      at4(A.iuy, o, G.uy);
+      at4(A.iuz, o, G.uz);
+      at4(A.iw, o, G.pw);
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const uint32_t o = (uint32_t)src[q] * 4u;
+        G.ca[q] = __float_as_int(at(A.icell, o));
+        G.px[q] = at(A.iox, o);
+        G.py[q] = at(A.ioy, o);
+        if (NDIM == 3) G.pz[q] = at(A.ioz, o);
+        G.ux[q] = at(A.iux, o);
+        G.uy[q] = at(A.iuy, o);
+        G.uz[q] = at(A.iuz, o);
+        G.pw[q] = at(A.iw, o);
+      }
     }
   } else {
 #pragma unroll
@@ -1289,7 +1324,7 @@ __device__ __forceinline__ void push_chunk(const PushArgs& A, int chunk, int nb)
 }
 
 template <int NDIM, int SHAPE, bool DEP, int PM>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NDIM == 2 ? 4 : 1)))
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4)))
 void k_gather_push(PushArgs A) {
   push_chunk<NDIM, SHAPE, DEP, PM, Chunk<NDIM>::PPT>(A, xcd_chunk(blockIdx.x, gridDim.x),
                                                      gridDim.x);
