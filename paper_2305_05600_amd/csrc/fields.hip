@@ -92,6 +92,48 @@ __global__ __launch_bounds__(kBlock) void k_field_stage(const float* __restrict_
   }
 }
 
+// The same stage in two passes: E = Ohm(B_src) once per cell, then the
+// Faraday update from curl E.  Each cell's E is formed once instead of once
+// per neighbour that needs it (2 NDIM times in k_field_stage), at the cost
+// of writing E and reading it back.
+template <int NDIM>
+__global__ __launch_bounds__(kBlock) void k_field_ohm_cells(const float* __restrict__ Bsrc,
+                                                            float eta, FGeo g, Aux aux,
+                                                            float* __restrict__ E) {
+  const int c = blockIdx.x * kBlock + threadIdx.x;
+  if (c >= g.ncell) return;
+  const int nc = g.ncell;
+  float e[3];
+  ohm_at<NDIM>(BSum<false>{Bsrc, nullptr}, aux, eta, c, g, e);
+  E[c] = e[0];
+  E[nc + c] = e[1];
+  E[2 * nc + c] = e[2];
+}
+
+template <int NDIM>
+__global__ __launch_bounds__(kBlock) void k_field_curl_update(const float* __restrict__ E,
+                                                              const float* Bbase, float* Bdst,
+                                                              float* lo, float coef, FGeo g) {
+  const int c = blockIdx.x * kBlock + threadIdx.x;
+  if (c >= g.ncell) return;
+  const int nc = g.ncell;
+  float ce[3];
+  curl_at<NDIM>(BSum<false>{E, nullptr}, c, g, ce);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const int q = a * nc + c;
+    const float d = -coef * ce[a];
+    const float hi = Bbase[q];
+    if (lo) {
+      const float y = lo[q] + d;
+      const float t = hi + y;
+      lo[q] = y - (t - hi);
+      Bdst[q] = t;
+    } else {
+      Bdst[q] = hi + d;
+    }
+  }
+}
 
 // K whole RK2 substeps for a 2D tile of kTX x kTY cells, all intermediate
 // fields in LDS.  Each substep needs B on a 4-cell halo (B -> Ea on halo 3 ->
@@ -680,11 +722,16 @@ int field_impl(hvpic_ctx* c, float* B, const float* n_half, const float* J_half,
       const int cblocks = (int)std::min<int64_t>(ceil_div(3ll * nc, kBlock), 1024);
       hipLaunchKernelGGL(k_copy, dim3(cblocks), blk, 0, s, (const float*)B, Xh, 3ll * nc);
       hipLaunchKernelGGL(k_fill, dim3(cblocks), blk, 0, s, Xl, 3ll * nc, 0.0f);
+      float* Es = c->fscratch + 19ll * nc;  // E of a stage
       for (int m = 0; m < c->p.nsub; ++m) {
-        hipLaunchKernelGGL((k_field_stage<NDIM>), grid, blk, 0, s, (const float*)Xh,
-                           (const float*)Xh, Yh, (float*)nullptr, 0.5f * h, eta, g, aux);
-        hipLaunchKernelGGL((k_field_stage<NDIM>), grid, blk, 0, s, (const float*)Yh,
-                           (const float*)Xh, Xh, Xl, h, eta, g, aux);
+        hipLaunchKernelGGL((k_field_ohm_cells<NDIM>), grid, blk, 0, s, (const float*)Xh, eta, g,
+                           aux, Es);
+        hipLaunchKernelGGL((k_field_curl_update<NDIM>), grid, blk, 0, s, (const float*)Es,
+                           (const float*)Xh, Yh, (float*)nullptr, 0.5f * h, g);
+        hipLaunchKernelGGL((k_field_ohm_cells<NDIM>), grid, blk, 0, s, (const float*)Yh, eta, g,
+                           aux, Es);
+        hipLaunchKernelGGL((k_field_curl_update<NDIM>), grid, blk, 0, s, (const float*)Es,
+                           (const float*)Xh, Xh, Xl, h, g);
       }
       fh = Xh;
       fl = Xl;
