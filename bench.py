@@ -497,7 +497,8 @@ def bench_open(args) -> dict:
                    "absorbed_total": g.absorbed, "injected_total": g.injected,
                    "steps_run": g.nstep},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": _traffic(n0, "gather map" if g.gather_map else "in place", "open"),
                      "kernel": ("k_gather_push (fused deposit, read through the gather map)"
                                 if g.gather_map else "k_gather_push (fused deposit, in place)"),
                      "kernel_ms": kernel_ms,
@@ -571,6 +572,16 @@ def main() -> int:
               "sharding of the step is a design note, not part of this build", file=sys.stderr)
         return 2
 
+    if args.calibrate_copy:
+        import torch
+
+        src = torch.ones(128 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     if args.workload == "ensemble":
         print(json.dumps(bench_ensemble(args)), flush=True)
         return 0
@@ -588,13 +599,6 @@ def main() -> int:
     from paper_2305_05600_amd import sim as S
     from paper_2305_05600_amd import workloads as W
 
-    if args.calibrate_copy:
-        src = torch.ones(128 << 20, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
 
     if args.workload == "harris":
         cfg, parts, B = W.harris_double()

@@ -1324,7 +1324,7 @@ __device__ __forceinline__ void push_chunk(const PushArgs& A, int chunk, int nb)
 }
 
 template <int NDIM, int SHAPE, bool DEP, int PM>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NDIM == 2 ? 4 : 3)))
 void k_gather_push(PushArgs A) {
   push_chunk<NDIM, SHAPE, DEP, PM, Chunk<NDIM>::PPT>(A, xcd_chunk(blockIdx.x, gridDim.x),
                                                      gridDim.x);
