@@ -234,10 +234,14 @@ __device__ __forceinline__ bool window_ok(int c0, int c1, const Geo& g, int& W) 
 
 // Linear cell of deposit-window column `off` in band (by, bz): the window
 // starts two cells before c0; band (by, bz) is shifted by by*nx + bz*nx*ny.
+// |by|, |bz| <= 2 and 0 <= c0 - 2 + off < ncell + WMAX, so the index is
+// within a few grid lengths of the grid: wrapped by adds and subtracts
+// instead of a 64-bit remainder.
 __device__ __forceinline__ int64_t window_cell(int c0, int off, int by, int bz, const Geo& g) {
   int64_t c = (int64_t)c0 - 2 + off + (int64_t)by * g.nx + (int64_t)bz * g.nxny;
-  c %= g.ncell;
-  return c < 0 ? c + g.ncell : c;
+  while (c < 0) c += g.ncell;
+  while (c >= g.ncell) c -= g.ncell;
+  return c;
 }
 
 // Fills the gather records of cells c0 .. c0 + ncells - 1 (all inside the
@@ -707,7 +711,7 @@ __device__ void dwin_init(double* win, uint8_t* wrap, int W, int c0, const Geo& 
   }
   for (int s = threadIdx.x; s < DWin<NDIM>::NB * W; s += kBlock) {
     const int band = s / W, col = s - band * W;
-    const int c = (int)window_cell(c0, col, band % 5 - 2, band / 5 - 2, g);
+    const int c = (int)window_cell(c0, col, band % 5 - 2, NDIM == 3 ? band / 5 - 2 : 0, g);
     const int i = c % g.nx, j = (c / g.nx) % g.ny;
     wrap[band * SW + col] = (uint8_t)wrap_bits<NDIM>(i, j, g);
   }
@@ -724,7 +728,7 @@ __device__ void dwin_flush(const double* win, int W, int c0, const Geo& g,
     const double v = win[band * SW * 4 + rest];
     if (v == 0.0) continue;
     const int ch = rest & 3, off = rest >> 2;
-    const int64_t c = window_cell(c0, off, band % 5 - 2, band / 5 - 2, g);
+    const int64_t c = window_cell(c0, off, band % 5 - 2, NDIM == 3 ? band / 5 - 2 : 0, g);
     unsafeAtomicAdd(acc + (int64_t)ch * g.ncell + c, v);
   }
 }
