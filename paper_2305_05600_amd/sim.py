@@ -516,7 +516,11 @@ class OpenSim:
       5. hvpic_open_field_advance  B1^n -> B1^{n+1}, E^{n+1}, B0 + B1^{n+1}
 
     The sort's info (its fallback flag and the live count) is the one
-    device-to-host read of a step, taken while the field advance runs.  When
+    device-to-host read of a step, taken while the field advance runs.  With
+    `overlap` (gather-map form) the sort runs on a side stream beside steps
+    4-5, as in GpuSim: they touch disjoint data (the store, the map,
+    cell_start and the sort's workspace against the moments, the fields and
+    the field scratch).  When
     far movers keep the sort from its neighbour path, hvpic_open_absorb and
     the general hvpic_sort_open order the store instead (the map restarts as
     the identity).  With gather_map=False every step takes that general
@@ -525,7 +529,8 @@ class OpenSim:
     deposited at x^0)."""
 
     def __init__(self, cfg, parts: dict, B0, B1, spec: dict, seed: int, capacity: int | None = None,
-                 device="cuda", diagnostics: bool = True, gather_map: bool = True):
+                 device="cuda", diagnostics: bool = True, gather_map: bool = True,
+                 overlap: bool = True):
         if not cfg.open_x or cfg.ndim != 2:
             raise ValueError("OpenSim needs a 2D config with open_x")
         self.cfg, self.spec, self.seed = cfg, spec, int(seed)
@@ -536,6 +541,10 @@ class OpenSim:
         cap = int(capacity) if capacity else 2 * n + 4 * cfg.ny * int(spec["ppc"]) + 4096
         self.capacity = cap
         self.s = torch.cuda.Stream(device)
+        self.overlap = overlap and gather_map
+        self.s_sort = torch.cuda.Stream(device) if self.overlap else self.s
+        self.ev_push = StreamEvent()
+        self.ev_sort = StreamEvent()
         self.ctx = H.Context(cfg, cap, device, stream=self.s)
         self.inflow = H.inflow_from(spec)
         nc = cfg.ncell
@@ -574,11 +583,12 @@ class OpenSim:
         self.nstep = 0
         self.absorbed = self.injected = 0
 
-    def _copy_info(self, src):
+    def _copy_info(self, src, stream=None):
         """Enqueues the copy of two int32 (the sort's info) to the host."""
-        with torch.cuda.stream(self.s):
+        stream = stream or self.s
+        with torch.cuda.stream(stream):
             self.h_info.copy_(src, non_blocking=True)
-            self.ev_info.record(self.s)
+            self.ev_info.record(stream)
 
     def _general_sort(self, absorb: bool):
         """Orders the current store p (all p.n ions) by the radix path with
@@ -614,9 +624,20 @@ class OpenSim:
             H.hvpic_open_inject(c, self.q, self.inflow, self.seed, self.nstep)
             self.injected += self.q.n - n_pushed
             total = self.q.n
-            H.hvpic_sort_open_perm(c, self.q, n_pushed, self.cs, self.perm, self.cs_alt,
-                                   self.info)
-            self._copy_info(self.info)
+            if self.overlap:
+                # the sort beside the field advance, once the push and the
+                # injection are done
+                self.ev_push.record(self.s)
+                self.ev_push.wait(self.s_sort)
+                self.ctx.set_stream(self.s_sort)
+            try:
+                H.hvpic_sort_open_perm(c, self.q, n_pushed, self.cs, self.perm, self.cs_alt,
+                                       self.info)
+                self._copy_info(self.info, self.s_sort)
+            finally:
+                if self.overlap:
+                    self.ctx.set_stream(self.s)
+                    self.ev_sort.record(self.s_sort)
         else:
             H.hvpic_gather_push(c, self.p, None, self.E, self.Btot, self.n_half, self.J_half, pd)
             n_before = self.p.n
@@ -633,6 +654,8 @@ class OpenSim:
         self.n_prev, self.n_half = self.n_half, self.n_prev
         self.J_prev, self.J_half = self.J_half, self.J_prev
         self.ev_info.synchronize()
+        if self.overlap:
+            self.ev_sort.wait(self.s)  # the next push reads the new map
         if self.gather_map:
             if int(self.h_info[0]) != 0:
                 # far movers: the general path on the pushed and injected store
@@ -657,6 +680,7 @@ class OpenSim:
     def synchronize(self):
         torch.cuda.current_stream(self.device).synchronize()
         self.s.synchronize()
+        self.s_sort.synchronize()
 
     def status(self):
         self.synchronize()
