@@ -10,7 +10,7 @@ import pytest
 
 import oracle as O
 from paper_2305_05600_amd import workloads as W
-from tests.helpers import (announce, check_field_diag, compare_particles,
+from tests.helpers import (_near_face, announce, check_field_diag, compare_particles,
                            deposit_point_straddlers, rel_l2)
 
 pytestmark = pytest.mark.gpu
@@ -519,3 +519,53 @@ def test_neighbour_sort_large_grid(H):
     flags, _ = H.hvpic_sync_status(ctx.ctx)
     assert flags == 0
     _check_sorted(cfg, pushed, q.to_numpy(), cs.cpu().numpy())
+
+
+@pytest.mark.parametrize("name,cfg", CASES)
+def test_gather_push_select(H, name, cfg):
+    """The push of the ions a gather map selects from a larger store (the
+    open step's form): the map takes a sorted subset of a sorted store, so
+    the source arrays hold ions the map leaves out, and its entries reach
+    past the number pushed.  The pushed store, its moments and diagnostics
+    equal the oracle's push of the same subset in map order; a map longer
+    than the store is rejected."""
+    announce("gather_push_select", name)
+    _, parts, B = W.random_box(71, cfg, 20.0, vmax_cells=0.9)
+    parts, _ = _sorted(cfg, parts)
+    E = W.random_field(72, cfg, 0.1)
+    n = parts["cell"].size
+    rng = np.random.default_rng(73)
+    sel = np.sort(rng.choice(n, size=(3 * n) // 4, replace=False))
+    # without the ions that the FP64 push puts within 1e-5 half-cells of a
+    # face, or whose mid-point deposit point lands there (exact cells)
+    probe = O.particles64({k: v[sel] for k, v in parts.items()})
+    O.push(cfg, probe, E, B)
+    near = np.zeros(sel.size, bool)
+    for k in ["ox", "oy"] + (["oz"] if cfg.ndim == 3 else []):
+        near |= _near_face(probe[k], 1e-5)
+    near |= deposit_point_straddlers(cfg, probe, 0.5 * cfg.dt)
+    print(f"straddlers removed: {int(near.sum())} of {sel.size}", flush=True)
+    sel = sel[~near]
+    sub = {k: v[sel] for k, v in parts.items()}
+    m = sel.size
+    ctx = H.Context(cfg, n)
+    p = H.Particles.from_numpy(parts, cfg.ndim)
+    q = H.Particles(cfg.ndim, n)
+    perm = dev(sel, np.int32)
+    nd = torch.zeros(cfg.ncell, dtype=torch.float32, device="cuda")
+    Jd = torch.zeros((3, cfg.ncell), dtype=torch.float32, device="cuda")
+    diag = torch.zeros(4, dtype=torch.float64, device="cuda")
+    H.hvpic_gather_push_select(ctx.ctx, p, m, perm, q, None, dev(E), dev(B), nd, Jd, diag)
+    flags, _ = H.hvpic_sync_status(ctx.ctx)
+    assert not flags & H.FLAG_BAD_INPUT
+    assert q.n == m
+    ref = O.particles64(sub)
+    rd, _ = O.push(cfg, ref, E, B)
+    compare_particles(cfg, q.to_numpy(), ref)
+    rn, rJ = O.deposit(cfg, ref, 0.5 * cfg.dt)
+    assert rel_l2(nd.cpu().numpy(), rn) < 1e-5 and rel_l2(Jd.cpu().numpy(), rJ) < 1e-5
+    assert np.allclose(diag.cpu().numpy(), rd, rtol=1e-5, atol=1e-6 * abs(rd[0]))
+    with pytest.raises(H.HvpicError):
+        H.hvpic_gather_push_select(ctx.ctx, p, n + 1, torch.zeros(n + 1, dtype=torch.int32,
+                                                                  device="cuda"), q, None,
+                                   dev(E), dev(B))

@@ -182,3 +182,31 @@ def test_open_flow_keeps_its_density():
     assert sim.absorbed > 0 and sim.injected > 0
     assert abs(n1 - n0) < 0.05 * n0
     assert np.abs(sim.B1).max() < 0.2
+
+
+def _splitmix_vectors():
+    import pathlib
+
+    state, outs = None, []
+    for line in (pathlib.Path(__file__).parent / "golden" / "splitmix64_vectors.txt").read_text().splitlines():
+        if line.startswith("state"):
+            state = int(line.split()[1])
+        elif line.startswith("output"):
+            outs.append(int(line.split()[1]))
+    return state, outs
+
+
+def test_draws_follow_the_published_splitmix64_sequence():
+    """The injection's uniform is (mix(seed + mix(ctr)) >> 11) 2^-53 with
+    mix the splitmix64 finaliser.  Choosing ctr = the published start state
+    makes mix(ctr) its first output; the seed that moves that onto the state
+    of output k makes the uniform output k's top 53 bits.  So the oracle's
+    generator reproduces the published sequence exactly."""
+    golden = 0x9E3779B97F4A7C15
+    M = (1 << 64) - 1
+    state, outs = _splitmix_vectors()
+    assert len(outs) >= 3
+    for k in range(1, len(outs)):
+        # mix(ctr) = outs[0]; want seed + outs[0] = state + k * golden
+        seed = (state + k * golden - outs[0]) & M
+        assert O.uniform(seed, state) == (outs[k] >> 11) * 2.0 ** -53, k
