@@ -286,8 +286,8 @@ def bench_surrogate(args) -> dict:
     operator where its proposal passes the residual test (tolerance
     --no-tol, 1e-2 by default): snapshots of the plain run, training on them
     (time-budgeted), then timed steps with the surrogate against plain
-    steps of the same run.  The plain subcycle is the fallback and the judge
-    of the error: the increment error of the proposals on held-out
+    steps of the same run.  The plain subcycle is the fallback and the
+    reference for the error: the increment error of the proposals on held-out
     snapshots is reported, and so is the residual ratio of the plain
     subcycle's own result under the same test (the oracle's Ohm's law and
     curl, FP64)."""

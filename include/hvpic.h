@@ -447,7 +447,7 @@ int hvpic_ensemble_time_phases(hvpic_ensemble* e, int steps, double* ms);
    NO = four periodic 3x3 convolutions 7 -> 32 -> 32 -> 32 -> 3 with tanh
    between them, run on the matrix cores with BF16 operands and FP32
    accumulation, trained here on snapshots of the plain solver (MSE of the
-   normalised increment, Adam).  The plain subcycle stays the judge: a
+   normalised increment, Adam).  The plain subcycle stays the reference: a
    proposal is used only if its residual against Faraday's law with Ohm's
    law at the midpoint,
        r = (B' - B^n)/dt + curl E((B^n + B')/2)   (moments held at n+1/2),
