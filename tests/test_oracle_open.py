@@ -210,3 +210,58 @@ def test_draws_follow_the_published_splitmix64_sequence():
         # mix(ctr) = outs[0]; want seed + outs[0] = state + k * golden
         seed = (state + k * golden - outs[0]) & M
         assert O.uniform(seed, state) == (outs[k] >> 11) * 2.0 ** -53, k
+
+
+@pytest.mark.parametrize("nx,ny,nsub,mode,eta_h,buf", [
+    (14, 9, 3, 0, 0.0, 3), (14, 9, 3, 0, 2e-3, 4), (5, 6, 2, 0, 1e-3, 1), (3, 4, 1, 0, 0.0, 2),
+    (14, 9, 0, 0, 1e-3, 3), (14, 9, 3, 1, 1e-3, 3), (30, 7, 4, 0, 0.0, 0)])
+def test_open_field_advance_matches_an_independent_numpy_form(nx, ny, nsub, mode, eta_h, buf):
+    """tests/bruteforce_open.py writes the open rules again with whole-array
+    NumPy stencils and a column mask for the ghost columns, importing nothing
+    from the oracle.  On fields that vary along x and y (so that every ghost
+    rule is exercised: the dropped x-derivatives in the ghost columns, the
+    refills after each stage, the buffer's per-column eta_h), with densities
+    below the floor in some cells, the two agree to rounding."""
+    from tests.bruteforce_open import OpenGrid
+
+    cfg = _cfg(nx=nx, ny=ny, nsub=nsub, eta_h=eta_h, buffer_cells=buf, eta_h_buffer=0.03,
+               gamma_e=5.0 / 3.0)
+    rng = np.random.default_rng(nx * 100 + ny + nsub)
+    B0 = np.zeros((3, cfg.ncell))
+    B0[:] = np.array([[0.3], [1.0], [-0.2]])
+    B1 = rng.normal(scale=0.1, size=(3, cfg.ncell))
+    nh = rng.uniform(0.02, 1.5, cfg.ncell)
+    nh[cfg.nx + 1] = 0.01  # an interior cell below the floor
+    npv = rng.uniform(0.5, 1.5, cfg.ncell)
+    Jh = rng.normal(scale=0.2, size=(3, cfg.ncell))
+    Jp = rng.normal(scale=0.2, size=(3, cfg.ncell))
+    nh, npv, Jh, Jp = (O.open_fill(cfg, a) for a in (nh, npv, Jh, Jp))
+    assert np.any(nh < cfg.n_floor)
+    rB1, rE, rBt, _, _ = O.open_field_advance(cfg, B0, B1, nh, Jh, npv, Jp, mode=mode)
+    bB1, bE, bBt = OpenGrid(cfg).field_advance(B0, B1, nh, Jh, npv, Jp, mode=mode)
+    for got, ref in ((bB1, rB1), (bE, rE), (bBt, rBt)):
+        assert np.allclose(got, ref, rtol=1e-11, atol=1e-12 * np.abs(ref).max())
+    # the ghost rules matter on these inputs: the periodic solver differs
+    pE = O.ohm(cfg.replace(open_x=0), B0 + rB1, nh if mode else 1.5 * nh - 0.5 * npv,
+               Jh if mode else 1.5 * Jh - 0.5 * Jp)
+    assert np.abs(pE - rE).max() > 1e-3 * np.abs(rE).max()
+
+
+def test_numpy_form_fails_on_a_planted_ghost_mistake():
+    """The comparison above is sharp: the NumPy form with the ghost column's
+    x-derivative kept (the rule of Sec. II.C dropped) disagrees with the
+    oracle."""
+    from tests.bruteforce_open import OpenGrid
+
+    cfg = _cfg(nx=14, ny=9, nsub=2)
+    rng = np.random.default_rng(5)
+    B0 = np.zeros((3, cfg.ncell))
+    B0[1] = 1.0
+    B1 = rng.normal(scale=0.1, size=(3, cfg.ncell))
+    n = O.open_fill(cfg, rng.uniform(0.5, 1.5, cfg.ncell))
+    J = O.open_fill(cfg, rng.normal(scale=0.2, size=(3, cfg.ncell)))
+    _, rE, _, _, _ = O.open_field_advance(cfg, B0, B1, n, J, n, J, mode=0)
+    g = OpenGrid(cfg)
+    g.interior = np.ones(cfg.nx)  # keep x-derivatives in the ghost columns
+    _, bE, _ = g.field_advance(B0, B1, n, J, n, J, mode=0)
+    assert np.abs(bE - rE).max() > 1e-3 * np.abs(rE).max()
