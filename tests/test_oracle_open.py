@@ -265,3 +265,70 @@ def test_numpy_form_fails_on_a_planted_ghost_mistake():
     g.interior = np.ones(cfg.nx)  # keep x-derivatives in the ghost columns
     _, bE, _ = g.field_advance(B0, B1, n, J, n, J, mode=0)
     assert np.abs(bE - rE).max() > 1e-3 * np.abs(rE).max()
+
+
+def test_injected_values_match_an_independent_inversion():
+    """Each injected ion against values computed another way: the counter
+    draws recomputed in Python from the generator's definition (splitmix64's
+    finaliser, the counter packing of the injection); the inflow flux F1 and
+    the flux-weighted speed distribution by numerical quadrature of
+    v f(v) (scipy.integrate.quad) and its inversion by root finding
+    (scipy.optimize.brentq), not the closed-form erf expressions; the
+    tangential velocities by Box-Muller; the entry depth v dt U.  Values are
+    compared after rounding to FP32, as the store holds them."""
+    import math
+
+    from scipy import integrate, optimize
+
+    M = (1 << 64) - 1
+
+    def mix(z):
+        z = (z + 0x9E3779B97F4A7C15) & M
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & M
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & M
+        return z ^ (z >> 31)
+
+    def uni(seed, ctr):
+        return (mix((seed + mix(ctr)) & M) >> 11) * 2.0 ** -53
+
+    def ctr(step, f, j, m, d):
+        return ((((step * 2 + f) << 16 | j) << 20 | m) << 7 | d) & M
+
+    cfg = _cfg(nx=6, ny=10, dt=0.05)
+    spec = dict(n=1.0, ux=0.5, uy=0.2, uz=-0.1, vth=0.4, ppc=128, faces=3)
+    seed, step = 77, 9
+    empty = {k: np.zeros(0, np.int32 if k == "cell" else np.float64)
+             for k in ("cell", "ox", "oy", "ux", "uy", "uz", "w")}
+    got = O.open_inject(cfg, spec, seed, step, empty)
+    vth = spec["vth"]
+    q = 0
+    for f in (0, 1):
+        u = spec["ux"] if f == 0 else -spec["ux"]
+        dens = lambda v: v * math.exp(-0.5 * (v - u) ** 2 / vth ** 2) / (math.sqrt(2 * math.pi) * vth)
+        F1 = integrate.quad(dens, 0.0, math.inf, epsabs=0, epsrel=1e-13)[0]
+        nexp = spec["ppc"] * cfg.dt / cfg.dx * F1
+        for j in range(cfg.ny):
+            k = math.floor(nexp + uni(seed, ctr(step, f, j, 0, 127)))
+            for m in range(k):
+                U = uni(seed, ctr(step, f, j, m, 0))
+                cdf = lambda v: integrate.quad(dens, 0.0, v, epsabs=0, epsrel=1e-13)[0] / F1 - U
+                v = optimize.brentq(cdf, 0.0, max(u, 0.0) + 10 * vth, xtol=1e-15, rtol=1e-15)
+
+                def normal(d):
+                    u1, u2 = uni(seed, ctr(step, f, j, m, d)), uni(seed, ctr(step, f, j, m, d + 1))
+                    return math.sqrt(-2.0 * math.log(1.0 - u1)) * math.cos(2 * math.pi * u2)
+
+                s = v * cfg.dt * uni(seed, ctr(step, f, j, m, 100))
+                o = -1.0 + 2.0 * s / cfg.dx
+                want = {"cell": (1 if f == 0 else cfg.nx - 2) + cfg.nx * j,
+                        "ox": o if f == 0 else -o,
+                        "oy": -1.0 + 2.0 * uni(seed, ctr(step, f, j, m, 101)),
+                        "ux": v if f == 0 else -v,
+                        "uy": spec["uy"] + vth * normal(96),
+                        "uz": spec["uz"] + vth * normal(98)}
+                assert got["cell"][q] == want["cell"], (f, j, m)
+                for key in ("ox", "oy", "ux", "uy", "uz"):
+                    assert abs(got[key][q] - np.float32(want[key])) <= 2e-7 * max(1.0, abs(want[key])), \
+                        (key, f, j, m, got[key][q], want[key])
+                q += 1
+    assert q == got["cell"].size and q > 50
