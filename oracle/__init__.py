@@ -89,7 +89,7 @@ def lib():
         L.orc_inflow_expected.argtypes = [P, I, _i32]
         L.orc_inflow_expected.restype = ctypes.c_double
         L.orc_open_inject.argtypes = [P, I, ctypes.c_uint64, _i64, _i64, _i64, _ip, _dp, _dp,
-                                      _dp, _dp, _dp, _dp]
+                                      _dp, _dp, _dp, _dp, _dp]
         L.orc_open_inject.restype = _i64
         L.orc_uniform.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
         L.orc_uniform.restype = ctypes.c_double
@@ -386,8 +386,9 @@ def open_inject(cfg, spec: dict, seed: int, step: int, parts: dict, cap_extra: i
     cap = n + cap_extra
     out = {k: np.concatenate([v, np.zeros(cap_extra, v.dtype)]) for k, v in parts.items()}
     out = {k: np.ascontiguousarray(v) for k, v in out.items()}
+    oz = _d(out["oz"]) if "oz" in out else None
     m = lib().orc_open_inject(ctypes.byref(params(cfg)), ctypes.byref(inflow(spec)), seed, step,
-                              n, cap, _i(out["cell"]), _d(out["ox"]), _d(out["oy"]),
+                              n, cap, _i(out["cell"]), _d(out["ox"]), _d(out["oy"]), oz,
                               _d(out["ux"]), _d(out["uy"]), _d(out["uz"]), _d(out["w"]))
     return {k: np.ascontiguousarray(v[:m]) for k, v in out.items()}
 

@@ -744,7 +744,7 @@ double orc_uniform(uint64_t seed, uint64_t ctr) {
   return (double)(mix64(seed + mix64(ctr)) >> 11) * (1.0 / 9007199254740992.0);
 }
 
-/* counter of draw d of ion m of row j of face f at a step */
+/* counter of draw d of ion m of row r = j + ny k of face f at a step */
 static uint64_t draw_ctr(int64_t step, int f, int j, int64_t m, int d) {
   return ((((uint64_t)step * 2u + (uint64_t)f) << 16 | (uint64_t)j) << 20 | (uint64_t)m) << 7 |
          (uint64_t)d;
@@ -797,33 +797,39 @@ double orc_inflow_expected(const orc_params* p, const orc_inflow* in, int32_t fa
 
 int64_t orc_open_inject(const orc_params* p, const orc_inflow* in, uint64_t seed, int64_t step,
                         int64_t np, int64_t cap, int32_t* cell, double* ox, double* oy,
-                        double* ux, double* uy, double* uz, double* w) {
+                        double* oz, double* ux, double* uy, double* uz, double* w) {
   double wb = in->n * p->dx * p->dy * p->dz / in->ppc;
+  int rows = p->ny * p->nz;
   for (int f = 0; f < 2; ++f) {
     if (!((in->faces >> f) & 1)) continue;
     double un = f == 0 ? in->ux : -in->ux;
     double nexp = orc_inflow_expected(p, in, f);
     int col = f == 0 ? 1 : p->nx - 2;
-    for (int j = 0; j < p->ny; ++j) {
-      int64_t k = (int64_t)floor(nexp + orc_uniform(seed, draw_ctr(step, f, j, 0, 127)));
-      for (int64_t m = 0; m < k && np < cap; ++m) {
+    for (int r = 0; r < rows; ++r) {
+      int j = r % p->ny, k = r / p->ny;
+      int64_t cnt = (int64_t)floor(nexp + orc_uniform(seed, draw_ctr(step, f, r, 0, 127)));
+      for (int64_t m = 0; m < cnt && np < cap; ++m) {
         /* normal speed: drifting Maxwellian weighted by v (v > 0), by
            inverting its distribution function at a uniform draw */
-        double v = inflow_speed(un, in->vth, orc_uniform(seed, draw_ctr(step, f, j, m, 0)));
-        double vy = in->uy + in->vth * normal_draw(seed, step, f, j, m, 96);
-        double vz = in->uz + in->vth * normal_draw(seed, step, f, j, m, 98);
+        double v = inflow_speed(un, in->vth, orc_uniform(seed, draw_ctr(step, f, r, m, 0)));
+        double vy = in->uy + in->vth * normal_draw(seed, step, f, r, m, 96);
+        double vz = in->uz + in->vth * normal_draw(seed, step, f, r, m, 98);
         /* entered at a uniform time within the step: depth v dt tau */
-        double s = v * p->dt * orc_uniform(seed, draw_ctr(step, f, j, m, 100));
+        double s = v * p->dt * orc_uniform(seed, draw_ctr(step, f, r, m, 100));
         double o = -1.0 + 2.0 * s / p->dx;
         if (o >= 1.0) o = 1.0 - 1e-7;
         /* the store holds FP32 values: the injected ion is what FP32 keeps */
         double xo = f == 0 ? o : -o;
         if (xo >= 1.0) xo = 1.0 - 1e-7;
-        cell[np] = (int32_t)cell_of(p, col, j, 0);
+        cell[np] = (int32_t)cell_of(p, col, j, k);
         ox[np] = (double)(float)xo;
         if (ox[np] >= 1.0) ox[np] = (double)nextafterf(1.0f, 0.0f);
-        oy[np] = (double)(float)(-1.0 + 2.0 * orc_uniform(seed, draw_ctr(step, f, j, m, 101)));
+        oy[np] = (double)(float)(-1.0 + 2.0 * orc_uniform(seed, draw_ctr(step, f, r, m, 101)));
         if (oy[np] >= 1.0) oy[np] = (double)nextafterf(1.0f, 0.0f);
+        if (p->ndim == 3 && oz) {
+          oz[np] = (double)(float)(-1.0 + 2.0 * orc_uniform(seed, draw_ctr(step, f, r, m, 102)));
+          if (oz[np] >= 1.0) oz[np] = (double)nextafterf(1.0f, 0.0f);
+        }
         ux[np] = (double)(float)(f == 0 ? v : -v);
         uy[np] = (double)(float)vy;
         uz[np] = (double)(float)vz;

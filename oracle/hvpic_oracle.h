@@ -41,8 +41,8 @@ typedef struct {
   double eta_h;                    /* hyper-resistivity                    */
   int32_t energy_eq;               /* 1: p_e evolved by the energy equation */
   double kappa0;                   /* heat conductivity in Q_e = -kappa0 grad T_e */
-  int32_t open_x;                  /* 1: x boundaries open (2D): columns 0 and
-                                      nx-1 are ghost columns                 */
+  int32_t open_x;                  /* 1: x boundaries open (2D or 3D): the cells
+                                      with i = 0 or nx-1 are ghost cells     */
   int32_t buffer_cells;            /* width of the enhanced eta_h layer        */
   double eta_h_buffer;             /* eta_h added at the open boundary (ramp)  */
 } orc_params;
@@ -162,10 +162,12 @@ int64_t orc_open_absorb(const orc_params* p, int64_t np, int32_t* cell);
 double orc_inflow_expected(const orc_params* p, const orc_inflow* in, int32_t face);
 
 /* Appends the ions injected this step (counter-based draws of seed and
-   step) after the np stored ones; returns the new count (at most cap). */
+   step) after the np stored ones; returns the new count (at most cap).  A
+   face's rows are its (j, k) cells, row r = j + ny k (ny nz <= 65536); oz
+   (3D) may be NULL in 2D. */
 int64_t orc_open_inject(const orc_params* p, const orc_inflow* in, uint64_t seed, int64_t step,
                         int64_t np, int64_t cap, int32_t* cell, double* ox, double* oy,
-                        double* ux, double* uy, double* uz, double* w);
+                        double* oz, double* ux, double* uy, double* uz, double* w);
 
 /* The uniform in [0, 1) of counter ctr and seed (splitmix64 mixing). */
 double orc_uniform(uint64_t seed, uint64_t ctr);

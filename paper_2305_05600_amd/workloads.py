@@ -185,32 +185,38 @@ def ensemble_run(spec: dict, shape: int = SHAPE_QS):
 def open_flow(seed: int = 9, nx: int = 64, ny: int = 32, ppc: int = 32, ux: float = 0.5,
               vth: float = 0.3, b0=(0.0, 1.0, 0.0), amp: float = 0.02, buffer_cells: int = 4,
               eta_h_buffer: float = 0.02, dt: float = 0.02, nsub: int = 4, dx: float = 0.5,
-              shape: int = SHAPE_QS, name: str | None = None):
-    """A plasma drifting along x through a 2D box open in x (Sec. II.C) and
-    periodic in y, across a fixed external field B0 (uniform, curl-free),
-    with a transverse B1 wave of amplitude amp in B1_z.
+              shape: int = SHAPE_QS, name: str | None = None, nz: int = 1):
+    """A plasma drifting along x through a box open in x (Sec. II.C) and
+    periodic in y (and z: nz > 1 makes the box 3D), across a fixed external
+    field B0 (uniform, curl-free), with a transverse B1 wave of amplitude amp
+    in B1_z.
 
-    The grid has nx interior columns plus a ghost column at each x end
-    (columns 0 and nx+1); ions (ppc per cell, density 1, drift ux, thermal
-    speed vth per component, T_e = vth^2) fill the interior columns.  The
+    The grid has nx interior columns plus a ghost column (3D: plane) at each
+    x end (i = 0 and nx+1); ions (ppc per cell, density 1, drift ux, thermal
+    speed vth per component, T_e = vth^2) fill the interior cells.  The
     same plasma enters through both faces (the inflow spec).  eta = 1e-3
     and a hyper-resistive buffer of buffer_cells cells with eta_h_buffer.
     Returns (cfg, parts, B0, B1, inflow)."""
-    cfg = Config(name=name or f"2d-open-flow-{nx}x{ny}-ppc{ppc}", ndim=2, nx=nx + 2, ny=ny,
-                 nz=1, dx=dx, dy=dx, dz=1.0, dt=dt, nsub=nsub, shape=shape, te=vth * vth,
-                 eta=1e-3, open_x=1, buffer_cells=buffer_cells, eta_h_buffer=eta_h_buffer)
+    ndim = 3 if nz > 1 else 2
+    tag = f"{nx}x{ny}" + (f"x{nz}" if ndim == 3 else "")
+    cfg = Config(name=name or f"{ndim}d-open-flow-{tag}-ppc{ppc}", ndim=ndim, nx=nx + 2, ny=ny,
+                 nz=nz, dx=dx, dy=dx, dz=dx if ndim == 3 else 1.0, dt=dt, nsub=nsub,
+                 shape=shape, te=vth * vth, eta=1e-3, open_x=1, buffer_cells=buffer_cells,
+                 eta_h_buffer=eta_h_buffer)
     rng = np.random.Generator(np.random.PCG64(seed))
-    ncol = nx * ny
+    ncol = nx * ny * nz
     n = ncol * ppc
     col = np.repeat(np.arange(ncol, dtype=np.int64), ppc)
     i = col % nx + 1
-    j = col // nx
+    j = (col // nx) % ny
+    k = col // (nx * ny)
     ox = _offsets(rng.uniform(-1.0, 1.0, n))
     oy = _offsets(rng.uniform(-1.0, 1.0, n))
+    oz = _offsets(rng.uniform(-1.0, 1.0, n)) if ndim == 3 else None
     u = rng.normal(0.0, vth, (3, n))
     u[0] += ux
     w = np.full(n, cfg.dx * cfg.dy * cfg.dz / ppc)
-    parts = _particles(cfg, i, j, 0 * i, ox, oy, None, u[0], u[1], u[2], w,
+    parts = _particles(cfg, i, j, k, ox, oy, oz, u[0], u[1], u[2], w,
                        order=rng.permutation(n))
     B0 = field_zeros(cfg)
     for a in range(3):

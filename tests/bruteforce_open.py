@@ -2,12 +2,13 @@
 advance (Sec. II.C), in NumPy, to check the C oracle against (it imports
 nothing from it).
 
-The 2D fields are held as [component][y][x] arrays and written another way
-than the oracle's cell loops:
+The fields are held as [component][z][y][x] arrays (nz = 1 in 2D) and
+written another way than the oracle's cell loops:
   * the ghost columns x = 0 and x = nx-1 are filled by slicing;
   * x-derivatives are whole-array periodic differences (np.roll) multiplied
     by a column mask that is 0 in the ghost columns, so Ohm's law there has
-    no x-gradient; y-derivatives are periodic differences everywhere;
+    no x-gradient; y- and z-derivatives are periodic differences everywhere
+    (the z ones only in 3D);
   * the hyper-resistive Laplacian is the forward difference of a backward
     difference, its x part masked the same way, and the buffer's eta_h is a
     per-column array built from the distance to the outermost interior
@@ -25,11 +26,9 @@ import numpy as np
 
 class OpenGrid:
     def __init__(self, cfg):
-        if cfg.ndim != 2:
-            raise ValueError("2D only")
         self.cfg = cfg
-        self.nx, self.ny = cfg.nx, cfg.ny
-        self.shape = (cfg.ny, cfg.nx)
+        self.nx, self.ny, self.nz = cfg.nx, cfg.ny, cfg.nz
+        self.shape = (cfg.nz, cfg.ny, cfg.nx)
         i = np.arange(cfg.nx)
         self.interior = ((i > 0) & (i < cfg.nx - 1)).astype(float)  # per column
         d = np.maximum(np.minimum(i, cfg.nx - 1 - i) - 1, 0)
@@ -42,7 +41,7 @@ class OpenGrid:
         return F.reshape((-1,) + self.shape) if F.ndim > 1 else F.reshape(self.shape)
 
     def flat(self, F):
-        return np.asarray(F).reshape(F.shape[0], -1) if F.ndim == 3 else np.asarray(F).ravel()
+        return np.asarray(F).reshape(F.shape[0], -1) if F.ndim == 4 else np.asarray(F).ravel()
 
     def fill(self, F):
         F = F.copy()
@@ -56,16 +55,24 @@ class OpenGrid:
     def dy(self, Q):
         return (np.roll(Q, -1, -2) - np.roll(Q, 1, -2)) / (2 * self.cfg.dy)
 
+    def dz(self, Q):
+        if self.cfg.ndim == 2:
+            return np.zeros_like(Q)
+        return (np.roll(Q, -1, -3) - np.roll(Q, 1, -3)) / (2 * self.cfg.dz)
+
     def lap(self, Q):
-        fx = (np.roll(Q, -1, -1) - Q) / self.cfg.dx
-        lx = (fx - np.roll(fx, 1, -1)) / self.cfg.dx
-        fy = (np.roll(Q, -1, -2) - Q) / self.cfg.dy
-        ly = (fy - np.roll(fy, 1, -2)) / self.cfg.dy
-        return ly + lx * self.interior
+        def second(axis, h):
+            f = (np.roll(Q, -1, axis) - Q) / h
+            return (f - np.roll(f, 1, axis)) / h
+        r = second(-2, self.cfg.dy) + second(-1, self.cfg.dx) * self.interior
+        if self.cfg.ndim == 3:
+            r = r + second(-3, self.cfg.dz)
+        return r
 
     def curl(self, A):
         Ax, Ay, Az = A
-        return np.stack([self.dy(Az), -self.dx(Az), self.dx(Ay) - self.dy(Ax)])
+        return np.stack([self.dy(Az) - self.dz(Ay), self.dz(Ax) - self.dx(Az),
+                         self.dx(Ay) - self.dy(Ax)])
 
     def ohm(self, B0, B1, n, Ji):
         c = self.cfg
@@ -74,7 +81,7 @@ class OpenGrid:
         pe = c.n0 * c.te * (ne / c.n0) ** c.gamma_e
         B = B0 + B1
         ui = Ji / ne
-        gp = np.stack([self.dx(pe), self.dy(pe), np.zeros_like(pe)])
+        gp = np.stack([self.dx(pe), self.dy(pe), self.dz(pe)])
         E = -gp / ne - np.cross(ui, B, axis=0) + np.cross(J, B, axis=0) / ne + c.eta * J
         hyper = np.stack([self.lap(J[a]) for a in range(3)]) * self.eta_h
         return E - hyper

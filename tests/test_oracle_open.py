@@ -212,10 +212,12 @@ def test_draws_follow_the_published_splitmix64_sequence():
         assert O.uniform(seed, state) == (outs[k] >> 11) * 2.0 ** -53, k
 
 
-@pytest.mark.parametrize("nx,ny,nsub,mode,eta_h,buf", [
-    (14, 9, 3, 0, 0.0, 3), (14, 9, 3, 0, 2e-3, 4), (5, 6, 2, 0, 1e-3, 1), (3, 4, 1, 0, 0.0, 2),
-    (14, 9, 0, 0, 1e-3, 3), (14, 9, 3, 1, 1e-3, 3), (30, 7, 4, 0, 0.0, 0)])
-def test_open_field_advance_matches_an_independent_numpy_form(nx, ny, nsub, mode, eta_h, buf):
+@pytest.mark.parametrize("nx,ny,nz,nsub,mode,eta_h,buf", [
+    (14, 9, 1, 3, 0, 0.0, 3), (14, 9, 1, 3, 0, 2e-3, 4), (5, 6, 1, 2, 0, 1e-3, 1),
+    (3, 4, 1, 1, 0, 0.0, 2), (14, 9, 1, 0, 0, 1e-3, 3), (14, 9, 1, 3, 1, 1e-3, 3),
+    (30, 7, 1, 4, 0, 0.0, 0), (9, 5, 4, 2, 0, 1e-3, 2), (6, 3, 5, 1, 1, 0.0, 1),
+    (4, 4, 2, 3, 0, 2e-3, 3)])
+def test_open_field_advance_matches_an_independent_numpy_form(nx, ny, nz, nsub, mode, eta_h, buf):
     """tests/bruteforce_open.py writes the open rules again with whole-array
     NumPy stencils and a column mask for the ghost columns, importing nothing
     from the oracle.  On fields that vary along x and y (so that every ghost
@@ -226,7 +228,9 @@ def test_open_field_advance_matches_an_independent_numpy_form(nx, ny, nsub, mode
 
     cfg = _cfg(nx=nx, ny=ny, nsub=nsub, eta_h=eta_h, buffer_cells=buf, eta_h_buffer=0.03,
                gamma_e=5.0 / 3.0)
-    rng = np.random.default_rng(nx * 100 + ny + nsub)
+    if nz > 1:
+        cfg = cfg.replace(ndim=3, nz=nz, dz=0.6)
+    rng = np.random.default_rng(nx * 100 + ny + 10 * nz + nsub)
     B0 = np.zeros((3, cfg.ncell))
     B0[:] = np.array([[0.3], [1.0], [-0.2]])
     B1 = rng.normal(scale=0.1, size=(3, cfg.ncell))
@@ -267,7 +271,8 @@ def test_numpy_form_fails_on_a_planted_ghost_mistake():
     assert np.abs(bE - rE).max() > 1e-3 * np.abs(rE).max()
 
 
-def test_injected_values_match_an_independent_inversion():
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_injected_values_match_an_independent_inversion(ndim):
     """Each injected ion against values computed another way: the counter
     draws recomputed in Python from the generator's definition (splitmix64's
     finaliser, the counter packing of the injection); the inflow flux F1 and
@@ -295,10 +300,12 @@ def test_injected_values_match_an_independent_inversion():
         return ((((step * 2 + f) << 16 | j) << 20 | m) << 7 | d) & M
 
     cfg = _cfg(nx=6, ny=10, dt=0.05)
+    if ndim == 3:
+        cfg = cfg.replace(ndim=3, ny=4, nz=3, dz=0.6)  # rows r = j + ny k
     spec = dict(n=1.0, ux=0.5, uy=0.2, uz=-0.1, vth=0.4, ppc=128, faces=3)
     seed, step = 77, 9
-    empty = {k: np.zeros(0, np.int32 if k == "cell" else np.float64)
-             for k in ("cell", "ox", "oy", "ux", "uy", "uz", "w")}
+    keys = ("cell", "ox", "oy") + (("oz",) if ndim == 3 else ()) + ("ux", "uy", "uz", "w")
+    empty = {k: np.zeros(0, np.int32 if k == "cell" else np.float64) for k in keys}
     got = O.open_inject(cfg, spec, seed, step, empty)
     vth = spec["vth"]
     q = 0
@@ -307,28 +314,48 @@ def test_injected_values_match_an_independent_inversion():
         dens = lambda v: v * math.exp(-0.5 * (v - u) ** 2 / vth ** 2) / (math.sqrt(2 * math.pi) * vth)
         F1 = integrate.quad(dens, 0.0, math.inf, epsabs=0, epsrel=1e-13)[0]
         nexp = spec["ppc"] * cfg.dt / cfg.dx * F1
-        for j in range(cfg.ny):
-            k = math.floor(nexp + uni(seed, ctr(step, f, j, 0, 127)))
+        for r in range(cfg.ny * cfg.nz):
+            j, kz = r % cfg.ny, r // cfg.ny
+            k = math.floor(nexp + uni(seed, ctr(step, f, r, 0, 127)))
             for m in range(k):
-                U = uni(seed, ctr(step, f, j, m, 0))
+                U = uni(seed, ctr(step, f, r, m, 0))
                 cdf = lambda v: integrate.quad(dens, 0.0, v, epsabs=0, epsrel=1e-13)[0] / F1 - U
                 v = optimize.brentq(cdf, 0.0, max(u, 0.0) + 10 * vth, xtol=1e-15, rtol=1e-15)
 
                 def normal(d):
-                    u1, u2 = uni(seed, ctr(step, f, j, m, d)), uni(seed, ctr(step, f, j, m, d + 1))
+                    u1, u2 = uni(seed, ctr(step, f, r, m, d)), uni(seed, ctr(step, f, r, m, d + 1))
                     return math.sqrt(-2.0 * math.log(1.0 - u1)) * math.cos(2 * math.pi * u2)
 
-                s = v * cfg.dt * uni(seed, ctr(step, f, j, m, 100))
+                s = v * cfg.dt * uni(seed, ctr(step, f, r, m, 100))
                 o = -1.0 + 2.0 * s / cfg.dx
-                want = {"cell": (1 if f == 0 else cfg.nx - 2) + cfg.nx * j,
+                want = {"cell": (1 if f == 0 else cfg.nx - 2) + cfg.nx * (j + cfg.ny * kz),
                         "ox": o if f == 0 else -o,
-                        "oy": -1.0 + 2.0 * uni(seed, ctr(step, f, j, m, 101)),
+                        "oy": -1.0 + 2.0 * uni(seed, ctr(step, f, r, m, 101)),
                         "ux": v if f == 0 else -v,
                         "uy": spec["uy"] + vth * normal(96),
                         "uz": spec["uz"] + vth * normal(98)}
+                if ndim == 3:
+                    want["oz"] = -1.0 + 2.0 * uni(seed, ctr(step, f, r, m, 102))
                 assert got["cell"][q] == want["cell"], (f, j, m)
-                for key in ("ox", "oy", "ux", "uy", "uz"):
+                for key in want:
+                    if key == "cell":
+                        continue
                     assert abs(got[key][q] - np.float32(want[key])) <= 2e-7 * max(1.0, abs(want[key])), \
                         (key, f, j, m, got[key][q], want[key])
                 q += 1
     assert q == got["cell"].size and q > 50
+
+
+def test_open_flow_3d_keeps_its_density():
+    """The 3D form of the open-flow workload (ghost planes at both x ends):
+    over 30 steps the faces inject about what the opposite faces absorb."""
+    cfg, parts, B0, B1, spec = W.open_flow(nx=12, ny=8, nz=6, ppc=8, amp=0.0)
+    sim = O.OpenOracleSim(cfg, parts, B0, B1, spec, seed=5)
+    n0 = sim.p["cell"].size
+    for _ in range(30):
+        sim.step()
+    n1 = sim.p["cell"].size
+    assert sim.absorbed > 100 and sim.injected > 100
+    assert abs(n1 - n0) < 0.05 * n0
+    i = sim.p["cell"] % cfg.nx
+    assert np.all((i >= 1) & (i <= cfg.nx - 2))  # nothing left in a ghost plane
