@@ -92,9 +92,9 @@ typedef struct {
                                 electron energy equation (gamma_e > 1), through
                                 hvpic_field_advance_pe                          */
   double kappa0;             /* electron heat conductivity (>= 0; energy_eq)    */
-  int32_t open_x;            /* 0: periodic in x; 1: open in x (Sec. II.C, 2D,
-                                nx >= 3): columns 0 and nx-1 are ghost columns,
-                                driven by the hvpic_open_* calls                */
+  int32_t open_x;            /* 0: periodic in x; 1: open in x (Sec. II.C,
+                                nx >= 3): the cells i = 0 and i = nx-1 are
+                                ghosts, driven by the hvpic_open_* calls        */
   int32_t buffer_cells;      /* open_x: width w of the absorbing layer (>= 0)    */
   double eta_h_buffer;       /* open_x: eta_h added in the layer, ramping from
                                 eta_h_buffer at the outermost interior column to
@@ -506,9 +506,11 @@ int hvpic_no_conv3x3_wgrad(int nimg, int nx, int ny, int cinp, int coutp, const 
                            void* hip_stream);
 
 /* ---------------------------------------------------------------------------
- * Open boundaries in x (Sec. II.C), 2D, for a context with open_x = 1.  The
- * grid's columns 0 and nx-1 are ghost columns outside the domain; the
- * domain is columns 1 .. nx-2.  The magnetic field is split B = B0 + B1:
+ * Open boundaries in x (Sec. II.C), 2D or 3D, for a context with open_x = 1.
+ * The grid's cells i = 0 and i = nx-1 (columns in 2D, planes in 3D; called
+ * ghost columns below) lie outside the domain; the domain is i = 1 .. nx-2.
+ * A face's rows are its ny nz cells (j, k), row r = j + ny k.  The magnetic
+ * field is split B = B0 + B1:
  * B0 (device [3][ncell]) is a fixed external field with curl B0 = 0 that
  * the caller keeps, only B1 is advanced, and the plasma current of Ohm's
  * Hall and resistive terms is J = curl B1.  In a ghost cell B1 and the
@@ -537,9 +539,9 @@ typedef struct {
   int32_t faces;
 } hvpic_inflow;
 
-/* Copies column 1 into column 0 and column nx-2 into column nx-1 of the
-   ncomp (1..16) component-major arrays F [ncomp][ncell] (the ghost rule of
-   B1 and the moments). */
+/* Copies column 1 into column 0 and column nx-2 into column nx-1, in every
+   row (j, k), of the ncomp (1..16) component-major arrays F [ncomp][ncell]
+   (the ghost rule of B1 and the moments). */
 int hvpic_open_fill(hvpic_ctx* ctx, float* F, int ncomp);
 
 /* hvpic_field_advance for open x: B1 (in/out [3][ncell]) advanced by the
@@ -592,9 +594,10 @@ int hvpic_sort_open_perm(hvpic_ctx* ctx, const hvpic_particles* in, int64_t n_pu
    the counter packing (step, face, row, ion, draw), so a run is repeatable.
    An injected ion sits in the first interior column at depth v dt U' from
    its face (v the inward normal speed, drawn from the flux-weighted
-   distribution by inverting its distribution function), uniformly in y,
-   tangential velocities drifting Maxwellian, weight n dx dy dz / ppc.
-   0 <= step < 2^20, ny <= 65535.  p's arrays must hold np_capacity ions;
+   distribution by inverting its distribution function), uniformly in y
+   (and z in 3D: p->oz required), tangential velocities drifting
+   Maxwellian, weight n dx dy dz / ppc.  0 <= step < 2^20, ny nz <= 65536,
+   fewer than 2^20 ions per row.  p's arrays must hold np_capacity ions;
    HVPIC_ENOMEM (nothing launched) when the injected ions would exceed it. */
 int hvpic_open_particles(hvpic_ctx* ctx, hvpic_particles* p, const hvpic_inflow* in,
                          uint64_t seed, int64_t step);

@@ -35,7 +35,7 @@ bool params_ok(const hvpic_params* p) {
   if (p->energy_eq && !(p->gamma_e > 1.0)) return false;  // W_e = sum p V/(gamma-1)
   if (!isfinite(p->kappa0) || p->kappa0 < 0.0) return false;
   if (p->open_x != 0 && p->open_x != 1) return false;
-  if (p->open_x && (p->ndim != 2 || p->nx < 3)) return false;
+  if (p->open_x && p->nx < 3) return false;
   if (p->buffer_cells < 0 || !isfinite(p->eta_h_buffer) || p->eta_h_buffer < 0.0) return false;
   if (p->np_capacity < 0 || p->np_capacity >= (1ll << 31) - 1) return false;
   return true;
@@ -109,7 +109,8 @@ Layout workspace_layout(const hvpic_params* p) {
   L.rhist = off;     off += align256(sizeof(uint32_t) * kRadixBins * ntiles);
   L.fscratch = off;  off += align256(sizeof(float) * 25 * nc);
   L.mom_acc = off;   off += align256(sizeof(double) * 4 * nc);
-  L.open_rows = off; off += align256(p->open_x ? sizeof(int32_t) * 3 * 2 * (size_t)p->ny : 0);
+  L.open_rows = off;
+  off += align256(p->open_x ? sizeof(int32_t) * 3 * 2 * (size_t)p->ny * (size_t)p->nz : 0);
   L.total = off;
   return L;
 }

@@ -29,7 +29,7 @@ namespace {
 
 struct OpenG {
   FGeo g;
-  float ilx, ily;        // 1/dx^2, 1/dy^2
+  float ilx, ily, ilz;   // 1/dx^2, 1/dy^2, 1/dz^2
   float eta, eta_h, eta_hb;
   int nbuf;
 };
@@ -46,18 +46,20 @@ __device__ __forceinline__ float eta_h_col(int i, const OpenG& o) {
   return e;
 }
 
-// ghost columns of ncomp component-major arrays <- their interior neighbours
-__global__ void k_open_fill(float* __restrict__ F, int ncomp, int nx, int ny, int ncell) {
+// ghost cells of ncomp component-major arrays <- their interior neighbours
+// (rows = ny nz grid rows along x per component)
+__global__ void k_open_fill(float* __restrict__ F, int ncomp, int nx, int rows, int ncell) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= ncomp * ny) return;
-  const int a = t / ny, j = t - (t / ny) * ny;
-  float* f = F + (int64_t)a * ncell + (int64_t)j * nx;
+  if (t >= ncomp * rows) return;
+  const int a = t / rows, r = t - (t / rows) * rows;
+  float* f = F + (int64_t)a * ncell + (int64_t)r * nx;
   f[0] = f[1];
   f[nx - 1] = f[nx - 2];
 }
 
 // 1/n_f, u_i and -grad(p_e)/n_f of the held moments (no x-component of the
-// pressure gradient in a ghost column)
+// pressure gradient in a ghost cell)
+template <int NDIM>
 __global__ __launch_bounds__(kBlock) void k_open_prep(const float* __restrict__ n,
                                                       const float* __restrict__ Ji, FGeo g,
                                                       Eos eos, Aux aux) {
@@ -74,11 +76,11 @@ __global__ __launch_bounds__(kBlock) void k_open_prep(const float* __restrict__ 
   auto pres = [&](int q) { return pressure(n[q], eos.nfloor, eos.te_n0, eos.n0, eos.gam, eos.iso); };
   aux.gp[c] = ghost_col(i, g.nx) ? 0.0f : -(pres(nn.xp) - pres(nn.xm)) * g.idx2 * inv;
   aux.gp[nc + c] = -(pres(nn.yp) - pres(nn.ym)) * g.idy2 * inv;
-  aux.gp[2 * nc + c] = 0.0f;
+  aux.gp[2 * nc + c] = NDIM == 3 ? -(pres(nn.zp) - pres(nn.zm)) * g.idz2 * inv : 0.0f;
 }
 
 // J = curl B1 (B1 = hi + lo with HAS_LO), no x-derivatives in the ghosts
-template <bool HAS_LO>
+template <int NDIM, bool HAS_LO>
 __global__ __launch_bounds__(kBlock) void k_open_curl(const float* __restrict__ Bh,
                                                       const float* __restrict__ Bl,
                                                       float* __restrict__ J, FGeo g) {
@@ -94,21 +96,29 @@ __global__ __launch_bounds__(kBlock) void k_open_curl(const float* __restrict__ 
   const float dyBx = (B(n.yp) - B(n.ym)) * g.idy2;
   const float dxBz = gh ? 0.0f : (B(2 * nc + n.xp) - B(2 * nc + n.xm)) * g.idx2;
   const float dxBy = gh ? 0.0f : (B(nc + n.xp) - B(nc + n.xm)) * g.idx2;
-  J[c] = dyBz;
-  J[nc + c] = -dxBz;
+  float dzBy = 0.f, dzBx = 0.f;
+  if (NDIM == 3) {
+    dzBy = (B(nc + n.zp) - B(nc + n.zm)) * g.idz2;
+    dzBx = (B(n.zp) - B(n.zm)) * g.idz2;
+  }
+  J[c] = dyBz - dzBy;
+  J[nc + c] = dzBx - dxBz;
   J[2 * nc + c] = dxBy - dyBx;
 }
 
-// lap of component a of J at c (x part dropped in a ghost column)
+// lap of component a of J at c (x part dropped in a ghost cell)
+template <int NDIM>
 __device__ __forceinline__ float lap_open(const float* __restrict__ J, int a, int c, int i,
                                           const Nbr& n, const OpenG& o) {
   const float* q = J + (int64_t)a * o.g.ncell;
   float r = (q[n.yp] + q[n.ym] - 2.0f * q[c]) * o.ily;
   if (!ghost_col(i, o.g.nx)) r += (q[n.xp] + q[n.xm] - 2.0f * q[c]) * o.ilx;
+  if (NDIM == 3) r += (q[n.zp] + q[n.zm] - 2.0f * q[c]) * o.ilz;
   return r;
 }
 
 // E = (J/n_f - u_i) x (B0 + B1) - grad(p_e)/n_f + eta J - eta_h(x) lap J
+template <int NDIM>
 __global__ __launch_bounds__(kBlock) void k_open_ohm(const float* __restrict__ B0,
                                                      const float* __restrict__ B1,
                                                      const float* __restrict__ J, Aux aux,
@@ -127,9 +137,9 @@ __global__ __launch_bounds__(kBlock) void k_open_ohm(const float* __restrict__ B
   const float eh = eta_h_col(i, o);
   float h0 = 0.f, h1 = 0.f, h2 = 0.f;
   if (eh != 0.0f) {
-    h0 = eh * lap_open(J, 0, c, i, n, o);
-    h1 = eh * lap_open(J, 1, c, i, n, o);
-    h2 = eh * lap_open(J, 2, c, i, n, o);
+    h0 = eh * lap_open<NDIM>(J, 0, c, i, n, o);
+    h1 = eh * lap_open<NDIM>(J, 1, c, i, n, o);
+    h2 = eh * lap_open<NDIM>(J, 2, c, i, n, o);
   }
   E[c] = (w1 * b2 - w2 * b1) + aux.gp[c] + o.eta * j0 - h0;
   E[nc + c] = (w2 * b0 - w0 * b2) + aux.gp[nc + c] + o.eta * j1 - h1;
@@ -138,6 +148,7 @@ __global__ __launch_bounds__(kBlock) void k_open_ohm(const float* __restrict__ B
 
 // B1_dst = B1_base - coef curl E in the interior (compensated into lo when
 // given); base and dst are read and written at the thread's own cell only
+template <int NDIM>
 __global__ __launch_bounds__(kBlock) void k_open_faraday(const float* __restrict__ E,
                                                          const float* Bbase, float* Bdst, float* lo,
                                                          float coef, FGeo g) {
@@ -148,7 +159,7 @@ __global__ __launch_bounds__(kBlock) void k_open_faraday(const float* __restrict
   if (ghost_col(i, g.nx)) return;
   const BSum<false> Ea{E, nullptr};
   float ce[3];
-  curl_at<2>(Ea, c, g, ce);
+  curl_at<NDIM>(Ea, c, g, ce);
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     const int q = a * g.ncell + c;
@@ -170,7 +181,7 @@ __global__ __launch_bounds__(kBlock) void k_open_faraday(const float* __restrict
 // B1 (when non-null), Btot = B0 + B1; per-block FP64 partials over the
 // interior cells of {|Btot|^2, Btot, electron energy of n_eff}; the cells of
 // na below the floor counted (all columns).
-template <bool EXTRAP, bool HAS_LO>
+template <int NDIM, bool EXTRAP, bool HAS_LO>
 __global__ __launch_bounds__(kBlock) void k_open_final(
     const float* __restrict__ Bh, const float* __restrict__ Bl, const float* __restrict__ J,
     const float* __restrict__ B0, float* __restrict__ B1out, float* __restrict__ Btot,
@@ -203,18 +214,19 @@ __global__ __launch_bounds__(kBlock) void k_open_final(
     };
     const float gp0 = gh ? 0.0f : -(pres(n.xp) - pres(n.xm)) * o.g.idx2 * inv;
     const float gp1 = -(pres(n.yp) - pres(n.ym)) * o.g.idy2 * inv;
+    const float gp2 = NDIM == 3 ? -(pres(n.zp) - pres(n.zm)) * o.g.idz2 * inv : 0.0f;
     const float j0 = J[c], j1 = J[nc + c], j2 = J[2 * nc + c];
     const float w0 = j0 * inv - u[0], w1 = j1 * inv - u[1], w2 = j2 * inv - u[2];
     const float eh = eta_h_col(i, o);
     float h0 = 0.f, h1 = 0.f, h2 = 0.f;
     if (eh != 0.0f) {
-      h0 = eh * lap_open(J, 0, c, i, n, o);
-      h1 = eh * lap_open(J, 1, c, i, n, o);
-      h2 = eh * lap_open(J, 2, c, i, n, o);
+      h0 = eh * lap_open<NDIM>(J, 0, c, i, n, o);
+      h1 = eh * lap_open<NDIM>(J, 1, c, i, n, o);
+      h2 = eh * lap_open<NDIM>(J, 2, c, i, n, o);
     }
     E[c] = (w1 * b2 - w2 * b1) + gp0 + o.eta * j0 - h0;
     E[nc + c] = (w2 * b0 - w0 * b2) + gp1 + o.eta * j1 - h1;
-    E[2 * nc + c] = (w0 * b1 - w1 * b0) + 0.0f + o.eta * j2 - h2;
+    E[2 * nc + c] = (w0 * b1 - w1 * b0) + gp2 + o.eta * j2 - h2;
     if (B1out) {
       B1out[c] = c0;
       B1out[nc + c] = c1;
@@ -262,16 +274,16 @@ __host__ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
 __host__ __device__ __forceinline__ double uniform01(uint64_t seed, uint64_t ctr) {
   return (double)(mix64(seed + mix64(ctr)) >> 11) * (1.0 / 9007199254740992.0);
 }
-// counter of draw d of ion m of row j of face f at a step
-__host__ __device__ __forceinline__ uint64_t draw_ctr(int64_t step, int f, int j, int64_t m,
+// counter of draw d of ion m of face row r (r = j + ny k) of face f at a step
+__host__ __device__ __forceinline__ uint64_t draw_ctr(int64_t step, int f, int r, int64_t m,
                                                       int d) {
-  return ((((uint64_t)step * 2u + (uint64_t)f) << 16 | (uint64_t)j) << 20 | (uint64_t)m) << 7 |
+  return ((((uint64_t)step * 2u + (uint64_t)f) << 16 | (uint64_t)r) << 20 | (uint64_t)m) << 7 |
          (uint64_t)d;
 }
 
-__device__ double normal_draw(uint64_t seed, int64_t step, int f, int j, int64_t m, int d) {
-  const double u1 = uniform01(seed, draw_ctr(step, f, j, m, d));
-  const double u2 = uniform01(seed, draw_ctr(step, f, j, m, d + 1));
+__device__ double normal_draw(uint64_t seed, int64_t step, int f, int r, int64_t m, int d) {
+  const double u1 = uniform01(seed, draw_ctr(step, f, r, m, d));
+  const double u2 = uniform01(seed, draw_ctr(step, f, r, m, d + 1));
   return sqrt(-2.0 * log(1.0 - u1)) * cos(6.283185307179586 * u2);
 }
 
@@ -301,28 +313,28 @@ __device__ double inflow_speed(double u, double vth, double U) {
 struct Inject {
   double nexp[2], un[2];
   double uy, uz, vth, dt, dx, w;
-  int faces, nx, ny;
+  int faces, nx, rows;  // rows = ny nz cells on a face
   uint64_t seed;
   int64_t step, n0;
 };
 
 // One block: per (face, row) the count floor(nexp + U) and its exclusive
-// prefix over the rows in order (face-major): the injected ions of row r
-// are stored from n0 + off[r].
+// prefix over the rows in order (face-major): the injected ions of face f's
+// row r are stored from n0 + off[f rows + r].
 __global__ __launch_bounds__(1024) void k_open_inject_count(Inject P, int32_t* __restrict__ cnt,
                                                            int32_t* __restrict__ off) {
   __shared__ int32_t s_sum[1024];
   __shared__ int32_t s_carry;
   if (threadIdx.x == 0) s_carry = 0;
   __syncthreads();
-  const int rows = 2 * P.ny;
+  const int rows = 2 * P.rows;
   for (int r0 = 0; r0 < rows; r0 += 1024) {
     const int r = r0 + (int)threadIdx.x;
     int k = 0;
     if (r < rows) {
-      const int f = r / P.ny, j = r - f * P.ny;
+      const int f = r / P.rows, rr = r - f * P.rows;
       if ((P.faces >> f) & 1)
-        k = (int)floor(P.nexp[f] + uniform01(P.seed, draw_ctr(P.step, f, j, 0, 127)));
+        k = (int)floor(P.nexp[f] + uniform01(P.seed, draw_ctr(P.step, f, rr, 0, 127)));
     }
     // inclusive scan over the block (Hillis-Steele in LDS)
     s_sum[threadIdx.x] = k;
@@ -344,20 +356,22 @@ __global__ __launch_bounds__(1024) void k_open_inject_count(Inject P, int32_t* _
   }
 }
 
-// One thread per injected ion t < total: its row r is the last with
-// off[r] <= t (that row holds it: off[r+1] = off[r] + cnt[r] > t), its rank
-// m = t - off[r]; the ion's draws are those of (step, face, row, m).
+// One thread per injected ion t < total: its (face, row) slot s is the last
+// with off[s] <= t (that slot holds it: off[s+1] = off[s] + cnt[s] > t), its
+// rank m = t - off[s]; the ion's draws are those of (step, face, row, m).
+// oz is written in 3D only (null in 2D).
 __global__ __launch_bounds__(256) void k_open_inject_draw(Inject P, const int32_t* __restrict__ off,
                                                          int64_t total, int32_t* __restrict__ cell,
                                                          float* __restrict__ ox,
                                                          float* __restrict__ oy,
+                                                         float* __restrict__ oz,
                                                          float* __restrict__ ux,
                                                          float* __restrict__ uy,
                                                          float* __restrict__ uz,
                                                          float* __restrict__ w) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= total) return;
-  int lo = 0, hi = 2 * P.ny - 1;  // off[0] = 0 <= t
+  int lo = 0, hi = 2 * P.rows - 1;  // off[0] = 0 <= t
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
     if ((int64_t)off[mid] <= t)
@@ -365,24 +379,30 @@ __global__ __launch_bounds__(256) void k_open_inject_draw(Inject P, const int32_
     else
       hi = mid - 1;
   }
-  const int r = lo, f = r / P.ny, j = r - f * P.ny;
-  const int64_t m = t - off[r];
-  const double v = inflow_speed(P.un[f], P.vth, uniform01(P.seed, draw_ctr(P.step, f, j, m, 0)));
-  const double vy = P.uy + P.vth * normal_draw(P.seed, P.step, f, j, m, 96);
-  const double vz = P.uz + P.vth * normal_draw(P.seed, P.step, f, j, m, 98);
-  const double s = v * P.dt * uniform01(P.seed, draw_ctr(P.step, f, j, m, 100));
+  const int f = lo / P.rows, r = lo - f * P.rows;
+  const int64_t m = t - off[lo];
+  const double v = inflow_speed(P.un[f], P.vth, uniform01(P.seed, draw_ctr(P.step, f, r, m, 0)));
+  const double vy = P.uy + P.vth * normal_draw(P.seed, P.step, f, r, m, 96);
+  const double vz = P.uz + P.vth * normal_draw(P.seed, P.step, f, r, m, 98);
+  const double s = v * P.dt * uniform01(P.seed, draw_ctr(P.step, f, r, m, 100));
   double o = -1.0 + 2.0 * s / P.dx;
   if (o >= 1.0) o = 1.0 - 1e-7;
   double xo = f == 0 ? o : -o;
   if (xo >= 1.0) xo = 1.0 - 1e-7;
   float fx = (float)xo;
   if (fx >= 1.0f) fx = 0.99999994f;
-  float fy = (float)(-1.0 + 2.0 * uniform01(P.seed, draw_ctr(P.step, f, j, m, 101)));
+  float fy = (float)(-1.0 + 2.0 * uniform01(P.seed, draw_ctr(P.step, f, r, m, 101)));
   if (fy >= 1.0f) fy = 0.99999994f;
   const int64_t q = P.n0 + t;
-  cell[q] = (f == 0 ? 1 : P.nx - 2) + P.nx * j;
+  // cell (col, j, k) = col + nx (j + ny k) = col + nx r
+  cell[q] = (f == 0 ? 1 : P.nx - 2) + P.nx * r;
   ox[q] = fx;
   oy[q] = fy;
+  if (oz) {
+    float fz = (float)(-1.0 + 2.0 * uniform01(P.seed, draw_ctr(P.step, f, r, m, 102)));
+    if (fz >= 1.0f) fz = 0.99999994f;
+    oz[q] = fz;
+  }
   ux[q] = (float)(f == 0 ? v : -v);
   uy[q] = (float)vy;
   uz[q] = (float)vz;
@@ -401,6 +421,7 @@ OpenG open_geo(const hvpic_ctx* c) {
   o.g = fgeo(c);
   o.ilx = (float)(1.0 / (c->p.dx * c->p.dx));
   o.ily = (float)(1.0 / (c->p.dy * c->p.dy));
+  o.ilz = (float)(1.0 / (c->p.dz * c->p.dz));
   o.eta = (float)c->p.eta;
   o.eta_h = (float)c->p.eta_h;
   o.eta_hb = (float)c->p.eta_h_buffer;
@@ -408,10 +429,14 @@ OpenG open_geo(const hvpic_ctx* c) {
   return o;
 }
 
+// cells on one open face: the grid rows along x
+int face_rows(const hvpic_ctx* c) { return c->p.ny * (c->p.ndim == 3 ? c->p.nz : 1); }
+
 void fill(hvpic_ctx* c, float* F, int ncomp) {
-  const int t = ncomp * c->p.ny;
+  const int rows = face_rows(c);
+  const int t = ncomp * rows;
   hipLaunchKernelGGL(k_open_fill, dim3((unsigned)ceil_div(t, 256)), dim3(256), 0, c->stream, F,
-                     ncomp, c->p.nx, c->p.ny, c->ncell);
+                     ncomp, c->p.nx, rows, c->ncell);
 }
 
 bool open_ok(const hvpic_ctx* c) { return c && c->magic == kMagic && c->p.open_x == 1; }
@@ -423,11 +448,12 @@ int inject_plan(hvpic_ctx* c, const hvpic_particles* p, const hvpic_inflow* in, 
                 int64_t step, Inject& P, int64_t& total) {
   if (!open_ok(c) || !p || !in || step < 0 || step >= (int64_t(1) << 20)) return HVPIC_EINVAL;
   if (p->n < 0 || p->n > c->p.np_capacity || !p->cell || !p->ox || !p->oy || !p->ux || !p->uy ||
-      !p->uz || !p->w)
+      !p->uz || !p->w || (c->p.ndim == 3 && !p->oz))
     return HVPIC_EINVAL;
+  const int rows = face_rows(c);
   if (!(in->n > 0.0) || !(in->vth > 0.0) || !isfinite(in->n) || !isfinite(in->vth) ||
       in->ppc < 1 || !isfinite(in->ux) || !isfinite(in->uy) || !isfinite(in->uz) ||
-      in->faces < 0 || in->faces > 3 || c->p.ny > 65535)
+      in->faces < 0 || in->faces > 3 || rows > 65536)
     return HVPIC_EINVAL;
   for (int f = 0; f < 2; ++f) {
     P.un[f] = f == 0 ? in->ux : -in->ux;
@@ -441,15 +467,15 @@ int inject_plan(hvpic_ctx* c, const hvpic_particles* p, const hvpic_inflow* in, 
   P.w = in->n * c->p.dx * c->p.dy * c->p.dz / in->ppc;
   P.faces = in->faces;
   P.nx = c->p.nx;
-  P.ny = c->p.ny;
+  P.rows = rows;
   P.seed = seed;
   P.step = step;
   P.n0 = p->n;
   total = 0;
   for (int f = 0; f < 2; ++f) {
     if (!((in->faces >> f) & 1)) continue;
-    for (int j = 0; j < c->p.ny; ++j) {
-      const int64_t k = (int64_t)floor(P.nexp[f] + uniform01(seed, draw_ctr(step, f, j, 0, 127)));
+    for (int r = 0; r < rows; ++r) {
+      const int64_t k = (int64_t)floor(P.nexp[f] + uniform01(seed, draw_ctr(step, f, r, 0, 127)));
       if (k >= (int64_t(1) << 20)) return HVPIC_EINVAL;  // beyond the counter's ion field
       total += k;
     }
@@ -465,13 +491,90 @@ void inject_launch(hvpic_ctx* c, hvpic_particles* p, const Inject& P, int64_t to
   c->inj_k = total;
   if (total > 0) {
     int32_t* cnt = c->open_rows;
-    int32_t* off = c->open_rows + 2 * c->p.ny;
+    int32_t* off = c->open_rows + 2 * P.rows;
+    float* oz = c->p.ndim == 3 ? p->oz : nullptr;
     hipLaunchKernelGGL(k_open_inject_count, dim3(1), dim3(1024), 0, c->stream, P, cnt, off);
     hipLaunchKernelGGL(k_open_inject_draw, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0,
-                       c->stream, P, (const int32_t*)off, total, p->cell, p->ox, p->oy, p->ux,
+                       c->stream, P, (const int32_t*)off, total, p->cell, p->ox, p->oy, oz, p->ux,
                        p->uy, p->uz, p->w);
   }
   p->n += total;
+}
+
+// the open field advance of one dimension (arguments checked by the caller)
+template <int NDIM>
+void open_advance(hvpic_ctx* c, const float* B0, float* B1, float* Btot, const float* n_half,
+                  const float* J_half, const float* n_prev, const float* J_prev, float* E_out,
+                  int mode, double* diag_out) {
+  const OpenG o = open_geo(c);
+  const FGeo& g = o.g;
+  const int nc = c->ncell;
+  const dim3 grid((unsigned)ceil_div(nc, kBlock)), blk(kBlock);
+  hipStream_t s = c->stream;
+  const Eos eos = make_eos(c);
+  Aux aux;
+  aux.inv = c->fscratch;
+  aux.u = c->fscratch + nc;
+  aux.gp = c->fscratch + 4ll * nc;
+  float* Xh = c->fscratch + 7ll * nc;
+  float* Xl = c->fscratch + 10ll * nc;
+  float* Yh = c->fscratch + 13ll * nc;
+  float* J = c->fscratch + 16ll * nc;
+  float* E = c->fscratch + 19ll * nc;
+  double* part = diag_out ? c->field_part : nullptr;
+  const float* fh = B1;
+  const float* fl = nullptr;
+  if (mode == 0) fill(c, B1, 3);
+  if (mode == 0 && c->p.nsub > 0) {
+    const float h = (float)(c->p.dt / c->p.nsub);
+    hipLaunchKernelGGL(k_open_prep<NDIM>, grid, blk, 0, s, n_half, J_half, g, eos, aux);
+    const int cblocks = (int)std::min<int64_t>(ceil_div(3ll * nc, kBlock), 1024);
+    hipLaunchKernelGGL(k_copy, dim3(cblocks), blk, 0, s, (const float*)B1, Xh, 3ll * nc);
+    hipLaunchKernelGGL(k_fill, dim3(cblocks), blk, 0, s, Xl, 3ll * nc, 0.0f);
+    for (int m = 0; m < c->p.nsub; ++m) {
+      hipLaunchKernelGGL((k_open_curl<NDIM, false>), grid, blk, 0, s, (const float*)Xh,
+                         (const float*)nullptr, J, g);
+      hipLaunchKernelGGL(k_open_ohm<NDIM>, grid, blk, 0, s, B0, (const float*)Xh, (const float*)J,
+                         aux, E, o);
+      hipLaunchKernelGGL(k_open_faraday<NDIM>, grid, blk, 0, s, (const float*)E, (const float*)Xh,
+                         Yh, (float*)nullptr, 0.5f * h, g);
+      fill(c, Yh, 3);
+      hipLaunchKernelGGL((k_open_curl<NDIM, false>), grid, blk, 0, s, (const float*)Yh,
+                         (const float*)nullptr, J, g);
+      hipLaunchKernelGGL(k_open_ohm<NDIM>, grid, blk, 0, s, B0, (const float*)Yh, (const float*)J,
+                         aux, E, o);
+      hipLaunchKernelGGL(k_open_faraday<NDIM>, grid, blk, 0, s, (const float*)E, (const float*)Xh,
+                         Xh, Xl, h, g);
+      fill(c, Xh, 3);
+      fill(c, Xl, 3);
+    }
+    fh = Xh;
+    fl = Xl;
+  }
+  if (fl)
+    hipLaunchKernelGGL((k_open_curl<NDIM, true>), grid, blk, 0, s, fh, fl, J, g);
+  else
+    hipLaunchKernelGGL((k_open_curl<NDIM, false>), grid, blk, 0, s, fh, fl, J, g);
+  float* B1out = fh == B1 ? nullptr : B1;
+  if (mode == 0 && fl)
+    hipLaunchKernelGGL((k_open_final<NDIM, true, true>), grid, blk, 0, s, fh, fl, (const float*)J,
+                       B0, B1out, Btot, n_half, n_prev, J_half, J_prev, 1.5f, -0.5f, o, eos, E_out,
+                       part, c->status);
+  else if (mode == 0)
+    hipLaunchKernelGGL((k_open_final<NDIM, true, false>), grid, blk, 0, s, fh, fl, (const float*)J,
+                       B0, B1out, Btot, n_half, n_prev, J_half, J_prev, 1.5f, -0.5f, o, eos, E_out,
+                       part, c->status);
+  else
+    hipLaunchKernelGGL((k_open_final<NDIM, false, false>), grid, blk, 0, s, fh, fl,
+                       (const float*)J, B0, B1out, Btot, n_half, n_prev, J_half, J_prev, 1.5f,
+                       -0.5f, o, eos, E_out, part, c->status);
+  if (diag_out) {
+    const double V = c->p.dx * c->p.dy * c->p.dz;
+    const double we_scale = eos.iso ? V * c->p.te : V * c->p.n0 * c->p.te / (c->p.gamma_e - 1.0);
+    const int interior = nc - 2 * face_rows(c);
+    hipLaunchKernelGGL(k_field_diag_final, dim3(1), dim3(1024), 0, s, (const double*)part,
+                       (int)grid.x, diag_out, 0.5 * V, 1.0 / (double)interior, we_scale);
+  }
 }
 
 }  // namespace
@@ -496,76 +599,10 @@ int hvpic_open_field_advance(hvpic_ctx* ctx, const float* B0, float* B1, float* 
     return HVPIC_EINVAL;
   if (mode != 0 && mode != 1) return HVPIC_EINVAL;
   if (mode == 0 && (!n_prev || !J_prev)) return HVPIC_EINVAL;
-  hvpic_ctx* c = ctx;
-  const OpenG o = open_geo(c);
-  const FGeo& g = o.g;
-  const int nc = c->ncell;
-  const dim3 grid((unsigned)ceil_div(nc, kBlock)), blk(kBlock);
-  hipStream_t s = c->stream;
-  const Eos eos = make_eos(c);
-  Aux aux;
-  aux.inv = c->fscratch;
-  aux.u = c->fscratch + nc;
-  aux.gp = c->fscratch + 4ll * nc;
-  float* Xh = c->fscratch + 7ll * nc;
-  float* Xl = c->fscratch + 10ll * nc;
-  float* Yh = c->fscratch + 13ll * nc;
-  float* J = c->fscratch + 16ll * nc;
-  float* E = c->fscratch + 19ll * nc;
-  double* part = diag_out ? c->field_part : nullptr;
-  const float* fh = B1;
-  const float* fl = nullptr;
-  if (mode == 0) fill(c, B1, 3);
-  if (mode == 0 && c->p.nsub > 0) {
-    const float h = (float)(c->p.dt / c->p.nsub);
-    hipLaunchKernelGGL(k_open_prep, grid, blk, 0, s, n_half, J_half, g, eos, aux);
-    const int cblocks = (int)std::min<int64_t>(ceil_div(3ll * nc, kBlock), 1024);
-    hipLaunchKernelGGL(k_copy, dim3(cblocks), blk, 0, s, (const float*)B1, Xh, 3ll * nc);
-    hipLaunchKernelGGL(k_fill, dim3(cblocks), blk, 0, s, Xl, 3ll * nc, 0.0f);
-    for (int m = 0; m < c->p.nsub; ++m) {
-      hipLaunchKernelGGL((k_open_curl<false>), grid, blk, 0, s, (const float*)Xh,
-                         (const float*)nullptr, J, g);
-      hipLaunchKernelGGL(k_open_ohm, grid, blk, 0, s, B0, (const float*)Xh, (const float*)J, aux,
-                         E, o);
-      hipLaunchKernelGGL(k_open_faraday, grid, blk, 0, s, (const float*)E, (const float*)Xh, Yh,
-                         (float*)nullptr, 0.5f * h, g);
-      fill(c, Yh, 3);
-      hipLaunchKernelGGL((k_open_curl<false>), grid, blk, 0, s, (const float*)Yh,
-                         (const float*)nullptr, J, g);
-      hipLaunchKernelGGL(k_open_ohm, grid, blk, 0, s, B0, (const float*)Yh, (const float*)J, aux,
-                         E, o);
-      hipLaunchKernelGGL(k_open_faraday, grid, blk, 0, s, (const float*)E, (const float*)Xh, Xh, Xl,
-                         h, g);
-      fill(c, Xh, 3);
-      fill(c, Xl, 3);
-    }
-    fh = Xh;
-    fl = Xl;
-  }
-  if (fl)
-    hipLaunchKernelGGL((k_open_curl<true>), grid, blk, 0, s, fh, fl, J, g);
+  if (ctx->p.ndim == 3)
+    open_advance<3>(ctx, B0, B1, Btot, n_half, J_half, n_prev, J_prev, E_out, mode, diag_out);
   else
-    hipLaunchKernelGGL((k_open_curl<false>), grid, blk, 0, s, fh, fl, J, g);
-  float* B1out = fh == B1 ? nullptr : B1;
-  if (mode == 0 && fl)
-    hipLaunchKernelGGL((k_open_final<true, true>), grid, blk, 0, s, fh, fl, (const float*)J, B0,
-                       B1out, Btot, n_half, n_prev, J_half, J_prev, 1.5f, -0.5f, o, eos, E_out, part,
-                       c->status);
-  else if (mode == 0)
-    hipLaunchKernelGGL((k_open_final<true, false>), grid, blk, 0, s, fh, fl, (const float*)J, B0,
-                       B1out, Btot, n_half, n_prev, J_half, J_prev, 1.5f, -0.5f, o, eos, E_out, part,
-                       c->status);
-  else
-    hipLaunchKernelGGL((k_open_final<false, false>), grid, blk, 0, s, fh, fl, (const float*)J, B0,
-                       B1out, Btot, n_half, n_prev, J_half, J_prev, 1.5f, -0.5f, o, eos, E_out, part,
-                       c->status);
-  if (diag_out) {
-    const double V = c->p.dx * c->p.dy * c->p.dz;
-    const double we_scale = eos.iso ? V * c->p.te : V * c->p.n0 * c->p.te / (c->p.gamma_e - 1.0);
-    const int interior = nc - 2 * c->p.ny;
-    hipLaunchKernelGGL(k_field_diag_final, dim3(1), dim3(1024), 0, s, (const double*)part,
-                       (int)grid.x, diag_out, 0.5 * V, 1.0 / (double)interior, we_scale);
-  }
+    open_advance<2>(ctx, B0, B1, Btot, n_half, J_half, n_prev, J_prev, E_out, mode, diag_out);
   return hipGetLastError() == hipSuccess ? HVPIC_OK : HVPIC_EHIP;
 }
 
@@ -620,8 +657,9 @@ int hvpic_sort_open_perm(hvpic_ctx* ctx, const hvpic_particles* in, int64_t n_pu
       return HVPIC_EINVAL;
     inj_cnt = c->open_rows;
   }
+  const int rows = face_rows(c);
   return launch_sort_open_perm(c, in, n_pushed, cell_start_prev, perm, cell_start, info, inj_cnt,
-                               c->open_rows + 2 * c->p.ny, c->open_rows + 4 * c->p.ny);
+                               c->open_rows + 2 * rows, c->open_rows + 4 * rows);
 }
 
 }  // extern "C"

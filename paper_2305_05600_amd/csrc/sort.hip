@@ -259,17 +259,18 @@ __device__ uint32_t tile_exclusive_scan(uint32_t* s) {
   return total;
 }
 
-// Open x boundaries (Sec. II.C): columns 0 and nx-1 are ghost columns.
+// Open x boundaries (Sec. II.C): the cells i = 0 and i = nx-1 are ghosts.
 // Ions whose new cell is a ghost cell are absorbed (left out of the order);
-// inj_cnt[f*ny + j] ions injected through face f into row j follow the
-// pushed ions in the store and come last in their cell (column 1 for f = 0,
-// nx-2 for f = 1).  inj_base receives the first slot of each such group;
-// info[0] = 1 when the neighbour path cannot be taken (far movers or an
-// inconsistent cell_start: nothing else is then written).
+// inj_cnt[f*rows + r] ions injected through face f into its row r = j + ny k
+// (rows = ny nz) follow the pushed ions in the store and come last in their
+// cell (i = 1 for f = 0, nx-2 for f = 1).  inj_base receives the first slot
+// of each such group; info[0] = 1 when the neighbour path cannot be taken
+// (far movers or an inconsistent cell_start: nothing else is then written).
 struct OpenSort {
-  const int32_t* inj_cnt;  // [2][ny] or null (no injection)
-  int32_t* inj_base;       // [2][ny]
+  const int32_t* inj_cnt;  // [2][rows] or null (no injection)
+  int32_t* inj_base;       // [2][rows]
   int32_t* info;           // device int32[2] or null
+  int rows;
 };
 
 // Per-new-cell totals, written to cs[c], and their per-tile sums (tiles of
@@ -303,8 +304,9 @@ __device__ __forceinline__ void nb_newcount_body(const uint32_t* __restrict__ cn
       if (i == 0 || i == g.nx - 1) {
         s = 0;
       } else if (os.inj_cnt) {
-        if (i == 1) s += (uint32_t)os.inj_cnt[j];
-        if (i == g.nx - 2) s += (uint32_t)os.inj_cnt[g.ny + j];
+        const int r = j + g.ny * k;
+        if (i == 1) s += (uint32_t)os.inj_cnt[r];
+        if (i == g.nx - 2) s += (uint32_t)os.inj_cnt[os.rows + r];
       }
     }
     cs[c] = (int32_t)s;
@@ -413,12 +415,13 @@ __device__ __forceinline__ void nb_bases_body(uint32_t* __restrict__ cnt, const 
                           (NDIM == 2 || (g.nz >= 3 && k >= 1 && k <= g.nz - 2));
     if (OPEN && os.inj_cnt && (i == 1 || i == g.nx - 2)) {
       // the injected ions of the cell follow all the moved ones
+      const int r = j + g.ny * k;
       uint32_t moved = 0;
       for (int d = 0; d < ND; ++d) moved += n[d];
-      if (i == 1) os.inj_base[j] = (int32_t)(start + moved);
+      if (i == 1) os.inj_base[r] = (int32_t)(start + moved);
       if (i == g.nx - 2)
-        os.inj_base[g.ny + j] =
-            (int32_t)(start + moved + (i == 1 ? (uint32_t)os.inj_cnt[j] : 0u));
+        os.inj_base[os.rows + r] =
+            (int32_t)(start + moved + (i == 1 ? (uint32_t)os.inj_cnt[r] : 0u));
     }
     if (interior) {
       uint32_t before = 0;
@@ -798,35 +801,37 @@ __global__ __launch_bounds__(kBlock) void k_nb_scatter(const int32_t* __restrict
                               blockIdx.x);
 }
 
-// The open-boundary form (gather map, 2D): absorbed ions left out, injected
+// The open-boundary form (gather map): absorbed ions left out, injected
 // ions appended to their cells.
-template <int TILE>
+template <int NDIM, int TILE>
 __global__ __launch_bounds__(kBlock) void k_nb_newcount_open(const uint32_t* __restrict__ cnt,
                                                              SortGeo g, int32_t* __restrict__ cs,
                                                              uint32_t* __restrict__ blk,
                                                              Status* st, OpenSort os) {
-  nb_newcount_body<2, TILE, true>(cnt, g, cs, blk, st, blockIdx.x, os);
+  nb_newcount_body<NDIM, TILE, true>(cnt, g, cs, blk, st, blockIdx.x, os);
 }
 
-template <int TILE>
+template <int NDIM, int TILE>
 __global__ __launch_bounds__(kBlock) void k_nb_bases_open(uint32_t* __restrict__ cnt, SortGeo g,
                                                           int32_t* __restrict__ cs,
                                                           const uint32_t* __restrict__ blk,
                                                           OpenSort os) {
-  nb_bases_body<2, TILE, true>(cnt, g, cs, blk, blockIdx.x, os);
+  nb_bases_body<NDIM, TILE, true>(cnt, g, cs, blk, blockIdx.x, os);
 }
 
+template <int NDIM>
 __global__ __launch_bounds__(kBlock) void k_nb_scatter_open(const int32_t* __restrict__ cs_prev,
                                                             int64_t n, SortGeo g,
                                                             uint32_t* __restrict__ bases,
                                                             Fields in, Fields out, int32_t* cs,
                                                             const Status* st) {
-  nb_scatter_body<2, true, true>(cs_prev, n, g, bases, in, out, cs, st, nullptr, nullptr,
-                                 nullptr, nullptr, blockIdx.x);
+  nb_scatter_body<NDIM, true, true>(cs_prev, n, g, bases, in, out, cs, st, nullptr, nullptr,
+                                    nullptr, nullptr, blockIdx.x);
 }
 
-// The gather-map entries of the injected ions (row r's ions are stored
-// contiguously from n_pushed + inj_off[r]) and info[1] = the live count.
+// The gather-map entries of the injected ions (slot r's ions, r over the
+// face-major (face, row) pairs, are stored contiguously from
+// n_pushed + inj_off[r]) and info[1] = the live count.
 __global__ void k_open_inject_perm(const int32_t* __restrict__ inj_cnt,
                                    const int32_t* __restrict__ inj_off,
                                    const int32_t* __restrict__ inj_base, int rows, int64_t n_pushed,
@@ -1034,9 +1039,13 @@ int launch_sort_open(hvpic_ctx* c, const hvpic_particles* in, hvpic_particles* o
   return hipGetLastError() == hipSuccess ? HVPIC_OK : HVPIC_EHIP;
 }
 
-int launch_sort_open_perm(hvpic_ctx* c, const hvpic_particles* in, int64_t n_pushed,
-                          const int32_t* cs_prev, int32_t* perm, int32_t* cs, int32_t* info,
-                          const int32_t* inj_cnt, const int32_t* inj_off, int32_t* inj_base) {
+namespace {
+
+template <int NDIM>
+void enqueue_sort_open_perm(hvpic_ctx* c, const hvpic_particles* in, int64_t n_pushed,
+                            const int32_t* cs_prev, int32_t* perm, int32_t* cs, int32_t* info,
+                            const int32_t* inj_cnt, const int32_t* inj_off, int32_t* inj_base,
+                            int rows) {
   hipStream_t s = c->stream;
   const SortGeo g = sort_geo(c);
   uint32_t* blk = (uint32_t*)c->sort_blk;
@@ -1044,34 +1053,47 @@ int launch_sort_open_perm(hvpic_ctx* c, const hvpic_particles* in, int64_t n_pus
                        c->cnt_n == n_pushed;
   if (!counted) {
     const int cblocks = (int)ceil_div(c->ncell, kWaves * kCellsPerWave);
-    hipLaunchKernelGGL((k_nb_count<2>), dim3(cblocks), dim3(kBlock), 0, s, in->cell, cs_prev,
+    hipLaunchKernelGGL((k_nb_count<NDIM>), dim3(cblocks), dim3(kBlock), 0, s, in->cell, cs_prev,
                        n_pushed, g, c->sort_cnt, c->status);
   }
-  const OpenSort os{inj_cnt, inj_base, info};
+  const OpenSort os{inj_cnt, inj_base, info, rows};
   if (c->ncell <= kNbTileSmall * 512) {
     const int tiles = (int)ceil_div(c->ncell, kNbTileSmall);
-    hipLaunchKernelGGL((k_nb_newcount_open<kNbTileSmall>), dim3(tiles), dim3(kBlock), 0, s,
+    hipLaunchKernelGGL((k_nb_newcount_open<NDIM, kNbTileSmall>), dim3(tiles), dim3(kBlock), 0, s,
                        (const uint32_t*)c->sort_cnt, g, cs, blk, c->status, os);
-    hipLaunchKernelGGL((k_nb_bases_open<kNbTileSmall>), dim3(tiles), dim3(kBlock), 0, s,
+    hipLaunchKernelGGL((k_nb_bases_open<NDIM, kNbTileSmall>), dim3(tiles), dim3(kBlock), 0, s,
                        c->sort_cnt, g, cs, (const uint32_t*)blk, os);
   } else {
     const int tiles = (int)ceil_div(c->ncell, kScanTile);
-    hipLaunchKernelGGL((k_nb_newcount_open<kScanTile>), dim3(tiles), dim3(kBlock), 0, s,
+    hipLaunchKernelGGL((k_nb_newcount_open<NDIM, kScanTile>), dim3(tiles), dim3(kBlock), 0, s,
                        (const uint32_t*)c->sort_cnt, g, cs, blk, c->status, os);
-    hipLaunchKernelGGL((k_nb_bases_open<kScanTile>), dim3(tiles), dim3(kBlock), 0, s,
+    hipLaunchKernelGGL((k_nb_bases_open<NDIM, kScanTile>), dim3(tiles), dim3(kBlock), 0, s,
                        c->sort_cnt, g, cs, (const uint32_t*)blk, os);
   }
   Fields out{};
   out.perm = perm;
   timing_begin(c, HVPIC_KERNEL_SORT_SCATTER);
   const int sblocks = (int)ceil_div(c->ncell, kWaves * kScatterCells);
-  hipLaunchKernelGGL(k_nb_scatter_open, dim3(sblocks), dim3(kBlock), 0, s, cs_prev, in->n, g,
-                     c->sort_cnt, fields_of(in), out, cs, (const Status*)c->status);
+  hipLaunchKernelGGL(k_nb_scatter_open<NDIM>, dim3(sblocks), dim3(kBlock), 0, s, cs_prev, in->n,
+                     g, c->sort_cnt, fields_of(in), out, cs, (const Status*)c->status);
   timing_end(c, HVPIC_KERNEL_SORT_SCATTER);
-  const int rows = 2 * c->p.ny;
-  hipLaunchKernelGGL(k_open_inject_perm, dim3((unsigned)ceil_div(rows, 256)), dim3(256), 0, s,
-                     inj_cnt, inj_off, (const int32_t*)inj_base, rows, n_pushed, perm,
+  hipLaunchKernelGGL(k_open_inject_perm, dim3((unsigned)ceil_div(2 * rows, 256)), dim3(256), 0, s,
+                     inj_cnt, inj_off, (const int32_t*)inj_base, 2 * rows, n_pushed, perm,
                      (const Status*)c->status, info, (const int32_t*)cs, c->ncell);
+}
+
+}  // namespace
+
+int launch_sort_open_perm(hvpic_ctx* c, const hvpic_particles* in, int64_t n_pushed,
+                          const int32_t* cs_prev, int32_t* perm, int32_t* cs, int32_t* info,
+                          const int32_t* inj_cnt, const int32_t* inj_off, int32_t* inj_base) {
+  const int rows = c->p.ny * (c->p.ndim == 3 ? c->p.nz : 1);
+  if (c->p.ndim == 3)
+    enqueue_sort_open_perm<3>(c, in, n_pushed, cs_prev, perm, cs, info, inj_cnt, inj_off,
+                              inj_base, rows);
+  else
+    enqueue_sort_open_perm<2>(c, in, n_pushed, cs_prev, perm, cs, info, inj_cnt, inj_off,
+                              inj_base, rows);
   c->cnt_clean = true;
   c->cnt_ready = false;
   return hipGetLastError() == hipSuccess ? HVPIC_OK : HVPIC_EHIP;

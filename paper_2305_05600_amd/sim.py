@@ -531,14 +531,15 @@ class OpenSim:
     def __init__(self, cfg, parts: dict, B0, B1, spec: dict, seed: int, capacity: int | None = None,
                  device="cuda", diagnostics: bool = True, gather_map: bool = True,
                  overlap: bool = True):
-        if not cfg.open_x or cfg.ndim != 2:
-            raise ValueError("OpenSim needs a 2D config with open_x")
+        if not cfg.open_x:
+            raise ValueError("OpenSim needs a config with open_x")
         self.cfg, self.spec, self.seed = cfg, spec, int(seed)
         self.device = device
         self.gather_map = gather_map
         n = int(parts["cell"].size)
         # room for the inflow to outrun the outflow for a while
-        cap = int(capacity) if capacity else 2 * n + 4 * cfg.ny * int(spec["ppc"]) + 4096
+        face = cfg.ny * (cfg.nz if cfg.ndim == 3 else 1)
+        cap = int(capacity) if capacity else 2 * n + 4 * face * int(spec["ppc"]) + 4096
         self.capacity = cap
         self.s = torch.cuda.Stream(device)
         self.overlap = overlap and gather_map
@@ -549,8 +550,8 @@ class OpenSim:
         self.inflow = H.inflow_from(spec)
         nc = cfg.ncell
         f32 = dict(dtype=torch.float32, device=device)
-        self.p = H.Particles.from_numpy(parts, 2, cap, device)
-        self.q = H.Particles(2, cap, device)
+        self.p = H.Particles.from_numpy(parts, cfg.ndim, cap, device)
+        self.q = H.Particles(cfg.ndim, cap, device)
         self.cs = torch.zeros(nc + 2, dtype=torch.int32, device=device)
         self.cs_alt = torch.zeros(nc + 2, dtype=torch.int32, device=device)
         self.perm = torch.zeros(cap, dtype=torch.int32, device=device) if gather_map else None

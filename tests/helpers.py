@@ -202,6 +202,8 @@ def drop_open_straddlers(cfg, parts: dict, B0, B1, spec: dict, seed: int, band=1
         p = O.apply_perm(p, perm)
         O.push(cfg, p, sim.E, sim.Btot)
         near = _near_face(p["ox"], band) | _near_face(p["oy"], band)
+        if cfg.ndim == 3:
+            near |= _near_face(p["oz"], band)
         near |= deposit_point_straddlers(cfg, p, 0.5 * cfg.dt, band)
         if not near.any():
             print(f"straddlers removed: {int((~keep).sum())} of {keep.size} "

@@ -59,7 +59,7 @@ def test_workspace_bytes_and_validation(H):
            dict(n_floor=0.0), dict(eta_h=-1e-3), dict(eta_h=float("nan")),
            dict(energy_eq=2), dict(energy_eq=1, gamma_e=1.0), dict(energy_eq=1, gamma_e=0.5),
            dict(kappa0=-0.1), dict(kappa0=float("inf")), dict(np_capacity=-1), dict(nsub=-1),
-           dict(open_x=2), dict(open_x=1, nx=2), dict(open_x=1, ndim=3, nz=4),
+           dict(open_x=2), dict(open_x=1, nx=2),
            dict(buffer_cells=-1), dict(eta_h_buffer=-0.1), dict(eta_h_buffer=float("nan"))]
     for b in bad:
         q = H.params_from(cfg, 65536)
@@ -75,6 +75,12 @@ def test_workspace_bytes_and_validation(H):
         # open x adds the injection's per-row counts, offsets and slots
         extra = -(-3 * 2 * cfg.ny * 4 // 256) * 256 if good.get("open_x") else 0
         assert H.hvpic_workspace_bytes(q) == nb + extra, good
+    # in 3D a face has ny nz rows
+    q3 = H.params_from(cfg, 65536)
+    q3.ndim, q3.nz = 3, 5
+    nb3 = H.hvpic_workspace_bytes(q3)
+    q3.open_x = 1
+    assert H.hvpic_workspace_bytes(q3) == nb3 + -(-3 * 2 * cfg.ny * 5 * 4 // 256) * 256
 
 
 def test_init_rejects_bad_arguments_without_device_work(H):

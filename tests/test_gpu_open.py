@@ -40,8 +40,20 @@ def _cfg(nx, ny, **kw):
     return W.Config(**base)
 
 
+def _cfg3(nx, ny, nz, **kw):
+    return _cfg(nx, ny, ndim=3, nz=nz, dz=0.45, **kw)
+
+
 GRIDS = [("37x23", _cfg(37, 23)), ("3x5", _cfg(3, 5)), ("6x2", _cfg(6, 2)),
-         ("70x9-wide-buffer", _cfg(70, 9, buffer_cells=12))]
+         ("70x9-wide-buffer", _cfg(70, 9, buffer_cells=12)),
+         ("3d-12x8x6", _cfg3(12, 8, 6)), ("3d-3x4x5", _cfg3(3, 4, 5)),
+         ("3d-20x3x4-wide-buffer", _cfg3(20, 3, 4, buffer_cells=6))]
+
+
+def _ghost(cfg):
+    """Mask of the ghost cells (i = 0 or nx-1) over the flat cell index."""
+    i = np.arange(cfg.ncell) % cfg.nx
+    return (i == 0) | (i == cfg.nx - 1)
 
 
 def _inputs(cfg, seed):
@@ -55,9 +67,9 @@ def _inputs(cfg, seed):
     return B0, B1, nh, npv, Jh, Jp
 
 
-def test_open_fill(H):
-    announce("open_fill")
-    cfg = _cfg(37, 23)
+@pytest.mark.parametrize("cfg", [_cfg(37, 23), _cfg3(9, 7, 5)], ids=["2d", "3d"])
+def test_open_fill(H, cfg):
+    announce("open_fill", cfg.ndim)
     ctx = H.Context(cfg, 1)
     F = np.random.default_rng(3).normal(size=(5, cfg.ncell)).astype(np.float32)
     Fd = dev(F)
@@ -87,9 +99,7 @@ def test_open_field_advance(H, name, cfg, mode, nsub, eta_h):
         assert rel_l2(Btd.cpu().numpy(), rBt) < 1e-5
         assert rel_l2(Ed.cpu().numpy(), rE) < 1e-5
         # the ghost columns on their own
-        g = np.zeros((cfg.ny, cfg.nx), bool)
-        g[:, [0, -1]] = True
-        g = g.ravel()
+        g = _ghost(cfg)
         assert rel_l2(Ed.cpu().numpy()[:, g], rE[:, g]) < 1e-5
         check_field_diag(diag.cpu().numpy(), rd)
         assert counts[2] == st.floor_hits
@@ -123,7 +133,13 @@ def test_entry_points_check_the_open_flag(H):
     with pytest.raises(H.HvpicError):
         H.hvpic_open_fill(b.ctx, z3, 3)
     with pytest.raises(H.HvpicError):
-        H.Context(cfg.replace(ndim=3, nz=2), 1)
+        H.Context(cfg.replace(nx=2), 1)
+    # a 3D injection needs the z offsets
+    c3 = _cfg3(6, 4, 3)
+    d = H.Context(c3, 4096)
+    p = H.Particles(2, 4096)
+    with pytest.raises(H.HvpicError):
+        H.hvpic_open_inject(d.ctx, p, H.inflow_from(_spec()), 1, 0)
 
 
 def _store(cfg, n, seed, dead_frac=0.0, ghost_frac=0.0):
@@ -132,13 +148,17 @@ def _store(cfg, n, seed, dead_frac=0.0, ghost_frac=0.0):
     rng = np.random.default_rng(seed)
     i = rng.integers(1, cfg.nx - 1, n)
     j = rng.integers(0, cfg.ny, n)
+    k = rng.integers(0, cfg.nz, n) if cfg.ndim == 3 else np.zeros(n, np.int64)
     g = rng.random(n) < ghost_frac
     i[g] = np.where(rng.random(g.sum()) < 0.5, 0, cfg.nx - 1)
-    cell = (i + cfg.nx * j).astype(np.int32)
+    cell = (i + cfg.nx * (j + cfg.ny * k)).astype(np.int32)
     cell[rng.random(n) < dead_frac] = cfg.ncell
     f = lambda: rng.uniform(-1, 1, n).astype(np.float32)
-    return dict(cell=cell, ox=f(), oy=f(), ux=f(), uy=f(), uz=f(),
-                w=rng.uniform(0.5, 1.5, n).astype(np.float32))
+    st = dict(cell=cell, ox=f(), oy=f(), ux=f(), uy=f(), uz=f(),
+              w=rng.uniform(0.5, 1.5, n).astype(np.float32))
+    if cfg.ndim == 3:
+        st["oz"] = f()
+    return st
 
 
 @pytest.mark.parametrize("nx,ny,n,dead", [(37, 23, 50000, 0.1), (6, 5, 257, 0.5), (6, 5, 0, 0.0),
@@ -167,37 +187,45 @@ def _pushed_store(cfg, n, seed, far=False):
     moved by -1, 0 or +1 along each axis, some into the ghost columns; with
     far, one ion moved by two cells.  Returns (store, cs_prev)."""
     rng = np.random.default_rng(seed)
+    nz = cfg.nz if cfg.ndim == 3 else 1
     i = rng.integers(1, cfg.nx - 1, n)
     j = rng.integers(0, cfg.ny, n)
-    old = np.sort((i + cfg.nx * j).astype(np.int64))
+    k = rng.integers(0, nz, n)
+    old = np.sort((i + cfg.nx * (j + cfg.ny * k)).astype(np.int64))
     cs_prev = np.concatenate([[0], np.cumsum(np.bincount(old, minlength=cfg.ncell))])
-    io, jo = old % cfg.nx, old // cfg.nx
+    io, jo, ko = old % cfg.nx, (old // cfg.nx) % cfg.ny, old // (cfg.nx * cfg.ny)
     di = rng.choice([-1, 0, 1], n, p=[0.15, 0.7, 0.15])
     dj = rng.choice([-1, 0, 1], n, p=[0.1, 0.8, 0.1])
+    dk = rng.choice([-1, 0, 1], n, p=[0.1, 0.8, 0.1]) if nz > 1 else np.zeros(n, np.int64)
     if far and n:
         di[n // 2] = 2 if io[n // 2] < cfg.nx - 3 else -2
-    cell = ((io + di) % cfg.nx + cfg.nx * ((jo + dj) % cfg.ny)).astype(np.int32)
+    cell = ((io + di) % cfg.nx +
+            cfg.nx * ((jo + dj) % cfg.ny + cfg.ny * ((ko + dk) % nz))).astype(np.int32)
     f = lambda: rng.uniform(-1, 1, n).astype(np.float32)
     st = dict(cell=cell, ox=f(), oy=f(), ux=f(), uy=f(), uz=f(),
               w=rng.uniform(0.5, 1.5, n).astype(np.float32))
+    if cfg.ndim == 3:
+        st["oz"] = f()
     return st, cs_prev.astype(np.int32)
 
 
-@pytest.mark.parametrize("nx,ny,n,inject", [(37, 23, 60000, True), (3, 8, 500, True),
-                                            (12, 9, 4000, False), (37, 23, 0, True),
-                                            (530, 300, 400000, True)])
-def test_sort_open_perm(H, nx, ny, n, inject):
+@pytest.mark.parametrize("nx,ny,nz,n,inject", [
+    (37, 23, 1, 60000, True), (3, 8, 1, 500, True), (12, 9, 1, 4000, False),
+    (37, 23, 1, 0, True), (530, 300, 1, 400000, True),
+    (14, 9, 7, 30000, True), (3, 5, 4, 800, True), (40, 30, 20, 300000, True)])
+def test_sort_open_perm(H, nx, ny, nz, n, inject):
     """The open gather-map sort against a stable argsort of the pushed and
     injected keys with the ghost-column ions left out: bit-exact map and
     cell_start, info = (0, live).  3 columns: both faces inject into the one
-    interior column; 530x300 takes the large-grid scan."""
-    announce("sort_open_perm", nx, ny, n, inject)
-    cfg = _cfg(nx, ny)
+    interior column; 530x300 takes the large-grid scan; nz > 1 is 3D (face
+    rows over j and k, moves along z too)."""
+    announce("sort_open_perm", nx, ny, nz, n, inject)
+    cfg = _cfg(nx, ny) if nz == 1 else _cfg3(nx, ny, nz)
     spec = _spec(ux=0.2, ppc=40)
-    cap = n + 4 * ny * spec["ppc"] + 64
+    cap = n + 4 * ny * nz * spec["ppc"] + 64
     ctx = H.Context(cfg, cap)
     st, cs_prev = _pushed_store(cfg, n, 17)
-    q = H.Particles.from_numpy(st, 2, cap)
+    q = H.Particles.from_numpy(st, cfg.ndim, cap)
     if inject:
         H.hvpic_open_inject(ctx.ctx, q, H.inflow_from(spec), 5, 3)
     total = q.n
@@ -257,20 +285,22 @@ def _spec(**kw):
     return s
 
 
-@pytest.mark.parametrize("nx,ny,n,spec,step", [
-    (37, 23, 20000, _spec(), 0),
-    (37, 23, 20000, _spec(ux=-0.8, faces=1), 17),
-    (10, 700, 3000, _spec(ppc=8, vth=1.0), 5),          # rows in more than one chunk
-    (5, 3, 0, _spec(ux=0.0, ppc=200, faces=2), 123456),
-    (8, 4, 100, _spec(ux=3.0, vth=0.1, ppc=50), 1),     # a cold fast beam: N > 1 per row
+@pytest.mark.parametrize("nx,ny,nz,n,spec,step", [
+    (37, 23, 1, 20000, _spec(), 0),
+    (37, 23, 1, 20000, _spec(ux=-0.8, faces=1), 17),
+    (10, 700, 1, 3000, _spec(ppc=8, vth=1.0), 5),          # rows in more than one chunk
+    (5, 3, 1, 0, _spec(ux=0.0, ppc=200, faces=2), 123456),
+    (8, 4, 1, 100, _spec(ux=3.0, vth=0.1, ppc=50), 1),     # a cold fast beam: N > 1 per row
+    (12, 9, 7, 20000, _spec(), 3),                         # 3D: rows over (j, k)
+    (6, 40, 30, 5000, _spec(ppc=8, ux=-0.3), 9),           # 3D, 1200 rows a face
 ])
-def test_absorb_and_inject(H, nx, ny, n, spec, step):
-    announce("absorb_inject", nx, ny, n, spec, step)
-    cfg = _cfg(nx, ny)
-    cap = n + 4 * ny * spec["ppc"] + 64
+def test_absorb_and_inject(H, nx, ny, nz, n, spec, step):
+    announce("absorb_inject", nx, ny, nz, n, spec, step)
+    cfg = _cfg(nx, ny) if nz == 1 else _cfg3(nx, ny, nz)
+    cap = n + 4 * ny * nz * spec["ppc"] + 64
     ctx = H.Context(cfg, cap)
     parts = _store(cfg, n, 11, ghost_frac=0.05)
-    p = H.Particles.from_numpy(parts, 2, cap)
+    p = H.Particles.from_numpy(parts, cfg.ndim, cap)
     seed = 0x9E3779B97F4A7C15 ^ step
     H.hvpic_open_particles(ctx.ctx, p, H.inflow_from(spec), seed, step)
     got = p.to_numpy()
@@ -286,12 +316,13 @@ def test_absorb_and_inject(H, nx, ny, n, spec, step):
         sl = slice(n, m)
         assert np.array_equal(got["cell"][sl], new["cell"][sl])
         assert np.array_equal(got["w"][sl].astype(np.float64), new["w"][sl])
-        for k in ("ox", "oy", "ux", "uy", "uz"):
+        offs = ("ox", "oy", "oz") if cfg.ndim == 3 else ("ox", "oy")
+        for k in offs + ("ux", "uy", "uz"):
             a = got[k][sl].astype(np.float64)
             b = new[k][sl]
             assert np.all(np.abs(a - b) <= 2e-7 * np.maximum(1.0, np.abs(b))), k
-        assert np.all(got["ox"][sl] >= -1) and np.all(got["ox"][sl] < 1)
-        assert np.all(got["oy"][sl] >= -1) and np.all(got["oy"][sl] < 1)
+        for k in offs:
+            assert np.all(got[k][sl] >= -1) and np.all(got[k][sl] < 1), k
 
 
 def test_inject_capacity_and_step_range(H):
@@ -309,18 +340,24 @@ def test_inject_capacity_and_step_range(H):
 
 
 @pytest.mark.parametrize("gather_map", [True, False])
-@pytest.mark.parametrize("case", ["open-flow-32x16-QS", "solar-wind-80x160-NGP", "far-mover"])
+@pytest.mark.parametrize("case", ["open-flow-32x16-QS", "solar-wind-80x160-NGP", "far-mover",
+                                  "3d-open-flow-16x10x8-QS", "3d-open-flow-12x8x6-NGP"])
 def test_open_step_matches_oracle(H, case, gather_map):
     """One step from a straddler-free start, in the gather-map form and the
     general (radix) form; the solar-wind box (1.28M ions, NGP) is large
     enough that its sort outlasts the host's enqueue; in far-mover one ion
     crosses 2.5 cells, which sends the gather-map form down the general
-    path for that step."""
+    path for that step; the 3d cases have ghost planes and face rows over
+    (j, k)."""
     announce("open_step", "one step", case, gather_map)
     from paper_2305_05600_amd.sim import OpenSim
 
     if case.startswith("solar-wind"):
         cfg, parts, B0, B1, spec = W.solar_wind_box(nx=80, ny=160)
+    elif case.startswith("3d-open-flow-16"):
+        cfg, parts, B0, B1, spec = W.open_flow(nx=16, ny=10, nz=8, ppc=16)
+    elif case.startswith("3d-open-flow-12"):
+        cfg, parts, B0, B1, spec = W.open_flow(nx=12, ny=8, nz=6, ppc=24, shape=W.SHAPE_NGP)
     else:
         cfg, parts, B0, B1, spec = W.open_flow(nx=32, ny=16, ppc=16)
     if case == "far-mover":
@@ -351,8 +388,7 @@ def test_open_step_matches_oracle(H, case, gather_map):
     # W_e of the extrapolated density over the interior: near n0 its terms
     # cancel (the uniform wind), so its error is bounded through n's
     n1 = 1.5 * ref.n_prev - 0.5 * O.open_fill(cfg, O.deposit(cfg, O.particles64(parts), 0.0)[0])
-    interior = np.ones((cfg.ny, cfg.nx), bool)
-    interior[:, [0, -1]] = False
+    interior = ~_ghost(cfg)
     check_field_diag(sim.field_diag.cpu().numpy(), ref.field_diag,
                      we_bound=electron_energy_bound(cfg, n1, mask=interior))
     check_push_diag(sim.push_diag.cpu().numpy(), ref.push_diag, cfg, ref.p)
@@ -361,14 +397,18 @@ def test_open_step_matches_oracle(H, case, gather_map):
 
 
 @pytest.mark.parametrize("gather_map", [True, False])
-def test_open_steps_history(H, gather_map):
+@pytest.mark.parametrize("nz", [1, 8], ids=["2d", "3d"])
+def test_open_steps_history(H, gather_map, nz):
     """Ten steps: the injected count of every step equals the oracle's (it
     does not depend on the ions), the absorbed totals agree up to ions whose
     FP32 and FP64 cells differ, and the energy history agrees to 1e-3."""
-    announce("open_step", "ten steps", gather_map)
+    announce("open_step", "ten steps", gather_map, nz)
     from paper_2305_05600_amd.sim import OpenSim
 
-    cfg, parts, B0, B1, spec = W.open_flow(nx=32, ny=16, ppc=16)
+    if nz == 1:
+        cfg, parts, B0, B1, spec = W.open_flow(nx=32, ny=16, ppc=16)
+    else:
+        cfg, parts, B0, B1, spec = W.open_flow(nx=16, ny=10, nz=nz, ppc=16)
     seed = 22
     ref = O.OpenOracleSim(cfg, parts, B0, B1, spec, seed)
     sim = OpenSim(cfg, parts, B0, B1, spec, seed, gather_map=gather_map)
@@ -388,13 +428,17 @@ def test_open_steps_history(H, gather_map):
     assert rel_l2(sim.B1.cpu().numpy(), ref.B1) < 1e-3
 
 
-def test_gather_map_form_equals_the_general_form(H):
+@pytest.mark.parametrize("nz", [1, 6], ids=["2d", "3d"])
+def test_gather_map_form_equals_the_general_form(H, nz):
     """The two sequences of the open step give bit-identical results (the
     same stable order, the same arithmetic) over 20 steps."""
-    announce("open_step", "gather map vs general")
+    announce("open_step", "gather map vs general", nz)
     from paper_2305_05600_amd.sim import OpenSim
 
-    cfg, parts, B0, B1, spec = W.open_flow(nx=48, ny=24, ppc=24)
+    if nz == 1:
+        cfg, parts, B0, B1, spec = W.open_flow(nx=48, ny=24, ppc=24)
+    else:
+        cfg, parts, B0, B1, spec = W.open_flow(nx=20, ny=12, nz=nz, ppc=16)
     a = OpenSim(cfg, parts, B0, B1, spec, 31, gather_map=True)
     b = OpenSim(cfg, parts, B0, B1, spec, 31, gather_map=False)
     for s in range(20):
