@@ -111,6 +111,8 @@ Layout workspace_layout(const hvpic_params* p) {
   L.mom_acc = off;   off += align256(sizeof(double) * 4 * nc);
   L.open_rows = off;
   off += align256(p->open_x ? sizeof(int32_t) * 3 * 2 * (size_t)p->ny * (size_t)p->nz : 0);
+  L.chunk_order = off;
+  off += align256(p->ndim == 3 ? sizeof(int32_t) * (size_t)(ceil_div(cap, kChunk3) + 1) : 0);
   L.total = off;
   return L;
 }
@@ -161,6 +163,7 @@ int hvpic_init(const hvpic_params* params, void* hip_stream, void* workspace, hv
   c->fscratch = (float*)(c->ws + L.fscratch);
   c->mom_acc = (double*)(c->ws + L.mom_acc);
   c->open_rows = params->open_x ? (int32_t*)(c->ws + L.open_rows) : nullptr;
+  c->chunk_order = params->ndim == 3 ? (int32_t*)(c->ws + L.chunk_order) : nullptr;
   hipLaunchKernelGGL(k_init_ws, dim3(256), dim3(256), 0, c->stream, c->status, c->mom_acc,
                      4ll * c->ncell, c->sort_cnt,
                      (int64_t)c->ncell * (params->ndim == 2 ? 9 : 27));

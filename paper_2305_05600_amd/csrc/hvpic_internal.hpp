@@ -183,8 +183,10 @@ struct hvpic_ctx {
   const int32_t* cnt_cs;
   int64_t cnt_n;
   // open boundaries: per face row the injected count, its offset within
-  // the injected block and the first slot in the sorted order [3][2][ny]
+  // the injected block and the first slot in the sorted order [3][2][ny nz]
   int32_t* open_rows;
+  // 3D: the order in which the push takes its chunks [chunks + 1], or null
+  int32_t* chunk_order;
   // the last injection: the store it appended to, its size before, count
   const int32_t* inj_cell;
   int64_t inj_n0, inj_k;
@@ -308,7 +310,7 @@ int launch_init_workspace(hvpic_ctx* c);
 // Workspace layout (bytes from the start; each region 256-byte aligned).
 struct Layout {
   size_t status, push_part, field_part, sort_cnt, sort_blk, rkey0, rkey1, rval0, rval1, rhist,
-      fscratch, mom_acc, open_rows, total;
+      fscratch, mom_acc, open_rows, chunk_order, total;
 };
 Layout workspace_layout(const hvpic_params* p);
 
@@ -318,6 +320,7 @@ constexpr int kRadixItems = 8;  // keys per thread per radix tile
 constexpr int kRadixTile = kBlock * kRadixItems;
 constexpr int kScanTile = 2048;  // elements per block of the prefix scans
 constexpr int kNbTileSmall = 512;  // cells per block of the neighbour sort's scans (small grids)
+constexpr int kChunk3 = 1024;      // ions per block of the 3D push
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 

@@ -48,6 +48,7 @@ struct Chunk {
   static constexpr int N = kBlock * PPT;
   static constexpr int WMAX = NDIM == 2 ? 64 : 24;
 };
+static_assert(Chunk<3>::N == kChunk3, "workspace sizing of the 3D chunk order");
 
 struct Geo {
   int nx, ny, nz, ncell, nxny;
@@ -86,6 +87,7 @@ struct PushArgs {
   const float *iox, *ioy, *ioz, *iux, *iuy, *iuz, *iw;
   float* wo;
   bool off32;               // every source byte offset fits 32 bits (n < 2^30)
+  const int32_t* order;     // position -> chunk (a permutation of the chunks), or null
 };
 
 struct DepArgs {
@@ -700,20 +702,21 @@ __device__ __forceinline__ void home_flush(Home<NDIM, SHAPE>& H, const WinLds& w
   home_clear(H);
 }
 
-// Clears columns [0, W) of every band of the deposit window (column 0 = cell
-// c0 - 2) and fills the wrap bits of their cells.
+// Clears the deposit window (every slot of every band, so that the loops
+// divide by the compile-time band width only) and fills the wrap bits of the
+// cells of columns [0, W) (column 0 = cell c0 - 2).
 template <int NDIM>
 __device__ void dwin_init(double* win, uint8_t* wrap, int W, int c0, const Geo& g) {
-  constexpr int SW = DWin<NDIM>::SW;
-  for (int s = threadIdx.x; s < DWin<NDIM>::NB * W * 4; s += kBlock) {
-    const int band = s / (W * 4), rest = s - band * W * 4;
-    win[band * SW * 4 + rest] = 0.0;
-  }
-  for (int s = threadIdx.x; s < DWin<NDIM>::NB * W; s += kBlock) {
-    const int band = s / W, col = s - band * W;
+  constexpr int SW = DWin<NDIM>::SW, NB = DWin<NDIM>::NB;
+  double2* w2 = reinterpret_cast<double2*>(win);
+  for (int s = threadIdx.x; s < NB * SW * 2; s += kBlock) w2[s] = make_double2(0.0, 0.0);
+  for (int s = threadIdx.x; s < NB * SW; s += kBlock) {
+    const int band = s / SW, col = s - band * SW;
+    if (col >= W) continue;
     const int c = (int)window_cell(c0, col, band % 5 - 2, NDIM == 3 ? band / 5 - 2 : 0, g);
-    const int i = c % g.nx, j = (c / g.nx) % g.ny;
-    wrap[band * SW + col] = (uint8_t)wrap_bits<NDIM>(i, j, g);
+    int i, j, k;
+    decompose(c, g, i, j, k);
+    wrap[s] = (uint8_t)wrap_bits<NDIM>(i, j, g);
   }
 }
 
@@ -722,12 +725,14 @@ __device__ void dwin_init(double* win, uint8_t* wrap, int W, int c0, const Geo& 
 template <int NDIM>
 __device__ void dwin_flush(const double* win, int W, int c0, const Geo& g,
                            double* __restrict__ acc) {
-  constexpr int SW = DWin<NDIM>::SW;
-  for (int s = threadIdx.x; s < DWin<NDIM>::NB * W * 4; s += kBlock) {
-    const int band = s / (W * 4), rest = s - band * W * 4;
-    const double v = win[band * SW * 4 + rest];
+  constexpr int SW = DWin<NDIM>::SW, NB = DWin<NDIM>::NB;
+  for (int s = threadIdx.x; s < NB * SW * 4; s += kBlock) {
+    const int band = s / (SW * 4), rest = s - band * (SW * 4);
+    const int off = rest >> 2;
+    if (off >= W) continue;
+    const double v = win[s];
     if (v == 0.0) continue;
-    const int ch = rest & 3, off = rest >> 2;
+    const int ch = rest & 3;
     const int64_t c = window_cell(c0, off, band % 5 - 2, NDIM == 3 ? band / 5 - 2 : 0, g);
     unsafeAtomicAdd(acc + (int64_t)ch * g.ncell + c, v);
   }
@@ -945,11 +950,14 @@ __device__ __forceinline__ void moves_window_init(const int32_t* __restrict__ cs
 }
 
 // Each block checks its share of cell_start (a monotone partition of [0, n]);
-// the scatter relies on it.
+// the scatter relies on it.  The shares are [f(bid), f(bid+1)) with
+// f(b) = floor(b ncell / nb) in FP64 (monotone in b, f(0) = 0, f(nb) = ncell:
+// a partition of the cells, without a 64-bit integer division).
 __device__ __forceinline__ void check_cell_start(const int32_t* __restrict__ cs, int ncell,
                                                  int64_t n, Status* st, int bid, int nb) {
-  const int64_t cb = (int64_t)bid * ncell / nb;
-  const int64_t ce = (int64_t)(bid + 1) * ncell / nb;
+  const int64_t cb = (int64_t)((double)bid * (double)ncell / (double)nb);
+  const int64_t ce = bid + 1 >= nb ? (int64_t)ncell
+                                   : (int64_t)((double)(bid + 1) * (double)ncell / (double)nb);
   bool bad = false;
   for (int64_t c = cb + threadIdx.x; c < ce; c += kBlock) {
     const int32_t v0 = cs[c], v1 = cs[c + 1];
@@ -1124,7 +1132,7 @@ __device__ __forceinline__ void push_chunk(const PushArgs& A, int chunk, int nb)
   constexpr int NF4 = Rec<NDIM, SHAPE>::NF4;
   constexpr int CN = kBlock * PPT;  // particles per chunk
   __shared__ float4 gw[Chunk<NDIM>::WMAX * NF4];
-  __shared__ double win[DEP ? DWin<NDIM>::LEN : 1];
+  __shared__ __attribute__((aligned(16))) double win[DEP ? DWin<NDIM>::LEN : 2];
   __shared__ uint8_t s_wrap[DEP ? DWin<NDIM>::NB * DWin<NDIM>::SW : 1];
   __shared__ float s_q[DEP ? kBlock / 64 * Queue<NDIM>::QCAP * Queue<NDIM>::QW : 1];
   __shared__ uint32_t s_cnt[Chunk<NDIM>::WMAX * Moves<NDIM>::ND];
@@ -1330,15 +1338,92 @@ __device__ __forceinline__ void push_chunk(const PushArgs& A, int chunk, int nb)
 template <int NDIM, int SHAPE, bool DEP, int PM>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NDIM == 2 ? 4 : 3)))
 void k_gather_push(PushArgs A) {
-  push_chunk<NDIM, SHAPE, DEP, PM, Chunk<NDIM>::PPT>(A, xcd_chunk(blockIdx.x, gridDim.x),
-                                                     gridDim.x);
+  int chunk = xcd_chunk(blockIdx.x, gridDim.x);
+  if (A.order) {
+    const int o = A.order[chunk];
+    if ((unsigned)o < gridDim.x) chunk = o;
+  }
+  push_chunk<NDIM, SHAPE, DEP, PM, Chunk<NDIM>::PPT>(A, chunk, gridDim.x);
+}
+
+// The order in which the 3D push takes its chunks.  The store is sorted by
+// cell with x fastest, so a chunk lies in one grid row (j, k) of cells or
+// straddles two.  In store order, an ion that moved in z in the last step
+// is read from a plane (nx ny cells) away, long after its cache lines left
+// the L2, while a y-neighbour row is only nx cells away.  Here the rows are
+// visited in tiles of kOrderTj rows along y, plane after plane within a
+// tile, so that both neighbours of a row are visited within kOrderTj rows
+// of it (all but the rows at a tile's edge in y).  A chunk goes with the
+// row of its first ion; the chunks of a row keep their order.  With the
+// counts K(r) of the chunks that start in row r, position p of the order
+// holds the chunk F(r) + p - P(t) for the row r at rank t, P the exclusive
+// prefix sum of K over the ranks.  One block; rows <= 65536.  For a valid
+// cell_start (monotone, cs[0] = 0, cs[ncell] = n) this is a permutation of
+// the nchunks chunks; otherwise the push flags the input, and every index
+// written here stays within [0, nchunks).
+constexpr int kOrderTj = 16;
+constexpr int kOrderPer = 16;  // ranks per thread per pass
+
+__global__ __launch_bounds__(1024) void k_chunk_order(const int32_t* __restrict__ cs, int nx,
+                                                      int ny, int nz, int nchunks,
+                                                      int32_t* __restrict__ order) {
+  __shared__ int s_w[16];
+  __shared__ int s_carry;
+  const int R = ny * nz;
+  const int tile = kOrderTj * nz;  // ranks per full tile
+  if (threadIdx.x == 0) s_carry = 0;
+  __syncthreads();
+  for (int t0 = 0; t0 < R; t0 += 1024 * kOrderPer) {
+    int F[kOrderPer], K[kOrderPer];
+    int sum = 0;
+#pragma unroll
+    for (int q = 0; q < kOrderPer; ++q) {
+      const int t = t0 + (int)threadIdx.x * kOrderPer + q;
+      F[q] = 0;
+      K[q] = 0;
+      if (t < R) {
+        const int jt = t / tile, local = t - jt * tile;
+        const int T = min(kOrderTj, ny - jt * kOrderTj);  // rows of this tile
+        const int k = local / T, j = jt * kOrderTj + (local - (local / T) * T);
+        const int64_t r = (int64_t)j + (int64_t)ny * k;
+        const int64_t a = cs[r * nx], b = cs[(r + 1) * nx];
+        const int64_t fa = min<int64_t>(max<int64_t>((a + kChunk3 - 1) / kChunk3, 0), nchunks);
+        const int64_t fb = min<int64_t>(max<int64_t>((b + kChunk3 - 1) / kChunk3, 0), nchunks);
+        F[q] = (int)fa;
+        K[q] = (int)max<int64_t>(fb - fa, 0);
+      }
+      sum += K[q];
+    }
+    // exclusive scan of the per-thread sums over the block
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int x = sum;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(x, o);
+      if (lane >= o) x += y;
+    }
+    if (lane == 63) s_w[wid] = x;
+    __syncthreads();
+    int before = s_carry, total = 0;
+    for (int w = 0; w < 16; ++w) {
+      if (w < wid) before += s_w[w];
+      total += s_w[w];
+    }
+    int p = before + x - sum;
+#pragma unroll
+    for (int q = 0; q < kOrderPer; ++q)
+      for (int m = 0; m < K[q]; ++m, ++p)
+        if (p < nchunks) order[p] = F[q] + m;
+    __syncthreads();
+    if (threadIdx.x == 0) s_carry += total;
+    __syncthreads();
+  }
 }
 
 // Stand-alone deposit at x - half_dt_back v (no push); same lane runs.
 template <int NDIM, int SHAPE>
 __global__ __launch_bounds__(kBlock) void k_deposit(DepArgs A) {
   constexpr int PPT = Chunk<NDIM>::PPT;
-  __shared__ double win[DWin<NDIM>::LEN];
+  __shared__ __attribute__((aligned(16))) double win[DWin<NDIM>::LEN];
   __shared__ uint8_t s_wrap[DWin<NDIM>::NB * DWin<NDIM>::SW];
   __shared__ float s_q[kBlock / 64 * Queue<NDIM>::QCAP * Queue<NDIM>::QW];
   __shared__ int s_c[2];
@@ -1586,6 +1671,7 @@ PushArgs push_args(hvpic_ctx* c, const hvpic_particles* in, const int32_t* perm,
   A.iuz = in->uz;
   A.iw = in->w;
   A.wo = p->w;
+  A.order = nullptr;
   return A;
 }
 
@@ -1605,6 +1691,13 @@ int launch_push(hvpic_ctx* c, const hvpic_particles* in, const int32_t* perm,
   if (cell_start != nullptr && !c->cnt_clean) zero_counts(c);
   const bool qs = c->p.shape == HVPIC_SHAPE_QS;
   int nblocks = 0;
+  if (c->p.ndim == 3 && cell_start != nullptr && c->chunk_order &&
+      (int64_t)c->p.ny * c->p.nz <= 65536) {
+    // the chunk order (a kernel of its own, outside the push's timing)
+    hipLaunchKernelGGL(k_chunk_order, dim3(1), dim3(1024), 0, c->stream, cell_start, c->p.nx,
+                       c->p.ny, c->p.nz, (int)ceil_div(p->n, Chunk<3>::N), c->chunk_order);
+    A.order = c->chunk_order;
+  }
   timing_begin(c, HVPIC_KERNEL_GATHER_PUSH);
   if (c->p.ndim == 2) {
     nblocks = (int)ceil_div(p->n, Chunk<2>::N);
