@@ -212,13 +212,15 @@ def _pushed_store(cfg, n, seed, far=False):
 @pytest.mark.parametrize("nx,ny,nz,n,inject", [
     (37, 23, 1, 60000, True), (3, 8, 1, 500, True), (12, 9, 1, 4000, False),
     (37, 23, 1, 0, True), (530, 300, 1, 400000, True),
-    (14, 9, 7, 30000, True), (3, 5, 4, 800, True), (40, 30, 20, 300000, True)])
+    (14, 9, 7, 30000, True), (3, 5, 4, 800, True), (40, 30, 20, 300000, True),
+    (2100, 2000, 1, 200000, True)])
 def test_sort_open_perm(H, nx, ny, nz, n, inject):
     """The open gather-map sort against a stable argsort of the pushed and
     injected keys with the ghost-column ions left out: bit-exact map and
     cell_start, info = (0, live).  3 columns: both faces inject into the one
-    interior column; 530x300 takes the large-grid scan; nz > 1 is 3D (face
-    rows over j and k, moves along z too)."""
+    interior column; 530x300 spans 311 scan tiles of 512 cells, and
+    2100x2000 takes the large-tile scan; nz > 1 is 3D (face rows over j and
+    k, moves along z too)."""
     announce("sort_open_perm", nx, ny, nz, n, inject)
     cfg = _cfg(nx, ny) if nz == 1 else _cfg3(nx, ny, nz)
     spec = _spec(ux=0.2, ppc=40)

@@ -500,9 +500,11 @@ def test_push_inconsistent_cell_start(H, name, cfg):
     _check_sorted(cfg, pushed, q.to_numpy(), cs.cpu().numpy())
 
 
-def test_neighbour_sort_large_grid(H):
-    """A grid above 512*512 cells takes the sort's large-tile scan path."""
-    cfg = cfg2(nx=1031, ny=517)
+@pytest.mark.parametrize("nx,ny", [(1031, 517), (2053, 2049)])
+def test_neighbour_sort_large_grid(H, nx, ny):
+    """Grids above 512*512 cells take the sort's large-tile scan path
+    (261 and 2054 tiles of 2048 cells)."""
+    cfg = cfg2(nx=nx, ny=ny)
     announce("nb_sort_large", cfg.ncell)
     _, parts, B = W.random_box(97, cfg, 0.7, vmax_cells=0.9)
     parts, cs0 = _sorted(cfg, parts)
