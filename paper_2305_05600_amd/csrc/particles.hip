@@ -1125,10 +1125,13 @@ __device__ void move_general(const PushArgs& A, float x, float y, float z, float
 // PM: 0 reads and writes the store in place; 1 and 2 read it through the
 // gather map A.perm (1: all byte offsets of the source arrays fit 32 bits).
 // The push of one chunk of PPT*kBlock consecutive particles of the store
-// (chunk `chunk` of the nb chunks of that store; bid = chunk as well: it
-// picks the block's share of the cell_start check and its diagnostic slot).
+// (chunk `chunk` of the nb chunks of that store).  slot, a bijection of the
+// launch's blocks onto [0, nb) that does not depend on the data, picks the
+// block's share of the cell_start check and its diagnostic slot, so that
+// the check covers every entry even where a chunk order built from a bad
+// cell_start repeats a chunk.
 template <int NDIM, int SHAPE, bool DEP, int PM, int PPT>
-__device__ __forceinline__ void push_chunk(const PushArgs& A, int chunk, int nb) {
+__device__ __forceinline__ void push_chunk(const PushArgs& A, int chunk, int slot, int nb) {
   constexpr int NF4 = Rec<NDIM, SHAPE>::NF4;
   constexpr int CN = kBlock * PPT;  // particles per chunk
   __shared__ float4 gw[Chunk<NDIM>::WMAX * NF4];
@@ -1178,7 +1181,7 @@ __device__ __forceinline__ void push_chunk(const PushArgs& A, int chunk, int nb)
     if (DEP) dwin_init<NDIM>(win, s_wrap, W, c0, g);
     if (cnt_on) moves_window_init<NDIM>(A.cs, c0, span, s_cs, s_cnt);
   }
-  if (cnt_on) check_cell_start(A.cs, g.ncell, A.n, A.st, chunk, nb);
+  if (cnt_on) check_cell_start(A.cs, g.ncell, A.n, A.st, slot, nb);
   __syncthreads();
 
   float dK = 0.f, dP0 = 0.f, dP1 = 0.f, dP2 = 0.f;
@@ -1326,7 +1329,7 @@ __device__ __forceinline__ void push_chunk(const PushArgs& A, int chunk, int nb)
   if (want_diag) {
     const double hm = 0.5 * A.ms;
     double v[4] = {hm * dK, hm * dP0, hm * dP1, hm * dP2};
-    block_partial<4>(v, A.diag_part, chunk);
+    block_partial<4>(v, A.diag_part, slot);
   }
   if (wok && (DEP || cnt_on)) {
     __syncthreads();
@@ -1338,12 +1341,13 @@ __device__ __forceinline__ void push_chunk(const PushArgs& A, int chunk, int nb)
 template <int NDIM, int SHAPE, bool DEP, int PM>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NDIM == 2 ? 4 : 3)))
 void k_gather_push(PushArgs A) {
-  int chunk = xcd_chunk(blockIdx.x, gridDim.x);
+  const int slot = xcd_chunk(blockIdx.x, gridDim.x);
+  int chunk = slot;
   if (A.order) {
-    const int o = A.order[chunk];
+    const int o = A.order[slot];
     if ((unsigned)o < gridDim.x) chunk = o;
   }
-  push_chunk<NDIM, SHAPE, DEP, PM, Chunk<NDIM>::PPT>(A, chunk, gridDim.x);
+  push_chunk<NDIM, SHAPE, DEP, PM, Chunk<NDIM>::PPT>(A, chunk, slot, gridDim.x);
 }
 
 // The order in which the 3D push takes its chunks.  The store is sorted by
@@ -1357,20 +1361,28 @@ void k_gather_push(PushArgs A) {
 // row of its first ion; the chunks of a row keep their order.  With the
 // counts K(r) of the chunks that start in row r, position p of the order
 // holds the chunk F(r) + p - P(t) for the row r at rank t, P the exclusive
-// prefix sum of K over the ranks.  One block; rows <= 65536.  For a valid
-// cell_start (monotone, cs[0] = 0, cs[ncell] = n) this is a permutation of
-// the nchunks chunks; otherwise the push flags the input, and every index
-// written here stays within [0, nchunks).
+// prefix sum of K over the ranks.  One block; rows <= 65536.  This is a
+// permutation of the nchunks chunks when cell_start does not decrease from
+// row start to row start, starts at 0 and ends at n; otherwise (the push
+// flags such a cell_start) the order is the store order, so that every chunk
+// is still pushed once.
 constexpr int kOrderTj = 16;
 constexpr int kOrderPer = 16;  // ranks per thread per pass
 
 __global__ __launch_bounds__(1024) void k_chunk_order(const int32_t* __restrict__ cs, int nx,
-                                                      int ny, int nz, int nchunks,
+                                                      int ny, int nz, int64_t n, int nchunks,
                                                       int32_t* __restrict__ order) {
   __shared__ int s_w[16];
   __shared__ int s_carry;
   const int R = ny * nz;
   const int tile = kOrderTj * nz;  // ranks per full tile
+  bool bad = threadIdx.x == 0 && (cs[0] != 0 || (int64_t)cs[(int64_t)R * nx] != n);
+  for (int r = threadIdx.x; r < R; r += 1024)
+    bad |= cs[(int64_t)(r + 1) * nx] < cs[(int64_t)r * nx];
+  if (__syncthreads_or(bad)) {
+    for (int p = threadIdx.x; p < nchunks; p += 1024) order[p] = p;
+    return;
+  }
   if (threadIdx.x == 0) s_carry = 0;
   __syncthreads();
   for (int t0 = 0; t0 < R; t0 += 1024 * kOrderPer) {
@@ -1695,7 +1707,8 @@ int launch_push(hvpic_ctx* c, const hvpic_particles* in, const int32_t* perm,
       (int64_t)c->p.ny * c->p.nz <= 65536) {
     // the chunk order (a kernel of its own, outside the push's timing)
     hipLaunchKernelGGL(k_chunk_order, dim3(1), dim3(1024), 0, c->stream, cell_start, c->p.nx,
-                       c->p.ny, c->p.nz, (int)ceil_div(p->n, Chunk<3>::N), c->chunk_order);
+                       c->p.ny, c->p.nz, p->n, (int)ceil_div(p->n, Chunk<3>::N),
+                       c->chunk_order);
     A.order = c->chunk_order;
   }
   timing_begin(c, HVPIC_KERNEL_GATHER_PUSH);
@@ -1805,7 +1818,7 @@ void k_gather_push_batch(const PushArgs* __restrict__ tab, const Item* __restric
   for_items(nitems, [&](int it) {
     const Item item = items[it];
     const PushArgs A = tab[item.run];
-    push_chunk<2, SHAPE, true, 1, PPT>(A, item.idx, item.nb);
+    push_chunk<2, SHAPE, true, 1, PPT>(A, item.idx, item.idx, item.nb);
     __syncthreads();  // the next item reuses the LDS
   });
 }

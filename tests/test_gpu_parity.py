@@ -460,12 +460,16 @@ def test_dense_single_cell(H, counted):
     assert rel_l2(nd.cpu().numpy(), rn) < 1e-5 and rel_l2(Jd.cpu().numpy(), rJ) < 1e-5
 
 
+@pytest.mark.parametrize("kind", ["claim", "decreasing"])
 @pytest.mark.parametrize("name,cfg", [CASES[0], CASES[2]])
-def test_push_inconsistent_cell_start(H, name, cfg):
+def test_push_inconsistent_cell_start(H, name, cfg, kind):
     """A cell_start that disagrees with the store: the push flags bad input,
     still pushes every particle from its own cell and deposits it, and the
-    next neighbour sort completes with the general sort."""
-    announce("push_bad_cs", name)
+    next neighbour sort completes with the general sort.  claim: a cell
+    claims its neighbour's particles (still monotone); decreasing: a row's
+    start exceeds the next row's (in 3D the push's chunk order then falls
+    back to the store order, so that no chunk is pushed twice or skipped)."""
+    announce("push_bad_cs", name, kind)
     _, parts, B = W.random_box(95, cfg, 6.0, vmax_cells=0.9)
     parts, cs0 = _sorted(cfg, parts)
     E = W.random_field(96, cfg, 0.1)
@@ -477,8 +481,12 @@ def test_push_inconsistent_cell_start(H, name, cfg):
     parts = {k: v[~near] for k, v in parts.items()}
     parts, cs0 = _sorted(cfg, parts)
     bad = cs0.copy()
-    mid = cfg.ncell // 2
-    bad[mid] = bad[mid + 1]  # cell mid-1 claims cell mid's particles
+    if kind == "claim":
+        mid = cfg.ncell // 2
+        bad[mid] = bad[mid + 1]  # cell mid-1 claims cell mid's particles
+    else:
+        mid = cfg.nx * (cfg.ncell // cfg.nx // 2)  # a row start
+        bad[mid] = bad[-1]
     n = parts["cell"].size
     ctx = H.Context(cfg, n)
     p = H.Particles.from_numpy(parts, cfg.ndim)
