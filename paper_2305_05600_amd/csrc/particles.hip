@@ -313,6 +313,47 @@ __device__ __forceinline__ void gather_rec(const float4* gw, int rel, float x, f
                                            float Ep[3], float Bp[3], int& i, int& j, int& k) {
   constexpr int NF4 = Rec<NDIM, SHAPE>::NF4;
   constexpr int NC = Rec<NDIM, SHAPE>::NC;
+  if (SHAPE == HVPIC_SHAPE_QS) {
+    // the record's monomials, then coefficient by coefficient (8-byte reads
+    // of its six components), so that few of the record's 30 (2D) or 42 (3D)
+    // values are live at once: the 3D push then fits four wavefronts per
+    // SIMD without spills
+    const float* q = reinterpret_cast<const float*>(gw + rel * NF4);
+    float m[NC];
+    m[0] = 1.0f;
+    m[1] = x;
+    m[2] = y;
+    if constexpr (NDIM == 2) {
+      m[3] = x * x;
+      m[4] = y * y;
+    } else {
+      m[3] = z;
+      m[4] = x * x;
+      m[5] = y * y;
+      m[6] = z * z;
+    }
+    float acc[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+#pragma unroll
+      for (int h = 0; h < 3; ++h) {
+        const float2 v = *reinterpret_cast<const float2*>(q + c * 6 + 2 * h);
+        acc[2 * h] = fmaf(m[c], v.x, acc[2 * h]);
+        acc[2 * h + 1] = fmaf(m[c], v.y, acc[2 * h + 1]);
+      }
+    }
+    Ep[0] = acc[0];
+    Ep[1] = acc[1];
+    Ep[2] = acc[2];
+    Bp[0] = acc[3];
+    Bp[1] = acc[4];
+    Bp[2] = acc[5];
+    const int* ri = reinterpret_cast<const int*>(q + NC * 6);
+    i = ri[0];
+    j = ri[1];
+    k = NDIM == 3 ? ri[2] : 0;
+    return;
+  }
   float r[NF4 * 4];
   const float4* p = gw + rel * NF4;
 #pragma unroll
@@ -1120,8 +1161,8 @@ __device__ void move_general(const PushArgs& A, float x, float y, float z, float
 // ---------------------------------------------------------------- kernels --
 
 // Fused gather + Boris push + move (+ mid-point deposit when DEP).
-// 2D: at most 128 VGPRs, so that four wavefronts per SIMD keep enough loads
-// in flight (the 3D windows already limit a CU to three blocks).
+// At most 128 VGPRs, so that four wavefronts per SIMD keep enough loads in
+// flight (a 3D block's 35.8 KB of LDS allows four blocks per CU as well).
 // PM: 0 reads and writes the store in place; 1 and 2 read it through the
 // gather map A.perm (1: all byte offsets of the source arrays fit 32 bits).
 // The push of one chunk of PPT*kBlock consecutive particles of the store
@@ -1339,7 +1380,7 @@ __device__ __forceinline__ void push_chunk(const PushArgs& A, int chunk, int slo
 }
 
 template <int NDIM, int SHAPE, bool DEP, int PM>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NDIM == 2 ? 4 : 3)))
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4)))
 void k_gather_push(PushArgs A) {
   const int slot = xcd_chunk(blockIdx.x, gridDim.x);
   int chunk = slot;
