@@ -262,3 +262,56 @@ def test_field_advance_no_branches(mods, tol):
         rE = O.ohm(cfg, rB, n1, J1)
     assert rel_l2(Bd.cpu().numpy(), rB) < 1e-5
     assert rel_l2(Ed.cpu().numpy(), rE) < 1e-5
+
+
+@pytest.mark.parametrize("tol", [0.0, 1e30])
+def test_field_advance_no_full_size(mods, tol):
+    """The benchmarked grid (the double Harris sheet, 512x256 cells, 10
+    subcycles, its B): the operator's forward there against the oracle's
+    network on the same BF16-rounded values, and both branches of the
+    surrogate's field advance against the oracle (tol = 0: the plain
+    subcycle; tol = huge: the proposal and Ohm's law of it)."""
+    H, S = mods
+    announce("no_field_full", tol)
+    cfg, _, B = W.harris_double(ppc=0.01)  # the grid and the field
+    B = np.asarray(B, np.float32)
+    nh = W.random_density(82, cfg, 0.5, 1.5)
+    npv = W.random_density(83, cfg, 0.5, 1.5)
+    Jh = W.random_field(84, cfg, 0.2)
+    Jp = W.random_field(85, cfg, 0.2)
+    rng = np.random.default_rng(21)
+    surr = S.Surrogate(cfg.nx, cfg.ny, batch=1)
+    params = [(w, rng.normal(scale=0.05, size=b.shape)) for w, b in NO.init_params(4)]
+    norm = _norm(rng)
+    surr.load(params, norm)
+    ctx = H.Context(cfg, 1)
+    Bd = _dev(B, np.float32)
+    Ed = torch.zeros((3, cfg.ncell), device="cuda")
+    diag = torch.zeros(3, dtype=torch.float64, device="cuda")
+    stats = torch.zeros(2, dtype=torch.float64, device="cuda")
+    prop = surr.predict(Bd.clone(), _dev(nh, np.float32), _dev(Jh, np.float32))
+    torch.cuda.synchronize()
+    ref = NO.predict(params, norm, B, nh, Jh, (cfg.ny, cfg.nx), round_bf16=True).reshape(3, -1)
+    inc_g = (prop.cpu().numpy() - B) / norm[2][:, None]
+    inc_r = (ref - B) / norm[2][:, None]
+    err = rel_l2(inc_g, inc_r)
+    print(f"network forward at {cfg.nx}x{cfg.ny}: increment rel L2 {err:.2e}", flush=True)
+    assert err < 1e-3
+    H.hvpic_field_advance_no(ctx.ctx, surr.params, surr.ws_one, Bd, _dev(nh, np.float32),
+                             _dev(Jh, np.float32), _dev(npv, np.float32), _dev(Jp, np.float32),
+                             Ed, tol, diag_out=diag, stats=stats)
+    torch.cuda.synchronize()
+    st = stats.cpu().numpy()
+    assert st[0] == pytest.approx(NO.residual(cfg, B, prop.cpu().numpy(), nh, Jh), rel=1e-3)
+    if tol == 0.0:
+        assert st[1] == 0.0
+        rB, rE, rd, _ = O.field_advance(cfg, B, nh, Jh, npv, Jp, mode=0)
+    else:
+        assert st[1] == 1.0
+        assert torch.equal(Bd, prop)
+        rB = prop.cpu().numpy().astype(np.float64)
+        rE = O.ohm(cfg, rB, 1.5 * nh.astype(np.float64) - 0.5 * npv,
+                   1.5 * Jh.astype(np.float64) - 0.5 * Jp)
+    eB, eE = rel_l2(Bd.cpu().numpy(), rB), rel_l2(Ed.cpu().numpy(), rE)
+    print(f"field advance (tol {tol:g}): rel L2 B {eB:.2e}, E {eE:.2e}", flush=True)
+    assert eB < 1e-5 and eE < 1e-5
