@@ -226,3 +226,41 @@ def test_ensemble_rejects_what_it_does_not_batch(mods):
         ens.set_tuning({"push_chunk": [3, 0, 0]})
     with pytest.raises(H.HvpicError):
         ens.set_tuning({"blocks_per_cu": [0, 1, 1, 1]})
+
+
+def test_ensemble_full_size(mods):
+    """The benchmarked ensemble at full size (64 runs, sides 64-256, 32-200
+    ions per cell: about 247M ions and 2.1M cells), with the default choices
+    (the plain path's chunk and tile) and the step replayed from its
+    hipGraph as the benchmark runs it: after three steps every run's
+    cell_start, E, B and moments equal those of the same run stepped on its
+    own, bit for bit, and so do the stores of the smallest and largest runs."""
+    H, S = mods
+    announce("ensemble_full_size")
+    specs = W.ensemble_specs()
+    runs = [W.ensemble_run(s) for s in specs]
+    n_total = sum(int(p["cell"].size) for _, p, _ in runs)
+    ens = S.Ensemble(_sims(S, runs))
+    plain = _sims(S, runs)
+    del runs
+    assert ens.tuning == H.hvpic_tuning_default().as_dict()
+    ens.capture(True)
+    for _ in range(3):
+        ens.step()
+        for g in plain:
+            g.step()
+    sizes = [s["side"] ** 2 * s["ppc"] for s in specs]
+    check = {int(np.argmin(sizes)), int(np.argmax(sizes))}
+    for r, g in enumerate(plain):
+        s = ens.state(r)
+        g.synchronize()
+        assert torch.equal(s["cs"], g.cs), r
+        for name, a, b in (("E", s["E"], g.E), ("B", s["B"], g.B), ("n", s["n_prev"], g.n_prev),
+                           ("J", s["J_prev"], g.J_prev)):
+            assert torch.equal(a, b), (r, name)
+        if r in check:
+            _same_state(ens, r, g, exact=True)
+        flags, _ = ens.status(r)
+        assert flags & (H.FLAG_BAD_INPUT | H.FLAG_NONFINITE) == 0, (r, flags)
+    print(f"ensemble: {len(specs)} runs, {n_total} ions, equal to the plain runs after "
+          f"3 graph-replayed steps", flush=True)
