@@ -1399,10 +1399,11 @@ void k_gather_push(PushArgs A) {
 // visited in tiles of kOrderTj rows along y, plane after plane within a
 // tile, so that both neighbours of a row are visited within kOrderTj rows
 // of it (all but the rows at a tile's edge in y).  A chunk goes with the
-// row of its first ion; the chunks of a row keep their order.  With the
-// counts K(r) of the chunks that start in row r, position p of the order
-// holds the chunk F(r) + p - P(t) for the row r at rank t, P the exclusive
-// prefix sum of K over the ranks.  One block; rows <= 65536.  This is a
+// row of its first ion; the chunks of a row keep their order.  With
+// F(r) = ceil(cs[r nx] / 1024), the first chunk that starts in row r, and
+// K(r) = F(r+1) - F(r) the chunks that start there, position p of the
+// order holds the chunk F(r) + p - P(t) for the row r at rank t, P the
+// exclusive prefix sum of K over the ranks.  One block; rows <= 65536.  This is a
 // permutation of the nchunks chunks when cell_start does not decrease from
 // row start to row start, starts at 0 and ends at n; otherwise (the push
 // flags such a cell_start) the order is the store order, so that every chunk
