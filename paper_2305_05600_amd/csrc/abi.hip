@@ -112,7 +112,10 @@ Layout workspace_layout(const hvpic_params* p) {
   L.open_rows = off;
   off += align256(p->open_x ? sizeof(int32_t) * 3 * 2 * (size_t)p->ny * (size_t)p->nz : 0);
   L.chunk_order = off;
-  off += align256(p->ndim == 3 ? sizeof(int32_t) * (size_t)(ceil_div(cap, kChunk3) + 1) : 0);
+  // the order, then per grid row (j, k) F, K, P and one decision word
+  off += align256(p->ndim == 3 ? sizeof(int32_t) * (size_t)(ceil_div(cap, kChunk3) + 1 +
+                                                           3 * (int64_t)p->ny * p->nz + 1)
+                               : 0);
   L.total = off;
   return L;
 }

@@ -185,7 +185,8 @@ struct hvpic_ctx {
   // open boundaries: per face row the injected count, its offset within
   // the injected block and the first slot in the sorted order [3][2][ny nz]
   int32_t* open_rows;
-  // 3D: the order in which the push takes its chunks [chunks + 1], or null
+  // 3D: the order in which the push takes its chunks [chunks + 1] and its
+  // per-row workspace, or null
   int32_t* chunk_order;
   // the last injection: the store it appended to, its size before, count
   const int32_t* inj_cell;

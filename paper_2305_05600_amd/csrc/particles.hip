@@ -1403,74 +1403,93 @@ void k_gather_push(PushArgs A) {
 // F(r) = ceil(cs[r nx] / 1024), the first chunk that starts in row r, and
 // K(r) = F(r+1) - F(r) the chunks that start there, position p of the
 // order holds the chunk F(r) + p - P(t) for the row r at rank t, P the
-// exclusive prefix sum of K over the ranks.  One block; rows <= 65536.  This is a
+// exclusive prefix sum of K over the ranks.  Three passes: per rank F and
+// K, the scan of K, then per rank its entries.  Rows <= 65536.  This is a
 // permutation of the nchunks chunks when cell_start does not decrease from
 // row start to row start, starts at 0 and ends at n; otherwise (the push
-// flags such a cell_start) the order is the store order, so that every chunk
-// is still pushed once.
+// flags such a cell_start) the order is the store order, so that every
+// chunk is still pushed once.
 constexpr int kOrderTj = 16;
-constexpr int kOrderPer = 16;  // ranks per thread per pass
+constexpr int kOrderPer = 16;  // ranks per thread per pass of the scan
 
-__global__ __launch_bounds__(1024) void k_chunk_order(const int32_t* __restrict__ cs, int nx,
-                                                      int ny, int nz, int64_t n, int nchunks,
-                                                      int32_t* __restrict__ order) {
+// Workspace of the order: the order itself, then F, K, P per rank and the
+// decision word.
+struct OrderWs {
+  int32_t *order, *F, *K, *P, *D;
+};
+
+// F and K of rank t's row; K = -1 marks a row start below the previous one.
+__global__ void k_order_rows(const int32_t* __restrict__ cs, int nx, int ny, int nz,
+                             int nchunks, OrderWs W) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ny * nz) return;
+  const int tile = kOrderTj * nz;  // ranks per full tile
+  const int jt = t / tile, local = t - jt * tile;
+  const int T = min(kOrderTj, ny - jt * kOrderTj);  // rows of this tile
+  const int k = local / T, j = jt * kOrderTj + (local - (local / T) * T);
+  const int64_t r = (int64_t)j + (int64_t)ny * k;
+  const int64_t a = cs[r * nx], b = cs[(r + 1) * nx];
+  const int64_t fa = min<int64_t>(max<int64_t>((a + kChunk3 - 1) / kChunk3, 0), nchunks);
+  const int64_t fb = min<int64_t>(max<int64_t>((b + kChunk3 - 1) / kChunk3, 0), nchunks);
+  W.F[t] = (int)fa;
+  W.K[t] = b < a ? -1 : (int)max<int64_t>(fb - fa, 0);
+}
+
+// One block: P = exclusive scan of K over the ranks, and the decision
+// D = 1 (store order) for a bad cell_start, else 0.
+__global__ __launch_bounds__(1024) void k_order_scan(const int32_t* __restrict__ cs, int nx,
+                                                     int R, int64_t n, OrderWs W) {
   __shared__ int s_w[16];
   __shared__ int s_carry;
-  const int R = ny * nz;
-  const int tile = kOrderTj * nz;  // ranks per full tile
   bool bad = threadIdx.x == 0 && (cs[0] != 0 || (int64_t)cs[(int64_t)R * nx] != n);
-  for (int r = threadIdx.x; r < R; r += 1024)
-    bad |= cs[(int64_t)(r + 1) * nx] < cs[(int64_t)r * nx];
-  if (__syncthreads_or(bad)) {
-    for (int p = threadIdx.x; p < nchunks; p += 1024) order[p] = p;
-    return;
-  }
   if (threadIdx.x == 0) s_carry = 0;
   __syncthreads();
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   for (int t0 = 0; t0 < R; t0 += 1024 * kOrderPer) {
-    int F[kOrderPer], K[kOrderPer];
-    int sum = 0;
+    int v[kOrderPer];
 #pragma unroll
     for (int q = 0; q < kOrderPer; ++q) {
-      const int t = t0 + (int)threadIdx.x * kOrderPer + q;
-      F[q] = 0;
-      K[q] = 0;
-      if (t < R) {
-        const int jt = t / tile, local = t - jt * tile;
-        const int T = min(kOrderTj, ny - jt * kOrderTj);  // rows of this tile
-        const int k = local / T, j = jt * kOrderTj + (local - (local / T) * T);
-        const int64_t r = (int64_t)j + (int64_t)ny * k;
-        const int64_t a = cs[r * nx], b = cs[(r + 1) * nx];
-        const int64_t fa = min<int64_t>(max<int64_t>((a + kChunk3 - 1) / kChunk3, 0), nchunks);
-        const int64_t fb = min<int64_t>(max<int64_t>((b + kChunk3 - 1) / kChunk3, 0), nchunks);
-        F[q] = (int)fa;
-        K[q] = (int)max<int64_t>(fb - fa, 0);
-      }
-      sum += K[q];
+      const int t = t0 + q * 1024 + (int)threadIdx.x;
+      v[q] = t < R ? W.K[t] : 0;
     }
-    // exclusive scan of the per-thread sums over the block
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    int x = sum;
-    for (int o = 1; o < 64; o <<= 1) {
-      const int y = __shfl_up(x, o);
-      if (lane >= o) x += y;
-    }
-    if (lane == 63) s_w[wid] = x;
-    __syncthreads();
-    int before = s_carry, total = 0;
-    for (int w = 0; w < 16; ++w) {
-      if (w < wid) before += s_w[w];
-      total += s_w[w];
-    }
-    int p = before + x - sum;
 #pragma unroll
-    for (int q = 0; q < kOrderPer; ++q)
-      for (int m = 0; m < K[q]; ++m, ++p)
-        if (p < nchunks) order[p] = F[q] + m;
-    __syncthreads();
-    if (threadIdx.x == 0) s_carry += total;
-    __syncthreads();
+    for (int q = 0; q < kOrderPer; ++q) {
+      const int t = t0 + q * 1024 + (int)threadIdx.x;
+      bad |= v[q] < 0;
+      const int own = max(v[q], 0);
+      int x = own;
+      for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+      }
+      if (lane == 63) s_w[wid] = x;
+      __syncthreads();
+      int before = s_carry, total = 0;
+      for (int w = 0; w < 16; ++w) {
+        if (w < wid) before += s_w[w];
+        total += s_w[w];
+      }
+      if (t < R) W.P[t] = before + x - own;
+      __syncthreads();
+      if (threadIdx.x == 0) s_carry += total;
+      __syncthreads();
+    }
   }
+  bad = __syncthreads_or(bad);
+  if (threadIdx.x == 0) W.D[0] = bad ? 1 : 0;
+}
+
+// Per rank its chunks at their positions, or (D = 1) the store order.
+__global__ void k_order_write(int R, int nchunks, OrderWs W) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (W.D[0] != 0) {
+    if (i < nchunks) W.order[i] = i;
+    return;
+  }
+  if (i >= R) return;
+  const int k = W.K[i], f = W.F[i], p = W.P[i];
+  for (int m = 0; m < k; ++m)
+    if (p + m < nchunks) W.order[p + m] = f + m;
 }
 
 // Stand-alone deposit at x - half_dt_back v (no push); same lane runs.
@@ -1747,11 +1766,22 @@ int launch_push(hvpic_ctx* c, const hvpic_particles* in, const int32_t* perm,
   int nblocks = 0;
   if (c->p.ndim == 3 && cell_start != nullptr && c->chunk_order &&
       (int64_t)c->p.ny * c->p.nz <= 65536) {
-    // the chunk order (a kernel of its own, outside the push's timing)
-    hipLaunchKernelGGL(k_chunk_order, dim3(1), dim3(1024), 0, c->stream, cell_start, c->p.nx,
-                       c->p.ny, c->p.nz, p->n, (int)ceil_div(p->n, Chunk<3>::N),
-                       c->chunk_order);
-    A.order = c->chunk_order;
+    // the chunk order (kernels of their own, outside the push's timing)
+    const int R = c->p.ny * c->p.nz;
+    const int nch = (int)ceil_div(p->n, Chunk<3>::N);
+    OrderWs W;
+    W.order = c->chunk_order;
+    W.F = W.order + ceil_div(std::max<int64_t>(c->p.np_capacity, 1), kChunk3) + 1;
+    W.K = W.F + R;
+    W.P = W.K + R;
+    W.D = W.P + R;
+    hipLaunchKernelGGL(k_order_rows, dim3((unsigned)ceil_div(R, 256)), dim3(256), 0, c->stream,
+                       cell_start, c->p.nx, c->p.ny, c->p.nz, nch, W);
+    hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(1024), 0, c->stream, cell_start, c->p.nx, R,
+                       p->n, W);
+    hipLaunchKernelGGL(k_order_write, dim3((unsigned)ceil_div(std::max(R, nch), 256)), dim3(256),
+                       0, c->stream, R, nch, W);
+    A.order = W.order;
   }
   timing_begin(c, HVPIC_KERNEL_GATHER_PUSH);
   if (c->p.ndim == 2) {
