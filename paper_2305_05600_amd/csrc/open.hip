@@ -146,11 +146,16 @@ __global__ __launch_bounds__(kBlock) void k_open_ohm(const float* __restrict__ B
   E[2 * nc + c] = (w0 * b1 - w1 * b0) + aux.gp[2 * nc + c] + o.eta * j2 - h2;
 }
 
-// B1_dst = B1_base - coef curl E in the interior (compensated into lo when
-// given); base and dst are read and written at the thread's own cell only
+// B1_dst = B1_base - coef curl E in the interior (compensated into lo_out
+// when given, from lo_in, or from zero when lo_in is null), and the ghost
+// rule: the threads of the outermost interior cells (i = 1, nx-2) also
+// write their values into the ghost cell beside them.  base and lo_in are
+// read at the thread's own cell only, and a ghost cell's thread reads and
+// writes nothing, so dst may be base and lo_out may be lo_in.
 template <int NDIM>
 __global__ __launch_bounds__(kBlock) void k_open_faraday(const float* __restrict__ E,
-                                                         const float* Bbase, float* Bdst, float* lo,
+                                                         const float* Bbase, float* Bdst,
+                                                         const float* lo_in, float* lo_out,
                                                          float coef, FGeo g) {
   const int c = blockIdx.x * kBlock + threadIdx.x;
   if (c >= g.ncell) return;
@@ -160,18 +165,29 @@ __global__ __launch_bounds__(kBlock) void k_open_faraday(const float* __restrict
   const BSum<false> Ea{E, nullptr};
   float ce[3];
   curl_at<NDIM>(Ea, c, g, ce);
+  const bool left = i == 1, right = i == g.nx - 2;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     const int q = a * g.ncell + c;
     const float d = -coef * ce[a];
     const float hi = Bbase[q];
-    if (lo) {
-      const float y = lo[q] + d;
-      const float t = hi + y;
-      lo[q] = y - (t - hi);
-      Bdst[q] = t;
+    float t, l = 0.0f;
+    if (lo_out) {
+      const float y = (lo_in ? lo_in[q] : 0.0f) + d;
+      t = hi + y;
+      l = y - (t - hi);
+      lo_out[q] = l;
     } else {
-      Bdst[q] = hi + d;
+      t = hi + d;
+    }
+    Bdst[q] = t;
+    if (left) {
+      Bdst[q - 1] = t;
+      if (lo_out) lo_out[q - 1] = l;
+    }
+    if (right) {
+      Bdst[q + 1] = t;
+      if (lo_out) lo_out[q + 1] = l;
     }
   }
 }
@@ -528,25 +544,21 @@ void open_advance(hvpic_ctx* c, const float* B0, float* B1, float* Btot, const f
   if (mode == 0 && c->p.nsub > 0) {
     const float h = (float)(c->p.dt / c->p.nsub);
     hipLaunchKernelGGL(k_open_prep<NDIM>, grid, blk, 0, s, n_half, J_half, g, eos, aux);
-    const int cblocks = (int)std::min<int64_t>(ceil_div(3ll * nc, kBlock), 1024);
-    hipLaunchKernelGGL(k_copy, dim3(cblocks), blk, 0, s, (const float*)B1, Xh, 3ll * nc);
-    hipLaunchKernelGGL(k_fill, dim3(cblocks), blk, 0, s, Xl, 3ll * nc, 0.0f);
     for (int m = 0; m < c->p.nsub; ++m) {
-      hipLaunchKernelGGL((k_open_curl<NDIM, false>), grid, blk, 0, s, (const float*)Xh,
-                         (const float*)nullptr, J, g);
-      hipLaunchKernelGGL(k_open_ohm<NDIM>, grid, blk, 0, s, B0, (const float*)Xh, (const float*)J,
-                         aux, E, o);
-      hipLaunchKernelGGL(k_open_faraday<NDIM>, grid, blk, 0, s, (const float*)E, (const float*)Xh,
-                         Yh, (float*)nullptr, 0.5f * h, g);
-      fill(c, Yh, 3);
+      // B1 (hi + lo) of the substep: the caller's B1 (lo = 0) at the first
+      const float* Xb = m == 0 ? (const float*)B1 : (const float*)Xh;
+      const float* Xlb = m == 0 ? nullptr : (const float*)Xl;
+      hipLaunchKernelGGL((k_open_curl<NDIM, false>), grid, blk, 0, s, Xb, (const float*)nullptr, J,
+                         g);
+      hipLaunchKernelGGL(k_open_ohm<NDIM>, grid, blk, 0, s, B0, Xb, (const float*)J, aux, E, o);
+      hipLaunchKernelGGL(k_open_faraday<NDIM>, grid, blk, 0, s, (const float*)E, Xb, Yh,
+                         (const float*)nullptr, (float*)nullptr, 0.5f * h, g);
       hipLaunchKernelGGL((k_open_curl<NDIM, false>), grid, blk, 0, s, (const float*)Yh,
                          (const float*)nullptr, J, g);
       hipLaunchKernelGGL(k_open_ohm<NDIM>, grid, blk, 0, s, B0, (const float*)Yh, (const float*)J,
                          aux, E, o);
-      hipLaunchKernelGGL(k_open_faraday<NDIM>, grid, blk, 0, s, (const float*)E, (const float*)Xh,
-                         Xh, Xl, h, g);
-      fill(c, Xh, 3);
-      fill(c, Xl, 3);
+      hipLaunchKernelGGL(k_open_faraday<NDIM>, grid, blk, 0, s, (const float*)E, Xb, Xh, Xlb, Xl,
+                         h, g);
     }
     fh = Xh;
     fl = Xl;
