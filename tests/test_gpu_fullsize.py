@@ -1,4 +1,7 @@
-"""Parity at the full size of the 3D beam box (128^3 cells, 134,217,728 ions,
+"""Parity at full size, on the 3D beam box (below) and the open solar-wind
+box (its own test).
+
+The 3D beam box (128^3 cells, 134,217,728 ions,
 QS, 4 subcycles), in the sequence the benchmark times: the push reads the
 store through the gather map with the fused deposit, the 3D chunk order is
 in use, and the sort runs beside the field advance.  The FP64 oracle cannot
@@ -135,3 +138,117 @@ def test_beam3d_full_size_sampled(mods):
     print(f"field advance: rel L2 B {eB:.2e}, E {eE:.2e}", flush=True)
     assert eB < 1e-5 and eE < 1e-5
     check_field_diag(g.field_diag.cpu().numpy(), rd)
+
+
+def test_open_solar_wind_full_size_sampled(mods):
+    """The open solar-wind box at full size (800x1600 cells + 2 ghost
+    columns, 128M ions, NGP, 5 subcycles) in the sequence the benchmark
+    times (gather map, open neighbour sort beside the field advance), second
+    step, on what the oracle computes at this size: 8192 sampled pushes;
+    the step's injection, whole; the open sort, whole, by its defining
+    properties (the map selects exactly the ions outside the ghost columns,
+    in stable cell order, and cell_start is the prefix sum of their
+    histogram); the moments at 64 sampled interior cells from every pushed
+    ion that can reach them; and the whole open field advance from the
+    step's own moments."""
+    H, S = mods
+    announce("open solar wind full size")
+    from paper_2305_05600_amd.sim import OpenSim
+
+    cfg, parts, B0, B1, spec = W.solar_wind_box()
+    nc = cfg.ncell
+    sim = OpenSim(cfg, parts, B0, B1, spec, 31)
+    del parts
+    sim.step()
+    sim.synchronize()
+    live1, inj1 = sim.live, sim.injected
+    keys7 = ("cell", "ox", "oy", "ux", "uy", "uz", "w")
+    P1 = {k: getattr(sim.p, k)[:sim.p.n].clone() for k in keys7}
+    perm1 = sim.perm[:live1].long().clone()
+    E1 = sim.E.double().cpu().numpy()
+    Bt1 = sim.Btot.double().cpu().numpy()
+    B1_1 = sim.B1.double().cpu().numpy()
+    sim.step()
+    sim.synchronize()
+    flags, _ = sim.status()
+    assert flags & (H.FLAG_BAD_INPUT | H.FLAG_NONFINITE | H.FLAG_MOVE_GT1) == 0, flags
+    assert sim.fallbacks == 0
+    n_inj = sim.injected - inj1
+    total = live1 + n_inj
+    Q = {k: getattr(sim.p, k)[:total] for k in keys7}  # pushed, then injected
+    rng = np.random.default_rng(13)
+
+    # the push of sampled ions
+    t = torch.from_numpy(rng.choice(live1, 8192, replace=False)).cuda()
+    ref = O.particles64({k: v[perm1[t]].cpu().numpy() for k, v in P1.items()})
+    O.push(cfg, ref, E1, Bt1)
+    got = {k: v[t].cpu().numpy() for k, v in Q.items()}
+    nstr = compare_particles(cfg, got, ref)
+    print(f"push: 8192 sampled ions, {nstr} face straddlers", flush=True)
+
+    # the injection of the step, whole
+    empty = {k: np.zeros(0, np.int32 if k == "cell" else np.float64) for k in keys7}
+    new = O.open_inject(cfg, spec, sim.seed, 1, empty)
+    assert new["cell"].size == n_inj > 0
+    gi = {k: v[live1:total].cpu().numpy() for k, v in Q.items()}
+    assert np.array_equal(gi["cell"], new["cell"])
+    assert np.array_equal(gi["w"].astype(np.float64), new["w"])
+    for k in ("ox", "oy", "ux", "uy", "uz"):
+        b = new[k]
+        assert np.all(np.abs(gi[k].astype(np.float64) - b) <= 2e-7 * np.maximum(1.0, np.abs(b))), k
+    print(f"injection: {n_inj} ions", flush=True)
+
+    # the open sort, whole
+    keys = Q["cell"].long()
+    i_ = keys % cfg.nx
+    inside = (i_ != 0) & (i_ != cfg.nx - 1)
+    perm2 = sim.perm[:sim.live].long()
+    assert sim.live == int(inside.sum())
+    ks = keys[perm2]
+    assert bool(inside[perm2].all())
+    assert bool((ks[1:] >= ks[:-1]).all())
+    eq = ks[1:] == ks[:-1]
+    assert bool((perm2[1:][eq] > perm2[:-1][eq]).all())
+    assert int(torch.bincount(perm2, minlength=total).max()) == 1
+    hist = torch.bincount(keys[inside], minlength=nc)
+    ref_cs = torch.cat([torch.zeros(1, dtype=torch.long, device="cuda"), torch.cumsum(hist, 0)])
+    assert torch.equal(sim.cs[:nc + 1].long(), ref_cs)
+    print(f"sort: {total} ions, {total - sim.live} absorbed", flush=True)
+
+    # the moments at sampled interior cells (NGP: an ion reaches the cell
+    # of its mid-point, within one cell of its new cell)
+    ci = rng.integers(3, cfg.nx - 3, 64)
+    cj = rng.integers(0, cfg.ny, 64)
+    cells = ci + cfg.nx * cj
+    d = np.arange(-1, 2)
+    near = ((ci[:, None, None] + d[None, :, None]) + cfg.nx * ((cj[:, None, None] + d[None, None, :])
+                                                            % cfg.ny)).ravel()
+    near = np.unique(near)
+    near_t = torch.from_numpy(near).cuda()
+    pushed = torch.arange(live1, device="cuda")
+    sel = pushed[torch.isin(keys[:live1], near_t)]
+    sub = O.particles64({k: v[sel].cpu().numpy() for k, v in Q.items()})
+    rn, rJ = O.deposit(cfg, sub, 0.5 * cfg.dt)
+    bad = deposit_point_straddlers(cfg, sub, 0.5 * cfg.dt)
+    sc = np.asarray(sub["cell"])[bad].astype(np.int64)
+    hit = np.zeros(64, bool)
+    for s_ in sc:
+        hit |= (np.abs(ci - s_ % cfg.nx) <= 1) & (np.minimum(np.abs(cj - s_ // cfg.nx),
+                                                             cfg.ny - np.abs(cj - s_ // cfg.nx)) <= 1)
+    keep = cells[~hit]
+    assert keep.size >= 48, keep.size
+    gn = sim.n_prev.double().cpu().numpy()
+    gJ = sim.J_prev.double().cpu().numpy()
+    en, eJ = rel_l2(gn[keep], rn[keep]), rel_l2(gJ[:, keep], rJ[:, keep])
+    print(f"moments: {keep.size} of 64 sampled cells ({sel.numel()} ions, {int(bad.sum())} "
+          f"straddlers), rel L2 n {en:.2e}, J {eJ:.2e}", flush=True)
+    assert en < 1e-5 and eJ < 1e-5
+
+    # the open field advance of the step, from its own moments
+    rB1, rE, rBt, rd, st = O.open_field_advance(cfg, sim.B0.double().cpu().numpy(), B1_1, gn, gJ,
+                                                sim.n_half.double().cpu().numpy(),
+                                                sim.J_half.double().cpu().numpy(), mode=0)
+    eB = rel_l2(sim.B1.cpu().numpy(), rB1)
+    eE = rel_l2(sim.E.cpu().numpy(), rE)
+    print(f"open field advance: rel L2 B1 {eB:.2e}, E {eE:.2e}", flush=True)
+    assert eB < 1e-5 and eE < 1e-5
