@@ -1,8 +1,8 @@
-"""Parity at full size, on the 3D beam box (below) and the open solar-wind
-box (its own test).
+"""Parity at full size: the 3D beam box (below) and the open solar-wind box
+(its test's docstring).
 
-The 3D beam box (128^3 cells, 134,217,728 ions,
-QS, 4 subcycles), in the sequence the benchmark times: the push reads the
+The 3D beam box (128^3 cells, 134,217,728 ions, QS, 4 subcycles), in the
+sequence the benchmark times: the push reads the
 store through the gather map with the fused deposit, the 3D chunk order is
 in use, and the sort runs beside the field advance.  The FP64 oracle cannot
 step 134M ions in a test's time, so the second step is checked on what it
